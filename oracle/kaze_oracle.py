@@ -1,0 +1,307 @@
+"""FP64 CPU oracle of the KAZE nonlinear scale space and detector response.
+
+TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT.  Only the tests, the smoke entry
+point and the CPU-baseline leg of the benchmark may import this module.  It
+shares no code, table or constant generator with the GPU library: it is a
+plain, slow, readable restatement of the method of Ramkumar B et al., "GPGPU
+Acceleration of the KAZE Image Feature Extraction Algorithm" (arXiv
+1706.06750), Sec. II-A and II-B, in float64 NumPy.
+
+Readings of passages the paper leaves open (each is also listed in the
+design notes):
+
+* Eq. 6 exponent: sigma_i = sigma0 * 2**(o + s/S) (the printed (o+s)/S would
+  give duplicate scales and is not octave periodic, as Eq. 8 requires).
+* N = O*S levels, i = 0..N-1; level 0 is the sigma0-smoothed base image
+  (Sec. III-A), t_0 = sigma0^2/2; one semi-implicit step per level with
+  tau_i = t_i - t_{i-1}.
+* Eq. 4 is evaluated by additive operator splitting (AOS): for m = 2
+  dimensions, L^{i} = 1/m sum_l (I - m tau A_l(L^{i-1}))^{-1} L^{i-1}, where A_l
+  is the 1-D nonlinear diffusion matrix with entries (g_j + g_k)/2 between
+  neighbours j,k (pixel spacing 1) and minus their sum on the diagonal.
+  Neumann (zero-flux) boundaries drop the flux across the image border.
+* All stencils extend the image by half-sample symmetric reflection
+  (x[-1] = x[0], x[-2] = x[1], ...), the reflection consistent with the
+  cell-centred Neumann boundary.
+* Gaussian kernels: radius ceil(3 sigma), taps exp(-j^2/(2 sigma^2))
+  normalised to sum 1.  The image used for the conductivity is smoothed with
+  sigma_cond = 1.0 before the Scharr derivatives (Sec. III-A).
+* Scharr derivatives at step s: central difference (f(x+s)-f(x-s))/(2s)
+  across, [3, 10, 3]/16 smoothing at offsets (-s, 0, +s) along the other axis
+  (s = 1 is the ordinary 3x3 Scharr kernel divided by 32).
+* Contrast factor k (Sec. II-A, Sec. III-A): magnitudes of the Scharr
+  gradient of the sigma_cond-smoothed base image over all pixels; zero
+  magnitudes excluded; 300 bins over [0, hmax], bin = min(floor(m/hmax*300),
+  299); b* = smallest bin whose cumulative count reaches 0.7 * npos;
+  k = hmax * (b*+1)/300 (upper bin edge).  With no positive magnitude k = 1.
+* Eq. 8: the scale factor is sigma_n,i = sigma_i / 2**o_i (the printed k_i
+  reuses the contrast-factor symbol); the derivative step is round(sigma_n)
+  (half away from zero); the det is weighted by the real sigma_n^2;
+  L_xx = D_x(D_x L), L_yy = D_y(D_y L), L_xy = D_y(D_x L), each derivative
+  image reflected at the border before the next derivative.
+* Extrema (Sec. II-B, the 3x3 "approximate" variant): levels 1..N-2, pixels
+  1..W-2 x 1..H-2, response strictly above the threshold and strictly above
+  all 26 neighbours in the 3x3x3 block; maxima only.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.linalg import solve_banded
+
+__all__ = [
+    "DEFAULTS", "level_schedule", "gaussian_taps", "gaussian_smooth",
+    "scharr_dx", "scharr_dy", "gradient_magnitude", "contrast_factor",
+    "conductivity_g2", "conductivity_g1", "aos_line_bands", "aos_solve_rows",
+    "aos_solve_cols", "aos_step", "build_scale_space", "derivative_step",
+    "detector_response", "find_extrema",
+]
+
+DEFAULTS = dict(sigma0=1.6, octaves=4, sublevels=4, sigma_cond=1.0,
+                k_percentile=0.7, k_bins=300, det_threshold=0.001)
+
+
+# --------------------------------------------------------------------------
+# Scale schedule: Eqs. 6 and 7 (Sec. II-A)
+# --------------------------------------------------------------------------
+def level_schedule(sigma0: float = 1.6, octaves: int = 4, sublevels: int = 4):
+    """Per level i: octave o, sublevel s, scale sigma_i and time t_i.
+
+    Eq. 6 maps (o, s) to sigma_i = sigma0 * 2**(o + s/S) (read as KAZE's own
+    definition); Eq. 7 converts it to the evolution time t_i = sigma_i^2 / 2.
+    """
+    out = []
+    for o in range(octaves):
+        for s in range(sublevels):
+            sigma = sigma0 * 2.0 ** (o + s / sublevels)
+            out.append({"i": len(out), "o": o, "s": s, "sigma": sigma,
+                        "t": 0.5 * sigma * sigma})
+    return out
+
+
+# --------------------------------------------------------------------------
+# Linear filters (Sec. III-A: Gaussian pre-smoothing, L_smooth, Scharr)
+# --------------------------------------------------------------------------
+def _extend(f: np.ndarray, r: int, axis: int) -> np.ndarray:
+    """Half-sample symmetric extension by r samples on both sides of an axis."""
+    pad = [(0, 0), (0, 0)]
+    pad[axis] = (r, r)
+    return np.pad(f, pad, mode="symmetric")
+
+
+def _correlate_axis(f: np.ndarray, taps: np.ndarray, offsets, axis: int
+                    ) -> np.ndarray:
+    """out[p] = sum_j taps[j] * f[p + offsets[j] along axis], reflected border."""
+    r = max(abs(int(o)) for o in offsets)
+    n = f.shape[axis]
+    fe = _extend(f, r, axis)
+    out = np.zeros_like(f, dtype=np.float64)
+    for w, o in zip(taps, offsets):
+        sl = [slice(None), slice(None)]
+        sl[axis] = slice(r + o, r + o + n)
+        out += w * fe[tuple(sl)]
+    return out
+
+
+def gaussian_taps(sigma: float) -> np.ndarray:
+    """Sampled Gaussian, radius ceil(3 sigma), normalised to unit sum."""
+    r = int(math.ceil(3.0 * sigma))
+    j = np.arange(-r, r + 1, dtype=np.float64)
+    w = np.exp(-(j * j) / (2.0 * sigma * sigma))
+    return w / w.sum()
+
+
+def gaussian_smooth(f: np.ndarray, sigma: float) -> np.ndarray:
+    """Separable Gaussian convolution G_sigma * f (Sec. III-A), x then y."""
+    taps = gaussian_taps(sigma)
+    r = len(taps) // 2
+    offs = list(range(-r, r + 1))
+    tmp = _correlate_axis(np.asarray(f, dtype=np.float64), taps, offs, axis=1)
+    return _correlate_axis(tmp, taps, offs, axis=0)
+
+
+def scharr_dx(f: np.ndarray, s: int = 1) -> np.ndarray:
+    """Scharr x-derivative of step s (Sec. II-B; Sec. III-B concatenated form).
+
+    Central difference (f(x+s) - f(x-s)) / (2s) along x, smoothed by
+    [3, 10, 3]/16 at y offsets (-s, 0, +s).
+    """
+    d = _correlate_axis(np.asarray(f, dtype=np.float64),
+                        [-1.0 / (2 * s), 1.0 / (2 * s)], [-s, s], axis=1)
+    return _correlate_axis(d, [3 / 16, 10 / 16, 3 / 16], [-s, 0, s], axis=0)
+
+
+def scharr_dy(f: np.ndarray, s: int = 1) -> np.ndarray:
+    """Scharr y-derivative of step s: the transpose of :func:`scharr_dx`."""
+    d = _correlate_axis(np.asarray(f, dtype=np.float64),
+                        [-1.0 / (2 * s), 1.0 / (2 * s)], [-s, s], axis=0)
+    return _correlate_axis(d, [3 / 16, 10 / 16, 3 / 16], [-s, 0, s], axis=1)
+
+
+def gradient_magnitude(L: np.ndarray, sigma_cond: float = 1.0) -> np.ndarray:
+    """|grad L_sigma|: Scharr gradient of G_sigma_cond * L (Eq. 2)."""
+    Ls = gaussian_smooth(L, sigma_cond)
+    Lx, Ly = scharr_dx(Ls), scharr_dy(Ls)
+    return np.sqrt(Lx * Lx + Ly * Ly)
+
+
+# --------------------------------------------------------------------------
+# Contrast factor and conductivity: Eqs. 2-3, Sec. III-A
+# --------------------------------------------------------------------------
+def contrast_factor(L0: np.ndarray, sigma_cond: float = 1.0,
+                    percentile: float = 0.7, nbins: int = 300) -> float:
+    """Contrast factor k from the gradient histogram of the base image."""
+    m = gradient_magnitude(L0, sigma_cond)
+    pos = m[m > 0.0]
+    if pos.size == 0:
+        return 1.0
+    hmax = float(m.max())
+    bins = np.minimum(np.floor(pos / hmax * nbins).astype(np.int64), nbins - 1)
+    hist = np.bincount(bins, minlength=nbins)
+    cum = np.cumsum(hist)
+    b = int(np.argmax(cum >= percentile * pos.size))
+    return hmax * (b + 1) / nbins
+
+
+def conductivity_g2(L: np.ndarray, k: float, sigma_cond: float = 1.0
+                    ) -> np.ndarray:
+    """Perona-Malik g2 = 1 / (1 + |grad L_sigma|^2 / k^2) (Eqs. 2-3)."""
+    Ls = gaussian_smooth(L, sigma_cond)
+    Lx, Ly = scharr_dx(Ls), scharr_dy(Ls)
+    return 1.0 / (1.0 + (Lx * Lx + Ly * Ly) / (k * k))
+
+
+def conductivity_g1(L: np.ndarray, k: float, sigma_cond: float = 1.0
+                    ) -> np.ndarray:
+    """Perona-Malik g1 = exp(-|grad L_sigma|^2 / k^2) (Eq. 3)."""
+    Ls = gaussian_smooth(L, sigma_cond)
+    Lx, Ly = scharr_dx(Ls), scharr_dy(Ls)
+    return np.exp(-(Lx * Lx + Ly * Ly) / (k * k))
+
+
+# --------------------------------------------------------------------------
+# Semi-implicit step, Eq. 4, by additive operator splitting
+# --------------------------------------------------------------------------
+def aos_line_bands(g_line: np.ndarray, tau: float, m: int = 2) -> np.ndarray:
+    """Banded form (scipy 'ab' layout) of I - m tau A(g) for one image line.
+
+    A has (g_j + g_{j+1})/2 between neighbours j, j+1 and minus the row sum
+    on the diagonal; the flux across either end of the line is dropped.
+    """
+    g = np.asarray(g_line, dtype=np.float64)
+    n = g.size
+    w = m * tau * 0.5 * (g[:-1] + g[1:])     # coupling weight of edge (j, j+1)
+    ab = np.zeros((3, n), dtype=np.float64)
+    ab[0, 1:] = -w                           # super-diagonal
+    ab[2, :-1] = -w                          # sub-diagonal
+    ab[1, :] = 1.0
+    ab[1, :-1] += w
+    ab[1, 1:] += w
+    return ab
+
+
+def aos_solve_rows(L: np.ndarray, g: np.ndarray, tau: float) -> np.ndarray:
+    """u_x: (I - 2 tau A_x(g)) u_x = L along every row."""
+    H, W = L.shape
+    out = np.empty((H, W), dtype=np.float64)
+    for y in range(H):
+        if W == 1:
+            out[y] = L[y]
+            continue
+        out[y] = solve_banded((1, 1), aos_line_bands(g[y], tau), L[y])
+    return out
+
+
+def aos_solve_cols(L: np.ndarray, g: np.ndarray, tau: float) -> np.ndarray:
+    """u_y: (I - 2 tau A_y(g)) u_y = L along every column."""
+    return aos_solve_rows(L.T, g.T, tau).T
+
+
+def aos_step(L: np.ndarray, g: np.ndarray, tau: float) -> np.ndarray:
+    """One AOS step of Eq. 4: L' = (u_x + u_y) / 2."""
+    L = np.asarray(L, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    return 0.5 * (aos_solve_rows(L, g, tau) + aos_solve_cols(L, g, tau))
+
+
+def build_scale_space(img: np.ndarray, sigma0: float = 1.6, octaves: int = 4,
+                      sublevels: int = 4, sigma_cond: float = 1.0,
+                      k_percentile: float = 0.7, k_bins: int = 300,
+                      k: float | None = None, diffusivity: str = "g2",
+                      return_g: bool = False):
+    """Nonlinear scale space (Sec. II-A, Sec. III-A).
+
+    Returns ``(levels [N][H][W] float64, k)`` and, if ``return_g``, the
+    conductivity image used by each step (``g[i]`` drives the step into level
+    i; ``g[0]`` is zero).
+    """
+    f = np.asarray(img, dtype=np.float64)
+    sched = level_schedule(sigma0, octaves, sublevels)
+    L0 = gaussian_smooth(f, sigma0)
+    if k is None:
+        k = contrast_factor(L0, sigma_cond, k_percentile, k_bins)
+    cond = conductivity_g2 if diffusivity == "g2" else conductivity_g1
+    levels = [L0]
+    gs = [np.zeros_like(L0)]
+    for i in range(1, len(sched)):
+        g = cond(levels[-1], k, sigma_cond)
+        tau = sched[i]["t"] - sched[i - 1]["t"]
+        levels.append(aos_step(levels[-1], g, tau))
+        gs.append(g)
+    if return_g:
+        return np.stack(levels), float(k), np.stack(gs)
+    return np.stack(levels), float(k)
+
+
+# --------------------------------------------------------------------------
+# Detector response: Eq. 8 and Sec. II-B
+# --------------------------------------------------------------------------
+def derivative_step(sigma_n: float) -> int:
+    """Scharr step for the normalised scale: round half away from zero, >= 1."""
+    return max(1, int(math.floor(sigma_n + 0.5)))
+
+
+def detector_response(levels: np.ndarray, sigma0: float = 1.6,
+                      octaves: int = 4, sublevels: int = 4) -> np.ndarray:
+    """Scale-normalised Hessian determinant of every level (Eq. 8)."""
+    sched = level_schedule(sigma0, octaves, sublevels)
+    out = np.empty_like(np.asarray(levels, dtype=np.float64))
+    for lev in sched:
+        i = lev["i"]
+        sn = lev["sigma"] / 2.0 ** lev["o"]
+        s = derivative_step(sn)
+        L = np.asarray(levels[i], dtype=np.float64)
+        Lx, Ly = scharr_dx(L, s), scharr_dy(L, s)
+        Lxx, Lyy, Lxy = scharr_dx(Lx, s), scharr_dy(Ly, s), scharr_dy(Lx, s)
+        out[i] = sn * sn * (Lxx * Lyy - Lxy * Lxy)
+    return out
+
+
+def find_extrema(det: np.ndarray, threshold: float = 0.001) -> np.ndarray:
+    """3x3x3 maxima above the threshold (Sec. II-B).
+
+    Returns an int64/float64 record array sorted by (level, y, x) with
+    columns level, y, x and response, as an (n, 4) float64 array.
+    """
+    det = np.asarray(det, dtype=np.float64)
+    N, H, W = det.shape
+    rows = []
+    if H < 3 or W < 3:
+        return np.zeros((0, 4))
+    for i in range(1, N - 1):
+        c = det[i, 1:H - 1, 1:W - 1]
+        mask = c > threshold
+        for dl in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    if dl == 0 and dy == 0 and dx == 0:
+                        continue
+                    nb = det[i + dl, 1 + dy:H - 1 + dy, 1 + dx:W - 1 + dx]
+                    mask &= c > nb
+        ys, xs = np.nonzero(mask)
+        for y, x in zip(ys, xs):
+            rows.append((i, y + 1, x + 1, c[y, x]))
+    if not rows:
+        return np.zeros((0, 4))
+    return np.array(sorted(rows), dtype=np.float64)
