@@ -1,0 +1,204 @@
+/*
+ * kaze.h - C ABI of the MI355X (gfx950) KAZE nonlinear scale-space library.
+ *
+ * The library computes the detector half of KAZE feature extraction
+ * (Ramkumar B et al., "GPGPU Acceleration of the KAZE Image Feature
+ * Extraction Algorithm", arXiv 1706.06750):
+ *
+ *   - the nonlinear scale space of Sec. II-A (Eqs. 1-7): Gaussian
+ *     pre-smoothing with sigma0, the contrast factor k from the gradient
+ *     histogram (Sec. III-A), the Perona-Malik conductivity (Eqs. 2-3), and
+ *     one semi-implicit step (Eq. 4) per level, evaluated by additive
+ *     operator splitting with tridiagonal solves along every row and every
+ *     column and zero-flux (Neumann) boundaries;
+ *   - the scale-normalised Hessian determinant of every level (Eq. 8);
+ *   - the 3x3x3 non-maximum suppression of Sec. II-B.
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers marked (device) are HIP device pointers on the current
+ *     device; pointers marked (host) are read during the call only.
+ *   - Images and levels are float32, row-major.  `levels` and `det` hold
+ *     N = octaves*sublevels planes of H rows of W floats, densely packed.
+ *   - Calls are asynchronous: they validate their arguments, enqueue work on
+ *     `stream` (a hipStream_t; NULL is the null stream) and return without
+ *     synchronising.  Argument errors are returned synchronously and
+ *     enqueue nothing.  A failed HIP launch returns KAZE_ERR_HIP.
+ *   - The caller owns every buffer.  The library allocates no device memory:
+ *     scratch lives in a caller-provided workspace of
+ *     kaze_workspace_bytes() bytes (256-byte aligned).  Two calls that
+ *     share a workspace must be ordered on the same stream.
+ *   - Size limits: 8 <= W <= 8192, 8 <= H <= 4096, N <= 64, Gaussian radius
+ *     ceil(3 sigma) <= 16, Scharr step of Eq. 8 <= 8.
+ *   - Nothing throws across the ABI.
+ */
+#ifndef KAZE_H
+#define KAZE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KAZE_OK = 0,
+    KAZE_ERR_INVALID_ARG = -1,  /* a pointer, size or parameter is invalid   */
+    KAZE_ERR_WORKSPACE = -2,    /* workspace missing, misaligned or too small */
+    KAZE_ERR_HIP = -3,          /* a HIP launch or runtime call failed        */
+    KAZE_ERR_UNSUPPORTED = -4   /* valid but outside the supported limits     */
+} kaze_status;
+
+/* Perona-Malik conductivity functions of Eq. 3. */
+typedef enum { KAZE_G1 = 1, KAZE_G2 = 2 } kaze_diffusivity;
+
+/*
+ * Parameters of the method (host struct, read during the call only).
+ * kaze_default_params() fills the values used throughout: sigma0 = 1.6,
+ * 4 octaves x 4 sublevels, sigma_cond = 1.0, g2, k at the 70th percentile
+ * of a 300-bin gradient histogram, detector threshold 0.001.
+ */
+typedef struct {
+    int    octaves;        /* O of Eq. 6                                        */
+    int    sublevels;      /* S of Eq. 6                                        */
+    double sigma0;         /* base scale of Eq. 6; pre-smoothing width          */
+    double sigma_cond;     /* Gaussian width before the conductivity gradient   */
+    int    diffusivity;    /* KAZE_G2 (default) or KAZE_G1, Eq. 3               */
+    int    k_bins;         /* histogram bins, 1..4096                           */
+    double k_percentile;   /* quantile of the gradient histogram, [1e-6, 1]     */
+    double k_override;     /* > 0: use this contrast factor, skip the histogram */
+    double det_threshold;  /* detector threshold of Sec. II-B (compared in FP32) */
+} kaze_params;
+
+/* One detected extremum: pixel position, level index and det response. */
+typedef struct {
+    int   x;
+    int   y;
+    int   level;
+    float response;
+} kaze_keypoint;
+
+/* Fills *p with the defaults listed above.  Returns KAZE_ERR_INVALID_ARG
+ * for a NULL pointer. */
+kaze_status kaze_default_params(kaze_params* p);
+
+/* Number of scale levels N = octaves * sublevels (Eq. 6), or a negative
+ * kaze_status if *p is invalid. */
+int kaze_num_levels(const kaze_params* p);
+
+/*
+ * Per-level schedule of Eqs. 6-7 and Eq. 8 (host arrays of length N, any of
+ * them may be NULL): sigma_i, evolution time t_i = sigma_i^2/2, the step
+ * tau_i = t_i - t_{i-1} into level i (tau_0 = 0), the normalised scale
+ * sigma_i / 2^o_i and the Scharr step round(sigma_i / 2^o_i).
+ */
+kaze_status kaze_schedule(const kaze_params* p, double* sigma, double* t,
+                          double* tau, double* sigma_norm, int* deriv_step);
+
+/* Workspace bytes that kaze_build_scale_space needs for a W x H image, or 0
+ * if the arguments are invalid. */
+size_t kaze_workspace_bytes(int W, int H, const kaze_params* p);
+
+/*
+ * Nonlinear scale space (Sec. II-A, Sec. III-A).
+ *   img      (device) W x H float32 image, row pitch ld_img >= W floats.
+ *   levels   (device) output, N x H x W float32: level 0 is G_sigma0 * img,
+ *            level i >= 1 is one AOS step of Eq. 4 from level i-1 with
+ *            tau_i, conductivity computed from level i-1.
+ *   k_out    (device) output, 1 float32: the contrast factor used (the
+ *            histogram quantile of Sec. III-A, or k_override).
+ *   ws       (device) workspace of at least kaze_workspace_bytes(W, H, p)
+ *            bytes, 256-byte aligned; its contents on entry are ignored.
+ *   stream   hipStream_t to enqueue on.
+ * The input image must not alias levels or the workspace.
+ */
+kaze_status kaze_build_scale_space(const float* img, int W, int H, int ld_img,
+                                   const kaze_params* p, float* levels,
+                                   float* k_out, void* ws, size_t ws_bytes,
+                                   void* stream);
+
+/*
+ * Conductivity of Eqs. 2-3 for one image and a given contrast factor:
+ *   g = 1/(1 + |grad L_s|^2/k^2)  (KAZE_G2)  or  exp(-|grad L_s|^2/k^2) (KAZE_G1),
+ * where grad is the 3x3 Scharr gradient (divided by 32) of
+ * L_s = G_sigma_cond * L, both with half-sample reflection at the border.
+ *   L        (device) input, W x H float32, row pitch W.
+ *   k        contrast factor, > 0.
+ *   g        (device) output, W x H float32; must not alias L.
+ */
+kaze_status kaze_conductivity(const float* L, int W, int H, const kaze_params* p,
+                              double k, float* g, void* stream);
+
+/*
+ * One AOS step of Eq. 4 with a given conductivity:
+ *   L_next = L + (delta_x + delta_y)/2,
+ *   (I - 2 tau A_l(g)) delta_l = 2 tau A_l(g) L   for l = rows, columns,
+ * A_l having couplings (g_j + g_k)/2 between neighbours along the line and
+ * no flux across the image border.
+ *   L, g     (device) inputs, W x H float32.
+ *   tau      step size, > 0.
+ *   L_next   (device) output, W x H float32; must not alias L, g or ws.
+ *   ws       (device) workspace of kaze_workspace_bytes(W, H, p) bytes
+ *            (any valid p), 256-byte aligned.
+ */
+kaze_status kaze_aos_step(const float* L, const float* g, int W, int H, double tau,
+                          float* L_next, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Detector response of Eq. 8 for every level:
+ *   det_i = sigma_n^2 (L_xx L_yy - L_xy^2), sigma_n = sigma_i / 2^o_i,
+ * with second derivatives formed by applying the concatenated Scharr filter
+ * of step round(sigma_n) twice (L_xx = D_x D_x L, L_yy = D_y D_y L,
+ * L_xy = D_y D_x L), each derivative image extended by half-sample
+ * reflection at the border.
+ *   levels   (device) input, N x H x W float32.
+ *   det      (device) output, N x H x W float32; must not alias levels.
+ */
+kaze_status kaze_detector_response(const float* levels, int W, int H,
+                                   const kaze_params* p, float* det,
+                                   void* stream);
+
+/*
+ * 3x3x3 non-maximum suppression (Sec. II-B, the 3x3 cross-level window):
+ * (x, y, i) is reported iff 1 <= i <= N-2, 1 <= x <= W-2, 1 <= y <= H-2,
+ * det_i(x, y) > det_threshold and det_i(x, y) is strictly greater than its
+ * 26 neighbours in levels i-1, i, i+1.
+ *   det      (device) input, N x H x W float32.
+ *   kps      (device) output array of `capacity` keypoints (may be NULL if
+ *            capacity is 0).  Only min(*count, capacity) entries are
+ *            written, in unspecified order.
+ *   count    (device) output, 1 int: the number of extrema found, which may
+ *            exceed capacity.  It is reset by the call itself.
+ */
+kaze_status kaze_find_extrema(const float* det, int W, int H,
+                              const kaze_params* p, kaze_keypoint* kps,
+                              int capacity, int* count, void* stream);
+
+/* Message for the most recent non-OK status returned on this thread. */
+const char* kaze_last_error(void);
+
+/*
+ * Kernel timing hook for measurement.  kaze_profile_begin(names) makes every
+ * following launch of the listed kernels (comma-separated names from
+ * kaze_kernel_names()) record a pair of hipEvents around it on its stream,
+ * up to 65536 launches.  kaze_profile_end() stops recording and reports,
+ * after synchronising on the recorded events, the number of launches and
+ * their summed duration in milliseconds.  Not thread safe.
+ */
+kaze_status kaze_profile_begin(const char* kernel_names);
+kaze_status kaze_profile_end(int* launches, double* total_ms);
+
+/* Comma-separated names of the library's kernels. */
+const char* kaze_kernel_names(void);
+
+/*
+ * Streaming copy of n floats (device to device) with the library's own
+ * vector-load kernel: a measurement of attainable HBM bandwidth and a
+ * reference point for hardware byte counters.
+ */
+kaze_status kaze_copy_f32(const float* src, float* dst, size_t n, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KAZE_H */

@@ -1,0 +1,182 @@
+// Internal declarations shared by the HIP translation units of libkaze.
+//
+// Numerical building blocks used by more than one kernel:
+//  * half-sample symmetric index reflection (the border rule of every
+//    stencil, consistent with the zero-flux boundary of Eq. 4),
+//  * the tridiagonal row of one AOS line system in increment form,
+//  * the chunk reduction and the wavefront parallel cyclic reduction (PCR)
+//    of the partitioned tridiagonal solver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kaze {
+
+constexpr int kMaxLevels = 64;
+constexpr int kMaxRadius = 16;   // Gaussian radius ceil(3 sigma)
+constexpr int kMaxStep = 8;      // Scharr step of the detector
+constexpr int kWave = 64;        // CDNA wavefront
+
+// Symmetric filter taps w[0..2r] (w[r] is the centre).
+struct Taps {
+    int r;
+    float w[2 * kMaxRadius + 1];
+};
+
+// Per-level constants of the detector response (Eq. 8).
+struct DetLevels {
+    int step[kMaxLevels];    // Scharr step round(sigma_n)
+    float sn2[kMaxLevels];   // sigma_n^2
+};
+
+// Half-sample symmetric reflection of index i into [0, n):
+// -1 -> 0, -2 -> 1, n -> n-1, n+1 -> n-2, periodic with period 2n.
+__device__ __forceinline__ int reflect_index(int i, int n) {
+    if (i >= 0 && i < n) return i;
+    const int p = 2 * n;
+    i %= p;
+    if (i < 0) i += p;
+    return i < n ? i : p - 1 - i;
+}
+
+// One row of a tridiagonal system: a*x[j-1] + b*x[j] + c*x[j+1] = d.
+struct Eq {
+    float a, b, c, d;
+};
+
+__device__ __forceinline__ Eq eq_identity() { return Eq{0.f, 1.f, 0.f, 0.f}; }
+
+// Row j of (I - 2 tau A(g)) delta = 2 tau A(g) L, the AOS line system in
+// increment form (delta = u - L).  wl, wr are the coupling weights
+// tau*(g[j-1]+g[j]) and tau*(g[j]+g[j+1]) (zero across the line ends) and
+// dl = L[j-1]-L[j], dr = L[j+1]-L[j].
+__device__ __forceinline__ Eq aos_row(float wl, float wr, float dl, float dr) {
+    return Eq{-wl, 1.f + wl + wr, -wr, wl * dl + wr * dr};
+}
+
+// Parallel cyclic reduction step: eliminate the couplings of e through the
+// neighbouring equations lo (below) and up (above).
+__device__ __forceinline__ Eq pcr_reduce(const Eq& e, const Eq& lo, const Eq& up) {
+    const float k1 = e.a / lo.b;
+    const float k2 = e.c / up.b;
+    Eq r;
+    r.a = -k1 * lo.a;
+    r.b = e.b - k1 * lo.c - k2 * up.a;
+    r.c = -k2 * up.c;
+    r.d = e.d - k1 * lo.d - k2 * up.d;
+    return r;
+}
+
+__device__ __forceinline__ float lane_read(float v, int src_lane) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src_lane << 2, __float_as_int(v)));
+}
+
+__device__ __forceinline__ Eq lane_read(const Eq& e, int src_lane) {
+    return Eq{lane_read(e.a, src_lane), lane_read(e.b, src_lane),
+              lane_read(e.c, src_lane), lane_read(e.d, src_lane)};
+}
+
+// Solve the interface system of a partitioned line on one wavefront.
+// Lane l owns chunk l and holds the reduced equations of the chunk's first
+// unknown (e0, index 2l) and last unknown (e1, index 2l+1); together they
+// form a tridiagonal system of 2*64 unknowns (lanes without a chunk hold
+// identity rows).  Must be called by all 64 lanes.  Returns the first and
+// last unknown of the lane's chunk.
+__device__ __forceinline__ void wave_pcr_pairs(Eq e0, Eq e1, int lane, float& z0, float& z1) {
+    // stride 1: e0 couples to the previous chunk's last (lane-1, e1) and the
+    // own last (e1); e1 couples to the own first (e0) and the next chunk's
+    // first (lane+1, e0).
+    {
+        Eq prev1 = lane_read(e1, lane > 0 ? lane - 1 : 0);
+        Eq next0 = lane_read(e0, lane < kWave - 1 ? lane + 1 : kWave - 1);
+        if (lane == 0) prev1 = eq_identity();
+        if (lane == kWave - 1) next0 = eq_identity();
+        const Eq n0 = pcr_reduce(e0, prev1, e1);
+        const Eq n1 = pcr_reduce(e1, e0, next0);
+        e0 = n0;
+        e1 = n1;
+    }
+    // Now the even and the odd unknowns form two independent tridiagonal
+    // systems with one equation per lane; reduce both with lane strides
+    // 1, 2, ..., 32.
+#pragma unroll
+    for (int s = 1; s < kWave; s <<= 1) {
+        const int lo_l = lane - s, up_l = lane + s;
+        Eq lo0 = lane_read(e0, lo_l >= 0 ? lo_l : 0);
+        Eq up0 = lane_read(e0, up_l < kWave ? up_l : kWave - 1);
+        Eq lo1 = lane_read(e1, lo_l >= 0 ? lo_l : 0);
+        Eq up1 = lane_read(e1, up_l < kWave ? up_l : kWave - 1);
+        if (lo_l < 0) { lo0 = eq_identity(); lo1 = eq_identity(); }
+        if (up_l >= kWave) { up0 = eq_identity(); up1 = eq_identity(); }
+        const Eq n0 = pcr_reduce(e0, lo0, up0);
+        const Eq n1 = pcr_reduce(e1, lo1, up1);
+        e0 = n0;
+        e1 = n1;
+    }
+    z0 = e0.d / e0.b;
+    z1 = e1.d / e1.b;
+}
+
+}  // namespace kaze
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (each returns the launch status).
+// ---------------------------------------------------------------------------
+namespace kaze {
+
+enum KernelId {
+    K_GAUSS = 0,
+    K_GRAD,
+    K_HIST,
+    K_KSELECT,
+    K_GFROM,
+    K_COND,
+    K_AOS_ROWS,
+    K_AOS_COL_REDUCE,
+    K_AOS_COL_IFACE,
+    K_AOS_COL_FINAL,
+    K_DET,
+    K_NMS,
+    K_FILL,
+    K_COPY,
+    K_COUNT
+};
+
+// Column chunk height of the partitioned column solve for an H-row image.
+int col_chunk_rows(int H);
+// Lanes and elements per lane of the row solve for a W-wide image.
+void row_partition(int W, int* lanes, int* per_lane);
+
+hipError_t launch_gauss(const float* src, int ld_src, float* dst, int W, int H,
+                        const Taps& taps, hipStream_t s);
+// mode 0: g2, 1: g1, 2: squared gradient magnitude + running max of |grad|
+// k is read from k_dev, or taken from k_host when k_dev is NULL.
+hipError_t launch_cond(const float* L, float* out, int W, int H, const Taps& taps,
+                       const float* k_dev, float k_host, int mode, unsigned* hmax_bits,
+                       hipStream_t s);
+hipError_t launch_hist(const float* m2, int n, const unsigned* hmax_bits, unsigned* hist,
+                       int nbins, hipStream_t s);
+hipError_t launch_kselect(const unsigned* hist, int nbins, const unsigned* hmax_bits,
+                          unsigned long long pct_mant, int pct_shift, float* k_out,
+                          hipStream_t s);
+hipError_t launch_g_from_m2(float* buf, int n, const float* k_dev, int mode, hipStream_t s);
+hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t s);
+hipError_t launch_fill_f32(float* p, int n, float v, hipStream_t s);
+
+hipError_t launch_aos_rows(const float* L, const float* g, float* dx, int W, int H,
+                           float tau, hipStream_t s);
+hipError_t launch_aos_col_reduce(const float* L, const float* g, float* red, int W, int H,
+                                 float tau, hipStream_t s);
+hipError_t launch_aos_col_iface(const float* red, float* z, int W, int H, hipStream_t s);
+hipError_t launch_aos_col_final(const float* L, const float* g, const float* z,
+                                const float* dx, float* Lnext, int W, int H, float tau,
+                                hipStream_t s);
+
+hipError_t launch_det(const float* levels, float* det, int W, int H, int N,
+                      const DetLevels& dl, hipStream_t s);
+hipError_t launch_nms(const float* det, int W, int H, int N, float threshold, void* kps,
+                      int capacity, int* count, hipStream_t s);
+hipError_t launch_copy(const float* src, float* dst, size_t n, hipStream_t s);
+
+}  // namespace kaze

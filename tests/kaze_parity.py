@@ -1,0 +1,42 @@
+"""Parity helpers shared by the GPU tests (comparison rules only; no method
+arithmetic)."""
+import numpy as np
+
+# Per-level bound on max |L_gpu - L_oracle| for images in [0, 1].
+LEVEL_TOL = 1e-4
+# Keypoints present on one side only are excused when the oracle response is
+# this close to the threshold or to one of its 26 neighbours.
+EXCUSE = 1e-5
+
+
+def note(msg):
+    print(msg, flush=True)
+
+
+def neighbours26(det, lev, y, x):
+    out = []
+    for dl in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if (dl, dy, dx) != (0, 0, 0):
+                    out.append(det[lev + dl, y + dy, x + dx])
+    return np.array(out)
+
+
+def excused(det_orc, p, threshold):
+    lev, y, x = (int(v) for v in p)
+    v = det_orc[lev, y, x]
+    if abs(v - threshold) < EXCUSE:
+        return True
+    nb = neighbours26(det_orc, lev, y, x)
+    return bool(np.min(np.abs(v - nb)) < EXCUSE)
+
+
+def compare_keypoints(kp_gpu, kp_orc, det_orc, threshold):
+    """Sets on (level, y, x) must agree up to excused points.  Returns
+    (n_common, unexcused_gpu_only, unexcused_oracle_only)."""
+    g = {tuple(int(v) for v in r[:3]) for r in kp_gpu}
+    o = {tuple(int(v) for v in r[:3]) for r in kp_orc}
+    bad_g = [p for p in g - o if not excused(det_orc, p, threshold)]
+    bad_o = [p for p in o - g if not excused(det_orc, p, threshold)]
+    return len(g & o), bad_g, bad_o

@@ -1,0 +1,156 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+symbol, lays out its structs like a C compiler does, and validates arguments
+before touching the GPU.  No kernel is launched here."""
+import ctypes
+import os
+import re
+import subprocess
+import textwrap
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kaze.h")
+
+
+def _gpu_visible():
+    import torch
+    return torch.cuda.device_count() > 0
+
+
+# These tests hand fake device addresses to entry points that must reject
+# them before any launch; they only run where no kernel could execute.
+no_gpu_only = pytest.mark.skipif(_gpu_visible(), reason="fake-pointer tests run without a GPU")
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_1706_06750_amd import build as B
+    if not os.path.exists(B.LIB_PATH):
+        B.build()
+    from paper_1706_06750_amd import kaze
+    return kaze
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*[\w\s\*]+?\b(kaze_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(K):
+    names = declared_functions()
+    assert len(names) >= 14
+    assert sorted(K.EXPORTS) == names
+    lib = ctypes.CDLL(K.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_struct_layout_matches_c_compiler(K, tmp_path):
+    prog = tmp_path / "layout.c"
+    prog.write_text(textwrap.dedent("""
+        #include <stdio.h>
+        #include <stddef.h>
+        #include "kaze.h"
+        int main(void) {
+          printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(kaze_params),
+                 offsetof(kaze_params, octaves), offsetof(kaze_params, sublevels),
+                 offsetof(kaze_params, sigma0), offsetof(kaze_params, sigma_cond),
+                 offsetof(kaze_params, diffusivity), offsetof(kaze_params, k_bins),
+                 offsetof(kaze_params, k_percentile), offsetof(kaze_params, k_override),
+                 offsetof(kaze_params, det_threshold), sizeof(kaze_keypoint));
+          return 0;
+        }"""))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog),
+                    "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    P = K.kaze_params
+    want = [ctypes.sizeof(P)] + [getattr(P, f).offset for f in
+                                 ("octaves", "sublevels", "sigma0", "sigma_cond", "diffusivity",
+                                  "k_bins", "k_percentile", "k_override", "det_threshold")]
+    want.append(ctypes.sizeof(K.kaze_keypoint))
+    assert got == want
+
+
+def test_defaults_and_schedule_match_oracle(K):
+    p = K.kaze_default_params()
+    assert (p.octaves, p.sublevels, p.k_bins, p.diffusivity) == (4, 4, 300, K.KAZE_G2)
+    assert (p.sigma0, p.sigma_cond, p.k_percentile, p.det_threshold) == (1.6, 1.0, 0.7, 0.001)
+    sch = K.kaze_schedule(p)
+    ref = O.level_schedule(1.6, 4, 4)
+    assert len(sch) == len(ref) == K.kaze_num_levels(p)
+    for i, (a, b) in enumerate(zip(sch, ref)):
+        assert a["sigma"] == pytest.approx(b["sigma"], rel=1e-15)
+        assert a["t"] == pytest.approx(b["t"], rel=1e-15)
+        if i:
+            assert a["tau"] == pytest.approx(b["t"] - ref[i - 1]["t"], rel=1e-14)
+        sn = b["sigma"] / 2 ** b["o"]
+        assert a["sigma_norm"] == pytest.approx(sn, rel=1e-15)
+        assert a["deriv_step"] == O.derivative_step(sn)
+
+
+def test_workspace_bytes(K):
+    p = K.kaze_default_params()
+    w = K.kaze_workspace_bytes(1920, 1200, p)
+    assert w >= 2 * 1920 * 1200 * 4 and w % 256 == 0
+    assert K.kaze_workspace_bytes(7, 100, p) == 0
+    assert K.kaze_workspace_bytes(100, 5000, p) == 0
+    bad = K.kaze_default_params(octaves=0)
+    assert K.kaze_workspace_bytes(64, 64, bad) == 0
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("octaves", 0, -1), ("sublevels", 0, -1), ("octaves", 17, -4), ("sigma0", 0.0, -1),
+    ("sigma0", 6.0, -4), ("diffusivity", 3, -1), ("k_percentile", 0.0, -1),
+    ("k_percentile", 1.5, -1), ("k_bins", 0, -1), ("k_bins", 5000, -1),
+])
+@no_gpu_only
+def test_invalid_params_rejected_before_launch(K, field, value, status):
+    p = K.kaze_default_params(**{field: value})
+    with pytest.raises(K.KazeError) as e:
+        K.kaze_build_scale_space(16, 64, 64, 64, p, 16, 16, 256, 1 << 30, 0)
+    assert e.value.status == status
+
+
+@no_gpu_only
+def test_invalid_buffers_rejected_before_launch(K):
+    p = K.kaze_default_params()
+    ws = K.kaze_workspace_bytes(64, 64, p)
+    cases = [
+        dict(img=0), dict(levels=0), dict(k_out=0), dict(W=7), dict(H=5000),
+        dict(ld=63), dict(ws=0), dict(ws=128 + 256), dict(ws_bytes=ws - 1), dict(img=18),
+    ]
+    for c in cases:
+        a = dict(img=256, W=64, H=64, ld=64, levels=512, k_out=1024, ws=4096, ws_bytes=ws)
+        a.update(c)
+        with pytest.raises(K.KazeError) as e:
+            K.kaze_build_scale_space(a["img"], a["W"], a["H"], a["ld"], p, a["levels"],
+                                     a["k_out"], a["ws"], a["ws_bytes"], 0)
+        assert e.value.status in (-1, -2, -4), c
+    with pytest.raises(K.KazeError):
+        K.kaze_find_extrema(256, 64, 64, p, 0, 5, 512, 0)       # capacity without buffer
+    with pytest.raises(K.KazeError):
+        K.kaze_find_extrema(256, 64, 64, p, 0, -1, 512, 0)
+    with pytest.raises(K.KazeError):
+        K.kaze_detector_response(0, 64, 64, p, 512, 0)
+    with pytest.raises(K.KazeError):
+        K.kaze_aos_step(256, 512, 64, 64, 0.0, 1024, 4096, ws, 0)  # tau must be > 0
+    with pytest.raises(K.KazeError):
+        K.kaze_conductivity(256, 64, 64, p, -1.0, 512, 0)
+    with pytest.raises(K.KazeError):
+        K.kaze_copy_f32(8, 1024, 16, 0)                         # misaligned
+    with pytest.raises(K.KazeError):
+        K.kaze_profile_begin("no_such_kernel")
+
+
+def test_kernel_names(K):
+    names = K.kaze_kernel_names()
+    for n in ("aos_rows", "aos_col_reduce", "aos_col_iface", "aos_col_final", "cond",
+              "det", "nms"):
+        assert n in names

@@ -1,0 +1,208 @@
+"""GPU path vs the FP64 oracle, through the C ABI.
+
+Stage-isolated tests feed each GPU stage the oracle's own (FP32-rounded)
+inputs, so they measure one stage's FP32 error; end-to-end tests run the
+whole path and apply the per-level bound LEVEL_TOL and the keypoint rule.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from synthetic import kaze_image
+from kaze_parity import LEVEL_TOL, compare_keypoints, note
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def run_gpu(K, img, params=None, capacity=1 << 16, stream=None):
+    H, W = img.shape
+    kz = K.Kaze(W, H, params, capacity=capacity)
+    x = dev(img)
+    kz.run(x, stream)
+    torch.cuda.synchronize()
+    return kz
+
+
+def run_oracle(img, **kw):
+    lev, k = O.build_scale_space(img.astype(np.float64), **kw)
+    det = O.detector_response(lev)
+    return lev, k, det
+
+
+def det_tolerance(level_err, sn2, s):
+    """Bound on |det_gpu - det_orc| given the level error eps: each second
+    derivative D_s D_s moves by at most eps/s^2 and is at most 1/(2 s^2) in
+    size for values in [0, 1], so det = sn^2 (Lxx Lyy - Lxy^2) moves by at
+    most sn^2 * 3 * (eps/s^2) * (1/(2 s^2)) * 2 (+ eps^2 terms); a floor of
+    1e-7 sn^2 covers FP32 rounding of the detector itself."""
+    return sn2 * (3.0 * level_err / s ** 4 + 1e-7)
+
+
+# ---------------------------------------------------------------- stages
+@pytest.mark.parametrize("W,H,seed", [(320, 240, 1), (67, 45, 5), (1920, 1200, 2)])
+def test_conductivity_stage(gpu_lib, W, H, seed):
+    K = gpu_lib
+    note(f"[conductivity] {W}x{H} seed {seed}")
+    img = kaze_image(W, H, seed).astype(np.float64)
+    L = f32(O.gaussian_smooth(img, 1.6))
+    k = O.contrast_factor(L)
+    p = K.kaze_default_params()
+    g = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    K.kaze_conductivity(dev(L), W, H, p, k, g)
+    torch.cuda.synchronize()
+    ref = O.conductivity_g2(L, float(np.float32(k)))
+    err = np.max(np.abs(g.cpu().numpy() - ref))
+    note(f"  max|g_gpu - g_orc| = {err:.3e}")
+    assert err < 2e-6
+
+
+@pytest.mark.parametrize("W,H,seed", [(320, 240, 1), (67, 45, 5), (1920, 1200, 2),
+                                      (130, 1100, 7), (64, 2100, 8), (4000, 20, 9),
+                                      (8192, 9, 10), (8, 8, 11)])
+def test_aos_step_stage(gpu_lib, W, H, seed):
+    K = gpu_lib
+    img = kaze_image(W, H, seed).astype(np.float64)
+    L = f32(O.gaussian_smooth(img, 1.6))
+    k = O.contrast_factor(L)
+    g = f32(O.conductivity_g2(L, k))
+    p = K.kaze_default_params()
+    ws_bytes = K.kaze_workspace_bytes(W, H, p)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    out = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    Ld, gd = dev(L), dev(g)
+    for tau in (0.5302, 5.9985, 67.8648):
+        note(f"[aos_step] {W}x{H} seed {seed} tau {tau}")
+        K.kaze_aos_step(Ld, gd, W, H, tau, out, ws, ws_bytes)
+        torch.cuda.synchronize()
+        ref = O.aos_step(L, g, tau)
+        err = np.max(np.abs(out.cpu().numpy() - ref))
+        note(f"  max|L_gpu - L_orc| = {err:.3e}")
+        assert err < 2e-6
+
+
+def test_detector_stage(gpu_lib):
+    K = gpu_lib
+    W, H = 320, 240
+    note(f"[detector] {W}x{H}")
+    lev, _ = O.build_scale_space(kaze_image(W, H, 1).astype(np.float64))
+    lev32 = f32(lev)
+    p = K.kaze_default_params()
+    det = torch.empty(lev.shape, dtype=torch.float32, device="cuda")
+    K.kaze_detector_response(dev(lev32), W, H, p, det)
+    torch.cuda.synchronize()
+    ref = O.detector_response(lev32)
+    d = det.cpu().numpy()
+    for i in range(lev.shape[0]):
+        err = np.max(np.abs(d[i] - ref[i]))
+        assert err < 1e-8, (i, err)
+
+
+# ---------------------------------------------------------------- end to end
+def check_end_to_end(K, W, H, seed, params=None, oracle_kw=None):
+    note(f"[end-to-end] {W}x{H} seed {seed} params {params and dict((f, getattr(params, f)) for f, _ in params._fields_)}")
+    img = kaze_image(W, H, seed)
+    kz = run_gpu(K, img, params)
+    lev_o, k_o, det_o = run_oracle(img, **(oracle_kw or {}))
+    k_g = float(kz.k.item())
+    note(f"  k gpu {k_g:.9g} oracle {k_o:.9g}")
+    assert k_g == pytest.approx(k_o, rel=1e-4)
+    lev_g = kz.levels.cpu().numpy()
+    det_g = kz.det.cpu().numpy()
+    sched = K.kaze_schedule(kz.p)
+    worst = 0.0
+    for i in range(kz.N):
+        e = float(np.max(np.abs(lev_g[i] - lev_o[i])))
+        de = float(np.max(np.abs(det_g[i] - det_o[i])))
+        sn2 = sched[i]["sigma_norm"] ** 2
+        note(f"  level {i:2d}: max|dL| {e:.2e}  max|ddet| {de:.2e}")
+        worst = max(worst, e)
+        assert e <= LEVEL_TOL, (i, e)
+        assert de <= det_tolerance(e, sn2, sched[i]["deriv_step"]), (i, de)
+    kp_g = kz.keypoints()
+    thr = kz.p.det_threshold
+    kp_o = O.find_extrema(det_o, thr)
+    common, bad_g, bad_o = compare_keypoints(kp_g, kp_o, det_o, thr)
+    note(f"  keypoints gpu {len(kp_g)} oracle {len(kp_o)} common {common} "
+         f"unexcused gpu-only {bad_g[:5]} oracle-only {bad_o[:5]}")
+    assert not bad_g and not bad_o
+    return worst
+
+
+def test_end_to_end_320x240(gpu_lib):
+    check_end_to_end(gpu_lib, 320, 240, 1)
+
+
+def test_end_to_end_1920x1200(gpu_lib):
+    check_end_to_end(gpu_lib, 1920, 1200, 2)
+
+
+@pytest.mark.parametrize("W,H,seed", [(8, 8, 21), (9, 13, 22), (67, 45, 23), (130, 1100, 24),
+                                      (64, 2100, 25), (4000, 20, 26), (8192, 9, 27),
+                                      (1000, 33, 28)])
+def test_end_to_end_ragged_and_extreme_shapes(gpu_lib, W, H, seed):
+    check_end_to_end(gpu_lib, W, H, seed)
+
+
+def test_k_override_and_g1(gpu_lib):
+    K = gpu_lib
+    p = K.kaze_default_params(k_override=0.004)
+    check_end_to_end(K, 320, 240, 3, p, dict(k=float(np.float32(0.004))))
+    p = K.kaze_default_params(diffusivity=K.KAZE_G1)
+    check_end_to_end(K, 320, 240, 4, p, dict(diffusivity="g1"))
+
+
+def test_constant_image(gpu_lib):
+    K = gpu_lib
+    note("[constant] 96x80")
+    img = np.full((80, 96), 0.4321, dtype=np.float32)
+    kz = run_gpu(K, img)
+    assert float(kz.k.item()) == 1.0
+    lev = kz.levels.cpu().numpy()
+    assert np.max(np.abs(lev - lev[0, 40, 40])) == 0.0
+    assert abs(lev[0, 40, 40] - 0.4321) < 1e-6
+    assert np.max(np.abs(kz.det.cpu().numpy())) == 0.0
+    assert int(kz.count.item()) == 0
+
+
+def test_deterministic_and_stream_ordered(gpu_lib):
+    K = gpu_lib
+    note("[determinism] 640x480 seed 31, default and side stream")
+    img = kaze_image(640, 480, 31)
+    a = run_gpu(K, img)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        kz = K.Kaze(640, 480)
+        x = dev(img)
+        kz.run(x, s)
+    s.synchronize()
+    assert torch.equal(a.levels, kz.levels)
+    assert torch.equal(a.det, kz.det)
+    assert np.array_equal(a.keypoints(), kz.keypoints())
+
+
+def test_capacity_overflow(gpu_lib):
+    K = gpu_lib
+    note("[capacity] 320x240 seed 1 capacity 1")
+    img = kaze_image(320, 240, 1)
+    full = run_gpu(K, img)
+    n = int(full.count.item())
+    assert n > 1
+    kps = torch.full((8, 4), -7, dtype=torch.int32, device="cuda")
+    count = torch.full((1,), 12345, dtype=torch.int32, device="cuda")
+    K.kaze_find_extrema(full.det, 320, 240, full.p, kps, 1, count)
+    torch.cuda.synchronize()
+    assert int(count.item()) == n
+    rows = kps.cpu().numpy()
+    assert (rows[1:] == -7).all()            # nothing written past the capacity
+    first = (int(rows[0, 2]), int(rows[0, 1]), int(rows[0, 0]))
+    assert first in {tuple(int(v) for v in r[:3]) for r in full.keypoints()}
