@@ -25,7 +25,7 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic HBM bytes per pixel of one AOS step: read L_{i-1} and the
 # conductivity g, write L_i (4 bytes each).
 AOS_ALGO_BYTES_PER_PX = 12
-AOS_KERNELS = ("aos_rows", "aos_col_reduce", "aos_col_iface", "aos_col_final")
+AOS_KERNELS = ("aos_reduce", "aos_iface", "aos_recover")
 
 
 def csrc_hash() -> str:
@@ -141,7 +141,7 @@ def main():
     value = args.steps / elapsed
     n_levels = kz.N
     aos_steps = (n_levels - 1) * args.steps
-    aos_us = 1e3 * ms_aos / aos_steps                 # one AOS step (4 launches)
+    aos_us = 1e3 * ms_aos / aos_steps                 # one AOS step (3 launches)
     algo_bytes = AOS_ALGO_BYTES_PER_PX * W * H
     achieved = algo_bytes / (aos_us * 1e-6) / 1e9
     traffic = traffic_from_profile(W, H)

@@ -27,8 +27,8 @@
  *     scratch lives in a caller-provided workspace of
  *     kaze_workspace_bytes() bytes (256-byte aligned).  Two calls that
  *     share a workspace must be ordered on the same stream.
- *   - Size limits: 8 <= W <= 8192, 8 <= H <= 4096, N <= 64, Gaussian radius
- *     ceil(3 sigma) <= 16, Scharr step of Eq. 8 <= 8.
+ *   - Size limits: 8 <= W, H <= 4096, N <= 64, Gaussian radius ceil(3 sigma)
+ *     <= 16 for sigma0 and <= 4 for sigma_cond, Scharr step of Eq. 8 <= 8.
  *   - Nothing throws across the ABI.
  */
 #ifndef KAZE_H

@@ -27,10 +27,8 @@ kaze_status fail(kaze_status st, const char* fmt, ...) {
 
 // ---------------------------------------------------------------- profiling
 const char* const kKernelNames[K_COUNT] = {
-    "gauss",          "grad",           "hist",           "kselect",
-    "g_from_m2",      "cond",           "aos_rows",       "aos_col_reduce",
-    "aos_col_iface",  "aos_col_final",  "det",            "nms",
-    "fill",           "copy"};
+    "gauss", "grad",        "hist",        "kselect", "cond", "aos_reduce",
+    "aos_iface", "aos_recover", "det", "nms",     "fill", "copy"};
 
 struct Profiler {
     unsigned mask = 0;  // bit i: record launches of kernel i
@@ -101,9 +99,11 @@ kaze_status check_params(const kaze_params* p) {
         return fail(KAZE_ERR_UNSUPPORTED, "at most %d levels", kMaxLevels);
     if (!(p->sigma0 > 0.0) || !(p->sigma_cond > 0.0))
         return fail(KAZE_ERR_INVALID_ARG, "sigma0 and sigma_cond must be > 0");
-    if (gauss_radius(p->sigma0) > kMaxRadius || gauss_radius(p->sigma_cond) > kMaxRadius)
-        return fail(KAZE_ERR_UNSUPPORTED, "Gaussian radius ceil(3 sigma) must be <= %d",
-                    kMaxRadius);
+    if (gauss_radius(p->sigma0) > kMaxRadius)
+        return fail(KAZE_ERR_UNSUPPORTED, "sigma0 radius ceil(3 sigma) must be <= %d", kMaxRadius);
+    if (gauss_radius(p->sigma_cond) > kMaxCondRadius)
+        return fail(KAZE_ERR_UNSUPPORTED, "sigma_cond radius ceil(3 sigma) must be <= %d",
+                    kMaxCondRadius);
     if (p->diffusivity != KAZE_G1 && p->diffusivity != KAZE_G2)
         return fail(KAZE_ERR_INVALID_ARG, "diffusivity must be KAZE_G1 or KAZE_G2");
     if (!(p->k_override > 0.0)) {
@@ -134,8 +134,9 @@ void schedule(const kaze_params* p, std::vector<Level>& lv) {
 
 kaze_status check_size(int W, int H) {
     if (W < 8 || H < 8) return fail(KAZE_ERR_INVALID_ARG, "image must be at least 8x8");
-    if (W > 8192 || H > 4096)
-        return fail(KAZE_ERR_UNSUPPORTED, "image larger than 8192x4096 (got %dx%d)", W, H);
+    if (W > kTile * kWave || H > kTile * kWave)
+        return fail(KAZE_ERR_UNSUPPORTED, "image larger than %dx%d (got %dx%d)", kTile * kWave,
+                    kTile * kWave, W, H);
     return KAZE_OK;
 }
 
@@ -150,26 +151,43 @@ kaze_status check_steps(const kaze_params* p) {
 
 // ---------------------------------------------------------------- workspace
 struct Workspace {
-    size_t g, dx, red, z, hist, hmax, total;
+    size_t g, rrow, rcol, zrow, zcol, hist, hmax, total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 Workspace layout(int W, int H, const kaze_params* p) {
     Workspace w;
-    const size_t px = (size_t)W * H;
-    const int MC = col_chunk_rows(H);
-    const size_t Pc = (size_t)((H + MC - 1) / MC);
+    const size_t ncx = (W + kTile - 1) / kTile, ncy = (H + kTile - 1) / kTile;
     const int nbins = p->k_bins > 0 ? p->k_bins : 1;
     size_t off = 0;
-    w.g = off;    off = align256(off + px * sizeof(float));
-    w.dx = off;   off = align256(off + px * sizeof(float));
-    w.red = off;  off = align256(off + (size_t)W * Pc * 8 * sizeof(float));
-    w.z = off;    off = align256(off + (size_t)W * Pc * 2 * sizeof(float));
+    w.g = off;    off = align256(off + (size_t)W * H * sizeof(float));
+    w.rrow = off; off = align256(off + (size_t)H * ncx * 8 * sizeof(float));
+    w.rcol = off; off = align256(off + (size_t)W * ncy * 8 * sizeof(float));
+    w.zrow = off; off = align256(off + (size_t)H * ncx * 2 * sizeof(float));
+    w.zcol = off; off = align256(off + (size_t)W * ncy * 2 * sizeof(float));
     w.hist = off; off = align256(off + (size_t)nbins * sizeof(unsigned));
     w.hmax = off; off = align256(off + sizeof(unsigned));
     w.total = off;
     return w;
+}
+
+ImageDesc image_desc(int W, int H, void* ws, const Workspace& w) {
+    char* base = static_cast<char*>(ws);
+    ImageDesc d;
+    d.L = nullptr;
+    d.Lnext = nullptr;
+    d.g = reinterpret_cast<float*>(base + w.g);
+    d.rrow = reinterpret_cast<float*>(base + w.rrow);
+    d.rcol = reinterpret_cast<float*>(base + w.rcol);
+    d.zrow = reinterpret_cast<float*>(base + w.zrow);
+    d.zcol = reinterpret_cast<float*>(base + w.zcol);
+    d.k = nullptr;
+    d.W = W;
+    d.H = H;
+    d.ncx = (W + kTile - 1) / kTile;
+    d.ncy = (H + kTile - 1) / kTile;
+    return d;
 }
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -188,14 +206,14 @@ void percentile_fraction(double pct, unsigned long long* mant, int* shift) {
     *shift = sh;
 }
 
-// a4-a5: rows, then the three column phases (reduce, interface, recover +
-// average) of one AOS step.
-kaze_status aos_step(const float* Lp, const float* g, int W, int H, float tau, float* Ln,
-                     float* dx, float* red, float* z, hipStream_t s) {
-    KZ_LAUNCH(K_AOS_ROWS, s, launch_aos_rows(Lp, g, dx, W, H, tau, s));
-    KZ_LAUNCH(K_AOS_COL_REDUCE, s, launch_aos_col_reduce(Lp, g, red, W, H, tau, s));
-    KZ_LAUNCH(K_AOS_COL_IFACE, s, launch_aos_col_iface(red, z, W, H, s));
-    KZ_LAUNCH(K_AOS_COL_FINAL, s, launch_aos_col_final(Lp, g, z, dx, Ln, W, H, tau, s));
+// a3-a5: (conductivity +) chunk reduction, interface solves, recovery.
+kaze_status aos_step(const ImageDesc& d, const Taps& tc, float tau, bool compute_g, int gmode,
+                     float k_host, hipStream_t s) {
+    const WorkList none{nullptr, nullptr, 0};
+    KZ_LAUNCH(K_AOS_REDUCE, s,
+              launch_aos_reduce(d, none, tc, tau, compute_g, gmode, k_host, 0, s));
+    KZ_LAUNCH(K_AOS_IFACE, s, launch_aos_iface(d, none, 0, s));
+    KZ_LAUNCH(K_AOS_RECOVER, s, launch_aos_recover(d, none, tau, 0, s));
     return KAZE_OK;
 }
 
@@ -261,11 +279,8 @@ kaze_status kaze_build_scale_space(const float* img, int W, int H, int ld_img,
                     w.total, ws_bytes);
 
     hipStream_t s = static_cast<hipStream_t>(stream);
+    ImageDesc d = image_desc(W, H, ws, w);
     char* base = static_cast<char*>(ws);
-    float* g = reinterpret_cast<float*>(base + w.g);
-    float* dx = reinterpret_cast<float*>(base + w.dx);
-    float* red = reinterpret_cast<float*>(base + w.red);
-    float* z = reinterpret_cast<float*>(base + w.z);
     unsigned* hist = reinterpret_cast<unsigned*>(base + w.hist);
     unsigned* hmax = reinterpret_cast<unsigned*>(base + w.hmax);
 
@@ -280,31 +295,26 @@ kaze_status kaze_build_scale_space(const float* img, int W, int H, int ld_img,
     // a1: base image L_0 = G_sigma0 * img
     KZ_LAUNCH(K_GAUSS, s, launch_gauss(img, ld_img, levels, W, H, t0, s));
 
-    // a2: contrast factor k
-    const bool use_hist = !(p->k_override > 0.0);
-    if (use_hist) {
+    // a2: contrast factor k from the gradient histogram of L_0
+    if (!(p->k_override > 0.0)) {
         unsigned long long mant;
         int shift;
         percentile_fraction(p->k_percentile, &mant, &shift);
         KZ_LAUNCH(K_FILL, s, launch_fill_u32(hist, p->k_bins, 0u, s));
         KZ_LAUNCH(K_FILL, s, launch_fill_u32(hmax, 1, 0u, s));
-        KZ_LAUNCH(K_GRAD, s, launch_cond(levels, g, W, H, tc, nullptr, 1.f, 2, hmax, s));
-        KZ_LAUNCH(K_HIST, s, launch_hist(g, (int)plane, hmax, hist, p->k_bins, s));
+        KZ_LAUNCH(K_GRAD, s, launch_cond(levels, d.g, W, H, tc, nullptr, 1.f, 2, hmax, s));
+        KZ_LAUNCH(K_HIST, s, launch_hist(d.g, (int)plane, hmax, hist, p->k_bins, s));
         KZ_LAUNCH(K_KSELECT, s, launch_kselect(hist, p->k_bins, hmax, mant, shift, k_out, s));
     } else {
         KZ_LAUNCH(K_FILL, s, launch_fill_f32(k_out, 1, (float)p->k_override, s));
     }
+    d.k = k_out;
 
-    // a3-a5: one AOS step per level
+    // a3-a5: one AOS step per level, conductivity from the previous level
     for (int i = 1; i < N; ++i) {
-        const float* Lp = levels + plane * (i - 1);
-        float* Ln = levels + plane * i;
-        const float tau = (float)lv[i].tau;
-        if (i == 1 && use_hist)
-            KZ_LAUNCH(K_GFROM, s, launch_g_from_m2(g, (int)plane, k_out, gmode, s));
-        else
-            KZ_LAUNCH(K_COND, s, launch_cond(Lp, g, W, H, tc, k_out, 1.f, gmode, nullptr, s));
-        st = aos_step(Lp, g, W, H, tau, Ln, dx, red, z, s);
+        d.L = levels + plane * (i - 1);
+        d.Lnext = levels + plane * i;
+        st = aos_step(d, tc, (float)lv[i].tau, true, gmode, 1.f, s);
         if (st != KAZE_OK) return st;
     }
     return KAZE_OK;
@@ -340,9 +350,11 @@ kaze_status kaze_aos_step(const float* L, const float* g, int W, int H, double t
     if (!ws || !aligned(ws, 256) || ws_bytes < w.total)
         return fail(KAZE_ERR_WORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
                     w.total, ws_bytes);
-    char* base = static_cast<char*>(ws);
-    return aos_step(L, g, W, H, (float)tau, L_next, reinterpret_cast<float*>(base + w.dx),
-                    reinterpret_cast<float*>(base + w.red), reinterpret_cast<float*>(base + w.z),
+    ImageDesc d = image_desc(W, H, ws, w);
+    d.L = L;
+    d.Lnext = L_next;
+    d.g = const_cast<float*>(g);  // read only when the conductivity is given
+    return aos_step(d, gauss_taps(p.sigma_cond), (float)tau, false, 0, 1.f,
                     static_cast<hipStream_t>(stream));
 }
 

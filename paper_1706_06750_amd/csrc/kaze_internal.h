@@ -121,21 +121,49 @@ __device__ __forceinline__ void wave_pcr_pairs(Eq e0, Eq e1, int lane, float& z0
 }  // namespace kaze
 
 // ---------------------------------------------------------------------------
-// Host-side launchers (each returns the launch status).
+// Tile-partitioned AOS step: data shared by the kernels of one step.
 // ---------------------------------------------------------------------------
 namespace kaze {
+
+constexpr int kTile = 64;        // tile edge = chunk length of every line solve
+constexpr int kMaxCondRadius = 8;  // Gaussian radius of sigma_cond in the fused kernel
+
+// One image of an AOS step.  Row line y is cut into ncx chunks of kTile
+// pixels (tile columns), column line x into ncy chunks (tile rows).
+struct ImageDesc {
+    const float* L;   // level i-1, W x H, pitch W
+    float* Lnext;     // level i
+    float* g;         // conductivity of L (written or read, see the kernel)
+    float* rrow;      // reduced interface rows of the row lines, [H][ncx][8]
+    float* rcol;      // ... of the column lines, [W][ncy][8]
+    float* zrow;      // first/last unknown of every row chunk, [H][ncx][2]
+    float* zcol;      // ... of every column chunk, [W][ncy][2]
+    const float* k;   // contrast factor (device scalar); NULL: use the host value
+    int W, H, ncx, ncy;
+};
+
+// Work list of a batched launch: entry t names an image and a tile (or a
+// line) inside it.  With a NULL list the launch covers image 0 only and
+// entry t is tile/line t of the descriptor passed by value.
+struct WorkList {
+    const ImageDesc* descs;  // device table, one per image (or NULL)
+    const int2* items;       // {image, local tile or line index}
+    int count;
+};
+
+inline int tiles_of(int W, int H) {
+    return ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
+}
 
 enum KernelId {
     K_GAUSS = 0,
     K_GRAD,
     K_HIST,
     K_KSELECT,
-    K_GFROM,
     K_COND,
-    K_AOS_ROWS,
-    K_AOS_COL_REDUCE,
-    K_AOS_COL_IFACE,
-    K_AOS_COL_FINAL,
+    K_AOS_REDUCE,
+    K_AOS_IFACE,
+    K_AOS_RECOVER,
     K_DET,
     K_NMS,
     K_FILL,
@@ -143,15 +171,11 @@ enum KernelId {
     K_COUNT
 };
 
-// Column chunk height of the partitioned column solve for an H-row image.
-int col_chunk_rows(int H);
-// Lanes and elements per lane of the row solve for a W-wide image.
-void row_partition(int W, int* lanes, int* per_lane);
-
 hipError_t launch_gauss(const float* src, int ld_src, float* dst, int W, int H,
                         const Taps& taps, hipStream_t s);
-// mode 0: g2, 1: g1, 2: squared gradient magnitude + running max of |grad|
-// k is read from k_dev, or taken from k_host when k_dev is NULL.
+// Conductivity of L on 64x64 tiles (the same code as the fused AOS kernel).
+// mode 0: g2, 1: g1, 2: squared gradient magnitude and the running maximum
+// of |grad| into hmax_bits.  k is read from k_dev, or k_host if NULL.
 hipError_t launch_cond(const float* L, float* out, int W, int H, const Taps& taps,
                        const float* k_dev, float k_host, int mode, unsigned* hmax_bits,
                        hipStream_t s);
@@ -160,18 +184,21 @@ hipError_t launch_hist(const float* m2, int n, const unsigned* hmax_bits, unsign
 hipError_t launch_kselect(const unsigned* hist, int nbins, const unsigned* hmax_bits,
                           unsigned long long pct_mant, int pct_shift, float* k_out,
                           hipStream_t s);
-hipError_t launch_g_from_m2(float* buf, int n, const float* k_dev, int mode, hipStream_t s);
 hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int n, float v, hipStream_t s);
 
-hipError_t launch_aos_rows(const float* L, const float* g, float* dx, int W, int H,
-                           float tau, hipStream_t s);
-hipError_t launch_aos_col_reduce(const float* L, const float* g, float* red, int W, int H,
-                                 float tau, hipStream_t s);
-hipError_t launch_aos_col_iface(const float* red, float* z, int W, int H, hipStream_t s);
-hipError_t launch_aos_col_final(const float* L, const float* g, const float* z,
-                                const float* dx, float* Lnext, int W, int H, float tau,
-                                hipStream_t s);
+// AOS step in three launches.  reduce: (conductivity if compute_g, else g
+// is read) + chunk reduction of every row and column chunk; iface: the
+// interface system of every line by wavefront PCR; recover: interior of
+// every chunk and L_next = L + (delta_x + delta_y)/2.
+// grid_cap > 0 caps the grid (persistent blocks looping over the list).
+hipError_t launch_aos_reduce(const ImageDesc& d0, const WorkList& w, const Taps& tc,
+                             float tau, bool compute_g, int gmode, float k_host, int grid_cap,
+                             hipStream_t s);
+hipError_t launch_aos_iface(const ImageDesc& d0, const WorkList& w, int grid_cap,
+                            hipStream_t s);
+hipError_t launch_aos_recover(const ImageDesc& d0, const WorkList& w, float tau, int grid_cap,
+                              hipStream_t s);
 
 hipError_t launch_det(const float* levels, float* det, int W, int H, int N,
                       const DetLevels& dl, hipStream_t s);

@@ -6,6 +6,7 @@
 // applied to that extension is itself half-sample symmetric, so halo values
 // of an intermediate (smoothed) image equal the reflected interior values.
 #include "kaze_internal.h"
+#include "tile_cond.h"
 
 namespace kaze {
 namespace {
@@ -48,92 +49,56 @@ __global__ __launch_bounds__(BX* BY) void gauss_kernel(const float* __restrict__
     }
 }
 
-// Squared Scharr gradient magnitude of G_sigma_cond * L on one tile, then
+// Conductivity of L on 64x64 tiles with the same LDS pipeline as the fused
+// AOS reduction (tile_cond.h):
 // mode 0: g2 = 1/(1 + |grad|^2/k^2)   (Eq. 3)
 // mode 1: g1 = exp(-|grad|^2/k^2)     (Eq. 3)
 // mode 2: |grad|^2, and the running maximum of |grad| (for the histogram).
-__global__ __launch_bounds__(BX* BY) void cond_kernel(const float* __restrict__ L,
-                                                        float* __restrict__ out, int W, int H,
-                                                        Taps taps, const float* __restrict__ k_dev,
-                                                        float k_host, int mode,
-                                                        unsigned* __restrict__ hmax_bits) {
-    constexpr int RH = kMaxRadius + 1;
-    __shared__ float s_in[(TY + 2 * RH) * (TX + 2 * RH)];
-    __shared__ float s_h[(TY + 2 * RH) * (TX + 2)];
-    __shared__ float s_s[(TY + 2) * (TX + 2)];
-    __shared__ float s_max[BX * BY / kWave];
-    const int r = taps.r;
-    const int rh = r + 1;
-    const int iw = TX + 2 * rh, ih = TY + 2 * rh;
-    const int tx0 = blockIdx.x * TX, ty0 = blockIdx.y * TY;
-    const int tx = threadIdx.x, ty = threadIdx.y;
-
-    for (int ly = ty; ly < ih; ly += BY) {
-        const int gy = reflect_index(ty0 + ly - rh, H);
-        const float* row = L + (size_t)gy * W;
-        for (int lx = tx; lx < iw; lx += BX)
-            s_in[ly * iw + lx] = row[reflect_index(tx0 + lx - rh, W)];
-    }
+__global__ __launch_bounds__(256) void cond_kernel(const float* __restrict__ L,
+                                                     float* __restrict__ out, int W, int H,
+                                                     Taps taps, const float* __restrict__ k_dev,
+                                                     float k_host, int mode,
+                                                     unsigned* __restrict__ hmax_bits) {
+    extern __shared__ float smem[];
+    __shared__ float s_max[256 / kWave];
+    const CondTile ct = cond_tile(taps.r);
+    float* sL = smem;
+    float* sH = smem + ct.offH;
+    float* sS = smem + ct.offS;
+    const int ncx = (W + kTile - 1) / kTile;
+    const int tx0 = (blockIdx.x % ncx) * kTile, ty0 = (blockIdx.x / ncx) * kTile;
+    load_L_ring(L, W, H, tx0, ty0, sL, ct);
     __syncthreads();
-    // horizontal pass on columns -1..TX of the tile
-    constexpr int HW = TX + 2;
-    for (int ly = ty; ly < ih; ly += BY) {
-        for (int lx = tx; lx < HW; lx += BX) {
-            float acc = 0.f;
-            for (int j = 0; j <= 2 * r; ++j) acc += taps.w[j] * s_in[ly * iw + lx + j];
-            s_h[ly * HW + lx] = acc;
-        }
-    }
-    __syncthreads();
-    // vertical pass on rows -1..TY
-    for (int ly = ty; ly < TY + 2; ly += BY) {
-        for (int lx = tx; lx < HW; lx += BX) {
-            float acc = 0.f;
-            for (int j = 0; j <= 2 * r; ++j) acc += taps.w[j] * s_h[(ly + j) * HW + lx];
-            s_s[ly * HW + lx] = acc;
-        }
-    }
+    smooth_tile(sL, sH, sS, ct, taps);
     __syncthreads();
     const float k = (mode == 2) ? 1.f : (k_dev ? k_dev[0] : k_host);
     const float inv_k2 = 1.f / (k * k);
-    const int gx = tx0 + tx;
     float local_max = 0.f;
-    for (int ly = ty; ly < TY; ly += BY) {
-        const int cy = ly + 1, cx = tx + 1;
-        // Scharr: central difference /2 across, [3 10 3]/16 along
-        const float dxm = 0.5f * (s_s[(cy - 1) * HW + cx + 1] - s_s[(cy - 1) * HW + cx - 1]);
-        const float dx0 = 0.5f * (s_s[cy * HW + cx + 1] - s_s[cy * HW + cx - 1]);
-        const float dxp = 0.5f * (s_s[(cy + 1) * HW + cx + 1] - s_s[(cy + 1) * HW + cx - 1]);
-        const float dym = 0.5f * (s_s[(cy + 1) * HW + cx - 1] - s_s[(cy - 1) * HW + cx - 1]);
-        const float dy0 = 0.5f * (s_s[(cy + 1) * HW + cx] - s_s[(cy - 1) * HW + cx]);
-        const float dyp = 0.5f * (s_s[(cy + 1) * HW + cx + 1] - s_s[(cy - 1) * HW + cx + 1]);
-        const float lx = 0.1875f * dxm + 0.625f * dx0 + 0.1875f * dxp;
-        const float ly_ = 0.1875f * dym + 0.625f * dy0 + 0.1875f * dyp;
-        const float m2 = lx * lx + ly_ * ly_;
-        const int gy = ty0 + ly;
-        const bool in = gx < W && gy < H;
+    for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x) {
+        const int ly = i / kTile, lx = i % kTile;
+        const int y = ty0 + ly, x = tx0 + lx;
+        if (y >= H || x >= W) continue;
+        const float m2 = scharr_m2(sS, ct.pS, ly + 1, lx + 1);
         float v;
-        if (mode == 0)
-            v = 1.f / (1.f + m2 * inv_k2);
-        else if (mode == 1)
-            v = expf(-m2 * inv_k2);
-        else {
+        if (mode == 2) {
             v = m2;
-            if (in) local_max = fmaxf(local_max, sqrtf(m2));
+            local_max = fmaxf(local_max, sqrtf(m2));
+        } else {
+            v = diffusivity(m2, inv_k2, mode);
         }
-        if (in) out[(size_t)gy * W + gx] = v;
+        out[(size_t)y * W + x] = v;
     }
     if (mode == 2) {
         // wavefront max, then one atomic per block (|grad| >= 0, so the
         // float bit pattern orders like an unsigned integer)
-        for (int off = 32; off > 0; off >>= 1)
+        for (int off = kWave / 2; off > 0; off >>= 1)
             local_max = fmaxf(local_max, __shfl_xor(local_max, off, kWave));
-        const int t = ty * BX + tx;
+        const int t = threadIdx.x;
         if ((t & (kWave - 1)) == 0) s_max[t / kWave] = local_max;
         __syncthreads();
         if (t == 0) {
             float m = s_max[0];
-            for (int i = 1; i < BX * BY / kWave; ++i) m = fmaxf(m, s_max[i]);
+            for (int i = 1; i < 256 / kWave; ++i) m = fmaxf(m, s_max[i]);
             atomicMax(hmax_bits, __float_as_uint(m));
         }
     }
@@ -194,16 +159,6 @@ __global__ void kselect_kernel(const unsigned* __restrict__ hist, int nbins,
     k_out[0] = (hmax * (float)(b + 1)) / (float)nbins;
 }
 
-__global__ __launch_bounds__(256) void g_from_m2_kernel(float* __restrict__ buf, int n,
-                                                          const float* __restrict__ k_dev, int mode) {
-    const float k = k_dev[0];
-    const float inv_k2 = 1.f / (k * k);
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const float m2 = buf[i];
-        buf[i] = (mode == 0) ? 1.f / (1.f + m2 * inv_k2) : expf(-m2 * inv_k2);
-    }
-}
-
 __global__ __launch_bounds__(256) void fill_u32_kernel(unsigned* p, int n, unsigned v) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
@@ -244,9 +199,9 @@ hipError_t launch_gauss(const float* src, int ld_src, float* dst, int W, int H,
 hipError_t launch_cond(const float* L, float* out, int W, int H, const Taps& taps,
                        const float* k_dev, float k_host, int mode, unsigned* hmax_bits,
                        hipStream_t s) {
-    dim3 grid((W + TX - 1) / TX, (H + TY - 1) / TY), block(BX, BY);
-    hipLaunchKernelGGL(cond_kernel, grid, block, 0, s, L, out, W, H, taps, k_dev, k_host, mode,
-                       hmax_bits);
+    const size_t lds = (size_t)cond_tile(taps.r).floats * sizeof(float);
+    hipLaunchKernelGGL(cond_kernel, dim3(tiles_of(W, H)), dim3(256), lds, s, L, out, W, H, taps,
+                       k_dev, k_host, mode, hmax_bits);
     return hipGetLastError();
 }
 
@@ -262,12 +217,6 @@ hipError_t launch_kselect(const unsigned* hist, int nbins, const unsigned* hmax_
                           hipStream_t s) {
     hipLaunchKernelGGL(kselect_kernel, dim3(1), dim3(64), 0, s, hist, nbins, hmax_bits,
                        pct_mant, pct_shift, k_out);
-    return hipGetLastError();
-}
-
-hipError_t launch_g_from_m2(float* buf, int n, const float* k_dev, int mode, hipStream_t s) {
-    hipLaunchKernelGGL(g_from_m2_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, buf, n,
-                       k_dev, mode);
     return hipGetLastError();
 }
 

@@ -101,6 +101,9 @@ def test_workspace_bytes(K):
     assert w >= 2 * 1920 * 1200 * 4 and w % 256 == 0
     assert K.kaze_workspace_bytes(7, 100, p) == 0
     assert K.kaze_workspace_bytes(100, 5000, p) == 0
+    assert K.kaze_workspace_bytes(4097, 64, p) == 0
+    assert K.kaze_workspace_bytes(4096, 4096, p) > 0
+    assert K.kaze_workspace_bytes(64, 64, K.kaze_default_params(sigma_cond=1.4)) == 0
     bad = K.kaze_default_params(octaves=0)
     assert K.kaze_workspace_bytes(64, 64, bad) == 0
 
@@ -109,6 +112,7 @@ def test_workspace_bytes(K):
     ("octaves", 0, -1), ("sublevels", 0, -1), ("octaves", 17, -4), ("sigma0", 0.0, -1),
     ("sigma0", 6.0, -4), ("diffusivity", 3, -1), ("k_percentile", 0.0, -1),
     ("k_percentile", 1.5, -1), ("k_bins", 0, -1), ("k_bins", 5000, -1),
+    ("sigma_cond", 1.4, -4),
 ])
 @no_gpu_only
 def test_invalid_params_rejected_before_launch(K, field, value, status):
