@@ -126,7 +126,7 @@ __device__ __forceinline__ void wave_pcr_pairs(Eq e0, Eq e1, int lane, float& z0
 namespace kaze {
 
 constexpr int kTile = 64;        // tile edge = chunk length of every line solve
-constexpr int kMaxCondRadius = 8;  // Gaussian radius of sigma_cond in the fused kernel
+constexpr int kMaxCondRadius = 4;  // sigma_cond radius that keeps the fused tile within 64 KB of LDS
 
 // One image of an AOS step.  Row line y is cut into ncx chunks of kTile
 // pixels (tile columns), column line x into ncy chunks (tile rows).
