@@ -87,6 +87,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="kaze_1920x1200")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-breakdown", action="store_true",
+                    help="skip the per-kernel timing pass (for profiler runs)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run the library's copy kernel on this many MiB, a known-size "
+                         "reference for hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -109,6 +114,15 @@ def main():
     kz = K.Kaze(W, H)
     stream = torch.cuda.current_stream()
 
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            K.kaze_copy_f32(src, dst, n)
+        torch.cuda.synchronize()
+        del src, dst
+
     for _ in range(args.warmup):
         kz.run(img)
     torch.cuda.synchronize()
@@ -117,7 +131,7 @@ def main():
     breakdown = {}
     probe_steps = max(5, min(20, args.steps))
     for name in K.kaze_kernel_names():
-        if name == "copy":
+        if name == "copy" or args.no_breakdown:
             continue
         K.kaze_profile_begin(name)
         for _ in range(probe_steps):

@@ -153,19 +153,22 @@ __device__ __forceinline__ void store_eqs(float* dst, const Eq& e0, const Eq& e1
     o[1] = make_float4(e1.a, e1.b, e1.c, e1.d);
 }
 
-template <bool COMPUTE_G>
+template <int RG, bool COMPUTE_G>
 __global__ __launch_bounds__(kBlock) void aos_reduce_kernel(ImageDesc d0, WorkList w, Taps tc,
                                                             float tau, int gmode, float k_host,
                                                             int count) {
+    using G = CondGeom<RG>;
     extern __shared__ float smem[];
-    const CondTile ct = cond_tile(tc.r);
     float* sL = smem;
-    float* sH = smem + ct.offH;
-    float* sS = smem + ct.offS;
-    float* sG = smem + ct.offG;
+    float* sS = smem + G::offS;
+    float* sG = smem + G::offG;
     const int tid = threadIdx.x;
 
-    for (int t = blockIdx.x; t < count; t += gridDim.x) {
+    {
+        // one block per work item: a grid-stride loop here was measured to
+        // double the register demand (spills) without saving launches
+        const int t = blockIdx.x;
+        if (t >= count) return;
         ImageDesc d;
         int lt;
         resolve(d0, w, t, d, lt);
@@ -173,47 +176,41 @@ __global__ __launch_bounds__(kBlock) void aos_reduce_kernel(ImageDesc d0, WorkLi
         const int cx = lt % d.ncx, cy = lt / d.ncx;
         const int tx0 = cx * kTile, ty0 = cy * kTile;
 
-        load_L_ring(d.L, W, H, tx0, ty0, sL, ct);
+        load_L_ring<RG>(d.L, W, H, tx0, ty0, sL);
         if (COMPUTE_G) {
             __syncthreads();
-            smooth_tile(sL, sH, sS, ct, tc);
+            smooth_tile<RG>(sL, sS, tc);
             __syncthreads();
             const float k = d.k ? d.k[0] : k_host;
             const float inv_k2 = 1.f / (k * k);
-            const int n = ct.nG, total = n * n;
-            for (int i = tid; i < total; i += kBlock) {
-                const int gy = i / n, gx = i - gy * n;
-                const float gval = diffusivity(scharr_m2(sS, ct.pS, gy, gx), inv_k2, gmode);
-                sG[gy * ct.pG + gx] = gval;
+            float* gout = d.g;
+            scharr_pass<RG>(sS, [&](int gy, int gx, float m2) {
+                const float gval = diffusivity(m2, inv_k2, gmode);
+                sG[gy * G::pG + gx] = gval;
                 const int y = ty0 - 1 + gy, x = tx0 - 1 + gx;
                 if (gy >= 1 && gy <= kTile && gx >= 1 && gx <= kTile && y < H && x < W)
-                    d.g[(size_t)y * W + x] = gval;
-            }
+                    gout[(size_t)y * W + x] = gval;
+            });
         } else {
-            const int n = ct.nG, total = n * n;
-            for (int i = tid; i < total; i += kBlock) {
-                const int gy = i / n, gx = i - gy * n;
-                const int y = reflect_index(ty0 - 1 + gy, H), x = reflect_index(tx0 - 1 + gx, W);
-                sG[gy * ct.pG + gx] = d.g[(size_t)y * W + x];
-            }
+            stage_region<G::nG, G::nG, G::pG, kBlock>(d.g, W, H, ty0 - 1, tx0 - 1, sG);
         }
         __syncthreads();
 
-        if (tid < kTile) {
-            const int y = ty0 + tid;
-            if (y < H) {
-                LineAcc A{sG + (tid + 1) * ct.pG + 1, sL + (tid + ct.R) * ct.pL + ct.R, 1, 1};
+        // tile rows (threads 0..63) and tile columns (64..127) share one code
+        // path; the choice is uniform per wavefront
+        if (tid < 2 * kTile) {
+            const bool is_row = tid < kTile;
+            const int c = is_row ? tid : tid - kTile;
+            const int line = (is_row ? ty0 : tx0) + c;  // image row y or column x
+            if (line < (is_row ? H : W)) {
+                const LineAcc A = is_row
+                    ? LineAcc{sG + (c + 1) * G::pG + 1, sL + (c + G::R) * G::pL + G::R, 1, 1}
+                    : LineAcc{sG + G::pG + (c + 1), sL + G::R * G::pL + (c + G::R), G::pG, G::pL};
                 Eq e0, e1;
-                chunk_reduce(A, tx0, W, tau, e0, e1);
-                store_eqs(d.rrow + ((size_t)y * d.ncx + cx) * 8, e0, e1);
-            }
-        } else if (tid < 2 * kTile) {
-            const int c = tid - kTile, x = tx0 + c;
-            if (x < W) {
-                LineAcc A{sG + ct.pG + (c + 1), sL + ct.R * ct.pL + (c + ct.R), ct.pG, ct.pL};
-                Eq e0, e1;
-                chunk_reduce(A, ty0, H, tau, e0, e1);
-                store_eqs(d.rcol + ((size_t)x * d.ncy + cy) * 8, e0, e1);
+                chunk_reduce(A, is_row ? tx0 : ty0, is_row ? W : H, tau, e0, e1);
+                float* dst = is_row ? d.rrow + ((size_t)line * d.ncx + cx) * 8
+                                    : d.rcol + ((size_t)line * d.ncy + cy) * 8;
+                store_eqs(dst, e0, e1);
             }
         }
         __syncthreads();
@@ -254,47 +251,69 @@ __global__ __launch_bounds__(kBlock) void aos_iface_kernel(ImageDesc d0, WorkLis
 }
 
 constexpr int kPitchT = kTile + 1;
+constexpr int kRecoverThreads = 2 * kTile;  // one thread per tile row and per tile column
 
-__global__ __launch_bounds__(kBlock) void aos_recover_kernel(ImageDesc d0, WorkList w, float tau,
-                                                             int count) {
+__global__ __launch_bounds__(kRecoverThreads) void aos_recover_kernel(ImageDesc d0, WorkList w,
+                                                                      float tau, int count) {
     __shared__ float sL[kTile * kPitchT];
     __shared__ float sG[kTile * kPitchT];
     __shared__ float sD[kTile * kPitchT];
     const int tid = threadIdx.x;
 
-    for (int t = blockIdx.x; t < count; t += gridDim.x) {
+    {
+        // one block per work item: a grid-stride loop here was measured to
+        // double the register demand (spills) without saving launches
+        const int t = blockIdx.x;
+        if (t >= count) return;
         ImageDesc d;
         int lt;
         resolve(d0, w, t, d, lt);
         const int W = d.W, H = d.H;
         const int cx = lt % d.ncx, cy = lt / d.ncx;
         const int tx0 = cx * kTile, ty0 = cy * kTile;
+        const bool full = ty0 + kTile <= H && tx0 + kTile <= W;
 
-        for (int i = tid; i < kTile * kTile; i += kBlock) {
-            const int ly = i / kTile, lx = i % kTile;
-            const int y = ty0 + ly, x = tx0 + lx;
-            const bool in = y < H && x < W;
-            sL[ly * kPitchT + lx] = in ? d.L[(size_t)y * W + x] : 0.f;
-            sG[ly * kPitchT + lx] = in ? d.g[(size_t)y * W + x] : 0.f;
+        // stage L and g (zero outside the image) in two halves, all loads of
+        // a half in flight together
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            constexpr int PER = kTile * kTile / (2 * kRecoverThreads);
+            float vl[PER], vg[PER];
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int i = tid + (half * PER + j) * kRecoverThreads;
+                const int y = ty0 + i / kTile, x = tx0 + i % kTile;
+                const bool in = full || (y < H && x < W);
+                const size_t o = in ? (size_t)y * W + x : 0;
+                vl[j] = in ? d.L[o] : 0.f;
+                vg[j] = in ? d.g[o] : 0.f;
+            }
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int i = tid + (half * PER + j) * kRecoverThreads;
+                sL[(i / kTile) * kPitchT + i % kTile] = vl[j];
+                sG[(i / kTile) * kPitchT + i % kTile] = vg[j];
+            }
         }
         __syncthreads();
 
         float xs[kTile];
-        const int c = tid - kTile;
-        const bool row_thread = tid < kTile && ty0 + tid < H;
-        const bool col_thread = tid >= kTile && tid < 2 * kTile && tx0 + c < W;
-        if (row_thread) {
-            const int y = ty0 + tid;
-            const float2 z = reinterpret_cast<const float2*>(d.zrow + ((size_t)y * d.ncx + cx) * 2)[0];
-            LineAcc A{sG + tid * kPitchT, sL + tid * kPitchT, 1, 1};
-            chunk_recover(A, tx0, W, tau, z.x, z.y, xs);
+        const bool is_row = tid < kTile;
+        const int c = is_row ? tid : tid - kTile;
+        const int line = (is_row ? ty0 : tx0) + c;
+        const bool active = line < (is_row ? H : W);
+        const bool col_thread = !is_row && active;
+        if (active) {
+            const float2 z = reinterpret_cast<const float2*>(
+                is_row ? d.zrow + ((size_t)line * d.ncx + cx) * 2
+                       : d.zcol + ((size_t)line * d.ncy + cy) * 2)[0];
+            const LineAcc A = is_row ? LineAcc{sG + c * kPitchT, sL + c * kPitchT, 1, 1}
+                                     : LineAcc{sG + c, sL + c, kPitchT, kPitchT};
+            chunk_recover(A, is_row ? tx0 : ty0, is_row ? W : H, tau, z.x, z.y, xs);
+            if (is_row) {
 #pragma unroll
-            for (int k = 0; k < kTile; ++k) sD[tid * kPitchT + k] = xs[k];
-        } else if (col_thread) {
-            const int x = tx0 + c;
-            const float2 z = reinterpret_cast<const float2*>(d.zcol + ((size_t)x * d.ncy + cy) * 2)[0];
-            LineAcc A{sG + c, sL + c, kPitchT, kPitchT};
-            chunk_recover(A, ty0, H, tau, z.x, z.y, xs);
+                for (int k = 0; k < kTile; ++k) sD[c * kPitchT + k] = xs[k];
+            }
         }
         __syncthreads();
         if (col_thread) {
@@ -320,19 +339,34 @@ int work_count(const ImageDesc& d0, const WorkList& w, bool lines) {
 
 }  // namespace
 
+template <int RG>
+hipError_t launch_reduce_r(const ImageDesc& d0, const WorkList& w, const Taps& tc, float tau,
+                           bool compute_g, int gmode, float k_host, int grid, int count,
+                           hipStream_t s) {
+    const size_t lds = (size_t)CondGeom<RG>::floats * sizeof(float);
+    if (compute_g)
+        hipLaunchKernelGGL((aos_reduce_kernel<RG, true>), dim3(grid), dim3(kBlock), lds, s, d0, w,
+                           tc, tau, gmode, k_host, count);
+    else
+        hipLaunchKernelGGL((aos_reduce_kernel<RG, false>), dim3(grid), dim3(kBlock), lds, s, d0,
+                           w, tc, tau, gmode, k_host, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_aos_reduce(const ImageDesc& d0, const WorkList& w, const Taps& tc, float tau,
                              bool compute_g, int gmode, float k_host, int grid_cap,
                              hipStream_t s) {
     const int count = work_count(d0, w, false);
     if (count <= 0) return hipSuccess;
-    const size_t lds = (size_t)cond_tile(tc.r).floats * sizeof(float);
-    if (compute_g)
-        hipLaunchKernelGGL(aos_reduce_kernel<true>, dim3(grid_of(count, grid_cap)), dim3(kBlock),
-                           lds, s, d0, w, tc, tau, gmode, k_host, count);
-    else
-        hipLaunchKernelGGL(aos_reduce_kernel<false>, dim3(grid_of(count, grid_cap)), dim3(kBlock),
-                           lds, s, d0, w, tc, tau, gmode, k_host, count);
-    return hipGetLastError();
+    const int grid = count;
+    (void)grid_cap;
+    switch (tc.r) {
+        case 1: return launch_reduce_r<1>(d0, w, tc, tau, compute_g, gmode, k_host, grid, count, s);
+        case 2: return launch_reduce_r<2>(d0, w, tc, tau, compute_g, gmode, k_host, grid, count, s);
+        case 3: return launch_reduce_r<3>(d0, w, tc, tau, compute_g, gmode, k_host, grid, count, s);
+        case 4: return launch_reduce_r<4>(d0, w, tc, tau, compute_g, gmode, k_host, grid, count, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_aos_iface(const ImageDesc& d0, const WorkList& w, int grid_cap, hipStream_t s) {
@@ -348,7 +382,8 @@ hipError_t launch_aos_recover(const ImageDesc& d0, const WorkList& w, float tau,
                               hipStream_t s) {
     const int count = work_count(d0, w, false);
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(aos_recover_kernel, dim3(grid_of(count, grid_cap)), dim3(kBlock), 0, s, d0,
+    (void)grid_cap;
+    hipLaunchKernelGGL(aos_recover_kernel, dim3(count), dim3(kRecoverThreads), 0, s, d0,
                        w, tau, count);
     return hipGetLastError();
 }

@@ -5,91 +5,99 @@
 //   D_x f(x,y) = sum_{dy in -s,0,s} w_dy (f(x+s, y+dy) - f(x-s, y+dy)) / (2s),
 //   w = (3, 10, 3)/16,
 // and every derivative image is extended by half-sample reflection before the
-// next derivative is taken.  One fused kernel per launch computes the first
-// derivatives of a 64x16 tile (plus an s-pixel ring) in LDS and the second
-// derivatives and det in registers; L_x, L_y, L_xx, ... never reach memory.
+// next derivative is taken.  One block per 64x32 tile and level computes the
+// first derivatives of the tile plus an s ring in LDS, then the second
+// derivatives and det; L_x, L_y, L_xx, ... never reach memory.
 #include "kaze_internal.h"
+#include "tile_cond.h"
 
 namespace kaze {
 namespace {
 
-constexpr int TX = 64;
-constexpr int TY = 16;
-constexpr int BX = 64;
-constexpr int BY = 4;
+constexpr int DTX = 64;
+constexpr int DTY = 32;
 
-__global__ __launch_bounds__(BX* BY) void det_kernel(const float* __restrict__ levels,
-                                                       float* __restrict__ det, int W, int H,
-                                                       DetLevels dl, int smax) {
+template <int S>
+struct DetGeom {
+    static constexpr int niy = DTY + 4 * S, nix = DTX + 4 * S;  // staged L
+    static constexpr int pI = nix | 1;
+    static constexpr int nfy = DTY + 2 * S, nfx = DTX + 2 * S;  // first derivatives
+    static constexpr int pF = nfx | 1;
+    static constexpr int offX = niy * pI;
+    static constexpr int offY = offX + nfy * pF;
+    static constexpr int floats = offY + nfy * pF;
+};
+
+template <int S>
+__global__ __launch_bounds__(kTileThreads) void det_kernel(const float* __restrict__ levels,
+                                                             float* __restrict__ det, int W, int H,
+                                                             DetLevels dl, int lev_first,
+                                                             int lev_count) {
+    using G = DetGeom<S>;
     extern __shared__ float smem[];
-    const int lev = blockIdx.z;
-    const int s = dl.step[lev];
+    float* sI = smem;
+    float* sX = smem + G::offX;
+    float* sY = smem + G::offY;
+    // levels of this launch: the ones with Scharr step S, in order
+    int lev = -1;
+    for (int i = lev_first, seen = 0; i < lev_first + lev_count; ++i)
+        if (dl.step[i] == S && seen++ == (int)blockIdx.z) lev = i;
+    if (lev < 0) return;  // uniform per block
     const float sn2 = dl.sn2[lev];
-    const int iw = TX + 4 * smax, ih = TY + 4 * smax;   // input tile + 2s ring
-    const int fw = TX + 2 * smax, fh = TY + 2 * smax;   // derivatives + s ring
-    float* s_in = smem;
-    float* s_lx = s_in + iw * ih;
-    float* s_ly = s_lx + fw * fh;
     const size_t plane = (size_t)W * H;
     const float* L = levels + plane * lev;
-    const int tx0 = blockIdx.x * TX, ty0 = blockIdx.y * TY;
-    const int tx = threadIdx.x, ty = threadIdx.y;
-    const int ro = 2 * s;  // origin of the input tile inside s_in
-
-    for (int ly = ty; ly < TY + 4 * s; ly += BY) {
-        const int gy = reflect_index(ty0 + ly - ro, H);
-        const float* row = L + (size_t)gy * W;
-        for (int lx = tx; lx < TX + 4 * s; lx += BX)
-            s_in[ly * iw + lx] = row[reflect_index(tx0 + lx - ro, W)];
-    }
+    const int ncx = (W + DTX - 1) / DTX;
+    const int tx0 = (blockIdx.x % ncx) * DTX, ty0 = (blockIdx.x / ncx) * DTY;
+    stage_region<G::niy, G::nix, G::pI, kTileThreads>(L, W, H, ty0 - 2 * S, tx0 - 2 * S, sI);
     __syncthreads();
 
     // First derivatives on the tile plus an s ring.  A ring position outside
     // the image takes the derivative at its reflected in-image position, so
     // the ring holds the reflected derivative image.  Ring positions more
     // than s past the last row/column feed no output pixel and are skipped
-    // (their reflected position may lie outside the loaded tile).
-    const float inv2s = 1.f / (float)(2 * s);
-    for (int py = ty; py < TY + 2 * s; py += BY) {
-        const int gy = ty0 + py - s;
-        if (gy > H - 1 + s) break;
-        const int ry = reflect_index(gy, H) - ty0 + ro;  // row inside s_in
-        for (int px = tx; px < TX + 2 * s; px += BX) {
-            const int gx = tx0 + px - s;
-            if (gx > W - 1 + s) break;
-            const int rx = reflect_index(gx, W) - tx0 + ro;
-            const float* c = s_in + ry * iw + rx;
-            const float ddx_m = c[-s * iw + s] - c[-s * iw - s];
-            const float ddx_0 = c[s] - c[-s];
-            const float ddx_p = c[s * iw + s] - c[s * iw - s];
-            const float ddy_m = c[s * iw - s] - c[-s * iw - s];
-            const float ddy_0 = c[s * iw] - c[-s * iw];
-            const float ddy_p = c[s * iw + s] - c[-s * iw + s];
-            s_lx[py * fw + px] = (0.1875f * ddx_m + 0.625f * ddx_0 + 0.1875f * ddx_p) * inv2s;
-            s_ly[py * fw + px] = (0.1875f * ddy_m + 0.625f * ddy_0 + 0.1875f * ddy_p) * inv2s;
+    // (their reflected position may lie outside the staged region).
+    constexpr float inv2s = 1.f / (float)(2 * S);
+    constexpr int nf = G::nfy * G::nfx;
+    const bool interior = ty0 - S >= 0 && tx0 - S >= 0 && ty0 + DTY + S <= H && tx0 + DTX + S <= W;
+#pragma unroll
+    for (int j = 0; j < (nf + kTileThreads - 1) / kTileThreads; ++j) {
+        const int i = threadIdx.x + j * kTileThreads;
+        if (i >= nf) continue;
+        const int py = i / G::nfx, px = i - py * G::nfx;
+        const int gy = ty0 - S + py, gx = tx0 - S + px;
+        int ry = py + S, rx = px + S;  // position inside sI
+        if (!interior) {
+            if (gy > H - 1 + S || gx > W - 1 + S) continue;
+            ry = reflect_index(gy, H) - ty0 + 2 * S;
+            rx = reflect_index(gx, W) - tx0 + 2 * S;
         }
+        const float* c = sI + ry * G::pI + rx;
+        const float a00 = c[-S * G::pI - S], a02 = c[-S * G::pI + S];
+        const float a20 = c[S * G::pI - S], a22 = c[S * G::pI + S];
+        const float a10 = c[-S], a12 = c[S], a01 = c[-S * G::pI], a21 = c[S * G::pI];
+        sX[py * G::pF + px] =
+            (0.1875f * (a02 - a00) + 0.625f * (a12 - a10) + 0.1875f * (a22 - a20)) * inv2s;
+        sY[py * G::pF + px] =
+            (0.1875f * (a20 - a00) + 0.625f * (a21 - a01) + 0.1875f * (a22 - a02)) * inv2s;
     }
     __syncthreads();
 
-    const int gx = tx0 + tx;
-    if (gx >= W) return;
-    for (int ly = ty; ly < TY; ly += BY) {
-        const int gy = ty0 + ly;
-        if (gy >= H) break;
-        const int cy = ly + s, cx = tx + s;
-        const float* lxc = s_lx + cy * fw + cx;
-        const float* lyc = s_ly + cy * fw + cx;
-        // L_xx = D_x(L_x), L_xy = D_y(L_x), L_yy = D_y(L_y)
-        const float xx = 0.1875f * (lxc[-s * fw + s] - lxc[-s * fw - s]) +
-                         0.625f * (lxc[s] - lxc[-s]) +
-                         0.1875f * (lxc[s * fw + s] - lxc[s * fw - s]);
-        const float xy = 0.1875f * (lxc[s * fw - s] - lxc[-s * fw - s]) +
-                         0.625f * (lxc[s * fw] - lxc[-s * fw]) +
-                         0.1875f * (lxc[s * fw + s] - lxc[-s * fw + s]);
-        const float yy = 0.1875f * (lyc[s * fw - s] - lyc[-s * fw - s]) +
-                         0.625f * (lyc[s * fw] - lyc[-s * fw]) +
-                         0.1875f * (lyc[s * fw + s] - lyc[-s * fw + s]);
-        const float Lxx = xx * inv2s, Lxy = xy * inv2s, Lyy = yy * inv2s;
+#pragma unroll
+    for (int j = 0; j < DTX * DTY / kTileThreads; ++j) {
+        const int i = threadIdx.x + j * kTileThreads;
+        const int ly = i / DTX, lx = i - ly * DTX;
+        const int gy = ty0 + ly, gx = tx0 + lx;
+        if (gy >= H || gx >= W) continue;
+        const float* x = sX + (ly + S) * G::pF + (lx + S);
+        const float* y = sY + (ly + S) * G::pF + (lx + S);
+        const float x00 = x[-S * G::pF - S], x02 = x[-S * G::pF + S];
+        const float x20 = x[S * G::pF - S], x22 = x[S * G::pF + S];
+        const float Lxx = (0.1875f * (x02 - x00) + 0.625f * (x[S] - x[-S]) + 0.1875f * (x22 - x20)) * inv2s;
+        const float Lxy = (0.1875f * (x20 - x00) + 0.625f * (x[S * G::pF] - x[-S * G::pF]) +
+                           0.1875f * (x22 - x02)) * inv2s;
+        const float Lyy = (0.1875f * (y[S * G::pF - S] - y[-S * G::pF - S]) +
+                           0.625f * (y[S * G::pF] - y[-S * G::pF]) +
+                           0.1875f * (y[S * G::pF + S] - y[-S * G::pF + S])) * inv2s;
         det[plane * lev + (size_t)gy * W + gx] = sn2 * (Lxx * Lyy - Lxy * Lxy);
     }
 }
@@ -99,63 +107,81 @@ struct KeypointOut {
     float response;
 };
 
+constexpr int NMS_ROWS = 8;  // rows per thread
+
 // (x, y, i) is an extremum iff det_i(x,y) > threshold and > all 26
 // neighbours in levels i-1..i+1; levels 1..N-2, 1-pixel image border excluded.
-__global__ __launch_bounds__(BX* BY) void nms_kernel(const float* __restrict__ det, int W, int H,
-                                                       float threshold,
-                                                       KeypointOut* __restrict__ kps, int capacity,
-                                                       int* __restrict__ count) {
-    const int x = blockIdx.x * BX + threadIdx.x;
-    const int y = blockIdx.y * BY + threadIdx.y;
+__global__ __launch_bounds__(256) void nms_kernel(const float* __restrict__ det, int W, int H,
+                                                    float threshold,
+                                                    KeypointOut* __restrict__ kps, int capacity,
+                                                    int* __restrict__ count) {
+    const int x = blockIdx.x * 64 + threadIdx.x % 64;
+    const int y0 = (blockIdx.y * 4 + threadIdx.x / 64) * NMS_ROWS;
     const int lev = blockIdx.z + 1;
-    if (x < 1 || y < 1 || x > W - 2 || y > H - 2) return;
+    if (x < 1 || x > W - 2) return;
     const size_t plane = (size_t)W * H;
-    const float* c = det + plane * lev + (size_t)y * W + x;
-    const float v = c[0];
-    if (!(v > threshold)) return;
-    bool is_max = true;
+    const float* base = det + plane * lev;
+    float v[NMS_ROWS];
 #pragma unroll
-    for (int dl = -1; dl <= 1; ++dl) {
+    for (int q = 0; q < NMS_ROWS; ++q) {
+        const int y = y0 + q;
+        v[q] = (y >= 1 && y <= H - 2) ? base[(size_t)y * W + x] : -INFINITY;
+    }
 #pragma unroll
-        for (int dy = -1; dy <= 1; ++dy) {
-#pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-                if (dl == 0 && dy == 0 && dx == 0) continue;
-                const float nb = c[(ptrdiff_t)dl * (ptrdiff_t)plane + dy * W + dx];
-                is_max = is_max && (v > nb);
-            }
+    for (int q = 0; q < NMS_ROWS; ++q) {
+        if (!(v[q] > threshold)) continue;
+        const int y = y0 + q;
+        const float* c = base + (size_t)y * W + x;
+        bool is_max = true;
+        for (int dl = -1; dl <= 1 && is_max; ++dl)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    if (dl == 0 && dy == 0 && dx == 0) continue;
+                    is_max = is_max && (v[q] > c[(ptrdiff_t)dl * (ptrdiff_t)plane + dy * W + dx]);
+                }
+        if (!is_max) continue;
+        const int idx = atomicAdd(count, 1);
+        if (idx < capacity) {
+            KeypointOut k;
+            k.x = x;
+            k.y = y;
+            k.level = lev;
+            k.response = v[q];
+            kps[idx] = k;
         }
     }
-    if (!is_max) return;
-    const int idx = atomicAdd(count, 1);
-    if (idx < capacity) {
-        KeypointOut k;
-        k.x = x;
-        k.y = y;
-        k.level = lev;
-        k.response = v;
-        kps[idx] = k;
-    }
+}
+
+template <int S>
+hipError_t launch_det_s(const float* levels, float* det, int W, int H, int N, const DetLevels& dl,
+                        hipStream_t s) {
+    int n = 0;
+    for (int i = 0; i < N; ++i) n += dl.step[i] == S;
+    if (n == 0) return hipSuccess;
+    const int tiles = ((W + DTX - 1) / DTX) * ((H + DTY - 1) / DTY);
+    const size_t lds = (size_t)DetGeom<S>::floats * sizeof(float);
+    hipLaunchKernelGGL(det_kernel<S>, dim3(tiles, 1, n), dim3(kTileThreads), lds, s, levels, det,
+                       W, H, dl, 0, N);
+    return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_det(const float* levels, float* det, int W, int H, int N, const DetLevels& dl,
                       hipStream_t s) {
-    int smax = 1;
-    for (int i = 0; i < N; ++i) smax = dl.step[i] > smax ? dl.step[i] : smax;
-    const size_t lds = sizeof(float) * ((size_t)(TX + 4 * smax) * (TY + 4 * smax) +
-                                        2 * (size_t)(TX + 2 * smax) * (TY + 2 * smax));
-    dim3 grid((W + TX - 1) / TX, (H + TY - 1) / TY, N), block(BX, BY);
-    hipLaunchKernelGGL(det_kernel, grid, block, lds, s, levels, det, W, H, dl, smax);
-    return hipGetLastError();
+    hipError_t e = hipSuccess;
+#define KZ_D(S) \
+    if (e == hipSuccess) e = launch_det_s<S>(levels, det, W, H, N, dl, s);
+    KZ_D(1) KZ_D(2) KZ_D(3) KZ_D(4) KZ_D(5) KZ_D(6) KZ_D(7) KZ_D(8)
+#undef KZ_D
+    return e;
 }
 
 hipError_t launch_nms(const float* det, int W, int H, int N, float threshold, void* kps,
                       int capacity, int* count, hipStream_t s) {
     if (N < 3) return hipSuccess;
-    dim3 grid((W + BX - 1) / BX, (H + BY - 1) / BY, N - 2), block(BX, BY);
-    hipLaunchKernelGGL(nms_kernel, grid, block, 0, s, det, W, H, threshold,
+    dim3 grid((W + 63) / 64, (H + 4 * NMS_ROWS - 1) / (4 * NMS_ROWS), N - 2);
+    hipLaunchKernelGGL(nms_kernel, grid, dim3(256), 0, s, det, W, H, threshold,
                        static_cast<KeypointOut*>(kps), capacity, count);
     return hipGetLastError();
 }

@@ -191,7 +191,8 @@ hipError_t launch_fill_f32(float* p, int n, float v, hipStream_t s);
 // is read) + chunk reduction of every row and column chunk; iface: the
 // interface system of every line by wavefront PCR; recover: interior of
 // every chunk and L_next = L + (delta_x + delta_y)/2.
-// grid_cap > 0 caps the grid (persistent blocks looping over the list).
+// grid_cap > 0 caps the grid of the line kernel (wavefronts loop over the
+// list); the tile kernels run one block per tile.
 hipError_t launch_aos_reduce(const ImageDesc& d0, const WorkList& w, const Taps& tc,
                              float tau, bool compute_g, int gmode, float k_host, int grid_cap,
                              hipStream_t s);

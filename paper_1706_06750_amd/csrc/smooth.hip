@@ -1,84 +1,142 @@
 // Gaussian pre-smoothing, conductivity and contrast factor (Sec. II-A,
 // Eqs. 2-3; Sec. III-A).
 //
-// All stencils read a 64x16 output tile plus halo into LDS with
-// half-sample symmetric reflection at the image border; a symmetric filter
-// applied to that extension is itself half-sample symmetric, so halo values
-// of an intermediate (smoothed) image equal the reflected interior values.
+// Stencils stage a 64x64 output tile plus its ring in LDS with half-sample
+// symmetric reflection at the image border; a symmetric filter applied to
+// that extension is itself half-sample symmetric, so ring values of an
+// intermediate (smoothed) image equal the reflected interior values.
 #include "kaze_internal.h"
 #include "tile_cond.h"
 
 namespace kaze {
 namespace {
 
-constexpr int TX = 64;
-constexpr int TY = 16;
-constexpr int BX = 64;
-constexpr int BY = 4;
+// ---------------------------------------------------------------- G_sigma0
+template <int R>
+struct GaussGeom {
+    static constexpr int n = kTile + 2 * R;   // staged rows and columns
+    static constexpr int pI = n | 1;
+    static constexpr int pH = kTile | 1;      // horizontal pass: n rows x kTile cols
+    static constexpr int offH = n * pI;
+    static constexpr int floats = offH + n * pH;
+};
 
-// G_sigma * src for one tile: horizontal then vertical pass through LDS.
-__global__ __launch_bounds__(BX* BY) void gauss_kernel(const float* __restrict__ src, int ld,
-                                                         float* __restrict__ dst, int W, int H,
-                                                         Taps taps) {
-    __shared__ float s_in[(TY + 2 * kMaxRadius) * (TX + 2 * kMaxRadius)];
-    __shared__ float s_h[(TY + 2 * kMaxRadius) * TX];
-    const int r = taps.r;
-    const int iw = TX + 2 * r, ih = TY + 2 * r;
-    const int tx0 = blockIdx.x * TX, ty0 = blockIdx.y * TY;
-    const int tx = threadIdx.x, ty = threadIdx.y;
-
-    for (int ly = ty; ly < ih; ly += BY) {
-        const int gy = reflect_index(ty0 + ly - r, H);
-        const float* row = src + (size_t)gy * ld;
-        for (int lx = tx; lx < iw; lx += BX)
-            s_in[ly * iw + lx] = row[reflect_index(tx0 + lx - r, W)];
+// L_0 = G_sigma0 * img on one 64x64 tile: horizontal then vertical pass.
+template <int R>
+__global__ __launch_bounds__(kTileThreads) void gauss_kernel(const float* __restrict__ src, int ld,
+                                                               float* __restrict__ dst, int W,
+                                                               int H, Taps taps) {
+    using G = GaussGeom<R>;
+    constexpr int T = 2 * R + 1;
+    extern __shared__ float smem[];
+    float* sI = smem;
+    float* sH = smem + G::offH;
+    const int ncx = (W + kTile - 1) / kTile;
+    const int tx0 = (blockIdx.x % ncx) * kTile, ty0 = (blockIdx.x / ncx) * kTile;
+    // staged load (the source has row pitch ld)
+    {
+        constexpr int TOTAL = G::n * G::n, PER = (TOTAL + kTileThreads - 1) / kTileThreads;
+        const int gy0 = ty0 - R, gx0 = tx0 - R;
+        const bool interior = gy0 >= 0 && gx0 >= 0 && gy0 + G::n <= H && gx0 + G::n <= W;
+        float v[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int i = threadIdx.x + j * kTileThreads;
+            if (i < TOTAL) {
+                const int ly = i / G::n, lx = i - ly * G::n;
+                const int gy = interior ? gy0 + ly : reflect_index(gy0 + ly, H);
+                const int gx = interior ? gx0 + lx : reflect_index(gx0 + lx, W);
+                v[j] = src[(size_t)gy * ld + gx];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int i = threadIdx.x + j * kTileThreads;
+            if (i < TOTAL) {
+                const int ly = i / G::n, lx = i - ly * G::n;
+                sI[ly * G::pI + lx] = v[j];
+            }
+        }
+    }
+    float w[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) w[t] = taps.w[t];
+    __syncthreads();
+    {
+        constexpr int runs = kTile / kRun, items = runs * G::n;
+#pragma unroll
+        for (int j = 0; j < (items + kTileThreads - 1) / kTileThreads; ++j) {
+            const int i = threadIdx.x + j * kTileThreads;
+            if (i < items) {
+                const int row = i % G::n, x0 = (i / G::n) * kRun;
+                const float* p = sI + row * G::pI + x0;
+                float v[kRun + T - 1];
+#pragma unroll
+                for (int q = 0; q < kRun + T - 1; ++q) v[q] = p[q];
+#pragma unroll
+                for (int q = 0; q < kRun; ++q) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int t = 0; t < T; ++t) acc += w[t] * v[q + t];
+                    sH[row * G::pH + x0 + q] = acc;
+                }
+            }
+        }
     }
     __syncthreads();
-    for (int ly = ty; ly < ih; ly += BY) {
-        float acc = 0.f;
-        for (int j = 0; j <= 2 * r; ++j) acc += taps.w[j] * s_in[ly * iw + tx + j];
-        s_h[ly * TX + tx] = acc;
-    }
-    __syncthreads();
-    const int gx = tx0 + tx;
-    for (int ly = ty; ly < TY; ly += BY) {
-        float acc = 0.f;
-        for (int j = 0; j <= 2 * r; ++j) acc += taps.w[j] * s_h[(ly + j) * TX + tx];
-        const int gy = ty0 + ly;
-        if (gx < W && gy < H) dst[(size_t)gy * W + gx] = acc;
+    {
+        constexpr int runs = kTile / kRun, items = runs * kTile;
+#pragma unroll
+        for (int j = 0; j < items / kTileThreads; ++j) {
+            const int i = threadIdx.x + j * kTileThreads;
+            const int col = i % kTile, y0 = (i / kTile) * kRun;
+            const float* p = sH + y0 * G::pH + col;
+            float v[kRun + T - 1];
+#pragma unroll
+            for (int q = 0; q < kRun + T - 1; ++q) v[q] = p[q * G::pH];
+            const int x = tx0 + col;
+#pragma unroll
+            for (int q = 0; q < kRun; ++q) {
+                float acc = 0.f;
+#pragma unroll
+                for (int t = 0; t < T; ++t) acc += w[t] * v[q + t];
+                const int y = ty0 + y0 + q;
+                if (x < W && y < H) dst[(size_t)y * W + x] = acc;
+            }
+        }
     }
 }
 
+// ------------------------------------------------------------ conductivity
 // Conductivity of L on 64x64 tiles with the same LDS pipeline as the fused
 // AOS reduction (tile_cond.h):
 // mode 0: g2 = 1/(1 + |grad|^2/k^2)   (Eq. 3)
 // mode 1: g1 = exp(-|grad|^2/k^2)     (Eq. 3)
 // mode 2: |grad|^2, and the running maximum of |grad| (for the histogram).
-__global__ __launch_bounds__(256) void cond_kernel(const float* __restrict__ L,
-                                                     float* __restrict__ out, int W, int H,
-                                                     Taps taps, const float* __restrict__ k_dev,
-                                                     float k_host, int mode,
-                                                     unsigned* __restrict__ hmax_bits) {
+template <int RG>
+__global__ __launch_bounds__(kTileThreads) void cond_kernel(const float* __restrict__ L,
+                                                              float* __restrict__ out, int W,
+                                                              int H, Taps taps,
+                                                              const float* __restrict__ k_dev,
+                                                              float k_host, int mode,
+                                                              unsigned* __restrict__ hmax_bits) {
+    using G = CondGeom<RG>;
     extern __shared__ float smem[];
-    __shared__ float s_max[256 / kWave];
-    const CondTile ct = cond_tile(taps.r);
+    __shared__ float s_max[kTileThreads / kWave];
     float* sL = smem;
-    float* sH = smem + ct.offH;
-    float* sS = smem + ct.offS;
+    float* sS = smem + G::offS;
     const int ncx = (W + kTile - 1) / kTile;
     const int tx0 = (blockIdx.x % ncx) * kTile, ty0 = (blockIdx.x / ncx) * kTile;
-    load_L_ring(L, W, H, tx0, ty0, sL, ct);
+    load_L_ring<RG>(L, W, H, tx0, ty0, sL);
     __syncthreads();
-    smooth_tile(sL, sH, sS, ct, taps);
+    smooth_tile<RG>(sL, sS, taps);
     __syncthreads();
     const float k = (mode == 2) ? 1.f : (k_dev ? k_dev[0] : k_host);
     const float inv_k2 = 1.f / (k * k);
     float local_max = 0.f;
-    for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x) {
-        const int ly = i / kTile, lx = i % kTile;
-        const int y = ty0 + ly, x = tx0 + lx;
-        if (y >= H || x >= W) continue;
-        const float m2 = scharr_m2(sS, ct.pS, ly + 1, lx + 1);
+    scharr_pass<RG>(sS, [&](int gy, int gx, float m2) {
+        const int y = ty0 - 1 + gy, x = tx0 - 1 + gx;
+        if (gy < 1 || gy > kTile || gx < 1 || gx > kTile || y >= H || x >= W) return;
         float v;
         if (mode == 2) {
             v = m2;
@@ -87,7 +145,7 @@ __global__ __launch_bounds__(256) void cond_kernel(const float* __restrict__ L,
             v = diffusivity(m2, inv_k2, mode);
         }
         out[(size_t)y * W + x] = v;
-    }
+    });
     if (mode == 2) {
         // wavefront max, then one atomic per block (|grad| >= 0, so the
         // float bit pattern orders like an unsigned integer)
@@ -98,12 +156,13 @@ __global__ __launch_bounds__(256) void cond_kernel(const float* __restrict__ L,
         __syncthreads();
         if (t == 0) {
             float m = s_max[0];
-            for (int i = 1; i < 256 / kWave; ++i) m = fmaxf(m, s_max[i]);
+            for (int i = 1; i < kTileThreads / kWave; ++i) m = fmaxf(m, s_max[i]);
             atomicMax(hmax_bits, __float_as_uint(m));
         }
     }
 }
 
+// --------------------------------------------------------------- contrast k
 // 300-bin (nbins) histogram of |grad| = sqrt(m2) over pixels with m2 > 0:
 // bin = min(floor(|grad|/hmax * nbins), nbins-1).  Integer atomics only, so
 // the counts are deterministic.
@@ -133,32 +192,51 @@ __global__ __launch_bounds__(256) void hist_kernel(const float* __restrict__ m2,
 // Smallest bin b whose cumulative count reaches percentile * npos; k is its
 // upper edge hmax*(b+1)/nbins.  No positive gradient: k = 1.  The
 // percentile is the exact binary fraction pct_mant * 2^-pct_shift, and the
-// test cum >= pct * npos is made exactly in 128-bit integers.
-__global__ void kselect_kernel(const unsigned* __restrict__ hist, int nbins,
-                               const unsigned* __restrict__ hmax_bits,
-                               unsigned long long pct_mant, int pct_shift,
-                               float* __restrict__ k_out) {
-    if (threadIdx.x != 0) return;
-    unsigned long long npos = 0;
-    for (int i = 0; i < nbins; ++i) npos += hist[i];
+// test cum >= pct * npos is made exactly in 128-bit integers.  One block:
+// per-thread segment sums, a block scan, then each thread searches its
+// segment.
+__global__ __launch_bounds__(256) void kselect_kernel(const unsigned* __restrict__ hist, int nbins,
+                                                        const unsigned* __restrict__ hmax_bits,
+                                                        unsigned long long pct_mant, int pct_shift,
+                                                        float* __restrict__ k_out) {
+    __shared__ unsigned long long s_scan[256];
+    __shared__ int s_best;
+    const int t = threadIdx.x;
+    const int seg = (nbins + 255) / 256;
+    const int b0 = t * seg, b1 = min(nbins, b0 + seg);
+    unsigned long long part = 0;
+    for (int b = b0; b < b1; ++b) part += hist[b];
+    s_scan[t] = part;
+    if (t == 0) s_best = nbins - 1;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {  // inclusive Hillis-Steele scan
+        const unsigned long long v = t >= off ? s_scan[t - off] : 0ull;
+        __syncthreads();
+        s_scan[t] += v;
+        __syncthreads();
+    }
+    const unsigned long long npos = s_scan[255];
     if (npos == 0) {
-        k_out[0] = 1.f;
+        if (t == 0) k_out[0] = 1.f;
         return;
     }
     const unsigned __int128 rhs = (unsigned __int128)pct_mant * npos;
-    unsigned long long cum = 0;
-    int b = nbins - 1;
-    for (int i = 0; i < nbins; ++i) {
-        cum += hist[i];
+    unsigned long long cum = s_scan[t] - part;  // exclusive prefix
+    for (int b = b0; b < b1; ++b) {
+        cum += hist[b];
         if (((unsigned __int128)cum << pct_shift) >= rhs) {
-            b = i;
+            atomicMin(&s_best, b);
             break;
         }
     }
-    const float hmax = __uint_as_float(hmax_bits[0]);
-    k_out[0] = (hmax * (float)(b + 1)) / (float)nbins;
+    __syncthreads();
+    if (t == 0) {
+        const float hmax = __uint_as_float(hmax_bits[0]);
+        k_out[0] = (hmax * (float)(s_best + 1)) / (float)nbins;
+    }
 }
 
+// ------------------------------------------------------------------ utility
 __global__ __launch_bounds__(256) void fill_u32_kernel(unsigned* p, int n, unsigned v) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
@@ -187,27 +265,54 @@ int grid_for(size_t n, int block, int cap) {
     return (int)(g < (size_t)cap ? g : (size_t)cap);
 }
 
+template <int R>
+hipError_t launch_gauss_r(const float* src, int ld, float* dst, int W, int H, const Taps& taps,
+                          hipStream_t s) {
+    const size_t lds = (size_t)GaussGeom<R>::floats * sizeof(float);
+    hipLaunchKernelGGL(gauss_kernel<R>, dim3(tiles_of(W, H)), dim3(kTileThreads), lds, s, src, ld,
+                       dst, W, H, taps);
+    return hipGetLastError();
+}
+
+template <int RG>
+hipError_t launch_cond_r(const float* L, float* out, int W, int H, const Taps& taps,
+                         const float* k_dev, float k_host, int mode, unsigned* hmax_bits,
+                         hipStream_t s) {
+    const size_t lds = (size_t)CondGeom<RG>::floats * sizeof(float);
+    hipLaunchKernelGGL(cond_kernel<RG>, dim3(tiles_of(W, H)), dim3(kTileThreads), lds, s, L, out,
+                       W, H, taps, k_dev, k_host, mode, hmax_bits);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_gauss(const float* src, int ld_src, float* dst, int W, int H,
                         const Taps& taps, hipStream_t s) {
-    dim3 grid((W + TX - 1) / TX, (H + TY - 1) / TY), block(BX, BY);
-    hipLaunchKernelGGL(gauss_kernel, grid, block, 0, s, src, ld_src, dst, W, H, taps);
-    return hipGetLastError();
+    switch (taps.r) {
+#define KZ_G(R) \
+    case R: return launch_gauss_r<R>(src, ld_src, dst, W, H, taps, s);
+        KZ_G(1) KZ_G(2) KZ_G(3) KZ_G(4) KZ_G(5) KZ_G(6) KZ_G(7) KZ_G(8)
+        KZ_G(9) KZ_G(10) KZ_G(11) KZ_G(12) KZ_G(13) KZ_G(14) KZ_G(15) KZ_G(16)
+#undef KZ_G
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_cond(const float* L, float* out, int W, int H, const Taps& taps,
                        const float* k_dev, float k_host, int mode, unsigned* hmax_bits,
                        hipStream_t s) {
-    const size_t lds = (size_t)cond_tile(taps.r).floats * sizeof(float);
-    hipLaunchKernelGGL(cond_kernel, dim3(tiles_of(W, H)), dim3(256), lds, s, L, out, W, H, taps,
-                       k_dev, k_host, mode, hmax_bits);
-    return hipGetLastError();
+    switch (taps.r) {
+        case 1: return launch_cond_r<1>(L, out, W, H, taps, k_dev, k_host, mode, hmax_bits, s);
+        case 2: return launch_cond_r<2>(L, out, W, H, taps, k_dev, k_host, mode, hmax_bits, s);
+        case 3: return launch_cond_r<3>(L, out, W, H, taps, k_dev, k_host, mode, hmax_bits, s);
+        case 4: return launch_cond_r<4>(L, out, W, H, taps, k_dev, k_host, mode, hmax_bits, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_hist(const float* m2, int n, const unsigned* hmax_bits, unsigned* hist,
                        int nbins, hipStream_t s) {
-    hipLaunchKernelGGL(hist_kernel, dim3(grid_for(n, 256, 1024)), dim3(256),
+    hipLaunchKernelGGL(hist_kernel, dim3(grid_for(n, 256 * 8, 512)), dim3(256),
                        nbins * sizeof(unsigned), s, m2, n, hmax_bits, hist, nbins);
     return hipGetLastError();
 }
@@ -215,8 +320,8 @@ hipError_t launch_hist(const float* m2, int n, const unsigned* hmax_bits, unsign
 hipError_t launch_kselect(const unsigned* hist, int nbins, const unsigned* hmax_bits,
                           unsigned long long pct_mant, int pct_shift, float* k_out,
                           hipStream_t s) {
-    hipLaunchKernelGGL(kselect_kernel, dim3(1), dim3(64), 0, s, hist, nbins, hmax_bits,
-                       pct_mant, pct_shift, k_out);
+    hipLaunchKernelGGL(kselect_kernel, dim3(1), dim3(256), 0, s, hist, nbins, hmax_bits, pct_mant,
+                       pct_shift, k_out);
     return hipGetLastError();
 }
 

@@ -9,100 +9,203 @@
 // the reflected in-image values, exactly as if each intermediate image were
 // reflected.  Used by the standalone conductivity kernel and by the fused
 // AOS reduction kernel, so both produce the same g.
+//
+// Geometry is compile-time (template on the Gaussian radius): every loop is
+// unrolled, global loads are staged through registers so that all of a
+// thread's loads are in flight together, and each filter pass computes runs
+// of 4 outputs per thread to reuse the values it reads from LDS.
 #pragma once
 
 #include "kaze_internal.h"
 
 namespace kaze {
 
-// LDS layout (in floats) of the tile pipeline; pitches are odd so that
-// threads walking down a column hit distinct banks.
-struct CondTile {
-    int r, R;       // Gaussian radius, ring of L
-    int nL, pL;     // L: nL x nL, pitch pL           (nL = kTile + 2R)
-    int pH;         // horizontal pass: nL rows x (kTile + 4) cols
-    int nS, pS;     // smoothed: nS x nS              (nS = kTile + 4)
-    int nG, pG;     // g: nG x nG, aliases the horizontal pass (nG = kTile + 2)
-    int offH, offS, offG;
-    int floats;
+constexpr int kTileThreads = 256;
+constexpr int kRun = 4;  // outputs per thread and work item in the filter passes
+
+template <int RG>
+struct CondGeom {
+    static constexpr int r = RG;                 // Gaussian radius
+    static constexpr int R = RG + 2;             // ring of L
+    static constexpr int nL = kTile + 2 * R;     // L region edge
+    static constexpr int pL = nL | 1;            // odd pitches: columns walk distinct banks
+    static constexpr int nS = kTile + 4;         // smoothed region edge (tile + 2 ring)
+    static constexpr int pS = nS | 1;            // horizontal pass: nL rows x nS cols; the
+                                                 // vertical pass overwrites it in place
+    static constexpr int nG = kTile + 2;         // g region edge (tile + 1 ring)
+    static constexpr int pG = nG | 1;
+    static constexpr int offS = nL * pL;         // smoothing work area
+    static constexpr int offG = offS;            // g overwrites the consumed smoothing area
+    static constexpr int floats = offS + nL * pS;
+    static_assert(nG * pG <= nL * pS, "g must fit in the smoothing area");
+    static_assert(nS % kRun == 0, "runs must tile the passes");
 };
 
-__host__ __device__ inline int odd_pitch(int n) { return n | 1; }
-
-__host__ __device__ inline CondTile cond_tile(int r) {
-    CondTile c;
-    c.r = r;
-    c.R = r + 2;
-    c.nL = kTile + 2 * c.R;
-    c.pL = odd_pitch(c.nL);
-    c.pH = odd_pitch(kTile + 4);
-    c.nS = kTile + 4;
-    c.pS = odd_pitch(c.nS);
-    c.nG = kTile + 2;
-    c.pG = odd_pitch(c.nG);
-    c.offH = c.nL * c.pL;
-    c.offS = c.offH + c.nL * c.pH;
-    c.offG = c.offH;  // g overwrites the horizontal pass once it is consumed
-    c.floats = c.offS + c.nS * c.pS;
-    return c;
+// Rectangular region [gy0, gy0+NY) x [gx0, gx0+NX) of a W x H image into LDS
+// (pitch P), half-sample reflected outside the image.  All loads of a
+// thread are issued before the first LDS store.
+template <int NY, int NX, int P, int NT>
+__device__ __forceinline__ void stage_region(const float* __restrict__ src, int W, int H, int gy0,
+                                             int gx0, float* dst) {
+    constexpr int TOTAL = NY * NX;
+    constexpr int PER = (TOTAL + NT - 1) / NT;
+    const bool interior = gy0 >= 0 && gx0 >= 0 && gy0 + NY <= H && gx0 + NX <= W;
+    float v[PER];
+    if (interior) {
+        const float* base = src + (size_t)gy0 * W + gx0;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int i = threadIdx.x + j * NT;
+            if (i < TOTAL) {
+                const int ly = i / NX, lx = i - ly * NX;
+                v[j] = base[(size_t)ly * W + lx];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int i = threadIdx.x + j * NT;
+            if (i < TOTAL) {
+                const int ly = i / NX, lx = i - ly * NX;
+                const int gy = reflect_index(gy0 + ly, H), gx = reflect_index(gx0 + lx, W);
+                v[j] = src[(size_t)gy * W + gx];
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int i = threadIdx.x + j * NT;
+        if (i < TOTAL) {
+            const int ly = i / NX, lx = i - ly * NX;
+            dst[ly * P + lx] = v[j];
+        }
+    }
 }
 
 // L on the tile + ring R (reflected) into sL.
+template <int RG>
 __device__ __forceinline__ void load_L_ring(const float* __restrict__ L, int W, int H, int tx0,
-                                            int ty0, float* sL, const CondTile& ct) {
-    const int n = ct.nL, total = n * n;
-    for (int i = threadIdx.x; i < total; i += blockDim.x) {
-        const int ly = i / n, lx = i - ly * n;
-        const int gy = reflect_index(ty0 - ct.R + ly, H);
-        const int gx = reflect_index(tx0 - ct.R + lx, W);
-        sL[ly * ct.pL + lx] = L[(size_t)gy * W + gx];
-    }
+                                            int ty0, float* sL) {
+    using G = CondGeom<RG>;
+    stage_region<G::nL, G::nL, G::pL, kTileThreads>(L, W, H, ty0 - G::R, tx0 - G::R, sL);
 }
 
-// Smoothed image L_s on the tile + 2 ring into sS (uses the sH region).
-__device__ __forceinline__ void smooth_tile(const float* sL, float* sH, float* sS,
-                                            const CondTile& ct, const Taps& taps) {
-    const int r2 = 2 * ct.r;
+// Smoothed image L_s on the tile + 2 ring into sS (nS x nS, pitch pS).
+template <int RG>
+__device__ __forceinline__ void smooth_tile(const float* sL, float* sS, const Taps& taps) {
+    using G = CondGeom<RG>;
+    constexpr int T = 2 * RG + 1;
+    float w[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) w[t] = taps.w[t];
+    // horizontal: item = (run along x, row); lanes walk rows (odd pitch)
     {
-        const int cols = kTile + 4, total = ct.nL * cols;
-        for (int i = threadIdx.x; i < total; i += blockDim.x) {
-            const int ly = i / cols, hx = i - ly * cols;
-            const float* src = sL + ly * ct.pL + hx;
-            float acc = 0.f;
-            for (int t = 0; t <= r2; ++t) acc += taps.w[t] * src[t];
-            sH[ly * ct.pH + hx] = acc;
+        constexpr int runs = G::nS / kRun, items = runs * G::nL;
+#pragma unroll 1
+        for (int i = threadIdx.x; i < items; i += kTileThreads) {
+            const int row = i % G::nL, x0 = (i / G::nL) * kRun;
+            const float* src = sL + row * G::pL + x0;
+            float v[kRun + T - 1];
+#pragma unroll
+            for (int q = 0; q < kRun + T - 1; ++q) v[q] = src[q];
+#pragma unroll
+            for (int q = 0; q < kRun; ++q) {
+                float acc = 0.f;
+#pragma unroll
+                for (int t = 0; t < T; ++t) acc += w[t] * v[q + t];
+                sS[row * G::pS + x0 + q] = acc;
+            }
         }
     }
     __syncthreads();
+    // vertical, in place: item = (column, quarter of the rows).  Every item
+    // reads its inputs into registers before the barrier and writes after.
     {
-        const int n = ct.nS, total = n * n;
-        for (int i = threadIdx.x; i < total; i += blockDim.x) {
-            const int sy = i / n, sx = i - sy * n;
-            const float* src = sH + sy * ct.pH + sx;
-            float acc = 0.f;
-            for (int t = 0; t <= r2; ++t) acc += taps.w[t] * src[t * ct.pH];
-            sS[sy * ct.pS + sx] = acc;
+        constexpr int NQ = 4, QR = G::nS / NQ, items = NQ * G::nS;
+        constexpr int PER = (items + kTileThreads - 1) / kTileThreads;
+        static_assert(G::nS % NQ == 0, "quarters must tile the rows");
+        float v[PER][QR + T - 1];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int i = threadIdx.x + j * kTileThreads;
+            if (i < items) {
+                const int col = i % G::nS, y0 = (i / G::nS) * QR;
+#pragma unroll
+                for (int q = 0; q < QR + T - 1; ++q) v[j][q] = sS[(y0 + q) * G::pS + col];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int i = threadIdx.x + j * kTileThreads;
+            if (i < items) {
+                const int col = i % G::nS, y0 = (i / G::nS) * QR;
+#pragma unroll
+                for (int q = 0; q < QR; ++q) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int t = 0; t < T; ++t) acc += w[t] * v[j][q + t];
+                    sS[(y0 + q) * G::pS + col] = acc;
+                }
+            }
         }
     }
 }
 
-// Squared Scharr gradient of L_s at (gy, gx) of the g grid (tile + 1 ring).
-__device__ __forceinline__ float scharr_m2(const float* sS, int pS, int gy, int gx) {
-    const float* c = sS + (gy + 1) * pS + (gx + 1);
-    const float dxm = 0.5f * (c[-pS + 1] - c[-pS - 1]);
-    const float dx0 = 0.5f * (c[1] - c[-1]);
-    const float dxp = 0.5f * (c[pS + 1] - c[pS - 1]);
-    const float dym = 0.5f * (c[pS - 1] - c[-pS - 1]);
-    const float dy0 = 0.5f * (c[pS] - c[-pS]);
-    const float dyp = 0.5f * (c[pS + 1] - c[-pS + 1]);
-    const float lx = 0.1875f * dxm + 0.625f * dx0 + 0.1875f * dxp;
-    const float ly = 0.1875f * dym + 0.625f * dy0 + 0.1875f * dyp;
-    return lx * lx + ly * ly;
+// Squared Scharr gradient magnitudes of L_s on the g grid (tile + 1 ring),
+// computed into registers; after a barrier f(gy, gx, m2) is called once per
+// position (gy, gx in [0, kTile + 2)), so f may overwrite the sS area.
+template <int RG, class F>
+__device__ __forceinline__ void scharr_pass(const float* sS, F&& f) {
+    using G = CondGeom<RG>;
+    constexpr int runs = (G::nG + kRun - 1) / kRun, items = runs * G::nG;
+    constexpr int PER = (items + kTileThreads - 1) / kTileThreads;
+    float m2[PER][kRun];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int i = threadIdx.x + j * kTileThreads;
+        if (i < items) {
+            const int gx = i % G::nG, gy0 = (i / G::nG) * kRun;
+            // g row gy uses sS rows gy .. gy+2 and columns gx .. gx+2
+            float a[kRun + 2], b[kRun + 2], c[kRun + 2];
+#pragma unroll
+            for (int q = 0; q < kRun + 2; ++q) {
+                const int sy = gy0 + q < G::nS ? gy0 + q : G::nS - 1;
+                const float* p = sS + sy * G::pS + gx;
+                a[q] = p[0];
+                b[q] = p[1];
+                c[q] = p[2];
+            }
+#pragma unroll
+            for (int q = 0; q < kRun; ++q) {
+                const float dxm = 0.5f * (c[q] - a[q]);
+                const float dx0 = 0.5f * (c[q + 1] - a[q + 1]);
+                const float dxp = 0.5f * (c[q + 2] - a[q + 2]);
+                const float dym = 0.5f * (a[q + 2] - a[q]);
+                const float dy0 = 0.5f * (b[q + 2] - b[q]);
+                const float dyp = 0.5f * (c[q + 2] - c[q]);
+                const float lx = 0.1875f * dxm + 0.625f * dx0 + 0.1875f * dxp;
+                const float ly = 0.1875f * dym + 0.625f * dy0 + 0.1875f * dyp;
+                m2[j][q] = lx * lx + ly * ly;
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int i = threadIdx.x + j * kTileThreads;
+        if (i < items) {
+            const int gx = i % G::nG, gy0 = (i / G::nG) * kRun;
+#pragma unroll
+            for (int q = 0; q < kRun; ++q)
+                if (gy0 + q < G::nG) f(gy0 + q, gx, m2[j][q]);
+        }
+    }
 }
 
 // Perona-Malik conductivity (Eq. 3): mode 0 g2, mode 1 g1.
 __device__ __forceinline__ float diffusivity(float m2, float inv_k2, int mode) {
-    return mode == 0 ? 1.f / (1.f + m2 * inv_k2) : expf(-m2 * inv_k2);
+    return mode == 0 ? __builtin_amdgcn_rcpf(1.f + m2 * inv_k2) : expf(-m2 * inv_k2);
 }
 
 }  // namespace kaze
