@@ -22,9 +22,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "1920x1200 scale-space+Hessian images/s, AOS vs surrogate; % HBM peak"
 HBM_PEAK_GBS = 8000.0
-# Algorithmic HBM bytes per pixel of one AOS step: read L_{i-1} and the
-# conductivity g, write L_i (4 bytes each).
-AOS_ALGO_BYTES_PER_PX = 12
+# The dominant kernels run one level of the scale space: conductivity and
+# AOS step (aos_reduce computes g and reduces every chunk, aos_iface solves
+# the interface systems, aos_recover recovers the chunks and averages).
+# Algorithmic HBM bytes per pixel and level: conductivity reads L_{i-1} and
+# writes g (8), the AOS step reads L_{i-1} and g and writes L_i (12).
+LEVEL_ALGO_BYTES_PER_PX = 20
 AOS_KERNELS = ("aos_reduce", "aos_iface", "aos_recover")
 
 
@@ -40,14 +43,14 @@ def csrc_hash() -> str:
 def traffic_from_profile(W, H):
     """HBM bytes per AOS step from the committed counter summary, if it was
     taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "aos_step_traffic_%dx%d.json" % (W, H))
+    path = os.path.join(ROOT, "profiles", "level_traffic_%dx%d.json" % (W, H))
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
     if d.get("csrc_hash") != csrc_hash():
         return None
-    return d.get("bytes_per_aos_step")
+    return d.get("bytes_per_level")
 
 
 CPU_BASELINE_SRC = r"""
@@ -155,8 +158,8 @@ def main():
     value = args.steps / elapsed
     n_levels = kz.N
     aos_steps = (n_levels - 1) * args.steps
-    aos_us = 1e3 * ms_aos / aos_steps                 # one AOS step (3 launches)
-    algo_bytes = AOS_ALGO_BYTES_PER_PX * W * H
+    aos_us = 1e3 * ms_aos / aos_steps                 # one level (3 launches)
+    algo_bytes = LEVEL_ALGO_BYTES_PER_PX * W * H
     achieved = algo_bytes / (aos_us * 1e-6) / 1e9
     traffic = traffic_from_profile(W, H)
 
@@ -177,7 +180,7 @@ def main():
                    "levels": n_levels, "path": "plain AOS (no surrogate)",
                    "keypoints": int(kz.count.item())},
         "roofline": {
-            "kernel": "aos_step = " + "+".join(AOS_KERNELS),
+            "kernel": "one level (conductivity + AOS step) = " + "+".join(AOS_KERNELS),
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,

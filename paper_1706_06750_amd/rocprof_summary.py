@@ -1,0 +1,112 @@
+"""Summaries of rocprofv3 CSV output for the benchmark's kernels.
+
+    python -m paper_1706_06750_amd.rocprof_summary stats  <kernel_stats.csv>
+    python -m paper_1706_06750_amd.rocprof_summary traffic <fetch_counter_collection.csv>
+        <write_counter_collection.csv> --image WxH --copy-mib M --out <json>
+
+``stats`` prints the kernel-duration table.  ``traffic`` turns FETCH_SIZE and
+WRITE_SIZE (KiB per dispatch) into HBM bytes per scale-space level: each
+counter is scaled by what it reads for the library's copy kernel, which moves
+a known number of bytes (M MiB read and M MiB written), and the bytes of the
+per-level kernels are summed per dispatch.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+
+LEVEL_KERNELS = ("aos_reduce_kernel", "aos_iface_kernel", "aos_recover_kernel")
+
+
+def short(name: str) -> str:
+    """'void kaze::(anonymous namespace)::det_kernel<2>(float const*, ...)'
+    -> 'det_kernel<2>'."""
+    n = name.replace("(anonymous namespace)::", "")
+    if n.startswith("void "):
+        n = n[5:]
+    depth = 0
+    for i, ch in enumerate(n):   # cut at the parameter list (outside <...>)
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            n = n[:i]
+            break
+    return n.split("::")[-1] if "<" not in n else n[n.rfind("::", 0, n.find("<")) + 2:]
+
+
+def csrc_hash(root: str) -> str:
+    h = hashlib.sha256()
+    d = os.path.join(root, "paper_1706_06750_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def stats(path: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    out = ["| kernel | calls | avg us | min us | max us | share |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        out.append("| %s | %s | %.2f | %.2f | %.2f | %.1f%% |" % (
+            short(r["Name"]), r["Calls"], float(r["AverageNs"]) / 1e3,
+            float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    return "\n".join(out)
+
+
+def counter_means(path: str, counter: str):
+    acc = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name", r.get("counter_name")) != counter:
+            continue
+        name = r.get("Kernel_Name", r.get("kernel_name"))
+        acc[short(name).split("<")[0]].append(float(r.get("Counter_Value", r.get("value"))))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def traffic(fetch_csv, write_csv, W, H, copy_mib, root):
+    f = counter_means(fetch_csv, "FETCH_SIZE")
+    w = counter_means(write_csv, "WRITE_SIZE")
+    known_kib = copy_mib * 1024.0
+    fs = known_kib / f["copy_kernel"]
+    ws = known_kib / w["copy_kernel"]
+    per = {}
+    for k in LEVEL_KERNELS:
+        per[k] = {"fetch_kib_raw": f[k], "write_kib_raw": w[k],
+                  "bytes": (f[k] * fs + w[k] * ws) * 1024.0}
+    total = sum(v["bytes"] for v in per.values())
+    return {"image": "%dx%d" % (W, H), "copy_scale_fetch": fs, "copy_scale_write": ws,
+            "kernels": per, "bytes_per_level": total,
+            "bytes_per_pixel_level": total / (W * H), "csrc_hash": csrc_hash(root)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("csv")
+    b = sub.add_parser("traffic")
+    b.add_argument("fetch_csv")
+    b.add_argument("write_csv")
+    b.add_argument("--image", required=True)
+    b.add_argument("--copy-mib", type=int, required=True)
+    b.add_argument("--out", required=True)
+    args = ap.parse_args()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if args.cmd == "stats":
+        print(stats(args.csv))
+    else:
+        W, H = (int(v) for v in args.image.split("x"))
+        d = traffic(args.fetch_csv, args.write_csv, W, H, args.copy_mib, root)
+        with open(args.out, "w") as fh:
+            json.dump(d, fh, indent=1)
+        print(json.dumps(d, indent=1))
+
+
+if __name__ == "__main__":
+    main()
