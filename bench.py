@@ -83,6 +83,22 @@ def cpu_baseline(W, H, seed):
                       "%.1f s" % (W, H, seed, r["seconds"])}
 
 
+def level_roofline(level_us, px, traffic):
+    algo = LEVEL_ALGO_BYTES_PER_PX * px
+    achieved = algo / (level_us * 1e-6) / 1e9
+    return {
+        "kernel": "one level (conductivity + AOS step) = " + "+".join(AOS_KERNELS),
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": algo,
+        "us_per_launch": round(level_us, 3),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,20 +118,13 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1706_06750_amd import kaze as K
     from synthetic import WORKLOADS, kaze_image
 
     cases = WORKLOADS[args.workload]()
-    if len(cases) != 1:
-        raise SystemExit("bench.py times single-image workloads")
-    W, H, seed = cases[0]
     torch.cuda.set_device(0)
-    img = torch.from_numpy(kaze_image(W, H, seed)).cuda()
-    kz = K.Kaze(W, H)
-    stream = torch.cuda.current_stream()
 
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * (1 << 20) // 4
@@ -126,6 +135,38 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if len(cases) == 1:
+        rec = bench_single(args, K, torch, kaze_image, cases[0])
+    else:
+        rec = bench_batch(args, K, torch, kaze_image, cases)
+    print(json.dumps(rec), flush=True)
+
+
+def record(args, value, ms_per_step, config, roofline, extra):
+    rec = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "images/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": config,
+        "roofline": roofline,
+    }
+    rec.update(extra)
+    return rec
+
+
+def bench_single(args, K, torch, kaze_image, case):
+    W, H, seed = case
+    img = torch.from_numpy(kaze_image(W, H, seed)).cuda()
+    kz = K.Kaze(W, H)
     for _ in range(args.warmup):
         kz.run(img)
     torch.cuda.synchronize()
@@ -141,10 +182,10 @@ def main():
             kz.run(img)
         n, ms = K.kaze_profile_end()
         if n:
-            breakdown[name] = {"launches_per_step": n / probe_steps, "ms_per_step": ms / probe_steps,
-                               "us_per_launch": 1e3 * ms / n}
+            breakdown[name] = {"launches_per_step": n / probe_steps,
+                               "ms_per_step": ms / probe_steps, "us_per_launch": 1e3 * ms / n}
 
-    # timed region; the AOS kernels carry HIP events on the same stream
+    # timed region; the level kernels carry HIP events on the same stream
     K.kaze_profile_begin(",".join(AOS_KERNELS))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -153,50 +194,79 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     n_aos, ms_aos = K.kaze_profile_end()
+    level_us = 1e3 * ms_aos / ((kz.N - 1) * args.steps)
+    roof = level_roofline(level_us, W * H, traffic_from_profile(W, H))
+    roof["launches_timed"] = n_aos
 
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = args.steps / elapsed
-    n_levels = kz.N
-    aos_steps = (n_levels - 1) * args.steps
-    aos_us = 1e3 * ms_aos / aos_steps                 # one level (3 launches)
-    algo_bytes = LEVEL_ALGO_BYTES_PER_PX * W * H
-    achieved = algo_bytes / (aos_us * 1e-6) / 1e9
-    traffic = traffic_from_profile(W, H)
+    # the same work replayed from a captured graph (one image per graph)
+    kb = K.KazeBatch([(W, H)], shape=0)
+    kb.inputs[0].copy_(img)
+    for _ in range(args.warmup):
+        kb.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        kb.run()
+    torch.cuda.synchronize()
+    graph_value = args.steps / (time.perf_counter() - t1)
+    kb.close()
 
-    rec = {
-        "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "images/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "image": "%dx%d" % (W, H), "seed": seed,
-                   "levels": n_levels, "path": "plain AOS (no surrogate)",
-                   "keypoints": int(kz.count.item())},
-        "roofline": {
-            "kernel": "one level (conductivity + AOS step) = " + "+".join(AOS_KERNELS),
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": algo_bytes,
-            "us_per_launch": round(aos_us, 3),
-            "launches_timed": aos_steps,
-        },
-        "kernel_breakdown": {k: {kk: round(vv, 4) for kk, vv in v.items()}
-                             for k, v in breakdown.items()},
-    }
+    extra = {"graph_replay_images_per_s": round(graph_value, 3),
+             "kernel_breakdown": {k: {kk: round(vv, 4) for kk, vv in v.items()}
+                                  for k, v in breakdown.items()}}
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(W, H, seed)
-    print(json.dumps(rec), flush=True)
+        extra["cpu_baseline"] = cpu_baseline(W, H, seed)
+    config = {"workload": args.workload, "image": "%dx%d" % (W, H), "seed": seed,
+              "levels": kz.N, "path": "plain AOS (no surrogate)",
+              "keypoints": int(kz.count.item())}
+    return record(args, args.steps / elapsed, 1e3 * elapsed / args.steps, config, roof, extra)
+
+
+def bench_batch(args, K, torch, kaze_image, cases):
+    sizes = [(W, H) for W, H, _ in cases]
+    kb = K.KazeBatch(sizes, shape="auto", capacity=1 << 12)
+    for x, (W, H, seed) in zip(kb.inputs, cases):
+        x.copy_(torch.from_numpy(kaze_image(W, H, seed)))
+    px = sum(W * H for W, H in sizes)
+    for _ in range(args.warmup):
+        kb.run()
+    torch.cuda.synchronize()
+
+    # timed region: graph replays, one per batch
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        kb.run()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    # the same launches issued eagerly with HIP events on the level kernels
+    eager_steps = max(2, min(args.steps, 10))
+    K.kaze_profile_begin(",".join(AOS_KERNELS))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(eager_steps):
+        kb.run(eager=True)
+    torch.cuda.synchronize()
+    eager_elapsed = time.perf_counter() - t1
+    n_aos, ms_aos = K.kaze_profile_end()
+    level_us = 1e3 * ms_aos / ((kb.N - 1) * eager_steps)
+    roof = level_roofline(level_us, px, None)
+    roof["launches_timed"] = n_aos
+    roof["timed_in"] = "eager pass of the same launches (%d batches)" % eager_steps
+
+    n = len(sizes)
+    config = {"workload": args.workload, "images": n, "pixels": px,
+              "sizes": "W in [%d,%d], H in [%d,%d]" % (min(w for w, _ in sizes),
+                                                       max(w for w, _ in sizes),
+                                                       min(h for _, h in sizes),
+                                                       max(h for _, h in sizes)),
+              "levels": kb.N, "path": "plain AOS, batched, graph replay",
+              "aos_tile": "%dx%d" % K.AOS_SHAPES[kb.shape],
+              "autotune_ms_per_shape": kb.tune_ms}
+    extra = {"eager_images_per_s": round(n * eager_steps / eager_elapsed, 3),
+             "megapixels_per_s": round(px * args.steps / elapsed / 1e6, 1)}
+    kb.close()
+    return record(args, n * args.steps / elapsed, 1e3 * elapsed / args.steps, config, roof, extra)
 
 
 if __name__ == "__main__":

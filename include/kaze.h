@@ -173,6 +173,72 @@ kaze_status kaze_find_extrema(const float* det, int W, int H,
                               const kaze_params* p, kaze_keypoint* kps,
                               int capacity, int* count, void* stream);
 
+/*
+ * Batches (many images of different sizes in one launch per phase).
+ *
+ * One image of a batch.  All pointers are (device); det/count may be NULL
+ * (then for every image of the batch), which skips the detector response
+ * and extrema.
+ */
+typedef struct {
+    const float* img;      /* W x H float32 input, row pitch ld_img          */
+    int W, H, ld_img;
+    float* levels;         /* N x H x W output                               */
+    float* det;            /* N x H x W output, or NULL                      */
+    float* k;              /* 1 float output: the contrast factor used       */
+    kaze_keypoint* kps;    /* keypoint output (NULL with capacity 0)         */
+    int capacity;
+    int* count;            /* 1 int output: extrema found, or NULL           */
+} kaze_image_desc;
+
+/* Tile shape of the row/column solves: 0 = 64x64, 1 = 64x32, 2 = 32x64,
+ * 3 = 32x32 (row chunk x column chunk); -1 = default (0).  A shape fits an
+ * image when W <= 64*TX and H <= 64*TY. */
+typedef struct {
+    int aos_shape;
+} kaze_batch_config;
+
+typedef struct kaze_batch kaze_batch;  /* opaque plan */
+
+/* Workspace bytes of a batch for the given shape (cfg NULL or shape -1: the
+ * maximum over every shape that fits all images); 0 if invalid. */
+size_t kaze_batch_workspace_bytes(const kaze_image_desc* images, int n,
+                                  const kaze_params* p,
+                                  const kaze_batch_config* cfg);
+
+/*
+ * Builds a plan for the images (host array of n descriptors, copied): the
+ * per-image descriptor tables and the tile, line and block work lists are
+ * written into ws (synchronously), and the whole sequence -- base image,
+ * contrast factor, N-1 AOS steps, detector response, extrema, each phase
+ * one launch over all images -- is captured once into a hipGraph.  The plan
+ * reads and writes the buffers named in the descriptors every time it runs;
+ * ws must stay allocated and untouched while the plan exists.
+ */
+kaze_status kaze_batch_create(const kaze_image_desc* images, int n,
+                              const kaze_params* p,
+                              const kaze_batch_config* cfg, void* ws,
+                              size_t ws_bytes, kaze_batch** out);
+
+/* Enqueues one run of the plan on stream: a single graph launch, or with
+ * eager != 0 the same launches issued one by one (for per-kernel timing).
+ * Runs that share a plan must be ordered on one stream. */
+kaze_status kaze_batch_run(kaze_batch* b, int eager, void* stream);
+
+kaze_status kaze_batch_destroy(kaze_batch* b);
+
+/*
+ * Autotuner: for every tile shape that fits all images, builds the plan in
+ * ws (sized for the maximum), times `reps` graph launches on stream, and
+ * returns the fastest shape in *best and, if ms_per_shape is not NULL, the
+ * mean milliseconds per run of each of the 4 shapes (-1 where it does not
+ * fit).  Synchronises the stream.
+ */
+kaze_status kaze_batch_autotune(const kaze_image_desc* images, int n,
+                                const kaze_params* p, void* ws, size_t ws_bytes,
+                                int reps, void* stream, kaze_batch_config* best,
+                                double* ms_per_shape);
+
 /* Message for the most recent non-OK status returned on this thread. */
 const char* kaze_last_error(void);
 

@@ -29,10 +29,8 @@ struct DetGeom {
 };
 
 template <int S>
-__global__ __launch_bounds__(kTileThreads) void det_kernel(const float* __restrict__ levels,
-                                                             float* __restrict__ det, int W, int H,
-                                                             DetLevels dl, int lev_first,
-                                                             int lev_count) {
+__global__ __launch_bounds__(kTileThreads) void det_kernel(BatchImage d0, ImgWork w, DetLevels dl,
+                                                             int N) {
     using G = DetGeom<S>;
     extern __shared__ float smem[];
     float* sI = smem;
@@ -40,14 +38,19 @@ __global__ __launch_bounds__(kTileThreads) void det_kernel(const float* __restri
     float* sY = smem + G::offY;
     // levels of this launch: the ones with Scharr step S, in order
     int lev = -1;
-    for (int i = lev_first, seen = 0; i < lev_first + lev_count; ++i)
-        if (dl.step[i] == S && seen++ == (int)blockIdx.z) lev = i;
+    for (int i = 0, seen = 0; i < N; ++i)
+        if (dl.step[i] == S && seen++ == (int)blockIdx.y) lev = i;
     if (lev < 0) return;  // uniform per block
+    BatchImage d;
+    int lt;
+    resolve(d0, w, (int)blockIdx.x, d, lt);
+    const int W = d.W, H = d.H;
+    float* __restrict__ det = d.det;
     const float sn2 = dl.sn2[lev];
     const size_t plane = (size_t)W * H;
-    const float* L = levels + plane * lev;
+    const float* L = d.levels + plane * lev;
     const int ncx = (W + DTX - 1) / DTX;
-    const int tx0 = (blockIdx.x % ncx) * DTX, ty0 = (blockIdx.x / ncx) * DTY;
+    const int tx0 = (lt % ncx) * DTX, ty0 = (lt / ncx) * DTY;
     stage_region<G::niy, G::nix, G::pI, kTileThreads>(L, W, H, ty0 - 2 * S, tx0 - 2 * S, sI);
     __syncthreads();
 
@@ -107,28 +110,30 @@ struct KeypointOut {
     float response;
 };
 
-constexpr int NMS_ROWS = 8;  // rows per thread
-
 // (x, y, i) is an extremum iff det_i(x,y) > threshold and > all 26
-// neighbours in levels i-1..i+1; levels 1..N-2, 1-pixel image border excluded.
-__global__ __launch_bounds__(256) void nms_kernel(const float* __restrict__ det, int W, int H,
-                                                    float threshold,
-                                                    KeypointOut* __restrict__ kps, int capacity,
-                                                    int* __restrict__ count) {
-    const int x = blockIdx.x * 64 + threadIdx.x % 64;
-    const int y0 = (blockIdx.y * 4 + threadIdx.x / 64) * NMS_ROWS;
-    const int lev = blockIdx.z + 1;
+// neighbours in levels i-1..i+1; levels 1..N-2, 1-pixel image border
+// excluded.  A block covers 64 columns x 4*kNmsRows rows of one level.
+__global__ __launch_bounds__(256) void nms_kernel(BatchImage d0, ImgWork w, float threshold) {
+    BatchImage d;
+    int lb;
+    resolve(d0, w, (int)blockIdx.x, d, lb);
+    const int W = d.W, H = d.H;
+    const int nbx = (W + 63) / 64;
+    const int x = (lb % nbx) * 64 + threadIdx.x % 64;
+    const int y0 = ((lb / nbx) * 4 + threadIdx.x / 64) * kNmsRows;
+    const int lev = blockIdx.y + 1;
     if (x < 1 || x > W - 2) return;
     const size_t plane = (size_t)W * H;
-    const float* base = det + plane * lev;
-    float v[NMS_ROWS];
+    const float* base = d.det + plane * lev;
+    float v[kNmsRows];
 #pragma unroll
-    for (int q = 0; q < NMS_ROWS; ++q) {
+    for (int q = 0; q < kNmsRows; ++q) {
         const int y = y0 + q;
         v[q] = (y >= 1 && y <= H - 2) ? base[(size_t)y * W + x] : -INFINITY;
     }
+    KeypointOut* kps = static_cast<KeypointOut*>(d.kps);
 #pragma unroll
-    for (int q = 0; q < NMS_ROWS; ++q) {
+    for (int q = 0; q < kNmsRows; ++q) {
         if (!(v[q] > threshold)) continue;
         const int y = y0 + q;
         const float* c = base + (size_t)y * W + x;
@@ -140,8 +145,8 @@ __global__ __launch_bounds__(256) void nms_kernel(const float* __restrict__ det,
                     is_max = is_max && (v[q] > c[(ptrdiff_t)dl * (ptrdiff_t)plane + dy * W + dx]);
                 }
         if (!is_max) continue;
-        const int idx = atomicAdd(count, 1);
-        if (idx < capacity) {
+        const int idx = atomicAdd(d.count, 1);
+        if (idx < d.capacity) {
             KeypointOut k;
             k.x = x;
             k.y = y;
@@ -153,36 +158,38 @@ __global__ __launch_bounds__(256) void nms_kernel(const float* __restrict__ det,
 }
 
 template <int S>
-hipError_t launch_det_s(const float* levels, float* det, int W, int H, int N, const DetLevels& dl,
+hipError_t launch_det_s(const BatchImage& d0, const ImgWork& w, int N, const DetLevels& dl,
                         hipStream_t s) {
     int n = 0;
     for (int i = 0; i < N; ++i) n += dl.step[i] == S;
-    if (n == 0) return hipSuccess;
-    const int tiles = ((W + DTX - 1) / DTX) * ((H + DTY - 1) / DTY);
+    const int count = w.items ? w.count : det_tiles_of(d0.W, d0.H);
+    if (n == 0 || count <= 0) return hipSuccess;
     const size_t lds = (size_t)DetGeom<S>::floats * sizeof(float);
-    hipLaunchKernelGGL(det_kernel<S>, dim3(tiles, 1, n), dim3(kTileThreads), lds, s, levels, det,
-                       W, H, dl, 0, N);
+    hipLaunchKernelGGL(det_kernel<S>, dim3(count, n), dim3(kTileThreads), lds, s, d0, w, dl, N);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_det(const float* levels, float* det, int W, int H, int N, const DetLevels& dl,
+int det_tiles_of(int W, int H) { return ((W + DTX - 1) / DTX) * ((H + DTY - 1) / DTY); }
+
+int nms_blocks_of(int W, int H) { return ((W + 63) / 64) * ((H + 4 * kNmsRows - 1) / (4 * kNmsRows)); }
+
+hipError_t launch_det(const BatchImage& d0, const ImgWork& w, int N, const DetLevels& dl,
                       hipStream_t s) {
     hipError_t e = hipSuccess;
 #define KZ_D(S) \
-    if (e == hipSuccess) e = launch_det_s<S>(levels, det, W, H, N, dl, s);
+    if (e == hipSuccess) e = launch_det_s<S>(d0, w, N, dl, s);
     KZ_D(1) KZ_D(2) KZ_D(3) KZ_D(4) KZ_D(5) KZ_D(6) KZ_D(7) KZ_D(8)
 #undef KZ_D
     return e;
 }
 
-hipError_t launch_nms(const float* det, int W, int H, int N, float threshold, void* kps,
-                      int capacity, int* count, hipStream_t s) {
-    if (N < 3) return hipSuccess;
-    dim3 grid((W + 63) / 64, (H + 4 * NMS_ROWS - 1) / (4 * NMS_ROWS), N - 2);
-    hipLaunchKernelGGL(nms_kernel, grid, dim3(256), 0, s, det, W, H, threshold,
-                       static_cast<KeypointOut*>(kps), capacity, count);
+hipError_t launch_nms(const BatchImage& d0, const ImgWork& w, int N, float threshold,
+                      hipStream_t s) {
+    const int count = w.items ? w.count : nms_blocks_of(d0.W, d0.H);
+    if (N < 3 || count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(nms_kernel, dim3(count, N - 2), dim3(256), 0, s, d0, w, threshold);
     return hipGetLastError();
 }
 

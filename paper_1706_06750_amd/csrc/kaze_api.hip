@@ -1,11 +1,13 @@
 // C ABI of libkaze: argument validation, the level schedule (Eqs. 6-7),
 // workspace layout and the launch sequence of the scale space (Sec. II-A,
-// Sec. III-A), detector response (Eq. 8) and extrema (Sec. II-B).
+// Sec. III-A), detector response (Eq. 8) and extrema (Sec. II-B), for one
+// image or for a batch of images replayed through a captured hipGraph.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "kaze.h"
@@ -32,6 +34,7 @@ const char* const kKernelNames[K_COUNT] = {
 
 struct Profiler {
     unsigned mask = 0;  // bit i: record launches of kernel i
+    bool capturing = false;
     std::vector<hipEvent_t> ev;  // pairs: start, stop
     int used = 0;
     static constexpr int kMaxPairs = 65536;
@@ -42,7 +45,8 @@ struct ProfScope {
     hipStream_t s;
     bool on;
     ProfScope(int id_, hipStream_t s_) : id(id_), s(s_), on(false) {
-        if (!(g_prof.mask & (1u << id)) || g_prof.used >= Profiler::kMaxPairs) return;
+        if (g_prof.capturing || !(g_prof.mask & (1u << id)) || g_prof.used >= Profiler::kMaxPairs)
+            return;
         const size_t need = 2 * (size_t)(g_prof.used + 1);
         while (g_prof.ev.size() < need) {
             hipEvent_t e;
@@ -67,6 +71,13 @@ struct ProfScope {
         if (e_ != hipSuccess)                                                         \
             return fail(KAZE_ERR_HIP, "%s launch failed: %s", kKernelNames[id],       \
                         hipGetErrorString(e_));                                       \
+    } while (0)
+
+#define KZ_HIP(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(KAZE_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
 // ---------------------------------------------------------------- parameters
@@ -132,9 +143,14 @@ void schedule(const kaze_params* p, std::vector<Level>& lv) {
     }
 }
 
+// Lines of at most 64 chunks (one per lane of the interface wavefront).
+bool shape_fits(int W, int H, int shape) {
+    return W <= kAosShapeTX[shape] * kWave && H <= kAosShapeTY[shape] * kWave;
+}
+
 kaze_status check_size(int W, int H) {
     if (W < 8 || H < 8) return fail(KAZE_ERR_INVALID_ARG, "image must be at least 8x8");
-    if (W > kTile * kWave || H > kTile * kWave)
+    if (!shape_fits(W, H, 0))
         return fail(KAZE_ERR_UNSUPPORTED, "image larger than %dx%d (got %dx%d)", kTile * kWave,
                     kTile * kWave, W, H);
     return KAZE_OK;
@@ -149,48 +165,15 @@ kaze_status check_steps(const kaze_params* p) {
     return KAZE_OK;
 }
 
-// ---------------------------------------------------------------- workspace
-struct Workspace {
-    size_t g, rrow, rcol, zrow, zcol, hist, hmax, total;
-};
-
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-
-Workspace layout(int W, int H, const kaze_params* p) {
-    Workspace w;
-    const size_t ncx = (W + kTile - 1) / kTile, ncy = (H + kTile - 1) / kTile;
-    const int nbins = p->k_bins > 0 ? p->k_bins : 1;
-    size_t off = 0;
-    w.g = off;    off = align256(off + (size_t)W * H * sizeof(float));
-    w.rrow = off; off = align256(off + (size_t)H * ncx * 8 * sizeof(float));
-    w.rcol = off; off = align256(off + (size_t)W * ncy * 8 * sizeof(float));
-    w.zrow = off; off = align256(off + (size_t)H * ncx * 2 * sizeof(float));
-    w.zcol = off; off = align256(off + (size_t)W * ncy * 2 * sizeof(float));
-    w.hist = off; off = align256(off + (size_t)nbins * sizeof(unsigned));
-    w.hmax = off; off = align256(off + sizeof(unsigned));
-    w.total = off;
-    return w;
+DetLevels det_levels(const std::vector<Level>& lv) {
+    DetLevels dl;
+    memset(&dl, 0, sizeof(dl));
+    for (size_t i = 0; i < lv.size(); ++i) {
+        dl.step[i] = lv[i].step;
+        dl.sn2[i] = (float)(lv[i].sigma_n * lv[i].sigma_n);
+    }
+    return dl;
 }
-
-ImageDesc image_desc(int W, int H, void* ws, const Workspace& w) {
-    char* base = static_cast<char*>(ws);
-    ImageDesc d;
-    d.L = nullptr;
-    d.Lnext = nullptr;
-    d.g = reinterpret_cast<float*>(base + w.g);
-    d.rrow = reinterpret_cast<float*>(base + w.rrow);
-    d.rcol = reinterpret_cast<float*>(base + w.rcol);
-    d.zrow = reinterpret_cast<float*>(base + w.zrow);
-    d.zcol = reinterpret_cast<float*>(base + w.zcol);
-    d.k = nullptr;
-    d.W = W;
-    d.H = H;
-    d.ncx = (W + kTile - 1) / kTile;
-    d.ncy = (H + kTile - 1) / kTile;
-    return d;
-}
-
-bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 // exact binary fraction of the percentile: pct = mant * 2^-shift
 void percentile_fraction(double pct, unsigned long long* mant, int* shift) {
@@ -206,14 +189,317 @@ void percentile_fraction(double pct, unsigned long long* mant, int* shift) {
     *shift = sh;
 }
 
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------- workspace
+// Per-image scratch: conductivity plane, interface equations and solutions
+// of the AOS tile shape, histogram and hmax.
+struct Scratch {
+    size_t g, rrow, rcol, zrow, zcol, hist, hmax, total;
+};
+
+Scratch scratch_layout(int W, int H, int nbins, int shape, size_t base) {
+    Scratch w;
+    const size_t ncx = (W + kAosShapeTX[shape] - 1) / kAosShapeTX[shape];
+    const size_t ncy = (H + kAosShapeTY[shape] - 1) / kAosShapeTY[shape];
+    size_t off = base;
+    w.g = off;    off = align256(off + (size_t)W * H * sizeof(float));
+    w.rrow = off; off = align256(off + (size_t)H * ncx * 8 * sizeof(float));
+    w.rcol = off; off = align256(off + (size_t)W * ncy * 8 * sizeof(float));
+    w.zrow = off; off = align256(off + (size_t)H * ncx * 2 * sizeof(float));
+    w.zcol = off; off = align256(off + (size_t)W * ncy * 2 * sizeof(float));
+    w.hist = off; off = align256(off + (size_t)(nbins > 0 ? nbins : 1) * sizeof(unsigned));
+    w.hmax = off; off = align256(off + sizeof(unsigned));
+    w.total = off - base;
+    return w;
+}
+
+int hist_bins(const kaze_params* p) { return p->k_override > 0.0 ? 1 : p->k_bins; }
+
+ImageDesc aos_desc(int W, int H, int shape, char* base, const Scratch& w, const float* k) {
+    ImageDesc d;
+    d.L = nullptr;
+    d.Lnext = nullptr;
+    d.g = reinterpret_cast<float*>(base + w.g);
+    d.rrow = reinterpret_cast<float*>(base + w.rrow);
+    d.rcol = reinterpret_cast<float*>(base + w.rcol);
+    d.zrow = reinterpret_cast<float*>(base + w.zrow);
+    d.zcol = reinterpret_cast<float*>(base + w.zcol);
+    d.k = k;
+    d.W = W;
+    d.H = H;
+    d.ncx = (W + kAosShapeTX[shape] - 1) / kAosShapeTX[shape];
+    d.ncy = (H + kAosShapeTY[shape] - 1) / kAosShapeTY[shape];
+    return d;
+}
+
+BatchImage batch_image(int W, int H) {
+    BatchImage b;
+    memset(&b, 0, sizeof(b));
+    b.W = W;
+    b.H = H;
+    return b;
+}
+
 // a3-a5: (conductivity +) chunk reduction, interface solves, recovery.
-kaze_status aos_step(const ImageDesc& d, const Taps& tc, float tau, bool compute_g, int gmode,
-                     float k_host, hipStream_t s) {
-    const WorkList none{nullptr, nullptr, 0};
+kaze_status aos_step(const ImageDesc& d, const AosWork& tiles, const AosWork& lines, int shape,
+                     const Taps& tc, float tau, bool compute_g, int gmode, float k_host,
+                     hipStream_t s) {
     KZ_LAUNCH(K_AOS_REDUCE, s,
-              launch_aos_reduce(d, none, tc, tau, compute_g, gmode, k_host, 0, s));
-    KZ_LAUNCH(K_AOS_IFACE, s, launch_aos_iface(d, none, 0, s));
-    KZ_LAUNCH(K_AOS_RECOVER, s, launch_aos_recover(d, none, tau, 0, s));
+              launch_aos_reduce(d, tiles, shape, tc, tau, compute_g, gmode, k_host, s));
+    KZ_LAUNCH(K_AOS_IFACE, s, launch_aos_iface(d, lines, s));
+    KZ_LAUNCH(K_AOS_RECOVER, s, launch_aos_recover(d, tiles, shape, tau, s));
+    return KAZE_OK;
+}
+
+// a1-a2: base image and contrast factor (or the given k) for one image or a
+// batch (images / tiles / hist items select the work).
+kaze_status base_and_k(const BatchImage& b0, const ImgWork& images, const ImgWork& tiles,
+                       const ImgWork& hist, const kaze_params* p, hipStream_t s) {
+    const Taps t0 = gauss_taps(p->sigma0);
+    const Taps tc = gauss_taps(p->sigma_cond);
+    const bool use_hist = !(p->k_override > 0.0);
+    KZ_LAUNCH(K_FILL, s,
+              launch_reset(b0, images, hist_bins(p), use_hist ? 0.f : (float)p->k_override, s));
+    KZ_LAUNCH(K_GAUSS, s, launch_gauss(b0, tiles, t0, s));
+    if (use_hist) {
+        unsigned long long mant;
+        int shift;
+        percentile_fraction(p->k_percentile, &mant, &shift);
+        KZ_LAUNCH(K_GRAD, s, launch_cond(b0, tiles, tc, 1.f, 2, s));
+        KZ_LAUNCH(K_HIST, s, launch_hist(b0, hist, p->k_bins, s));
+        KZ_LAUNCH(K_KSELECT, s, launch_kselect(b0, images, p->k_bins, mant, shift, s));
+    }
+    return KAZE_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// Batches: device tables, graph capture and replay.
+// ============================================================================
+struct kaze_batch {
+    int n = 0;
+    int N = 0;
+    int shape = 0;
+    bool with_det = false;
+    bool with_nms = false;
+    kaze_params p;
+    std::vector<Level> lv;
+    BatchImage* d_imgs = nullptr;
+    ImageDesc* d_lvl = nullptr;  // (N-1) x n, level i at row i-1
+    int2 *d_items = nullptr, *d_tiles = nullptr, *d_aos = nullptr, *d_lines = nullptr,
+         *d_hist = nullptr, *d_det = nullptr, *d_nms = nullptr;
+    int n_tiles = 0, n_aos = 0, n_lines = 0, n_hist = 0, n_det = 0, n_nms = 0;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+struct BatchLayout {
+    size_t imgs, lvl, items, tiles, aos, lines, hist, det, nms, tables_end;
+    std::vector<size_t> scratch;  // per image
+    size_t total;
+    int n_tiles, n_aos, n_lines, n_hist, n_det, n_nms;
+};
+
+BatchLayout batch_layout(const kaze_image_desc* im, int n, const kaze_params* p, int shape) {
+    BatchLayout L;
+    const int N = p->octaves * p->sublevels;
+    L.n_tiles = L.n_aos = L.n_lines = L.n_hist = L.n_det = L.n_nms = 0;
+    for (int j = 0; j < n; ++j) {
+        L.n_tiles += tiles_of(im[j].W, im[j].H);
+        L.n_aos += tiles_of(im[j].W, im[j].H, kAosShapeTX[shape], kAosShapeTY[shape]);
+        L.n_lines += im[j].W + im[j].H;
+        L.n_hist += (im[j].W * im[j].H + kHistChunk - 1) / kHistChunk;
+        L.n_det += det_tiles_of(im[j].W, im[j].H);
+        L.n_nms += nms_blocks_of(im[j].W, im[j].H);
+    }
+    size_t off = 0;
+    L.imgs = off;  off = align256(off + n * sizeof(BatchImage));
+    L.lvl = off;   off = align256(off + (size_t)(N > 1 ? N - 1 : 1) * n * sizeof(ImageDesc));
+    L.items = off; off = align256(off + n * sizeof(int2));
+    L.tiles = off; off = align256(off + L.n_tiles * sizeof(int2));
+    L.aos = off;   off = align256(off + L.n_aos * sizeof(int2));
+    L.lines = off; off = align256(off + L.n_lines * sizeof(int2));
+    L.hist = off;  off = align256(off + L.n_hist * sizeof(int2));
+    L.det = off;   off = align256(off + L.n_det * sizeof(int2));
+    L.nms = off;   off = align256(off + L.n_nms * sizeof(int2));
+    L.tables_end = off;
+    L.scratch.resize(n);
+    for (int j = 0; j < n; ++j) {
+        L.scratch[j] = off;
+        off += scratch_layout(im[j].W, im[j].H, hist_bins(p), shape, 0).total;
+    }
+    L.total = off;
+    return L;
+}
+
+kaze_status check_batch(const kaze_image_desc* im, int n, const kaze_params* p, int shape) {
+    kaze_status st = check_params(p);
+    if (st != KAZE_OK) return st;
+    if ((st = check_steps(p)) != KAZE_OK) return st;
+    if (!im || n < 1) return fail(KAZE_ERR_INVALID_ARG, "a batch needs at least one image");
+    if (shape < 0 || shape >= kAosShapes) return fail(KAZE_ERR_INVALID_ARG, "bad AOS tile shape");
+    const bool det0 = im[0].det != nullptr, cnt0 = im[0].count != nullptr;
+    for (int j = 0; j < n; ++j) {
+        const kaze_image_desc& d = im[j];
+        if ((st = check_size(d.W, d.H)) != KAZE_OK) return st;
+        if (!shape_fits(d.W, d.H, shape))
+            return fail(KAZE_ERR_UNSUPPORTED, "image %d (%dx%d) does not fit tile shape %dx%d", j,
+                        d.W, d.H, kAosShapeTX[shape], kAosShapeTY[shape]);
+        if (!d.img || !d.levels || !d.k)
+            return fail(KAZE_ERR_INVALID_ARG, "image %d: img, levels and k must be non-NULL", j);
+        if (d.ld_img < d.W) return fail(KAZE_ERR_INVALID_ARG, "image %d: ld_img < W", j);
+        if ((d.det != nullptr) != det0 || (d.count != nullptr) != cnt0)
+            return fail(KAZE_ERR_INVALID_ARG, "det and count must be given for all images or none");
+        if (d.count && !d.det)
+            return fail(KAZE_ERR_INVALID_ARG, "image %d: extrema need det", j);
+        if (d.capacity < 0 || (d.capacity > 0 && !d.kps))
+            return fail(KAZE_ERR_INVALID_ARG, "image %d: bad keypoint buffer", j);
+        if (!aligned(d.img, 4) || !aligned(d.levels, 4) || !aligned(d.k, 4) ||
+            (d.det && !aligned(d.det, 4)) || (d.count && !aligned(d.count, 4)) ||
+            (d.kps && !aligned(d.kps, 4)))
+            return fail(KAZE_ERR_INVALID_ARG, "image %d: buffers must be 4-byte aligned", j);
+    }
+    return KAZE_OK;
+}
+
+// The whole a1-a7 sequence of a batch, one launch per phase for all images.
+kaze_status enqueue_batch(const kaze_batch& B, hipStream_t s) {
+    const kaze_params* p = &B.p;
+    const BatchImage b0 = batch_image(0, 0);
+    const ImgWork images{B.d_imgs, B.d_items, B.n};
+    const ImgWork tiles{B.d_imgs, B.d_tiles, B.n_tiles};
+    const ImgWork hist{B.d_imgs, B.d_hist, B.n_hist};
+    kaze_status st = base_and_k(b0, images, tiles, hist, p, s);
+    if (st != KAZE_OK) return st;
+    const Taps tc = gauss_taps(p->sigma_cond);
+    const int gmode = p->diffusivity == KAZE_G2 ? 0 : 1;
+    ImageDesc a0;
+    memset(&a0, 0, sizeof(a0));
+    for (int i = 1; i < B.N; ++i) {
+        const ImageDesc* lvl = B.d_lvl + (size_t)(i - 1) * B.n;
+        const AosWork at{lvl, B.d_aos, B.n_aos};
+        const AosWork al{lvl, B.d_lines, B.n_lines};
+        st = aos_step(a0, at, al, B.shape, tc, (float)B.lv[i].tau, true, gmode, 1.f, s);
+        if (st != KAZE_OK) return st;
+    }
+    if (B.with_det) {
+        const ImgWork det{B.d_imgs, B.d_det, B.n_det};
+        KZ_LAUNCH(K_DET, s, launch_det(b0, det, B.N, det_levels(B.lv), s));
+    }
+    if (B.with_nms) {
+        const ImgWork nms{B.d_imgs, B.d_nms, B.n_nms};
+        KZ_LAUNCH(K_NMS, s, launch_nms(b0, nms, B.N, (float)p->det_threshold, s));
+    }
+    return KAZE_OK;
+}
+
+kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p, int shape,
+                         void* ws, size_t ws_bytes, kaze_batch** out) {
+    kaze_status st = check_batch(im, n, p, shape);
+    if (st != KAZE_OK) return st;
+    if (!out) return fail(KAZE_ERR_INVALID_ARG, "out pointer is NULL");
+    const BatchLayout L = batch_layout(im, n, p, shape);
+    if (!ws || !aligned(ws, 256) || ws_bytes < L.total)
+        return fail(KAZE_ERR_WORKSPACE, "batch workspace needs %zu bytes, 256-byte aligned (got %zu)",
+                    L.total, ws_bytes);
+    char* base = static_cast<char*>(ws);
+    kaze_batch* B = new kaze_batch();
+    B->n = n;
+    B->p = *p;
+    schedule(p, B->lv);
+    B->N = (int)B->lv.size();
+    B->shape = shape;
+    B->with_det = im[0].det != nullptr;
+    B->with_nms = im[0].count != nullptr;
+    B->d_imgs = reinterpret_cast<BatchImage*>(base + L.imgs);
+    B->d_lvl = reinterpret_cast<ImageDesc*>(base + L.lvl);
+    B->d_items = reinterpret_cast<int2*>(base + L.items);
+    B->d_tiles = reinterpret_cast<int2*>(base + L.tiles);
+    B->d_aos = reinterpret_cast<int2*>(base + L.aos);
+    B->d_lines = reinterpret_cast<int2*>(base + L.lines);
+    B->d_hist = reinterpret_cast<int2*>(base + L.hist);
+    B->d_det = reinterpret_cast<int2*>(base + L.det);
+    B->d_nms = reinterpret_cast<int2*>(base + L.nms);
+    B->n_tiles = L.n_tiles;
+    B->n_aos = L.n_aos;
+    B->n_lines = L.n_lines;
+    B->n_hist = L.n_hist;
+    B->n_det = L.n_det;
+    B->n_nms = L.n_nms;
+
+    // host image of the tables, uploaded once
+    std::vector<char> host(L.tables_end, 0);
+    BatchImage* himgs = reinterpret_cast<BatchImage*>(host.data() + L.imgs);
+    ImageDesc* hlvl = reinterpret_cast<ImageDesc*>(host.data() + L.lvl);
+    int2* hitems = reinterpret_cast<int2*>(host.data() + L.items);
+    int2* ht = reinterpret_cast<int2*>(host.data() + L.tiles);
+    int2* ha = reinterpret_cast<int2*>(host.data() + L.aos);
+    int2* hl = reinterpret_cast<int2*>(host.data() + L.lines);
+    int2* hh = reinterpret_cast<int2*>(host.data() + L.hist);
+    int2* hd = reinterpret_cast<int2*>(host.data() + L.det);
+    int2* hn = reinterpret_cast<int2*>(host.data() + L.nms);
+    int it = 0, ia = 0, il = 0, ih = 0, idt = 0, inm = 0;
+    const int nb = hist_bins(p);
+    for (int j = 0; j < n; ++j) {
+        const kaze_image_desc& d = im[j];
+        const Scratch sc = scratch_layout(d.W, d.H, nb, shape, L.scratch[j]);
+        BatchImage b = batch_image(d.W, d.H);
+        b.img = d.img;
+        b.ld = d.ld_img;
+        b.levels = d.levels;
+        b.det = d.det;
+        b.g = reinterpret_cast<float*>(base + sc.g);
+        b.hist = reinterpret_cast<unsigned*>(base + sc.hist);
+        b.hmax = reinterpret_cast<unsigned*>(base + sc.hmax);
+        b.k = d.k;
+        b.kps = d.kps;
+        b.capacity = d.capacity;
+        b.count = d.count;
+        himgs[j] = b;
+        hitems[j] = make_int2(j, 0);
+        const size_t plane = (size_t)d.W * d.H;
+        for (int i = 1; i < B->N; ++i) {
+            ImageDesc a = aos_desc(d.W, d.H, shape, base, sc, d.k);
+            a.L = d.levels + plane * (i - 1);
+            a.Lnext = d.levels + plane * i;
+            hlvl[(size_t)(i - 1) * n + j] = a;
+        }
+        for (int t = 0; t < tiles_of(d.W, d.H); ++t) ht[it++] = make_int2(j, t);
+        for (int t = 0; t < tiles_of(d.W, d.H, kAosShapeTX[shape], kAosShapeTY[shape]); ++t)
+            ha[ia++] = make_int2(j, t);
+        for (int t = 0; t < d.W + d.H; ++t) hl[il++] = make_int2(j, t);
+        for (int t = 0; t < (d.W * d.H + kHistChunk - 1) / kHistChunk; ++t) hh[ih++] = make_int2(j, t);
+        for (int t = 0; t < det_tiles_of(d.W, d.H); ++t) hd[idt++] = make_int2(j, t);
+        for (int t = 0; t < nms_blocks_of(d.W, d.H); ++t) hn[inm++] = make_int2(j, t);
+    }
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipMemcpy(base, host.data(), L.tables_end, hipMemcpyHostToDevice);
+    // capture the whole sequence once on a private stream (default priority)
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) {
+        g_prof.capturing = true;
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            st = enqueue_batch(*B, cs);
+            const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+            if (st == KAZE_OK && e2 != hipSuccess) e = e2;
+        }
+        g_prof.capturing = false;
+    }
+    if (e == hipSuccess && st == KAZE_OK) e = hipGraphInstantiate(&B->exec, graph, nullptr, nullptr, 0);
+    if (graph) hipGraphDestroy(graph);
+    if (cs) hipStreamDestroy(cs);
+    if (st != KAZE_OK || e != hipSuccess) {
+        delete B;
+        return st != KAZE_OK ? st : fail(KAZE_ERR_HIP, "batch graph setup failed: %s",
+                                         hipGetErrorString(e));
+    }
+    *out = B;
     return KAZE_OK;
 }
 
@@ -228,8 +514,8 @@ kaze_status kaze_default_params(kaze_params* p) {
     p->sigma0 = 1.6;
     p->sigma_cond = 1.0;
     p->diffusivity = KAZE_G2;
-    p->k_percentile = 0.7;
     p->k_bins = 300;
+    p->k_percentile = 0.7;
     p->k_override = 0.0;
     p->det_threshold = 0.001;
     return KAZE_OK;
@@ -259,7 +545,7 @@ kaze_status kaze_schedule(const kaze_params* p, double* sigma, double* t, double
 
 size_t kaze_workspace_bytes(int W, int H, const kaze_params* p) {
     if (check_params(p) != KAZE_OK || check_size(W, H) != KAZE_OK) return 0;
-    return layout(W, H, p).total;
+    return scratch_layout(W, H, hist_bins(p), 0, 0).total;
 }
 
 kaze_status kaze_build_scale_space(const float* img, int W, int H, int ld_img,
@@ -273,48 +559,36 @@ kaze_status kaze_build_scale_space(const float* img, int W, int H, int ld_img,
     if (ld_img < W) return fail(KAZE_ERR_INVALID_ARG, "ld_img (%d) < W (%d)", ld_img, W);
     if (!aligned(img, 4) || !aligned(levels, 4) || !aligned(k_out, 4))
         return fail(KAZE_ERR_INVALID_ARG, "float buffers must be 4-byte aligned");
-    const Workspace w = layout(W, H, p);
+    const Scratch w = scratch_layout(W, H, hist_bins(p), 0, 0);
     if (!ws || !aligned(ws, 256) || ws_bytes < w.total)
         return fail(KAZE_ERR_WORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
                     w.total, ws_bytes);
 
     hipStream_t s = static_cast<hipStream_t>(stream);
-    ImageDesc d = image_desc(W, H, ws, w);
     char* base = static_cast<char*>(ws);
-    unsigned* hist = reinterpret_cast<unsigned*>(base + w.hist);
-    unsigned* hmax = reinterpret_cast<unsigned*>(base + w.hmax);
+    BatchImage b = batch_image(W, H);
+    b.img = img;
+    b.ld = ld_img;
+    b.levels = levels;
+    b.g = reinterpret_cast<float*>(base + w.g);
+    b.hist = reinterpret_cast<unsigned*>(base + w.hist);
+    b.hmax = reinterpret_cast<unsigned*>(base + w.hmax);
+    b.k = k_out;
+    const ImgWork none{nullptr, nullptr, 0};
+    st = base_and_k(b, none, none, none, p, s);
+    if (st != KAZE_OK) return st;
 
     std::vector<Level> lv;
     schedule(p, lv);
-    const int N = (int)lv.size();
     const size_t plane = (size_t)W * H;
-    const Taps t0 = gauss_taps(p->sigma0);
     const Taps tc = gauss_taps(p->sigma_cond);
     const int gmode = p->diffusivity == KAZE_G2 ? 0 : 1;
-
-    // a1: base image L_0 = G_sigma0 * img
-    KZ_LAUNCH(K_GAUSS, s, launch_gauss(img, ld_img, levels, W, H, t0, s));
-
-    // a2: contrast factor k from the gradient histogram of L_0
-    if (!(p->k_override > 0.0)) {
-        unsigned long long mant;
-        int shift;
-        percentile_fraction(p->k_percentile, &mant, &shift);
-        KZ_LAUNCH(K_FILL, s, launch_fill_u32(hist, p->k_bins, 0u, s));
-        KZ_LAUNCH(K_FILL, s, launch_fill_u32(hmax, 1, 0u, s));
-        KZ_LAUNCH(K_GRAD, s, launch_cond(levels, d.g, W, H, tc, nullptr, 1.f, 2, hmax, s));
-        KZ_LAUNCH(K_HIST, s, launch_hist(d.g, (int)plane, hmax, hist, p->k_bins, s));
-        KZ_LAUNCH(K_KSELECT, s, launch_kselect(hist, p->k_bins, hmax, mant, shift, k_out, s));
-    } else {
-        KZ_LAUNCH(K_FILL, s, launch_fill_f32(k_out, 1, (float)p->k_override, s));
-    }
-    d.k = k_out;
-
-    // a3-a5: one AOS step per level, conductivity from the previous level
-    for (int i = 1; i < N; ++i) {
+    ImageDesc d = aos_desc(W, H, 0, base, w, k_out);
+    const AosWork anone{nullptr, nullptr, 0};
+    for (size_t i = 1; i < lv.size(); ++i) {
         d.L = levels + plane * (i - 1);
         d.Lnext = levels + plane * i;
-        st = aos_step(d, tc, (float)lv[i].tau, true, gmode, 1.f, s);
+        st = aos_step(d, anone, anone, 0, tc, (float)lv[i].tau, true, gmode, 1.f, s);
         if (st != KAZE_OK) return st;
     }
     return KAZE_OK;
@@ -330,9 +604,12 @@ kaze_status kaze_conductivity(const float* L, int W, int H, const kaze_params* p
         return fail(KAZE_ERR_INVALID_ARG, "float buffers must be 4-byte aligned");
     if (!(k > 0.0) || !isfinite(k)) return fail(KAZE_ERR_INVALID_ARG, "k must be > 0");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Taps tc = gauss_taps(p->sigma_cond);
+    BatchImage b = batch_image(W, H);
+    b.levels = const_cast<float*>(L);  // read only
+    b.g = g;
     const int gmode = p->diffusivity == KAZE_G2 ? 0 : 1;
-    KZ_LAUNCH(K_COND, s, launch_cond(L, g, W, H, tc, nullptr, (float)k, gmode, nullptr, s));
+    const ImgWork none{nullptr, nullptr, 0};
+    KZ_LAUNCH(K_COND, s, launch_cond(b, none, gauss_taps(p->sigma_cond), (float)k, gmode, s));
     return KAZE_OK;
 }
 
@@ -346,15 +623,16 @@ kaze_status kaze_aos_step(const float* L, const float* g, int W, int H, double t
     if (!(tau > 0.0) || !isfinite(tau)) return fail(KAZE_ERR_INVALID_ARG, "tau must be > 0");
     kaze_params p;
     kaze_default_params(&p);
-    const Workspace w = layout(W, H, &p);
+    const Scratch w = scratch_layout(W, H, hist_bins(&p), 0, 0);
     if (!ws || !aligned(ws, 256) || ws_bytes < w.total)
         return fail(KAZE_ERR_WORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
                     w.total, ws_bytes);
-    ImageDesc d = image_desc(W, H, ws, w);
+    ImageDesc d = aos_desc(W, H, 0, static_cast<char*>(ws), w, nullptr);
     d.L = L;
     d.Lnext = L_next;
     d.g = const_cast<float*>(g);  // read only when the conductivity is given
-    return aos_step(d, gauss_taps(p.sigma_cond), (float)tau, false, 0, 1.f,
+    const AosWork anone{nullptr, nullptr, 0};
+    return aos_step(d, anone, anone, 0, gauss_taps(p.sigma_cond), (float)tau, false, 0, 1.f,
                     static_cast<hipStream_t>(stream));
 }
 
@@ -369,14 +647,12 @@ kaze_status kaze_detector_response(const float* levels, int W, int H, const kaze
         return fail(KAZE_ERR_INVALID_ARG, "float buffers must be 4-byte aligned");
     std::vector<Level> lv;
     schedule(p, lv);
-    DetLevels dl;
-    memset(&dl, 0, sizeof(dl));
-    for (size_t i = 0; i < lv.size(); ++i) {
-        dl.step[i] = lv[i].step;
-        dl.sn2[i] = (float)(lv[i].sigma_n * lv[i].sigma_n);
-    }
+    BatchImage b = batch_image(W, H);
+    b.levels = const_cast<float*>(levels);  // read only
+    b.det = det;
+    const ImgWork none{nullptr, nullptr, 0};
     hipStream_t s = static_cast<hipStream_t>(stream);
-    KZ_LAUNCH(K_DET, s, launch_det(levels, det, W, H, (int)lv.size(), dl, s));
+    KZ_LAUNCH(K_DET, s, launch_det(b, none, (int)lv.size(), det_levels(lv), s));
     return KAZE_OK;
 }
 
@@ -391,28 +667,124 @@ kaze_status kaze_find_extrema(const float* det, int W, int H, const kaze_params*
     if (!aligned(det, 4) || !aligned(count, 4) || (kps && !aligned(kps, 4)))
         return fail(KAZE_ERR_INVALID_ARG, "buffers must be 4-byte aligned");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int N = p->octaves * p->sublevels;
-    KZ_LAUNCH(K_FILL, s, launch_fill_u32(reinterpret_cast<unsigned*>(count), 1, 0u, s));
-    KZ_LAUNCH(K_NMS, s, launch_nms(det, W, H, N, (float)p->det_threshold, kps, capacity, count, s));
+    BatchImage b = batch_image(W, H);
+    b.det = const_cast<float*>(det);  // read only
+    b.kps = kps;
+    b.capacity = capacity;
+    b.count = count;
+    const ImgWork none{nullptr, nullptr, 0};
+    KZ_LAUNCH(K_FILL, s, launch_reset(b, none, 0, 0.f, s));
+    KZ_LAUNCH(K_NMS, s, launch_nms(b, none, p->octaves * p->sublevels, (float)p->det_threshold, s));
     return KAZE_OK;
 }
 
+// ---------------------------------------------------------------- batches
+size_t kaze_batch_workspace_bytes(const kaze_image_desc* images, int n, const kaze_params* p,
+                                  const kaze_batch_config* cfg) {
+    if (check_params(p) != KAZE_OK || !images || n < 1) return 0;
+    size_t best = 0;
+    for (int sh = 0; sh < kAosShapes; ++sh) {
+        if (cfg && cfg->aos_shape >= 0 && cfg->aos_shape != sh) continue;
+        bool fits = true;
+        for (int j = 0; j < n; ++j)
+            fits = fits && check_size(images[j].W, images[j].H) == KAZE_OK &&
+                   shape_fits(images[j].W, images[j].H, sh);
+        if (fits) best = std::max(best, batch_layout(images, n, p, sh).total);
+    }
+    return best;
+}
+
+kaze_status kaze_batch_create(const kaze_image_desc* images, int n, const kaze_params* p,
+                              const kaze_batch_config* cfg, void* ws, size_t ws_bytes,
+                              kaze_batch** out) {
+    const int shape = cfg && cfg->aos_shape >= 0 ? cfg->aos_shape : 0;
+    return batch_create(images, n, p, shape, ws, ws_bytes, out);
+}
+
+kaze_status kaze_batch_run(kaze_batch* b, int eager, void* stream) {
+    if (!b) return fail(KAZE_ERR_INVALID_ARG, "batch is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (eager) return enqueue_batch(*b, s);
+    KZ_HIP(hipGraphLaunch(b->exec, s));
+    return KAZE_OK;
+}
+
+kaze_status kaze_batch_destroy(kaze_batch* b) {
+    if (!b) return KAZE_OK;
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    delete b;
+    return KAZE_OK;
+}
+
+kaze_status kaze_batch_autotune(const kaze_image_desc* images, int n, const kaze_params* p,
+                                void* ws, size_t ws_bytes, int reps, void* stream,
+                                kaze_batch_config* best, double* ms_per_shape) {
+    if (!best) return fail(KAZE_ERR_INVALID_ARG, "best is NULL");
+    if (reps < 1) return fail(KAZE_ERR_INVALID_ARG, "reps must be >= 1");
+    if (!images || n < 1) return fail(KAZE_ERR_INVALID_ARG, "a batch needs at least one image");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double best_ms = -1.0;
+    int best_shape = -1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    KZ_HIP(hipEventCreate(&e0));
+    KZ_HIP(hipEventCreate(&e1));
+    kaze_status result = KAZE_OK;
+    for (int sh = 0; sh < kAosShapes; ++sh) {
+        if (ms_per_shape) ms_per_shape[sh] = -1.0;
+        bool fits = true;
+        for (int j = 0; j < n; ++j) fits = fits && shape_fits(images[j].W, images[j].H, sh);
+        if (!fits) continue;
+        kaze_batch* b = nullptr;
+        kaze_status st = batch_create(images, n, p, sh, ws, ws_bytes, &b);
+        if (st != KAZE_OK) {
+            result = st;
+            break;
+        }
+        hipError_t e = hipGraphLaunch(b->exec, s);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(b->exec, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        kaze_batch_destroy(b);
+        if (e != hipSuccess) {
+            result = fail(KAZE_ERR_HIP, "autotune timing failed: %s", hipGetErrorString(e));
+            break;
+        }
+        const double per = (double)ms / reps;
+        if (ms_per_shape) ms_per_shape[sh] = per;
+        if (best_shape < 0 || per < best_ms) {
+            best_ms = per;
+            best_shape = sh;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (result != KAZE_OK) return result;
+    if (best_shape < 0) return fail(KAZE_ERR_UNSUPPORTED, "no AOS tile shape fits the batch");
+    best->aos_shape = best_shape;
+    return KAZE_OK;
+}
+
+// ---------------------------------------------------------------- utility
 const char* kaze_last_error(void) { return g_err; }
 
 kaze_status kaze_profile_begin(const char* kernel_names) {
     if (!kernel_names) return fail(KAZE_ERR_INVALID_ARG, "kernel name list is NULL");
     unsigned mask = 0;
-    const char* p = kernel_names;
-    while (*p) {
-        const char* e = strchr(p, ',');
-        const size_t n = e ? (size_t)(e - p) : strlen(p);
+    const char* q = kernel_names;
+    while (*q) {
+        const char* e = strchr(q, ',');
+        const size_t n = e ? (size_t)(e - q) : strlen(q);
         int found = -1;
         for (int i = 0; i < K_COUNT; ++i)
-            if (strlen(kKernelNames[i]) == n && strncmp(p, kKernelNames[i], n) == 0) found = i;
-        if (found < 0) return fail(KAZE_ERR_INVALID_ARG, "unknown kernel name in '%s'", kernel_names);
+            if (strlen(kKernelNames[i]) == n && strncmp(q, kKernelNames[i], n) == 0) found = i;
+        if (found < 0)
+            return fail(KAZE_ERR_INVALID_ARG, "unknown kernel name in '%s'", kernel_names);
         mask |= 1u << found;
-        p += n;
-        if (*p == ',') ++p;
+        q += n;
+        if (*q == ',') ++q;
     }
     if (!mask) return fail(KAZE_ERR_INVALID_ARG, "empty kernel name list");
     g_prof.mask = mask;

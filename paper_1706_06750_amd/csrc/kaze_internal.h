@@ -121,15 +121,33 @@ __device__ __forceinline__ void wave_pcr_pairs(Eq e0, Eq e1, int lane, float& z0
 }  // namespace kaze
 
 // ---------------------------------------------------------------------------
-// Tile-partitioned AOS step: data shared by the kernels of one step.
+// Descriptors and work lists shared by the kernels and the host code.
 // ---------------------------------------------------------------------------
 namespace kaze {
 
-constexpr int kTile = 64;        // tile edge = chunk length of every line solve
+constexpr int kTile = 64;          // edge of the stencil tiles; default AOS tile
 constexpr int kMaxCondRadius = 4;  // sigma_cond radius that keeps the fused tile within 64 KB of LDS
+constexpr int kHistChunk = 8192;   // pixels per block of the histogram kernel
+constexpr int kNmsRows = 8;        // rows per thread of the extrema kernel
 
-// One image of an AOS step.  Row line y is cut into ncx chunks of kTile
-// pixels (tile columns), column line x into ncy chunks (tile rows).
+// Buffers of one image of a (possibly batched) scale-space computation.
+struct BatchImage {
+    const float* img;   // input, row pitch ld
+    int ld;
+    float* levels;      // N planes of W x H
+    float* det;         // N planes of W x H
+    float* g;           // conductivity plane (squared gradient while k is formed)
+    unsigned* hist;     // k histogram
+    unsigned* hmax;     // running max of |grad| (float bits)
+    float* k;           // contrast factor (device scalar)
+    void* kps;          // keypoints, capacity entries
+    int capacity;
+    int* count;
+    int W, H;
+};
+
+// One image of an AOS step.  Row line y is cut into ncx chunks of TX pixels
+// (tile columns), column line x into ncy chunks of TY pixels (tile rows).
 struct ImageDesc {
     const float* L;   // level i-1, W x H, pitch W
     float* Lnext;     // level i
@@ -142,18 +160,37 @@ struct ImageDesc {
     int W, H, ncx, ncy;
 };
 
-// Work list of a batched launch: entry t names an image and a tile (or a
-// line) inside it.  With a NULL list the launch covers image 0 only and
-// entry t is tile/line t of the descriptor passed by value.
-struct WorkList {
-    const ImageDesc* descs;  // device table, one per image (or NULL)
-    const int2* items;       // {image, local tile or line index}
+// Work list of a batched launch: entry t names an image (index into descs)
+// and a local tile, line or block index inside it.  With a NULL list the
+// launch covers the single image passed by value and entry t is local
+// index t.
+template <class D>
+struct Work {
+    const D* descs;
+    const int2* items;
     int count;
 };
 
-inline int tiles_of(int W, int H) {
-    return ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
+template <class D>
+__device__ __forceinline__ void resolve(const D& d0, const Work<D>& w, int t, D& d, int& local) {
+    if (w.items) {
+        const int2 it = w.items[t];
+        d = w.descs[it.x];
+        local = it.y;
+    } else {
+        d = d0;
+        local = t;
+    }
 }
+
+inline int tiles_of(int W, int H, int tx = kTile, int ty = kTile) {
+    return ((W + tx - 1) / tx) * ((H + ty - 1) / ty);
+}
+
+// AOS tile shapes the autotuner chooses from (row chunk TX x column chunk TY).
+constexpr int kAosShapes = 4;
+constexpr int kAosShapeTX[kAosShapes] = {64, 64, 32, 32};
+constexpr int kAosShapeTY[kAosShapes] = {64, 32, 64, 32};
 
 enum KernelId {
     K_GAUSS = 0,
@@ -171,40 +208,45 @@ enum KernelId {
     K_COUNT
 };
 
-hipError_t launch_gauss(const float* src, int ld_src, float* dst, int W, int H,
-                        const Taps& taps, hipStream_t s);
-// Conductivity of L on 64x64 tiles (the same code as the fused AOS kernel).
-// mode 0: g2, 1: g1, 2: squared gradient magnitude and the running maximum
-// of |grad| into hmax_bits.  k is read from k_dev, or k_host if NULL.
-hipError_t launch_cond(const float* L, float* out, int W, int H, const Taps& taps,
-                       const float* k_dev, float k_host, int mode, unsigned* hmax_bits,
-                       hipStream_t s);
-hipError_t launch_hist(const float* m2, int n, const unsigned* hmax_bits, unsigned* hist,
-                       int nbins, hipStream_t s);
-hipError_t launch_kselect(const unsigned* hist, int nbins, const unsigned* hmax_bits,
-                          unsigned long long pct_mant, int pct_shift, float* k_out,
-                          hipStream_t s);
-hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t s);
-hipError_t launch_fill_f32(float* p, int n, float v, hipStream_t s);
+using ImgWork = Work<BatchImage>;
+using AosWork = Work<ImageDesc>;
 
-// AOS step in three launches.  reduce: (conductivity if compute_g, else g
-// is read) + chunk reduction of every row and column chunk; iface: the
-// interface system of every line by wavefront PCR; recover: interior of
-// every chunk and L_next = L + (delta_x + delta_y)/2.
-// grid_cap > 0 caps the grid of the line kernel (wavefronts loop over the
-// list); the tile kernels run one block per tile.
-hipError_t launch_aos_reduce(const ImageDesc& d0, const WorkList& w, const Taps& tc,
-                             float tau, bool compute_g, int gmode, float k_host, int grid_cap,
-                             hipStream_t s);
-hipError_t launch_aos_iface(const ImageDesc& d0, const WorkList& w, int grid_cap,
-                            hipStream_t s);
-hipError_t launch_aos_recover(const ImageDesc& d0, const WorkList& w, float tau, int grid_cap,
+// a1: levels[0] = G_sigma0 * img on 64x64 tiles (items: image, tile).
+hipError_t launch_gauss(const BatchImage& d0, const ImgWork& w, const Taps& taps, hipStream_t s);
+// Conductivity of levels[0] into g on 64x64 tiles (items: image, tile):
+// mode 0: g2, 1: g1 (k from d.k, or k_host if NULL), 2: squared gradient
+// magnitude and the running maximum of |grad| into hmax.
+hipError_t launch_cond(const BatchImage& d0, const ImgWork& w, const Taps& taps, float k_host,
+                       int mode, hipStream_t s);
+// a2: histogram of sqrt(g) (items: image, chunk of kHistChunk pixels) and
+// the quantile (items: image, 0).
+hipError_t launch_hist(const BatchImage& d0, const ImgWork& w, int nbins, hipStream_t s);
+hipError_t launch_kselect(const BatchImage& d0, const ImgWork& w, int nbins,
+                          unsigned long long pct_mant, int pct_shift, hipStream_t s);
+// Per image (items: image, 0): zero hist, hmax and count; k = k_fill if > 0.
+hipError_t launch_reset(const BatchImage& d0, const ImgWork& w, int nbins, float k_fill,
+                        hipStream_t s);
+
+// a3-a5: AOS step in three launches with tiles of kAosShapeTX/TY[shape].
+// reduce: (conductivity if compute_g, else g is read) + chunk reduction of
+// every row and column chunk; iface: the interface system of every line by
+// wavefront PCR (items: image, line; rows first, then columns); recover:
+// interior of every chunk and L_next = L + (delta_x + delta_y)/2.
+hipError_t launch_aos_reduce(const ImageDesc& d0, const AosWork& w, int shape, const Taps& tc,
+                             float tau, bool compute_g, int gmode, float k_host, hipStream_t s);
+hipError_t launch_aos_iface(const ImageDesc& d0, const AosWork& w, hipStream_t s);
+hipError_t launch_aos_recover(const ImageDesc& d0, const AosWork& w, int shape, float tau,
                               hipStream_t s);
 
-hipError_t launch_det(const float* levels, float* det, int W, int H, int N,
-                      const DetLevels& dl, hipStream_t s);
-hipError_t launch_nms(const float* det, int W, int H, int N, float threshold, void* kps,
-                      int capacity, int* count, hipStream_t s);
+// a6: det of every level (items: image, det tile of 64 x 32).
+hipError_t launch_det(const BatchImage& d0, const ImgWork& w, int N, const DetLevels& dl,
+                      hipStream_t s);
+int det_tiles_of(int W, int H);
+// a7: extrema of levels 1..N-2 (items: image, block of 64 x 4*kNmsRows pixels).
+hipError_t launch_nms(const BatchImage& d0, const ImgWork& w, int N, float threshold,
+                      hipStream_t s);
+int nms_blocks_of(int W, int H);
+hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t s);
 hipError_t launch_copy(const float* src, float* dst, size_t n, hipStream_t s);
 
 }  // namespace kaze

@@ -23,16 +23,20 @@ struct GaussGeom {
 
 // L_0 = G_sigma0 * img on one 64x64 tile: horizontal then vertical pass.
 template <int R>
-__global__ __launch_bounds__(kTileThreads) void gauss_kernel(const float* __restrict__ src, int ld,
-                                                               float* __restrict__ dst, int W,
-                                                               int H, Taps taps) {
+__global__ __launch_bounds__(kTileThreads) void gauss_kernel(BatchImage d0, ImgWork work, Taps taps) {
     using G = GaussGeom<R>;
     constexpr int T = 2 * R + 1;
     extern __shared__ float smem[];
     float* sI = smem;
     float* sH = smem + G::offH;
+    BatchImage d;
+    int lt;
+    resolve(d0, work, (int)blockIdx.x, d, lt);
+    const float* __restrict__ src = d.img;
+    float* __restrict__ dst = d.levels;
+    const int W = d.W, H = d.H, ld = d.ld;
     const int ncx = (W + kTile - 1) / kTile;
-    const int tx0 = (blockIdx.x % ncx) * kTile, ty0 = (blockIdx.x / ncx) * kTile;
+    const int tx0 = (lt % ncx) * kTile, ty0 = (lt / ncx) * kTile;
     // staged load (the source has row pitch ld)
     {
         constexpr int TOTAL = G::n * G::n, PER = (TOTAL + kTileThreads - 1) / kTileThreads;
@@ -114,27 +118,28 @@ __global__ __launch_bounds__(kTileThreads) void gauss_kernel(const float* __rest
 // mode 1: g1 = exp(-|grad|^2/k^2)     (Eq. 3)
 // mode 2: |grad|^2, and the running maximum of |grad| (for the histogram).
 template <int RG>
-__global__ __launch_bounds__(kTileThreads) void cond_kernel(const float* __restrict__ L,
-                                                              float* __restrict__ out, int W,
-                                                              int H, Taps taps,
-                                                              const float* __restrict__ k_dev,
-                                                              float k_host, int mode,
-                                                              unsigned* __restrict__ hmax_bits) {
+__global__ __launch_bounds__(kTileThreads) void cond_kernel(BatchImage d0, ImgWork w, Taps taps,
+                                                              float k_host, int mode) {
     using G = CondGeom<RG>;
     extern __shared__ float smem[];
     __shared__ float s_max[kTileThreads / kWave];
     float* sL = smem;
     float* sS = smem + G::offS;
+    BatchImage d;
+    int lt;
+    resolve(d0, w, (int)blockIdx.x, d, lt);
+    const int W = d.W, H = d.H;
+    float* __restrict__ out = d.g;
     const int ncx = (W + kTile - 1) / kTile;
-    const int tx0 = (blockIdx.x % ncx) * kTile, ty0 = (blockIdx.x / ncx) * kTile;
-    load_L_ring<RG>(L, W, H, tx0, ty0, sL);
+    const int tx0 = (lt % ncx) * kTile, ty0 = (lt / ncx) * kTile;
+    load_L_ring<G>(d.levels, W, H, tx0, ty0, sL);
     __syncthreads();
-    smooth_tile<RG>(sL, sS, taps);
+    smooth_tile<G>(sL, sS, taps);
     __syncthreads();
-    const float k = (mode == 2) ? 1.f : (k_dev ? k_dev[0] : k_host);
+    const float k = (mode == 2) ? 1.f : (d.k ? d.k[0] : k_host);
     const float inv_k2 = 1.f / (k * k);
     float local_max = 0.f;
-    scharr_pass<RG>(sS, [&](int gy, int gx, float m2) {
+    scharr_pass<G>(sS, [&](int gy, int gx, float m2) {
         const int y = ty0 - 1 + gy, x = tx0 - 1 + gx;
         if (gy < 1 || gy > kTile || gx < 1 || gx > kTile || y >= H || x >= W) return;
         float v;
@@ -157,7 +162,7 @@ __global__ __launch_bounds__(kTileThreads) void cond_kernel(const float* __restr
         if (t == 0) {
             float m = s_max[0];
             for (int i = 1; i < kTileThreads / kWave; ++i) m = fmaxf(m, s_max[i]);
-            atomicMax(hmax_bits, __float_as_uint(m));
+            atomicMax(d.hmax, __float_as_uint(m));
         }
     }
 }
@@ -166,16 +171,19 @@ __global__ __launch_bounds__(kTileThreads) void cond_kernel(const float* __restr
 // 300-bin (nbins) histogram of |grad| = sqrt(m2) over pixels with m2 > 0:
 // bin = min(floor(|grad|/hmax * nbins), nbins-1).  Integer atomics only, so
 // the counts are deterministic.
-__global__ __launch_bounds__(256) void hist_kernel(const float* __restrict__ m2, int n,
-                                                     const unsigned* __restrict__ hmax_bits,
-                                                     unsigned* __restrict__ hist, int nbins) {
+__global__ __launch_bounds__(256) void hist_kernel(BatchImage d0, ImgWork w, int nbins) {
     extern __shared__ unsigned s_hist[];
+    BatchImage d;
+    int chunk;
+    resolve(d0, w, (int)blockIdx.x, d, chunk);
     for (int i = threadIdx.x; i < nbins; i += blockDim.x) s_hist[i] = 0u;
     __syncthreads();
-    const float hmax = __uint_as_float(hmax_bits[0]);
+    const float hmax = __uint_as_float(d.hmax[0]);
     const float fb = (float)nbins;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const float v = m2[i];
+    const int n = d.W * d.H;
+    const int i0 = chunk * kHistChunk, i1 = min(n, i0 + kHistChunk);
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        const float v = d.g[i];
         if (v > 0.f) {
             const float m = sqrtf(v);
             int b = (int)floorf(m / hmax * fb);
@@ -186,7 +194,7 @@ __global__ __launch_bounds__(256) void hist_kernel(const float* __restrict__ m2,
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nbins; i += blockDim.x)
-        if (s_hist[i]) atomicAdd(&hist[i], s_hist[i]);
+        if (s_hist[i]) atomicAdd(&d.hist[i], s_hist[i]);
 }
 
 // Smallest bin b whose cumulative count reaches percentile * npos; k is its
@@ -195,10 +203,13 @@ __global__ __launch_bounds__(256) void hist_kernel(const float* __restrict__ m2,
 // test cum >= pct * npos is made exactly in 128-bit integers.  One block:
 // per-thread segment sums, a block scan, then each thread searches its
 // segment.
-__global__ __launch_bounds__(256) void kselect_kernel(const unsigned* __restrict__ hist, int nbins,
-                                                        const unsigned* __restrict__ hmax_bits,
-                                                        unsigned long long pct_mant, int pct_shift,
-                                                        float* __restrict__ k_out) {
+__global__ __launch_bounds__(256) void kselect_kernel(BatchImage d0, ImgWork w, int nbins,
+                                                        unsigned long long pct_mant,
+                                                        int pct_shift) {
+    BatchImage d;
+    int unused;
+    resolve(d0, w, (int)blockIdx.x, d, unused);
+    const unsigned* __restrict__ hist = d.hist;
     __shared__ unsigned long long s_scan[256];
     __shared__ int s_best;
     const int t = threadIdx.x;
@@ -217,7 +228,7 @@ __global__ __launch_bounds__(256) void kselect_kernel(const unsigned* __restrict
     }
     const unsigned long long npos = s_scan[255];
     if (npos == 0) {
-        if (t == 0) k_out[0] = 1.f;
+        if (t == 0) d.k[0] = 1.f;
         return;
     }
     const unsigned __int128 rhs = (unsigned __int128)pct_mant * npos;
@@ -231,8 +242,8 @@ __global__ __launch_bounds__(256) void kselect_kernel(const unsigned* __restrict
     }
     __syncthreads();
     if (t == 0) {
-        const float hmax = __uint_as_float(hmax_bits[0]);
-        k_out[0] = (hmax * (float)(s_best + 1)) / (float)nbins;
+        const float hmax = __uint_as_float(d.hmax[0]);
+        d.k[0] = (hmax * (float)(s_best + 1)) / (float)nbins;
     }
 }
 
@@ -241,8 +252,20 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(unsigned* p, int n, unsig
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void fill_f32_kernel(float* p, int n, float v) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+// Per image: zero the histogram, hmax and the keypoint count; set k when
+// it is given rather than formed.
+__global__ __launch_bounds__(256) void reset_kernel(BatchImage d0, ImgWork w, int nbins,
+                                                      float k_fill) {
+    BatchImage d;
+    int unused;
+    resolve(d0, w, (int)blockIdx.x, d, unused);
+    if (d.hist)
+        for (int i = threadIdx.x; i < nbins; i += blockDim.x) d.hist[i] = 0u;
+    if (threadIdx.x == 0) {
+        if (d.hmax) d.hmax[0] = 0u;
+        if (d.count) d.count[0] = 0;
+        if (k_fill > 0.f && d.k) d.k[0] = k_fill;
+    }
 }
 
 // Streaming copy with 16-byte vector accesses (bandwidth reference).
@@ -265,32 +288,35 @@ int grid_for(size_t n, int block, int cap) {
     return (int)(g < (size_t)cap ? g : (size_t)cap);
 }
 
+int item_count(const ImgWork& w, int single) { return w.items ? w.count : single; }
+
 template <int R>
-hipError_t launch_gauss_r(const float* src, int ld, float* dst, int W, int H, const Taps& taps,
+hipError_t launch_gauss_r(const BatchImage& d0, const ImgWork& w, const Taps& taps,
                           hipStream_t s) {
+    const int count = item_count(w, tiles_of(d0.W, d0.H));
+    if (count <= 0) return hipSuccess;
     const size_t lds = (size_t)GaussGeom<R>::floats * sizeof(float);
-    hipLaunchKernelGGL(gauss_kernel<R>, dim3(tiles_of(W, H)), dim3(kTileThreads), lds, s, src, ld,
-                       dst, W, H, taps);
+    hipLaunchKernelGGL(gauss_kernel<R>, dim3(count), dim3(kTileThreads), lds, s, d0, w, taps);
     return hipGetLastError();
 }
 
 template <int RG>
-hipError_t launch_cond_r(const float* L, float* out, int W, int H, const Taps& taps,
-                         const float* k_dev, float k_host, int mode, unsigned* hmax_bits,
-                         hipStream_t s) {
+hipError_t launch_cond_r(const BatchImage& d0, const ImgWork& w, const Taps& taps, float k_host,
+                         int mode, hipStream_t s) {
+    const int count = item_count(w, tiles_of(d0.W, d0.H));
+    if (count <= 0) return hipSuccess;
     const size_t lds = (size_t)CondGeom<RG>::floats * sizeof(float);
-    hipLaunchKernelGGL(cond_kernel<RG>, dim3(tiles_of(W, H)), dim3(kTileThreads), lds, s, L, out,
-                       W, H, taps, k_dev, k_host, mode, hmax_bits);
+    hipLaunchKernelGGL(cond_kernel<RG>, dim3(count), dim3(kTileThreads), lds, s, d0, w, taps,
+                       k_host, mode);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_gauss(const float* src, int ld_src, float* dst, int W, int H,
-                        const Taps& taps, hipStream_t s) {
+hipError_t launch_gauss(const BatchImage& d0, const ImgWork& w, const Taps& taps, hipStream_t s) {
     switch (taps.r) {
 #define KZ_G(R) \
-    case R: return launch_gauss_r<R>(src, ld_src, dst, W, H, taps, s);
+    case R: return launch_gauss_r<R>(d0, w, taps, s);
         KZ_G(1) KZ_G(2) KZ_G(3) KZ_G(4) KZ_G(5) KZ_G(6) KZ_G(7) KZ_G(8)
         KZ_G(9) KZ_G(10) KZ_G(11) KZ_G(12) KZ_G(13) KZ_G(14) KZ_G(15) KZ_G(16)
 #undef KZ_G
@@ -298,40 +324,44 @@ hipError_t launch_gauss(const float* src, int ld_src, float* dst, int W, int H,
     }
 }
 
-hipError_t launch_cond(const float* L, float* out, int W, int H, const Taps& taps,
-                       const float* k_dev, float k_host, int mode, unsigned* hmax_bits,
-                       hipStream_t s) {
+hipError_t launch_cond(const BatchImage& d0, const ImgWork& w, const Taps& taps, float k_host,
+                       int mode, hipStream_t s) {
     switch (taps.r) {
-        case 1: return launch_cond_r<1>(L, out, W, H, taps, k_dev, k_host, mode, hmax_bits, s);
-        case 2: return launch_cond_r<2>(L, out, W, H, taps, k_dev, k_host, mode, hmax_bits, s);
-        case 3: return launch_cond_r<3>(L, out, W, H, taps, k_dev, k_host, mode, hmax_bits, s);
-        case 4: return launch_cond_r<4>(L, out, W, H, taps, k_dev, k_host, mode, hmax_bits, s);
+        case 1: return launch_cond_r<1>(d0, w, taps, k_host, mode, s);
+        case 2: return launch_cond_r<2>(d0, w, taps, k_host, mode, s);
+        case 3: return launch_cond_r<3>(d0, w, taps, k_host, mode, s);
+        case 4: return launch_cond_r<4>(d0, w, taps, k_host, mode, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_hist(const float* m2, int n, const unsigned* hmax_bits, unsigned* hist,
-                       int nbins, hipStream_t s) {
-    hipLaunchKernelGGL(hist_kernel, dim3(grid_for(n, 256 * 8, 512)), dim3(256),
-                       nbins * sizeof(unsigned), s, m2, n, hmax_bits, hist, nbins);
+hipError_t launch_hist(const BatchImage& d0, const ImgWork& w, int nbins, hipStream_t s) {
+    const int count = item_count(w, (d0.W * d0.H + kHistChunk - 1) / kHistChunk);
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(hist_kernel, dim3(count), dim3(256), nbins * sizeof(unsigned), s, d0, w,
+                       nbins);
     return hipGetLastError();
 }
 
-hipError_t launch_kselect(const unsigned* hist, int nbins, const unsigned* hmax_bits,
-                          unsigned long long pct_mant, int pct_shift, float* k_out,
-                          hipStream_t s) {
-    hipLaunchKernelGGL(kselect_kernel, dim3(1), dim3(256), 0, s, hist, nbins, hmax_bits, pct_mant,
-                       pct_shift, k_out);
+hipError_t launch_kselect(const BatchImage& d0, const ImgWork& w, int nbins,
+                          unsigned long long pct_mant, int pct_shift, hipStream_t s) {
+    const int count = item_count(w, 1);
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(kselect_kernel, dim3(count), dim3(256), 0, s, d0, w, nbins, pct_mant,
+                       pct_shift);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(const BatchImage& d0, const ImgWork& w, int nbins, float k_fill,
+                        hipStream_t s) {
+    const int count = item_count(w, 1);
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reset_kernel, dim3(count), dim3(256), 0, s, d0, w, nbins, k_fill);
     return hipGetLastError();
 }
 
 hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t s) {
     hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, p, n, v);
-    return hipGetLastError();
-}
-
-hipError_t launch_fill_f32(float* p, int n, float v, hipStream_t s) {
-    hipLaunchKernelGGL(fill_f32_kernel, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 

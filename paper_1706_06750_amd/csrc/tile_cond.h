@@ -23,22 +23,26 @@ namespace kaze {
 constexpr int kTileThreads = 256;
 constexpr int kRun = 4;  // outputs per thread and work item in the filter passes
 
-template <int RG>
+// Tile of TX x TY pixels; RG is the Gaussian radius of sigma_cond.
+template <int RG, int TX = kTile, int TY = kTile>
 struct CondGeom {
     static constexpr int r = RG;                 // Gaussian radius
     static constexpr int R = RG + 2;             // ring of L
-    static constexpr int nL = kTile + 2 * R;     // L region edge
-    static constexpr int pL = nL | 1;            // odd pitches: columns walk distinct banks
-    static constexpr int nS = kTile + 4;         // smoothed region edge (tile + 2 ring)
-    static constexpr int pS = nS | 1;            // horizontal pass: nL rows x nS cols; the
+    static constexpr int nLy = TY + 2 * R;       // L region
+    static constexpr int nLx = TX + 2 * R;
+    static constexpr int pL = nLx | 1;           // odd pitches: columns walk distinct banks
+    static constexpr int nSy = TY + 4;           // smoothed region (tile + 2 ring)
+    static constexpr int nSx = TX + 4;
+    static constexpr int pS = nSx | 1;           // horizontal pass: nLy rows x nSx cols; the
                                                  // vertical pass overwrites it in place
-    static constexpr int nG = kTile + 2;         // g region edge (tile + 1 ring)
-    static constexpr int pG = nG | 1;
-    static constexpr int offS = nL * pL;         // smoothing work area
+    static constexpr int nGy = TY + 2;           // g region (tile + 1 ring)
+    static constexpr int nGx = TX + 2;
+    static constexpr int pG = nGx | 1;
+    static constexpr int offS = nLy * pL;        // smoothing work area
     static constexpr int offG = offS;            // g overwrites the consumed smoothing area
-    static constexpr int floats = offS + nL * pS;
-    static_assert(nG * pG <= nL * pS, "g must fit in the smoothing area");
-    static_assert(nS % kRun == 0, "runs must tile the passes");
+    static constexpr int floats = offS + nLy * pS;
+    static_assert(nGy * pG <= nLy * pS, "g must fit in the smoothing area");
+    static_assert(nSx % kRun == 0 && nSy % 4 == 0, "runs must tile the passes");
 };
 
 // Rectangular region [gy0, gy0+NY) x [gx0, gx0+NX) of a W x H image into LDS
@@ -83,27 +87,25 @@ __device__ __forceinline__ void stage_region(const float* __restrict__ src, int 
 }
 
 // L on the tile + ring R (reflected) into sL.
-template <int RG>
+template <class G>
 __device__ __forceinline__ void load_L_ring(const float* __restrict__ L, int W, int H, int tx0,
                                             int ty0, float* sL) {
-    using G = CondGeom<RG>;
-    stage_region<G::nL, G::nL, G::pL, kTileThreads>(L, W, H, ty0 - G::R, tx0 - G::R, sL);
+    stage_region<G::nLy, G::nLx, G::pL, kTileThreads>(L, W, H, ty0 - G::R, tx0 - G::R, sL);
 }
 
-// Smoothed image L_s on the tile + 2 ring into sS (nS x nS, pitch pS).
-template <int RG>
+// Smoothed image L_s on the tile + 2 ring into sS (nSy x nSx, pitch pS).
+template <class G>
 __device__ __forceinline__ void smooth_tile(const float* sL, float* sS, const Taps& taps) {
-    using G = CondGeom<RG>;
-    constexpr int T = 2 * RG + 1;
+    constexpr int T = 2 * G::r + 1;
     float w[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) w[t] = taps.w[t];
     // horizontal: item = (run along x, row); lanes walk rows (odd pitch)
     {
-        constexpr int runs = G::nS / kRun, items = runs * G::nL;
+        constexpr int runs = G::nSx / kRun, items = runs * G::nLy;
 #pragma unroll 1
         for (int i = threadIdx.x; i < items; i += kTileThreads) {
-            const int row = i % G::nL, x0 = (i / G::nL) * kRun;
+            const int row = i % G::nLy, x0 = (i / G::nLy) * kRun;
             const float* src = sL + row * G::pL + x0;
             float v[kRun + T - 1];
 #pragma unroll
@@ -121,15 +123,14 @@ __device__ __forceinline__ void smooth_tile(const float* sL, float* sS, const Ta
     // vertical, in place: item = (column, quarter of the rows).  Every item
     // reads its inputs into registers before the barrier and writes after.
     {
-        constexpr int NQ = 4, QR = G::nS / NQ, items = NQ * G::nS;
+        constexpr int NQ = 4, QR = G::nSy / NQ, items = NQ * G::nSx;
         constexpr int PER = (items + kTileThreads - 1) / kTileThreads;
-        static_assert(G::nS % NQ == 0, "quarters must tile the rows");
         float v[PER][QR + T - 1];
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int i = threadIdx.x + j * kTileThreads;
             if (i < items) {
-                const int col = i % G::nS, y0 = (i / G::nS) * QR;
+                const int col = i % G::nSx, y0 = (i / G::nSx) * QR;
 #pragma unroll
                 for (int q = 0; q < QR + T - 1; ++q) v[j][q] = sS[(y0 + q) * G::pS + col];
             }
@@ -139,7 +140,7 @@ __device__ __forceinline__ void smooth_tile(const float* sL, float* sS, const Ta
         for (int j = 0; j < PER; ++j) {
             const int i = threadIdx.x + j * kTileThreads;
             if (i < items) {
-                const int col = i % G::nS, y0 = (i / G::nS) * QR;
+                const int col = i % G::nSx, y0 = (i / G::nSx) * QR;
 #pragma unroll
                 for (int q = 0; q < QR; ++q) {
                     float acc = 0.f;
@@ -154,23 +155,23 @@ __device__ __forceinline__ void smooth_tile(const float* sL, float* sS, const Ta
 
 // Squared Scharr gradient magnitudes of L_s on the g grid (tile + 1 ring),
 // computed into registers; after a barrier f(gy, gx, m2) is called once per
-// position (gy, gx in [0, kTile + 2)), so f may overwrite the sS area.
-template <int RG, class F>
+// position (gy in [0, TY + 2), gx in [0, TX + 2)), so f may overwrite the
+// sS area.
+template <class G, class F>
 __device__ __forceinline__ void scharr_pass(const float* sS, F&& f) {
-    using G = CondGeom<RG>;
-    constexpr int runs = (G::nG + kRun - 1) / kRun, items = runs * G::nG;
+    constexpr int runs = (G::nGy + kRun - 1) / kRun, items = runs * G::nGx;
     constexpr int PER = (items + kTileThreads - 1) / kTileThreads;
     float m2[PER][kRun];
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const int i = threadIdx.x + j * kTileThreads;
         if (i < items) {
-            const int gx = i % G::nG, gy0 = (i / G::nG) * kRun;
+            const int gx = i % G::nGx, gy0 = (i / G::nGx) * kRun;
             // g row gy uses sS rows gy .. gy+2 and columns gx .. gx+2
             float a[kRun + 2], b[kRun + 2], c[kRun + 2];
 #pragma unroll
             for (int q = 0; q < kRun + 2; ++q) {
-                const int sy = gy0 + q < G::nS ? gy0 + q : G::nS - 1;
+                const int sy = gy0 + q < G::nSy ? gy0 + q : G::nSy - 1;
                 const float* p = sS + sy * G::pS + gx;
                 a[q] = p[0];
                 b[q] = p[1];
@@ -195,10 +196,10 @@ __device__ __forceinline__ void scharr_pass(const float* sS, F&& f) {
     for (int j = 0; j < PER; ++j) {
         const int i = threadIdx.x + j * kTileThreads;
         if (i < items) {
-            const int gx = i % G::nG, gy0 = (i / G::nG) * kRun;
+            const int gx = i % G::nGx, gy0 = (i / G::nGx) * kRun;
 #pragma unroll
             for (int q = 0; q < kRun; ++q)
-                if (gy0 + q < G::nG) f(gy0 + q, gx, m2[j][q]);
+                if (gy0 + q < G::nGy) f(gy0 + q, gx, m2[j][q]);
         }
     }
 }

@@ -28,7 +28,8 @@ EXPORTS = (
     "kaze_workspace_bytes", "kaze_build_scale_space", "kaze_conductivity",
     "kaze_aos_step", "kaze_detector_response", "kaze_find_extrema",
     "kaze_last_error", "kaze_profile_begin", "kaze_profile_end",
-    "kaze_kernel_names", "kaze_copy_f32",
+    "kaze_kernel_names", "kaze_copy_f32", "kaze_batch_workspace_bytes",
+    "kaze_batch_create", "kaze_batch_run", "kaze_batch_destroy", "kaze_batch_autotune",
 )
 
 
@@ -57,6 +58,21 @@ class kaze_keypoint(ctypes.Structure):
                 ("response", ctypes.c_float)]
 
 
+class kaze_image_desc(ctypes.Structure):
+    _fields_ = [("img", ctypes.c_void_p), ("W", ctypes.c_int), ("H", ctypes.c_int),
+                ("ld_img", ctypes.c_int), ("levels", ctypes.c_void_p), ("det", ctypes.c_void_p),
+                ("k", ctypes.c_void_p), ("kps", ctypes.c_void_p), ("capacity", ctypes.c_int),
+                ("count", ctypes.c_void_p)]
+
+
+class kaze_batch_config(ctypes.Structure):
+    _fields_ = [("aos_shape", ctypes.c_int)]
+
+
+# Row-chunk x column-chunk tile shape of each kaze_batch_config.aos_shape.
+AOS_SHAPES = ((64, 64), (64, 32), (32, 64), (32, 32))
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
@@ -80,6 +96,11 @@ def _load():
         "kaze_profile_end": (i32, [ctypes.POINTER(i32), ctypes.POINTER(f64)]),
         "kaze_kernel_names": (ctypes.c_char_p, []),
         "kaze_copy_f32": (i32, [vp, vp, sz, vp]),
+        "kaze_batch_workspace_bytes": (sz, [vp, i32, P, vp]),
+        "kaze_batch_create": (i32, [vp, i32, P, vp, vp, sz, ctypes.POINTER(vp)]),
+        "kaze_batch_run": (i32, [vp, i32, vp]),
+        "kaze_batch_destroy": (i32, [vp]),
+        "kaze_batch_autotune": (i32, [vp, i32, P, vp, sz, i32, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -190,6 +211,45 @@ def kaze_kernel_names():
     return lib.kaze_kernel_names().decode().split(",")
 
 
+def _descs(images):
+    arr = (kaze_image_desc * len(images))(*images)
+    return arr
+
+
+def _cfg(shape):
+    return None if shape is None else ctypes.byref(kaze_batch_config(int(shape)))
+
+
+def kaze_batch_workspace_bytes(images, p, shape=None) -> int:
+    return int(lib.kaze_batch_workspace_bytes(_descs(images), len(images), ctypes.byref(p),
+                                              _cfg(shape)))
+
+
+def kaze_batch_create(images, p, shape, ws, ws_bytes):
+    h = ctypes.c_void_p()
+    _check(lib.kaze_batch_create(_descs(images), len(images), ctypes.byref(p), _cfg(shape),
+                                 _ptr(ws), ws_bytes, ctypes.byref(h)))
+    return h
+
+
+def kaze_batch_run(handle, eager=False, stream=None):
+    _check(lib.kaze_batch_run(handle, 1 if eager else 0, _stream(stream)))
+
+
+def kaze_batch_destroy(handle):
+    _check(lib.kaze_batch_destroy(handle))
+
+
+def kaze_batch_autotune(images, p, ws, ws_bytes, reps=3, stream=None):
+    """Returns (best shape index, ms per run of each of the 4 shapes)."""
+    best = kaze_batch_config(-1)
+    ms = (ctypes.c_double * 4)()
+    _check(lib.kaze_batch_autotune(_descs(images), len(images), ctypes.byref(p), _ptr(ws),
+                                   ws_bytes, reps, _stream(stream), ctypes.byref(best),
+                                   ctypes.cast(ms, ctypes.c_void_p)))
+    return best.aos_shape, [ms[i] for i in range(4)]
+
+
 # ---------------------------------------------------------------------------
 # Convenience wrapper: torch tensors in, torch tensors out.
 # ---------------------------------------------------------------------------
@@ -247,3 +307,107 @@ class Kaze:
             order = np.lexsort((out[:, 2], out[:, 1], out[:, 0]))
             out = out[order]
         return out
+
+
+class KazeBatch:
+    """Many images of different sizes through one captured graph per run.
+
+    ``sizes`` is a list of (W, H).  Per-image device buffers are allocated
+    here (torch); ``inputs[j]`` is image j's input tensor [H][W] to fill
+    before ``run()``.  ``shape`` selects the row/column tile shape (0-3);
+    ``shape="auto"`` runs the library's autotuner, caching the choice in the
+    JSON file ``tune_cache`` when given (keyed by GPU architecture and the
+    list of sizes)."""
+
+    def __init__(self, sizes, params=None, capacity=1 << 14, shape="auto", tune_cache=None,
+                 device="cuda", with_detector=True):
+        import torch
+        self.p = params if params is not None else kaze_default_params()
+        self.N = kaze_num_levels(self.p)
+        self.sizes = [(int(w), int(h)) for w, h in sizes]
+        dev = torch.device(device)
+        self.inputs, self.levels, self.det, self.k, self.kps, self.count = [], [], [], [], [], []
+        descs = []
+        for W, H in self.sizes:
+            x = torch.zeros((H, W), dtype=torch.float32, device=dev)
+            lv = torch.empty((self.N, H, W), dtype=torch.float32, device=dev)
+            dt = torch.empty_like(lv) if with_detector else None
+            k = torch.empty(1, dtype=torch.float32, device=dev)
+            kp = torch.empty((max(capacity, 1), 4), dtype=torch.int32, device=dev)
+            ct = torch.zeros(1, dtype=torch.int32, device=dev)
+            self.inputs.append(x)
+            self.levels.append(lv)
+            self.det.append(dt)
+            self.k.append(k)
+            self.kps.append(kp)
+            self.count.append(ct)
+            descs.append(kaze_image_desc(x.data_ptr(), W, H, W, lv.data_ptr(),
+                                         dt.data_ptr() if dt is not None else None, k.data_ptr(),
+                                         kp.data_ptr() if with_detector else None,
+                                         capacity if with_detector else 0,
+                                         ct.data_ptr() if with_detector else None))
+        self.descs = descs
+        self.capacity = capacity
+        self.ws_bytes = kaze_batch_workspace_bytes(descs, self.p)
+        if self.ws_bytes == 0:
+            raise KazeError(KAZE_ERR_INVALID_ARG, "batch sizes or parameters are invalid")
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.tune_ms = None
+        if shape == "auto":
+            shape = self._tuned_shape(tune_cache)
+        self.shape = int(shape)
+        self.handle = kaze_batch_create(descs, self.p, self.shape, self.ws, self.ws_bytes)
+
+    def _key(self):
+        import hashlib
+        import torch
+        arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName
+        sig = hashlib.sha1(repr(sorted(self.sizes)).encode()).hexdigest()[:16]
+        return "%s|n=%d|%s" % (arch, len(self.sizes), sig)
+
+    def _tuned_shape(self, cache_path):
+        import json
+        cache = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as fh:
+                cache = json.load(fh)
+        key = self._key()
+        if key in cache:
+            self.tune_ms = cache[key].get("ms")
+            return cache[key]["shape"]
+        best, ms = kaze_batch_autotune(self.descs, self.p, self.ws, self.ws_bytes)
+        self.tune_ms = ms
+        if cache_path:
+            cache[key] = {"shape": best, "ms": ms, "tile": AOS_SHAPES[best]}
+            tmp = cache_path + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(cache, fh, indent=1)
+            os.replace(tmp, cache_path)
+        return best
+
+    def run(self, eager=False, stream=None):
+        kaze_batch_run(self.handle, eager, stream)
+
+    def keypoints(self, j):
+        """Image j's keypoints as in Kaze.keypoints(); synchronises."""
+        import numpy as np
+        import torch
+        n = min(int(self.count[j].item()), self.capacity)
+        if n == 0:
+            return np.zeros((0, 4))
+        raw = self.kps[j][:n].cpu()
+        xyl = raw[:, :3].numpy().astype(np.int64)
+        resp = raw[:, 3].contiguous().view(dtype=torch.float32).numpy()
+        out = np.stack([xyl[:, 2], xyl[:, 1], xyl[:, 0], resp.astype(np.float64)], axis=1)
+        return out[np.lexsort((out[:, 2], out[:, 1], out[:, 0]))]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            kaze_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

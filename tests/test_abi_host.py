@@ -76,6 +76,31 @@ def test_struct_layout_matches_c_compiler(K, tmp_path):
                                   "k_bins", "k_percentile", "k_override", "det_threshold")]
     want.append(ctypes.sizeof(K.kaze_keypoint))
     assert got == want
+    prog2 = tmp_path / "layout2.c"
+    prog2.write_text(textwrap.dedent("""
+        #include <stdio.h>
+        #include <stddef.h>
+        #include "kaze.h"
+        int main(void) {
+          printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(kaze_image_desc),
+                 offsetof(kaze_image_desc, img), offsetof(kaze_image_desc, W),
+                 offsetof(kaze_image_desc, H), offsetof(kaze_image_desc, ld_img),
+                 offsetof(kaze_image_desc, levels), offsetof(kaze_image_desc, det),
+                 offsetof(kaze_image_desc, k), offsetof(kaze_image_desc, kps),
+                 offsetof(kaze_image_desc, capacity), offsetof(kaze_image_desc, count),
+                 sizeof(kaze_batch_config));
+          return 0;
+        }"""))
+    exe2 = tmp_path / "layout2"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog2),
+                    "-o", str(exe2)], check=True)
+    got2 = [int(v) for v in subprocess.run([str(exe2)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    D = K.kaze_image_desc
+    want2 = [ctypes.sizeof(D)] + [getattr(D, f).offset for f in
+                                  ("img", "W", "H", "ld_img", "levels", "det", "k", "kps",
+                                   "capacity", "count")] + [ctypes.sizeof(K.kaze_batch_config)]
+    assert got2 == want2
 
 
 def test_defaults_and_schedule_match_oracle(K):
@@ -157,3 +182,40 @@ def test_kernel_names(K):
     names = K.kaze_kernel_names()
     for n in ("aos_reduce", "aos_iface", "aos_recover", "cond", "det", "nms"):
         assert n in names
+
+
+def test_batch_workspace_query(K):
+    p = K.kaze_default_params()
+    D = K.kaze_image_desc
+    small = [D(256, 100, 80, 100, 512, 1024, 2048, 4096, 10, 8192),
+             D(256, 300, 200, 300, 512, 1024, 2048, 4096, 10, 8192)]
+    sizes = [K.kaze_batch_workspace_bytes(small, p, s) for s in range(4)]
+    assert all(v > 0 and v % 256 == 0 for v in sizes)
+    assert K.kaze_batch_workspace_bytes(small, p) == max(sizes)
+    # 3000 rows fit 64-row column chunks (<= 64 chunks) but not 32-row ones
+    tall = [D(256, 100, 3000, 100, 512, 1024, 2048, 4096, 10, 8192)]
+    assert K.kaze_batch_workspace_bytes(tall, p, 1) == 0
+    assert K.kaze_batch_workspace_bytes(tall, p, 0) > 0
+    assert K.kaze_batch_workspace_bytes([D(256, 7, 80, 7, 512, 0, 2048, 0, 0, 0)], p) == 0
+
+
+@no_gpu_only
+def test_batch_create_rejects_before_any_device_call(K):
+    p = K.kaze_default_params()
+    D = K.kaze_image_desc
+    good = D(256, 100, 80, 100, 512, 1024, 2048, 4096, 10, 8192)
+    ws = K.kaze_batch_workspace_bytes([good], p, 0)
+    cases = [
+        [D(0, 100, 80, 100, 512, 1024, 2048, 4096, 10, 8192)],        # no input
+        [D(256, 100, 80, 90, 512, 1024, 2048, 4096, 10, 8192)],       # ld < W
+        [good, D(256, 100, 80, 100, 512, 0, 2048, 4096, 10, 8192)],   # det for some only
+        [D(256, 100, 80, 100, 512, 1024, 2048, 0, 10, 8192)],         # capacity without kps
+        [D(258, 100, 80, 100, 512, 1024, 2048, 4096, 10, 8192)],      # misaligned input
+    ]
+    for c in cases:
+        with pytest.raises(K.KazeError):
+            K.kaze_batch_create(c, p, 0, 1 << 20, ws)
+    with pytest.raises(K.KazeError):
+        K.kaze_batch_create([good], p, 0, 1 << 20, ws - 1)            # workspace too small
+    with pytest.raises(K.KazeError):
+        K.kaze_batch_create([good], p, 7, 1 << 20, ws)                # no such shape

@@ -1,0 +1,117 @@
+"""Batched form through the C ABI: many images of uneven sizes, one launch per
+phase, replayed from a captured hipGraph, with the tile shape of the line
+solves chosen by the autotuner."""
+import numpy as np
+import pytest
+
+import oracle as O
+from synthetic import batch_sizes, kaze_image
+from kaze_parity import LEVEL_TOL, compare_keypoints, note
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# ragged sizes covering partial tiles of every shape, one image too narrow
+# for a full 64-wide tile and one taller than wide
+SIZES = [(67, 45), (320, 240), (200, 130), (130, 260), (64, 64), (9, 13)]
+
+
+def single(K, img):
+    H, W = img.shape
+    kz = K.Kaze(W, H)
+    kz.run(torch.from_numpy(img).cuda())
+    torch.cuda.synchronize()
+    return kz
+
+
+def make_batch(K, sizes, seeds, shape, **kw):
+    kb = K.KazeBatch(sizes, shape=shape, **kw)
+    imgs = [kaze_image(W, H, s) for (W, H), s in zip(sizes, seeds)]
+    for x, im in zip(kb.inputs, imgs):
+        x.copy_(torch.from_numpy(im))
+    return kb, imgs
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2, 3])
+def test_batch_matches_single_image_path(gpu_lib, shape):
+    K = gpu_lib
+    note(f"[batch] shape {K.AOS_SHAPES[shape]} sizes {SIZES}")
+    kb, imgs = make_batch(K, SIZES, range(40, 40 + len(SIZES)), shape)
+    kb.run()
+    torch.cuda.synchronize()
+    for j, im in enumerate(imgs):
+        ref = single(K, im)
+        assert float(kb.k[j].item()) == float(ref.k.item())
+        dl = (kb.levels[j] - ref.levels).abs().max().item()
+        dd = (kb.det[j] - ref.det).abs().max().item()
+        note(f"  image {j} {SIZES[j]}: max|dL| {dl:.2e} max|ddet| {dd:.2e}")
+        if shape == 0:
+            # same tile shape as the single-image path: identical arithmetic
+            assert dl == 0.0 and dd == 0.0
+            assert np.array_equal(kb.keypoints(j), ref.keypoints())
+        else:
+            # a different partition of the lines changes only the FP32 rounding
+            assert dl < 2e-6
+            assert dd < 1e-8
+    kb.close()
+
+
+def test_batch_graph_replays_match_eager(gpu_lib):
+    K = gpu_lib
+    note("[batch] graph replays vs eager, shape 3")
+    kb, _ = make_batch(K, SIZES, range(60, 60 + len(SIZES)), 3)
+    kb.run(eager=True)
+    torch.cuda.synchronize()
+    ref_lv = [t.clone() for t in kb.levels]
+    ref_det = [t.clone() for t in kb.det]
+    ref_cnt = [int(c.item()) for c in kb.count]
+    for r in range(3):
+        for t in kb.levels:
+            t.fill_(-1.0)
+        kb.run()
+        torch.cuda.synchronize()
+        for j in range(len(SIZES)):
+            assert torch.equal(kb.levels[j], ref_lv[j]), (r, j)
+            assert torch.equal(kb.det[j], ref_det[j]), (r, j)
+            assert int(kb.count[j].item()) == ref_cnt[j], (r, j)
+    kb.close()
+
+
+def test_autotuner_and_cache(gpu_lib, tmp_path):
+    K = gpu_lib
+    cache = str(tmp_path / "tune.json")
+    note("[batch] autotune")
+    kb = K.KazeBatch(SIZES, shape="auto", tune_cache=cache)
+    assert kb.shape in (0, 1, 2, 3)
+    assert kb.tune_ms is not None and min(m for m in kb.tune_ms if m > 0) > 0
+    note(f"  ms per shape {kb.tune_ms} -> {K.AOS_SHAPES[kb.shape]}")
+    kb.close()
+    kb2 = K.KazeBatch(SIZES, shape="auto", tune_cache=cache)
+    assert kb2.shape == kb.shape
+    kb2.close()
+
+
+def test_uneven_batch_images_vs_oracle(gpu_lib):
+    """Two images of the 64-image uneven workload, inside a batch of four,
+    against the FP64 oracle."""
+    K = gpu_lib
+    sizes = batch_sizes(64, 3, 640, 1920, 480, 1200)[:4]
+    seeds = [3000 + j for j in range(4)]
+    note(f"[batch] uneven workload images {sizes}")
+    kb, imgs = make_batch(K, sizes, seeds, "auto")
+    kb.run()
+    torch.cuda.synchronize()
+    for j in (0, 3):
+        lev_o, k_o = O.build_scale_space(imgs[j].astype(np.float64))
+        det_o = O.detector_response(lev_o)
+        lev_g = kb.levels[j].cpu().numpy()
+        err = max(float(np.max(np.abs(lev_g[i] - lev_o[i]))) for i in range(kb.N))
+        kp_o = O.find_extrema(det_o, 0.001)
+        common, bad_g, bad_o = compare_keypoints(kb.keypoints(j), kp_o, det_o, 0.001)
+        note(f"  image {j} {sizes[j]}: k {kb.k[j].item():.6g}/{k_o:.6g} worst level err "
+             f"{err:.2e} keypoints {common}/{len(kp_o)}")
+        assert float(kb.k[j].item()) == pytest.approx(k_o, rel=1e-4)
+        assert err <= LEVEL_TOL
+        assert not bad_g and not bad_o
+    kb.close()
