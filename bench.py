@@ -163,15 +163,31 @@ def record(args, value, ms_per_step, config, roofline, extra):
     return rec
 
 
+def timed_graph_runs(args, K, torch, kb):
+    """Timed region: graph replays of the plan; an event pair brackets the
+    AOS-step segment of every run on the stream it runs on.  Returns
+    (seconds, microseconds per level)."""
+    K.kaze_profile_begin("aos_reduce")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        kb.run()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    runs, ms = K.kaze_profile_end()
+    assert runs == args.steps
+    return elapsed, 1e3 * ms / (runs * (kb.N - 1))
+
+
 def bench_single(args, K, torch, kaze_image, case):
     W, H, seed = case
     img = torch.from_numpy(kaze_image(W, H, seed)).cuda()
+
+    # per-kernel breakdown and eager throughput of the single-image calls
     kz = K.Kaze(W, H)
     for _ in range(args.warmup):
         kz.run(img)
     torch.cuda.synchronize()
-
-    # per-kernel breakdown (untimed pass)
     breakdown = {}
     probe_steps = max(5, min(20, args.steps))
     for name in K.kaze_kernel_names():
@@ -184,41 +200,34 @@ def bench_single(args, K, torch, kaze_image, case):
         if n:
             breakdown[name] = {"launches_per_step": n / probe_steps,
                                "ms_per_step": ms / probe_steps, "us_per_launch": 1e3 * ms / n}
-
-    # timed region; the level kernels carry HIP events on the same stream
-    K.kaze_profile_begin(",".join(AOS_KERNELS))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    t1 = time.perf_counter()
     for _ in range(args.steps):
         kz.run(img)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    n_aos, ms_aos = K.kaze_profile_end()
-    level_us = 1e3 * ms_aos / ((kz.N - 1) * args.steps)
-    roof = level_roofline(level_us, W * H, traffic_from_profile(W, H))
-    roof["launches_timed"] = n_aos
+    eager_value = args.steps / (time.perf_counter() - t1)
 
-    # the same work replayed from a captured graph (one image per graph)
-    kb = K.KazeBatch([(W, H)], shape=0)
+    # timed path: the image's plan replayed from its captured graphs
+    kb = K.KazeBatch([(W, H)], shape="auto")
     kb.inputs[0].copy_(img)
     for _ in range(args.warmup):
         kb.run()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        kb.run()
-    torch.cuda.synchronize()
-    graph_value = args.steps / (time.perf_counter() - t1)
+    elapsed, level_us = timed_graph_runs(args, K, torch, kb)
+    roof = level_roofline(level_us, W * H,
+                          traffic_from_profile(W, H) if kb.shape == 0 else None)
+    roof["timed_in"] = "the timed region (event pair around each run's AOS segment)"
+    kps = int(kb.count[0].item())
+    shape = K.AOS_SHAPES[kb.shape]
     kb.close()
 
-    extra = {"graph_replay_images_per_s": round(graph_value, 3),
+    extra = {"eager_images_per_s": round(eager_value, 3),
              "kernel_breakdown": {k: {kk: round(vv, 4) for kk, vv in v.items()}
                                   for k, v in breakdown.items()}}
     if not args.no_cpu_baseline:
         extra["cpu_baseline"] = cpu_baseline(W, H, seed)
     config = {"workload": args.workload, "image": "%dx%d" % (W, H), "seed": seed,
-              "levels": kz.N, "path": "plain AOS (no surrogate)",
-              "keypoints": int(kz.count.item())}
+              "levels": kz.N, "path": "plain AOS (no surrogate), graph replay",
+              "aos_tile": "%dx%d" % shape, "keypoints": kps}
     return record(args, args.steps / elapsed, 1e3 * elapsed / args.steps, config, roof, extra)
 
 
@@ -231,28 +240,9 @@ def bench_batch(args, K, torch, kaze_image, cases):
     for _ in range(args.warmup):
         kb.run()
     torch.cuda.synchronize()
-
-    # timed region: graph replays, one per batch
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        kb.run()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-
-    # the same launches issued eagerly with HIP events on the level kernels
-    eager_steps = max(2, min(args.steps, 10))
-    K.kaze_profile_begin(",".join(AOS_KERNELS))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(eager_steps):
-        kb.run(eager=True)
-    torch.cuda.synchronize()
-    eager_elapsed = time.perf_counter() - t1
-    n_aos, ms_aos = K.kaze_profile_end()
-    level_us = 1e3 * ms_aos / ((kb.N - 1) * eager_steps)
+    elapsed, level_us = timed_graph_runs(args, K, torch, kb)
     roof = level_roofline(level_us, px, None)
-    roof["launches_timed"] = n_aos
-    roof["timed_in"] = "eager pass of the same launches (%d batches)" % eager_steps
+    roof["timed_in"] = "the timed region (event pair around each run's AOS segment)"
 
     n = len(sizes)
     config = {"workload": args.workload, "images": n, "pixels": px,
@@ -263,8 +253,7 @@ def bench_batch(args, K, torch, kaze_image, cases):
               "levels": kb.N, "path": "plain AOS, batched, graph replay",
               "aos_tile": "%dx%d" % K.AOS_SHAPES[kb.shape],
               "autotune_ms_per_shape": kb.tune_ms}
-    extra = {"eager_images_per_s": round(n * eager_steps / eager_elapsed, 3),
-             "megapixels_per_s": round(px * args.steps / elapsed / 1e6, 1)}
+    extra = {"megapixels_per_s": round(px * args.steps / elapsed / 1e6, 1)}
     kb.close()
     return record(args, n * args.steps / elapsed, 1e3 * elapsed / args.steps, config, roof, extra)
 

@@ -220,9 +220,12 @@ kaze_status kaze_batch_create(const kaze_image_desc* images, int n,
                               const kaze_batch_config* cfg, void* ws,
                               size_t ws_bytes, kaze_batch** out);
 
-/* Enqueues one run of the plan on stream: a single graph launch, or with
- * eager != 0 the same launches issued one by one (for per-kernel timing).
- * Runs that share a plan must be ordered on one stream. */
+/* Enqueues one run of the plan on stream: three graph launches (base image
+ * and contrast factor; the AOS steps; detector response and extrema), or
+ * with eager != 0 the same kernel launches issued one by one.  Runs that
+ * share a plan must be ordered on one stream.  Under kaze_profile_begin
+ * with aos_reduce listed, a graph run records one event pair around its
+ * AOS-step segment. */
 kaze_status kaze_batch_run(kaze_batch* b, int eager, void* stream);
 
 kaze_status kaze_batch_destroy(kaze_batch* b);

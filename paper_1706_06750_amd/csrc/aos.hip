@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void aos_reduce_kernel(ImageDesc d0, AosWor
     // double the register demand (spills) without saving launches
     ImageDesc d;
     int lt;
-    resolve(d0, w, t, d, lt);
+    resolve(d0, w, xcd_contiguous(t, (int)gridDim.x), d, lt);
     const int W = d.W, H = d.H;
     const int cx = lt % d.ncx, cy = lt / d.ncx;
     const int tx0 = cx * TX, ty0 = cy * TY;
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(kRecoverThreads) void aos_recover_kernel(ImageDesc 
     const int tid = threadIdx.x;
     ImageDesc d;
     int lt;
-    resolve(d0, w, (int)blockIdx.x, d, lt);
+    resolve(d0, w, xcd_contiguous((int)blockIdx.x, (int)gridDim.x), d, lt);
     const int W = d.W, H = d.H;
     const int cx = lt % d.ncx, cy = lt / d.ncx;
     const int tx0 = cx * TX, ty0 = cy * TY;

@@ -292,8 +292,11 @@ struct kaze_batch {
     int2 *d_items = nullptr, *d_tiles = nullptr, *d_aos = nullptr, *d_lines = nullptr,
          *d_hist = nullptr, *d_det = nullptr, *d_nms = nullptr;
     int n_tiles = 0, n_aos = 0, n_lines = 0, n_hist = 0, n_det = 0, n_nms = 0;
-    hipGraphExec_t exec = nullptr;
+    // captured segments: 0 base image + k, 1 the N-1 AOS steps, 2 det + extrema
+    hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
 };
+
+extern "C" kaze_status kaze_batch_destroy(kaze_batch* b);
 
 namespace {
 
@@ -366,25 +369,32 @@ kaze_status check_batch(const kaze_image_desc* im, int n, const kaze_params* p, 
     return KAZE_OK;
 }
 
-// The whole a1-a7 sequence of a batch, one launch per phase for all images.
-kaze_status enqueue_batch(const kaze_batch& B, hipStream_t s) {
+// The a1-a7 sequence of a batch, one launch per phase for all images, in
+// three segments: 0 base image and contrast factor, 1 the AOS steps, 2
+// detector response and extrema.
+kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s) {
     const kaze_params* p = &B.p;
     const BatchImage b0 = batch_image(0, 0);
-    const ImgWork images{B.d_imgs, B.d_items, B.n};
-    const ImgWork tiles{B.d_imgs, B.d_tiles, B.n_tiles};
-    const ImgWork hist{B.d_imgs, B.d_hist, B.n_hist};
-    kaze_status st = base_and_k(b0, images, tiles, hist, p, s);
-    if (st != KAZE_OK) return st;
-    const Taps tc = gauss_taps(p->sigma_cond);
-    const int gmode = p->diffusivity == KAZE_G2 ? 0 : 1;
-    ImageDesc a0;
-    memset(&a0, 0, sizeof(a0));
-    for (int i = 1; i < B.N; ++i) {
-        const ImageDesc* lvl = B.d_lvl + (size_t)(i - 1) * B.n;
-        const AosWork at{lvl, B.d_aos, B.n_aos};
-        const AosWork al{lvl, B.d_lines, B.n_lines};
-        st = aos_step(a0, at, al, B.shape, tc, (float)B.lv[i].tau, true, gmode, 1.f, s);
-        if (st != KAZE_OK) return st;
+    if (seg == 0) {
+        const ImgWork images{B.d_imgs, B.d_items, B.n};
+        const ImgWork tiles{B.d_imgs, B.d_tiles, B.n_tiles};
+        const ImgWork hist{B.d_imgs, B.d_hist, B.n_hist};
+        return base_and_k(b0, images, tiles, hist, p, s);
+    }
+    if (seg == 1) {
+        const Taps tc = gauss_taps(p->sigma_cond);
+        const int gmode = p->diffusivity == KAZE_G2 ? 0 : 1;
+        ImageDesc a0;
+        memset(&a0, 0, sizeof(a0));
+        for (int i = 1; i < B.N; ++i) {
+            const ImageDesc* lvl = B.d_lvl + (size_t)(i - 1) * B.n;
+            const AosWork at{lvl, B.d_aos, B.n_aos};
+            const AosWork al{lvl, B.d_lines, B.n_lines};
+            const kaze_status st =
+                aos_step(a0, at, al, B.shape, tc, (float)B.lv[i].tau, true, gmode, 1.f, s);
+            if (st != KAZE_OK) return st;
+        }
+        return KAZE_OK;
     }
     if (B.with_det) {
         const ImgWork det{B.d_imgs, B.d_det, B.n_det};
@@ -393,6 +403,14 @@ kaze_status enqueue_batch(const kaze_batch& B, hipStream_t s) {
     if (B.with_nms) {
         const ImgWork nms{B.d_imgs, B.d_nms, B.n_nms};
         KZ_LAUNCH(K_NMS, s, launch_nms(b0, nms, B.N, (float)p->det_threshold, s));
+    }
+    return KAZE_OK;
+}
+
+kaze_status enqueue_batch(const kaze_batch& B, hipStream_t s) {
+    for (int seg = 0; seg < 3; ++seg) {
+        const kaze_status st = enqueue_segment(B, seg, s);
+        if (st != KAZE_OK) return st;
     }
     return KAZE_OK;
 }
@@ -477,29 +495,42 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
         for (int t = 0; t < nms_blocks_of(d.W, d.H); ++t) hn[inm++] = make_int2(j, t);
     }
     hipStream_t cs = nullptr;
-    hipGraph_t graph = nullptr;
     hipError_t e = hipMemcpy(base, host.data(), L.tables_end, hipMemcpyHostToDevice);
-    // capture the whole sequence once on a private stream (default priority)
+    // capture each segment once on a private stream (default priority)
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (e == hipSuccess) {
+    for (int seg = 0; seg < 3 && e == hipSuccess && st == KAZE_OK; ++seg) {
+        hipGraph_t graph = nullptr;
         g_prof.capturing = true;
         e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            st = enqueue_batch(*B, cs);
+            st = enqueue_segment(*B, seg, cs);
             const hipError_t e2 = hipStreamEndCapture(cs, &graph);
             if (st == KAZE_OK && e2 != hipSuccess) e = e2;
         }
         g_prof.capturing = false;
+        if (e == hipSuccess && st == KAZE_OK)
+            e = hipGraphInstantiate(&B->exec[seg], graph, nullptr, nullptr, 0);
+        if (graph) hipGraphDestroy(graph);
     }
-    if (e == hipSuccess && st == KAZE_OK) e = hipGraphInstantiate(&B->exec, graph, nullptr, nullptr, 0);
-    if (graph) hipGraphDestroy(graph);
     if (cs) hipStreamDestroy(cs);
     if (st != KAZE_OK || e != hipSuccess) {
-        delete B;
+        kaze_batch_destroy(B);
         return st != KAZE_OK ? st : fail(KAZE_ERR_HIP, "batch graph setup failed: %s",
                                          hipGetErrorString(e));
     }
     *out = B;
+    return KAZE_OK;
+}
+
+kaze_status run_graphs(const kaze_batch& B, hipStream_t s) {
+    KZ_HIP(hipGraphLaunch(B.exec[0], s));
+    {
+        // the level segment holds every AOS launch of the run; with
+        // aos_reduce in the profiling list one event pair brackets it
+        ProfScope ps(K_AOS_REDUCE, s);
+        KZ_HIP(hipGraphLaunch(B.exec[1], s));
+    }
+    KZ_HIP(hipGraphLaunch(B.exec[2], s));
     return KAZE_OK;
 }
 
@@ -705,13 +736,13 @@ kaze_status kaze_batch_run(kaze_batch* b, int eager, void* stream) {
     if (!b) return fail(KAZE_ERR_INVALID_ARG, "batch is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (eager) return enqueue_batch(*b, s);
-    KZ_HIP(hipGraphLaunch(b->exec, s));
-    return KAZE_OK;
+    return run_graphs(*b, s);
 }
 
 kaze_status kaze_batch_destroy(kaze_batch* b) {
     if (!b) return KAZE_OK;
-    if (b->exec) hipGraphExecDestroy(b->exec);
+    for (hipGraphExec_t& x : b->exec)
+        if (x) hipGraphExecDestroy(x);
     delete b;
     return KAZE_OK;
 }
@@ -740,9 +771,10 @@ kaze_status kaze_batch_autotune(const kaze_image_desc* images, int n, const kaze
             result = st;
             break;
         }
-        hipError_t e = hipGraphLaunch(b->exec, s);  // warm-up
+        hipError_t e = run_graphs(*b, s) == KAZE_OK ? hipSuccess : hipErrorUnknown;  // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, s);
-        for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(b->exec, s);
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+            e = run_graphs(*b, s) == KAZE_OK ? hipSuccess : hipErrorUnknown;
         if (e == hipSuccess) e = hipEventRecord(e1, s);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.f;

@@ -171,6 +171,18 @@ struct Work {
     int count;
 };
 
+constexpr int kXcds = 8;  // accelerator complex dies; workgroups are dealt round-robin
+
+// Launch-order index t of a one-block-per-item grid of n blocks -> work item,
+// such that XCD x (which receives blocks x, x+8, x+16, ...) works through
+// one contiguous run of the list: neighbouring tiles, whose rings overlap,
+// then share that XCD's L2.
+__device__ __forceinline__ int xcd_contiguous(int t, int n) {
+    const int x = t % kXcds, j = t / kXcds;
+    const int per = n / kXcds, rem = n % kXcds;
+    return x * per + (x < rem ? x : rem) + j;
+}
+
 template <class D>
 __device__ __forceinline__ void resolve(const D& d0, const Work<D>& w, int t, D& d, int& local) {
     if (w.items) {

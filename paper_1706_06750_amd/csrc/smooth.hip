@@ -31,7 +31,7 @@ __global__ __launch_bounds__(kTileThreads) void gauss_kernel(BatchImage d0, ImgW
     float* sH = smem + G::offH;
     BatchImage d;
     int lt;
-    resolve(d0, work, (int)blockIdx.x, d, lt);
+    resolve(d0, work, xcd_contiguous((int)blockIdx.x, (int)gridDim.x), d, lt);
     const float* __restrict__ src = d.img;
     float* __restrict__ dst = d.levels;
     const int W = d.W, H = d.H, ld = d.ld;
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kTileThreads) void cond_kernel(BatchImage d0, ImgWo
     float* sS = smem + G::offS;
     BatchImage d;
     int lt;
-    resolve(d0, w, (int)blockIdx.x, d, lt);
+    resolve(d0, w, xcd_contiguous((int)blockIdx.x, (int)gridDim.x), d, lt);
     const int W = d.W, H = d.H;
     float* __restrict__ out = d.g;
     const int ncx = (W + kTile - 1) / kTile;
