@@ -30,7 +30,7 @@ import math
 
 import numpy as np
 
-__all__ = ["shape_counts", "kaze_image", "batch_sizes", "WORKLOADS"]
+__all__ = ["shape_counts", "kaze_image", "batch_sizes", "surrogate_params", "WORKLOADS"]
 
 # (width, height, n_blobs, n_shapes) of the two reference workloads; other
 # sizes scale the counts with the pixel count (never below the small case).
@@ -126,3 +126,20 @@ WORKLOADS = {
     "kaze_4k32_720p32": lambda: ([(3840, 2160, 5000 + j) for j in range(32)]
                                  + [(1280, 720, 5100 + j) for j in range(32)]),
 }
+
+
+def surrogate_params(seed: int, channels=(3, 32, 32, 32, 32, 32, 1),
+                     last_scale: float = 0.1) -> np.ndarray:
+    """Seeded initial parameters of a stack of 3x3 convolutions, flat float32:
+    per layer the weights [co][ci][3][3] (He-normal, std sqrt(2 / (9 ci)))
+    then the biases [co] (zero).  The last layer's weights are scaled by
+    ``last_scale``."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    nl = len(channels) - 1
+    for li, (ci, co) in enumerate(zip(channels[:-1], channels[1:])):
+        W = rng.normal(0.0, math.sqrt(2.0 / (9 * ci)), size=(co, ci, 3, 3))
+        if li == nl - 1:
+            W *= last_scale
+        parts += [W.ravel(), np.zeros(co)]
+    return np.concatenate(parts).astype(np.float32)
