@@ -161,6 +161,7 @@ __global__ __launch_bounds__(kBlock) void aos_reduce_kernel(ImageDesc d0, AosWor
     ImageDesc d;
     int lt;
     resolve(d0, w, xcd_contiguous(t, (int)gridDim.x), d, lt);
+    if (d.gate && *d.gate <= d.bound) return;  // whole block
     const int W = d.W, H = d.H;
     const int cx = lt % d.ncx, cy = lt / d.ncx;
     const int tx0 = cx * TX, ty0 = cy * TY;
@@ -211,6 +212,7 @@ __global__ __launch_bounds__(kBlock) void aos_iface_kernel(ImageDesc d0, AosWork
         ImageDesc d;
         int line;
         resolve(d0, w, t, d, line);
+        if (d.gate && *d.gate <= d.bound) continue;  // whole wavefront
         const float* R;
         float* Z;
         int nch;
@@ -250,6 +252,7 @@ __global__ __launch_bounds__(kRecoverThreads) void aos_recover_kernel(ImageDesc 
     ImageDesc d;
     int lt;
     resolve(d0, w, xcd_contiguous((int)blockIdx.x, (int)gridDim.x), d, lt);
+    if (d.gate && *d.gate <= d.bound) return;  // whole block
     const int W = d.W, H = d.H;
     const int cx = lt % d.ncx, cy = lt / d.ncx;
     const int tx0 = cx * TX, ty0 = cy * TY;
@@ -305,6 +308,89 @@ __global__ __launch_bounds__(kRecoverThreads) void aos_recover_kernel(ImageDesc 
             if (y < H) d.Lnext[(size_t)y * W + x] = sL[k * P + c] + 0.5f * (sD[k * P + c] + xc[k]);
         }
     }
+}
+
+// Global-memory accessor of one whole line for the probe solves: element
+// k of the chunk at pos0, index clamped into the line (positions outside it
+// get zero coupling weights in the chunk routines).
+struct GlobalLineAcc {
+    const float* gp;  // line element 0
+    const float* Lp;
+    int stride, pos0, n;
+    __device__ __forceinline__ int at(int k) const {
+        const int i = pos0 + k;
+        return (i < 0 ? 0 : (i >= n ? n - 1 : i)) * stride;
+    }
+    __device__ __forceinline__ float g(int k) const { return gp[at(k)]; }
+    __device__ __forceinline__ float L(int k) const { return Lp[at(k)]; }
+};
+
+constexpr int kProbeChunk = 64;  // unknowns per lane: lines of up to 64 x 64
+
+// One wavefront per line through a probe window: lines 0..kProbeMax-1 are
+// rows y0 + j, lines kProbeMax.. are columns x0 + j.
+__global__ __launch_bounds__(kBlock) void aos_probe_kernel(ImageDesc d, const int4* rects,
+                                                           int nprobes, float tau, float* delta) {
+    const int lane = threadIdx.x % kWave;
+    const int wv = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const int probe = wv / (2 * kProbeMax), j = wv % (2 * kProbeMax);
+    if (probe >= nprobes) return;
+    const int4 r = rects[probe];  // x0, y0, w, h
+    const bool row = j < kProbeMax;
+    const int off = row ? j : j - kProbeMax;
+    if (off >= (row ? r.w : r.z)) return;  // whole wavefront
+    const int W = d.W, H = d.H;
+    const int n = row ? W : H;
+    const int line = row ? r.y + off : r.x + off;
+    const int win0 = row ? r.x : r.y, win1 = win0 + (row ? r.z : r.w);
+    const size_t base = row ? (size_t)line * W : (size_t)line;
+    const int stride = row ? 1 : W;
+    const int pos0 = lane * kProbeChunk;
+    const GlobalLineAcc A{d.g + base, d.L + base, stride, pos0, n};
+    Eq e0 = eq_identity(), e1 = eq_identity();
+    if (pos0 < n) chunk_reduce<kProbeChunk>(A, pos0, n, tau, e0, e1);
+    float z0, z1;
+    wave_pcr_pairs(e0, e1, lane, z0, z1);
+    if (pos0 < n && pos0 < win1 && pos0 + kProbeChunk > win0) {
+        float x[kProbeChunk];
+        chunk_recover<kProbeChunk>(A, pos0, n, tau, z0, z1, x);
+        float* out = delta + (size_t)probe * 2 * kProbeMax * kProbeMax;
+#pragma unroll
+        for (int k = 0; k < kProbeChunk; ++k) {
+            const int pos = pos0 + k;
+            if (pos >= win0 && pos < win1) {
+                if (row)
+                    out[off * kProbeMax + (pos - win0)] = x[k];
+                else
+                    out[kProbeMax * kProbeMax + (pos - win0) * kProbeMax + off] = x[k];
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void probe_err_kernel(const float* L, const float* cand, int W,
+                                                           const int4* rects, const float* delta,
+                                                           unsigned* err) {
+    __shared__ float red[kBlock];
+    const int4 r = rects[blockIdx.x];
+    const float* dl = delta + (size_t)blockIdx.x * 2 * kProbeMax * kProbeMax;
+    float m = 0.f;
+    for (int i = threadIdx.x; i < r.z * r.w; i += kBlock) {
+        const int py = i / r.z, px = i - py * r.z;
+        const size_t o = (size_t)(r.y + py) * W + (r.x + px);
+        const float exact =
+            L[o] + 0.5f * (dl[py * kProbeMax + px] + dl[kProbeMax * kProbeMax + py * kProbeMax + px]);
+        float e = fabsf(cand[o] - exact);
+        if (!(e <= 3.402823466e38f)) e = __builtin_inff();  // NaN or inf
+        m = e > m ? e : m;
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w2 = kBlock / 2; w2 > 0; w2 >>= 1) {
+        if ((int)threadIdx.x < w2) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w2]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(err, __float_as_uint(red[0]));
 }
 
 int work_count(const ImageDesc& d0, const AosWork& w, int tx, int ty, bool lines) {
@@ -379,6 +465,23 @@ hipError_t launch_aos_recover(const ImageDesc& d0, const AosWork& w, int shape, 
         case 3: return launch_recover_s<32, 32>(d0, w, tau, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_aos_probe(const ImageDesc& d, const int4* rects, int nprobes, float tau,
+                            float* delta, hipStream_t s) {
+    if (nprobes <= 0) return hipSuccess;
+    const int waves = nprobes * 2 * kProbeMax, per = kBlock / kWave;
+    hipLaunchKernelGGL(aos_probe_kernel, dim3((waves + per - 1) / per), dim3(kBlock), 0, s, d, rects,
+                       nprobes, tau, delta);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_err(const float* L, const float* cand, int W, const int4* rects,
+                            int nprobes, const float* delta, unsigned* err, hipStream_t s) {
+    if (nprobes <= 0) return hipSuccess;
+    hipLaunchKernelGGL(probe_err_kernel, dim3(nprobes), dim3(kBlock), 0, s, L, cand, W, rects, delta,
+                       err);
+    return hipGetLastError();
 }
 
 }  // namespace kaze

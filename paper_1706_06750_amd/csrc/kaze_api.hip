@@ -12,25 +12,36 @@
 
 #include "kaze.h"
 #include "kaze_internal.h"
+#include "kaze_surrogate.h"
+#include "sg_internal.h"
+
+namespace {
+thread_local char g_err[512] = "";
+}  // namespace
+
+namespace kaze {
+kaze_status set_error(kaze_status st, const char* fmt, va_list ap) {
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    return st;
+}
+}  // namespace kaze
 
 namespace {
 
 using namespace kaze;
 
-thread_local char g_err[512] = "";
-
 kaze_status fail(kaze_status st, const char* fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    set_error(st, fmt, ap);
     va_end(ap);
     return st;
 }
 
 // ---------------------------------------------------------------- profiling
 const char* const kKernelNames[K_COUNT] = {
-    "gauss", "grad",        "hist",        "kselect", "cond", "aos_reduce",
-    "aos_iface", "aos_recover", "det", "nms",     "fill", "copy"};
+    "gauss", "grad", "hist", "kselect", "cond", "aos_reduce", "aos_iface", "aos_recover",
+    "det",   "nms",  "fill", "copy",    "sg_conv", "sg_probe"};
 
 struct Profiler {
     unsigned mask = 0;  // bit i: record launches of kernel i
@@ -229,6 +240,8 @@ ImageDesc aos_desc(int W, int H, int shape, char* base, const Scratch& w, const 
     d.k = k;
     d.W = W;
     d.H = H;
+    d.gate = nullptr;
+    d.bound = 0.f;
     d.ncx = (W + kAosShapeTX[shape] - 1) / kAosShapeTX[shape];
     d.ncy = (H + kAosShapeTY[shape] - 1) / kAosShapeTY[shape];
     return d;
@@ -510,9 +523,9 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
         g_prof.capturing = false;
         if (e == hipSuccess && st == KAZE_OK)
             e = hipGraphInstantiate(&B->exec[seg], graph, nullptr, nullptr, 0);
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
     }
-    if (cs) hipStreamDestroy(cs);
+    if (cs) (void)hipStreamDestroy(cs);
     if (st != KAZE_OK || e != hipSuccess) {
         kaze_batch_destroy(B);
         return st != KAZE_OK ? st : fail(KAZE_ERR_HIP, "batch graph setup failed: %s",
@@ -531,6 +544,186 @@ kaze_status run_graphs(const kaze_batch& B, hipStream_t s) {
         KZ_HIP(hipGraphLaunch(B.exec[1], s));
     }
     KZ_HIP(hipGraphLaunch(B.exec[2], s));
+    return KAZE_OK;
+}
+
+// ============================================================================
+// Surrogate scale space: every AOS step may be replaced by the learned
+// surrogate, accepted per level by the probe check and otherwise recomputed
+// exactly.
+// ============================================================================
+struct SgLayout {
+    size_t scratch, x0, xa, xb, delta, tau, rects, items, total;
+    int max_items;
+};
+
+// Conv items (chunk * strips + strip) whose output rows/columns meet a probe
+// window grown by the receptive-field radius: outside that region stale
+// activations can reach at most kProbeHalo - 1 pixels inward.
+void sg_probe_items(const sg::Geo& g, const int4* rects, int n, std::vector<int>& out) {
+    std::vector<char> mark((size_t)g.strips * g.chunks, 0);
+    for (int p = 0; p < n; ++p) {
+        const int4 r = rects[p];
+        const int xa = std::max(0, r.x - sg::kProbeHalo), xb = std::min(g.W - 1, r.x + r.z - 1 + sg::kProbeHalo);
+        const int ya = std::max(0, r.y - sg::kProbeHalo), yb = std::min(g.H - 1, r.y + r.w - 1 + sg::kProbeHalo);
+        for (int c = ya / g.R; c <= yb / g.R; ++c)
+            for (int st = xa / sg::kStrip; st <= xb / sg::kStrip; ++st) mark[(size_t)c * g.strips + st] = 1;
+    }
+    out.clear();
+    for (size_t i = 0; i < mark.size(); ++i)
+        if (mark[i]) out.push_back((int)i);
+}
+
+int sg_max_items(const kaze_sg_config* c) {
+    // a window of probe_size + 2 halo pixels spans at most this many strips x chunks
+    const int span = c->probe_size + 2 * sg::kProbeHalo;
+    const int per = (span / sg::kStrip + 2) * (span / sg::kConvRows + 2);
+    return std::max(1, c->probes * per);
+}
+
+SgLayout sg_layout(int W, int H, const kaze_params* p, const kaze_sg_config* c, int shape) {
+    SgLayout L;
+    const int N = p->octaves * p->sublevels;
+    const sg::Geo g = sg::make_geo(1, W, H, sg::kConvRows);
+    const size_t nhwc = (size_t)g.sx;
+    size_t off = 0;
+    L.scratch = off;
+    off = align256(off + scratch_layout(W, H, hist_bins(p), shape, 0).total);
+    L.x0 = off;    off = align256(off + nhwc * 8 * sizeof(sg::bf16));
+    L.xa = off;    off = align256(off + nhwc * 32 * sizeof(sg::bf16));
+    L.xb = off;    off = align256(off + nhwc * 32 * sizeof(sg::bf16));
+    L.delta = off; off = align256(off + (size_t)std::max(1, c->probes) * 2 * kProbeMax * kProbeMax * sizeof(float));
+    L.tau = off;   off = align256(off + (size_t)N * sizeof(float));
+    L.rects = off; off = align256(off + (size_t)N * std::max(1, c->probes) * sizeof(int4));
+    L.max_items = sg_max_items(c);
+    L.items = off; off = align256(off + (size_t)N * L.max_items * sizeof(int));
+    L.total = off;
+    return L;
+}
+
+kaze_status check_sg_config(const kaze_sg_config* c) {
+    if (!c) return fail(KAZE_ERR_INVALID_ARG, "surrogate config is NULL");
+    if (c->probes < 0 || c->probes > 16) return fail(KAZE_ERR_INVALID_ARG, "probes must be in [0, 16]");
+    if (c->probe_size < 8 || c->probe_size > kProbeMax)
+        return fail(KAZE_ERR_INVALID_ARG, "probe_size must be in [8, %d]", kProbeMax);
+    if (isnan(c->bound)) return fail(KAZE_ERR_INVALID_ARG, "bound is NaN");
+    if (c->aos_shape < -1 || c->aos_shape >= kAosShapes)
+        return fail(KAZE_ERR_INVALID_ARG, "bad AOS tile shape");
+    return KAZE_OK;
+}
+
+}  // namespace
+
+struct kaze_sg_scale_space {
+    int W = 0, H = 0, N = 0, shape = 0, probes = 0;
+    float bound = 0.f;
+    bool with_det = false, with_nms = false;
+    kaze_params p;
+    std::vector<Level> lv;
+    BatchImage b;
+    ImageDesc aos;  // scratch pointers of the AOS step; L, Lnext, gate set per level
+    const unsigned char* packed = nullptr;
+    sg::Geo geo;
+    sg::bf16 *x0 = nullptr, *xa = nullptr, *xb = nullptr;
+    float *delta = nullptr, *err = nullptr, *tau = nullptr;
+    int4* rects = nullptr;
+    int* items = nullptr;
+    std::vector<int> item_off, item_cnt;
+    hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+// The six convolutions of one surrogate step L_i = L_{i-1} + f, over every
+// strip of the image or over an item list; gated on *gate <= bound if gate.
+kaze_status sg_chain(const kaze_sg_scale_space& S, int i, const float* Lp, float* Li,
+                     const int* items, int nitems, const float* gate, hipStream_t s) {
+    const sg::PackLayout P = sg::pack_layout();
+    sg::bf16* buf[sg::kLayers] = {S.x0, S.xa, S.xb, S.xa, S.xb, S.xa};
+    for (int l = 0; l < sg::kLayers; ++l) {
+        sg::ConvArgs a;
+        memset(&a, 0, sizeof(a));
+        a.in = buf[l];
+        a.wfrag = reinterpret_cast<const sg::bf16x8*>(S.packed + P.fwd[l]);
+        a.bias = reinterpret_cast<const float*>(S.packed + P.bias[l]);
+        a.items = items;
+        a.nitems = nitems;
+        a.gate = gate;
+        a.bound = S.bound;
+        if (l == 0) {
+            a.tauw = reinterpret_cast<const float*>(S.packed + P.tauw);
+            a.tausum = reinterpret_cast<const float*>(S.packed + P.tausum);
+            a.tau = S.tau + i;
+        }
+        if (l < sg::kLayers - 1) {
+            a.out = buf[l + 1];
+            KZ_LAUNCH(K_SG_CONV, s, sg::launch_conv(l == 0 ? 8 : 32, 2, sg::EPI_RELU, l == 0, a, S.geo, s));
+        } else {
+            a.fout = Li;
+            a.base = Lp;
+            KZ_LAUNCH(K_SG_CONV, s, sg::launch_conv(32, 1, sg::EPI_OUT, false, a, S.geo, s));
+        }
+    }
+    return KAZE_OK;
+}
+
+kaze_status sg_segment(const kaze_sg_scale_space& S, int seg, hipStream_t s) {
+    const kaze_params* p = &S.p;
+    const ImgWork none{nullptr, nullptr, 0};
+    if (seg == 0) return base_and_k(S.b, none, none, none, p, s);
+    if (seg == 2) {
+        if (S.with_det) KZ_LAUNCH(K_DET, s, launch_det(S.b, none, S.N, det_levels(S.lv), s));
+        if (S.with_nms)
+            KZ_LAUNCH(K_NMS, s, launch_nms(S.b, none, S.N, (float)p->det_threshold, s));
+        return KAZE_OK;
+    }
+    const Taps tc = gauss_taps(p->sigma_cond);
+    const int gmode = p->diffusivity == KAZE_G2 ? 0 : 1;
+    const size_t plane = (size_t)S.W * S.H;
+    const AosWork anone{nullptr, nullptr, 0};
+    KZ_LAUNCH(K_FILL, s, launch_fill_u32(reinterpret_cast<unsigned*>(S.err), S.N, 0u, s));
+    for (int i = 1; i < S.N; ++i) {
+        const float* Lp = S.b.levels + plane * (i - 1);
+        float* Li = S.b.levels + plane * i;
+        const float tau = (float)S.lv[i].tau;
+        // conductivity of L_{i-1}: input of the surrogate and of the probe
+        BatchImage bc = S.b;
+        bc.levels = const_cast<float*>(Lp);
+        KZ_LAUNCH(K_COND, s, launch_cond(bc, none, tc, 1.f, gmode, s));
+        KZ_LAUNCH(K_SG_CONV, s, sg::launch_pack_input(Lp, S.b.g, S.tau + i, S.x0, nullptr, S.geo, s));
+        ImageDesc d = S.aos;
+        d.L = Lp;
+        d.Lnext = Li;
+        if (S.probes > 0) {
+            kaze_status st = sg_chain(S, i, Lp, Li, S.items + S.item_off[i], S.item_cnt[i], nullptr, s);
+            if (st != KAZE_OK) return st;
+            const int4* r = S.rects + (size_t)i * S.probes;
+            KZ_LAUNCH(K_SG_PROBE, s, launch_aos_probe(d, r, S.probes, tau, S.delta, s));
+            KZ_LAUNCH(K_SG_PROBE, s, launch_probe_err(Lp, Li, S.W, r, S.probes, S.delta,
+                                                      reinterpret_cast<unsigned*>(S.err + i), s));
+        }
+        kaze_status st = sg_chain(S, i, Lp, Li, nullptr, 0, S.err + i, s);
+        if (st != KAZE_OK) return st;
+        d.gate = S.err + i;
+        d.bound = S.bound;
+        st = aos_step(d, anone, anone, S.shape, tc, tau, true, gmode, 1.f, s);
+        if (st != KAZE_OK) return st;
+    }
+    return KAZE_OK;
+}
+
+kaze_status sg_run(const kaze_sg_scale_space& S, bool eager, hipStream_t s) {
+    for (int seg = 0; seg < 3; ++seg) {
+        // with aos_reduce in the profiling list one event pair brackets the
+        // level segment (all steps of the run)
+        ProfScope ps(seg == 1 ? K_AOS_REDUCE : K_COUNT, s);
+        if (eager) {
+            const kaze_status st = sg_segment(S, seg, s);
+            if (st != KAZE_OK) return st;
+        } else {
+            KZ_HIP(hipGraphLaunch(S.exec[seg], s));
+        }
+    }
     return KAZE_OK;
 }
 
@@ -742,7 +935,7 @@ kaze_status kaze_batch_run(kaze_batch* b, int eager, void* stream) {
 kaze_status kaze_batch_destroy(kaze_batch* b) {
     if (!b) return KAZE_OK;
     for (hipGraphExec_t& x : b->exec)
-        if (x) hipGraphExecDestroy(x);
+        if (x) (void)hipGraphExecDestroy(x);
     delete b;
     return KAZE_OK;
 }
@@ -791,12 +984,186 @@ kaze_status kaze_batch_autotune(const kaze_image_desc* images, int n, const kaze
             best_shape = sh;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (result != KAZE_OK) return result;
     if (best_shape < 0) return fail(KAZE_ERR_UNSUPPORTED, "no AOS tile shape fits the batch");
     best->aos_shape = best_shape;
     return KAZE_OK;
+}
+
+// ------------------------------------------------------ surrogate scale space
+kaze_status kaze_sg_default_config(kaze_sg_config* c) {
+    if (!c) return fail(KAZE_ERR_INVALID_ARG, "config pointer is NULL");
+    c->bound = 2.5e-4;
+    c->probes = 4;
+    c->probe_size = 32;
+    c->aos_shape = -1;
+    return KAZE_OK;
+}
+
+size_t kaze_sg_scale_space_workspace_bytes(int W, int H, const kaze_params* p,
+                                           const kaze_sg_config* c) {
+    if (check_params(p) != KAZE_OK || check_sg_config(c) != KAZE_OK ||
+        check_size(W, H) != KAZE_OK)
+        return 0;
+    const int shape = c->aos_shape >= 0 ? c->aos_shape : 0;
+    if (!shape_fits(W, H, shape)) return 0;
+    return sg_layout(W, H, p, c, shape).total;
+}
+
+kaze_status kaze_sg_scale_space_destroy(kaze_sg_scale_space* S) {
+    if (!S) return KAZE_OK;
+    for (hipGraphExec_t& x : S->exec)
+        if (x) (void)hipGraphExecDestroy(x);
+    delete S;
+    return KAZE_OK;
+}
+
+kaze_status kaze_sg_scale_space_create(const kaze_image_desc* im, const kaze_params* p,
+                                       const kaze_sg_config* c, const void* packed,
+                                       const int* probe_xy, float* err, void* ws,
+                                       size_t ws_bytes, kaze_sg_scale_space** out) {
+    if (!out) return fail(KAZE_ERR_INVALID_ARG, "out pointer is NULL");
+    *out = nullptr;
+    kaze_status st = check_params(p);
+    if (st != KAZE_OK) return st;
+    if ((st = check_steps(p)) != KAZE_OK) return st;
+    if ((st = check_sg_config(c)) != KAZE_OK) return st;
+    if (!im) return fail(KAZE_ERR_INVALID_ARG, "image descriptor is NULL");
+    const int W = im->W, H = im->H;
+    if ((st = check_size(W, H)) != KAZE_OK) return st;
+    const int shape = c->aos_shape >= 0 ? c->aos_shape : 0;
+    if (!shape_fits(W, H, shape))
+        return fail(KAZE_ERR_UNSUPPORTED, "image does not fit AOS tile shape %d", shape);
+    if (!im->img || !im->levels || !im->k)
+        return fail(KAZE_ERR_INVALID_ARG, "img, levels and k must be non-NULL");
+    if (im->ld_img < W) return fail(KAZE_ERR_INVALID_ARG, "ld_img < W");
+    if (im->count && !im->det) return fail(KAZE_ERR_INVALID_ARG, "extrema need det");
+    if (im->capacity < 0 || (im->capacity > 0 && !im->kps))
+        return fail(KAZE_ERR_INVALID_ARG, "bad keypoint buffer");
+    if (!packed || !aligned(packed, 256))
+        return fail(KAZE_ERR_INVALID_ARG, "packed weights must be non-NULL and 256-byte aligned");
+    if (!err || !aligned(err, 4)) return fail(KAZE_ERR_INVALID_ARG, "err must be non-NULL");
+    if (!aligned(im->img, 4) || !aligned(im->levels, 4) || !aligned(im->k, 4))
+        return fail(KAZE_ERR_INVALID_ARG, "float buffers must be 4-byte aligned");
+    const int N = p->octaves * p->sublevels;
+    if (c->probes > 0) {
+        if (!probe_xy) return fail(KAZE_ERR_INVALID_ARG, "probe_xy is NULL with probes > 0");
+        for (int i = 1; i < N; ++i)
+            for (int q = 0; q < c->probes; ++q) {
+                const int x0 = probe_xy[((size_t)i * c->probes + q) * 2];
+                const int y0 = probe_xy[((size_t)i * c->probes + q) * 2 + 1];
+                if (x0 < 0 || x0 >= W || y0 < 0 || y0 >= H)
+                    return fail(KAZE_ERR_INVALID_ARG, "probe (%d, %d) of level %d outside the image",
+                                x0, y0, i);
+            }
+    }
+    const SgLayout L = sg_layout(W, H, p, c, shape);
+    if (!ws || !aligned(ws, 256) || ws_bytes < L.total)
+        return fail(KAZE_ERR_WORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
+                    L.total, ws_bytes);
+
+    char* base = static_cast<char*>(ws);
+    kaze_sg_scale_space* S = new kaze_sg_scale_space();
+    S->W = W;
+    S->H = H;
+    S->N = N;
+    S->shape = shape;
+    S->probes = c->probes;
+    S->bound = (float)c->bound;
+    S->p = *p;
+    schedule(p, S->lv);
+    S->with_det = im->det != nullptr;
+    S->with_nms = im->count != nullptr;
+    const Scratch sc = scratch_layout(W, H, hist_bins(p), shape, L.scratch);
+    BatchImage b = batch_image(W, H);
+    b.img = im->img;
+    b.ld = im->ld_img;
+    b.levels = im->levels;
+    b.det = im->det;
+    b.g = reinterpret_cast<float*>(base + sc.g);
+    b.hist = reinterpret_cast<unsigned*>(base + sc.hist);
+    b.hmax = reinterpret_cast<unsigned*>(base + sc.hmax);
+    b.k = im->k;
+    b.kps = im->kps;
+    b.capacity = im->capacity;
+    b.count = im->count;
+    S->b = b;
+    S->aos = aos_desc(W, H, shape, base, sc, im->k);
+    S->packed = static_cast<const unsigned char*>(packed);
+    S->geo = sg::make_geo(1, W, H, sg::kConvRows);
+    S->x0 = reinterpret_cast<sg::bf16*>(base + L.x0);
+    S->xa = reinterpret_cast<sg::bf16*>(base + L.xa);
+    S->xb = reinterpret_cast<sg::bf16*>(base + L.xb);
+    S->delta = reinterpret_cast<float*>(base + L.delta);
+    S->tau = reinterpret_cast<float*>(base + L.tau);
+    S->rects = reinterpret_cast<int4*>(base + L.rects);
+    S->items = reinterpret_cast<int*>(base + L.items);
+    S->err = err;
+
+    // host tables: tau per level, probe windows and conv items per level
+    const int P = std::max(1, c->probes);
+    std::vector<float> htau(N, 0.f);
+    std::vector<int4> hrect((size_t)N * P, make_int4(0, 0, 0, 0));
+    std::vector<int> hitems((size_t)N * L.max_items, 0);
+    S->item_off.assign(N, 0);
+    S->item_cnt.assign(N, 0);
+    std::vector<int> tmp;
+    for (int i = 1; i < N; ++i) {
+        htau[i] = (float)S->lv[i].tau;
+        for (int q = 0; q < c->probes; ++q) {
+            const int x0 = probe_xy[((size_t)i * c->probes + q) * 2];
+            const int y0 = probe_xy[((size_t)i * c->probes + q) * 2 + 1];
+            hrect[(size_t)i * P + q] =
+                make_int4(x0, y0, std::min(c->probe_size, W - x0), std::min(c->probe_size, H - y0));
+        }
+        sg_probe_items(S->geo, hrect.data() + (size_t)i * P, c->probes, tmp);
+        if ((int)tmp.size() > L.max_items) {
+            kaze_sg_scale_space_destroy(S);
+            return fail(KAZE_ERR_UNSUPPORTED, "probe windows need %zu items (max %d)", tmp.size(),
+                        L.max_items);
+        }
+        S->item_off[i] = i * L.max_items;
+        S->item_cnt[i] = (int)tmp.size();
+        std::copy(tmp.begin(), tmp.end(), hitems.begin() + (size_t)i * L.max_items);
+    }
+    hipError_t e = hipMemset(base + L.x0, 0, L.delta - L.x0);  // zero rings of the activations
+    if (e == hipSuccess) e = hipMemcpy(S->tau, htau.data(), N * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(S->rects, hrect.data(), hrect.size() * sizeof(int4), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(S->items, hitems.data(), hitems.size() * sizeof(int), hipMemcpyHostToDevice);
+
+    hipStream_t cs = nullptr;
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    for (int seg = 0; seg < 3 && e == hipSuccess && st == KAZE_OK; ++seg) {
+        hipGraph_t graph = nullptr;
+        g_prof.capturing = true;
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            st = sg_segment(*S, seg, cs);
+            const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+            if (st == KAZE_OK && e2 != hipSuccess) e = e2;
+        }
+        g_prof.capturing = false;
+        if (e == hipSuccess && st == KAZE_OK)
+            e = hipGraphInstantiate(&S->exec[seg], graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+    if (cs) (void)hipStreamDestroy(cs);
+    if (st != KAZE_OK || e != hipSuccess) {
+        kaze_sg_scale_space_destroy(S);
+        return st != KAZE_OK ? st : fail(KAZE_ERR_HIP, "surrogate scale-space setup failed: %s",
+                                         hipGetErrorString(e));
+    }
+    *out = S;
+    return KAZE_OK;
+}
+
+kaze_status kaze_sg_scale_space_run(kaze_sg_scale_space* S, int eager, void* stream) {
+    if (!S) return fail(KAZE_ERR_INVALID_ARG, "surrogate scale space is NULL");
+    return sg_run(*S, eager != 0, static_cast<hipStream_t>(stream));
 }
 
 // ---------------------------------------------------------------- utility

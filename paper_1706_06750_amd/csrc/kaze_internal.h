@@ -158,6 +158,10 @@ struct ImageDesc {
     float* zcol;      // ... of every column chunk, [W][ncy][2]
     const float* k;   // contrast factor (device scalar); NULL: use the host value
     int W, H, ncx, ncy;
+    // optional gate: the step is skipped when *gate <= bound (the level was
+    // accepted from the surrogate); NULL: always run
+    const float* gate;
+    float bound;
 };
 
 // Work list of a batched launch: entry t names an image (index into descs)
@@ -217,6 +221,8 @@ enum KernelId {
     K_NMS,
     K_FILL,
     K_COPY,
+    K_SG_CONV,
+    K_SG_PROBE,
     K_COUNT
 };
 
@@ -249,6 +255,18 @@ hipError_t launch_aos_reduce(const ImageDesc& d0, const AosWork& w, int shape, c
 hipError_t launch_aos_iface(const ImageDesc& d0, const AosWork& w, hipStream_t s);
 hipError_t launch_aos_recover(const ImageDesc& d0, const AosWork& w, int shape, float tau,
                               hipStream_t s);
+
+// Exact AOS increments on small probe windows: rects[p] = (x0, y0, w, h),
+// w, h <= kProbeMax.  Every row and column through a window is solved whole
+// (one wavefront per line, chunks of 64 per lane); delta[p] receives the row
+// increments [h][w] then the column increments [h][w] (pitch kProbeMax).
+// probe_err then compares L + (delta_x + delta_y)/2 with cand on every
+// window and raises *err (float bits, atomic max; NaN counts as +inf).
+constexpr int kProbeMax = 32;
+hipError_t launch_aos_probe(const ImageDesc& d, const int4* rects, int nprobes, float tau,
+                            float* delta, hipStream_t s);
+hipError_t launch_probe_err(const float* L, const float* cand, int W, const int4* rects,
+                            int nprobes, const float* delta, unsigned* err, hipStream_t s);
 
 // a6: det of every level (items: image, det tile of 64 x 32).
 hipError_t launch_det(const BatchImage& d0, const ImgWork& w, int N, const DetLevels& dl,

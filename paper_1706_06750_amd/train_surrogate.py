@@ -1,0 +1,166 @@
+"""Train the AOS-step surrogate on the GPU.
+
+Training pairs come from the plain method on the fly: for every synthetic
+image the library builds the scale space, and each step i -> i+1 gives one
+pair (L_{i-1}, g(L_{i-1}), tau_i) -> L_i.  The forward pass, the backward
+pass and Adam run in libkaze's MFMA kernels; this module only schedules
+them and moves tensors.
+
+    python -m paper_1706_06750_amd.train_surrogate [--images 2000] [--size 512]
+        [--epochs 3] [--batch 16] [--lr 1e-3] [--out weights/surrogate_512.npz]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+
+PKG_DIR = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG_DIR)
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from synthetic import kaze_image, surrogate_params  # noqa: E402
+
+DEFAULT_OUT = os.path.join(PKG_DIR, "weights", "surrogate_512.npz")
+
+
+def _gen(args):
+    W, seed = args
+    return kaze_image(W, W, seed)
+
+
+def make_images(n, size, seed0, workers):
+    """n seeded size x size images (seeds seed0 + j) as one float32 array."""
+    jobs = [(size, seed0 + j) for j in range(n)]
+    if workers <= 1:
+        return np.stack([_gen(j) for j in jobs])
+    with ProcessPoolExecutor(workers) as ex:
+        return np.stack(list(ex.map(_gen, jobs, chunksize=8)))
+
+
+class PairSource:
+    """Level pairs of a chunk of images from the plain GPU path."""
+
+    def __init__(self, K, size, chunk):
+        import torch
+        self.K, self.size, self.chunk = K, size, chunk
+        self.kb = K.KazeBatch([(size, size)] * chunk, shape=0, with_detector=False)
+        self.N = self.kb.N
+        sched = K.kaze_schedule(self.kb.p)
+        self.tau = torch.tensor([s["tau"] for s in sched], dtype=torch.float32, device="cuda")
+        n = chunk * (self.N - 1)
+        self.L = torch.empty((n, size, size), device="cuda")
+        self.g = torch.empty_like(self.L)
+        self.Ln = torch.empty_like(self.L)
+        self.t = torch.empty(n, device="cuda")
+
+    def fill(self, images):
+        """images: [chunk][size][size] device tensor -> pairs in L, g, Ln, t."""
+        K, s = self.K, self.size
+        for j in range(self.chunk):
+            self.kb.inputs[j].copy_(images[j])
+        self.kb.run()
+        r = 0
+        for j in range(self.chunk):
+            lev = self.kb.levels[j]
+            k = float(self.kb.k[j].item())
+            for i in range(1, self.N):
+                self.L[r].copy_(lev[i - 1])
+                self.Ln[r].copy_(lev[i])
+                K.kaze_conductivity(lev[i - 1], s, s, self.kb.p, k, self.g[r])
+                self.t[r] = self.tau[i]
+                r += 1
+        return r
+
+
+def train(images=2000, size=512, epochs=3, batch=16, lr=1e-3, lr_min=1e-5, chunk=16, seed=0,
+          image_seed=400000, workers=None, log_every=100, out=DEFAULT_OUT, verbose=True):
+    import torch
+    from . import kaze as K
+    from . import surrogate as S
+
+    workers = workers or min(16, os.cpu_count() or 1)
+    t0 = time.time()
+    host = make_images(images, size, image_seed, workers)
+    imgs = torch.from_numpy(host).cuda()
+    del host
+    t_gen = time.time() - t0
+    src = PairSource(K, size, chunk)
+    w = S.Weights(surrogate_params(seed))
+    plan = S.Plan(batch, size, size, training=True)
+    rng = np.random.default_rng(seed + 1)
+    pairs_per_chunk = chunk * (src.N - 1)
+    steps_per_chunk = pairs_per_chunk // batch
+    n_chunks = images // chunk
+    total = epochs * n_chunks * steps_per_chunk
+    history = []
+    step = 0
+    torch.cuda.synchronize()
+    t1 = time.time()
+    for ep in range(epochs):
+        order = rng.permutation(n_chunks)
+        for c in order:
+            src.fill(imgs[c * chunk:(c + 1) * chunk])
+            perm = torch.from_numpy(rng.permutation(pairs_per_chunk)).cuda()
+            for b in range(steps_per_chunk):
+                idx = perm[b * batch:(b + 1) * batch]
+                L = src.L.index_select(0, idx)
+                g = src.g.index_select(0, idx)
+                Ln = src.Ln.index_select(0, idx)
+                tau = src.t.index_select(0, idx)
+                loss = plan.gradients(w, L, g, tau, Ln)
+                cur = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * step / max(1, total)))
+                w.adam(lr=cur)
+                step += 1
+                if step % log_every == 0 or step == total:
+                    lv = float(loss.item())
+                    history.append((step, lv))
+                    if verbose:
+                        print("step %d/%d epoch %d loss %.4e lr %.2e %.1fs" %
+                              (step, total, ep, lv, cur, time.time() - t1), flush=True)
+    torch.cuda.synchronize()
+    t_train = time.time() - t1
+    params = w.params.cpu().numpy()
+    meta = {"images": images, "size": size, "epochs": epochs, "batch": batch, "lr": lr,
+            "lr_min": lr_min, "chunk": chunk, "init_seed": seed, "image_seed": image_seed,
+            "steps": step, "pairs_per_epoch": n_chunks * pairs_per_chunk,
+            "image_generation_s": round(t_gen, 2), "train_s": round(t_train, 2),
+            "loss_history": history}
+    if out:
+        os.makedirs(os.path.dirname(out), exist_ok=True)
+        np.savez(out, params=params, meta=json.dumps(meta))
+    return params, meta
+
+
+def load(path=DEFAULT_OUT):
+    """(params float32, meta dict) of a saved surrogate."""
+    d = np.load(path, allow_pickle=False)
+    return d["params"].astype(np.float32), json.loads(str(d["meta"]))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--images", type=int, default=2000)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--epochs", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--chunk", type=int, default=16)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--workers", type=int, default=None)
+    ap.add_argument("--out", default=DEFAULT_OUT)
+    a = ap.parse_args()
+    _, meta = train(a.images, a.size, a.epochs, a.batch, a.lr, chunk=a.chunk, seed=a.seed,
+                    workers=a.workers, out=a.out)
+    print(json.dumps({k: v for k, v in meta.items() if k != "loss_history"}))
+
+
+if __name__ == "__main__":
+    main()

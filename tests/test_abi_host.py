@@ -14,6 +14,7 @@ import oracle as O
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "kaze.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("kaze.h", "kaze_surrogate.h")]
 
 
 def _gpu_visible():
@@ -36,15 +37,18 @@ def K():
 
 
 def declared_functions():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*[\w\s\*]+?\b(kaze_\w+)\s*\(", src, flags=re.M)))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"^\s*[\w\s\*]+?\b(kaze_\w+)\s*\(", src, flags=re.M))
+    return sorted(names)
 
 
 def test_every_declared_symbol_is_exported(K):
+    from paper_1706_06750_amd import surrogate as S
     names = declared_functions()
-    assert len(names) >= 14
-    assert sorted(K.EXPORTS) == names
+    assert len(names) >= 23
+    assert sorted(K.EXPORTS + S.EXPORTS) == names
     lib = ctypes.CDLL(K.LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n
@@ -219,3 +223,42 @@ def test_batch_create_rejects_before_any_device_call(K):
         K.kaze_batch_create([good], p, 0, 1 << 20, ws - 1)            # workspace too small
     with pytest.raises(K.KazeError):
         K.kaze_batch_create([good], p, 7, 1 << 20, ws)                # no such shape
+
+
+def test_surrogate_sizes_and_rejections(K):
+    from oracle import cnn_oracle as C
+    from paper_1706_06750_amd import surrogate as S
+    assert S.kaze_sg_param_count() == C.param_count() == 38177
+    assert S.kaze_sg_packed_bytes() % 256 == 0 and S.kaze_sg_packed_bytes() > 38177 * 2
+    assert S.kaze_sg_workspace_bytes(0, 64, 64, 0) == 0
+    assert S.kaze_sg_workspace_bytes(1, 8193, 64, 0) == 0
+    assert S.kaze_sg_workspace_bytes(1, 64, 64, 2) == 0
+    inf = S.kaze_sg_workspace_bytes(2, 100, 37, 0)
+    tr = S.kaze_sg_workspace_bytes(2, 100, 37, 1)
+    # inference holds the input planes and two activation buffers
+    assert inf >= 2 * 102 * 39 * (8 + 2 * 32) * 2 and tr > 4 * inf
+    with pytest.raises(K.KazeError) as e:
+        S.kaze_sg_plan_create(1, 64, 64, 0, None, 1 << 20, stream=0)
+    assert e.value.status == K.KAZE_ERR_WORKSPACE
+    with pytest.raises(K.KazeError):
+        S.kaze_sg_plan_create(1, 0, 64, 0, None, 1 << 20, stream=0)
+    with pytest.raises(K.KazeError):
+        S.kaze_sg_adam(None, None, None, None, 10, 1, stream=0)
+    with pytest.raises(K.KazeError):
+        S.kaze_sg_pack(None, None, stream=0)
+
+
+@no_gpu_only
+def test_surrogate_rejects_before_launch(K):
+    from paper_1706_06750_amd import surrogate as S
+    fake = 1 << 40
+    with pytest.raises(K.KazeError) as e:   # too small
+        S.kaze_sg_plan_create(1, 64, 64, 1, fake, 1024, stream=0)
+    assert e.value.status == K.KAZE_ERR_WORKSPACE
+    with pytest.raises(K.KazeError) as e:   # misaligned
+        S.kaze_sg_plan_create(1, 64, 64, 0, fake + 8, 1 << 30, stream=0)
+    assert e.value.status == K.KAZE_ERR_WORKSPACE
+    with pytest.raises(K.KazeError):        # misaligned packed weights
+        S.kaze_sg_pack(fake, fake + 4, stream=0)
+    with pytest.raises(K.KazeError):        # bad Adam hyper-parameters
+        S.kaze_sg_adam(fake, fake, fake, fake, 10, 1, lr=-1.0, stream=0)

@@ -1,0 +1,165 @@
+"""Surrogate scale space through the C ABI: forced fallback equals the plain
+path, forced acceptance equals the FP64 oracle's surrogate chain, the probe
+error matches the oracle, mixed decisions are consistent, and graph replays
+equal eager runs."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import cnn_oracle as C
+from synthetic import kaze_image, surrogate_params
+from kaze_parity import note
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def S(gpu_lib):
+    from paper_1706_06750_amd import surrogate
+    return surrogate
+
+
+def make(S, K, W, H, seed, th, **cfg):
+    w = S.Weights(th)
+    c = S.kaze_sg_default_config(**cfg)
+    ss = S.SurrogateScaleSpace(W, H, w, config=c, probe_seed=seed)
+    ss.img.copy_(torch.from_numpy(kaze_image(W, H, seed)))
+    return ss, w
+
+
+@pytest.mark.parametrize("W,H,shape", [(96, 80, 0), (131, 67, 3)])
+def test_forced_fallback_equals_plain_path(S, gpu_lib, W, H, shape):
+    K = gpu_lib
+    note("[sgss] forced fallback %dx%d shape %d" % (W, H, shape))
+    ss, _ = make(S, K, W, H, 11, surrogate_params(1), bound=-1.0, aos_shape=shape)
+    ss.run()
+    torch.cuda.synchronize()
+    assert not any(ss.accepted())
+    kb = K.KazeBatch([(W, H)], shape=shape)
+    kb.inputs[0].copy_(ss.img)
+    kb.run()
+    torch.cuda.synchronize()
+    assert torch.equal(ss.k, kb.k[0])
+    assert torch.equal(ss.levels, kb.levels[0])
+    assert torch.equal(ss.det, kb.det[0])
+    assert np.array_equal(ss.keypoints(), kb.keypoints(0))
+    err = ss.err.cpu().numpy()
+    note("  probe errors %s" % " ".join("%.1e" % v for v in err[1:]))
+    assert err[0] == 0 and np.all(err[1:] > 0) and np.all(np.isfinite(err))
+    ss.close()
+    kb.close()
+
+
+def test_forced_acceptance_equals_oracle_chain(S, gpu_lib):
+    """Every level from the surrogate: the chain of 15 steps against the
+    quantized FP64 chain.  Differences are the BF16 rounding flips of each
+    step (see the forward tests); an untrained network is not contractive,
+    so later steps amplify them (about 1.3x per step here).  Each level's
+    inputs are checked bitwise by test_mixed_decisions_are_consistent."""
+    K = gpu_lib
+    W, H = 72, 56
+    th = surrogate_params(2, last_scale=0.1)
+    note("[sgss] forced acceptance %dx%d" % (W, H))
+    ss, _ = make(S, K, W, H, 12, th, bound=float("inf"), probes=0)
+    ss.run()
+    torch.cuda.synchronize()
+    assert all(ss.accepted()[1:])
+    img = kaze_image(W, H, 12).astype(np.float64)
+    lev_o, k_o = C.surrogate_scale_space(img, th.astype(np.float64), [True] * 16, quantized=True)
+    lev_g = ss.levels.cpu().numpy()
+    assert float(ss.k.item()) == pytest.approx(k_o, rel=1e-4)
+    errs = [float(np.abs(lev_g[i] - lev_o[i]).max()) for i in range(16)]
+    steps = [float(np.abs(lev_o[i] - lev_o[i - 1]).max()) for i in range(1, 16)]
+    note("  max|dL| per level %s" % " ".join("%.1e" % e for e in errs))
+    note("  max step size     %s" % " ".join("%.1e" % e for e in steps))
+    assert errs[0] <= 1e-6
+    assert errs[1] <= 2e-2 * steps[0]
+    for i in range(1, 16):
+        assert errs[i] <= 0.05 * i * max(steps) + 1e-5, i
+
+
+def test_probe_error_matches_oracle(S, gpu_lib):
+    """err[1] (L_0 agrees to FP32 rounding) against the oracle's surrogate step
+    and exact AOS step on the same windows."""
+    K = gpu_lib
+    W, H = 100, 70
+    th = surrogate_params(3, last_scale=0.3)
+    note("[sgss] probe error %dx%d" % (W, H))
+    ss, _ = make(S, K, W, H, 13, th, bound=float("inf"), probes=3, probe_size=24)
+    ss.run()
+    torch.cuda.synchronize()
+    img = kaze_image(W, H, 13).astype(np.float64)
+    lev, k = O.build_scale_space(img)
+    L0 = lev[0]
+    g = O.conductivity_g2(L0, k)
+    tau = O.level_schedule()[1]["t"] - O.level_schedule()[0]["t"]
+    sur = C.surrogate_step(th.astype(np.float64), L0, g, tau, quantized=True)
+    exact = O.aos_step(L0, g, tau)
+    e_o = 0.0
+    for (x0, y0) in ss.probe_xy[1]:
+        win = (slice(y0, y0 + 24), slice(x0, x0 + 24))
+        e_o = max(e_o, float(np.abs(sur[win] - exact[win]).max()))
+    e_g = float(ss.err[1].item())
+    fscale = float(np.abs(sur - L0).max())
+    note("  err[1] gpu %.6e oracle %.6e (max |f| %.3e)" % (e_g, e_o, fscale))
+    assert abs(e_g - e_o) <= 5e-3 * fscale + 1e-5
+
+
+def test_mixed_decisions_are_consistent(S, gpu_lib):
+    """With a bound between the probe errors some levels keep the surrogate
+    step and others fall back; each level must equal the surrogate forward
+    pass or the exact AOS step of the level before it."""
+    K = gpu_lib
+    W, H = 88, 64
+    th = surrogate_params(4, last_scale=0.05)
+    ss, w = make(S, K, W, H, 14, th, bound=float("inf"), probes=4)
+    ss.run()
+    torch.cuda.synchronize()
+    errs = ss.err.cpu().numpy()[1:]
+    bound = float(np.median(errs))
+    note("[sgss] mixed: probe errors %s, bound %.3e" % (" ".join("%.1e" % e for e in errs), bound))
+    ss2, _ = make(S, K, W, H, 14, th, bound=bound, probes=4)
+    ss2.run()
+    torch.cuda.synchronize()
+    acc = ss2.accepted()
+    assert 0 < sum(acc) < 15
+    p = ss2.p
+    sched = K.kaze_schedule(p)
+    lev = ss2.levels
+    k = float(ss2.k.item())
+    plan = S.Plan(1, W, H)
+    ws = torch.empty(K.kaze_workspace_bytes(W, H, p), dtype=torch.uint8, device="cuda")
+    for i in range(1, 16):
+        g = torch.empty((H, W), device="cuda")
+        K.kaze_conductivity(lev[i - 1], W, H, p, k, g)
+        tau = torch.tensor([sched[i]["tau"]], dtype=torch.float32, device="cuda")
+        if acc[i]:
+            ref = plan.forward(w, lev[i - 1][None].contiguous(), g[None].contiguous(), tau)[0]
+            torch.cuda.synchronize()
+            assert torch.equal(ref, lev[i]), i
+        else:
+            ref = torch.empty((H, W), device="cuda")
+            K.kaze_aos_step(lev[i - 1], g, W, H, sched[i]["tau"], ref, ws, ws.numel())
+            torch.cuda.synchronize()
+            assert (ref - lev[i]).abs().max().item() <= 2e-6, i
+
+
+def test_graph_replays_equal_eager(S, gpu_lib):
+    K = gpu_lib
+    W, H = 64, 64
+    ss, _ = make(S, K, W, H, 15, surrogate_params(5, last_scale=0.05), bound=1e-2, probes=2)
+    ss.run(eager=True)
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in (ss.levels, ss.det, ss.err, ss.k)]
+    cnt = int(ss.count.item())
+    for r in range(3):
+        ss.levels.fill_(-1.0)
+        ss.err.fill_(-1.0)
+        ss.run()
+        torch.cuda.synchronize()
+        for a, b in zip((ss.levels, ss.det, ss.err, ss.k), ref):
+            assert torch.equal(a, b), r
+        assert int(ss.count.item()) == cnt
+    ss.close()
