@@ -10,7 +10,6 @@ conductivity + AOS step, the Hessian determinant of all 16 levels and the
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import subprocess
@@ -22,6 +21,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "1920x1200 scale-space+Hessian images/s, AOS vs surrogate; % HBM peak"
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0   # dense MFMA, MI355X
+# hidden 32 -> 32 convolution of the surrogate: 2 * 32 * 32 * 9 FLOP per pixel
+CONV_FLOP_PER_PX = 2 * 32 * 32 * 9
 # The dominant kernels run one level of the scale space: conductivity and
 # AOS step (aos_reduce computes g and reduces every chunk, aos_iface solves
 # the interface systems, aos_recover recovers the chunks and averages).
@@ -31,26 +33,19 @@ LEVEL_ALGO_BYTES_PER_PX = 20
 AOS_KERNELS = ("aos_reduce", "aos_iface", "aos_recover")
 
 
-def csrc_hash() -> str:
-    h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_1706_06750_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
-    return h.hexdigest()[:16]
-
-
-def traffic_from_profile(W, H):
-    """HBM bytes per AOS step from the committed counter summary, if it was
-    taken on the current kernel sources."""
+def traffic_from_profile(W, H, aos_tile):
+    """HBM bytes per level (conductivity + AOS step) from the committed
+    counter summary, if it was taken on the current per-level kernel sources
+    with the same tile shape."""
+    from paper_1706_06750_amd.rocprof_summary import csrc_hash
     path = os.path.join(ROOT, "profiles", "level_traffic_%dx%d.json" % (W, H))
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("csrc_hash") != csrc_hash():
+    if d.get("csrc_hash") != csrc_hash(ROOT) or d.get("aos_tile") != aos_tile:
         return None
-    return d.get("bytes_per_level")
+    return round(d.get("bytes_per_level"))
 
 
 CPU_BASELINE_SRC = r"""
@@ -106,6 +101,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="kaze_1920x1200")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the surrogate measurements (plain path only)")
     ap.add_argument("--no-breakdown", action="store_true",
                     help="skip the per-kernel timing pass (for profiler runs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -214,7 +211,7 @@ def bench_single(args, K, torch, kaze_image, case):
     torch.cuda.synchronize()
     elapsed, level_us = timed_graph_runs(args, K, torch, kb)
     roof = level_roofline(level_us, W * H,
-                          traffic_from_profile(W, H) if kb.shape == 0 else None)
+                          traffic_from_profile(W, H, "%dx%d" % K.AOS_SHAPES[kb.shape]))
     roof["timed_in"] = "the timed region (event pair around each run's AOS segment)"
     kps = int(kb.count[0].item())
     shape = K.AOS_SHAPES[kb.shape]
@@ -223,12 +220,70 @@ def bench_single(args, K, torch, kaze_image, case):
     extra = {"eager_images_per_s": round(eager_value, 3),
              "kernel_breakdown": {k: {kk: round(vv, 4) for kk, vv in v.items()}
                                   for k, v in breakdown.items()}}
+    if not args.no_surrogate:
+        extra["surrogate"] = bench_surrogate(args, K, torch, img, W, H, seed,
+                                             args.steps / elapsed)
     if not args.no_cpu_baseline:
         extra["cpu_baseline"] = cpu_baseline(W, H, seed)
     config = {"workload": args.workload, "image": "%dx%d" % (W, H), "seed": seed,
               "levels": kz.N, "path": "plain AOS (no surrogate), graph replay",
               "aos_tile": "%dx%d" % shape, "keypoints": kps}
     return record(args, args.steps / elapsed, 1e3 * elapsed / args.steps, config, roof, extra)
+
+
+def bench_surrogate(args, K, torch, img, W, H, seed, plain_value):
+    """The surrogate form on the same image: the default per-level check and
+    fallback, and every level forced to the surrogate (its cost without
+    checks); plus the MFMA roofline of the hidden 32 -> 32 convolution."""
+    import math
+    from paper_1706_06750_amd import surrogate as S
+    from paper_1706_06750_amd import train_surrogate as T
+    if not os.path.exists(T.DEFAULT_OUT):
+        return {"skipped": "no trained weights (%s)" % os.path.relpath(T.DEFAULT_OUT, ROOT)}
+    params, meta = T.load()
+    w = S.Weights(params)
+    out = {"weights": os.path.relpath(T.DEFAULT_OUT, ROOT),
+           "trained_on": "%d images %dx%d, %d epochs" % (meta["images"], meta["size"],
+                                                         meta["size"], meta["epochs"])}
+    steps = max(5, args.steps // 4)
+    for name, cfg in (("default", {}), ("all_surrogate", {"bound": math.inf, "probes": 0})):
+        c = S.kaze_sg_default_config(**cfg)
+        ss = S.SurrogateScaleSpace(W, H, w, config=c, probe_seed=seed)
+        ss.img.copy_(img)
+        for _ in range(max(2, args.warmup // 4)):
+            ss.run()
+        torch.cuda.synchronize()
+        K.kaze_profile_begin("aos_reduce")
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ss.run()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        runs, ms = K.kaze_profile_end()
+        acc = ss.accepted()
+        val = steps / el
+        out[name] = {"bound": c.bound, "probes": c.probes, "images_per_s": round(val, 3),
+                     "us_per_level": round(1e3 * ms / (runs * (ss.N - 1)), 3),
+                     "levels_accepted": int(sum(acc)),
+                     "accepted": [int(a) for a in acc],
+                     "probe_err": [float("%.3e" % e) for e in ss.err.cpu().tolist()],
+                     "speedup_vs_plain": round(val / plain_value, 4)}
+        if name == "all_surrogate":
+            # eager run with events around every hidden-layer launch
+            K.kaze_profile_begin("sg_conv")
+            for _ in range(2):
+                ss.run(eager=True)
+            n, cms = K.kaze_profile_end()
+            us = 1e3 * cms / n
+            flop = CONV_FLOP_PER_PX * W * H
+            tf = flop / (us * 1e-6) / 1e12
+            out["conv_roofline"] = {"kernel": "conv_kernel<32, 2, relu> (hidden layer)",
+                                    "bound": "mfma", "achieved": round(tf, 1),
+                                    "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                    "frac": round(tf / BF16_PEAK_TFLOPS, 4),
+                                    "flop_per_launch": flop, "us_per_launch": round(us, 3)}
+        ss.close()
+    return out
 
 
 def bench_batch(args, K, torch, kaze_image, cases):

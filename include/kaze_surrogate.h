@@ -12,7 +12,9 @@
  *   input planes (L, g, tau / 68), six 3x3 convolutions (cross-correlation,
  *   one pixel of zero padding) 3 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1 with a
  *   bias per output channel and ReLU after layers 1..5; f is the output of
- *   layer 6.  Loss: mean of (f - (L_next - L))^2 over all pixels.
+ *   layer 6 divided by 64 (a fixed scale: one step moves a level by about
+ *   1e-3 while the hidden activations are of order one).  Loss: mean over
+ *   all pixels of w_s (f - (L_next - L))^2, w_s a weight per sample.
  *
  * Parameters are one flat FP32 vector of kaze_sg_param_count() = 38,177
  * values: for each layer the weights [co][ci][3][3], then the biases [co].
@@ -93,13 +95,15 @@ kaze_status kaze_sg_forward(const kaze_sg_plan* plan, const void* packed, const 
  * Forward and backward pass of the residual loss over the plan's n samples
  * (training plan only).
  *   L_next   (device) n x H x W float32 target levels.
+ *   weight   (device) n float32 loss weights, or NULL for weight 1.
  *   grad     (device) output, kaze_sg_param_count() floats: d loss / d params
  *            (straight-through for the BF16 rounding of the weights).
- *   loss     (device) output, 1 float: mean (f - (L_next - L))^2.
+ *   loss     (device) output, 1 float: mean over the n H W pixels of
+ *            w_s (f - (L_next - L))^2.
  */
 kaze_status kaze_sg_gradients(const kaze_sg_plan* plan, const void* packed, const float* L,
                               const float* g, const float* tau, const float* L_next,
-                              float* grad, float* loss, void* stream);
+                              const float* weight, float* grad, float* loss, void* stream);
 
 /*
  * One Adam update (Kingma and Ba, with bias correction) of `count` FP32

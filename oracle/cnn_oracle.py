@@ -15,8 +15,14 @@ checked against:
 * six 3x3 convolutions (cross-correlation, zero padding of one pixel) with
   channel counts 3 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, bias per output
   channel, ReLU after layers 1..5, nothing after layer 6;
-* the network output f is the residual: L_next ~ L + f;
-* loss: mean over every pixel of every sample of (f - (L_next - L))^2;
+* the network output f is OUT_SCALE times the output of layer 6 and is the
+  residual of the step: L_next ~ L + f.  One step moves a level by about
+  1e-3 (RMS) while the hidden activations are of order one; the fixed
+  power-of-two scale lets layer 6 work at order-one values;
+* loss: mean over every pixel of every sample of w_s (f - (L_next - L))^2,
+  with a weight w_s per sample (1 unless given; training uses 1 / tau so
+  that the small steps of the first levels count as much as the large ones
+  of the last);
 * Adam (Kingma and Ba 2015) with bias correction on the flat FP32 parameter
   vector.
 
@@ -40,13 +46,14 @@ import numpy as np
 from . import kaze_oracle as K
 
 __all__ = [
-    "TAU_REF", "CHANNELS", "param_shapes", "param_count", "unflatten",
+    "TAU_REF", "OUT_SCALE", "CHANNELS", "param_shapes", "param_count", "unflatten",
     "flatten", "bf16_round", "conv3x3", "conv3x3_input_grad",
     "conv3x3_weight_grad", "input_planes", "forward", "backward",
     "loss_and_grad", "adam_step", "surrogate_step", "surrogate_scale_space",
 ]
 
 TAU_REF = 68.0
+OUT_SCALE = 1.0 / 64.0
 CHANNELS = (3, 32, 32, 32, 32, 32, 1)
 
 
@@ -149,7 +156,7 @@ def forward(theta, L, g, tau, quantized=False):
         Wl = bf16_round(W) if (quantized and li > 0) else W
         Z = conv3x3(X, Wl, b)
         if li == len(layers) - 1:
-            return Z[:, 0], acts
+            return OUT_SCALE * Z[:, 0], acts
         X = np.maximum(Z, 0.0)
         if quantized:
             X = bf16_round(X)
@@ -160,7 +167,7 @@ def forward(theta, L, g, tau, quantized=False):
 def backward(theta, acts, dF, quantized=False):
     """Gradient of sum(dF * f) with respect to the flat parameter vector."""
     layers = unflatten(theta)
-    dZ = np.asarray(dF, dtype=np.float64)[:, None]
+    dZ = OUT_SCALE * np.asarray(dF, dtype=np.float64)[:, None]
     grads = [None] * len(layers)
     for li in range(len(layers) - 1, -1, -1):
         W, _ = layers[li]
@@ -175,16 +182,19 @@ def backward(theta, acts, dF, quantized=False):
     return flatten(grads)
 
 
-def loss_and_grad(theta, L, g, tau, L_next, quantized=False):
-    """(loss, grad, f) for the residual MSE of one batch of level steps."""
+def loss_and_grad(theta, L, g, tau, L_next, quantized=False, weights=None):
+    """(loss, grad, f) for the weighted residual MSE of one batch of level
+    steps (weights: one per sample, default 1)."""
     L = np.asarray(L, dtype=np.float64)
     L_next = np.asarray(L_next, dtype=np.float64)
     if L.ndim == 2:
         L, L_next, g = L[None], L_next[None], np.asarray(g)[None]
     f, acts = forward(theta, L, g, tau, quantized)
     r = f - (L_next - L)
-    loss = float(np.mean(r * r))
-    dF = 2.0 * r / r.size
+    w = np.ones(L.shape[0]) if weights is None else np.asarray(weights, dtype=np.float64).reshape(-1)
+    wr = w[:, None, None] * r
+    loss = float(np.sum(wr * r) / r.size)
+    dF = 2.0 * wr / r.size
     return loss, backward(theta, acts, dF, quantized), f
 
 

@@ -41,7 +41,8 @@ kaze_status fail(kaze_status st, const char* fmt, ...) {
 // ---------------------------------------------------------------- profiling
 const char* const kKernelNames[K_COUNT] = {
     "gauss", "grad", "hist", "kselect", "cond", "aos_reduce", "aos_iface", "aos_recover",
-    "det",   "nms",  "fill", "copy",    "sg_conv", "sg_probe"};
+    "det",   "nms",  "fill", "copy",    "sg_pack", "sg_conv1", "sg_conv", "sg_conv6",
+    "sg_probe"};
 
 struct Profiler {
     unsigned mask = 0;  // bit i: record launches of kernel i
@@ -574,10 +575,14 @@ void sg_probe_items(const sg::Geo& g, const int4* rects, int n, std::vector<int>
         if (mark[i]) out.push_back((int)i);
 }
 
+// Probe windows are short: their convolutions run with few rows per wave,
+// so that the latency of one wave's row sweep stays small.
+constexpr int kProbeRows = 4;
+
 int sg_max_items(const kaze_sg_config* c) {
     // a window of probe_size + 2 halo pixels spans at most this many strips x chunks
     const int span = c->probe_size + 2 * sg::kProbeHalo;
-    const int per = (span / sg::kStrip + 2) * (span / sg::kConvRows + 2);
+    const int per = (span / sg::kStrip + 2) * (span / kProbeRows + 2);
     return std::max(1, c->probes * per);
 }
 
@@ -623,7 +628,7 @@ struct kaze_sg_scale_space {
     BatchImage b;
     ImageDesc aos;  // scratch pointers of the AOS step; L, Lnext, gate set per level
     const unsigned char* packed = nullptr;
-    sg::Geo geo;
+    sg::Geo geo, geo_probe;
     sg::bf16 *x0 = nullptr, *xa = nullptr, *xb = nullptr;
     float *delta = nullptr, *err = nullptr, *tau = nullptr;
     int4* rects = nullptr;
@@ -636,8 +641,8 @@ namespace {
 
 // The six convolutions of one surrogate step L_i = L_{i-1} + f, over every
 // strip of the image or over an item list; gated on *gate <= bound if gate.
-kaze_status sg_chain(const kaze_sg_scale_space& S, int i, const float* Lp, float* Li,
-                     const int* items, int nitems, const float* gate, hipStream_t s) {
+kaze_status sg_chain(const kaze_sg_scale_space& S, const sg::Geo& geo, int i, const float* Lp,
+                     float* Li, const int* items, int nitems, const float* gate, hipStream_t s) {
     const sg::PackLayout P = sg::pack_layout();
     sg::bf16* buf[sg::kLayers] = {S.x0, S.xa, S.xb, S.xa, S.xb, S.xa};
     for (int l = 0; l < sg::kLayers; ++l) {
@@ -652,16 +657,16 @@ kaze_status sg_chain(const kaze_sg_scale_space& S, int i, const float* Lp, float
         a.bound = S.bound;
         if (l == 0) {
             a.tauw = reinterpret_cast<const float*>(S.packed + P.tauw);
-            a.tausum = reinterpret_cast<const float*>(S.packed + P.tausum);
             a.tau = S.tau + i;
         }
         if (l < sg::kLayers - 1) {
             a.out = buf[l + 1];
-            KZ_LAUNCH(K_SG_CONV, s, sg::launch_conv(l == 0 ? 8 : 32, 2, sg::EPI_RELU, l == 0, a, S.geo, s));
+            KZ_LAUNCH(l == 0 ? K_SG_CONV1 : K_SG_CONV, s,
+                      sg::launch_conv(l == 0 ? 8 : 32, 2, sg::EPI_RELU, l == 0, a, geo, s));
         } else {
             a.fout = Li;
             a.base = Lp;
-            KZ_LAUNCH(K_SG_CONV, s, sg::launch_conv(32, 1, sg::EPI_OUT, false, a, S.geo, s));
+            KZ_LAUNCH(K_SG_CONV6, s, sg::launch_conv(32, 1, sg::EPI_OUT, false, a, geo, s));
         }
     }
     return KAZE_OK;
@@ -690,19 +695,20 @@ kaze_status sg_segment(const kaze_sg_scale_space& S, int seg, hipStream_t s) {
         BatchImage bc = S.b;
         bc.levels = const_cast<float*>(Lp);
         KZ_LAUNCH(K_COND, s, launch_cond(bc, none, tc, 1.f, gmode, s));
-        KZ_LAUNCH(K_SG_CONV, s, sg::launch_pack_input(Lp, S.b.g, S.tau + i, S.x0, nullptr, S.geo, s));
+        KZ_LAUNCH(K_SG_PACK, s, sg::launch_pack_input(Lp, S.b.g, S.tau + i, S.x0, nullptr, S.geo, s));
         ImageDesc d = S.aos;
         d.L = Lp;
         d.Lnext = Li;
         if (S.probes > 0) {
-            kaze_status st = sg_chain(S, i, Lp, Li, S.items + S.item_off[i], S.item_cnt[i], nullptr, s);
+            kaze_status st = sg_chain(S, S.geo_probe, i, Lp, Li, S.items + S.item_off[i], S.item_cnt[i],
+                                     nullptr, s);
             if (st != KAZE_OK) return st;
             const int4* r = S.rects + (size_t)i * S.probes;
             KZ_LAUNCH(K_SG_PROBE, s, launch_aos_probe(d, r, S.probes, tau, S.delta, s));
             KZ_LAUNCH(K_SG_PROBE, s, launch_probe_err(Lp, Li, S.W, r, S.probes, S.delta,
                                                       reinterpret_cast<unsigned*>(S.err + i), s));
         }
-        kaze_status st = sg_chain(S, i, Lp, Li, nullptr, 0, S.err + i, s);
+        kaze_status st = sg_chain(S, S.geo, i, Lp, Li, nullptr, 0, S.err + i, s);
         if (st != KAZE_OK) return st;
         d.gate = S.err + i;
         d.bound = S.bound;
@@ -1093,6 +1099,7 @@ kaze_status kaze_sg_scale_space_create(const kaze_image_desc* im, const kaze_par
     S->aos = aos_desc(W, H, shape, base, sc, im->k);
     S->packed = static_cast<const unsigned char*>(packed);
     S->geo = sg::make_geo(1, W, H, sg::kConvRows);
+    S->geo_probe = sg::make_geo(1, W, H, kProbeRows);
     S->x0 = reinterpret_cast<sg::bf16*>(base + L.x0);
     S->xa = reinterpret_cast<sg::bf16*>(base + L.xa);
     S->xb = reinterpret_cast<sg::bf16*>(base + L.xb);
@@ -1118,7 +1125,7 @@ kaze_status kaze_sg_scale_space_create(const kaze_image_desc* im, const kaze_par
             hrect[(size_t)i * P + q] =
                 make_int4(x0, y0, std::min(c->probe_size, W - x0), std::min(c->probe_size, H - y0));
         }
-        sg_probe_items(S->geo, hrect.data() + (size_t)i * P, c->probes, tmp);
+        sg_probe_items(S->geo_probe, hrect.data() + (size_t)i * P, c->probes, tmp);
         if ((int)tmp.size() > L.max_items) {
             kaze_sg_scale_space_destroy(S);
             return fail(KAZE_ERR_UNSUPPORTED, "probe windows need %zu items (max %d)", tmp.size(),

@@ -221,7 +221,10 @@ enum KernelId {
     K_NMS,
     K_FILL,
     K_COPY,
+    K_SG_PACK,
+    K_SG_CONV1,
     K_SG_CONV,
+    K_SG_CONV6,
     K_SG_PROBE,
     K_COUNT
 };

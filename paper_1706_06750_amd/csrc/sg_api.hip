@@ -135,7 +135,6 @@ kaze_status forward(const kaze_sg_plan* p, const unsigned char* pk, const float*
         a.bias = reinterpret_cast<const float*>(pk + P.bias[l]);
         if (l == 0) {
             a.tauw = reinterpret_cast<const float*>(pk + P.tauw);
-            a.tausum = reinterpret_cast<const float*>(pk + P.tausum);
             a.tau = tau;
         }
         if (l < kLayers - 1) {
@@ -210,7 +209,7 @@ kaze_status kaze_sg_forward(const kaze_sg_plan* plan, const void* packed, const 
 
 kaze_status kaze_sg_gradients(const kaze_sg_plan* plan, const void* packed, const float* L,
                               const float* g, const float* tau, const float* L_next,
-                              float* grad, float* loss, void* stream) {
+                              const float* weight, float* grad, float* loss, void* stream) {
     kaze_status st = check_plan(plan, packed, L, g, tau);
     if (st != KAZE_OK) return st;
     if (!plan->training) return fail(KAZE_ERR_INVALID_ARG, "plan was created for inference only");
@@ -221,8 +220,8 @@ kaze_status kaze_sg_gradients(const kaze_sg_plan* plan, const void* packed, cons
     const Geo& gg = plan->g;
     st = forward(plan, pk, L, g, tau, plan->f, nullptr, s);
     if (st != KAZE_OK) return st;
-    SG_HIP(launch_loss(plan->f, L, L_next, plan->dz[5], plan->dzp[5], plan->lpart, plan->loss_blocks,
-                       gg, s));
+    SG_HIP(launch_loss(plan->f, L, L_next, weight, plan->dz[5], plan->dzp[5], plan->lpart,
+                       plan->loss_blocks, gg, s));
     SG_HIP(launch_sum(plan->lpart, plan->loss_blocks, (float)(1.0 / ((double)gg.n * gg.W * gg.H)),
                       loss, s));
     // layer index l = 5 .. 0: weight gradient from (input of l, dZ of l), then

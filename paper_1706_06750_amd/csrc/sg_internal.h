@@ -29,6 +29,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kLayers = 6;
 constexpr int kCh = 32;                 // hidden channels
 constexpr float kTauRef = 68.0f;        // the tau input plane holds tau / kTauRef
+constexpr float kOutScale = 1.0f / 64;  // f = kOutScale * (output of layer 6)
 constexpr int kParams = (3 * 32 * 9 + 32) + 4 * (32 * 32 * 9 + 32) + (32 * 9 + 1);
 constexpr int kPartStride = 9 * 32 * 32 + 32;  // weight-gradient partial of one wave
 constexpr int kStrip = 16;              // output pixels per MFMA column block
@@ -49,10 +50,9 @@ ParamLayout param_layout();
 //   dgr[l]  : input-gradient fragments of layer l (l >= 1), transposed and
 //             flipped taps, [2][KS][64] x 8
 //   bias[l] : FP32 [32] (zero beyond co)
-//   tauw    : FP32 [32][9] layer-1 tap weights of the tau plane, and
-//   tausum  : FP32 [32] their sums (interior pixels)
+//   tauw    : FP32 [32][9] layer-1 tap weights of the tau plane
 struct PackLayout {
-    size_t fwd[kLayers], dgr[kLayers], bias[kLayers], tauw, tausum, bytes;
+    size_t fwd[kLayers], dgr[kLayers], bias[kLayers], tauw, bytes;
 };
 PackLayout pack_layout();
 
@@ -74,7 +74,6 @@ struct ConvArgs {
     const bf16x8* wfrag;  // packed fragments
     const float* bias;    // FP32 [16 MB] (EPI_RELU, EPI_OUT)
     const float* tauw;    // layer 1: FP32 [32][9] tau tap weights, else NULL
-    const float* tausum;  // layer 1: FP32 [32]
     const float* tau;     // [n] step sizes (layer 1)
     bf16* out;            // NHWC padded output, 32 channels (EPI_RELU, EPI_MASK)
     bf16* outp;           // planar copy of the output (X or dZ layout), or NULL
@@ -91,8 +90,8 @@ hipError_t launch_conv(int cin, int mb, int epi, bool tau_term, const ConvArgs& 
                        const Geo& g, hipStream_t s);
 hipError_t launch_pack_input(const float* L, const float* gc, const float* tau, bf16* x0,
                              bf16* x0p, const Geo& g, hipStream_t s);
-hipError_t launch_loss(const float* f, const float* L, const float* Ln, bf16* dz6, bf16* dz6p,
-                       float* lpart, int nblocks, const Geo& g, hipStream_t s);
+hipError_t launch_loss(const float* f, const float* L, const float* Ln, const float* wts, bf16* dz6,
+                       bf16* dz6p, float* lpart, int nblocks, const Geo& g, hipStream_t s);
 int loss_blocks(const Geo& g);
 hipError_t launch_wgrad(int cin, int cout, const bf16* xp, const bf16* dzp, float* part,
                         const Geo& g, int R, hipStream_t s);

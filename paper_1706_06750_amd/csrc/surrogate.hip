@@ -2,7 +2,7 @@
 //
 // The network is six 3x3 convolutions (cross-correlation, zero padding)
 // 3 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1 with ReLU after layers 1..5; its
-// output f is the residual of the step, L_next ~ L + f.  Inputs are the
+// output f = (layer 6) / 64 is the residual of the step, L_next ~ L + f.  Inputs are the
 // previous level L, its conductivity g and the plane tau / 68.
 //
 // Every convolution is an implicit GEMM on v_mfma_f32_16x16x32_bf16 with
@@ -57,39 +57,28 @@ struct ConvK {
 template <int MB, int EPI, bool TAU>
 __device__ inline void conv_epilogue(const ConvArgs& a, const Geo& g, int s, int y, int x, int q,
                                      const f32x4 (&acc)[MB], const float (&bias)[MB][4],
-                                     float taup) {
+                                     const float (&tcs)[MB][4][3]) {
     if (x >= g.W) return;
     const size_t pix = (size_t)s * g.sx + (size_t)(y + 1) * g.pw + (x + 1);
     if constexpr (EPI == EPI_OUT) {
         if (q != 0) return;
-        const float f = acc[0][0] + bias[0][0];
+        const float f = (acc[0][0] + bias[0][0]) * kOutScale;
         const size_t o = ((size_t)s * g.H + y) * g.W + x;
         a.fout[o] = a.base ? a.base[o] + f : f;
         return;
     } else {
-        const bool interior = y >= 1 && y <= g.H - 2 && x >= 1 && x <= g.W - 2;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
             float v[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int co = 16 * mb + 4 * q + r;
                 float z = acc[mb][r];
                 if constexpr (EPI == EPI_RELU) {
                     z += bias[mb][r];
-                    if constexpr (TAU) {
-                        float t;
-                        if (interior) {
-                            t = a.tausum[co];
-                        } else {
-                            t = 0.f;
-#pragma unroll
-                            for (int k = 0; k < 9; ++k) {
-                                const int yy = y + k / 3 - 1, xx = x + k % 3 - 1;
-                                if (yy >= 0 && yy < g.H && xx >= 0 && xx < g.W) t += a.tauw[co * 9 + k];
-                            }
-                        }
-                        z += taup * t;
+                    if constexpr (TAU) {  // tau-plane taps inside the image
+                        z += tcs[mb][r][1];
+                        if (y >= 1) z += tcs[mb][r][0];
+                        if (y + 1 < g.H) z += tcs[mb][r][2];
                     }
                     z = z > 0.f ? z : 0.f;
                 }
@@ -153,7 +142,27 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a, Geo g) {
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) bias[mb][r] = (EPI == EPI_MASK) ? 0.f : a.bias[16 * mb + 4 * q + r];
-    const float taup = TAU ? a.tau[s] / kTauRef : 0.f;
+    // layer 1: per output channel and tap row, tau / 68 times the sum of the
+    // tau-plane tap weights whose column lies inside the image
+    float tcs[MB][4][3];
+    if constexpr (TAU) {
+        const float taup = a.tau[s] / kTauRef;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int ty = 0; ty < 3; ++ty) {
+                    const int co = 16 * mb + 4 * q + r;
+                    float t = 0.f;
+#pragma unroll
+                    for (int tx = 0; tx < 3; ++tx) {
+                        const int xx = x + tx - 1;
+                        if (xx >= 0 && xx < g.W) t += a.tauw[co * 9 + ty * 3 + tx];
+                    }
+                    tcs[mb][r][ty] = taup * t;
+                }
+    }
 
     // lane's column base: padded pixel (row 0, column xl) of sample s
     const bf16* col = a.in + ((size_t)s * g.sx + xl) * CIN;
@@ -169,9 +178,9 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a, Geo g) {
         R[1] = ld8(p_ + CIN);                               \
         R[2] = ld8(p_ + 2 * CIN);                           \
     }
-#define KZ_STEP(yy, RA, RB, RC)                                                       \
+#define KZ_STEP(yy, RA, RB, RC, RD)                                                   \
     {                                                                                 \
-        KZ_LOADROW(RC, (yy) + 2)                                                      \
+        if ((yy) + 1 < y1) KZ_LOADROW(RD, (yy) + 3)                                   \
         f32x4 acc[MB];                                                                \
         _Pragma("unroll") for (int mb = 0; mb < MB; ++mb) acc[mb] = f32x4{0.f, 0.f, 0.f, 0.f}; \
         _Pragma("unroll") for (int dx = 0; dx < 3; ++dx)                              \
@@ -183,15 +192,19 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a, Geo g) {
         _Pragma("unroll") for (int dx = 0; dx < 3; ++dx)                              \
             _Pragma("unroll") for (int mb = 0; mb < MB; ++mb)                         \
                 acc[mb] = mfma(wf[mb][6 + dx], RC[dx], acc[mb]);                      \
-        conv_epilogue<MB, EPI, TAU>(a, g, s, (yy), x, q, acc, bias, taup);            \
+        conv_epilogue<MB, EPI, TAU>(a, g, s, (yy), x, q, acc, bias, tcs);             \
     }
-        bf16x8 ra[3], rb[3], rc[3];
+        // padded rows y, y+1, y+2 feed output row y; row y+3 is loaded one
+        // step ahead
+        bf16x8 ra[3], rb[3], rc[3], rd[3];
         KZ_LOADROW(ra, y0)
         KZ_LOADROW(rb, y0 + 1)
-        for (int y = y0; y < y1; y += 3) {
-            KZ_STEP(y, ra, rb, rc)
-            if (y + 1 < y1) KZ_STEP(y + 1, rb, rc, ra)
-            if (y + 2 < y1) KZ_STEP(y + 2, rc, ra, rb)
+        KZ_LOADROW(rc, y0 + 2)
+        for (int y = y0; y < y1; y += 4) {
+            KZ_STEP(y, ra, rb, rc, rd)
+            if (y + 1 < y1) KZ_STEP(y + 1, rb, rc, rd, ra)
+            if (y + 2 < y1) KZ_STEP(y + 2, rc, rd, ra, rb)
+            if (y + 3 < y1) KZ_STEP(y + 3, rd, ra, rb, rc)
         }
 #undef KZ_STEP
 #undef KZ_LOADROW
@@ -211,7 +224,7 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a, Geo g) {
 #pragma unroll
                 for (int k = 0; k < KS; ++k) acc[mb] = mfma(wf[mb][k], b[k], acc[mb]);
             }
-            conv_epilogue<MB, EPI, TAU>(a, g, s, y, x, q, acc, bias, taup);
+            conv_epilogue<MB, EPI, TAU>(a, g, s, y, x, q, acc, bias, tcs);
         }
     }
 }
@@ -246,11 +259,12 @@ __global__ void pack_input_kernel(const float* __restrict__ L, const float* __re
 }
 
 // ---------------------------------------------------------------- the loss
-// r = f - (L_next - L); per-block partial sums of r^2; dZ6 = 2 r / count in
-// BF16 (NHWC8 channel 0 and planar).
+// r = f - (L_next - L); per-block partial sums of w_s r^2; dZ6 =
+// (2 w_s r / count) kOutScale in BF16 (NHWC8 channel 0 and planar).
 __global__ __launch_bounds__(256) void loss_kernel(const float* __restrict__ f,
                                                    const float* __restrict__ L,
                                                    const float* __restrict__ Ln,
+                                                   const float* __restrict__ wts,
                                                    bf16* __restrict__ dz6, bf16* __restrict__ dz6p,
                                                    float* __restrict__ lpart, Geo g, float dscale) {
     __shared__ float red[256];
@@ -258,12 +272,13 @@ __global__ __launch_bounds__(256) void loss_kernel(const float* __restrict__ f,
     const size_t total = per * g.n;
     float acc = 0.f;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
-        const float r = f[i] - (Ln[i] - L[i]);
-        acc += r * r;
         const int s = (int)(i / per);
+        const float wr = (f[i] - (Ln[i] - L[i])) * (wts ? wts[s] : 1.f);
+        const float r = f[i] - (Ln[i] - L[i]);
+        acc += wr * r;
         const size_t rr = i - (size_t)s * per;
         const int y = (int)(rr / g.W), x = (int)(rr - (size_t)y * g.W);
-        const bf16 d = (bf16)(r * dscale);
+        const bf16 d = (bf16)(wr * dscale);
         dz6[((size_t)s * g.sx + (size_t)(y + 1) * g.pw + (x + 1)) * 8] = d;
         dz6p[((size_t)s * g.H + y) * g.PZ + x] = d;
     }
@@ -462,7 +477,7 @@ struct PackJobs {
     PackJob j[11];
     int w[kLayers];  // weight offsets in the parameter vector
     int b[kLayers];
-    size_t bias_off[kLayers], tauw_off, tausum_off;
+    size_t bias_off[kLayers], tauw_off;
 };
 
 __device__ inline float hi_of(float w) { return (float)(bf16)w; }
@@ -518,13 +533,8 @@ __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ P, 
             const int con = ll == kLayers - 1 ? 1 : 32;
             reinterpret_cast<float*>(packed + jobs.bias_off[ll])[c] = c < con ? P[jobs.b[ll] + c] : 0.f;
         }
-        float sum = 0.f;
-        for (int t = 0; t < 9; ++t) {
-            const float w = P[jobs.w[0] + (c * 3 + 2) * 9 + t];
-            reinterpret_cast<float*>(packed + jobs.tauw_off)[c * 9 + t] = w;
-            sum += w;
-        }
-        reinterpret_cast<float*>(packed + jobs.tausum_off)[c] = sum;
+        for (int t = 0; t < 9; ++t)
+            reinterpret_cast<float*>(packed + jobs.tauw_off)[c * 9 + t] = P[jobs.w[0] + (c * 3 + 2) * 9 + t];
     }
 }
 
@@ -589,8 +599,6 @@ PackLayout pack_layout() {
     }
     P.tauw = o;
     o += 32 * 9 * sizeof(float);
-    P.tausum = o;
-    o += 32 * sizeof(float);
     P.bytes = (o + 255) & ~(size_t)255;
     return P;
 }
@@ -644,11 +652,11 @@ int loss_blocks(const Geo& g) {
     return (int)(b < 1024 ? b : 1024);
 }
 
-hipError_t launch_loss(const float* f, const float* L, const float* Ln, bf16* dz6, bf16* dz6p,
-                       float* lpart, int nblocks, const Geo& g, hipStream_t s) {
+hipError_t launch_loss(const float* f, const float* L, const float* Ln, const float* wts, bf16* dz6,
+                       bf16* dz6p, float* lpart, int nblocks, const Geo& g, hipStream_t s) {
     const double count = (double)g.n * g.W * g.H;
-    hipLaunchKernelGGL(loss_kernel, dim3(nblocks), dim3(256), 0, s, f, L, Ln, dz6, dz6p, lpart, g,
-                       (float)(2.0 / count));
+    hipLaunchKernelGGL(loss_kernel, dim3(nblocks), dim3(256), 0, s, f, L, Ln, wts, dz6, dz6p, lpart, g,
+                       (float)(2.0 * kOutScale / count));
     return hipGetLastError();
 }
 
@@ -700,7 +708,6 @@ hipError_t launch_pack_weights(const float* params, void* packed, hipStream_t s)
         J.bias_off[l] = P.bias[l];
     }
     J.tauw_off = P.tauw;
-    J.tausum_off = P.tausum;
     hipLaunchKernelGGL(pack_kernel, dim3((maxf * 64 + 255) / 256, n), dim3(256), 0, s, params,
                        static_cast<unsigned char*>(packed), J);
     return hipGetLastError();

@@ -40,10 +40,15 @@ def short(name: str) -> str:
     return n.split("::")[-1] if "<" not in n else n[n.rfind("::", 0, n.find("<")) + 2:]
 
 
+# Sources of the per-level kernels: a change to any of them invalidates a
+# traffic summary.
+LEVEL_SOURCES = ("aos.hip", "tile_cond.h", "kaze_internal.h")
+
+
 def csrc_hash(root: str) -> str:
     h = hashlib.sha256()
     d = os.path.join(root, "paper_1706_06750_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in LEVEL_SOURCES:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -69,7 +74,7 @@ def counter_means(path: str, counter: str):
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
-def traffic(fetch_csv, write_csv, W, H, copy_mib, root):
+def traffic(fetch_csv, write_csv, W, H, copy_mib, root, aos_tile):
     f = counter_means(fetch_csv, "FETCH_SIZE")
     w = counter_means(write_csv, "WRITE_SIZE")
     known_kib = copy_mib * 1024.0
@@ -80,7 +85,8 @@ def traffic(fetch_csv, write_csv, W, H, copy_mib, root):
         per[k] = {"fetch_kib_raw": f[k], "write_kib_raw": w[k],
                   "bytes": (f[k] * fs + w[k] * ws) * 1024.0}
     total = sum(v["bytes"] for v in per.values())
-    return {"image": "%dx%d" % (W, H), "copy_scale_fetch": fs, "copy_scale_write": ws,
+    return {"image": "%dx%d" % (W, H), "aos_tile": aos_tile,
+            "copy_scale_fetch": fs, "copy_scale_write": ws,
             "kernels": per, "bytes_per_level": total,
             "bytes_per_pixel_level": total / (W * H), "csrc_hash": csrc_hash(root)}
 
@@ -95,6 +101,7 @@ def main():
     b.add_argument("write_csv")
     b.add_argument("--image", required=True)
     b.add_argument("--copy-mib", type=int, required=True)
+    b.add_argument("--aos-tile", required=True, help="AOS tile shape of the run, e.g. 32x32")
     b.add_argument("--out", required=True)
     args = ap.parse_args()
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -102,7 +109,7 @@ def main():
         print(stats(args.csv))
     else:
         W, H = (int(v) for v in args.image.split("x"))
-        d = traffic(args.fetch_csv, args.write_csv, W, H, args.copy_mib, root)
+        d = traffic(args.fetch_csv, args.write_csv, W, H, args.copy_mib, root, args.aos_tile)
         with open(args.out, "w") as fh:
             json.dump(d, fh, indent=1)
         print(json.dumps(d, indent=1))

@@ -34,7 +34,7 @@ for _name, (_res, _args) in {
     "kaze_sg_plan_create": (_i32, [_i32, _i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
     "kaze_sg_plan_destroy": (None, [_vp]),
     "kaze_sg_forward": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
-    "kaze_sg_gradients": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "kaze_sg_gradients": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "kaze_sg_adam": (_i32, [_vp, _vp, _vp, _vp, _i32, _i32, _f64, _f64, _f64, _f64, _vp]),
     "kaze_sg_default_config": (_i32, [ctypes.POINTER(kaze_sg_config)]),
     "kaze_sg_scale_space_workspace_bytes": (_sz, [_i32, _i32, ctypes.POINTER(kaze_params),
@@ -88,9 +88,9 @@ def kaze_sg_forward(plan, packed, L, g, tau, out, add_input=1, stream=None):
                                int(add_input), _stream(stream)))
 
 
-def kaze_sg_gradients(plan, packed, L, g, tau, L_next, grad, loss, stream=None):
+def kaze_sg_gradients(plan, packed, L, g, tau, L_next, weight, grad, loss, stream=None):
     _check(lib.kaze_sg_gradients(plan, _ptr(packed), _ptr(L), _ptr(g), _ptr(tau), _ptr(L_next),
-                                 _ptr(grad), _ptr(loss), _stream(stream)))
+                                 _ptr(weight), _ptr(grad), _ptr(loss), _stream(stream)))
 
 
 def kaze_sg_adam(params, grad, m, v, count, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
@@ -154,8 +154,9 @@ class Plan:
         kaze_sg_forward(self.handle, w.packed, L, g, tau, out, add_input, stream)
         return out
 
-    def gradients(self, w: Weights, L, g, tau, L_next, stream=None):
-        kaze_sg_gradients(self.handle, w.packed, L, g, tau, L_next, w.grad, self.loss, stream)
+    def gradients(self, w: Weights, L, g, tau, L_next, weight=None, stream=None):
+        kaze_sg_gradients(self.handle, w.packed, L, g, tau, L_next, weight, w.grad, self.loss,
+                          stream)
         return self.loss
 
     def close(self):

@@ -2,9 +2,11 @@
 
 Training pairs come from the plain method on the fly: for every synthetic
 image the library builds the scale space, and each step i -> i+1 gives one
-pair (L_{i-1}, g(L_{i-1}), tau_i) -> L_i.  The forward pass, the backward
-pass and Adam run in libkaze's MFMA kernels; this module only schedules
-them and moves tensors.
+pair (L_{i-1}, g(L_{i-1}), tau_i) -> L_i.  Each pair's loss is weighted by
+1 / tau_i: a step moves a level by an amount that grows with tau (about 12x
+from the first to the last level), and unweighted the large steps would
+decide the whole fit.  The forward pass, the backward pass and Adam run in
+libkaze's MFMA kernels; this module only schedules them and moves tensors.
 
     python -m paper_1706_06750_amd.train_surrogate [--images 2000] [--size 512]
         [--epochs 3] [--batch 16] [--lr 1e-3] [--out weights/surrogate_512.npz]
@@ -80,6 +82,36 @@ class PairSource:
         return r
 
 
+def evaluate(K, S, w, size=512, images=16, image_seed=410000, workers=None, chunk=16):
+    """Per-level error of the network on held-out level pairs (images not
+    used in training): RMS and max |f - (L_i - L_{i-1})|, next to the same
+    figures for taking no step at all (f = 0)."""
+    import torch
+    host = make_images(images, size, image_seed, workers or 1)
+    imgs = torch.from_numpy(host).cuda()
+    src = PairSource(K, size, chunk)
+    N = src.N
+    plan = S.Plan(chunk * (N - 1), size, size, training=False)
+    sq = np.zeros(N)
+    mx = np.zeros(N)
+    sq0 = np.zeros(N)
+    mx0 = np.zeros(N)
+    cnt = 0
+    for c in range(images // chunk):
+        src.fill(imgs[c * chunk:(c + 1) * chunk])
+        f = plan.forward(w, src.L, src.g, src.t, add_input=False)
+        r = (f - (src.Ln - src.L)).reshape(chunk, N - 1, -1)
+        d = (src.Ln - src.L).reshape(chunk, N - 1, -1)
+        sq[1:] += (r.double() ** 2).mean(dim=2).sum(dim=0).cpu().numpy()
+        mx[1:] = np.maximum(mx[1:], r.abs().amax(dim=(0, 2)).cpu().numpy())
+        sq0[1:] += (d.double() ** 2).mean(dim=2).sum(dim=0).cpu().numpy()
+        mx0[1:] = np.maximum(mx0[1:], d.abs().amax(dim=(0, 2)).cpu().numpy())
+        cnt += chunk
+    return {"rms": np.sqrt(sq / cnt).tolist(), "max": mx.tolist(),
+            "rms_no_step": np.sqrt(sq0 / cnt).tolist(), "max_no_step": mx0.tolist(),
+            "images": images, "image_seed": image_seed}
+
+
 def train(images=2000, size=512, epochs=3, batch=16, lr=1e-3, lr_min=1e-5, chunk=16, seed=0,
           image_seed=400000, workers=None, log_every=100, out=DEFAULT_OUT, verbose=True):
     import torch
@@ -115,7 +147,7 @@ def train(images=2000, size=512, epochs=3, batch=16, lr=1e-3, lr_min=1e-5, chunk
                 g = src.g.index_select(0, idx)
                 Ln = src.Ln.index_select(0, idx)
                 tau = src.t.index_select(0, idx)
-                loss = plan.gradients(w, L, g, tau, Ln)
+                loss = plan.gradients(w, L, g, tau, Ln, weight=1.0 / tau)
                 cur = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * step / max(1, total)))
                 w.adam(lr=cur)
                 step += 1
@@ -128,11 +160,16 @@ def train(images=2000, size=512, epochs=3, batch=16, lr=1e-3, lr_min=1e-5, chunk
     torch.cuda.synchronize()
     t_train = time.time() - t1
     params = w.params.cpu().numpy()
+    held = evaluate(K, S, w, size, workers=workers)
+    if verbose:
+        print("held-out per-level RMS  %s" % " ".join("%.1e" % v for v in held["rms"][1:]))
+        print("held-out per-level max  %s" % " ".join("%.1e" % v for v in held["max"][1:]))
+        print("no step: per-level max  %s" % " ".join("%.1e" % v for v in held["max_no_step"][1:]))
     meta = {"images": images, "size": size, "epochs": epochs, "batch": batch, "lr": lr,
             "lr_min": lr_min, "chunk": chunk, "init_seed": seed, "image_seed": image_seed,
             "steps": step, "pairs_per_epoch": n_chunks * pairs_per_chunk,
             "image_generation_s": round(t_gen, 2), "train_s": round(t_train, 2),
-            "loss_history": history}
+            "held_out": held, "loss_history": history}
     if out:
         os.makedirs(os.path.dirname(out), exist_ok=True)
         np.savez(out, params=params, meta=json.dumps(meta))

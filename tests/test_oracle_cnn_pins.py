@@ -100,7 +100,7 @@ def test_identity_network_closed_form():
     g = np.linspace(0.2, 1.0, L.size).reshape(L.shape)
     tau = 17.0
     f, _ = C.forward(th, L, g, tau)
-    ref = a[0] * L + a[1] * g + a[2] * tau / C.TAU_REF + 0.125
+    ref = C.OUT_SCALE * (a[0] * L + a[1] * g + a[2] * tau / C.TAU_REF + 0.125)
     assert np.allclose(f[0], ref, rtol=0, atol=1e-14)
     # every intermediate value is exactly representable: the BF16 storage
     # rounding changes nothing when weights and planes are BF16 numbers
@@ -164,7 +164,7 @@ def test_input_gradient_by_central_differences():
 
     f, acts = C.forward(th, L, g, 2.0)
     # dObj/dX0 by chaining the oracle's transposed convolutions by hand
-    dZ = w[:, None]
+    dZ = C.OUT_SCALE * w[:, None]
     for li in range(5, 0, -1):
         dX = C.conv3x3_input_grad(dZ, layers[li][0])
         dZ = dX * (acts[li] > 0)
@@ -249,13 +249,13 @@ def test_quantized_rounding_points_closed_form():
     tau = 11.0
     fq, acts = C.forward(th, L, g, tau, quantized=True)
     q = C.bf16_round
-    ref = (q(a[0]) * q(L) + q(a[1]) * q(g) + q(a[2]) * q(tau / C.TAU_REF))[0]
+    ref = C.OUT_SCALE * (q(a[0]) * q(L) + q(a[1]) * q(g) + q(a[2]) * q(tau / C.TAU_REF))[0]
     assert np.allclose(fq[0], ref, rtol=0, atol=1e-15)
     # weight gradient of the centre tap of layer 6, channel 0 (L's copy)
     dF = rng.normal(size=(1, 6, 8)) * 1e-3
     grad = C.backward(th, acts, dF, quantized=True)
     W6 = C.unflatten(grad)[-1][0]
-    assert np.isclose(W6[0, 0, 1, 1], np.sum(q(dF) * q(L)), rtol=1e-13)
+    assert np.isclose(W6[0, 0, 1, 1], np.sum(q(C.OUT_SCALE * dF) * q(L)), rtol=1e-13)
     grad_x = C.backward(th, acts, dF, quantized=False)
     assert not np.isclose(C.unflatten(grad_x)[-1][0][0, 0, 1, 1], W6[0, 0, 1, 1], rtol=1e-9)
 
@@ -273,3 +273,18 @@ def test_surrogate_scale_space_reduces_to_the_plain_method():
     layers[-1][0][...] = 0.0
     lev3, _ = C.surrogate_scale_space(img, C.flatten(layers), [False] * 8 + [True] * 8)
     assert np.array_equal(lev3[8:], np.broadcast_to(lev[7], (8,) + lev[7].shape))
+
+
+def test_weighted_loss_is_the_weighted_sum_of_per_sample_losses():
+    rng = np.random.default_rng(13)
+    th = surrogate_params(8).astype(np.float64)
+    L = rng.uniform(0, 1, size=(3, 7, 9))
+    g = rng.uniform(0.1, 1, size=(3, 7, 9))
+    Ln = L + 0.01 * rng.normal(size=L.shape)
+    tau = np.array([0.5, 3.0, 40.0])
+    w = np.array([2.0, 0.25, 1.0 / 40.0])
+    loss, grad, _ = C.loss_and_grad(th, L, g, tau, Ln, weights=w)
+    parts = [C.loss_and_grad(th, L[j], g[j], tau[j], Ln[j]) for j in range(3)]
+    # each single-sample loss is a mean over its own pixels (1/3 of the batch)
+    assert np.isclose(loss, sum(w[j] * parts[j][0] for j in range(3)) / 3, rtol=1e-12)
+    assert np.allclose(grad, sum(w[j] * parts[j][1] for j in range(3)) / 3, rtol=1e-10, atol=1e-18)
