@@ -24,19 +24,23 @@ HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0   # dense MFMA, MI355X
 # hidden 32 -> 32 convolution of the surrogate: 2 * 32 * 32 * 9 FLOP per pixel
 CONV_FLOP_PER_PX = 2 * 32 * 32 * 9
-# The dominant kernels run one level of the scale space: conductivity and
-# AOS step (aos_reduce computes g and reduces every chunk, aos_iface solves
-# the interface systems, aos_recover recovers the chunks and averages).
-# Algorithmic HBM bytes per pixel and level: conductivity reads L_{i-1} and
-# writes g (8), the AOS step reads L_{i-1} and g and writes L_i (12).
-LEVEL_ALGO_BYTES_PER_PX = 20
+# The dominant work is the level segment of a run: 15 levels of conductivity
+# and AOS step (aos_reduce computes g and reduces every chunk, aos_iface
+# solves the interface systems, aos_recover recovers the chunks and
+# averages), with the detector response of each of the 16 levels running on
+# a second stream beside the later steps.  Algorithmic HBM bytes per pixel:
+# conductivity reads L_{i-1} and writes g (8), the AOS step reads L_{i-1}
+# and g and writes L_i (12), the detector reads L_i and writes det_i (8).
+STEP_ALGO_BYTES_PER_PX = 20
+DET_ALGO_BYTES_PER_PX = 8
 AOS_KERNELS = ("aos_reduce", "aos_iface", "aos_recover")
 
 
-def traffic_from_profile(W, H, aos_tile):
-    """HBM bytes per level (conductivity + AOS step) from the committed
-    counter summary, if it was taken on the current per-level kernel sources
-    with the same tile shape."""
+def traffic_from_profile(W, H, aos_tile, with_det):
+    """HBM bytes per step of the level segment from the committed counter
+    summary, if it was taken on the current per-level kernel sources with the
+    same tile shape (the detector's share only where it runs in the
+    segment)."""
     from paper_1706_06750_amd.rocprof_summary import csrc_hash
     path = os.path.join(ROOT, "profiles", "level_traffic_%dx%d.json" % (W, H))
     if not os.path.exists(path):
@@ -45,7 +49,10 @@ def traffic_from_profile(W, H, aos_tile):
         d = json.load(fh)
     if d.get("csrc_hash") != csrc_hash(ROOT) or d.get("aos_tile") != aos_tile:
         return None
-    return round(d.get("bytes_per_level"))
+    b = d["bytes_per_level"]
+    if not with_det:
+        b -= d["kernels"]["det_kernel"]["bytes"]
+    return round(b)
 
 
 CPU_BASELINE_SRC = r"""
@@ -78,11 +85,15 @@ def cpu_baseline(W, H, seed):
                       "%.1f s" % (W, H, seed, r["seconds"])}
 
 
-def level_roofline(level_us, px, traffic):
-    algo = LEVEL_ALGO_BYTES_PER_PX * px
+def level_roofline(level_us, px, traffic, levels=16, with_det=True):
+    """Per step of the level segment (its time / (levels - 1)); algorithmic
+    bytes of the segment spread over the steps."""
+    seg = (levels - 1) * STEP_ALGO_BYTES_PER_PX + (levels * DET_ALGO_BYTES_PER_PX if with_det else 0)
+    algo = seg * px / (levels - 1)
     achieved = algo / (level_us * 1e-6) / 1e9
     return {
-        "kernel": "one level (conductivity + AOS step) = " + "+".join(AOS_KERNELS),
+        "kernel": "one level of the level segment: conductivity + AOS step (" +
+                  "+".join(AOS_KERNELS) + ")" + (" with det_kernel overlapped" if with_det else ""),
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
@@ -211,7 +222,9 @@ def bench_single(args, K, torch, kaze_image, case):
     torch.cuda.synchronize()
     elapsed, level_us = timed_graph_runs(args, K, torch, kb)
     roof = level_roofline(level_us, W * H,
-                          traffic_from_profile(W, H, "%dx%d" % K.AOS_SHAPES[kb.shape]))
+                          traffic_from_profile(W, H, "%dx%d" % K.AOS_SHAPES[kb.shape],
+                                               kb.det_in_level_segment),
+                          with_det=kb.det_in_level_segment)
     roof["timed_in"] = "the timed region (event pair around each run's AOS segment)"
     kps = int(kb.count[0].item())
     shape = K.AOS_SHAPES[kb.shape]
@@ -296,7 +309,7 @@ def bench_batch(args, K, torch, kaze_image, cases):
         kb.run()
     torch.cuda.synchronize()
     elapsed, level_us = timed_graph_runs(args, K, torch, kb)
-    roof = level_roofline(level_us, px, None)
+    roof = level_roofline(level_us, px, None, with_det=kb.det_in_level_segment)
     roof["timed_in"] = "the timed region (event pair around each run's AOS segment)"
 
     n = len(sizes)

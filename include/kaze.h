@@ -220,6 +220,15 @@ kaze_status kaze_batch_create(const kaze_image_desc* images, int n,
                               const kaze_batch_config* cfg, void* ws,
                               size_t ws_bytes, kaze_batch** out);
 
+/*
+ * Properties of a created batch: the AOS tile shape in use and whether the
+ * level segment of a graph run (the one kaze_profile_begin("aos_reduce")
+ * brackets) also holds the detector response (1: large batches, where it
+ * runs on a second stream beside the steps; 0: it runs after them).
+ */
+kaze_status kaze_batch_properties(const kaze_batch* b, int* aos_shape,
+                                  int* det_in_level_segment);
+
 /* Enqueues one run of the plan on stream: three graph launches (base image
  * and contrast factor; the AOS steps; detector response and extrema), or
  * with eager != 0 the same kernel launches issued one by one.  Runs that

@@ -30,15 +30,15 @@ struct DetGeom {
 
 template <int S>
 __global__ __launch_bounds__(kTileThreads) void det_kernel(BatchImage d0, ImgWork w, DetLevels dl,
-                                                             int N) {
+                                                             int lev0, int lev1) {
     using G = DetGeom<S>;
     extern __shared__ float smem[];
     float* sI = smem;
     float* sX = smem + G::offX;
     float* sY = smem + G::offY;
-    // levels of this launch: the ones with Scharr step S, in order
+    // levels of this launch: the ones in [lev0, lev1) with Scharr step S
     int lev = -1;
-    for (int i = 0, seen = 0; i < N; ++i)
+    for (int i = lev0, seen = 0; i < lev1; ++i)
         if (dl.step[i] == S && seen++ == (int)blockIdx.y) lev = i;
     if (lev < 0) return;  // uniform per block
     BatchImage d;
@@ -158,14 +158,15 @@ __global__ __launch_bounds__(256) void nms_kernel(BatchImage d0, ImgWork w, floa
 }
 
 template <int S>
-hipError_t launch_det_s(const BatchImage& d0, const ImgWork& w, int N, const DetLevels& dl,
-                        hipStream_t s) {
+hipError_t launch_det_s(const BatchImage& d0, const ImgWork& w, int lev0, int lev1,
+                        const DetLevels& dl, hipStream_t s) {
     int n = 0;
-    for (int i = 0; i < N; ++i) n += dl.step[i] == S;
+    for (int i = lev0; i < lev1; ++i) n += dl.step[i] == S;
     const int count = w.items ? w.count : det_tiles_of(d0.W, d0.H);
     if (n == 0 || count <= 0) return hipSuccess;
     const size_t lds = (size_t)DetGeom<S>::floats * sizeof(float);
-    hipLaunchKernelGGL(det_kernel<S>, dim3(count, n), dim3(kTileThreads), lds, s, d0, w, dl, N);
+    hipLaunchKernelGGL(det_kernel<S>, dim3(count, n), dim3(kTileThreads), lds, s, d0, w, dl, lev0,
+                       lev1);
     return hipGetLastError();
 }
 
@@ -175,11 +176,11 @@ int det_tiles_of(int W, int H) { return ((W + DTX - 1) / DTX) * ((H + DTY - 1) /
 
 int nms_blocks_of(int W, int H) { return ((W + 63) / 64) * ((H + 4 * kNmsRows - 1) / (4 * kNmsRows)); }
 
-hipError_t launch_det(const BatchImage& d0, const ImgWork& w, int N, const DetLevels& dl,
-                      hipStream_t s) {
+hipError_t launch_det(const BatchImage& d0, const ImgWork& w, int lev0, int lev1,
+                      const DetLevels& dl, hipStream_t s) {
     hipError_t e = hipSuccess;
 #define KZ_D(S) \
-    if (e == hipSuccess) e = launch_det_s<S>(d0, w, N, dl, s);
+    if (e == hipSuccess) e = launch_det_s<S>(d0, w, lev0, lev1, dl, s);
     KZ_D(1) KZ_D(2) KZ_D(3) KZ_D(4) KZ_D(5) KZ_D(6) KZ_D(7) KZ_D(8)
 #undef KZ_D
     return e;

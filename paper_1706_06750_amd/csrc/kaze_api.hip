@@ -306,9 +306,19 @@ struct kaze_batch {
     int2 *d_items = nullptr, *d_tiles = nullptr, *d_aos = nullptr, *d_lines = nullptr,
          *d_hist = nullptr, *d_det = nullptr, *d_nms = nullptr;
     int n_tiles = 0, n_aos = 0, n_lines = 0, n_hist = 0, n_det = 0, n_nms = 0;
-    // captured segments: 0 base image + k, 1 the N-1 AOS steps, 2 det + extrema
+    // captured segments: 0 base image + k, 1 the N-1 AOS steps with the
+    // detector response of each level on a forked stream, 2 extrema
     hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+    hipStream_t side = nullptr;      // fork target while a segment is captured
+    std::vector<hipEvent_t> ev;      // fork / join points (N + 1)
+    bool fork_det = false;           // detector response beside the steps
 };
+
+// A captured fork spreads a graph over several hardware queues, and every
+// dependency between queues costs about 10-25 us on this runtime (measured):
+// the detector response runs beside the steps only when each step is long
+// enough to hide that, i.e. for batches of at least this many pixels.
+constexpr double kForkDetPixels = 8e6;
 
 extern "C" kaze_status kaze_batch_destroy(kaze_batch* b);
 
@@ -384,9 +394,10 @@ kaze_status check_batch(const kaze_image_desc* im, int n, const kaze_params* p, 
 }
 
 // The a1-a7 sequence of a batch, one launch per phase for all images, in
-// three segments: 0 base image and contrast factor, 1 the AOS steps, 2
-// detector response and extrema.
-kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s) {
+// three segments: 0 base image and contrast factor, 1 the AOS steps and the
+// detector response, 2 extrema.  With a side stream the detector response
+// of each level forks off the step sequence (used while capturing).
+kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStream_t side) {
     const kaze_params* p = &B.p;
     const BatchImage b0 = batch_image(0, 0);
     if (seg == 0) {
@@ -395,25 +406,44 @@ kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s) {
         const ImgWork hist{B.d_imgs, B.d_hist, B.n_hist};
         return base_and_k(b0, images, tiles, hist, p, s);
     }
+    const ImgWork det{B.d_imgs, B.d_det, B.n_det};
+    const DetLevels dl = det_levels(B.lv);
+    const bool fork = B.fork_det && side != nullptr;
     if (seg == 1) {
+        // The detector response of level i needs level i only: with a side
+        // stream (graph capture of a large batch) it runs there, overlapping
+        // the later steps.
         const Taps tc = gauss_taps(p->sigma_cond);
         const int gmode = p->diffusivity == KAZE_G2 ? 0 : 1;
+        hipStream_t ds = fork ? side : s;
+        auto det_level = [&](int i) -> kaze_status {
+            if (!fork) return KAZE_OK;
+            {
+                KZ_HIP(hipEventRecord(B.ev[i], s));
+                KZ_HIP(hipStreamWaitEvent(ds, B.ev[i], 0));
+            }
+            KZ_LAUNCH(K_DET, ds, launch_det(b0, det, i, i + 1, dl, ds));
+            return KAZE_OK;
+        };
+        kaze_status st = det_level(0);
+        if (st != KAZE_OK) return st;
         ImageDesc a0;
         memset(&a0, 0, sizeof(a0));
         for (int i = 1; i < B.N; ++i) {
             const ImageDesc* lvl = B.d_lvl + (size_t)(i - 1) * B.n;
             const AosWork at{lvl, B.d_aos, B.n_aos};
             const AosWork al{lvl, B.d_lines, B.n_lines};
-            const kaze_status st =
-                aos_step(a0, at, al, B.shape, tc, (float)B.lv[i].tau, true, gmode, 1.f, s);
+            st = aos_step(a0, at, al, B.shape, tc, (float)B.lv[i].tau, true, gmode, 1.f, s);
             if (st != KAZE_OK) return st;
+            if ((st = det_level(i)) != KAZE_OK) return st;
+        }
+        if (fork) {  // join
+            KZ_HIP(hipEventRecord(B.ev[B.N], ds));
+            KZ_HIP(hipStreamWaitEvent(s, B.ev[B.N], 0));
         }
         return KAZE_OK;
     }
-    if (B.with_det) {
-        const ImgWork det{B.d_imgs, B.d_det, B.n_det};
-        KZ_LAUNCH(K_DET, s, launch_det(b0, det, B.N, det_levels(B.lv), s));
-    }
+    if (B.with_det && !fork) KZ_LAUNCH(K_DET, s, launch_det(b0, det, 0, B.N, dl, s));
     if (B.with_nms) {
         const ImgWork nms{B.d_imgs, B.d_nms, B.n_nms};
         KZ_LAUNCH(K_NMS, s, launch_nms(b0, nms, B.N, (float)p->det_threshold, s));
@@ -423,7 +453,7 @@ kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s) {
 
 kaze_status enqueue_batch(const kaze_batch& B, hipStream_t s) {
     for (int seg = 0; seg < 3; ++seg) {
-        const kaze_status st = enqueue_segment(B, seg, s);
+        const kaze_status st = enqueue_segment(B, seg, s, nullptr);
         if (st != KAZE_OK) return st;
     }
     return KAZE_OK;
@@ -447,6 +477,9 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
     B->shape = shape;
     B->with_det = im[0].det != nullptr;
     B->with_nms = im[0].count != nullptr;
+    double px = 0;
+    for (int j = 0; j < n; ++j) px += (double)im[j].W * im[j].H;
+    B->fork_det = B->with_det && px >= kForkDetPixels;
     B->d_imgs = reinterpret_cast<BatchImage*>(base + L.imgs);
     B->d_lvl = reinterpret_cast<ImageDesc*>(base + L.lvl);
     B->d_items = reinterpret_cast<int2*>(base + L.items);
@@ -510,14 +543,21 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
     }
     hipStream_t cs = nullptr;
     hipError_t e = hipMemcpy(base, host.data(), L.tables_end, hipMemcpyHostToDevice);
-    // capture each segment once on a private stream (default priority)
+    // capture each segment once on a private stream (default priority); the
+    // detector response forks to a second one
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking);
+    for (int i = 0; i <= B->N && e == hipSuccess; ++i) {
+        hipEvent_t ev = nullptr;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) B->ev.push_back(ev);
+    }
     for (int seg = 0; seg < 3 && e == hipSuccess && st == KAZE_OK; ++seg) {
         hipGraph_t graph = nullptr;
         g_prof.capturing = true;
         e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            st = enqueue_segment(*B, seg, cs);
+            st = enqueue_segment(*B, seg, cs, B->side);
             const hipError_t e2 = hipStreamEndCapture(cs, &graph);
             if (st == KAZE_OK && e2 != hipSuccess) e = e2;
         }
@@ -677,7 +717,7 @@ kaze_status sg_segment(const kaze_sg_scale_space& S, int seg, hipStream_t s) {
     const ImgWork none{nullptr, nullptr, 0};
     if (seg == 0) return base_and_k(S.b, none, none, none, p, s);
     if (seg == 2) {
-        if (S.with_det) KZ_LAUNCH(K_DET, s, launch_det(S.b, none, S.N, det_levels(S.lv), s));
+        if (S.with_det) KZ_LAUNCH(K_DET, s, launch_det(S.b, none, 0, S.N, det_levels(S.lv), s));
         if (S.with_nms)
             KZ_LAUNCH(K_NMS, s, launch_nms(S.b, none, S.N, (float)p->det_threshold, s));
         return KAZE_OK;
@@ -882,7 +922,7 @@ kaze_status kaze_detector_response(const float* levels, int W, int H, const kaze
     b.det = det;
     const ImgWork none{nullptr, nullptr, 0};
     hipStream_t s = static_cast<hipStream_t>(stream);
-    KZ_LAUNCH(K_DET, s, launch_det(b, none, (int)lv.size(), det_levels(lv), s));
+    KZ_LAUNCH(K_DET, s, launch_det(b, none, 0, (int)lv.size(), det_levels(lv), s));
     return KAZE_OK;
 }
 
@@ -931,6 +971,13 @@ kaze_status kaze_batch_create(const kaze_image_desc* images, int n, const kaze_p
     return batch_create(images, n, p, shape, ws, ws_bytes, out);
 }
 
+kaze_status kaze_batch_properties(const kaze_batch* b, int* aos_shape, int* det_in_level_segment) {
+    if (!b) return fail(KAZE_ERR_INVALID_ARG, "batch is NULL");
+    if (aos_shape) *aos_shape = b->shape;
+    if (det_in_level_segment) *det_in_level_segment = b->fork_det ? 1 : 0;
+    return KAZE_OK;
+}
+
 kaze_status kaze_batch_run(kaze_batch* b, int eager, void* stream) {
     if (!b) return fail(KAZE_ERR_INVALID_ARG, "batch is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -942,6 +989,8 @@ kaze_status kaze_batch_destroy(kaze_batch* b) {
     if (!b) return KAZE_OK;
     for (hipGraphExec_t& x : b->exec)
         if (x) (void)hipGraphExecDestroy(x);
+    for (hipEvent_t ev : b->ev) (void)hipEventDestroy(ev);
+    if (b->side) (void)hipStreamDestroy(b->side);
     delete b;
     return KAZE_OK;
 }

@@ -271,9 +271,9 @@ hipError_t launch_aos_probe(const ImageDesc& d, const int4* rects, int nprobes, 
 hipError_t launch_probe_err(const float* L, const float* cand, int W, const int4* rects,
                             int nprobes, const float* delta, unsigned* err, hipStream_t s);
 
-// a6: det of every level (items: image, det tile of 64 x 32).
-hipError_t launch_det(const BatchImage& d0, const ImgWork& w, int N, const DetLevels& dl,
-                      hipStream_t s);
+// a6: det of the levels lev0 .. lev1-1 (items: image, det tile of 64 x 32).
+hipError_t launch_det(const BatchImage& d0, const ImgWork& w, int lev0, int lev1,
+                      const DetLevels& dl, hipStream_t s);
 int det_tiles_of(int W, int H);
 // a7: extrema of levels 1..N-2 (items: image, block of 64 x 4*kNmsRows pixels).
 hipError_t launch_nms(const BatchImage& d0, const ImgWork& w, int N, float threshold,

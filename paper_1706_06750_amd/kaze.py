@@ -30,6 +30,7 @@ EXPORTS = (
     "kaze_last_error", "kaze_profile_begin", "kaze_profile_end",
     "kaze_kernel_names", "kaze_copy_f32", "kaze_batch_workspace_bytes",
     "kaze_batch_create", "kaze_batch_run", "kaze_batch_destroy", "kaze_batch_autotune",
+    "kaze_batch_properties",
 )
 
 
@@ -99,6 +100,7 @@ def _load():
         "kaze_batch_workspace_bytes": (sz, [vp, i32, P, vp]),
         "kaze_batch_create": (i32, [vp, i32, P, vp, vp, sz, ctypes.POINTER(vp)]),
         "kaze_batch_run": (i32, [vp, i32, vp]),
+        "kaze_batch_properties": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "kaze_batch_destroy": (i32, [vp]),
         "kaze_batch_autotune": (i32, [vp, i32, P, vp, sz, i32, vp, vp, vp]),
     }
@@ -232,6 +234,13 @@ def kaze_batch_create(images, p, shape, ws, ws_bytes):
     return h
 
 
+def kaze_batch_properties(handle):
+    """(aos_shape, det_in_level_segment) of a created batch."""
+    a, d = ctypes.c_int(), ctypes.c_int()
+    _check(lib.kaze_batch_properties(handle, ctypes.byref(a), ctypes.byref(d)))
+    return a.value, bool(d.value)
+
+
 def kaze_batch_run(handle, eager=False, stream=None):
     _check(lib.kaze_batch_run(handle, 1 if eager else 0, _stream(stream)))
 
@@ -357,6 +366,7 @@ class KazeBatch:
             shape = self._tuned_shape(tune_cache)
         self.shape = int(shape)
         self.handle = kaze_batch_create(descs, self.p, self.shape, self.ws, self.ws_bytes)
+        self.det_in_level_segment = kaze_batch_properties(self.handle)[1]
 
     def _key(self):
         import hashlib

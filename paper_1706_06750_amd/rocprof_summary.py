@@ -5,10 +5,11 @@
         <write_counter_collection.csv> --image WxH --copy-mib M --out <json>
 
 ``stats`` prints the kernel-duration table.  ``traffic`` turns FETCH_SIZE and
-WRITE_SIZE (KiB per dispatch) into HBM bytes per scale-space level: each
-counter is scaled by what it reads for the library's copy kernel, which moves
-a known number of bytes (M MiB read and M MiB written), and the bytes of the
-per-level kernels are summed per dispatch.
+WRITE_SIZE (KiB per dispatch) into HBM bytes per step of the level segment:
+each counter is scaled by what it reads for the library's copy kernel, which
+moves a known number of bytes (M MiB read and M MiB written); the bytes of
+one dispatch of each AOS kernel are summed, plus those of one detector
+dispatch (one level) times 16/15 (16 detector levels per 15 steps).
 """
 from __future__ import annotations
 
@@ -19,7 +20,8 @@ import hashlib
 import json
 import os
 
-LEVEL_KERNELS = ("aos_reduce_kernel", "aos_iface_kernel", "aos_recover_kernel")
+LEVEL_KERNELS = ("aos_reduce_kernel", "aos_iface_kernel", "aos_recover_kernel", "det_kernel")
+DET_PER_STEP = 16.0 / 15.0
 
 
 def short(name: str) -> str:
@@ -42,7 +44,7 @@ def short(name: str) -> str:
 
 # Sources of the per-level kernels: a change to any of them invalidates a
 # traffic summary.
-LEVEL_SOURCES = ("aos.hip", "tile_cond.h", "kaze_internal.h")
+LEVEL_SOURCES = ("aos.hip", "tile_cond.h", "kaze_internal.h", "detect.hip")
 
 
 def csrc_hash(root: str) -> str:
@@ -82,8 +84,9 @@ def traffic(fetch_csv, write_csv, W, H, copy_mib, root, aos_tile):
     ws = known_kib / w["copy_kernel"]
     per = {}
     for k in LEVEL_KERNELS:
+        mult = DET_PER_STEP if k == "det_kernel" else 1.0
         per[k] = {"fetch_kib_raw": f[k], "write_kib_raw": w[k],
-                  "bytes": (f[k] * fs + w[k] * ws) * 1024.0}
+                  "bytes": mult * (f[k] * fs + w[k] * ws) * 1024.0}
     total = sum(v["bytes"] for v in per.values())
     return {"image": "%dx%d" % (W, H), "aos_tile": aos_tile,
             "copy_scale_fetch": fs, "copy_scale_write": ws,

@@ -115,3 +115,29 @@ def test_uneven_batch_images_vs_oracle(gpu_lib):
         assert err <= LEVEL_TOL
         assert not bad_g and not bad_o
     kb.close()
+
+
+def test_large_batch_forks_detector_and_matches_eager(gpu_lib):
+    """Above the size where the detector response runs beside the steps (a
+    second stream inside the captured graph), replays still equal the eager
+    sequence bitwise."""
+    K = gpu_lib
+    sizes = [(1920, 1200), (1800, 1100), (1700, 1000), (1600, 1200)]
+    note("[batch] large batch %s" % sizes)
+    kb, _ = make_batch(K, sizes, range(80, 84), 1)
+    assert kb.det_in_level_segment
+    kb.run(eager=True)
+    torch.cuda.synchronize()
+    ref_lv = [t.clone() for t in kb.levels]
+    ref_det = [t.clone() for t in kb.det]
+    ref_cnt = [int(c.item()) for c in kb.count]
+    for r in range(2):
+        for t in kb.det:
+            t.fill_(-1.0)
+        kb.run()
+        torch.cuda.synchronize()
+        for j in range(len(sizes)):
+            assert torch.equal(kb.levels[j], ref_lv[j]), (r, j)
+            assert torch.equal(kb.det[j], ref_det[j]), (r, j)
+            assert int(kb.count[j].item()) == ref_cnt[j], (r, j)
+    kb.close()
