@@ -42,6 +42,20 @@ design notes):
 * Extrema (Sec. II-B, the 3x3 "approximate" variant): levels 1..N-2, pixels
   1..W-2 x 1..H-2, response strictly above the threshold and strictly above
   all 26 neighbours in the 3x3x3 block; maxima only.
+* FED (Eq. 5, the scheme the paper's own GPU code runs): the step from
+  t_{i-1} to t_i (length T = tau_i) is one cycle of n explicit steps
+  L <- L + tau_j sum_l A_l(g) L with the same A_l as the AOS step and g
+  computed once from L_{i-1}.  tau_max = 1/4, the stability limit of the 2-D
+  explicit scheme with unit spacing and g <= 1; n is the smallest cycle
+  length whose total time tau_max (n^2 + n)/3 reaches T, and the Eq. 5 step
+  sizes are scaled by T over that total so the cycle ends exactly at t_i.
+  With g fixed the n step operators commute, so their order changes only
+  the rounding: in the order j = 0 .. n-1 the intermediate values of a
+  29-step cycle grow by ~1e12.  The steps are applied in the order
+  i -> kappa i mod n (the kappa-cycles of Grewenig et al. 2010), kappa
+  coprime to n and chosen to minimise the error-growth bound
+  max_k max|prod_{j<k}(1 + tau_j mu)| max|prod_{j>=k}(1 + tau_j mu)| over
+  mu in [-8, 0] on a grid of 2001 points (ties: smallest kappa).
 """
 from __future__ import annotations
 
@@ -55,7 +69,8 @@ __all__ = [
     "scharr_dx", "scharr_dy", "gradient_magnitude", "contrast_factor",
     "conductivity_g2", "conductivity_g1", "aos_line_bands", "aos_solve_rows",
     "aos_solve_cols", "aos_step", "build_scale_space", "derivative_step",
-    "detector_response", "find_extrema",
+    "detector_response", "find_extrema", "FED_TAU_MAX", "fed_step_sizes",
+    "fed_order", "diffusion_operator", "explicit_step", "fed_cycle",
 ]
 
 DEFAULTS = dict(sigma0=1.6, octaves=4, sublevels=4, sigma_cond=1.0,
@@ -225,12 +240,88 @@ def aos_step(L: np.ndarray, g: np.ndarray, tau: float) -> np.ndarray:
     return 0.5 * (aos_solve_rows(L, g, tau) + aos_solve_cols(L, g, tau))
 
 
+# --------------------------------------------------------------------------
+# FED: Eq. 5
+# --------------------------------------------------------------------------
+FED_TAU_MAX = 0.25
+
+
+def fed_step_sizes(T: float, tau_max: float = FED_TAU_MAX) -> np.ndarray:
+    """Step sizes of one FED cycle of total time T (Eq. 5, scaled to T)."""
+    if not (T > 0.0):
+        raise ValueError("T must be > 0")
+    n = 1
+    while tau_max * (n * n + n) / 3.0 < T:
+        n += 1
+    j = np.arange(n, dtype=np.float64)
+    tau = tau_max / (2.0 * np.cos(np.pi * (2.0 * j + 1.0) / (4.0 * n + 2.0)) ** 2)
+    return tau * (T / tau.sum())
+
+
+def fed_order(tau: np.ndarray) -> np.ndarray:
+    """Application order of a cycle's steps: i -> kappa i mod n (see the
+    module notes)."""
+    n = len(tau)
+    mu = np.linspace(-8.0, 0.0, 2001)
+    best, best_k = None, 1
+    for kappa in range(1, max(n, 2)):
+        if math.gcd(kappa, n) != 1:
+            continue
+        order = [(kappa * i) % n for i in range(n)]
+        pre = np.ones_like(mu)
+        prefix = [1.0]
+        for j in order:
+            pre = pre * (1.0 + tau[j] * mu)
+            prefix.append(np.abs(pre).max())
+        suf = np.ones_like(mu)
+        suffix = [1.0]
+        for j in order[::-1]:
+            suf = suf * (1.0 + tau[j] * mu)
+            suffix.append(np.abs(suf).max())
+        suffix = suffix[::-1]
+        bound = max(a * b for a, b in zip(prefix, suffix))
+        if best is None or bound < best * (1.0 - 1e-12):
+            best, best_k = bound, kappa
+    return np.array([(best_k * i) % n for i in range(n)], dtype=np.int64)
+
+
+def diffusion_operator(L: np.ndarray, g: np.ndarray) -> np.ndarray:
+    """sum_l A_l(g) L: the flux (g_j + g_k)/2 (L_k - L_j) from every
+    neighbour k along rows and columns, none across the border."""
+    L = np.asarray(L, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    out = np.zeros_like(L)
+    wx = 0.5 * (g[:, :-1] + g[:, 1:])
+    fx = wx * (L[:, 1:] - L[:, :-1])
+    out[:, :-1] += fx
+    out[:, 1:] -= fx
+    wy = 0.5 * (g[:-1, :] + g[1:, :])
+    fy = wy * (L[1:, :] - L[:-1, :])
+    out[:-1, :] += fy
+    out[1:, :] -= fy
+    return out
+
+
+def explicit_step(L: np.ndarray, g: np.ndarray, tau: float) -> np.ndarray:
+    return np.asarray(L, dtype=np.float64) + tau * diffusion_operator(L, g)
+
+
+def fed_cycle(L: np.ndarray, g: np.ndarray, T: float) -> np.ndarray:
+    """One FED cycle of total time T with the conductivity g held fixed."""
+    out = np.asarray(L, dtype=np.float64)
+    tau = fed_step_sizes(T)
+    for j in fed_order(tau):
+        out = explicit_step(out, g, tau[j])
+    return out
+
+
 def build_scale_space(img: np.ndarray, sigma0: float = 1.6, octaves: int = 4,
                       sublevels: int = 4, sigma_cond: float = 1.0,
                       k_percentile: float = 0.7, k_bins: int = 300,
                       k: float | None = None, diffusivity: str = "g2",
-                      return_g: bool = False):
-    """Nonlinear scale space (Sec. II-A, Sec. III-A).
+                      return_g: bool = False, scheme: str = "aos"):
+    """Nonlinear scale space (Sec. II-A, Sec. III-A), each level reached by
+    one AOS step (Eq. 4) or one FED cycle (Eq. 5).
 
     Returns ``(levels [N][H][W] float64, k)`` and, if ``return_g``, the
     conductivity image used by each step (``g[i]`` drives the step into level
@@ -247,7 +338,12 @@ def build_scale_space(img: np.ndarray, sigma0: float = 1.6, octaves: int = 4,
     for i in range(1, len(sched)):
         g = cond(levels[-1], k, sigma_cond)
         tau = sched[i]["t"] - sched[i - 1]["t"]
-        levels.append(aos_step(levels[-1], g, tau))
+        if scheme == "aos":
+            levels.append(aos_step(levels[-1], g, tau))
+        elif scheme == "fed":
+            levels.append(fed_cycle(levels[-1], g, tau))
+        else:
+            raise ValueError("scheme must be 'aos' or 'fed'")
         gs.append(g)
     if return_g:
         return np.stack(levels), float(k), np.stack(gs)
