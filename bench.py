@@ -22,8 +22,9 @@ sys.path.insert(0, ROOT)
 METRIC = "1920x1200 scale-space+Hessian images/s, AOS vs surrogate; % HBM peak"
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0   # dense MFMA, MI355X
-# hidden 32 -> 32 convolution of the surrogate: 2 * 32 * 32 * 9 FLOP per pixel
-CONV_FLOP_PER_PX = 2 * 32 * 32 * 9
+# the middle pair of the surrogate's layers (two 32 -> 32 convolutions in one
+# launch): 2 * 2 * 32 * 32 * 9 FLOP per pixel
+CONV_FLOP_PER_PX = 2 * 2 * 32 * 32 * 9
 # The dominant work is the level segment of a run: 15 levels of conductivity
 # and AOS step (aos_reduce computes g and reduces every chunk, aos_iface
 # solves the interface systems, aos_recover recovers the chunks and
@@ -49,10 +50,9 @@ def traffic_from_profile(W, H, aos_tile, with_det):
         d = json.load(fh)
     if d.get("csrc_hash") != csrc_hash(ROOT) or d.get("aos_tile") != aos_tile:
         return None
-    b = d["bytes_per_level"]
-    if not with_det:
-        b -= d["kernels"]["det_kernel"]["bytes"]
-    return round(b)
+    if bool(d.get("det_in_segment")) != bool(with_det):
+        return None
+    return round(d["bytes_per_level"])
 
 
 CPU_BASELINE_SRC = r"""
@@ -290,7 +290,7 @@ def bench_surrogate(args, K, torch, img, W, H, seed, plain_value):
             us = 1e3 * cms / n
             flop = CONV_FLOP_PER_PX * W * H
             tf = flop / (us * 1e-6) / 1e12
-            out["conv_roofline"] = {"kernel": "conv_kernel<32, 2, relu> (hidden layer)",
+            out["conv_roofline"] = {"kernel": "conv2_kernel<32, 2> (layers 3 and 4 fused)",
                                     "bound": "mfma", "achieved": round(tf, 1),
                                     "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                                     "frac": round(tf / BF16_PEAK_TFLOPS, 4),
@@ -322,8 +322,56 @@ def bench_batch(args, K, torch, kaze_image, cases):
               "aos_tile": "%dx%d" % K.AOS_SHAPES[kb.shape],
               "autotune_ms_per_shape": kb.tune_ms}
     extra = {"megapixels_per_s": round(px * args.steps / elapsed / 1e6, 1)}
+    plain_value = n * args.steps / elapsed
     kb.close()
-    return record(args, n * args.steps / elapsed, 1e3 * elapsed / args.steps, config, roof, extra)
+    del kb
+    torch.cuda.empty_cache()
+    if not args.no_surrogate and args.workload == "kaze_4k32_720p32":
+        extra["surrogate"] = bench_surrogate_batch(args, K, torch, kaze_image, cases, plain_value)
+    return record(args, plain_value, 1e3 * elapsed / args.steps, config, roof, extra)
+
+
+def bench_surrogate_batch(args, K, torch, kaze_image, cases, plain_value):
+    """The surrogate form over a batch: one surrogate plan per image size,
+    run once per image of the batch (default check and fallback)."""
+    from paper_1706_06750_amd import surrogate as S
+    from paper_1706_06750_amd import train_surrogate as T
+    if not os.path.exists(T.DEFAULT_OUT):
+        return {"skipped": "no trained weights"}
+    params, _ = T.load()
+    w = S.Weights(params)
+    plans = {}
+    for W, H, seed in cases:
+        if (W, H) not in plans:
+            plans[(W, H)] = S.SurrogateScaleSpace(W, H, w, probe_seed=seed, capacity=1 << 12)
+    imgs = [torch.from_numpy(kaze_image(W, H, seed)).cuda() for W, H, seed in cases]
+    accepted = 0
+
+    def one_pass():
+        nonlocal accepted
+        for (W, H, _), img in zip(cases, imgs):
+            ss = plans[(W, H)]
+            ss.img.copy_(img)
+            ss.run()
+        accepted = sum(int(sum(p.accepted())) for p in plans.values())
+
+    one_pass()
+    torch.cuda.synchronize()
+    steps = max(1, args.steps // 5)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_pass()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    val = len(cases) * steps / el
+    out = {"plans": ["%dx%d" % k for k in plans], "images_per_s": round(val, 3),
+           "levels_accepted_in_last_images": accepted,
+           "speedup_vs_plain_batched": round(val / plain_value, 4),
+           "note": "input copy and one graph run per image; the plain batched path is one graph "
+                   "for all images"}
+    for p in plans.values():
+        p.close()
+    return out
 
 
 if __name__ == "__main__":

@@ -684,6 +684,34 @@ namespace {
 kaze_status sg_chain(const kaze_sg_scale_space& S, const sg::Geo& geo, int i, const float* Lp,
                      float* Li, const int* items, int nitems, const float* gate, hipStream_t s) {
     const sg::PackLayout P = sg::pack_layout();
+    if (!items) {  // whole image: three fused pairs of layers
+        sg::bf16* buf[3] = {S.x0, S.xa, S.xb};
+        for (int pr = 0; pr < 3; ++pr) {
+            sg::Conv2Args c;
+            memset(&c, 0, sizeof(c));
+            const int la = 2 * pr, lb = la + 1;
+            c.in = buf[pr];
+            c.wa = reinterpret_cast<const sg::bf16x8*>(S.packed + P.fwd[la]);
+            c.ba = reinterpret_cast<const float*>(S.packed + P.bias[la]);
+            c.wb = reinterpret_cast<const sg::bf16x8*>(S.packed + P.fwd[lb]);
+            c.bb = reinterpret_cast<const float*>(S.packed + P.bias[lb]);
+            c.gate = gate;
+            c.bound = S.bound;
+            if (pr == 0) {
+                c.tauw = reinterpret_cast<const float*>(S.packed + P.tauw);
+                c.tau = S.tau + i;
+            }
+            if (pr < 2) {
+                c.out = buf[pr + 1];
+            } else {
+                c.fout = Li;
+                c.base = Lp;
+            }
+            KZ_LAUNCH(pr == 0 ? K_SG_CONV1 : (pr == 1 ? K_SG_CONV : K_SG_CONV6), s,
+                      sg::launch_conv2(pr == 0 ? 8 : 32, pr < 2 ? 2 : 1, c, geo, s));
+        }
+        return KAZE_OK;
+    }
     sg::bf16* buf[sg::kLayers] = {S.x0, S.xa, S.xb, S.xa, S.xb, S.xa};
     for (int l = 0; l < sg::kLayers; ++l) {
         sg::ConvArgs a;

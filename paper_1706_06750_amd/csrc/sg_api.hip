@@ -128,6 +128,29 @@ kaze_status forward(const kaze_sg_plan* p, const unsigned char* pk, const float*
     const PackLayout P = pack_layout();
     const Geo& g = p->g;
     SG_HIP(launch_pack_input(L, gc, tau, p->x[0], p->training ? p->xp[0] : nullptr, g, s));
+    if (!p->training) {  // three fused pairs of layers
+        for (int pr = 0; pr < 3; ++pr) {
+            Conv2Args c = {};
+            const int la = 2 * pr, lb = la + 1;
+            c.in = p->x[pr];
+            c.wa = reinterpret_cast<const bf16x8*>(pk + P.fwd[la]);
+            c.ba = reinterpret_cast<const float*>(pk + P.bias[la]);
+            c.wb = reinterpret_cast<const bf16x8*>(pk + P.fwd[lb]);
+            c.bb = reinterpret_cast<const float*>(pk + P.bias[lb]);
+            if (pr == 0) {
+                c.tauw = reinterpret_cast<const float*>(pk + P.tauw);
+                c.tau = tau;
+            }
+            if (pr < 2) {
+                c.out = p->x[pr + 1];
+            } else {
+                c.fout = fout;
+                c.base = base;
+            }
+            SG_HIP(launch_conv2(pr == 0 ? 8 : 32, pr < 2 ? 2 : 1, c, g, s));
+        }
+        return KAZE_OK;
+    }
     for (int l = 0; l < kLayers; ++l) {
         ConvArgs a = {};
         a.in = p->x[l];

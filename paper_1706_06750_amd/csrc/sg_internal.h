@@ -88,6 +88,27 @@ struct ConvArgs {
 
 hipError_t launch_conv(int cin, int mb, int epi, bool tau_term, const ConvArgs& a,
                        const Geo& g, hipStream_t s);
+
+// Two consecutive layers in one pass (inference, whole image): layer a
+// CINA -> 32 with ReLU (CINA = 8: layer 1 with the tau plane), then layer b
+// 32 -> 32 with ReLU (MBB = 2) or 32 -> 1 output (MBB = 1).  Layer a's
+// output stays on chip; results equal two conv_kernel launches bitwise.
+struct Conv2Args {
+    const bf16* in;       // NHWC padded input of layer a, CINA channels
+    const bf16x8* wa;     // layer a fragments [2][KSA][64]
+    const float* ba;      // layer a bias [32]
+    const float* tauw;    // layer 1: FP32 [32][9] tau tap weights
+    const float* tau;     // layer 1: step sizes [n]
+    const bf16x8* wb;     // layer b fragments [MBB][9][64]
+    const float* bb;      // layer b bias [32]
+    bf16* out;            // MBB == 2: NHWC padded output, 32 channels
+    float* fout;          // MBB == 1: [n][H][W] output
+    const float* base;    // MBB == 1: added to f, or NULL
+    const float* gate;    // optional: run only if *gate <= bound
+    float bound;
+};
+
+hipError_t launch_conv2(int cina, int mbb, const Conv2Args& a, const Geo& g, hipStream_t s);
 hipError_t launch_pack_input(const float* L, const float* gc, const float* tau, bf16* x0,
                              bf16* x0p, const Geo& g, hipStream_t s);
 hipError_t launch_loss(const float* f, const float* L, const float* Ln, const float* wts, bf16* dz6,

@@ -229,6 +229,233 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a, Geo g) {
     }
 }
 
+// ------------------------------------------------- two layers in one pass
+// Inference: layer a (CINA -> 32, ReLU) and layer b (32 -> 32 with ReLU, or
+// 32 -> 1 output) over a strip of kPairOut output columns and R rows, with
+// layer a's output kept on chip.  Waves 0-7 ("A") compute layer a on the
+// kPairMid columns [x0 - 8, x0 + 120), one 16-column block each, into a ring
+// of 4 rows in LDS; positions outside the image are stored as zero, which is
+// layer b's zero padding.  Waves 8-11 ("B") compute layer b on 7 blocks of
+// 16 columns from that ring.  At step t the A waves produce row y0 - 1 + t
+// and the B waves output row y0 + t - 3 from the rows produced at steps
+// t-3 .. t-1, so one barrier per step separates writers and readers.  Every
+// value is computed by the same MFMA sequence as in conv_kernel, so the
+// results are bitwise those of two conv_kernel launches.
+
+constexpr int kPairOut = 112;           // output columns per block
+constexpr int kPairMid = 128;           // layer-a columns per block (8 blocks)
+constexpr int kPairPix = 40;            // LDS pitch of one pixel in BF16 (80 B)
+constexpr int kPairThreads = 768;       // 8 A waves + 4 B waves
+
+template <int CINA, int MBB, bool TAU>
+__global__ __launch_bounds__(kPairThreads) void conv2_kernel(Conv2Args a, Geo g) {
+    constexpr int KSA = CINA == 32 ? 9 : 3;
+    if (a.gate && !(*a.gate <= a.bound)) return;  // whole grid
+    __shared__ __align__(16) bf16 ring[4][kPairMid * kPairPix];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int j = lane & 15, q = lane >> 4;
+    const int s = blockIdx.y;
+    const int strip = (int)blockIdx.x % g.strips, chunk = (int)blockIdx.x / g.strips;
+    const int x0 = strip * kPairOut, y0 = chunk * g.R, y1 = min(g.H, y0 + g.R);
+    const int steps = (y1 - y0) + 3;
+
+    if (wv < 8) {
+        // ---------------------------------------------------------- A waves
+        const int xm = x0 - 8 + 16 * wv + j;  // this lane's layer-a column
+        const bool colok = xm >= 0 && xm < g.W;
+        const int xl = min(max(xm, 0), g.W - 1);
+        bf16x8 wf[2][KSA];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int k = 0; k < KSA; ++k) wf[mb][k] = a.wa[(mb * KSA + k) * 64 + lane];
+        float bias[2][4];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) bias[mb][r] = a.ba[16 * mb + 4 * q + r];
+        float tcs[2][4][3];
+        if constexpr (TAU) {
+            const float taup = a.tau[s] / kTauRef;
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int ty = 0; ty < 3; ++ty) {
+                        const int co = 16 * mb + 4 * q + r;
+                        float t = 0.f;
+#pragma unroll
+                        for (int tx = 0; tx < 3; ++tx) {
+                            const int xx = xm + tx - 1;
+                            if (xx >= 0 && xx < g.W) t += a.tauw[co * 9 + ty * 3 + tx];
+                        }
+                        tcs[mb][r][ty] = taup * t;
+                    }
+        }
+        const bf16* col = a.in + ((size_t)s * g.sx + xl) * CINA;
+        const size_t rowstride = (size_t)g.pw * CINA;
+        bf16* mid = &ring[0][0] + (16 * wv + j) * kPairPix;  // + slot * kPairMid * kPairPix
+
+        // stores layer a's row ya (zero outside the image) into ring slot sl
+        auto store_row = [&](int sl, int ya, const f32x4 (&acc)[2]) {
+            const bool ok = colok && ya >= 0 && ya < g.H;
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) {
+                float v[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float z = acc[mb][r] + bias[mb][r];
+                    if constexpr (TAU) {
+                        z += tcs[mb][r][1];
+                        if (ya >= 1) z += tcs[mb][r][0];
+                        if (ya + 1 < g.H) z += tcs[mb][r][2];
+                    }
+                    z = z > 0.f ? z : 0.f;
+                    v[r] = ok ? z : 0.f;
+                }
+                const bf16x4 o = {(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
+                *reinterpret_cast<bf16x4*>(mid + sl * kPairMid * kPairPix + 16 * mb + 4 * q) = o;
+            }
+        };
+
+        if constexpr (CINA == 32) {
+            const bf16* cq = col + 8 * q;
+#define KZ_LOADROW(R, yp)                                                 \
+    {                                                                     \
+        const int yp_ = (yp);                                             \
+        if (yp_ >= 0 && yp_ <= g.H + 1) {                                 \
+            const bf16* p_ = cq + (size_t)yp_ * rowstride;                \
+            R[0] = ld8(p_);                                               \
+            R[1] = ld8(p_ + CINA);                                        \
+            R[2] = ld8(p_ + 2 * CINA);                                    \
+        }                                                                 \
+    }
+            // layer-a row ya reads padded rows ya, ya+1, ya+2; the ring holds
+            // them with row ya+3 loaded one step ahead
+#define KZ_ASTEP(tt, RA, RB, RC, RD)                                                          \
+    {                                                                                         \
+        const int ya_ = y0 - 1 + (tt);                                                        \
+        if ((tt) < steps) {                                                                   \
+            if ((tt) <= steps - 3) KZ_LOADROW(RD, ya_ + 3)                                    \
+            f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};           \
+            if (ya_ >= 0 && ya_ < g.H && (tt) <= steps - 2) {                                 \
+                _Pragma("unroll") for (int dx = 0; dx < 3; ++dx)                              \
+                    _Pragma("unroll") for (int mb = 0; mb < 2; ++mb)                          \
+                        acc[mb] = mfma(wf[mb][dx], RA[dx], acc[mb]);                          \
+                _Pragma("unroll") for (int dx = 0; dx < 3; ++dx)                              \
+                    _Pragma("unroll") for (int mb = 0; mb < 2; ++mb)                          \
+                        acc[mb] = mfma(wf[mb][3 + dx], RB[dx], acc[mb]);                      \
+                _Pragma("unroll") for (int dx = 0; dx < 3; ++dx)                              \
+                    _Pragma("unroll") for (int mb = 0; mb < 2; ++mb)                          \
+                        acc[mb] = mfma(wf[mb][6 + dx], RC[dx], acc[mb]);                      \
+            }                                                                                 \
+            if ((tt) <= steps - 2) store_row((tt) & 3, ya_, acc);                             \
+            __syncthreads();                                                                  \
+        }                                                                                     \
+    }
+            bf16x8 ra[3], rb[3], rc[3], rd[3];
+            KZ_LOADROW(ra, y0 - 1)
+            KZ_LOADROW(rb, y0)
+            KZ_LOADROW(rc, y0 + 1)
+            for (int t = 0; t < steps; t += 4) {
+                KZ_ASTEP(t, ra, rb, rc, rd)
+                KZ_ASTEP(t + 1, rb, rc, rd, ra)
+                KZ_ASTEP(t + 2, rc, rd, ra, rb)
+                KZ_ASTEP(t + 3, rd, ra, rb, rc)
+            }
+#undef KZ_ASTEP
+#undef KZ_LOADROW
+        } else {
+            for (int t = 0; t < steps; ++t) {
+                const int ya = y0 - 1 + t;
+                if (t <= steps - 2) {
+                    f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+                    if (ya >= 0 && ya < g.H) {
+                        bf16x8 b[KSA];
+#pragma unroll
+                        for (int k = 0; k < KSA; ++k) {
+                            const int tp = 4 * k + q;
+                            b[k] = tp < 9 ? ld8(col + (size_t)(ya + tp / 3) * rowstride + (tp % 3) * CINA)
+                                          : zero8();
+                        }
+#pragma unroll
+                        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                            for (int k = 0; k < KSA; ++k) acc[mb] = mfma(wf[mb][k], b[k], acc[mb]);
+                    }
+                    store_row(t & 3, ya, acc);
+                }
+                __syncthreads();
+            }
+        }
+    } else {
+        // ---------------------------------------------------------- B waves
+        const int bw = wv - 8;  // output blocks 2 bw, 2 bw + 1 (block 7 does not exist)
+        bf16x8 wf[MBB][9];
+#pragma unroll
+        for (int mb = 0; mb < MBB; ++mb)
+#pragma unroll
+            for (int k = 0; k < 9; ++k) wf[mb][k] = a.wb[(mb * 9 + k) * 64 + lane];
+        float bias[MBB][4];
+#pragma unroll
+        for (int mb = 0; mb < MBB; ++mb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) bias[mb][r] = a.bb[16 * mb + 4 * q + r];
+        const int nblk = bw < 3 ? 2 : 1;
+        for (int t = 0; t < steps; ++t) {
+            if (t >= 3) {
+                const int yb = y0 + t - 3;
+#pragma unroll
+                for (int kb = 0; kb < 2; ++kb) {
+                    if (kb >= nblk) continue;
+                    const int k = 2 * bw + kb;
+                    const int x = x0 + 16 * k + j;
+                    f32x4 acc[MBB];
+#pragma unroll
+                    for (int mb = 0; mb < MBB; ++mb) acc[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ty = 0; ty < 3; ++ty) {
+                        const bf16* rowp = &ring[(t - 3 + ty) & 3][0] + (16 * k + j + 7) * kPairPix + 8 * q;
+                        bf16x8 bv[3];
+#pragma unroll
+                        for (int dx = 0; dx < 3; ++dx)
+                            bv[dx] = *reinterpret_cast<const bf16x8*>(rowp + dx * kPairPix);
+#pragma unroll
+                        for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                            for (int mb = 0; mb < MBB; ++mb)
+                                acc[mb] = mfma(wf[mb][3 * ty + dx], bv[dx], acc[mb]);
+                    }
+                    if (x < g.W) {
+                        if constexpr (MBB == 1) {
+                            if (q == 0) {
+                                const float f = (acc[0][0] + bias[0][0]) * kOutScale;
+                                const size_t o = ((size_t)s * g.H + yb) * g.W + x;
+                                a.fout[o] = a.base ? a.base[o] + f : f;
+                            }
+                        } else {
+                            const size_t pix = (size_t)s * g.sx + (size_t)(yb + 1) * g.pw + (x + 1);
+#pragma unroll
+                            for (int mb = 0; mb < MBB; ++mb) {
+                                float v[4];
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) {
+                                    const float z = acc[mb][r] + bias[mb][r];
+                                    v[r] = z > 0.f ? z : 0.f;
+                                }
+                                const bf16x4 o = {(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
+                                *reinterpret_cast<bf16x4*>(a.out + pix * kCh + 16 * mb + 4 * q) = o;
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // ------------------------------------------------------------ input packing
 // NHWC8: (L_hi, L_lo, L_hi, g_hi, g_lo, g_hi, 0, 0); planar (weight
 // gradient of layer 1): (L_hi, L_lo, g_hi, g_lo, tau_hi, tau_lo, 0, 0).
@@ -633,6 +860,23 @@ hipError_t launch_conv(int cin, int mb, int epi, bool tau_term, const ConvArgs& 
         hipLaunchKernelGGL((conv_kernel<32, 2, EPI_MASK, false>), grid, block, 0, s, a, g);
     else if (cin == 8 && mb == 2 && epi == EPI_MASK && !tau_term)
         hipLaunchKernelGGL((conv_kernel<8, 2, EPI_MASK, false>), grid, block, 0, s, a, g);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_conv2(int cina, int mbb, const Conv2Args& a, const Geo& g, hipStream_t s) {
+    const int strips = (g.W + kPairOut - 1) / kPairOut;
+    Geo gg = g;
+    gg.strips = strips;
+    gg.chunks = (g.H + g.R - 1) / g.R;
+    const dim3 grid(strips * gg.chunks, g.n), block(kPairThreads);
+    if (cina == 8 && mbb == 2)
+        hipLaunchKernelGGL((conv2_kernel<8, 2, true>), grid, block, 0, s, a, gg);
+    else if (cina == 32 && mbb == 2)
+        hipLaunchKernelGGL((conv2_kernel<32, 2, false>), grid, block, 0, s, a, gg);
+    else if (cina == 32 && mbb == 1)
+        hipLaunchKernelGGL((conv2_kernel<32, 1, false>), grid, block, 0, s, a, gg);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -66,29 +66,42 @@ def stats(path: str) -> str:
     return "\n".join(out)
 
 
-def counter_means(path: str, counter: str):
+def counter_means(path: str, counter: str, aos_tile: str | None = None):
+    """Mean counter value per dispatch, by kernel.  With aos_tile ("32x32")
+    only the AOS kernels instantiated for that tile shape count (the
+    autotuner runs every shape first)."""
     acc = collections.defaultdict(list)
+    tx, ty = (aos_tile.split("x") if aos_tile else (None, None))
     for r in csv.DictReader(open(path)):
         if r.get("Counter_Name", r.get("counter_name")) != counter:
             continue
-        name = r.get("Kernel_Name", r.get("kernel_name"))
-        acc[short(name).split("<")[0]].append(float(r.get("Counter_Value", r.get("value"))))
+        name = short(r.get("Kernel_Name", r.get("kernel_name")))
+        base = name.split("<")[0]
+        if aos_tile and base == "aos_reduce_kernel" and ", %s, %s," % (tx, ty) not in name:
+            continue
+        if aos_tile and base == "aos_recover_kernel" and "<%s, %s>" % (tx, ty) not in name:
+            continue
+        acc[base].append(float(r.get("Counter_Value", r.get("value"))))
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
-def traffic(fetch_csv, write_csv, W, H, copy_mib, root, aos_tile):
-    f = counter_means(fetch_csv, "FETCH_SIZE")
-    w = counter_means(write_csv, "WRITE_SIZE")
+def traffic(fetch_csv, write_csv, W, H, copy_mib, root, aos_tile, det_per_level=False):
+    """det_per_level: the detector runs once per level (large batches); else
+    its dispatches cover several levels and it is reported apart."""
+    f = counter_means(fetch_csv, "FETCH_SIZE", aos_tile)
+    w = counter_means(write_csv, "WRITE_SIZE", aos_tile)
     known_kib = copy_mib * 1024.0
     fs = known_kib / f["copy_kernel"]
     ws = known_kib / w["copy_kernel"]
     per = {}
     for k in LEVEL_KERNELS:
+        if k == "det_kernel" and not det_per_level:
+            continue
         mult = DET_PER_STEP if k == "det_kernel" else 1.0
         per[k] = {"fetch_kib_raw": f[k], "write_kib_raw": w[k],
                   "bytes": mult * (f[k] * fs + w[k] * ws) * 1024.0}
     total = sum(v["bytes"] for v in per.values())
-    return {"image": "%dx%d" % (W, H), "aos_tile": aos_tile,
+    return {"image": "%dx%d" % (W, H), "aos_tile": aos_tile, "det_in_segment": det_per_level,
             "copy_scale_fetch": fs, "copy_scale_write": ws,
             "kernels": per, "bytes_per_level": total,
             "bytes_per_pixel_level": total / (W * H), "csrc_hash": csrc_hash(root)}

@@ -122,9 +122,9 @@ def test_large_batch_forks_detector_and_matches_eager(gpu_lib):
     second stream inside the captured graph), replays still equal the eager
     sequence bitwise."""
     K = gpu_lib
-    sizes = [(1920, 1200), (1800, 1100), (1700, 1000), (1600, 1200)]
+    sizes = [(1920, 1200), (1900, 1150), (1800, 1100), (1700, 1000), (1600, 1200)]  # 10 Mpx
     note("[batch] large batch %s" % sizes)
-    kb, _ = make_batch(K, sizes, range(80, 84), 1)
+    kb, _ = make_batch(K, sizes, range(80, 85), 1)
     assert kb.det_in_level_segment
     kb.run(eager=True)
     torch.cuda.synchronize()
