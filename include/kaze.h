@@ -191,9 +191,14 @@ typedef struct {
     int* count;            /* 1 int output: extrema found, or NULL           */
 } kaze_image_desc;
 
-/* Tile shape of the row/column solves: 0 = 64x64, 1 = 64x32, 2 = 32x64,
- * 3 = 32x32 (row chunk x column chunk); -1 = default (0).  A shape fits an
- * image when W <= 64*TX and H <= 64*TY. */
+/* Number of AOS tile shapes. */
+#define KAZE_AOS_SHAPES 2
+
+/* Tile shape of the row/column solves (width x height of the blocks of the
+ * reduction and recovery launches): 0 = 60x32, 1 = 60x64; -1 = default (0).
+ * Row lines are always cut into chunks of 30 pixels and column lines into
+ * chunks of 32, so both shapes compute the same result; they differ in
+ * occupancy only.  Every shape fits every image size. */
 typedef struct {
     int aos_shape;
 } kaze_batch_config;
@@ -243,8 +248,8 @@ kaze_status kaze_batch_destroy(kaze_batch* b);
  * Autotuner: for every tile shape that fits all images, builds the plan in
  * ws (sized for the maximum), times `reps` graph launches on stream, and
  * returns the fastest shape in *best and, if ms_per_shape is not NULL, the
- * mean milliseconds per run of each of the 4 shapes (-1 where it does not
- * fit).  Synchronises the stream.
+ * mean milliseconds per run of each of the KAZE_AOS_SHAPES shapes (-1 where
+ * it does not fit).  Synchronises the stream.
  */
 kaze_status kaze_batch_autotune(const kaze_image_desc* images, int n,
                                 const kaze_params* p, void* ws, size_t ws_bytes,

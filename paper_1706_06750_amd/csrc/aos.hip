@@ -42,17 +42,27 @@ constexpr int kBlock = 256;
 // v_rcp_f32: <= 1 ulp; the pivots are >= 1 (diagonally dominant rows).
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Coupling weight tau*(g_a + g_b) between neighbours a, b of a line, zero
+// across the line end when `inside` is false.  PRE: the accessor returns g
+// already multiplied by tau.  CHECK = false: the caller guarantees the whole
+// chunk and its right neighbour lie inside the line, so no test is made.
+template <bool CHECK, bool PRE>
+__device__ __forceinline__ float coupling(bool inside, float tau, float ga, float gb) {
+    const float w = PRE ? ga + gb : tau * (ga + gb);
+    return CHECK ? (inside ? w : 0.f) : w;
+}
+
 // Chunk of M unknowns at line positions pos0 .. pos0+M-1 of a line of n
 // pixels.  Acc::g(k), Acc::L(k) give conductivity and level at chunk index
 // k in [-1, M] (the ring supplies -1 and M).  Positions past the line end
 // are identity rows (decoupled, solution 0).
-template <int M, class Acc>
+template <int M, bool CHECK = true, bool PRE = false, class Acc>
 __device__ __forceinline__ void chunk_reduce(const Acc& A, int pos0, int n, float tau, Eq& E0,
                                              Eq& E1) {
     float gm = A.g(-1), Lm = A.L(-1), g0 = A.g(0), L0 = A.L(0);
     float gp = A.g(1), Lp = A.L(1);
-    float wl = (pos0 > 0 && pos0 < n) ? tau * (gm + g0) : 0.f;
-    float wr = (pos0 < n - 1) ? tau * (g0 + gp) : 0.f;
+    float wl = coupling<true, PRE>(pos0 > 0 && pos0 < n, tau, gm, g0);
+    float wr = coupling<CHECK, PRE>(pos0 < n - 1, tau, g0, gp);
     const Eq first = aos_row(wl, wr, Lm - L0, Lp - L0);
     wl = wr;
     Lm = L0;
@@ -61,11 +71,11 @@ __device__ __forceinline__ void chunk_reduce(const Acc& A, int pos0, int n, floa
     // x_k + cp x_{k+1} = dp + ep x_0 over the interior, and
     // x_1 = al + be x_0 + P x_{M-1} accumulated along the way.
     float cp = 0.f, dp = 0.f, ep = 1.f, P = 1.f, al = 0.f, be = 0.f;
-#pragma unroll 8
+#pragma unroll
     for (int k = 1; k <= M - 2; ++k) {
         gp = A.g(k + 1);
         Lp = A.L(k + 1);
-        wr = (pos0 + k < n - 1) ? tau * (g0 + gp) : 0.f;
+        wr = coupling<CHECK, PRE>(pos0 + k < n - 1, tau, g0, gp);
         const float d = wl * (Lm - L0) + wr * (Lp - L0);
         const float r = rcp(1.f + wl + wr + wl * cp);
         dp = (d + wl * dp) * r;
@@ -81,7 +91,7 @@ __device__ __forceinline__ void chunk_reduce(const Acc& A, int pos0, int n, floa
     }
     gp = A.g(M);
     Lp = A.L(M);
-    wr = (pos0 + M - 1 < n - 1) ? tau * (g0 + gp) : 0.f;
+    wr = coupling<CHECK, PRE>(pos0 + M - 1 < n - 1, tau, g0, gp);
     const Eq last = aos_row(wl, wr, Lm - L0, Lp - L0);
     E1 = Eq{last.a * ep, last.b - last.a * cp, last.c, last.d - last.a * dp};
     E0 = Eq{first.a, first.b + first.c * be, first.c * P, first.d - first.c * al};
@@ -89,17 +99,17 @@ __device__ __forceinline__ void chunk_reduce(const Acc& A, int pos0, int n, floa
 
 // Interior of a chunk by a Thomas sweep with both ends known (z0 at k = 0,
 // z1 at k = M-1).  On return x[k] holds the increment of every element.
-template <int M, class Acc>
+template <int M, bool CHECK = true, bool PRE = false, class Acc>
 __device__ __forceinline__ void chunk_recover(const Acc& A, int pos0, int n, float tau, float z0,
                                               float z1, float (&x)[M]) {
     float cpa[M];
     float gm = A.g(0), Lm = A.L(0), g0 = A.g(1), L0 = A.L(1);
-    float wl = (pos0 + 1 < n) ? tau * (gm + g0) : 0.f;
+    float wl = coupling<CHECK, PRE>(pos0 + 1 < n, tau, gm, g0);
     float cp = 0.f, dp = 0.f;
 #pragma unroll
     for (int k = 1; k <= M - 2; ++k) {
         const float gp = A.g(k + 1), Lp = A.L(k + 1);
-        const float wr = (pos0 + k < n - 1) ? tau * (g0 + gp) : 0.f;
+        const float wr = coupling<CHECK, PRE>(pos0 + k < n - 1, tau, g0, gp);
         float d = wl * (Lm - L0) + wr * (Lp - L0);
         const float b = 1.f + wl + wr;
         float a = -wl, c = -wr;
@@ -127,185 +137,450 @@ __device__ __forceinline__ void chunk_recover(const Acc& A, int pos0, int n, flo
     for (int k = M - 2; k >= 1; --k) x[k] -= cpa[k] * x[k + 1];
 }
 
-// LDS accessor of one chunk: element k at offset k * stride (k may be -1).
-struct LineAcc {
+// LDS accessor of one chunk with compile-time strides: element k (which may
+// be -1) at gp[k * GS] and Lp[k * LS], so every access is an immediate
+// offset from the thread's base address.
+template <int GS, int LS>
+struct LdsLine {
     const float* gp;  // element 0
     const float* Lp;
-    int gs, Ls;       // strides between consecutive chunk elements
-    __device__ __forceinline__ float g(int k) const { return gp[k * gs]; }
-    __device__ __forceinline__ float L(int k) const { return Lp[k * Ls]; }
+    __device__ __forceinline__ float g(int k) const { return gp[k * GS]; }
+    __device__ __forceinline__ float L(int k) const { return Lp[k * LS]; }
 };
 
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef float vf2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) vf4 gvf4;
+typedef __attribute__((address_space(1))) vf2 gvf2;
+
 __device__ __forceinline__ void store_eqs(float* dst, const Eq& e0, const Eq& e1) {
-    float4* o = reinterpret_cast<float4*>(dst);
-    o[0] = make_float4(e0.a, e0.b, e0.c, e0.d);
-    o[1] = make_float4(e1.a, e1.b, e1.c, e1.d);
+    gvf4* o = (gvf4*)dst;
+    o[0] = vf4{e0.a, e0.b, e0.c, e0.d};
+    o[1] = vf4{e1.a, e1.b, e1.c, e1.d};
 }
 
-// Row chunks are walked by threads [0, TY), column chunks by threads
-// [128, 128 + TX): rows and columns never share a wavefront.
-constexpr int kColThread0 = 128;
+// Index i of a line of n pixels reflected half-sample symmetrically into
+// [0, n) (one reflection covers every ring used here, n >= 8), clamped for
+// positions of partial tiles far past the image, which feed no output.
+__device__ __forceinline__ int reflect_clamp(int i, int n) {
+    i = i < 0 ? -1 - i : i;
+    i = i >= n ? 2 * n - 1 - i : i;
+    return i < 0 ? 0 : i;
+}
 
-template <int RG, int TX, int TY, bool COMPUTE_G>
-__global__ __launch_bounds__(kBlock) void aos_reduce_kernel(ImageDesc d0, AosWork w, Taps tc,
-                                                            float tau, int gmode, float k_host) {
-    using G = CondGeom<RG, TX, TY>;
+// Global-memory views of the image planes: with the address space explicit
+// and the row offsets wave-uniform, a row access is one load or store with a
+// scalar base and the lane's byte offset.
+typedef __attribute__((address_space(1))) float gfloat;
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// LDS geometry of the reduction tile: kAosTX x TY pixels.  With the
+// conductivity computed here (CG) the tile holds L on a ring of RG + 2 (the
+// Gaussian of radius RG plus Scharr plus the chunk ends), the smoothed image
+// S on the tile + 2 ring (exactly one wavefront wide: kAosTX + 4 = 64) and g
+// on the tile + 1 ring; otherwise L and g on the tile + 1 ring.  The S area
+// has rows beyond the tile + 2 ring so that every wavefront's band of g rows
+// reads whole rows; they are never written and feed no stored value.
+template <int RG, int TY, bool CG>
+struct RedGeom {
+    static constexpr int WAVES = 4;
+    static constexpr int R = CG ? RG + 2 : 1;
+    static constexpr int NLY = TY + 2 * R, NLX = kAosTX + 2 * R, PL = NLX | 1;
+    static constexpr int NSY = TY + 4, PS = kWave + 1;
+    static constexpr int NGY = TY + 2, NGX = kAosTX + 2, PG = NGX | 1;
+    static constexpr int SPW = (NSY + WAVES - 1) / WAVES;  // S rows per wavefront
+    static constexpr int QPW = (NGY + WAVES - 1) / WAVES;  // g rows per wavefront
+    static constexpr int NSA = WAVES * QPW + 2;             // S rows allocated
+    static constexpr int offS = NLY * PL;
+    static constexpr int offG = offS + (CG ? NSA * PS : 0);
+    static constexpr int floats = offG + NGY * PG;
+    static_assert(kAosTX + 4 == kWave, "the smoothed band is one wavefront wide");
+    static_assert(NLX <= 2 * kWave, "two loads per L row");
+    static_assert(SPW * WAVES == NSY, "S bands tile the region");
+    static_assert(NSA >= NSY, "S area holds the region");
+};
+
+constexpr int kRedThreads = 256;
+
+// Rows [0, NY) x columns [0, NX) of src, with image origin (gy0, gx0),
+// half-sample reflected at the image border, into LDS at pitch P, each value
+// times `scale`; wavefront w loads rows w, w+4, ...; lane l loads columns l
+// and 64 + l (those below NX).  All loads of a lane are issued before its
+// first LDS store.
+template <int NY, int NX, int P>
+__device__ __forceinline__ void load_region(const float* src, int W, int H, int gy0, int gx0,
+                                            float scale, float* dst, int wave, int lane) {
+    constexpr int WAVES = kRedThreads / kWave;
+    constexpr int PER = (NY + WAVES - 1) / WAVES;
+    const gfloat* gs = (const gfloat*)src;
+    const bool has_a = lane < NX;
+    const bool has_b = lane < NX - kWave;
+    const int xa = reflect_clamp(gx0 + lane, W);
+    const int xb = reflect_clamp(gx0 + kWave + lane, W);
+    float va[PER], vb[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int r = wave + WAVES * i;
+        if (r < NY) {
+            const gfloat* row = gs + (ptrdiff_t)uniform(reflect_clamp(gy0 + r, H)) * W;
+            va[i] = has_a ? row[xa] : 0.f;
+            vb[i] = has_b ? row[xb] : 0.f;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int r = wave + WAVES * i;
+        if (r < NY) {
+            if (has_a) dst[r * P + lane] = scale * va[i];
+            if (has_b) dst[r * P + kWave + lane] = scale * vb[i];
+        }
+    }
+}
+
+// Perona-Malik conductivity (Eq. 3) as a compile-time choice: GM 0 g2,
+// GM 1 g1; m2 is the squared gradient magnitude times 1/k^2.
+template <int GM>
+__device__ __forceinline__ float diffusivity_of(float m2k) {
+    return GM == 0 ? __builtin_amdgcn_rcpf(1.f + m2k) : expf(-m2k);
+}
+
+// Phases 2-3 of the reduction with the conductivity: S = Gaussian of L on
+// the tile + 2 ring (one lane per column; each wavefront a band of rows;
+// the horizontal pass is recomputed along the band in registers, the
+// vertical pass rolls over it), then the 3x3 Scharr gradient of S and g on
+// the tile + 1 ring: tau * g into LDS for the sweeps, g (tile interior) to
+// gout for the recovery.
+template <int RG, int TY, int GM>
+__device__ __forceinline__ void tile_conductivity(const float* sL, float* sS, float* sG,
+                                                  const Taps& tc, float inv_k2, float tau,
+                                                  float* gout, int W, int H, int tx0, int ty0,
+                                                  int wave, int lane) {
+    using G = RedGeom<RG, TY, true>;
+    constexpr int r = RG, T = 2 * RG + 1;
+    float w[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) w[t] = tc.w[t];
+    {
+        const int s0 = wave * G::SPW;
+        float h[G::SPW + 2 * r];
+        const float* lp = sL + s0 * G::PL + lane;
+#pragma unroll
+        for (int k = 0; k < G::SPW + 2 * r; ++k) {
+            const float* q = lp + k * G::PL;
+            float acc = w[r] * q[r];
+#pragma unroll
+            for (int t = 0; t < r; ++t) acc += w[t] * (q[t] + q[2 * r - t]);
+            h[k] = acc;
+        }
+        float* sp = sS + s0 * G::PS + lane;
+#pragma unroll
+        for (int k = 0; k < G::SPW; ++k) {
+            float acc = w[r] * h[k + r];
+#pragma unroll
+            for (int t = 0; t < r; ++t) acc += w[t] * (h[k + t] + h[k + 2 * r - t]);
+            sp[k * G::PS] = acc;
+        }
+    }
+    __syncthreads();
+    // g rows [q0, q0 + QPW): g(q, i) from S rows q..q+2, columns i..i+2.
+    // Unscaled Scharr: Lx' = 32 Lx, Ly' = 32 Ly, so |grad|^2 = m2' / 1024.
+    {
+        const int q0 = wave * G::QPW;
+        const int ic = lane < G::NGX ? lane : G::NGX - 1;
+        const float c2 = inv_k2 * (1.f / 1024.f);
+        const float* sp = sS + q0 * G::PS + ic;
+        float D[G::QPW + 2], Tt[G::QPW + 2];
+#pragma unroll
+        for (int k = 0; k < G::QPW + 2; ++k) {
+            const float a = sp[k * G::PS], b = sp[k * G::PS + 1], c = sp[k * G::PS + 2];
+            D[k] = c - a;
+            Tt[k] = 3.f * (a + c) + 10.f * b;
+        }
+        const bool lane_g = lane < G::NGX;
+        const bool col_in = lane >= 1 && lane <= kAosTX && tx0 - 1 + lane < W;
+        float* gl = sG + q0 * G::PG + lane;
+        gfloat* grow = (gfloat*)gout + (ptrdiff_t)uniform(ty0 - 1 + q0) * W + (tx0 - 1);
+#pragma unroll
+        for (int k = 0; k < G::QPW; ++k) {
+            const float lx = 3.f * (D[k] + D[k + 2]) + 10.f * D[k + 1];
+            const float ly = Tt[k + 2] - Tt[k];
+            const float gv = diffusivity_of<GM>((lx * lx + ly * ly) * c2);
+            const int q = q0 + k;
+            if (q < G::NGY) {
+                if (lane_g) gl[k * G::PG] = tau * gv;
+                if (q >= 1 && q <= TY && ty0 - 1 + q < H && col_in)
+                    grow[(ptrdiff_t)k * W + lane] = gv;
+            }
+        }
+    }
+}
+
+// Reduction: one block of 256 threads per tile of kAosTX x TY pixels.
+// Every tile row holds two row chunks (kRowChunk each), every tile column
+// TY / kColChunk column chunks; the row chunks are walked by the lanes of
+// TY / 32 wavefronts (lane = 32 * half + row), the column chunks by as many
+// wavefronts (lane = column), so every sweep runs on full wavefronts.  The
+// LDS copy of g is pre-multiplied by tau.
+template <int RG, int TY, bool CG, int GM>
+__global__ __launch_bounds__(kRedThreads) void aos_reduce_kernel(ImageDesc d0, AosWork w, Taps tc,
+                                                                 float tau, float k_host) {
+    using G = RedGeom<RG, TY, CG>;
     extern __shared__ float smem[];
     float* sL = smem;
     float* sS = smem + G::offS;
     float* sG = smem + G::offG;
-    const int tid = threadIdx.x;
-    const int t = blockIdx.x;
-    // one block per work item: a grid-stride loop here was measured to
-    // double the register demand (spills) without saving launches
-    ImageDesc d;
-    int lt;
-    resolve(d0, w, xcd_contiguous(t, (int)gridDim.x), d, lt);
-    if (d.gate && *d.gate <= d.bound) return;  // whole block
-    const int W = d.W, H = d.H;
-    const int cx = lt % d.ncx, cy = lt / d.ncx;
-    const int tx0 = cx * TX, ty0 = cy * TY;
-
-    load_L_ring<G>(d.L, W, H, tx0, ty0, sL);
-    if (COMPUTE_G) {
-        __syncthreads();
-        smooth_tile<G>(sL, sS, tc);
-        __syncthreads();
-        const float k = d.k ? d.k[0] : k_host;
-        const float inv_k2 = 1.f / (k * k);
-        float* gout = d.g;
-        scharr_pass<G>(sS, [&](int gy, int gx, float m2) {
-            const float gval = diffusivity(m2, inv_k2, gmode);
-            sG[gy * G::pG + gx] = gval;
-            const int y = ty0 - 1 + gy, x = tx0 - 1 + gx;
-            if (gy >= 1 && gy <= TY && gx >= 1 && gx <= TX && y < H && x < W)
-                gout[(size_t)y * W + x] = gval;
-        });
-    } else {
-        stage_region<G::nGy, G::nGx, G::pG, kBlock>(d.g, W, H, ty0 - 1, tx0 - 1, sG);
-    }
-    __syncthreads();
-
-    Eq e0, e1;
-    if (tid < TY) {
-        const int y = ty0 + tid;
-        if (y < H) {
-            const LineAcc A{sG + (tid + 1) * G::pG + 1, sL + (tid + G::R) * G::pL + G::R, 1, 1};
-            chunk_reduce<TX>(A, tx0, W, tau, e0, e1);
-            store_eqs(d.rrow + ((size_t)y * d.ncx + cx) * 8, e0, e1);
-        }
-    } else if (tid >= kColThread0 && tid < kColThread0 + TX) {
-        const int c = tid - kColThread0, x = tx0 + c;
-        if (x < W) {
-            const LineAcc A{sG + G::pG + (c + 1), sL + G::R * G::pL + (c + G::R), G::pG, G::pL};
-            chunk_reduce<TY>(A, ty0, H, tau, e0, e1);
-            store_eqs(d.rcol + ((size_t)x * d.ncy + cy) * 8, e0, e1);
-        }
-    }
-}
-
-// One wavefront per line; lane p holds chunk p's two interface equations.
-__global__ __launch_bounds__(kBlock) void aos_iface_kernel(ImageDesc d0, AosWork w, int count) {
-    const int lane = threadIdx.x % kWave;
-    const int waves = kBlock / kWave;
-    for (int t = blockIdx.x * waves + threadIdx.x / kWave; t < count; t += gridDim.x * waves) {
-        ImageDesc d;
-        int line;
-        resolve(d0, w, t, d, line);
-        if (d.gate && *d.gate <= d.bound) continue;  // whole wavefront
-        const float* R;
-        float* Z;
-        int nch;
-        if (line < d.H) {
-            nch = d.ncx;
-            R = d.rrow + (size_t)line * nch * 8;
-            Z = d.zrow + (size_t)line * nch * 2;
-        } else {
-            nch = d.ncy;
-            R = d.rcol + (size_t)(line - d.H) * nch * 8;
-            Z = d.zcol + (size_t)(line - d.H) * nch * 2;
-        }
-        Eq e0 = eq_identity(), e1 = eq_identity();
-        if (lane < nch) {
-            const float4* r = reinterpret_cast<const float4*>(R + lane * 8);
-            const float4 a = r[0], b = r[1];
-            e0 = Eq{a.x, a.y, a.z, a.w};
-            e1 = Eq{b.x, b.y, b.z, b.w};
-        }
-        float z0, z1;
-        wave_pcr_pairs(e0, e1, lane, z0, z1);
-        if (lane < nch) reinterpret_cast<float2*>(Z + lane * 2)[0] = make_float2(z0, z1);
-    }
-}
-
-// Row chunks: threads [0, TY); column chunks: threads [64, 64 + TX).
-constexpr int kRecoverThreads = 128;
-
-template <int TX, int TY>
-__global__ __launch_bounds__(kRecoverThreads) void aos_recover_kernel(ImageDesc d0, AosWork w,
-                                                                      float tau) {
-    constexpr int P = TX + 1;
-    __shared__ float sL[TY * P];
-    __shared__ float sG[TY * P];
-    __shared__ float sD[TY * P];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, wave = uniform(tid >> 6), lane = tid & (kWave - 1);
     ImageDesc d;
     int lt;
     resolve(d0, w, xcd_contiguous((int)blockIdx.x, (int)gridDim.x), d, lt);
     if (d.gate && *d.gate <= d.bound) return;  // whole block
     const int W = d.W, H = d.H;
-    const int cx = lt % d.ncx, cy = lt / d.ncx;
-    const int tx0 = cx * TX, ty0 = cy * TY;
-    const bool full = ty0 + TY <= H && tx0 + TX <= W;
+    const int ntx = (W + kAosTX - 1) / kAosTX;
+    const int cx = lt % ntx, cy = lt / ntx;
+    const int tx0 = cx * kAosTX, ty0 = cy * TY;
 
-    // stage L and g (zero outside the image) in two halves, all loads of a
-    // half in flight together
+    load_region<G::NLY, G::NLX, G::PL>(d.L, W, H, ty0 - G::R, tx0 - G::R, 1.f, sL, wave, lane);
+    if constexpr (!CG)
+        load_region<G::NGY, G::NGX, G::PG>(d.g, W, H, ty0 - 1, tx0 - 1, tau, sG, wave, lane);
+    __syncthreads();
+    if constexpr (CG) {
+        const float k = d.k ? d.k[0] : k_host;
+        tile_conductivity<RG, TY, GM>(sL, sS, sG, tc, 1.f / (k * k), tau, d.g, W, H, tx0, ty0,
+                                      wave, lane);
+        __syncthreads();
+    }
+
+    constexpr int SW = TY / 32;  // sweep wavefronts per direction
+    Eq e0, e1;
+    if (wave < SW) {
+        const int r = wave * 32 + (lane & 31), h = lane >> 5;
+        const int y = ty0 + r, pos0 = tx0 + h * kRowChunk;
+        if (y < H && pos0 < W) {
+            const LdsLine<1, 1> A{sG + (r + 1) * G::PG + 1 + h * kRowChunk,
+                                  sL + (r + G::R) * G::PL + G::R + h * kRowChunk};
+            if (tx0 + kAosTX < W)  // both chunks and their right neighbours inside
+                chunk_reduce<kRowChunk, false, true>(A, pos0, W, 1.f, e0, e1);
+            else
+                chunk_reduce<kRowChunk, true, true>(A, pos0, W, 1.f, e0, e1);
+            store_eqs(d.rrow + ((size_t)(2 * cx + h) * H + y) * 8, e0, e1);
+        }
+    } else if (wave < 2 * SW) {
+        const int v = wave - SW, c = lane;
+        const int x = tx0 + c, pos0 = ty0 + v * kColChunk;
+        if (c < kAosTX && x < W && pos0 < H) {
+            const LdsLine<G::PG, G::PL> A{sG + (v * kColChunk + 1) * G::PG + 1 + c,
+                                          sL + (v * kColChunk + G::R) * G::PL + G::R + c};
+            if (pos0 + kColChunk < H)
+                chunk_reduce<kColChunk, false, true>(A, pos0, H, 1.f, e0, e1);
+            else
+                chunk_reduce<kColChunk, true, true>(A, pos0, H, 1.f, e0, e1);
+            store_eqs(d.rcol + ((size_t)(pos0 / kColChunk) * W + x) * 8, e0, e1);
+        }
+    }
+}
+
+// PCR step with reciprocal pivots (the pivots of these diagonally
+// dominant systems are >= their off-diagonal sums).
+__device__ __forceinline__ Eq pcr_reduce_rcp(const Eq& e, const Eq& lo, const Eq& up) {
+    const float k1 = e.a * rcp(lo.b);
+    const float k2 = e.c * rcp(up.b);
+    return Eq{-k1 * lo.a, e.b - k1 * lo.c - k2 * up.a, -k2 * up.c, e.d - k1 * lo.d - k2 * up.d};
+}
+
+// PCR over segments of P lanes (P a power of two, segments aligned): lane
+// `pos` of a segment holds the two reduced equations of its part of the
+// line (e0 for its first unknown, e1 for its last); neighbours outside the
+// segment are identity rows.  Every lane of the wavefront must take part.
+__device__ __forceinline__ void seg_pcr_pairs(Eq e0, Eq e1, int lane, int pos, int P, float& z0,
+                                              float& z1) {
+    {
+        Eq prev1 = lane_read(e1, lane > 0 ? lane - 1 : 0);
+        Eq next0 = lane_read(e0, lane < kWave - 1 ? lane + 1 : kWave - 1);
+        if (pos == 0) prev1 = eq_identity();
+        if (pos == P - 1) next0 = eq_identity();
+        const Eq n0 = pcr_reduce_rcp(e0, prev1, e1);
+        const Eq n1 = pcr_reduce_rcp(e1, e0, next0);
+        e0 = n0;
+        e1 = n1;
+    }
+    for (int st = 1; st < P; st <<= 1) {
+        const bool has_lo = pos >= st, has_up = pos + st < P;
+        Eq lo0 = lane_read(e0, has_lo ? lane - st : lane);
+        Eq up0 = lane_read(e0, has_up ? lane + st : lane);
+        Eq lo1 = lane_read(e1, has_lo ? lane - st : lane);
+        Eq up1 = lane_read(e1, has_up ? lane + st : lane);
+        if (!has_lo) { lo0 = eq_identity(); lo1 = eq_identity(); }
+        if (!has_up) { up0 = eq_identity(); up1 = eq_identity(); }
+        const Eq n0 = pcr_reduce_rcp(e0, lo0, up0);
+        const Eq n1 = pcr_reduce_rcp(e1, lo1, up1);
+        e0 = n0;
+        e1 = n1;
+    }
+    z0 = e0.d * rcp(e0.b);
+    z1 = e1.d * rcp(e1.b);
+}
+
+// Interface systems.  A line of nch chunks has 2 nch unknowns (first and
+// last of every chunk) coupled by the chunks' reduced equations into one
+// tridiagonal system.  Lane `pos` of the line's P = iface_lanes(nch) lanes
+// holds chunks pos*kIfaceM .. pos*kIfaceM + kIfaceM - 1 (identity rows past
+// the line end): it reduces its 2 kIfaceM rows to two equations in its first
+// and last unknown (the same elimination as the chunk reduction), the lanes
+// of the line solve those by PCR, and each lane substitutes back through its
+// own rows, kept in registers.  All loads of a lane are issued at once.
+constexpr int kIfaceThreads = 256;
+
+__global__ __launch_bounds__(kIfaceThreads) void aos_iface_kernel(ImageDesc d0, AosWork w,
+                                                                   int count) {
+    constexpr int NR = 2 * kIfaceM;  // rows per lane
+    const int t = uniform(blockIdx.x * (kIfaceThreads / kWave) + (int)(threadIdx.x / kWave));
+    const int lane = threadIdx.x & (kWave - 1);
+    if (t >= count) return;  // whole wavefront
+    ImageDesc d;
+    int grp;
+    resolve(d0, w, t, d, grp);
+    if (d.gate && *d.gate <= d.bound) return;  // whole wavefront
+    const int rgroups = iface_groups(d.H, d.nchr);
+    const bool row = grp < rgroups;
+    const int nch = row ? d.nchr : d.nchc;
+    const int nl = row ? d.H : d.W;
+    const int P = iface_lanes(nch);
+    const int pos = lane & (P - 1);
+    const int line = (row ? grp : grp - rgroups) * (kWave / P) + lane / P;
+    const bool live = line < nl;
+    const int lc = live ? line : nl - 1;  // clamped: every lane loads in bounds
+    gfloat* R = (gfloat*)(row ? d.rrow : d.rcol) + (size_t)lc * 8;
+    gfloat* Z = (gfloat*)(row ? d.zrow : d.zcol) + (size_t)lc * 2;
+    const size_t rs = (size_t)nl * 8, zs = (size_t)nl * 2;  // chunk strides
+    const int c0 = pos * kIfaceM;
+
+    Eq e[NR];
+    {
+        vf4 va[kIfaceM], vb[kIfaceM];
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        constexpr int PER = TX * TY / (2 * kRecoverThreads);
+        for (int j = 0; j < kIfaceM; ++j) {
+            const int c = c0 + j < nch ? c0 + j : nch - 1;
+            const gvf4* q = (const gvf4*)(R + c * rs);
+            va[j] = q[0];
+            vb[j] = q[1];
+        }
+#pragma unroll
+        for (int j = 0; j < kIfaceM; ++j) {
+            const bool ok = c0 + j < nch;
+            e[2 * j] = ok ? Eq{va[j].x, va[j].y, va[j].z, va[j].w} : eq_identity();
+            e[2 * j + 1] = ok ? Eq{vb[j].x, vb[j].y, vb[j].z, vb[j].w} : eq_identity();
+        }
+    }
+    // x_k = dp_k + ep_k x_0 - cp_k x_{k+1} for the interior rows k, and
+    // x_1 = al + be x_0 + pp x_{NR-1}
+    float CP[NR], DP[NR], EP[NR];
+    float cp = 0.f, dp = 0.f, ep = 1.f, pp = 1.f, al = 0.f, be = 0.f;
+#pragma unroll
+    for (int k = 1; k <= NR - 2; ++k) {
+        const Eq& q = e[k];
+        const float r = rcp(q.b - q.a * cp);
+        dp = (q.d - q.a * dp) * r;
+        ep = -q.a * ep * r;
+        cp = q.c * r;
+        al += pp * dp;
+        be += pp * ep;
+        pp = -pp * cp;
+        CP[k] = cp;
+        DP[k] = dp;
+        EP[k] = ep;
+    }
+    const Eq& f = e[0];
+    const Eq& l = e[NR - 1];
+    const Eq E0{f.a, f.b + f.c * be, f.c * pp, f.d - f.c * al};
+    const Eq E1{l.a * ep, l.b - l.a * cp, l.c, l.d - l.a * dp};
+    float x[NR];
+    seg_pcr_pairs(E0, E1, lane, pos, P, x[0], x[NR - 1]);
+#pragma unroll
+    for (int k = NR - 2; k >= 1; --k) x[k] = DP[k] + EP[k] * x[0] - CP[k] * x[k + 1];
+#pragma unroll
+    for (int j = 0; j < kIfaceM; ++j)
+        if (live && c0 + j < nch) *(gvf2*)(Z + (c0 + j) * zs) = vf2{x[2 * j], x[2 * j + 1]};
+}
+
+// Recovery: TY / 32 row and TY / 32 column wavefronts per tile; L and
+// tau * g of the tile (zero outside the image) staged in LDS.  Both sweeps
+// keep their increments in registers; after a barrier the row lanes fold
+// theirs into the LDS copy of L (L + delta_x / 2), and after a second one
+// the column lanes store L_i = L + (delta_x + delta_y)/2 one row at a time
+// (coalesced).  Two LDS planes per tile.
+template <int TY>
+__global__ __launch_bounds__(TY * 4) void aos_recover_kernel(ImageDesc d0, AosWork w, float tau) {
+    constexpr int NT = TY * 4, WAVES = NT / kWave, SW = TY / 32, P = kAosTX + 1;
+    __shared__ float sL[TY * P];
+    __shared__ float sG[TY * P];
+    const int tid = threadIdx.x, wave = uniform(tid >> 6), lane = tid & (kWave - 1);
+    ImageDesc d;
+    int lt;
+    resolve(d0, w, xcd_contiguous((int)blockIdx.x, (int)gridDim.x), d, lt);
+    if (d.gate && *d.gate <= d.bound) return;  // whole block
+    const int W = d.W, H = d.H;
+    const int ntx = (W + kAosTX - 1) / kAosTX;
+    const int cx = lt % ntx, cy = lt / ntx;
+    const int tx0 = cx * kAosTX, ty0 = cy * TY;
+    {
+        constexpr int PER = TY / WAVES;
+        const bool in_x = lane < kAosTX && tx0 + lane < W;
+        const gfloat* Lb = (const gfloat*)d.L + (ptrdiff_t)uniform(ty0 + wave) * W + tx0;
+        const gfloat* gb = (const gfloat*)d.g + (ptrdiff_t)uniform(ty0 + wave) * W + tx0;
         float vl[PER], vg[PER];
 #pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const int i = tid + (half * PER + j) * kRecoverThreads;
-            const int y = ty0 + i / TX, x = tx0 + i % TX;
-            const bool in = full || (y < H && x < W);
-            const size_t o = in ? (size_t)y * W + x : 0;
-            vl[j] = in ? d.L[o] : 0.f;
-            vg[j] = in ? d.g[o] : 0.f;
+        for (int i = 0; i < PER; ++i) {
+            const bool in = in_x && ty0 + wave + WAVES * i < H;
+            vl[i] = in ? Lb[(ptrdiff_t)(WAVES * i) * W + lane] : 0.f;
+            vg[i] = in ? gb[(ptrdiff_t)(WAVES * i) * W + lane] : 0.f;
         }
+        if (lane < kAosTX) {
 #pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const int i = tid + (half * PER + j) * kRecoverThreads;
-            sL[(i / TX) * P + i % TX] = vl[j];
-            sG[(i / TX) * P + i % TX] = vg[j];
+            for (int i = 0; i < PER; ++i) {
+                const int r = wave + WAVES * i;
+                sL[r * P + lane] = vl[i];
+                sG[r * P + lane] = tau * vg[i];
+            }
         }
     }
     __syncthreads();
-
-    float xc[TY];
-    const int c = tid - 64;
-    const bool col_thread = tid >= 64 && c < TX && tx0 + c < W;
-    if (tid < TY && ty0 + tid < H) {
-        const int y = ty0 + tid;
-        const float2 z = reinterpret_cast<const float2*>(d.zrow + ((size_t)y * d.ncx + cx) * 2)[0];
-        float xr[TX];
-        const LineAcc A{sG + tid * P, sL + tid * P, 1, 1};
-        chunk_recover<TX>(A, tx0, W, tau, z.x, z.y, xr);
-#pragma unroll
-        for (int k = 0; k < TX; ++k) sD[tid * P + k] = xr[k];
-    } else if (col_thread) {
-        const int x = tx0 + c;
-        const float2 z = reinterpret_cast<const float2*>(d.zcol + ((size_t)x * d.ncy + cy) * 2)[0];
-        const LineAcc A{sG + c, sL + c, P, P};
-        chunk_recover<TY>(A, ty0, H, tau, z.x, z.y, xc);
+    float xs[kColChunk];  // row lanes: delta_x of the chunk; column lanes: delta_y
+    const int v = wave - SW, c = lane;
+    const int xcol = tx0 + c, pos0c = ty0 + v * kColChunk;
+    const bool col_lane = wave >= SW && c < kAosTX && xcol < W && pos0c < H;
+    const int r = wave * 32 + (lane & 31), h = lane >> 5;
+    const bool row_lane = wave < SW && ty0 + r < H && tx0 + h * kRowChunk < W;
+    if (row_lane) {
+        const int y = ty0 + r, pos0 = tx0 + h * kRowChunk;
+        const vf2 z = *(const gvf2*)((const gfloat*)d.zrow + ((size_t)(2 * cx + h) * H + y) * 2);
+        const LdsLine<1, 1> A{sG + r * P + h * kRowChunk, sL + r * P + h * kRowChunk};
+        float (&xr)[kRowChunk] = *reinterpret_cast<float (*)[kRowChunk]>(xs);
+        if (tx0 + kAosTX < W)
+            chunk_recover<kRowChunk, false, true>(A, pos0, W, 1.f, z.x, z.y, xr);
+        else
+            chunk_recover<kRowChunk, true, true>(A, pos0, W, 1.f, z.x, z.y, xr);
+    } else if (col_lane) {
+        const vf2 z = *(const gvf2*)((const gfloat*)d.zcol + ((size_t)(pos0c / kColChunk) * W + xcol) * 2);
+        const LdsLine<P, P> A{sG + v * kColChunk * P + c, sL + v * kColChunk * P + c};
+        if (pos0c + kColChunk < H)
+            chunk_recover<kColChunk, false, true>(A, pos0c, H, 1.f, z.x, z.y, xs);
+        else
+            chunk_recover<kColChunk, true, true>(A, pos0c, H, 1.f, z.x, z.y, xs);
     }
     __syncthreads();
-    if (col_thread) {
-        const int x = tx0 + c;
+    if (row_lane) {
+        float* lp = sL + r * P + h * kRowChunk;
 #pragma unroll
-        for (int k = 0; k < TY; ++k) {
-            const int y = ty0 + k;
-            if (y < H) d.Lnext[(size_t)y * W + x] = sL[k * P + c] + 0.5f * (sD[k * P + c] + xc[k]);
+        for (int k = 0; k < kRowChunk; ++k) lp[k] += 0.5f * xs[k];
+    }
+    __syncthreads();
+    if (col_lane) {
+        gfloat* ob = (gfloat*)d.Lnext + (ptrdiff_t)uniform(pos0c) * W + tx0;
+        const int rows = uniform(H - pos0c);
+#pragma unroll
+        for (int k = 0; k < kColChunk; ++k) {
+            const int rr = v * kColChunk + k;
+            if (k < rows) ob[(ptrdiff_t)k * W + c] = sL[rr * P + c] + 0.5f * xs[k];
         }
     }
 }
@@ -393,44 +668,48 @@ __global__ __launch_bounds__(kBlock) void probe_err_kernel(const float* L, const
     if (threadIdx.x == 0) atomicMax(err, __float_as_uint(red[0]));
 }
 
-int work_count(const ImageDesc& d0, const AosWork& w, int tx, int ty, bool lines) {
+int work_count(const ImageDesc& d0, const AosWork& w, int ty, bool lines) {
     if (w.items) return w.count;
-    return lines ? d0.H + d0.W : tiles_of(d0.W, d0.H, tx, ty);
+    return lines ? aos_line_groups(d0.W, d0.H) : aos_tiles_of(d0.W, d0.H, ty);
 }
 
-template <int RG, int TX, int TY>
+template <int RG, int TY, bool CG, int GM>
 hipError_t launch_reduce_t(const ImageDesc& d0, const AosWork& w, const Taps& tc, float tau,
-                           bool compute_g, int gmode, float k_host, hipStream_t s) {
-    const int count = work_count(d0, w, TX, TY, false);
+                           float k_host, hipStream_t s) {
+    const int count = work_count(d0, w, TY, false);
     if (count <= 0) return hipSuccess;
-    const size_t lds = (size_t)CondGeom<RG, TX, TY>::floats * sizeof(float);
-    if (compute_g)
-        hipLaunchKernelGGL((aos_reduce_kernel<RG, TX, TY, true>), dim3(count), dim3(kBlock), lds,
-                           s, d0, w, tc, tau, gmode, k_host);
-    else
-        hipLaunchKernelGGL((aos_reduce_kernel<RG, TX, TY, false>), dim3(count), dim3(kBlock), lds,
-                           s, d0, w, tc, tau, gmode, k_host);
+    const size_t lds = (size_t)RedGeom<RG, TY, CG>::floats * sizeof(float);
+    hipLaunchKernelGGL((aos_reduce_kernel<RG, TY, CG, GM>), dim3(count), dim3(kRedThreads), lds, s,
+                       d0, w, tc, tau, k_host);
     return hipGetLastError();
 }
 
-template <int TX, int TY>
+template <int RG, int TY>
+hipError_t launch_reduce_g(const ImageDesc& d0, const AosWork& w, const Taps& tc, float tau,
+                           int gmode, float k_host, hipStream_t s) {
+    if (gmode == 0) return launch_reduce_t<RG, TY, true, 0>(d0, w, tc, tau, k_host, s);
+    if (gmode == 1) return launch_reduce_t<RG, TY, true, 1>(d0, w, tc, tau, k_host, s);
+    return hipErrorInvalidValue;
+}
+
+template <int TY>
 hipError_t launch_reduce_s(const ImageDesc& d0, const AosWork& w, const Taps& tc, float tau,
                            bool compute_g, int gmode, float k_host, hipStream_t s) {
+    if (!compute_g) return launch_reduce_t<1, TY, false, 0>(d0, w, tc, tau, k_host, s);
     switch (tc.r) {
-        case 1: return launch_reduce_t<1, TX, TY>(d0, w, tc, tau, compute_g, gmode, k_host, s);
-        case 2: return launch_reduce_t<2, TX, TY>(d0, w, tc, tau, compute_g, gmode, k_host, s);
-        case 3: return launch_reduce_t<3, TX, TY>(d0, w, tc, tau, compute_g, gmode, k_host, s);
-        case 4: return launch_reduce_t<4, TX, TY>(d0, w, tc, tau, compute_g, gmode, k_host, s);
+        case 1: return launch_reduce_g<1, TY>(d0, w, tc, tau, gmode, k_host, s);
+        case 2: return launch_reduce_g<2, TY>(d0, w, tc, tau, gmode, k_host, s);
+        case 3: return launch_reduce_g<3, TY>(d0, w, tc, tau, gmode, k_host, s);
+        case 4: return launch_reduce_g<4, TY>(d0, w, tc, tau, gmode, k_host, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <int TX, int TY>
+template <int TY>
 hipError_t launch_recover_s(const ImageDesc& d0, const AosWork& w, float tau, hipStream_t s) {
-    const int count = work_count(d0, w, TX, TY, false);
+    const int count = work_count(d0, w, TY, false);
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL((aos_recover_kernel<TX, TY>), dim3(count), dim3(kRecoverThreads), 0, s, d0,
-                       w, tau);
+    hipLaunchKernelGGL((aos_recover_kernel<TY>), dim3(count), dim3(TY * 4), 0, s, d0, w, tau);
     return hipGetLastError();
 }
 
@@ -439,30 +718,26 @@ hipError_t launch_recover_s(const ImageDesc& d0, const AosWork& w, float tau, hi
 hipError_t launch_aos_reduce(const ImageDesc& d0, const AosWork& w, int shape, const Taps& tc,
                              float tau, bool compute_g, int gmode, float k_host, hipStream_t s) {
     switch (shape) {
-        case 0: return launch_reduce_s<64, 64>(d0, w, tc, tau, compute_g, gmode, k_host, s);
-        case 1: return launch_reduce_s<64, 32>(d0, w, tc, tau, compute_g, gmode, k_host, s);
-        case 2: return launch_reduce_s<32, 64>(d0, w, tc, tau, compute_g, gmode, k_host, s);
-        case 3: return launch_reduce_s<32, 32>(d0, w, tc, tau, compute_g, gmode, k_host, s);
+        case 0: return launch_reduce_s<32>(d0, w, tc, tau, compute_g, gmode, k_host, s);
+        case 1: return launch_reduce_s<64>(d0, w, tc, tau, compute_g, gmode, k_host, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_aos_iface(const ImageDesc& d0, const AosWork& w, hipStream_t s) {
-    const int count = work_count(d0, w, 0, 0, true);
+    const int count = work_count(d0, w, 0, true);
     if (count <= 0) return hipSuccess;
-    const int waves = kBlock / kWave;
-    hipLaunchKernelGGL(aos_iface_kernel, dim3((count + waves - 1) / waves), dim3(kBlock), 0, s, d0,
-                       w, count);
+    const int waves = kIfaceThreads / kWave;
+    hipLaunchKernelGGL(aos_iface_kernel, dim3((count + waves - 1) / waves), dim3(kIfaceThreads), 0,
+                       s, d0, w, count);
     return hipGetLastError();
 }
 
 hipError_t launch_aos_recover(const ImageDesc& d0, const AosWork& w, int shape, float tau,
                               hipStream_t s) {
     switch (shape) {
-        case 0: return launch_recover_s<64, 64>(d0, w, tau, s);
-        case 1: return launch_recover_s<64, 32>(d0, w, tau, s);
-        case 2: return launch_recover_s<32, 64>(d0, w, tau, s);
-        case 3: return launch_recover_s<32, 32>(d0, w, tau, s);
+        case 0: return launch_recover_s<32>(d0, w, tau, s);
+        case 1: return launch_recover_s<64>(d0, w, tau, s);
         default: return hipErrorInvalidValue;
     }
 }

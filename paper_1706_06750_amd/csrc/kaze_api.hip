@@ -155,16 +155,20 @@ void schedule(const kaze_params* p, std::vector<Level>& lv) {
     }
 }
 
-// Lines of at most 64 chunks (one per lane of the interface wavefront).
+static_assert(kAosShapes == KAZE_AOS_SHAPES, "the public shape count matches the kernels");
+
+// Every AOS tile shape takes every image size the library accepts.
 bool shape_fits(int W, int H, int shape) {
-    return W <= kAosShapeTX[shape] * kWave && H <= kAosShapeTY[shape] * kWave;
+    (void)W;
+    (void)H;
+    return shape >= 0 && shape < kAosShapes;
 }
 
 kaze_status check_size(int W, int H) {
     if (W < 8 || H < 8) return fail(KAZE_ERR_INVALID_ARG, "image must be at least 8x8");
-    if (!shape_fits(W, H, 0))
-        return fail(KAZE_ERR_UNSUPPORTED, "image larger than %dx%d (got %dx%d)", kTile * kWave,
-                    kTile * kWave, W, H);
+    if (W > kMaxSide || H > kMaxSide)
+        return fail(KAZE_ERR_UNSUPPORTED, "image larger than %dx%d (got %dx%d)", kMaxSide,
+                    kMaxSide, W, H);
     return KAZE_OK;
 }
 
@@ -213,8 +217,8 @@ struct Scratch {
 
 Scratch scratch_layout(int W, int H, int nbins, int shape, size_t base) {
     Scratch w;
-    const size_t ncx = (W + kAosShapeTX[shape] - 1) / kAosShapeTX[shape];
-    const size_t ncy = (H + kAosShapeTY[shape] - 1) / kAosShapeTY[shape];
+    (void)shape;
+    const size_t ncx = aos_row_chunks(W), ncy = aos_col_chunks(H);
     size_t off = base;
     w.g = off;    off = align256(off + (size_t)W * H * sizeof(float));
     w.rrow = off; off = align256(off + (size_t)H * ncx * 8 * sizeof(float));
@@ -243,8 +247,9 @@ ImageDesc aos_desc(int W, int H, int shape, char* base, const Scratch& w, const 
     d.H = H;
     d.gate = nullptr;
     d.bound = 0.f;
-    d.ncx = (W + kAosShapeTX[shape] - 1) / kAosShapeTX[shape];
-    d.ncy = (H + kAosShapeTY[shape] - 1) / kAosShapeTY[shape];
+    (void)shape;
+    d.nchr = aos_row_chunks(W);
+    d.nchc = aos_col_chunks(H);
     return d;
 }
 
@@ -337,8 +342,8 @@ BatchLayout batch_layout(const kaze_image_desc* im, int n, const kaze_params* p,
     L.n_tiles = L.n_aos = L.n_lines = L.n_hist = L.n_det = L.n_nms = 0;
     for (int j = 0; j < n; ++j) {
         L.n_tiles += tiles_of(im[j].W, im[j].H);
-        L.n_aos += tiles_of(im[j].W, im[j].H, kAosShapeTX[shape], kAosShapeTY[shape]);
-        L.n_lines += im[j].W + im[j].H;
+        L.n_aos += aos_tiles_of(im[j].W, im[j].H, kAosShapeTY[shape]);
+        L.n_lines += aos_line_groups(im[j].W, im[j].H);
         L.n_hist += (im[j].W * im[j].H + kHistChunk - 1) / kHistChunk;
         L.n_det += det_tiles_of(im[j].W, im[j].H);
         L.n_nms += nms_blocks_of(im[j].W, im[j].H);
@@ -375,7 +380,7 @@ kaze_status check_batch(const kaze_image_desc* im, int n, const kaze_params* p, 
         if ((st = check_size(d.W, d.H)) != KAZE_OK) return st;
         if (!shape_fits(d.W, d.H, shape))
             return fail(KAZE_ERR_UNSUPPORTED, "image %d (%dx%d) does not fit tile shape %dx%d", j,
-                        d.W, d.H, kAosShapeTX[shape], kAosShapeTY[shape]);
+                        d.W, d.H, kAosTX, kAosShapeTY[shape]);
         if (!d.img || !d.levels || !d.k)
             return fail(KAZE_ERR_INVALID_ARG, "image %d: img, levels and k must be non-NULL", j);
         if (d.ld_img < d.W) return fail(KAZE_ERR_INVALID_ARG, "image %d: ld_img < W", j);
@@ -534,9 +539,9 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
             hlvl[(size_t)(i - 1) * n + j] = a;
         }
         for (int t = 0; t < tiles_of(d.W, d.H); ++t) ht[it++] = make_int2(j, t);
-        for (int t = 0; t < tiles_of(d.W, d.H, kAosShapeTX[shape], kAosShapeTY[shape]); ++t)
+        for (int t = 0; t < aos_tiles_of(d.W, d.H, kAosShapeTY[shape]); ++t)
             ha[ia++] = make_int2(j, t);
-        for (int t = 0; t < d.W + d.H; ++t) hl[il++] = make_int2(j, t);
+        for (int t = 0; t < aos_line_groups(d.W, d.H); ++t) hl[il++] = make_int2(j, t);
         for (int t = 0; t < (d.W * d.H + kHistChunk - 1) / kHistChunk; ++t) hh[ih++] = make_int2(j, t);
         for (int t = 0; t < det_tiles_of(d.W, d.H); ++t) hd[idt++] = make_int2(j, t);
         for (int t = 0; t < nms_blocks_of(d.W, d.H); ++t) hn[inm++] = make_int2(j, t);

@@ -125,7 +125,8 @@ __device__ __forceinline__ void wave_pcr_pairs(Eq e0, Eq e1, int lane, float& z0
 // ---------------------------------------------------------------------------
 namespace kaze {
 
-constexpr int kTile = 64;          // edge of the stencil tiles; default AOS tile
+constexpr int kTile = 64;          // edge of the stencil tiles
+constexpr int kMaxSide = 4096;     // largest image width or height
 constexpr int kMaxCondRadius = 4;  // sigma_cond radius that keeps the fused tile within 64 KB of LDS
 constexpr int kHistChunk = 8192;   // pixels per block of the histogram kernel
 constexpr int kNmsRows = 8;        // rows per thread of the extrema kernel
@@ -146,18 +147,53 @@ struct BatchImage {
     int W, H;
 };
 
-// One image of an AOS step.  Row line y is cut into ncx chunks of TX pixels
-// (tile columns), column line x into ncy chunks of TY pixels (tile rows).
+// AOS line partition: every row line is cut into chunks of kRowChunk pixels,
+// every column line into chunks of kColChunk pixels.  The reduction and
+// recovery tiles are kAosTX pixels wide (two row chunks) and
+// kAosShapeTY[shape] high (one or two column chunks); the partition of the
+// lines, and so the arithmetic, is the same for every shape.
+constexpr int kAosTX = 60;
+constexpr int kRowChunk = 30;
+constexpr int kColChunk = 32;
+constexpr int kAosShapes = 2;
+constexpr int kAosShapeTY[kAosShapes] = {32, 64};
+
+__host__ __device__ inline int aos_row_chunks(int W) { return (W + kRowChunk - 1) / kRowChunk; }
+__host__ __device__ inline int aos_col_chunks(int H) { return (H + kColChunk - 1) / kColChunk; }
+inline int aos_tiles_of(int W, int H, int ty) {
+    return ((W + kAosTX - 1) / kAosTX) * ((H + ty - 1) / ty);
+}
+// Interface solve: every lane holds kIfaceM consecutive chunks of a line and
+// a line spans iface_lanes(chunks) lanes (a power of two), so a wavefront
+// serves 64 / iface_lanes lines of one direction of one image.  Work items:
+// the row-line groups of the image, then its column-line groups.
+constexpr int kIfaceM = 8;
+__host__ __device__ inline int iface_lanes(int nch) {
+    int p = 1;
+    while (p * kIfaceM < nch) p <<= 1;
+    return p;
+}
+__host__ __device__ inline int iface_groups(int lines, int nch) {
+    const int per = 64 / iface_lanes(nch);
+    return (lines + per - 1) / per;
+}
+inline int aos_line_groups(int W, int H) {
+    return iface_groups(H, aos_row_chunks(W)) + iface_groups(W, aos_col_chunks(H));
+}
+
+// One image of an AOS step.  Interface equations and solutions are stored
+// chunk-major, so that the lanes of one wavefront (consecutive lines) touch
+// consecutive addresses.
 struct ImageDesc {
     const float* L;   // level i-1, W x H, pitch W
     float* Lnext;     // level i
     float* g;         // conductivity of L (written or read, see the kernel)
-    float* rrow;      // reduced interface rows of the row lines, [H][ncx][8]
-    float* rcol;      // ... of the column lines, [W][ncy][8]
-    float* zrow;      // first/last unknown of every row chunk, [H][ncx][2]
-    float* zcol;      // ... of every column chunk, [W][ncy][2]
+    float* rrow;      // reduced equations of the row chunks, [nchr][H][8]
+    float* rcol;      // ... of the column chunks, [nchc][W][8]
+    float* zrow;      // first/last unknown of every row chunk, [nchr][H][2]
+    float* zcol;      // ... of every column chunk, [nchc][W][2]
     const float* k;   // contrast factor (device scalar); NULL: use the host value
-    int W, H, ncx, ncy;
+    int W, H, nchr, nchc;
     // optional gate: the step is skipped when *gate <= bound (the level was
     // accepted from the surrogate); NULL: always run
     const float* gate;
@@ -187,12 +223,19 @@ __device__ __forceinline__ int xcd_contiguous(int t, int n) {
     return x * per + (x < rem ? x : rem) + j;
 }
 
+// t must be wave-uniform; the tables are read through the constant address
+// space, so descriptor and item land in scalar registers.
 template <class D>
 __device__ __forceinline__ void resolve(const D& d0, const Work<D>& w, int t, D& d, int& local) {
     if (w.items) {
-        const int2 it = w.items[t];
-        d = w.descs[it.x];
-        local = it.y;
+        typedef __attribute__((address_space(4))) const int cint;
+        static_assert(sizeof(D) % sizeof(int) == 0, "descriptors are whole words");
+        const cint* it = (const cint*)w.items + 2 * t;
+        const cint* src = (const cint*)(w.descs + it[0]);
+        int* dst = reinterpret_cast<int*>(&d);
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(D) / sizeof(int)); ++i) dst[i] = src[i];
+        local = it[1];
     } else {
         d = d0;
         local = t;
@@ -203,10 +246,6 @@ inline int tiles_of(int W, int H, int tx = kTile, int ty = kTile) {
     return ((W + tx - 1) / tx) * ((H + ty - 1) / ty);
 }
 
-// AOS tile shapes the autotuner chooses from (row chunk TX x column chunk TY).
-constexpr int kAosShapes = 4;
-constexpr int kAosShapeTX[kAosShapes] = {64, 64, 32, 32};
-constexpr int kAosShapeTY[kAosShapes] = {64, 32, 64, 32};
 
 enum KernelId {
     K_GAUSS = 0,
@@ -248,11 +287,12 @@ hipError_t launch_kselect(const BatchImage& d0, const ImgWork& w, int nbins,
 hipError_t launch_reset(const BatchImage& d0, const ImgWork& w, int nbins, float k_fill,
                         hipStream_t s);
 
-// a3-a5: AOS step in three launches with tiles of kAosShapeTX/TY[shape].
+// a3-a5: AOS step in three launches on tiles of kAosTX x kAosShapeTY[shape].
 // reduce: (conductivity if compute_g, else g is read) + chunk reduction of
-// every row and column chunk; iface: the interface system of every line by
-// wavefront PCR (items: image, line; rows first, then columns); recover:
-// interior of every chunk and L_next = L + (delta_x + delta_y)/2.
+// every row and column chunk (items: image, tile); iface: the interface
+// system of every line (items: image, group of lines, row groups first, see
+// iface_lanes); recover: interior of every chunk and
+// L_next = L + (delta_x + delta_y)/2 (items: image, tile).
 hipError_t launch_aos_reduce(const ImageDesc& d0, const AosWork& w, int shape, const Taps& tc,
                              float tau, bool compute_g, int gmode, float k_host, hipStream_t s);
 hipError_t launch_aos_iface(const ImageDesc& d0, const AosWork& w, hipStream_t s);

@@ -70,8 +70,9 @@ class kaze_batch_config(ctypes.Structure):
     _fields_ = [("aos_shape", ctypes.c_int)]
 
 
-# Row-chunk x column-chunk tile shape of each kaze_batch_config.aos_shape.
-AOS_SHAPES = ((64, 64), (64, 32), (32, 64), (32, 32))
+# Block tile (width x height) of each kaze_batch_config.aos_shape; rows are
+# cut into chunks of 30 pixels and columns into chunks of 32 for every shape.
+AOS_SHAPES = ((60, 32), (60, 64))
 
 
 def _load():
@@ -250,13 +251,13 @@ def kaze_batch_destroy(handle):
 
 
 def kaze_batch_autotune(images, p, ws, ws_bytes, reps=3, stream=None):
-    """Returns (best shape index, ms per run of each of the 4 shapes)."""
+    """Returns (best shape index, ms per run of each shape in AOS_SHAPES)."""
     best = kaze_batch_config(-1)
-    ms = (ctypes.c_double * 4)()
+    ms = (ctypes.c_double * len(AOS_SHAPES))()
     _check(lib.kaze_batch_autotune(_descs(images), len(images), ctypes.byref(p), _ptr(ws),
                                    ws_bytes, reps, _stream(stream), ctypes.byref(best),
                                    ctypes.cast(ms, ctypes.c_void_p)))
-    return best.aos_shape, [ms[i] for i in range(4)]
+    return best.aos_shape, [ms[i] for i in range(len(AOS_SHAPES))]
 
 
 # ---------------------------------------------------------------------------

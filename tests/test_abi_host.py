@@ -193,13 +193,14 @@ def test_batch_workspace_query(K):
     D = K.kaze_image_desc
     small = [D(256, 100, 80, 100, 512, 1024, 2048, 4096, 10, 8192),
              D(256, 300, 200, 300, 512, 1024, 2048, 4096, 10, 8192)]
-    sizes = [K.kaze_batch_workspace_bytes(small, p, s) for s in range(4)]
+    sizes = [K.kaze_batch_workspace_bytes(small, p, s) for s in range(len(K.AOS_SHAPES))]
     assert all(v > 0 and v % 256 == 0 for v in sizes)
     assert K.kaze_batch_workspace_bytes(small, p) == max(sizes)
-    # 3000 rows fit 64-row column chunks (<= 64 chunks) but not 32-row ones
-    tall = [D(256, 100, 3000, 100, 512, 1024, 2048, 4096, 10, 8192)]
-    assert K.kaze_batch_workspace_bytes(tall, p, 1) == 0
-    assert K.kaze_batch_workspace_bytes(tall, p, 0) > 0
+    # every shape fits every accepted size; 4096 is the largest side
+    tall = [D(256, 100, 4096, 100, 512, 1024, 2048, 4096, 10, 8192)]
+    assert all(K.kaze_batch_workspace_bytes(tall, p, s) > 0 for s in range(len(K.AOS_SHAPES)))
+    assert K.kaze_batch_workspace_bytes([D(256, 100, 4097, 100, 512, 0, 2048, 0, 0, 0)], p) == 0
+    assert K.kaze_batch_workspace_bytes(small, p, len(K.AOS_SHAPES)) == 0
     assert K.kaze_batch_workspace_bytes([D(256, 7, 80, 7, 512, 0, 2048, 0, 0, 0)], p) == 0
 
 

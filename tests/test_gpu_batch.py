@@ -12,9 +12,10 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-# ragged sizes covering partial tiles of every shape, one image too narrow
-# for a full 64-wide tile and one taller than wide
-SIZES = [(67, 45), (320, 240), (200, 130), (130, 260), (64, 64), (9, 13)]
+# ragged sizes covering partial tiles of every shape (60 wide, 32 or 64
+# high; row chunks of 30, column chunks of 32), images narrower than a row
+# chunk and taller than wide, an exact multiple of the tile
+SIZES = [(67, 45), (320, 240), (200, 130), (130, 260), (64, 64), (9, 13), (120, 96), (31, 33)]
 
 
 def single(K, img):
@@ -33,7 +34,7 @@ def make_batch(K, sizes, seeds, shape, **kw):
     return kb, imgs
 
 
-@pytest.mark.parametrize("shape", [0, 1, 2, 3])
+@pytest.mark.parametrize("shape", [0, 1])
 def test_batch_matches_single_image_path(gpu_lib, shape):
     K = gpu_lib
     note(f"[batch] shape {K.AOS_SHAPES[shape]} sizes {SIZES}")
@@ -46,21 +47,16 @@ def test_batch_matches_single_image_path(gpu_lib, shape):
         dl = (kb.levels[j] - ref.levels).abs().max().item()
         dd = (kb.det[j] - ref.det).abs().max().item()
         note(f"  image {j} {SIZES[j]}: max|dL| {dl:.2e} max|ddet| {dd:.2e}")
-        if shape == 0:
-            # same tile shape as the single-image path: identical arithmetic
-            assert dl == 0.0 and dd == 0.0
-            assert np.array_equal(kb.keypoints(j), ref.keypoints())
-        else:
-            # a different partition of the lines changes only the FP32 rounding
-            assert dl < 2e-6
-            assert dd < 1e-8
+        # every shape partitions the lines the same way: identical arithmetic
+        assert dl == 0.0 and dd == 0.0
+        assert np.array_equal(kb.keypoints(j), ref.keypoints())
     kb.close()
 
 
 def test_batch_graph_replays_match_eager(gpu_lib):
     K = gpu_lib
-    note("[batch] graph replays vs eager, shape 3")
-    kb, _ = make_batch(K, SIZES, range(60, 60 + len(SIZES)), 3)
+    note("[batch] graph replays vs eager, shape 1")
+    kb, _ = make_batch(K, SIZES, range(60, 60 + len(SIZES)), 1)
     kb.run(eager=True)
     torch.cuda.synchronize()
     ref_lv = [t.clone() for t in kb.levels]
@@ -83,7 +79,7 @@ def test_autotuner_and_cache(gpu_lib, tmp_path):
     cache = str(tmp_path / "tune.json")
     note("[batch] autotune")
     kb = K.KazeBatch(SIZES, shape="auto", tune_cache=cache)
-    assert kb.shape in (0, 1, 2, 3)
+    assert kb.shape in range(len(K.AOS_SHAPES))
     assert kb.tune_ms is not None and min(m for m in kb.tune_ms if m > 0) > 0
     note(f"  ms per shape {kb.tune_ms} -> {K.AOS_SHAPES[kb.shape]}")
     kb.close()
