@@ -37,13 +37,13 @@ DET_ALGO_BYTES_PER_PX = 8
 AOS_KERNELS = ("aos_reduce", "aos_iface", "aos_recover")
 
 
-def traffic_from_profile(W, H, aos_tile, with_det):
+def traffic_from_profile(key, aos_tile, with_det):
     """HBM bytes per step of the level segment from the committed counter
-    summary, if it was taken on the current per-level kernel sources with the
-    same tile shape (the detector's share only where it runs in the
-    segment)."""
+    summary profiles/level_traffic_<key>.json, if it was taken on the current
+    per-level kernel sources with the same tile shape (the detector's share
+    only where it runs in the segment)."""
     from paper_1706_06750_amd.rocprof_summary import csrc_hash
-    path = os.path.join(ROOT, "profiles", "level_traffic_%dx%d.json" % (W, H))
+    path = os.path.join(ROOT, "profiles", "level_traffic_%s.json" % key)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -222,7 +222,7 @@ def bench_single(args, K, torch, kaze_image, case):
     torch.cuda.synchronize()
     elapsed, level_us = timed_graph_runs(args, K, torch, kb)
     roof = level_roofline(level_us, W * H,
-                          traffic_from_profile(W, H, "%dx%d" % K.AOS_SHAPES[kb.shape],
+                          traffic_from_profile("%dx%d" % (W, H), "%dx%d" % K.AOS_SHAPES[kb.shape],
                                                kb.det_in_level_segment),
                           with_det=kb.det_in_level_segment)
     roof["timed_in"] = "the timed region (event pair around each run's AOS segment)"
@@ -309,7 +309,11 @@ def bench_batch(args, K, torch, kaze_image, cases):
         kb.run()
     torch.cuda.synchronize()
     elapsed, level_us = timed_graph_runs(args, K, torch, kb)
-    roof = level_roofline(level_us, px, None, with_det=kb.det_in_level_segment)
+    roof = level_roofline(level_us, px,
+                          traffic_from_profile(args.workload.replace("kaze_", ""),
+                                               "%dx%d" % K.AOS_SHAPES[kb.shape],
+                                               kb.det_in_level_segment),
+                          with_det=kb.det_in_level_segment)
     roof["timed_in"] = "the timed region (event pair around each run's AOS segment)"
 
     n = len(sizes)

@@ -51,11 +51,18 @@ typedef enum {
 /* Perona-Malik conductivity functions of Eq. 3. */
 typedef enum { KAZE_G1 = 1, KAZE_G2 = 2 } kaze_diffusivity;
 
+/* How each level is reached from the one before, with the conductivity of
+ * the level before held fixed:
+ *   KAZE_AOS  one semi-implicit step of Eq. 4 (additive operator splitting);
+ *   KAZE_FED  one fast-explicit-diffusion cycle of Eq. 5 (see
+ *             kaze_fed_schedule). */
+typedef enum { KAZE_AOS = 0, KAZE_FED = 1 } kaze_scheme;
+
 /*
  * Parameters of the method (host struct, read during the call only).
  * kaze_default_params() fills the values used throughout: sigma0 = 1.6,
  * 4 octaves x 4 sublevels, sigma_cond = 1.0, g2, k at the 70th percentile
- * of a 300-bin gradient histogram, detector threshold 0.001.
+ * of a 300-bin gradient histogram, detector threshold 0.001, AOS steps.
  */
 typedef struct {
     int    octaves;        /* O of Eq. 6                                        */
@@ -67,6 +74,7 @@ typedef struct {
     double k_percentile;   /* quantile of the gradient histogram, [1e-6, 1]     */
     double k_override;     /* > 0: use this contrast factor, skip the histogram */
     double det_threshold;  /* detector threshold of Sec. II-B (compared in FP32) */
+    int    scheme;         /* KAZE_AOS (default) or KAZE_FED                     */
 } kaze_params;
 
 /* One detected extremum: pixel position, level index and det response. */
@@ -102,8 +110,9 @@ size_t kaze_workspace_bytes(int W, int H, const kaze_params* p);
  * Nonlinear scale space (Sec. II-A, Sec. III-A).
  *   img      (device) W x H float32 image, row pitch ld_img >= W floats.
  *   levels   (device) output, N x H x W float32: level 0 is G_sigma0 * img,
- *            level i >= 1 is one AOS step of Eq. 4 from level i-1 with
- *            tau_i, conductivity computed from level i-1.
+ *            level i >= 1 is one AOS step of Eq. 4 (or one FED cycle of
+ *            Eq. 5, p->scheme) from level i-1 with tau_i, conductivity
+ *            computed from level i-1.
  *   k_out    (device) output, 1 float32: the contrast factor used (the
  *            histogram quantile of Sec. III-A, or k_override).
  *   ws       (device) workspace of at least kaze_workspace_bytes(W, H, p)
@@ -142,6 +151,40 @@ kaze_status kaze_conductivity(const float* L, int W, int H, const kaze_params* p
  */
 kaze_status kaze_aos_step(const float* L, const float* g, int W, int H, double tau,
                           float* L_next, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Step sizes of one fast-explicit-diffusion cycle of total time T (Eq. 5),
+ * as used for every level when p->scheme is KAZE_FED (host, double):
+ *   n = the smallest cycle length with tau_max (n^2 + n) / 3 >= T, where
+ *       tau_max = 1/4 is the stability limit of the explicit 5-point step
+ *       with unit grid spacing and g <= 1;
+ *   tau_j = tau_max / (2 cos^2(pi (2j + 1) / (4n + 2))), j = 0..n-1, scaled
+ *       so that they sum to T;
+ *   order: the steps are applied as j = kappa * i mod n, i = 0..n-1, with
+ *       the kappa coprime to n (smallest on ties) that minimises
+ *       max_i (max|prefix product| * max|suffix product|) of the step
+ *       factors (1 + tau_j mu) over mu in [-8, 0] (2001 points), which
+ *       bounds how much rounding errors can grow inside the cycle.
+ * Returns n (or a negative kaze_status for T <= 0 or not finite) and, if
+ * tau is not NULL and capacity >= n, writes the n step sizes in application
+ * order.
+ */
+int kaze_fed_schedule(double T, double* tau, int capacity);
+
+/*
+ * One FED cycle of total time T with a given conductivity (the counterpart
+ * of kaze_aos_step): n explicit steps
+ *   L <- L + tau_j sum_q (g_p + g_q)/2 (L_q - L_p)
+ * over the 4-neighbours q of every pixel p, none across the image border,
+ * with the step sizes of kaze_fed_schedule(T).
+ *   L, g     (device) inputs, W x H float32.
+ *   T        cycle time, > 0.
+ *   L_next   (device) output, W x H float32; must not alias L, g or ws.
+ *   ws       (device) workspace of kaze_workspace_bytes(W, H, p) bytes for a
+ *            p with scheme KAZE_FED, 256-byte aligned.
+ */
+kaze_status kaze_fed_cycle(const float* L, const float* g, int W, int H, double T,
+                           float* L_next, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Detector response of Eq. 8 for every level:

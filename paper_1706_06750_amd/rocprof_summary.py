@@ -67,25 +67,26 @@ def stats(path: str) -> str:
 
 
 def counter_means(path: str, counter: str, aos_tile: str | None = None):
-    """Mean counter value per dispatch, by kernel.  With aos_tile ("32x32")
-    only the AOS kernels instantiated for that tile shape count (the
+    """Mean counter value per dispatch, by kernel.  With aos_tile ("60x32")
+    only the AOS kernels instantiated for that tile height count (the
     autotuner runs every shape first)."""
     acc = collections.defaultdict(list)
-    tx, ty = (aos_tile.split("x") if aos_tile else (None, None))
+    ty = aos_tile.split("x")[1] if aos_tile else None
     for r in csv.DictReader(open(path)):
         if r.get("Counter_Name", r.get("counter_name")) != counter:
             continue
         name = short(r.get("Kernel_Name", r.get("kernel_name")))
         base = name.split("<")[0]
-        if aos_tile and base == "aos_reduce_kernel" and ", %s, %s," % (tx, ty) not in name:
+        # aos_reduce_kernel<RG, TY, CG, GM>, aos_recover_kernel<TY>
+        if ty and base == "aos_reduce_kernel" and name.split("<")[1].split(",")[1].strip() != ty:
             continue
-        if aos_tile and base == "aos_recover_kernel" and "<%s, %s>" % (tx, ty) not in name:
+        if ty and base == "aos_recover_kernel" and name.split("<")[1].rstrip(">").strip() != ty:
             continue
         acc[base].append(float(r.get("Counter_Value", r.get("value"))))
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
-def traffic(fetch_csv, write_csv, W, H, copy_mib, root, aos_tile, det_per_level=False):
+def traffic(fetch_csv, write_csv, W, H, copy_mib, root, aos_tile, det_per_level=False, pixels=0):
     """det_per_level: the detector runs once per level (large batches); else
     its dispatches cover several levels and it is reported apart."""
     f = counter_means(fetch_csv, "FETCH_SIZE", aos_tile)
@@ -101,10 +102,12 @@ def traffic(fetch_csv, write_csv, W, H, copy_mib, root, aos_tile, det_per_level=
         per[k] = {"fetch_kib_raw": f[k], "write_kib_raw": w[k],
                   "bytes": mult * (f[k] * fs + w[k] * ws) * 1024.0}
     total = sum(v["bytes"] for v in per.values())
-    return {"image": "%dx%d" % (W, H), "aos_tile": aos_tile, "det_in_segment": det_per_level,
+    return {"image": "%dx%d" % (W, H) if W else None, "aos_tile": aos_tile,
+            "det_in_segment": det_per_level,
             "copy_scale_fetch": fs, "copy_scale_write": ws,
             "kernels": per, "bytes_per_level": total,
-            "bytes_per_pixel_level": total / (W * H), "csrc_hash": csrc_hash(root)}
+            "pixels": pixels or W * H,
+            "bytes_per_pixel_level": total / (pixels or W * H), "csrc_hash": csrc_hash(root)}
 
 
 def main():
@@ -115,17 +118,22 @@ def main():
     b = sub.add_parser("traffic")
     b.add_argument("fetch_csv")
     b.add_argument("write_csv")
-    b.add_argument("--image", required=True)
+    b.add_argument("--image", required=True, help="WxH of the single image, or a workload name")
     b.add_argument("--copy-mib", type=int, required=True)
-    b.add_argument("--aos-tile", required=True, help="AOS tile shape of the run, e.g. 32x32")
+    b.add_argument("--aos-tile", required=True, help="AOS tile shape of the run, e.g. 60x32")
+    b.add_argument("--det-per-level", action="store_true",
+                   help="the detector runs once per level inside the level segment (large batches)")
+    b.add_argument("--pixels", type=int, default=0,
+                   help="pixels per level when the run covers several images (default W*H)")
     b.add_argument("--out", required=True)
     args = ap.parse_args()
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     if args.cmd == "stats":
         print(stats(args.csv))
     else:
-        W, H = (int(v) for v in args.image.split("x"))
-        d = traffic(args.fetch_csv, args.write_csv, W, H, args.copy_mib, root, args.aos_tile)
+        W, H = (int(v) for v in args.image.split("x")) if "x" in args.image else (0, 0)
+        d = traffic(args.fetch_csv, args.write_csv, W, H, args.copy_mib, root, args.aos_tile,
+                    args.det_per_level, args.pixels)
         with open(args.out, "w") as fh:
             json.dump(d, fh, indent=1)
         print(json.dumps(d, indent=1))
