@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate measurements (plain path only)")
+    ap.add_argument("--no-fed", action="store_true",
+                    help="skip the FED-scheme measurement")
     ap.add_argument("--no-breakdown", action="store_true",
                     help="skip the per-kernel timing pass (for profiler runs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -233,6 +235,8 @@ def bench_single(args, K, torch, kaze_image, case):
     extra = {"eager_images_per_s": round(eager_value, 3),
              "kernel_breakdown": {k: {kk: round(vv, 4) for kk, vv in v.items()}
                                   for k, v in breakdown.items()}}
+    if not args.no_fed:
+        extra["fed"] = bench_fed(args, K, torch, img, W, H, args.steps / elapsed, eager_value)
     if not args.no_surrogate:
         extra["surrogate"] = bench_surrogate(args, K, torch, img, W, H, seed,
                                              args.steps / elapsed)
@@ -242,6 +246,40 @@ def bench_single(args, K, torch, kaze_image, case):
               "levels": kz.N, "path": "plain AOS (no surrogate), graph replay",
               "aos_tile": "%dx%d" % shape, "keypoints": kps}
     return record(args, args.steps / elapsed, 1e3 * elapsed / args.steps, config, roof, extra)
+
+
+def bench_fed(args, K, torch, img, W, H, plain_value, plain_eager):
+    """The FED scheme (one fast-explicit-diffusion cycle per level) on the
+    same image, eager calls: images/s, time per level (conductivity + cycle,
+    event pairs around every launch) and the cycle lengths."""
+    p = K.kaze_default_params()
+    p.scheme = K.KAZE_FED
+    kz = K.Kaze(W, H, p)
+    for _ in range(max(2, args.warmup // 4)):
+        kz.run(img)
+    torch.cuda.synchronize()
+    steps = max(5, args.steps // 4)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        kz.run(img)
+    torch.cuda.synchronize()
+    val = steps / (time.perf_counter() - t0)
+    per = {}
+    for name in ("fed", "cond"):
+        K.kaze_profile_begin(name)
+        for _ in range(3):
+            kz.run(img)
+        n, ms = K.kaze_profile_end()
+        per[name] = (n / 3, 1e3 * ms / 3)
+    sched = K.kaze_schedule(p)
+    cycles = [len(K.kaze_fed_schedule(sched[i]["tau"])) for i in range(1, kz.N)]
+    level_us = (per["fed"][1] + per["cond"][1]) / (kz.N - 1)  # us per image / steps
+    return {"images_per_s": round(val, 3), "path": "eager calls",
+            "explicit_steps_per_image": int(sum(cycles)),
+            "launches_per_image": int(per["fed"][0]),
+            "us_per_level": round(level_us, 3),
+            "speedup_vs_plain_aos_eager": round(val / plain_eager, 4),
+            "speedup_vs_plain_aos_graph": round(val / plain_value, 4)}
 
 
 def bench_surrogate(args, K, torch, img, W, H, seed, plain_value):

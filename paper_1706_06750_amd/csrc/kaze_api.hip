@@ -12,6 +12,7 @@
 
 #include "kaze.h"
 #include "kaze_internal.h"
+#include "fed_internal.h"
 #include "kaze_surrogate.h"
 #include "sg_internal.h"
 
@@ -42,7 +43,7 @@ kaze_status fail(kaze_status st, const char* fmt, ...) {
 const char* const kKernelNames[K_COUNT] = {
     "gauss", "grad", "hist", "kselect", "cond", "aos_reduce", "aos_iface", "aos_recover",
     "det",   "nms",  "fill", "copy",    "sg_pack", "sg_conv1", "sg_conv", "sg_conv6",
-    "sg_probe"};
+    "sg_probe", "fed"};
 
 struct Profiler {
     unsigned mask = 0;  // bit i: record launches of kernel i
@@ -137,6 +138,8 @@ kaze_status check_params(const kaze_params* p) {
     }
     if (!isfinite(p->det_threshold))
         return fail(KAZE_ERR_INVALID_ARG, "det_threshold must be finite");
+    if (p->scheme != KAZE_AOS && p->scheme != KAZE_FED)
+        return fail(KAZE_ERR_INVALID_ARG, "scheme must be KAZE_AOS or KAZE_FED");
     return KAZE_OK;
 }
 
@@ -212,10 +215,11 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // Per-image scratch: conductivity plane, interface equations and solutions
 // of the AOS tile shape, histogram and hmax.
 struct Scratch {
-    size_t g, rrow, rcol, zrow, zcol, hist, hmax, total;
+    size_t g, rrow, rcol, zrow, zcol, hist, hmax, tmp, total;
 };
 
-Scratch scratch_layout(int W, int H, int nbins, int shape, size_t base) {
+// fed: room for the second plane of the explicit steps (FED scheme only).
+Scratch scratch_layout(int W, int H, int nbins, int shape, size_t base, bool fed = false) {
     Scratch w;
     (void)shape;
     const size_t ncx = aos_row_chunks(W), ncy = aos_col_chunks(H);
@@ -227,6 +231,7 @@ Scratch scratch_layout(int W, int H, int nbins, int shape, size_t base) {
     w.zcol = off; off = align256(off + (size_t)W * ncy * 2 * sizeof(float));
     w.hist = off; off = align256(off + (size_t)(nbins > 0 ? nbins : 1) * sizeof(unsigned));
     w.hmax = off; off = align256(off + sizeof(unsigned));
+    w.tmp = off;  off = align256(off + (fed ? (size_t)W * H * sizeof(float) : 0));
     w.total = off - base;
     return w;
 }
@@ -269,6 +274,27 @@ kaze_status aos_step(const ImageDesc& d, const AosWork& tiles, const AosWork& li
               launch_aos_reduce(d, tiles, shape, tc, tau, compute_g, gmode, k_host, s));
     KZ_LAUNCH(K_AOS_IFACE, s, launch_aos_iface(d, lines, s));
     KZ_LAUNCH(K_AOS_RECOVER, s, launch_aos_recover(d, tiles, shape, tau, s));
+    return KAZE_OK;
+}
+
+// One FED cycle of total time T (Eq. 5) from L into out with g fixed: the
+// steps of fed_schedule(T) in launches of kFedS, alternating between out and
+// tmp so that the last launch writes out.
+kaze_status fed_cycle(const float* L, const float* g, float* out, float* tmp, int W, int H,
+                      double T, hipStream_t s) {
+    const std::vector<double> tau = fed_schedule(T);
+    const int n = (int)tau.size();
+    const int launches = (n + kFedS - 1) / kFedS;
+    const float* src = L;
+    for (int l = 0; l < launches; ++l) {
+        float* dst = ((launches - 1 - l) % 2 == 0) ? out : tmp;
+        FedSteps st;
+        st.n = std::min(kFedS, n - l * kFedS);
+        for (int j = 0; j < kFedS; ++j)
+            st.half_tau[j] = j < st.n ? (float)(0.5 * tau[l * kFedS + j]) : 0.f;
+        KZ_LAUNCH(K_FED, s, launch_fed(src, g, dst, W, H, st, s));
+        src = dst;
+    }
     return KAZE_OK;
 }
 
@@ -371,6 +397,8 @@ BatchLayout batch_layout(const kaze_image_desc* im, int n, const kaze_params* p,
 kaze_status check_batch(const kaze_image_desc* im, int n, const kaze_params* p, int shape) {
     kaze_status st = check_params(p);
     if (st != KAZE_OK) return st;
+    if (p->scheme != KAZE_AOS)
+        return fail(KAZE_ERR_UNSUPPORTED, "batches run the AOS scheme only");
     if ((st = check_steps(p)) != KAZE_OK) return st;
     if (!im || n < 1) return fail(KAZE_ERR_INVALID_ARG, "a batch needs at least one image");
     if (shape < 0 || shape >= kAosShapes) return fail(KAZE_ERR_INVALID_ARG, "bad AOS tile shape");
@@ -821,6 +849,7 @@ kaze_status kaze_default_params(kaze_params* p) {
     p->k_percentile = 0.7;
     p->k_override = 0.0;
     p->det_threshold = 0.001;
+    p->scheme = KAZE_AOS;
     return KAZE_OK;
 }
 
@@ -848,7 +877,7 @@ kaze_status kaze_schedule(const kaze_params* p, double* sigma, double* t, double
 
 size_t kaze_workspace_bytes(int W, int H, const kaze_params* p) {
     if (check_params(p) != KAZE_OK || check_size(W, H) != KAZE_OK) return 0;
-    return scratch_layout(W, H, hist_bins(p), 0, 0).total;
+    return scratch_layout(W, H, hist_bins(p), 0, 0, p->scheme == KAZE_FED).total;
 }
 
 kaze_status kaze_build_scale_space(const float* img, int W, int H, int ld_img,
@@ -862,7 +891,8 @@ kaze_status kaze_build_scale_space(const float* img, int W, int H, int ld_img,
     if (ld_img < W) return fail(KAZE_ERR_INVALID_ARG, "ld_img (%d) < W (%d)", ld_img, W);
     if (!aligned(img, 4) || !aligned(levels, 4) || !aligned(k_out, 4))
         return fail(KAZE_ERR_INVALID_ARG, "float buffers must be 4-byte aligned");
-    const Scratch w = scratch_layout(W, H, hist_bins(p), 0, 0);
+    const bool fed = p->scheme == KAZE_FED;
+    const Scratch w = scratch_layout(W, H, hist_bins(p), 0, 0, fed);
     if (!ws || !aligned(ws, 256) || ws_bytes < w.total)
         return fail(KAZE_ERR_WORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
                     w.total, ws_bytes);
@@ -891,7 +921,15 @@ kaze_status kaze_build_scale_space(const float* img, int W, int H, int ld_img,
     for (size_t i = 1; i < lv.size(); ++i) {
         d.L = levels + plane * (i - 1);
         d.Lnext = levels + plane * i;
-        st = aos_step(d, anone, anone, 0, tc, (float)lv[i].tau, true, gmode, 1.f, s);
+        if (fed) {
+            BatchImage bc = b;
+            bc.levels = const_cast<float*>(d.L);  // conductivity of level i-1
+            KZ_LAUNCH(K_COND, s, launch_cond(bc, none, tc, 1.f, gmode, s));
+            st = fed_cycle(d.L, b.g, d.Lnext, reinterpret_cast<float*>(base + w.tmp), W, H,
+                           lv[i].tau, s);
+        } else {
+            st = aos_step(d, anone, anone, 0, tc, (float)lv[i].tau, true, gmode, 1.f, s);
+        }
         if (st != KAZE_OK) return st;
     }
     return KAZE_OK;
@@ -939,6 +977,34 @@ kaze_status kaze_aos_step(const float* L, const float* g, int W, int H, double t
                     static_cast<hipStream_t>(stream));
 }
 
+int kaze_fed_schedule(double T, double* tau, int capacity) {
+    if (!(T > 0.0) || !isfinite(T)) return fail(KAZE_ERR_INVALID_ARG, "T must be > 0 and finite");
+    const std::vector<double> t = fed_schedule(T);
+    const int n = (int)t.size();
+    if (tau && capacity >= n)
+        for (int i = 0; i < n; ++i) tau[i] = t[i];
+    return n;
+}
+
+kaze_status kaze_fed_cycle(const float* L, const float* g, int W, int H, double T, float* L_next,
+                           void* ws, size_t ws_bytes, void* stream) {
+    kaze_status st = check_size(W, H);
+    if (st != KAZE_OK) return st;
+    if (!L || !g || !L_next) return fail(KAZE_ERR_INVALID_ARG, "L, g and L_next must be non-NULL");
+    if (!aligned(L, 4) || !aligned(g, 4) || !aligned(L_next, 4))
+        return fail(KAZE_ERR_INVALID_ARG, "float buffers must be 4-byte aligned");
+    if (!(T > 0.0) || !isfinite(T)) return fail(KAZE_ERR_INVALID_ARG, "T must be > 0");
+    kaze_params p;
+    kaze_default_params(&p);
+    p.scheme = KAZE_FED;
+    const Scratch w = scratch_layout(W, H, hist_bins(&p), 0, 0, true);
+    if (!ws || !aligned(ws, 256) || ws_bytes < w.total)
+        return fail(KAZE_ERR_WORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
+                    w.total, ws_bytes);
+    float* tmp = reinterpret_cast<float*>(static_cast<char*>(ws) + w.tmp);
+    return fed_cycle(L, g, L_next, tmp, W, H, T, static_cast<hipStream_t>(stream));
+}
+
 kaze_status kaze_detector_response(const float* levels, int W, int H, const kaze_params* p,
                                    float* det, void* stream) {
     kaze_status st = check_params(p);
@@ -984,7 +1050,7 @@ kaze_status kaze_find_extrema(const float* det, int W, int H, const kaze_params*
 // ---------------------------------------------------------------- batches
 size_t kaze_batch_workspace_bytes(const kaze_image_desc* images, int n, const kaze_params* p,
                                   const kaze_batch_config* cfg) {
-    if (check_params(p) != KAZE_OK || !images || n < 1) return 0;
+    if (check_params(p) != KAZE_OK || p->scheme != KAZE_AOS || !images || n < 1) return 0;
     size_t best = 0;
     for (int sh = 0; sh < kAosShapes; ++sh) {
         if (cfg && cfg->aos_shape >= 0 && cfg->aos_shape != sh) continue;
@@ -1092,7 +1158,7 @@ kaze_status kaze_sg_default_config(kaze_sg_config* c) {
 
 size_t kaze_sg_scale_space_workspace_bytes(int W, int H, const kaze_params* p,
                                            const kaze_sg_config* c) {
-    if (check_params(p) != KAZE_OK || check_sg_config(c) != KAZE_OK ||
+    if (check_params(p) != KAZE_OK || p->scheme != KAZE_AOS || check_sg_config(c) != KAZE_OK ||
         check_size(W, H) != KAZE_OK)
         return 0;
     const int shape = c->aos_shape >= 0 ? c->aos_shape : 0;
@@ -1116,6 +1182,8 @@ kaze_status kaze_sg_scale_space_create(const kaze_image_desc* im, const kaze_par
     *out = nullptr;
     kaze_status st = check_params(p);
     if (st != KAZE_OK) return st;
+    if (p->scheme != KAZE_AOS)
+        return fail(KAZE_ERR_UNSUPPORTED, "the surrogate falls back to AOS steps only");
     if ((st = check_steps(p)) != KAZE_OK) return st;
     if ((st = check_sg_config(c)) != KAZE_OK) return st;
     if (!im) return fail(KAZE_ERR_INVALID_ARG, "image descriptor is NULL");

@@ -265,6 +265,7 @@ enum KernelId {
     K_SG_CONV,
     K_SG_CONV6,
     K_SG_PROBE,
+    K_FED,
     K_COUNT
 };
 

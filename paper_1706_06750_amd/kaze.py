@@ -21,6 +21,8 @@ KAZE_ERR_HIP = -3
 KAZE_ERR_UNSUPPORTED = -4
 KAZE_G1 = 1
 KAZE_G2 = 2
+KAZE_AOS = 0
+KAZE_FED = 1
 
 # Every symbol include/kaze.h declares.
 EXPORTS = (
@@ -30,7 +32,7 @@ EXPORTS = (
     "kaze_last_error", "kaze_profile_begin", "kaze_profile_end",
     "kaze_kernel_names", "kaze_copy_f32", "kaze_batch_workspace_bytes",
     "kaze_batch_create", "kaze_batch_run", "kaze_batch_destroy", "kaze_batch_autotune",
-    "kaze_batch_properties",
+    "kaze_batch_properties", "kaze_fed_schedule", "kaze_fed_cycle",
 )
 
 
@@ -51,6 +53,7 @@ class kaze_params(ctypes.Structure):
         ("k_percentile", ctypes.c_double),
         ("k_override", ctypes.c_double),
         ("det_threshold", ctypes.c_double),
+        ("scheme", ctypes.c_int),
     ]
 
 
@@ -91,6 +94,8 @@ def _load():
         "kaze_build_scale_space": (i32, [vp, i32, i32, i32, P, vp, vp, vp, sz, vp]),
         "kaze_conductivity": (i32, [vp, i32, i32, P, f64, vp, vp]),
         "kaze_aos_step": (i32, [vp, vp, i32, i32, f64, vp, vp, sz, vp]),
+        "kaze_fed_schedule": (i32, [f64, vp, i32]),
+        "kaze_fed_cycle": (i32, [vp, vp, i32, i32, f64, vp, vp, sz, vp]),
         "kaze_detector_response": (i32, [vp, i32, i32, P, vp, vp]),
         "kaze_find_extrema": (i32, [vp, i32, i32, P, vp, i32, vp, vp]),
         "kaze_last_error": (ctypes.c_char_p, []),
@@ -183,6 +188,22 @@ def kaze_conductivity(L, W, H, p, k, g, stream=None):
 def kaze_aos_step(L, g, W, H, tau, L_next, ws, ws_bytes, stream=None):
     _check(lib.kaze_aos_step(_ptr(L), _ptr(g), W, H, float(tau), _ptr(L_next), _ptr(ws),
                              ws_bytes, _stream(stream)))
+
+
+def kaze_fed_schedule(T):
+    """Step sizes of one FED cycle of total time T in application order
+    (list of floats)."""
+    n = lib.kaze_fed_schedule(float(T), None, 0)
+    if n < 0:
+        _check(n)
+    buf = (ctypes.c_double * n)()
+    lib.kaze_fed_schedule(float(T), ctypes.cast(buf, ctypes.c_void_p), n)
+    return [buf[i] for i in range(n)]
+
+
+def kaze_fed_cycle(L, g, W, H, T, L_next, ws, ws_bytes, stream=None):
+    _check(lib.kaze_fed_cycle(_ptr(L), _ptr(g), W, H, float(T), _ptr(L_next), _ptr(ws), ws_bytes,
+                              _stream(stream)))
 
 
 def kaze_detector_response(levels, W, H, p, det, stream=None):

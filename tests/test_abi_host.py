@@ -263,3 +263,19 @@ def test_surrogate_rejects_before_launch(K):
         S.kaze_sg_pack(fake, fake + 4, stream=0)
     with pytest.raises(K.KazeError):        # bad Adam hyper-parameters
         S.kaze_sg_adam(fake, fake, fake, fake, 10, 1, lr=-1.0, stream=0)
+
+
+def test_fed_scheme_is_single_image_only(K):
+    p = K.kaze_default_params()
+    assert p.scheme == K.KAZE_AOS
+    p.scheme = K.KAZE_FED
+    D = K.kaze_image_desc
+    small = [D(256, 100, 80, 100, 512, 1024, 2048, 4096, 10, 8192)]
+    assert K.kaze_batch_workspace_bytes(small, p) == 0
+    q = K.kaze_default_params()
+    fed_ws = K.kaze_workspace_bytes(100, 80, p)
+    aos_ws = K.kaze_workspace_bytes(100, 80, q)
+    assert fed_ws >= aos_ws + 100 * 80 * 4   # the second plane of the explicit steps
+    p.scheme = 7
+    assert K.kaze_workspace_bytes(100, 80, p) == 0
+
