@@ -71,6 +71,7 @@ __all__ = [
     "aos_solve_cols", "aos_step", "build_scale_space", "derivative_step",
     "detector_response", "find_extrema", "FED_TAU_MAX", "fed_step_sizes",
     "fed_order", "diffusion_operator", "explicit_step", "fed_cycle",
+    "EDGE_RATIO", "quadratic_fit_3x3", "refine_keypoints",
 ]
 
 DEFAULTS = dict(sigma0=1.6, octaves=4, sublevels=4, sigma_cond=1.0,
@@ -313,6 +314,73 @@ def fed_cycle(L: np.ndarray, g: np.ndarray, T: float) -> np.ndarray:
     for j in fed_order(tau):
         out = explicit_step(out, g, tau[j])
     return out
+
+
+# Keypoint refinement (Sec. II-B, Eqs. 9-12).
+#
+# Readings: the "two-dimensional quadratic function" fitted to the 3x3
+# detector responses is the least-squares fit of
+#   q(u, v) = a + b u + c v + d u^2 + e v^2 + f u v,   u, v in {-1, 0, 1},
+# to the nine samples; its stationary point gives the sub-pixel offset and
+# its value there the refined response.  The Hessian of Eqs. 9-12 ("from 8
+# points around" the candidate) is that of the same quadratic,
+# [[2d, f], [f, 2e]]; Eq. 10's trace is D_xx + D_yy (the printed D_xy is a
+# typo); the ratio r of Eq. 12 is not given in the paper and is taken as 10,
+# SIFT's value.  A candidate is kept when its Hessian is negative definite
+# (a maximum), Tr(H)^2 / Det(H) < (r + 1)^2 / r and both offsets are at most
+# one pixel.
+EDGE_RATIO = 10.0
+
+
+def quadratic_fit_3x3(p: np.ndarray):
+    """Least-squares coefficients (a, b, c, d, e, f) of the quadratic above
+    for a 3x3 patch p[v + 1][u + 1] (rows v, columns u).
+
+    On the 3x3 grid the regressors 1, u, v, u^2 - 2/3, v^2 - 2/3 and u v are
+    mutually orthogonal, so each coefficient is a projection."""
+    p = np.asarray(p, dtype=np.float64)
+    u = np.array([-1.0, 0.0, 1.0])
+    U, V = np.meshgrid(u, u)          # U[v][u] = u, V[v][u] = v
+    b = (p * U).sum() / (U * U).sum()
+    c = (p * V).sum() / (V * V).sum()
+    f = (p * U * V).sum() / (U * U * V * V).sum()
+    Uc, Vc = U * U - 2.0 / 3.0, V * V - 2.0 / 3.0
+    d = (p * Uc).sum() / (Uc * Uc).sum()
+    e = (p * Vc).sum() / (Vc * Vc).sum()
+    a = p.mean() - 2.0 / 3.0 * (d + e)
+    return a, b, c, d, e, f
+
+
+def refine_keypoints(det: np.ndarray, kps: np.ndarray, edge_ratio: float = EDGE_RATIO):
+    """Sub-pixel position, refined response and edge test of every extremum.
+
+    kps: (n, 4) rows (level, y, x, response) as from find_extrema.
+    Returns (n, 6) float64 rows (level, y + dv, x + du, q(du, dv), ratio,
+    kept) with ratio = Tr(H)^2 / Det(H) (inf when Det(H) <= 0) and kept 1.0
+    or 0.0."""
+    det = np.asarray(det, dtype=np.float64)
+    out = []
+    thr = (edge_ratio + 1.0) ** 2 / edge_ratio
+    for lev, y, x, _ in np.asarray(kps, dtype=np.float64).reshape(-1, 4):
+        lev, y, x = int(lev), int(y), int(x)
+        a, b, c, d, e, f = quadratic_fit_3x3(det[lev, y - 1:y + 2, x - 1:x + 2])
+        hxx, hyy, hxy = 2.0 * d, 2.0 * e, f
+        dt = hxx * hyy - hxy * hxy
+        tr = hxx + hyy
+        ratio = tr * tr / dt if dt > 0.0 else np.inf
+        if dt != 0.0:
+            du = -(hyy * b - hxy * c) / dt
+            dv = -(hxx * c - hxy * b) / dt
+        else:
+            du = dv = np.inf
+        maximum = dt > 0.0 and tr < 0.0
+        kept = maximum and ratio < thr and abs(du) <= 1.0 and abs(dv) <= 1.0
+        if np.isfinite(du) and np.isfinite(dv):
+            val = a + b * du + c * dv + d * du * du + e * dv * dv + f * du * dv
+        else:
+            val = np.nan
+        out.append((lev, y + dv, x + du, val, ratio, 1.0 if kept else 0.0))
+    return np.array(out, dtype=np.float64).reshape(-1, 6)
 
 
 def build_scale_space(img: np.ndarray, sigma0: float = 1.6, octaves: int = 4,
