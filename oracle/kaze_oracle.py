@@ -42,6 +42,15 @@ design notes):
 * Extrema (Sec. II-B, the 3x3 "approximate" variant): levels 1..N-2, pixels
   1..W-2 x 1..H-2, response strictly above the threshold and strictly above
   all 26 neighbours in the 3x3x3 block; maxima only.
+* Extrema, the "exact" variant (Sec. II-B, Sec. III-B, Sec. IV): the same
+  candidates (threshold, 3x3 maximum in their own level), which must also
+  lie strictly above every response of levels i-1 and i+1 in a square
+  window centred on them whose side is the odd number nearest sigma_i, at
+  least 3: half-side h_i = max(1, round((sigma_i - 1) / 2)) with sigma_i the
+  candidate level's scale of Eq. 6 (1 at the first levels, 10 at the last of
+  the default 16).  Window pixels outside the image are left out.  With
+  h_i = 1 this is the approximate variant, and every larger window only
+  adds comparisons, so the exact set is a subset (as the paper observes).
 * FED (Eq. 5, the scheme the paper's own GPU code runs): the step from
   t_{i-1} to t_i (length T = tau_i) is one cycle of n explicit steps
   L <- L + tau_j sum_l A_l(g) L with the same A_l as the AOS step and g
@@ -69,7 +78,7 @@ __all__ = [
     "scharr_dx", "scharr_dy", "gradient_magnitude", "contrast_factor",
     "conductivity_g2", "conductivity_g1", "aos_line_bands", "aos_solve_rows",
     "aos_solve_cols", "aos_step", "build_scale_space", "derivative_step",
-    "detector_response", "find_extrema", "FED_TAU_MAX", "fed_step_sizes",
+    "detector_response", "find_extrema", "cross_level_radius", "FED_TAU_MAX", "fed_step_sizes",
     "fed_order", "diffusion_operator", "explicit_step", "fed_cycle",
     "EDGE_RATIO", "quadratic_fit_3x3", "refine_keypoints",
 ]
@@ -442,12 +451,22 @@ def detector_response(levels: np.ndarray, sigma0: float = 1.6,
     return out
 
 
-def find_extrema(det: np.ndarray, threshold: float = 0.001) -> np.ndarray:
-    """3x3x3 maxima above the threshold (Sec. II-B).
+def cross_level_radius(sigma: float) -> int:
+    """Half-side h of the sigma x sigma window of the exact cross-level
+    check: 2h + 1 is the odd side nearest sigma (round half up), at least 3."""
+    return max(1, int(math.floor((sigma - 1.0) / 2.0 + 0.5)))
 
-    Returns an int64/float64 record array sorted by (level, y, x) with
-    columns level, y, x and response, as an (n, 4) float64 array.
+
+def find_extrema(det: np.ndarray, threshold: float = 0.001, radii=None) -> np.ndarray:
+    """3x3x3 maxima above the threshold (Sec. II-B), or with ``radii`` (one
+    half-side per level) the exact variant: 3x3 maxima of their own level
+    that also exceed levels i-1 and i+1 on the window of half-side radii[i].
+
+    Returns an (n, 4) float64 array with columns level, y, x and response,
+    sorted by (level, y, x).
     """
+    if radii is not None:
+        return _find_extrema_windowed(det, threshold, radii)
     det = np.asarray(det, dtype=np.float64)
     N, H, W = det.shape
     rows = []
@@ -469,3 +488,30 @@ def find_extrema(det: np.ndarray, threshold: float = 0.001) -> np.ndarray:
     if not rows:
         return np.zeros((0, 4))
     return np.array(sorted(rows), dtype=np.float64)
+
+
+def _find_extrema_windowed(det, threshold, radii):
+    det = np.asarray(det, dtype=np.float64)
+    N, H, W = det.shape
+    rows = []
+    if H < 3 or W < 3:
+        return np.zeros((0, 4))
+    for i in range(1, N - 1):
+        h = int(radii[i])
+        # candidates: above the threshold and above the 8 neighbours of level i
+        c = det[i, 1:H - 1, 1:W - 1]
+        mask = c > threshold
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if dy or dx:
+                    mask &= c > det[i, 1 + dy:H - 1 + dy, 1 + dx:W - 1 + dx]
+        for y, x in zip(*np.nonzero(mask)):
+            y, x = int(y) + 1, int(x) + 1
+            v = det[i, y, x]
+            y0, y1 = max(0, y - h), min(H, y + h + 1)
+            x0, x1 = max(0, x - h), min(W, x + h + 1)
+            if np.all(v > det[i - 1, y0:y1, x0:x1]) and np.all(v > det[i + 1, y0:y1, x0:x1]):
+                rows.append((i, y, x, v))
+    if not rows:
+        return np.zeros((0, 4))
+    return np.array(rows, dtype=np.float64)
