@@ -37,6 +37,11 @@ DET_ALGO_BYTES_PER_PX = 8
 AOS_KERNELS = ("aos_reduce", "aos_iface", "aos_recover")
 
 
+def tile_label(K, shape):
+    """Width x height of the AOS tile of a shape, e.g. '60x32'."""
+    return "%dx%d" % K.AOS_SHAPES[shape]
+
+
 def traffic_from_profile(key, aos_tile, with_det):
     """HBM bytes per step of the level segment from the committed counter
     summary profiles/level_traffic_<key>.json, if it was taken on the current
@@ -224,12 +229,12 @@ def bench_single(args, K, torch, kaze_image, case):
     torch.cuda.synchronize()
     elapsed, level_us = timed_graph_runs(args, K, torch, kb)
     roof = level_roofline(level_us, W * H,
-                          traffic_from_profile("%dx%d" % (W, H), "%dx%d" % K.AOS_SHAPES[kb.shape],
+                          traffic_from_profile("%dx%d" % (W, H), tile_label(K, kb.shape),
                                                kb.det_in_level_segment),
                           with_det=kb.det_in_level_segment)
     roof["timed_in"] = "the timed region (event pair around each run's AOS segment)"
     kps = int(kb.count[0].item())
-    shape = K.AOS_SHAPES[kb.shape]
+    shape = tile_label(K, kb.shape)
     kb.close()
 
     extra = {"eager_images_per_s": round(eager_value, 3),
@@ -244,7 +249,7 @@ def bench_single(args, K, torch, kaze_image, case):
         extra["cpu_baseline"] = cpu_baseline(W, H, seed)
     config = {"workload": args.workload, "image": "%dx%d" % (W, H), "seed": seed,
               "levels": kz.N, "path": "plain AOS (no surrogate), graph replay",
-              "aos_tile": "%dx%d" % shape, "keypoints": kps}
+              "aos_tile": shape, "keypoints": kps}
     return record(args, args.steps / elapsed, 1e3 * elapsed / args.steps, config, roof, extra)
 
 
@@ -349,8 +354,7 @@ def bench_batch(args, K, torch, kaze_image, cases):
     elapsed, level_us = timed_graph_runs(args, K, torch, kb)
     roof = level_roofline(level_us, px,
                           traffic_from_profile(args.workload.replace("kaze_", ""),
-                                               "%dx%d" % K.AOS_SHAPES[kb.shape],
-                                               kb.det_in_level_segment),
+                                               tile_label(K, kb.shape), kb.det_in_level_segment),
                           with_det=kb.det_in_level_segment)
     roof["timed_in"] = "the timed region (event pair around each run's AOS segment)"
 
@@ -361,7 +365,7 @@ def bench_batch(args, K, torch, kaze_image, cases):
                                                        min(h for _, h in sizes),
                                                        max(h for _, h in sizes)),
               "levels": kb.N, "path": "plain AOS, batched, graph replay",
-              "aos_tile": "%dx%d" % K.AOS_SHAPES[kb.shape],
+              "aos_tile": tile_label(K, kb.shape),
               "autotune_ms_per_shape": kb.tune_ms}
     extra = {"megapixels_per_s": round(px * args.steps / elapsed / 1e6, 1)}
     plain_value = n * args.steps / elapsed

@@ -58,6 +58,14 @@ typedef enum { KAZE_G1 = 1, KAZE_G2 = 2 } kaze_diffusivity;
  *             kaze_fed_schedule). */
 typedef enum { KAZE_AOS = 0, KAZE_FED = 1 } kaze_scheme;
 
+/* Cross-level window of the extrema test (Sec. II-B, Sec. III-B, Sec. IV):
+ *   KAZE_WINDOW_3X3    the "approximate" test: 3x3 in levels i-1 and i+1;
+ *   KAZE_WINDOW_SIGMA  the "exact" test: a square window of side 2h+1 in
+ *                      levels i-1 and i+1, the odd side nearest sigma_i
+ *                      (h = max(1, round((sigma_i - 1)/2)), half up),
+ *                      clipped at the image border. */
+typedef enum { KAZE_WINDOW_3X3 = 0, KAZE_WINDOW_SIGMA = 1 } kaze_extrema_window;
+
 /*
  * Parameters of the method (host struct, read during the call only).
  * kaze_default_params() fills the values used throughout: sigma0 = 1.6,
@@ -75,6 +83,7 @@ typedef struct {
     double k_override;     /* > 0: use this contrast factor, skip the histogram */
     double det_threshold;  /* detector threshold of Sec. II-B (compared in FP32) */
     int    scheme;         /* KAZE_AOS (default) or KAZE_FED                     */
+    int    extrema_window; /* KAZE_WINDOW_3X3 (default) or KAZE_WINDOW_SIGMA     */
 } kaze_params;
 
 /* One detected extremum: pixel position, level index and det response. */
@@ -84,6 +93,15 @@ typedef struct {
     int   level;
     float response;
 } kaze_keypoint;
+
+/* A refined extremum (kaze_refine_keypoints). */
+typedef struct {
+    float x, y;        /* sub-pixel position                                   */
+    int   level;
+    float response;    /* value of the fitted quadratic at its maximum         */
+    float edge_ratio;  /* Tr(H)^2 / Det(H) of Eqs. 10-12; +inf if Det(H) <= 0   */
+    int   kept;        /* 1: a maximum, edge_ratio below (r+1)^2/r, |offset| <= 1 */
+} kaze_keypoint_refined;
 
 /* Fills *p with the defaults listed above.  Returns KAZE_ERR_INVALID_ARG
  * for a NULL pointer. */
@@ -201,10 +219,11 @@ kaze_status kaze_detector_response(const float* levels, int W, int H,
                                    void* stream);
 
 /*
- * 3x3x3 non-maximum suppression (Sec. II-B, the 3x3 cross-level window):
- * (x, y, i) is reported iff 1 <= i <= N-2, 1 <= x <= W-2, 1 <= y <= H-2,
- * det_i(x, y) > det_threshold and det_i(x, y) is strictly greater than its
- * 26 neighbours in levels i-1, i, i+1.
+ * Non-maximum suppression (Sec. II-B): (x, y, i) is reported iff
+ * 1 <= i <= N-2, 1 <= x <= W-2, 1 <= y <= H-2, det_i(x, y) > det_threshold,
+ * det_i(x, y) is strictly greater than its 8 neighbours in level i and than
+ * every response of levels i-1 and i+1 in the cross-level window of
+ * p->extrema_window (3x3: the 26 neighbours of the 3x3x3 block).
  *   det      (device) input, N x H x W float32.
  *   kps      (device) output array of `capacity` keypoints (may be NULL if
  *            capacity is 0).  Only min(*count, capacity) entries are
@@ -238,10 +257,10 @@ typedef struct {
 #define KAZE_AOS_SHAPES 2
 
 /* Tile shape of the row/column solves (width x height of the blocks of the
- * reduction and recovery launches): 0 = 60x32, 1 = 60x64; -1 = default (0).
- * Row lines are always cut into chunks of 30 pixels and column lines into
- * chunks of 32, so both shapes compute the same result; they differ in
- * occupancy only.  Every shape fits every image size. */
+ * reduction and recovery launches): 0 = 60x32, 1 = 60x64; -1 = default (0).  Row lines are always cut into chunks of 30 pixels and
+ * column lines into chunks of 32, and every shape evaluates the same
+ * arithmetic, so all give the same result; they differ in speed only.
+ * Every shape fits every image size. */
 typedef struct {
     int aos_shape;
 } kaze_batch_config;
@@ -298,6 +317,29 @@ kaze_status kaze_batch_autotune(const kaze_image_desc* images, int n,
                                 const kaze_params* p, void* ws, size_t ws_bytes,
                                 int reps, void* stream, kaze_batch_config* best,
                                 double* ms_per_shape);
+
+/*
+ * Sub-pixel refinement and edge test of extrema (Sec. II-B, Eqs. 9-12).
+ * For keypoint i (i < min(*count, capacity)) the detector responses of its
+ * level in the 3x3 window around it are fitted in the least-squares sense by
+ *   q(u, v) = a + b u + c v + d u^2 + e v^2 + f u v,  u, v in {-1, 0, 1};
+ * the stationary point of q gives the offset (u*, v*) and q(u*, v*) the
+ * refined response, H = [[2d, f], [f, 2e]] is the Hessian of Eq. 9, and the
+ * keypoint is kept when H is negative definite, Tr(H)^2 / Det(H) <
+ * (r+1)^2 / r (Eq. 12, r = edge_ratio) and |u*|, |v*| <= 1.
+ *   det       (device) N x H x W detector responses (kaze_detector_response).
+ *   kps       (device) extrema as written by kaze_find_extrema; an entry
+ *             without a full 3x3 window in its level gets kept = 0 and NaN
+ *             response and edge_ratio.
+ *   count     (device) 1 int: the number of extrema (read on the device).
+ *   capacity  entries of kps and out.
+ *   edge_ratio  r of Eq. 12, > 1 (the paper gives none; 10 is SIFT's).
+ *   out       (device) capacity entries; entry i refines kps[i].
+ */
+kaze_status kaze_refine_keypoints(const float* det, int W, int H, const kaze_params* p,
+                                  const kaze_keypoint* kps, const int* count, int capacity,
+                                  double edge_ratio, kaze_keypoint_refined* out,
+                                  void* stream);
 
 /* Message for the most recent non-OK status returned on this thread. */
 const char* kaze_last_error(void);

@@ -59,6 +59,7 @@ __device__ __forceinline__ float coupling(bool inside, float tau, float ga, floa
 template <int M, bool CHECK = true, bool PRE = false, class Acc>
 __device__ __forceinline__ void chunk_reduce(const Acc& A, int pos0, int n, float tau, Eq& E0,
                                              Eq& E1) {
+#pragma clang fp contract(off)
     float gm = A.g(-1), Lm = A.L(-1), g0 = A.g(0), L0 = A.L(0);
     float gp = A.g(1), Lp = A.L(1);
     float wl = coupling<true, PRE>(pos0 > 0 && pos0 < n, tau, gm, g0);
@@ -76,13 +77,13 @@ __device__ __forceinline__ void chunk_reduce(const Acc& A, int pos0, int n, floa
         gp = A.g(k + 1);
         Lp = A.L(k + 1);
         wr = coupling<CHECK, PRE>(pos0 + k < n - 1, tau, g0, gp);
-        const float d = wl * (Lm - L0) + wr * (Lp - L0);
-        const float r = rcp(1.f + wl + wr + wl * cp);
-        dp = (d + wl * dp) * r;
-        ep = wl * ep * r;
+        const float d = __builtin_fmaf(wl, Lm - L0, wr * (Lp - L0));
+        const float r = rcp(__builtin_fmaf(wl, cp, (1.f + wl) + wr));
+        dp = __builtin_fmaf(wl, dp, d) * r;
+        ep = (wl * ep) * r;
         cp = -wr * r;
-        al += P * dp;
-        be += P * ep;
+        al = __builtin_fmaf(P, dp, al);
+        be = __builtin_fmaf(P, ep, be);
         P = -P * cp;
         wl = wr;
         Lm = L0;
@@ -102,6 +103,7 @@ __device__ __forceinline__ void chunk_reduce(const Acc& A, int pos0, int n, floa
 template <int M, bool CHECK = true, bool PRE = false, class Acc>
 __device__ __forceinline__ void chunk_recover(const Acc& A, int pos0, int n, float tau, float z0,
                                               float z1, float (&x)[M]) {
+#pragma clang fp contract(off)
     float cpa[M];
     float gm = A.g(0), Lm = A.L(0), g0 = A.g(1), L0 = A.L(1);
     float wl = coupling<CHECK, PRE>(pos0 + 1 < n, tau, gm, g0);
@@ -110,20 +112,20 @@ __device__ __forceinline__ void chunk_recover(const Acc& A, int pos0, int n, flo
     for (int k = 1; k <= M - 2; ++k) {
         const float gp = A.g(k + 1), Lp = A.L(k + 1);
         const float wr = coupling<CHECK, PRE>(pos0 + k < n - 1, tau, g0, gp);
-        float d = wl * (Lm - L0) + wr * (Lp - L0);
-        const float b = 1.f + wl + wr;
+        float d = __builtin_fmaf(wl, Lm - L0, wr * (Lp - L0));
+        const float b = (1.f + wl) + wr;
         float a = -wl, c = -wr;
         if (k == 1) {
-            d -= a * z0;
+            d = __builtin_fmaf(-a, z0, d);
             a = 0.f;
         }
         if (k == M - 2) {
-            d -= c * z1;
+            d = __builtin_fmaf(-c, z1, d);
             c = 0.f;
         }
-        const float r = rcp(b - a * cp);
+        const float r = rcp(__builtin_fmaf(-a, cp, b));
         cp = c * r;
-        dp = (d - a * dp) * r;
+        dp = __builtin_fmaf(-a, dp, d) * r;
         cpa[k] = cp;
         x[k] = dp;
         wl = wr;
@@ -134,7 +136,7 @@ __device__ __forceinline__ void chunk_recover(const Acc& A, int pos0, int n, flo
     x[0] = z0;
     x[M - 1] = z1;
 #pragma unroll
-    for (int k = M - 2; k >= 1; --k) x[k] -= cpa[k] * x[k + 1];
+    for (int k = M - 2; k >= 1; --k) x[k] = __builtin_fmaf(-cpa[k], x[k + 1], x[k]);
 }
 
 // LDS accessor of one chunk with compile-time strides: element k (which may
@@ -207,10 +209,10 @@ constexpr int kRedThreads = 256;
 // times `scale`; wavefront w loads rows w, w+4, ...; lane l loads columns l
 // and 64 + l (those below NX).  All loads of a lane are issued before its
 // first LDS store.
-template <int NY, int NX, int P>
+template <int NY, int NX, int P, int NT = kRedThreads>
 __device__ __forceinline__ void load_region(const float* src, int W, int H, int gy0, int gx0,
                                             float scale, float* dst, int wave, int lane) {
-    constexpr int WAVES = kRedThreads / kWave;
+    constexpr int WAVES = NT / kWave;
     constexpr int PER = (NY + WAVES - 1) / WAVES;
     const gfloat* gs = (const gfloat*)src;
     const bool has_a = lane < NX;
@@ -244,73 +246,88 @@ __device__ __forceinline__ float diffusivity_of(float m2k) {
     return GM == 0 ? __builtin_amdgcn_rcpf(1.f + m2k) : expf(-m2k);
 }
 
-// Phases 2-3 of the reduction with the conductivity: S = Gaussian of L on
-// the tile + 2 ring (one lane per column; each wavefront a band of rows;
-// the horizontal pass is recomputed along the band in registers, the
-// vertical pass rolls over it), then the 3x3 Scharr gradient of S and g on
-// the tile + 1 ring: tau * g into LDS for the sweeps, g (tile interior) to
-// gout for the recovery.
+// The Gaussian-smoothed image S on rows [s0, s0 + SPW) of a grid of 64
+// columns (one lane per column) whose element (s, j) is the Gaussian of the
+// L region around (s + r, j + r): the horizontal pass is recomputed along
+// the band in registers, the vertical pass rolls over it.
+template <int r, int SPW, int PL, int PS>
+__device__ __forceinline__ void smooth_band(const float* sL, float* sS, int s0, int lane,
+                                            const float (&w)[2 * r + 1]) {
+#pragma clang fp contract(off)
+    float h[SPW + 2 * r];
+    const float* lp = sL + s0 * PL + lane;
+#pragma unroll
+    for (int k = 0; k < SPW + 2 * r; ++k) {
+        const float* q = lp + k * PL;
+        float acc = w[r] * q[r];
+#pragma unroll
+        for (int t = 0; t < r; ++t) acc = __builtin_fmaf(w[t], q[t] + q[2 * r - t], acc);
+        h[k] = acc;
+    }
+    float* sp = sS + s0 * PS + lane;
+#pragma unroll
+    for (int k = 0; k < SPW; ++k) {
+        float acc = w[r] * h[k + r];
+#pragma unroll
+        for (int t = 0; t < r; ++t) acc = __builtin_fmaf(w[t], h[k + t] + h[k + 2 * r - t], acc);
+        sp[k * PS] = acc;
+    }
+}
+
+// Conductivity on rows [q0, q0 + QPW) of a grid whose element (q, i) is
+// centred on S(q + 1, i + 1): the 3x3 Scharr gradient of S (unscaled:
+// Lx' = 32 Lx, Ly' = 32 Ly, so |grad|^2 = m2' / 1024, folded into c2 =
+// 1/(1024 k^2)) and g of Eq. 3 for column ic, into gv.
+template <int QPW, int PS, int GM>
+__device__ __forceinline__ void conductivity_band(const float* sS, int q0, int ic, float c2,
+                                                  float (&gv)[QPW]) {
+#pragma clang fp contract(off)
+    const float* sp = sS + q0 * PS + ic;
+    float D[QPW + 2], Tt[QPW + 2];
+#pragma unroll
+    for (int k = 0; k < QPW + 2; ++k) {
+        const float a = sp[k * PS], b = sp[k * PS + 1], c = sp[k * PS + 2];
+        D[k] = c - a;
+        Tt[k] = __builtin_fmaf(10.f, b, 3.f * (a + c));
+    }
+#pragma unroll
+    for (int k = 0; k < QPW; ++k) {
+        const float lx = __builtin_fmaf(10.f, D[k + 1], 3.f * (D[k] + D[k + 2]));
+        const float ly = Tt[k + 2] - Tt[k];
+        gv[k] = diffusivity_of<GM>(__builtin_fmaf(lx, lx, ly * ly) * c2);
+    }
+}
+
+// Phases 2-3 of the reduction with the conductivity: S on the tile + 2 ring
+// (each wavefront a band of rows), then g on the tile + 1 ring: tau * g into
+// LDS for the sweeps and g of the tile to gout for the recovery.
 template <int RG, int TY, int GM>
 __device__ __forceinline__ void tile_conductivity(const float* sL, float* sS, float* sG,
                                                   const Taps& tc, float inv_k2, float tau,
                                                   float* gout, int W, int H, int tx0, int ty0,
                                                   int wave, int lane) {
     using G = RedGeom<RG, TY, true>;
-    constexpr int r = RG, T = 2 * RG + 1;
+    constexpr int T = 2 * RG + 1;
     float w[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) w[t] = tc.w[t];
-    {
-        const int s0 = wave * G::SPW;
-        float h[G::SPW + 2 * r];
-        const float* lp = sL + s0 * G::PL + lane;
-#pragma unroll
-        for (int k = 0; k < G::SPW + 2 * r; ++k) {
-            const float* q = lp + k * G::PL;
-            float acc = w[r] * q[r];
-#pragma unroll
-            for (int t = 0; t < r; ++t) acc += w[t] * (q[t] + q[2 * r - t]);
-            h[k] = acc;
-        }
-        float* sp = sS + s0 * G::PS + lane;
-#pragma unroll
-        for (int k = 0; k < G::SPW; ++k) {
-            float acc = w[r] * h[k + r];
-#pragma unroll
-            for (int t = 0; t < r; ++t) acc += w[t] * (h[k + t] + h[k + 2 * r - t]);
-            sp[k * G::PS] = acc;
-        }
-    }
+    smooth_band<RG, G::SPW, G::PL, G::PS>(sL, sS, wave * G::SPW, lane, w);
     __syncthreads();
-    // g rows [q0, q0 + QPW): g(q, i) from S rows q..q+2, columns i..i+2.
-    // Unscaled Scharr: Lx' = 32 Lx, Ly' = 32 Ly, so |grad|^2 = m2' / 1024.
-    {
-        const int q0 = wave * G::QPW;
-        const int ic = lane < G::NGX ? lane : G::NGX - 1;
-        const float c2 = inv_k2 * (1.f / 1024.f);
-        const float* sp = sS + q0 * G::PS + ic;
-        float D[G::QPW + 2], Tt[G::QPW + 2];
+    const int q0 = wave * G::QPW;
+    float gv[G::QPW];
+    conductivity_band<G::QPW, G::PS, GM>(sS, q0, lane < G::NGX ? lane : G::NGX - 1,
+                                         inv_k2 * (1.f / 1024.f), gv);
+    const bool lane_g = lane < G::NGX;
+    const bool col_in = lane >= 1 && lane <= kAosTX && tx0 - 1 + lane < W;
+    float* gl = sG + q0 * G::PG + lane;
+    gfloat* grow = (gfloat*)gout + (ptrdiff_t)uniform(ty0 - 1 + q0) * W + (tx0 - 1);
 #pragma unroll
-        for (int k = 0; k < G::QPW + 2; ++k) {
-            const float a = sp[k * G::PS], b = sp[k * G::PS + 1], c = sp[k * G::PS + 2];
-            D[k] = c - a;
-            Tt[k] = 3.f * (a + c) + 10.f * b;
-        }
-        const bool lane_g = lane < G::NGX;
-        const bool col_in = lane >= 1 && lane <= kAosTX && tx0 - 1 + lane < W;
-        float* gl = sG + q0 * G::PG + lane;
-        gfloat* grow = (gfloat*)gout + (ptrdiff_t)uniform(ty0 - 1 + q0) * W + (tx0 - 1);
-#pragma unroll
-        for (int k = 0; k < G::QPW; ++k) {
-            const float lx = 3.f * (D[k] + D[k + 2]) + 10.f * D[k + 1];
-            const float ly = Tt[k + 2] - Tt[k];
-            const float gv = diffusivity_of<GM>((lx * lx + ly * ly) * c2);
-            const int q = q0 + k;
-            if (q < G::NGY) {
-                if (lane_g) gl[k * G::PG] = tau * gv;
-                if (q >= 1 && q <= TY && ty0 - 1 + q < H && col_in)
-                    grow[(ptrdiff_t)k * W + lane] = gv;
-            }
+    for (int k = 0; k < G::QPW; ++k) {
+        const int q = q0 + k;
+        if (q < G::NGY) {
+            if (lane_g) gl[k * G::PG] = tau * gv[k];
+            if (q >= 1 && q <= TY && ty0 - 1 + q < H && col_in)
+                grow[(ptrdiff_t)k * W + lane] = gv[k];
         }
     }
 }
@@ -503,16 +520,19 @@ __global__ __launch_bounds__(kIfaceThreads) void aos_iface_kernel(ImageDesc d0, 
 }
 
 // Recovery: TY / 32 row and TY / 32 column wavefronts per tile; L and
-// tau * g of the tile (zero outside the image) staged in LDS.  Both sweeps
-// keep their increments in registers; after a barrier the row lanes fold
-// theirs into the LDS copy of L (L + delta_x / 2), and after a second one
-// the column lanes store L_i = L + (delta_x + delta_y)/2 one row at a time
-// (coalesced).  Two LDS planes per tile.
+// tau * g of the tile staged in LDS.  Both sweeps keep their increments in
+// registers; after a barrier the row lanes fold theirs into the LDS copy of
+// L (L + delta_x / 2), and after a second one the column lanes store
+// L_i = L + (delta_x + delta_y)/2 one row at a time (coalesced).
 template <int TY>
 __global__ __launch_bounds__(TY * 4) void aos_recover_kernel(ImageDesc d0, AosWork w, float tau) {
-    constexpr int NT = TY * 4, WAVES = NT / kWave, SW = TY / 32, P = kAosTX + 1;
-    __shared__ float sL[TY * P];
-    __shared__ float sG[TY * P];
+    constexpr int NT = TY * 4, WAVES = NT / kWave, SW = TY / 32;
+    // LDS layout: (row, column) of the tile at sL[row * PL + column], tau * g
+    // at sG[row * PG + column]
+    constexpr int PL = kAosTX + 1, PG = kAosTX + 1;
+    extern __shared__ float smem[];
+    float* sL = smem;
+    float* sG = smem + TY * PL;
     const int tid = threadIdx.x, wave = uniform(tid >> 6), lane = tid & (kWave - 1);
     ImageDesc d;
     int lt;
@@ -538,8 +558,8 @@ __global__ __launch_bounds__(TY * 4) void aos_recover_kernel(ImageDesc d0, AosWo
 #pragma unroll
             for (int i = 0; i < PER; ++i) {
                 const int r = wave + WAVES * i;
-                sL[r * P + lane] = vl[i];
-                sG[r * P + lane] = tau * vg[i];
+                sL[r * PL + lane] = vl[i];
+                sG[r * PG + lane] = tau * vg[i];
             }
         }
     }
@@ -553,7 +573,7 @@ __global__ __launch_bounds__(TY * 4) void aos_recover_kernel(ImageDesc d0, AosWo
     if (row_lane) {
         const int y = ty0 + r, pos0 = tx0 + h * kRowChunk;
         const vf2 z = *(const gvf2*)((const gfloat*)d.zrow + ((size_t)(2 * cx + h) * H + y) * 2);
-        const LdsLine<1, 1> A{sG + r * P + h * kRowChunk, sL + r * P + h * kRowChunk};
+        const LdsLine<1, 1> A{sG + r * PG + h * kRowChunk, sL + r * PL + h * kRowChunk};
         float (&xr)[kRowChunk] = *reinterpret_cast<float (*)[kRowChunk]>(xs);
         if (tx0 + kAosTX < W)
             chunk_recover<kRowChunk, false, true>(A, pos0, W, 1.f, z.x, z.y, xr);
@@ -561,7 +581,7 @@ __global__ __launch_bounds__(TY * 4) void aos_recover_kernel(ImageDesc d0, AosWo
             chunk_recover<kRowChunk, true, true>(A, pos0, W, 1.f, z.x, z.y, xr);
     } else if (col_lane) {
         const vf2 z = *(const gvf2*)((const gfloat*)d.zcol + ((size_t)(pos0c / kColChunk) * W + xcol) * 2);
-        const LdsLine<P, P> A{sG + v * kColChunk * P + c, sL + v * kColChunk * P + c};
+        const LdsLine<PG, PL> A{sG + v * kColChunk * PG + c, sL + v * kColChunk * PL + c};
         if (pos0c + kColChunk < H)
             chunk_recover<kColChunk, false, true>(A, pos0c, H, 1.f, z.x, z.y, xs);
         else
@@ -569,9 +589,9 @@ __global__ __launch_bounds__(TY * 4) void aos_recover_kernel(ImageDesc d0, AosWo
     }
     __syncthreads();
     if (row_lane) {
-        float* lp = sL + r * P + h * kRowChunk;
+        float* lp = sL + r * PL + h * kRowChunk;
 #pragma unroll
-        for (int k = 0; k < kRowChunk; ++k) lp[k] += 0.5f * xs[k];
+        for (int k = 0; k < kRowChunk; ++k) lp[k] = __builtin_fmaf(0.5f, xs[k], lp[k]);
     }
     __syncthreads();
     if (col_lane) {
@@ -580,7 +600,8 @@ __global__ __launch_bounds__(TY * 4) void aos_recover_kernel(ImageDesc d0, AosWo
 #pragma unroll
         for (int k = 0; k < kColChunk; ++k) {
             const int rr = v * kColChunk + k;
-            if (k < rows) ob[(ptrdiff_t)k * W + c] = sL[rr * P + c] + 0.5f * xs[k];
+            if (k < rows)
+                ob[(ptrdiff_t)k * W + c] = __builtin_fmaf(0.5f, xs[k], sL[rr * PL + c]);
         }
     }
 }
@@ -706,10 +727,11 @@ hipError_t launch_reduce_s(const ImageDesc& d0, const AosWork& w, const Taps& tc
 }
 
 template <int TY>
-hipError_t launch_recover_s(const ImageDesc& d0, const AosWork& w, float tau, hipStream_t s) {
+hipError_t launch_recover_t(const ImageDesc& d0, const AosWork& w, float tau, hipStream_t s) {
     const int count = work_count(d0, w, TY, false);
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL((aos_recover_kernel<TY>), dim3(count), dim3(TY * 4), 0, s, d0, w, tau);
+    const size_t lds = (size_t)2 * TY * (kAosTX + 1) * sizeof(float);
+    hipLaunchKernelGGL((aos_recover_kernel<TY>), dim3(count), dim3(TY * 4), lds, s, d0, w, tau);
     return hipGetLastError();
 }
 
@@ -736,8 +758,8 @@ hipError_t launch_aos_iface(const ImageDesc& d0, const AosWork& w, hipStream_t s
 hipError_t launch_aos_recover(const ImageDesc& d0, const AosWork& w, int shape, float tau,
                               hipStream_t s) {
     switch (shape) {
-        case 0: return launch_recover_s<32>(d0, w, tau, s);
-        case 1: return launch_recover_s<64>(d0, w, tau, s);
+        case 0: return launch_recover_t<32>(d0, w, tau, s);
+        case 1: return launch_recover_t<64>(d0, w, tau, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -43,7 +43,7 @@ kaze_status fail(kaze_status st, const char* fmt, ...) {
 const char* const kKernelNames[K_COUNT] = {
     "gauss", "grad", "hist", "kselect", "cond", "aos_reduce", "aos_iface", "aos_recover",
     "det",   "nms",  "fill", "copy",    "sg_pack", "sg_conv1", "sg_conv", "sg_conv6",
-    "sg_probe", "fed"};
+    "sg_probe", "fed", "refine"};
 
 struct Profiler {
     unsigned mask = 0;  // bit i: record launches of kernel i
@@ -140,7 +140,27 @@ kaze_status check_params(const kaze_params* p) {
         return fail(KAZE_ERR_INVALID_ARG, "det_threshold must be finite");
     if (p->scheme != KAZE_AOS && p->scheme != KAZE_FED)
         return fail(KAZE_ERR_INVALID_ARG, "scheme must be KAZE_AOS or KAZE_FED");
+    if (p->extrema_window != KAZE_WINDOW_3X3 && p->extrema_window != KAZE_WINDOW_SIGMA)
+        return fail(KAZE_ERR_INVALID_ARG, "extrema_window must be KAZE_WINDOW_3X3 or KAZE_WINDOW_SIGMA");
     return KAZE_OK;
+}
+
+// Cross-level window half-sides: 1, or for the exact test the h whose side
+// 2h + 1 is the odd number nearest sigma_i (half up), at least 1; capped at
+// the largest image side (the window is clipped to the image anyway).
+NmsRadii nms_radii(const kaze_params* p) {
+    NmsRadii r;
+    const int N = p->octaves * p->sublevels;
+    for (int i = 0; i < kMaxLevels; ++i) r.h[i] = 1;
+    if (p->extrema_window == KAZE_WINDOW_SIGMA) {
+        for (int i = 0; i < N; ++i) {
+            const int o = i / p->sublevels, s = i % p->sublevels;
+            const double sigma = p->sigma0 * pow(2.0, o + (double)s / p->sublevels);
+            const double h = floor((sigma - 1.0) / 2.0 + 0.5);
+            r.h[i] = h < 1.0 ? 1 : (h > kMaxSide ? kMaxSide : (int)h);
+        }
+    }
+    return r;
 }
 
 void schedule(const kaze_params* p, std::vector<Level>& lv) {
@@ -479,7 +499,7 @@ kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStre
     if (B.with_det && !fork) KZ_LAUNCH(K_DET, s, launch_det(b0, det, 0, B.N, dl, s));
     if (B.with_nms) {
         const ImgWork nms{B.d_imgs, B.d_nms, B.n_nms};
-        KZ_LAUNCH(K_NMS, s, launch_nms(b0, nms, B.N, (float)p->det_threshold, s));
+        KZ_LAUNCH(K_NMS, s, launch_nms(b0, nms, B.N, (float)p->det_threshold, nms_radii(p), s));
     }
     return KAZE_OK;
 }
@@ -780,7 +800,8 @@ kaze_status sg_segment(const kaze_sg_scale_space& S, int seg, hipStream_t s) {
     if (seg == 2) {
         if (S.with_det) KZ_LAUNCH(K_DET, s, launch_det(S.b, none, 0, S.N, det_levels(S.lv), s));
         if (S.with_nms)
-            KZ_LAUNCH(K_NMS, s, launch_nms(S.b, none, S.N, (float)p->det_threshold, s));
+            KZ_LAUNCH(K_NMS, s,
+                      launch_nms(S.b, none, S.N, (float)p->det_threshold, nms_radii(p), s));
         return KAZE_OK;
     }
     const Taps tc = gauss_taps(p->sigma_cond);
@@ -850,6 +871,7 @@ kaze_status kaze_default_params(kaze_params* p) {
     p->k_override = 0.0;
     p->det_threshold = 0.001;
     p->scheme = KAZE_AOS;
+    p->extrema_window = KAZE_WINDOW_3X3;
     return KAZE_OK;
 }
 
@@ -977,6 +999,29 @@ kaze_status kaze_aos_step(const float* L, const float* g, int W, int H, double t
                     static_cast<hipStream_t>(stream));
 }
 
+static_assert(sizeof(kaze_keypoint) == 16 && sizeof(kaze_keypoint_refined) == 24,
+              "keypoint records as the kernels write them");
+
+kaze_status kaze_refine_keypoints(const float* det, int W, int H, const kaze_params* p,
+                                  const kaze_keypoint* kps, const int* count, int capacity,
+                                  double edge_ratio, kaze_keypoint_refined* out, void* stream) {
+    kaze_status st = check_params(p);
+    if (st != KAZE_OK) return st;
+    if ((st = check_size(W, H)) != KAZE_OK) return st;
+    if (capacity < 0) return fail(KAZE_ERR_INVALID_ARG, "capacity must be >= 0");
+    if (capacity > 0 && (!det || !kps || !count || !out))
+        return fail(KAZE_ERR_INVALID_ARG, "det, kps, count and out must be non-NULL");
+    if (!aligned(det, 4) || !aligned(kps, 4) || !aligned(count, 4) || !aligned(out, 4))
+        return fail(KAZE_ERR_INVALID_ARG, "buffers must be 4-byte aligned");
+    if (!(edge_ratio > 1.0) || !isfinite(edge_ratio))
+        return fail(KAZE_ERR_INVALID_ARG, "edge_ratio must be > 1");
+    const float thr = (float)((edge_ratio + 1.0) * (edge_ratio + 1.0) / edge_ratio);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int N = kaze_num_levels(p);
+    KZ_LAUNCH(K_REFINE, s, launch_refine(det, W, H, N, kps, count, capacity, thr, out, s));
+    return KAZE_OK;
+}
+
 int kaze_fed_schedule(double T, double* tau, int capacity) {
     if (!(T > 0.0) || !isfinite(T)) return fail(KAZE_ERR_INVALID_ARG, "T must be > 0 and finite");
     const std::vector<double> t = fed_schedule(T);
@@ -1043,7 +1088,8 @@ kaze_status kaze_find_extrema(const float* det, int W, int H, const kaze_params*
     b.count = count;
     const ImgWork none{nullptr, nullptr, 0};
     KZ_LAUNCH(K_FILL, s, launch_reset(b, none, 0, 0.f, s));
-    KZ_LAUNCH(K_NMS, s, launch_nms(b, none, p->octaves * p->sublevels, (float)p->det_threshold, s));
+    KZ_LAUNCH(K_NMS, s, launch_nms(b, none, p->octaves * p->sublevels, (float)p->det_threshold,
+                                   nms_radii(p), s));
     return KAZE_OK;
 }
 

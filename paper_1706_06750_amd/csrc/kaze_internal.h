@@ -52,7 +52,7 @@ __device__ __forceinline__ Eq eq_identity() { return Eq{0.f, 1.f, 0.f, 0.f}; }
 // tau*(g[j-1]+g[j]) and tau*(g[j]+g[j+1]) (zero across the line ends) and
 // dl = L[j-1]-L[j], dr = L[j+1]-L[j].
 __device__ __forceinline__ Eq aos_row(float wl, float wr, float dl, float dr) {
-    return Eq{-wl, 1.f + wl + wr, -wr, wl * dl + wr * dr};
+    return Eq{-wl, (1.f + wl) + wr, -wr, __builtin_fmaf(wl, dl, wr * dr)};
 }
 
 // Parallel cyclic reduction step: eliminate the couplings of e through the
@@ -223,6 +223,15 @@ __device__ __forceinline__ int xcd_contiguous(int t, int n) {
     return x * per + (x < rem ? x : rem) + j;
 }
 
+// Block (x, y) of a 2-D grid remapped so that XCD x receives a contiguous
+// run of the row-major block order (x fastest).
+__device__ __forceinline__ void xcd_grid(int& bx, int& by) {
+    const int gx = (int)gridDim.x, n = gx * (int)gridDim.y;
+    const int t = xcd_contiguous((int)(blockIdx.x + blockIdx.y * gridDim.x), n);
+    bx = t % gx;
+    by = t / gx;
+}
+
 // t must be wave-uniform; the tables are read through the constant address
 // space, so descriptor and item land in scalar registers.
 template <class D>
@@ -266,6 +275,7 @@ enum KernelId {
     K_SG_CONV6,
     K_SG_PROBE,
     K_FED,
+    K_REFINE,
     K_COUNT
 };
 
@@ -317,9 +327,18 @@ hipError_t launch_det(const BatchImage& d0, const ImgWork& w, int lev0, int lev1
                       const DetLevels& dl, hipStream_t s);
 int det_tiles_of(int W, int H);
 // a7: extrema of levels 1..N-2 (items: image, block of 64 x 4*kNmsRows pixels).
+// Half-side of the cross-level window of each level (1: the 3x3x3 test).
+struct NmsRadii {
+    int h[kMaxLevels];
+};
 hipError_t launch_nms(const BatchImage& d0, const ImgWork& w, int N, float threshold,
-                      hipStream_t s);
+                      const NmsRadii& radii, hipStream_t s);
 int nms_blocks_of(int W, int H);
+// Refinement and edge test of capacity-bounded extrema (entries of 16 and 24
+// bytes: kaze_keypoint and kaze_keypoint_refined) on N levels of W x H;
+// thr = (r+1)^2/r.
+hipError_t launch_refine(const float* det, int W, int H, int N, const void* kps,
+                         const int* count, int capacity, float thr, void* out, hipStream_t s);
 hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t s);
 hipError_t launch_copy(const float* src, float* dst, size_t n, hipStream_t s);
 

@@ -23,6 +23,8 @@ KAZE_G1 = 1
 KAZE_G2 = 2
 KAZE_AOS = 0
 KAZE_FED = 1
+KAZE_WINDOW_3X3 = 0
+KAZE_WINDOW_SIGMA = 1
 
 # Every symbol include/kaze.h declares.
 EXPORTS = (
@@ -32,7 +34,7 @@ EXPORTS = (
     "kaze_last_error", "kaze_profile_begin", "kaze_profile_end",
     "kaze_kernel_names", "kaze_copy_f32", "kaze_batch_workspace_bytes",
     "kaze_batch_create", "kaze_batch_run", "kaze_batch_destroy", "kaze_batch_autotune",
-    "kaze_batch_properties", "kaze_fed_schedule", "kaze_fed_cycle",
+    "kaze_batch_properties", "kaze_fed_schedule", "kaze_fed_cycle", "kaze_refine_keypoints",
 )
 
 
@@ -54,12 +56,19 @@ class kaze_params(ctypes.Structure):
         ("k_override", ctypes.c_double),
         ("det_threshold", ctypes.c_double),
         ("scheme", ctypes.c_int),
+        ("extrema_window", ctypes.c_int),
     ]
 
 
 class kaze_keypoint(ctypes.Structure):
     _fields_ = [("x", ctypes.c_int), ("y", ctypes.c_int), ("level", ctypes.c_int),
                 ("response", ctypes.c_float)]
+
+
+class kaze_keypoint_refined(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_float), ("y", ctypes.c_float), ("level", ctypes.c_int),
+                ("response", ctypes.c_float), ("edge_ratio", ctypes.c_float),
+                ("kept", ctypes.c_int)]
 
 
 class kaze_image_desc(ctypes.Structure):
@@ -98,6 +107,7 @@ def _load():
         "kaze_fed_cycle": (i32, [vp, vp, i32, i32, f64, vp, vp, sz, vp]),
         "kaze_detector_response": (i32, [vp, i32, i32, P, vp, vp]),
         "kaze_find_extrema": (i32, [vp, i32, i32, P, vp, i32, vp, vp]),
+        "kaze_refine_keypoints": (i32, [vp, i32, i32, P, vp, vp, i32, f64, vp, vp]),
         "kaze_last_error": (ctypes.c_char_p, []),
         "kaze_profile_begin": (i32, [ctypes.c_char_p]),
         "kaze_profile_end": (i32, [ctypes.POINTER(i32), ctypes.POINTER(f64)]),
@@ -216,6 +226,11 @@ def kaze_find_extrema(det, W, H, p, kps, capacity, count, stream=None):
                                  _ptr(count), _stream(stream)))
 
 
+def kaze_refine_keypoints(det, W, H, p, kps, count, capacity, edge_ratio, out, stream=None):
+    _check(lib.kaze_refine_keypoints(_ptr(det), W, H, ctypes.byref(p), _ptr(kps), _ptr(count),
+                                     capacity, float(edge_ratio), _ptr(out), _stream(stream)))
+
+
 def kaze_copy_f32(src, dst, n, stream=None):
     _check(lib.kaze_copy_f32(_ptr(src), _ptr(dst), n, _stream(stream)))
 
@@ -322,6 +337,35 @@ class Kaze:
         self.scale_space(img, stream)
         self.detector(stream)
         self.extrema(stream)
+
+    def refine(self, edge_ratio=10.0, stream=None):
+        """Sub-pixel refinement and edge test of the extrema of the last
+        run (kaze_refine_keypoints); fills ``self.refined``, an
+        (capacity, 6) int32 tensor of kaze_keypoint_refined records in the
+        order of ``self.kps``."""
+        import torch
+        if getattr(self, "refined", None) is None:
+            self.refined = torch.empty((max(self.capacity, 1), 6), dtype=torch.int32,
+                                       device=self.kps.device)
+        kaze_refine_keypoints(self.det, self.W, self.H, self.p, self.kps, self.count,
+                              self.capacity, edge_ratio, self.refined, stream)
+
+    def refined_keypoints(self):
+        """Host (n, 6) float64 array (level, y, x, response, edge_ratio,
+        kept) of the last refine(), sorted like keypoints(); synchronises."""
+        import numpy as np
+        import torch
+        n = min(int(self.count.item()), self.capacity)
+        raw = self.refined[:n].cpu()
+        f = raw.view(torch.float32).numpy().astype(np.float64)
+        i = raw.numpy()
+        ints = self.kps[:n].cpu().numpy()
+        out = np.stack([i[:, 2], f[:, 1], f[:, 0], f[:, 3], f[:, 4], i[:, 5]], axis=1) \
+            if n else np.zeros((0, 6))
+        if n:
+            order = np.lexsort((ints[:, 0], ints[:, 1], ints[:, 2]))
+            out = out[order]
+        return out
 
     def keypoints(self):
         """Host (n, 4) float64 array (level, y, x, response) sorted by

@@ -23,20 +23,33 @@ def neighbours26(det, lev, y, x):
     return np.array(out)
 
 
-def excused(det_orc, p, threshold):
+def window_neighbours(det, lev, y, x, h):
+    """The 8 neighbours in level lev and the responses of levels lev-1 and
+    lev+1 within h pixels (clipped to the image)."""
+    N, H, W = det.shape
+    own = det[lev, y - 1:y + 2, x - 1:x + 2].ravel()
+    own = np.delete(own, 4)
+    y0, y1, x0, x1 = max(0, y - h), min(H, y + h + 1), max(0, x - h), min(W, x + h + 1)
+    return np.concatenate([own, det[lev - 1, y0:y1, x0:x1].ravel(),
+                           det[lev + 1, y0:y1, x0:x1].ravel()])
+
+
+def excused(det_orc, p, threshold, radii=None):
     lev, y, x = (int(v) for v in p)
     v = det_orc[lev, y, x]
     if abs(v - threshold) < EXCUSE:
         return True
-    nb = neighbours26(det_orc, lev, y, x)
+    nb = neighbours26(det_orc, lev, y, x) if radii is None else \
+        window_neighbours(det_orc, lev, y, x, int(radii[lev]))
     return bool(np.min(np.abs(v - nb)) < EXCUSE)
 
 
-def compare_keypoints(kp_gpu, kp_orc, det_orc, threshold):
-    """Sets on (level, y, x) must agree up to excused points.  Returns
-    (n_common, unexcused_gpu_only, unexcused_oracle_only)."""
+def compare_keypoints(kp_gpu, kp_orc, det_orc, threshold, radii=None):
+    """Sets on (level, y, x) must agree up to excused points (radii: the
+    cross-level window half-sides of the exact test, None for 3x3x3).
+    Returns (n_common, unexcused_gpu_only, unexcused_oracle_only)."""
     g = {tuple(int(v) for v in r[:3]) for r in kp_gpu}
     o = {tuple(int(v) for v in r[:3]) for r in kp_orc}
-    bad_g = [p for p in g - o if not excused(det_orc, p, threshold)]
-    bad_o = [p for p in o - g if not excused(det_orc, p, threshold)]
+    bad_g = [p for p in g - o if not excused(det_orc, p, threshold, radii)]
+    bad_o = [p for p in o - g if not excused(det_orc, p, threshold, radii)]
     return len(g & o), bad_g, bad_o

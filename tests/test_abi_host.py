@@ -111,6 +111,7 @@ def test_defaults_and_schedule_match_oracle(K):
     p = K.kaze_default_params()
     assert (p.octaves, p.sublevels, p.k_bins, p.diffusivity) == (4, 4, 300, K.KAZE_G2)
     assert (p.sigma0, p.sigma_cond, p.k_percentile, p.det_threshold) == (1.6, 1.0, 0.7, 0.001)
+    assert (p.scheme, p.extrema_window) == (K.KAZE_AOS, K.KAZE_WINDOW_3X3)
     sch = K.kaze_schedule(p)
     ref = O.level_schedule(1.6, 4, 4)
     assert len(sch) == len(ref) == K.kaze_num_levels(p)
@@ -141,7 +142,8 @@ def test_workspace_bytes(K):
     ("octaves", 0, -1), ("sublevels", 0, -1), ("octaves", 17, -4), ("sigma0", 0.0, -1),
     ("sigma0", 6.0, -4), ("diffusivity", 3, -1), ("k_percentile", 0.0, -1),
     ("k_percentile", 1.5, -1), ("k_bins", 0, -1), ("k_bins", 5000, -1),
-    ("sigma_cond", 1.4, -4),
+    ("sigma_cond", 1.4, -4), ("scheme", 2, -1), ("extrema_window", 2, -1),
+    ("extrema_window", -1, -1),
 ])
 @no_gpu_only
 def test_invalid_params_rejected_before_launch(K, field, value, status):
@@ -279,3 +281,19 @@ def test_fed_scheme_is_single_image_only(K):
     p.scheme = 7
     assert K.kaze_workspace_bytes(100, 80, p) == 0
 
+
+
+@no_gpu_only
+def test_refine_arguments_rejected_before_launch(K):
+    p = K.kaze_default_params()
+    ok = dict(det=256, W=64, H=64, kps=512, count=768, capacity=4, r=10.0, out=1024)
+    cases = [dict(capacity=-1), dict(r=1.0), dict(r=0.5), dict(r=float("inf")), dict(det=0),
+             dict(kps=0), dict(count=0), dict(out=0), dict(out=1026), dict(W=7), dict(H=4097)]
+    for c in cases:
+        a = dict(ok, **c)
+        with pytest.raises(K.KazeError):
+            K.kaze_refine_keypoints(a["det"], a["W"], a["H"], p, a["kps"], a["count"],
+                                    a["capacity"], a["r"], a["out"], 0)
+    bad = K.kaze_default_params(octaves=0)
+    with pytest.raises(K.KazeError):
+        K.kaze_refine_keypoints(256, 64, 64, bad, 512, 768, 4, 10.0, 1024, 0)

@@ -29,7 +29,7 @@ def make(S, K, W, H, seed, th, **cfg):
     return ss, w
 
 
-@pytest.mark.parametrize("W,H,shape", [(96, 80, 0), (131, 67, 1)])
+@pytest.mark.parametrize("W,H,shape", [(96, 80, 0), (131, 67, 1), (75, 133, 1)])
 def test_forced_fallback_equals_plain_path(S, gpu_lib, W, H, shape):
     K = gpu_lib
     note("[sgss] forced fallback %dx%d shape %d" % (W, H, shape))
