@@ -65,6 +65,11 @@ design notes):
   coprime to n and chosen to minimise the error-growth bound
   max_k max|prod_{j<k}(1 + tau_j mu)| max|prod_{j>=k}(1 + tau_j mu)| over
   mu in [-8, 0] on a grid of 2001 points (ties: smallest kappa).
+* Sub-steps per level (the stepping variant of the method's AOS form): with
+  m sub-steps the level step of length tau_i is split into m equal steps of
+  tau_i / m, each of which recomputes the conductivity from its own starting
+  image and then takes one AOS step (or one FED cycle) of that length.  m = 1
+  is the method as stated.
 """
 from __future__ import annotations
 
@@ -79,7 +84,7 @@ __all__ = [
     "conductivity_g2", "conductivity_g1", "aos_line_bands", "aos_solve_rows",
     "aos_solve_cols", "aos_step", "build_scale_space", "derivative_step",
     "detector_response", "find_extrema", "cross_level_radius", "FED_TAU_MAX", "fed_step_sizes",
-    "fed_order", "diffusion_operator", "explicit_step", "fed_cycle",
+    "fed_order", "diffusion_operator", "explicit_step", "fed_cycle", "level_step",
     "EDGE_RATIO", "quadratic_fit_3x3", "refine_keypoints",
 ]
 
@@ -392,17 +397,36 @@ def refine_keypoints(det: np.ndarray, kps: np.ndarray, edge_ratio: float = EDGE_
     return np.array(out, dtype=np.float64).reshape(-1, 6)
 
 
+def level_step(L: np.ndarray, k: float, tau: float, scheme: str = "aos",
+               substeps: int = 1, diffusivity: str = "g2", sigma_cond: float = 1.0):
+    """The step from one level to the next, of total length tau: ``substeps``
+    equal steps, each with the conductivity (Eqs. 2-3) of its own starting
+    image, by AOS (Eq. 4) or by one FED cycle (Eq. 5)."""
+    if scheme not in ("aos", "fed"):
+        raise ValueError("scheme must be 'aos' or 'fed'")
+    if substeps < 1:
+        raise ValueError("substeps must be >= 1")
+    cond = conductivity_g2 if diffusivity == "g2" else conductivity_g1
+    out = np.asarray(L, dtype=np.float64)
+    for _ in range(substeps):
+        g = cond(out, k, sigma_cond)
+        out = aos_step(out, g, tau / substeps) if scheme == "aos" else \
+            fed_cycle(out, g, tau / substeps)
+    return out
+
+
 def build_scale_space(img: np.ndarray, sigma0: float = 1.6, octaves: int = 4,
                       sublevels: int = 4, sigma_cond: float = 1.0,
                       k_percentile: float = 0.7, k_bins: int = 300,
                       k: float | None = None, diffusivity: str = "g2",
-                      return_g: bool = False, scheme: str = "aos"):
+                      return_g: bool = False, scheme: str = "aos", substeps: int = 1):
     """Nonlinear scale space (Sec. II-A, Sec. III-A), each level reached by
-    one AOS step (Eq. 4) or one FED cycle (Eq. 5).
+    one AOS step (Eq. 4) or one FED cycle (Eq. 5), or by ``substeps`` of
+    them of equal length (see level_step).
 
     Returns ``(levels [N][H][W] float64, k)`` and, if ``return_g``, the
-    conductivity image used by each step (``g[i]`` drives the step into level
-    i; ``g[0]`` is zero).
+    conductivity image of each level's starting image (``g[i]`` drives the
+    (first sub-)step into level i; ``g[0]`` is zero).
     """
     f = np.asarray(img, dtype=np.float64)
     sched = level_schedule(sigma0, octaves, sublevels)
@@ -413,15 +437,10 @@ def build_scale_space(img: np.ndarray, sigma0: float = 1.6, octaves: int = 4,
     levels = [L0]
     gs = [np.zeros_like(L0)]
     for i in range(1, len(sched)):
-        g = cond(levels[-1], k, sigma_cond)
         tau = sched[i]["t"] - sched[i - 1]["t"]
-        if scheme == "aos":
-            levels.append(aos_step(levels[-1], g, tau))
-        elif scheme == "fed":
-            levels.append(fed_cycle(levels[-1], g, tau))
-        else:
-            raise ValueError("scheme must be 'aos' or 'fed'")
-        gs.append(g)
+        if return_g:
+            gs.append(cond(levels[-1], k, sigma_cond))
+        levels.append(level_step(levels[-1], k, tau, scheme, substeps, diffusivity, sigma_cond))
     if return_g:
         return np.stack(levels), float(k), np.stack(gs)
     return np.stack(levels), float(k)
