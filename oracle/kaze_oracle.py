@@ -70,6 +70,40 @@ design notes):
   tau_i / m, each of which recomputes the conductivity from its own starting
   image and then takes one AOS step (or one FED cycle) of that length.  m = 1
   is the method as stated.
+* Description stage (Sec. II-C, Sec. III-C).  The derivatives are the
+  detector's first derivatives (Eq. 8's concatenated Scharr filter of step
+  round(sigma_n)) scaled by sigma_n, Lx = sigma_n D_x L and Ly = sigma_n D_y L.
+  The keypoint's scale unit is s = sigma_i of its level (Eq. 6, in pixels;
+  no level is downsampled); the implementation section's "1.5 times the
+  scale" conflicts with the method section and is not followed.  Samples
+  at real positions are bilinear in Lx and Ly with pixel centres at integer
+  coordinates and the half-sample reflection of the image, repeated with
+  period 2n for positions more than one image away.
+* Dominant orientation: samples at (x, y) + s (u, v) for integers u, v with
+  u^2 + v^2 <= 36 (radius 6 s, step s: 113 samples), each response
+  w (Lx, Ly) with w = exp(-(u^2 + v^2) / (2 * 2.5^2)) (a Gaussian of 2.5 s
+  at the keypoint; the paper gives no width and 2.5 s is the descriptor's
+  sigma_1), at the angle phi = atan2(w Ly, w Lx).  A sector of pi/3 slides
+  round the circle; its sum changes only where an edge crosses a response,
+  so every sum it takes is one of the sums over the half-open sectors
+  (phi_k, phi_k + pi/3] and (phi_k - pi/3, phi_k], k = 1..113.  The
+  orientation is the angle of the longest of these sums (ties: the first
+  in the order k = 1.., "after" before "before").
+* M-SURF descriptor: the 24 s x 24 s window centred on the keypoint and
+  turned by the orientation theta has 4 x 4 subregions of 9 s x 9 s
+  centred at -7.5, -2.5, 2.5, 7.5 (units of s) along and across theta, so
+  neighbours overlap by 2 s on either side; each subregion is sampled on a
+  9 x 9 grid of step s around its centre.  A sample at (u, v) lies at
+  (x, y) + s (u cos theta - v sin theta, u sin theta + v cos theta); its
+  derivatives along and across theta are d_u = Lx cos + Ly sin,
+  d_v = -Lx sin + Ly cos, weighted by exp(-((u-c_u)^2 + (v-c_v)^2) /
+  (2 * 2.5^2)) (sigma_1 = 2.5 s at the subregion centre) and summed into
+  (sum d_u, sum d_v, sum |d_u|, sum |d_v|).  Each subregion's four sums are
+  weighted by exp(-((a-1.5)^2 + (b-1.5)^2) / (2 * 1.5^2)) over the 4 x 4
+  mask (sigma_2 = 1.5 in subregion units: in pixels it would weight the
+  corner subregions by e^-25), ordered by subregion row b (across), column
+  a (along), then the four sums, and the 64-vector is scaled to unit length
+  (left zero if it is zero).
 """
 from __future__ import annotations
 
@@ -85,7 +119,9 @@ __all__ = [
     "aos_solve_cols", "aos_step", "build_scale_space", "derivative_step",
     "detector_response", "find_extrema", "cross_level_radius", "FED_TAU_MAX", "fed_step_sizes",
     "fed_order", "diffusion_operator", "explicit_step", "fed_cycle", "level_step",
-    "EDGE_RATIO", "quadratic_fit_3x3", "refine_keypoints",
+    "EDGE_RATIO", "quadratic_fit_3x3", "refine_keypoints", "first_derivatives",
+    "bilinear", "orientation_samples", "dominant_orientation", "msurf_descriptor",
+    "describe_keypoints",
 ]
 
 DEFAULTS = dict(sigma0=1.6, octaves=4, sublevels=4, sigma_cond=1.0,
@@ -534,3 +570,112 @@ def _find_extrema_windowed(det, threshold, radii):
     if not rows:
         return np.zeros((0, 4))
     return np.array(rows, dtype=np.float64)
+
+
+# --------------------------------------------------------------------------
+# Description stage (Sec. II-C, Sec. III-C): first derivatives, dominant
+# orientation, M-SURF descriptor
+# --------------------------------------------------------------------------
+def first_derivatives(levels: np.ndarray, sigma0: float = 1.6, octaves: int = 4,
+                      sublevels: int = 4):
+    """Scale-normalised first derivatives of every level: Lx = sigma_n D_x L,
+    Ly = sigma_n D_y L with the detector's Scharr step (Eq. 8)."""
+    sched = level_schedule(sigma0, octaves, sublevels)
+    lx = np.empty_like(np.asarray(levels, dtype=np.float64))
+    ly = np.empty_like(lx)
+    for lev in sched:
+        i = lev["i"]
+        sn = lev["sigma"] / 2.0 ** lev["o"]
+        s = derivative_step(sn)
+        lx[i] = sn * scharr_dx(levels[i], s)
+        ly[i] = sn * scharr_dy(levels[i], s)
+    return lx, ly
+
+
+def _mirror(i, n):
+    """Half-sample reflection repeated with period 2n: index into 0..n-1."""
+    i = np.mod(i, 2 * n)
+    return np.where(i >= n, 2 * n - 1 - i, i)
+
+
+def bilinear(img: np.ndarray, x, y):
+    """Bilinear value of img at real positions (x, y), pixel centres at
+    integer coordinates, reflected outside the image."""
+    img = np.asarray(img, dtype=np.float64)
+    H, W = img.shape
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    x0, y0 = np.floor(x), np.floor(y)
+    fx, fy = x - x0, y - y0
+    x0, y0 = x0.astype(np.int64), y0.astype(np.int64)
+    xa, xb = _mirror(x0, W), _mirror(x0 + 1, W)
+    ya, yb = _mirror(y0, H), _mirror(y0 + 1, H)
+    top = (1 - fx) * img[ya, xa] + fx * img[ya, xb]
+    bot = (1 - fx) * img[yb, xa] + fx * img[yb, xb]
+    return (1 - fy) * top + fy * bot
+
+
+def orientation_samples():
+    """Integer offsets (u, v) with u^2 + v^2 <= 36, row by row (v, then u)."""
+    return [(u, v) for v in range(-6, 7) for u in range(-6, 7) if u * u + v * v <= 36]
+
+
+def dominant_orientation(lx: np.ndarray, ly: np.ndarray, x: float, y: float, s: float):
+    """Angle of the longest sum of Gaussian-weighted derivative responses
+    over a sliding pi/3 sector (radius 6 s, step s).  Returns (theta, the
+    sums' lengths in the order the readings list them)."""
+    uv = np.array(orientation_samples(), dtype=np.float64)
+    w = np.exp(-(uv[:, 0] ** 2 + uv[:, 1] ** 2) / (2.0 * 2.5 ** 2))
+    px, py = x + s * uv[:, 0], y + s * uv[:, 1]
+    rx, ry = w * bilinear(lx, px, py), w * bilinear(ly, px, py)
+    phi = np.arctan2(ry, rx)
+    two_pi, sector = 2.0 * np.pi, np.pi / 3.0
+    lengths, sums = [], []
+    for k in range(len(phi)):
+        d_after = np.mod(phi - phi[k], two_pi)     # phi_j - phi_k in [0, 2 pi)
+        d_before = np.mod(phi[k] - phi, two_pi)    # phi_k - phi_j in [0, 2 pi)
+        for m in ((d_after > 0.0) & (d_after <= sector), d_before < sector):
+            sx, sy = rx[m].sum(), ry[m].sum()
+            sums.append((sx, sy))
+            lengths.append(math.hypot(sx, sy))
+    best = int(np.argmax(lengths))
+    return math.atan2(sums[best][1], sums[best][0]), np.array(lengths)
+
+
+def msurf_descriptor(lx: np.ndarray, ly: np.ndarray, x: float, y: float, s: float,
+                     theta: float) -> np.ndarray:
+    """64-D M-SURF descriptor of one keypoint (see the readings above)."""
+    c, sn = math.cos(theta), math.sin(theta)
+    centres = (-7.5, -2.5, 2.5, 7.5)
+    out = []
+    for b, cv in enumerate(centres):
+        for a, cu in enumerate(centres):
+            t = np.arange(9, dtype=np.float64) - 4.0
+            U, V = np.meshgrid(cu + t, cv + t)
+            px = x + s * (U * c - V * sn)
+            py = y + s * (U * sn + V * c)
+            gx, gy = bilinear(lx, px, py), bilinear(ly, px, py)
+            du, dv = gx * c + gy * sn, -gx * sn + gy * c
+            w1 = np.exp(-((U - cu) ** 2 + (V - cv) ** 2) / (2.0 * 2.5 ** 2))
+            w2 = math.exp(-((a - 1.5) ** 2 + (b - 1.5) ** 2) / (2.0 * 1.5 ** 2))
+            out += [w2 * (w1 * du).sum(), w2 * (w1 * dv).sum(),
+                    w2 * (w1 * np.abs(du)).sum(), w2 * (w1 * np.abs(dv)).sum()]
+    d = np.array(out)
+    n = np.linalg.norm(d)
+    return d / n if n > 0.0 else d
+
+
+def describe_keypoints(lx: np.ndarray, ly: np.ndarray, kps: np.ndarray,
+                       sigma0: float = 1.6, octaves: int = 4, sublevels: int = 4):
+    """Orientation and descriptor of every keypoint; kps rows (level, y, x,
+    ...) with real y, x.  Returns (theta (n,), descriptors (n, 64))."""
+    sched = level_schedule(sigma0, octaves, sublevels)
+    kps = np.asarray(kps, dtype=np.float64).reshape(-1, np.shape(kps)[-1] if len(kps) else 4)
+    th, desc = [], []
+    for row in kps:
+        lev, y, x = int(row[0]), float(row[1]), float(row[2])
+        s = sched[lev]["sigma"]
+        t, _ = dominant_orientation(lx[lev], ly[lev], x, y, s)
+        th.append(t)
+        desc.append(msurf_descriptor(lx[lev], ly[lev], x, y, s, t))
+    return np.array(th), np.array(desc).reshape(-1, 64)
