@@ -119,6 +119,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate measurements (plain path only)")
+    ap.add_argument("--no-substeps", action="store_true",
+                    help="skip the sub-steps-per-level measurement")
+    ap.add_argument("--no-keypoints", action="store_true",
+                    help="skip the extrema-window and refinement measurements")
     ap.add_argument("--no-fed", action="store_true",
                     help="skip the FED-scheme measurement")
     ap.add_argument("--no-breakdown", action="store_true",
@@ -215,11 +219,15 @@ def bench_single(args, K, torch, kaze_image, case):
         if n:
             breakdown[name] = {"launches_per_step": n / probe_steps,
                                "ms_per_step": ms / probe_steps, "us_per_launch": 1e3 * ms / n}
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(3):
         kz.run(img)
     torch.cuda.synchronize()
-    eager_value = args.steps / (time.perf_counter() - t1)
+    eager_steps = max(50, args.steps)
+    t1 = time.perf_counter()
+    for _ in range(eager_steps):
+        kz.run(img)
+    torch.cuda.synchronize()
+    eager_value = eager_steps / (time.perf_counter() - t1)
 
     # timed path: the image's plan replayed from its captured graphs
     kb = K.KazeBatch([(W, H)], shape="auto")
@@ -242,6 +250,10 @@ def bench_single(args, K, torch, kaze_image, case):
                                   for k, v in breakdown.items()}}
     if not args.no_fed:
         extra["fed"] = bench_fed(args, K, torch, img, W, H, args.steps / elapsed, eager_value)
+    if not args.no_keypoints:
+        extra["keypoints"] = bench_keypoints(args, K, torch, img, W, H)
+    if not args.no_substeps:
+        extra["substeps"] = bench_substeps(args, K, torch, img, W, H, eager_value)
     if not args.no_surrogate:
         extra["surrogate"] = bench_surrogate(args, K, torch, img, W, H, seed,
                                              args.steps / elapsed)
@@ -285,6 +297,70 @@ def bench_fed(args, K, torch, img, W, H, plain_value, plain_eager):
             "us_per_level": round(level_us, 3),
             "speedup_vs_plain_aos_eager": round(val / plain_eager, 4),
             "speedup_vs_plain_aos_graph": round(val / plain_value, 4)}
+
+
+def bench_substeps(args, K, torch, img, W, H, plain_eager):
+    """m AOS sub-steps per level (each recomputing the conductivity): eager
+    images/s and the time of one sub-step (event pairs around the AOS
+    launches)."""
+    out = {}
+    for m in (2, 4):
+        kz = K.Kaze(W, H, K.kaze_default_params(substeps=m))
+        for _ in range(2):
+            kz.run(img)
+        torch.cuda.synchronize()
+        steps = max(20, args.steps // 4)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            kz.run(img)
+        torch.cuda.synchronize()
+        val = steps / (time.perf_counter() - t0)
+        K.kaze_profile_begin(",".join(AOS_KERNELS))
+        kz.run(img)
+        n, ms = K.kaze_profile_end()
+        out[str(m)] = {"images_per_s": round(val, 3), "path": "eager calls",
+                       "us_per_substep": round(1e3 * ms / (n / 3), 3),
+                       "relative_to_one_step": round(val / plain_eager, 4)}
+    return out
+
+
+def bench_keypoints(args, K, torch, img, W, H):
+    """The extrema stage with the 3x3 and the sigma x sigma cross-level
+    window (nms launch time, keypoint counts), and the refinement and edge
+    test of the window's extrema (refine launch time, kept count); event
+    pairs around every launch, eager calls."""
+    out = {}
+    for name, window in (("window_3x3", K.KAZE_WINDOW_3X3), ("window_sigma", K.KAZE_WINDOW_SIGMA)):
+        p = K.kaze_default_params()
+        p.extrema_window = window
+        kz = K.Kaze(W, H, p)
+        kz.run(img)
+        torch.cuda.synchronize()
+        K.kaze_profile_begin("nms")
+        for _ in range(10):
+            kz.extrema()
+        n, ms = K.kaze_profile_end()
+        out[name] = {"keypoints": int(kz.count.item()), "nms_us": round(1e3 * ms / n, 3)}
+    kz.refine()
+    torch.cuda.synchronize()
+    K.kaze_profile_begin("refine")
+    for _ in range(10):
+        kz.refine()
+    n, ms = K.kaze_profile_end()
+    kept = int(kz.refined_keypoints()[:, 5].sum())
+    out["refine"] = {"keypoints": int(kz.count.item()), "kept": kept,
+                     "us_per_launch": round(1e3 * ms / n, 3), "edge_ratio": 10.0}
+    kz.describe()
+    torch.cuda.synchronize()
+    for name in ("deriv", "describe"):
+        K.kaze_profile_begin(name)
+        for _ in range(10):
+            kz.describe()
+        n, ms = K.kaze_profile_end()
+        out[name] = {"us_per_launch": round(1e3 * ms / n, 3)}
+    out["describe"]["keypoints"] = int(kz.count.item())
+    out["deriv"]["levels"] = kz.N
+    return out
 
 
 def bench_surrogate(args, K, torch, img, W, H, seed, plain_value):

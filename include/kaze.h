@@ -84,6 +84,10 @@ typedef struct {
     double det_threshold;  /* detector threshold of Sec. II-B (compared in FP32) */
     int    scheme;         /* KAZE_AOS (default) or KAZE_FED                     */
     int    extrema_window; /* KAZE_WINDOW_3X3 (default) or KAZE_WINDOW_SIGMA     */
+    int    substeps;       /* steps per level, 1..64 (default 1): the step of
+                            * length tau_i is split into this many equal steps
+                            * (AOS steps or FED cycles), each with the
+                            * conductivity of its own starting image          */
 } kaze_params;
 
 /* One detected extremum: pixel position, level index and det response. */
@@ -340,6 +344,44 @@ kaze_status kaze_refine_keypoints(const float* det, int W, int H, const kaze_par
                                   const kaze_keypoint* kps, const int* count, int capacity,
                                   double edge_ratio, kaze_keypoint_refined* out,
                                   void* stream);
+
+/*
+ * Description stage (Sec. II-C, Sec. III-C).
+ *
+ * kaze_derivatives: scale-normalised first derivatives of every level,
+ *   Lx = sigma_n D_x L and Ly = sigma_n D_y L, with the concatenated Scharr
+ *   filter of Eq. 8 (step round(sigma_n), reflected border).
+ *   levels   (device) N x H x W float32 input.
+ *   lx, ly   (device) N x H x W float32 outputs (distinct from levels).
+ */
+kaze_status kaze_derivatives(const float* levels, int W, int H, const kaze_params* p,
+                             float* lx, float* ly, void* stream);
+
+/*
+ * kaze_describe_keypoints: dominant orientation and 64-D M-SURF descriptor
+ * of keypoint i < min(*count, capacity), at its (sub-pixel) position, with
+ * the scale unit s = sigma_i of its level (Eq. 6).  Samples are bilinear in
+ * Lx and Ly (pixel centres at integers, reflected outside the image).
+ *   Orientation: responses w (Lx, Ly) at (x, y) + s (u, v) for integers
+ *   u^2 + v^2 <= 36, w = exp(-(u^2 + v^2) / 12.5); the angle of the longest
+ *   sum over a sliding pi/3 sector.
+ *   Descriptor: 4 x 4 subregions of 9 x 9 samples of step s centred at
+ *   -7.5, -2.5, 2.5, 7.5 s along and across the orientation; sums of the
+ *   turned derivatives and their magnitudes weighted by a Gaussian of 2.5 s
+ *   at the subregion centre, and per subregion by a Gaussian of 1.5
+ *   subregions over the 4 x 4 mask; unit length.  Order: subregion row
+ *   (across), column (along), then (sum d_u, sum d_v, sum |d_u|, sum |d_v|).
+ *   lx, ly       (device) from kaze_derivatives.
+ *   kps, count   (device) as written by kaze_refine_keypoints and
+ *                kaze_find_extrema; entries with a level outside [0, N) or a
+ *                non-finite position get angle NaN and a zero descriptor.
+ *   angles       (device) capacity floats (radians, atan2 convention).
+ *   descriptors  (device) capacity x 64 floats.
+ */
+kaze_status kaze_describe_keypoints(const float* lx, const float* ly, int W, int H,
+                                    const kaze_params* p, const kaze_keypoint_refined* kps,
+                                    const int* count, int capacity, float* angles,
+                                    float* descriptors, void* stream);
 
 /* Message for the most recent non-OK status returned on this thread. */
 const char* kaze_last_error(void);

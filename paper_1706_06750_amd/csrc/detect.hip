@@ -115,11 +115,26 @@ struct KeypointOut {
     float response;
 };
 
+__device__ __forceinline__ void push_keypoint(const BatchImage& d, KeypointOut* kps, int x, int y,
+                                              int lev, float v) {
+    const int idx = atomicAdd(d.count, 1);
+    if (idx < d.capacity) {
+        KeypointOut k;
+        k.x = x;
+        k.y = y;
+        k.level = lev;
+        k.response = v;
+        kps[idx] = k;
+    }
+}
+
 // (x, y, i) is an extremum iff det_i(x,y) > threshold, > its 8 neighbours
 // in level i and > every response of levels i-1 and i+1 within h = radii.h[i]
 // pixels in x and y (clipped to the image; h = 1 is the 3x3x3 block);
 // levels 1..N-2, 1-pixel image border excluded.  A block covers 64 columns
 // x 4*kNmsRows rows of one level.
+// WIDE false: every half-side is 1 (the 3x3x3 test, no wavefront-wide part).
+template <bool WIDE>
 __global__ __launch_bounds__(256) void nms_kernel(BatchImage d0, ImgWork w, float threshold,
                                                   NmsRadii radii) {
     // The descriptor is read with ordinary loads here: the scalar-load form of
@@ -142,51 +157,67 @@ __global__ __launch_bounds__(256) void nms_kernel(BatchImage d0, ImgWork w, floa
     const int y0 = ((lb / nbx) * 4 + threadIdx.x / 64) * kNmsRows;
     const int lev = by + 1;
     const int h = radii.h[lev];
-    if (x < 1 || x > W - 2) return;
     const size_t plane = (size_t)W * H;
     const float* base = d.det + plane * lev;
+    KeypointOut* kps = static_cast<KeypointOut*>(d.kps);
+    const bool x_in = x >= 1 && x <= W - 2;
     float v[kNmsRows];
 #pragma unroll
     for (int q = 0; q < kNmsRows; ++q) {
         const int y = y0 + q;
-        v[q] = (y >= 1 && y <= H - 2) ? base[(size_t)y * W + x] : -INFINITY;
+        v[q] = (x_in && y >= 1 && y <= H - 2) ? base[(size_t)y * W + x] : -INFINITY;
     }
-    KeypointOut* kps = static_cast<KeypointOut*>(d.kps);
+    if (!WIDE || h == 1) {
+        if (!x_in) return;
 #pragma unroll
-    for (int q = 0; q < kNmsRows; ++q) {
-        if (!(v[q] > threshold)) continue;
-        const int y = y0 + q;
-        const float* c = base + (size_t)y * W + x;
-        bool is_max = true;
-        if (h == 1) {
+        for (int q = 0; q < kNmsRows; ++q) {
+            if (!(v[q] > threshold)) continue;
+            const int y = y0 + q;
+            const float* c = base + (size_t)y * W + x;
+            bool is_max = true;
             for (int dl = -1; dl <= 1 && is_max; ++dl)
                 for (int dy = -1; dy <= 1; ++dy)
                     for (int dx = -1; dx <= 1; ++dx) {
                         if (dl == 0 && dy == 0 && dx == 0) continue;
                         is_max = is_max && (v[q] > c[(ptrdiff_t)dl * (ptrdiff_t)plane + dy * W + dx]);
                     }
-        } else {
+            if (is_max) push_keypoint(d, kps, x, y, lev, v[q]);
+        }
+        return;
+    }
+    // Wider cross-level window: the own-level 3x3 test per lane, then the
+    // wavefront takes its candidates one at a time and all 64 lanes compare
+    // the window of levels lev-1 and lev+1 (clipped to the image) together.
+    // Every lane of the wavefront runs this part (the row y is uniform).
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int q = 0; q < kNmsRows; ++q) {
+        const int y = y0 + q;
+        bool cand = v[q] > threshold;  // false outside the image (-inf)
+        if (cand) {
+            const float* c = base + (size_t)y * W + x;
             for (int dy = -1; dy <= 1; ++dy)
                 for (int dx = -1; dx <= 1; ++dx)
-                    if (dy != 0 || dx != 0) is_max = is_max && (v[q] > c[dy * W + dx]);
-            const int y0 = max(y - h, 0), y1 = min(y + h, H - 1);
-            const int x0 = max(x - h, 0), x1 = min(x + h, W - 1);
-            for (int dl = -1; dl <= 1 && is_max; dl += 2) {
-                const float* o = base + (ptrdiff_t)dl * (ptrdiff_t)plane;
-                for (int yy = y0; yy <= y1 && is_max; ++yy)
-                    for (int xx = x0; xx <= x1; ++xx)
-                        is_max = is_max && (v[q] > o[(size_t)yy * W + xx]);
-            }
+                    if (dy != 0 || dx != 0) cand = cand && (v[q] > c[dy * W + dx]);
         }
-        if (!is_max) continue;
-        const int idx = atomicAdd(d.count, 1);
-        if (idx < d.capacity) {
-            KeypointOut k;
-            k.x = x;
-            k.y = y;
-            k.level = lev;
-            k.response = v[q];
-            kps[idx] = k;
+        unsigned long long m = __ballot(cand);
+        while (m) {
+            const int l = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            const int cx = __builtin_amdgcn_readlane(x, l);
+            const float cv = __builtin_bit_cast(
+                float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v[q]), l));
+            const int wy0 = max(y - h, 0), wy1 = min(y + h, H - 1);
+            const int wx0 = max(cx - h, 0), wx1 = min(cx + h, W - 1);
+            const int ww = wx1 - wx0 + 1, n = ww * (wy1 - wy0 + 1);
+            bool ok = true;
+            for (int t = lane; t < 2 * n; t += kWave) {
+                const int u = t < n ? t : t - n;
+                const ptrdiff_t off = t < n ? -(ptrdiff_t)plane : (ptrdiff_t)plane;
+                const int yy = wy0 + u / ww, xx = wx0 + u % ww;
+                ok = ok && (cv > base[off + (ptrdiff_t)yy * W + xx]);
+            }
+            if (__ballot(!ok) == 0 && lane == l) push_keypoint(d, kps, x, y, lev, v[q]);
         }
     }
 }
@@ -194,21 +225,14 @@ __global__ __launch_bounds__(256) void nms_kernel(BatchImage d0, ImgWork w, floa
 // Keypoint refinement (Sec. II-B, Eqs. 9-12): one thread per extremum.  The
 // least-squares quadratic on the 3x3 window has orthogonal regressors, so
 // each coefficient is a projection of the nine samples.
-struct RefinedOut {
-    float x, y;
-    int level;
-    float response, edge_ratio;
-    int kept;
-};
-
 __global__ __launch_bounds__(256) void refine_kernel(const float* det, int W, int H, int N,
                                                      const KeypointOut* kps, const int* count,
-                                                     int capacity, float thr, RefinedOut* out) {
+                                                     int capacity, float thr, RefinedKeypoint* out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = min(*count, capacity);
     if (i >= n) return;
     const KeypointOut k = kps[i];
-    RefinedOut r;
+    RefinedKeypoint r;
     r.level = k.level;
     if (k.level < 0 || k.level >= N || k.x < 1 || k.x > W - 2 || k.y < 1 || k.y > H - 2) {
         // no full 3x3 window: not a keypoint find_extrema writes
@@ -282,7 +306,7 @@ hipError_t launch_refine(const float* det, int W, int H, int N, const void* kps,
     if (capacity <= 0) return hipSuccess;
     hipLaunchKernelGGL(refine_kernel, dim3((capacity + 255) / 256), dim3(256), 0, s, det, W, H, N,
                        static_cast<const KeypointOut*>(kps), count, capacity, thr,
-                       static_cast<RefinedOut*>(out));
+                       static_cast<RefinedKeypoint*>(out));
     return hipGetLastError();
 }
 
@@ -290,7 +314,14 @@ hipError_t launch_nms(const BatchImage& d0, const ImgWork& w, int N, float thres
                       const NmsRadii& radii, hipStream_t s) {
     const int count = w.items ? w.count : nms_blocks_of(d0.W, d0.H);
     if (N < 3 || count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(nms_kernel, dim3(count, N - 2), dim3(256), 0, s, d0, w, threshold, radii);
+    bool wide = false;
+    for (int i = 0; i < N && i < kMaxLevels; ++i) wide = wide || radii.h[i] > 1;
+    if (wide)
+        hipLaunchKernelGGL(nms_kernel<true>, dim3(count, N - 2), dim3(256), 0, s, d0, w, threshold,
+                           radii);
+    else
+        hipLaunchKernelGGL(nms_kernel<false>, dim3(count, N - 2), dim3(256), 0, s, d0, w,
+                           threshold, radii);
     return hipGetLastError();
 }
 

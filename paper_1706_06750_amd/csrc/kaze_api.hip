@@ -43,7 +43,7 @@ kaze_status fail(kaze_status st, const char* fmt, ...) {
 const char* const kKernelNames[K_COUNT] = {
     "gauss", "grad", "hist", "kselect", "cond", "aos_reduce", "aos_iface", "aos_recover",
     "det",   "nms",  "fill", "copy",    "sg_pack", "sg_conv1", "sg_conv", "sg_conv6",
-    "sg_probe", "fed", "refine"};
+    "sg_probe", "fed", "refine", "deriv", "describe"};
 
 struct Profiler {
     unsigned mask = 0;  // bit i: record launches of kernel i
@@ -142,6 +142,8 @@ kaze_status check_params(const kaze_params* p) {
         return fail(KAZE_ERR_INVALID_ARG, "scheme must be KAZE_AOS or KAZE_FED");
     if (p->extrema_window != KAZE_WINDOW_3X3 && p->extrema_window != KAZE_WINDOW_SIGMA)
         return fail(KAZE_ERR_INVALID_ARG, "extrema_window must be KAZE_WINDOW_3X3 or KAZE_WINDOW_SIGMA");
+    if (p->substeps < 1 || p->substeps > kMaxSubsteps)
+        return fail(KAZE_ERR_INVALID_ARG, "substeps must be in [1, %d]", kMaxSubsteps);
     return KAZE_OK;
 }
 
@@ -235,11 +237,13 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // Per-image scratch: conductivity plane, interface equations and solutions
 // of the AOS tile shape, histogram and hmax.
 struct Scratch {
-    size_t g, rrow, rcol, zrow, zcol, hist, hmax, tmp, total;
+    size_t g, rrow, rcol, zrow, zcol, hist, hmax, tmp, sub, total;
 };
 
-// fed: room for the second plane of the explicit steps (FED scheme only).
-Scratch scratch_layout(int W, int H, int nbins, int shape, size_t base, bool fed = false) {
+// fed: room for the second plane of the explicit steps (FED scheme only);
+// sub: the plane between the sub-steps of a level (more than one sub-step).
+Scratch scratch_layout(int W, int H, int nbins, int shape, size_t base, bool fed = false,
+                       bool sub = false) {
     Scratch w;
     (void)shape;
     const size_t ncx = aos_row_chunks(W), ncy = aos_col_chunks(H);
@@ -252,6 +256,7 @@ Scratch scratch_layout(int W, int H, int nbins, int shape, size_t base, bool fed
     w.hist = off; off = align256(off + (size_t)(nbins > 0 ? nbins : 1) * sizeof(unsigned));
     w.hmax = off; off = align256(off + sizeof(unsigned));
     w.tmp = off;  off = align256(off + (fed ? (size_t)W * H * sizeof(float) : 0));
+    w.sub = off;  off = align256(off + (sub ? (size_t)W * H * sizeof(float) : 0));
     w.total = off - base;
     return w;
 }
@@ -353,7 +358,7 @@ struct kaze_batch {
     kaze_params p;
     std::vector<Level> lv;
     BatchImage* d_imgs = nullptr;
-    ImageDesc* d_lvl = nullptr;  // (N-1) x n, level i at row i-1
+    ImageDesc* d_lvl = nullptr;  // (N-1) x m x n: sub-step q of level i at row (i-1) m + q
     int2 *d_items = nullptr, *d_tiles = nullptr, *d_aos = nullptr, *d_lines = nullptr,
          *d_hist = nullptr, *d_det = nullptr, *d_nms = nullptr;
     int n_tiles = 0, n_aos = 0, n_lines = 0, n_hist = 0, n_det = 0, n_nms = 0;
@@ -396,7 +401,8 @@ BatchLayout batch_layout(const kaze_image_desc* im, int n, const kaze_params* p,
     }
     size_t off = 0;
     L.imgs = off;  off = align256(off + n * sizeof(BatchImage));
-    L.lvl = off;   off = align256(off + (size_t)(N > 1 ? N - 1 : 1) * n * sizeof(ImageDesc));
+    L.lvl = off;
+    off = align256(off + (size_t)(N > 1 ? N - 1 : 1) * p->substeps * n * sizeof(ImageDesc));
     L.items = off; off = align256(off + n * sizeof(int2));
     L.tiles = off; off = align256(off + L.n_tiles * sizeof(int2));
     L.aos = off;   off = align256(off + L.n_aos * sizeof(int2));
@@ -408,7 +414,7 @@ BatchLayout batch_layout(const kaze_image_desc* im, int n, const kaze_params* p,
     L.scratch.resize(n);
     for (int j = 0; j < n; ++j) {
         L.scratch[j] = off;
-        off += scratch_layout(im[j].W, im[j].H, hist_bins(p), shape, 0).total;
+        off += scratch_layout(im[j].W, im[j].H, hist_bins(p), shape, 0, false, p->substeps > 1).total;
     }
     L.total = off;
     return L;
@@ -482,12 +488,16 @@ kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStre
         if (st != KAZE_OK) return st;
         ImageDesc a0;
         memset(&a0, 0, sizeof(a0));
+        const int m = p->substeps;
         for (int i = 1; i < B.N; ++i) {
-            const ImageDesc* lvl = B.d_lvl + (size_t)(i - 1) * B.n;
-            const AosWork at{lvl, B.d_aos, B.n_aos};
-            const AosWork al{lvl, B.d_lines, B.n_lines};
-            st = aos_step(a0, at, al, B.shape, tc, (float)B.lv[i].tau, true, gmode, 1.f, s);
-            if (st != KAZE_OK) return st;
+            for (int q = 0; q < m; ++q) {
+                const ImageDesc* lvl = B.d_lvl + ((size_t)(i - 1) * m + q) * B.n;
+                const AosWork at{lvl, B.d_aos, B.n_aos};
+                const AosWork al{lvl, B.d_lines, B.n_lines};
+                st = aos_step(a0, at, al, B.shape, tc, (float)(B.lv[i].tau / m), true, gmode, 1.f,
+                              s);
+                if (st != KAZE_OK) return st;
+            }
             if ((st = det_level(i)) != KAZE_OK) return st;
         }
         if (fork) {  // join
@@ -562,9 +572,10 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
     int2* hn = reinterpret_cast<int2*>(host.data() + L.nms);
     int it = 0, ia = 0, il = 0, ih = 0, idt = 0, inm = 0;
     const int nb = hist_bins(p);
+    const int m = p->substeps;
     for (int j = 0; j < n; ++j) {
         const kaze_image_desc& d = im[j];
-        const Scratch sc = scratch_layout(d.W, d.H, nb, shape, L.scratch[j]);
+        const Scratch sc = scratch_layout(d.W, d.H, nb, shape, L.scratch[j], false, m > 1);
         BatchImage b = batch_image(d.W, d.H);
         b.img = d.img;
         b.ld = d.ld_img;
@@ -580,11 +591,16 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
         himgs[j] = b;
         hitems[j] = make_int2(j, 0);
         const size_t plane = (size_t)d.W * d.H;
+        float* mid = reinterpret_cast<float*>(base + sc.sub);
         for (int i = 1; i < B->N; ++i) {
-            ImageDesc a = aos_desc(d.W, d.H, shape, base, sc, d.k);
-            a.L = d.levels + plane * (i - 1);
-            a.Lnext = d.levels + plane * i;
-            hlvl[(size_t)(i - 1) * n + j] = a;
+            const float* src = d.levels + plane * (i - 1);
+            for (int q = 0; q < m; ++q) {  // as in kaze_build_scale_space
+                ImageDesc a = aos_desc(d.W, d.H, shape, base, sc, d.k);
+                a.L = src;
+                a.Lnext = ((m - 1 - q) % 2 == 0) ? d.levels + plane * i : mid;
+                hlvl[((size_t)(i - 1) * m + q) * n + j] = a;
+                src = a.Lnext;
+            }
         }
         for (int t = 0; t < tiles_of(d.W, d.H); ++t) ht[it++] = make_int2(j, t);
         for (int t = 0; t < aos_tiles_of(d.W, d.H, kAosShapeTY[shape]); ++t)
@@ -872,6 +888,7 @@ kaze_status kaze_default_params(kaze_params* p) {
     p->det_threshold = 0.001;
     p->scheme = KAZE_AOS;
     p->extrema_window = KAZE_WINDOW_3X3;
+    p->substeps = 1;
     return KAZE_OK;
 }
 
@@ -899,7 +916,7 @@ kaze_status kaze_schedule(const kaze_params* p, double* sigma, double* t, double
 
 size_t kaze_workspace_bytes(int W, int H, const kaze_params* p) {
     if (check_params(p) != KAZE_OK || check_size(W, H) != KAZE_OK) return 0;
-    return scratch_layout(W, H, hist_bins(p), 0, 0, p->scheme == KAZE_FED).total;
+    return scratch_layout(W, H, hist_bins(p), 0, 0, p->scheme == KAZE_FED, p->substeps > 1).total;
 }
 
 kaze_status kaze_build_scale_space(const float* img, int W, int H, int ld_img,
@@ -914,7 +931,8 @@ kaze_status kaze_build_scale_space(const float* img, int W, int H, int ld_img,
     if (!aligned(img, 4) || !aligned(levels, 4) || !aligned(k_out, 4))
         return fail(KAZE_ERR_INVALID_ARG, "float buffers must be 4-byte aligned");
     const bool fed = p->scheme == KAZE_FED;
-    const Scratch w = scratch_layout(W, H, hist_bins(p), 0, 0, fed);
+    const int m = p->substeps;
+    const Scratch w = scratch_layout(W, H, hist_bins(p), 0, 0, fed, m > 1);
     if (!ws || !aligned(ws, 256) || ws_bytes < w.total)
         return fail(KAZE_ERR_WORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
                     w.total, ws_bytes);
@@ -940,19 +958,29 @@ kaze_status kaze_build_scale_space(const float* img, int W, int H, int ld_img,
     const int gmode = p->diffusivity == KAZE_G2 ? 0 : 1;
     ImageDesc d = aos_desc(W, H, 0, base, w, k_out);
     const AosWork anone{nullptr, nullptr, 0};
+    float* mid = reinterpret_cast<float*>(base + w.sub);
     for (size_t i = 1; i < lv.size(); ++i) {
-        d.L = levels + plane * (i - 1);
-        d.Lnext = levels + plane * i;
-        if (fed) {
-            BatchImage bc = b;
-            bc.levels = const_cast<float*>(d.L);  // conductivity of level i-1
-            KZ_LAUNCH(K_COND, s, launch_cond(bc, none, tc, 1.f, gmode, s));
-            st = fed_cycle(d.L, b.g, d.Lnext, reinterpret_cast<float*>(base + w.tmp), W, H,
-                           lv[i].tau, s);
-        } else {
-            st = aos_step(d, anone, anone, 0, tc, (float)lv[i].tau, true, gmode, 1.f, s);
+        // m sub-steps from level i-1 to level i, alternating between the
+        // level's plane and the sub-step plane so that the last one writes
+        // the level
+        const double tau = lv[i].tau / m;
+        const float* src = levels + plane * (i - 1);
+        float* out = levels + plane * i;
+        for (int q = 0; q < m; ++q) {
+            float* dst = ((m - 1 - q) % 2 == 0) ? out : mid;
+            d.L = src;
+            d.Lnext = dst;
+            if (fed) {
+                BatchImage bc = b;
+                bc.levels = const_cast<float*>(src);  // conductivity of the step's start
+                KZ_LAUNCH(K_COND, s, launch_cond(bc, none, tc, 1.f, gmode, s));
+                st = fed_cycle(src, b.g, dst, reinterpret_cast<float*>(base + w.tmp), W, H, tau, s);
+            } else {
+                st = aos_step(d, anone, anone, 0, tc, (float)tau, true, gmode, 1.f, s);
+            }
+            if (st != KAZE_OK) return st;
+            src = dst;
         }
-        if (st != KAZE_OK) return st;
     }
     return KAZE_OK;
 }
@@ -999,8 +1027,9 @@ kaze_status kaze_aos_step(const float* L, const float* g, int W, int H, double t
                     static_cast<hipStream_t>(stream));
 }
 
-static_assert(sizeof(kaze_keypoint) == 16 && sizeof(kaze_keypoint_refined) == 24,
-              "keypoint records as the kernels write them");
+static_assert(sizeof(kaze_keypoint) == 16 && sizeof(kaze_keypoint_refined) == 24 &&
+                  sizeof(RefinedKeypoint) == sizeof(kaze_keypoint_refined),
+              "keypoint records as the kernels read and write them");
 
 kaze_status kaze_refine_keypoints(const float* det, int W, int H, const kaze_params* p,
                                   const kaze_keypoint* kps, const int* count, int capacity,
@@ -1019,6 +1048,53 @@ kaze_status kaze_refine_keypoints(const float* det, int W, int H, const kaze_par
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int N = kaze_num_levels(p);
     KZ_LAUNCH(K_REFINE, s, launch_refine(det, W, H, N, kps, count, capacity, thr, out, s));
+    return KAZE_OK;
+}
+
+static DescLevels desc_levels(const kaze_params* p) {
+    std::vector<Level> lv;
+    schedule(p, lv);
+    DescLevels dl;
+    memset(&dl, 0, sizeof(dl));
+    for (size_t i = 0; i < lv.size(); ++i) {
+        dl.step[i] = lv[i].step;
+        dl.sn[i] = (float)lv[i].sigma_n;
+        dl.sigma[i] = (float)lv[i].sigma;
+    }
+    return dl;
+}
+
+kaze_status kaze_derivatives(const float* levels, int W, int H, const kaze_params* p, float* lx,
+                             float* ly, void* stream) {
+    kaze_status st = check_params(p);
+    if (st != KAZE_OK) return st;
+    if ((st = check_size(W, H)) != KAZE_OK) return st;
+    if ((st = check_steps(p)) != KAZE_OK) return st;
+    if (!levels || !lx || !ly) return fail(KAZE_ERR_INVALID_ARG, "levels, lx and ly must be non-NULL");
+    if (!aligned(levels, 4) || !aligned(lx, 4) || !aligned(ly, 4))
+        return fail(KAZE_ERR_INVALID_ARG, "float buffers must be 4-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    KZ_LAUNCH(K_DERIV, s, launch_deriv(levels, W, H, kaze_num_levels(p), desc_levels(p), lx, ly, s));
+    return KAZE_OK;
+}
+
+kaze_status kaze_describe_keypoints(const float* lx, const float* ly, int W, int H,
+                                    const kaze_params* p, const kaze_keypoint_refined* kps,
+                                    const int* count, int capacity, float* angles,
+                                    float* descriptors, void* stream) {
+    kaze_status st = check_params(p);
+    if (st != KAZE_OK) return st;
+    if ((st = check_size(W, H)) != KAZE_OK) return st;
+    if (capacity < 0) return fail(KAZE_ERR_INVALID_ARG, "capacity must be >= 0");
+    if (capacity > 0 && (!lx || !ly || !kps || !count || !angles || !descriptors))
+        return fail(KAZE_ERR_INVALID_ARG, "lx, ly, kps, count, angles and descriptors must be non-NULL");
+    if (!aligned(lx, 4) || !aligned(ly, 4) || !aligned(kps, 4) || !aligned(count, 4) ||
+        !aligned(angles, 4) || !aligned(descriptors, 4))
+        return fail(KAZE_ERR_INVALID_ARG, "buffers must be 4-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    KZ_LAUNCH(K_DESCRIBE, s,
+              launch_describe(lx, ly, W, H, kaze_num_levels(p), desc_levels(p), kps, count,
+                              capacity, angles, descriptors, s));
     return KAZE_OK;
 }
 
@@ -1204,8 +1280,8 @@ kaze_status kaze_sg_default_config(kaze_sg_config* c) {
 
 size_t kaze_sg_scale_space_workspace_bytes(int W, int H, const kaze_params* p,
                                            const kaze_sg_config* c) {
-    if (check_params(p) != KAZE_OK || p->scheme != KAZE_AOS || check_sg_config(c) != KAZE_OK ||
-        check_size(W, H) != KAZE_OK)
+    if (check_params(p) != KAZE_OK || p->scheme != KAZE_AOS || p->substeps != 1 ||
+        check_sg_config(c) != KAZE_OK || check_size(W, H) != KAZE_OK)
         return 0;
     const int shape = c->aos_shape >= 0 ? c->aos_shape : 0;
     if (!shape_fits(W, H, shape)) return 0;
@@ -1230,6 +1306,8 @@ kaze_status kaze_sg_scale_space_create(const kaze_image_desc* im, const kaze_par
     if (st != KAZE_OK) return st;
     if (p->scheme != KAZE_AOS)
         return fail(KAZE_ERR_UNSUPPORTED, "the surrogate falls back to AOS steps only");
+    if (p->substeps != 1)
+        return fail(KAZE_ERR_UNSUPPORTED, "the surrogate replaces whole level steps (substeps 1)");
     if ((st = check_steps(p)) != KAZE_OK) return st;
     if ((st = check_sg_config(c)) != KAZE_OK) return st;
     if (!im) return fail(KAZE_ERR_INVALID_ARG, "image descriptor is NULL");

@@ -14,6 +14,7 @@
 namespace kaze {
 
 constexpr int kMaxLevels = 64;
+constexpr int kMaxSubsteps = 64;  // steps per level
 constexpr int kMaxRadius = 16;   // Gaussian radius ceil(3 sigma)
 constexpr int kMaxStep = 8;      // Scharr step of the detector
 constexpr int kWave = 64;        // CDNA wavefront
@@ -28,6 +29,22 @@ struct Taps {
 struct DetLevels {
     int step[kMaxLevels];    // Scharr step round(sigma_n)
     float sn2[kMaxLevels];   // sigma_n^2
+};
+
+// Per-level constants of the description stage: Scharr step, sigma_n and
+// the level's scale sigma_i (Eq. 6).
+struct DescLevels {
+    int step[kMaxLevels];
+    float sn[kMaxLevels];
+    float sigma[kMaxLevels];
+};
+
+// The record of kaze_keypoint_refined (24 bytes).
+struct RefinedKeypoint {
+    float x, y;
+    int level;
+    float response, edge_ratio;
+    int kept;
 };
 
 // Half-sample symmetric reflection of index i into [0, n):
@@ -276,6 +293,8 @@ enum KernelId {
     K_SG_PROBE,
     K_FED,
     K_REFINE,
+    K_DERIV,
+    K_DESCRIBE,
     K_COUNT
 };
 
@@ -340,6 +359,13 @@ int nms_blocks_of(int W, int H);
 hipError_t launch_refine(const float* det, int W, int H, int N, const void* kps,
                          const int* count, int capacity, float thr, void* out, hipStream_t s);
 hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t s);
+// Description stage: scale-normalised first derivatives of N levels, and
+// orientation + M-SURF descriptor of min(*count, capacity) refined keypoints.
+hipError_t launch_deriv(const float* levels, int W, int H, int N, const DescLevels& dl, float* lx,
+                        float* ly, hipStream_t s);
+hipError_t launch_describe(const float* lx, const float* ly, int W, int H, int N,
+                           const DescLevels& dl, const void* kps, const int* count, int capacity,
+                           float* angles, float* desc, hipStream_t s);
 hipError_t launch_copy(const float* src, float* dst, size_t n, hipStream_t s);
 
 }  // namespace kaze

@@ -35,6 +35,7 @@ EXPORTS = (
     "kaze_kernel_names", "kaze_copy_f32", "kaze_batch_workspace_bytes",
     "kaze_batch_create", "kaze_batch_run", "kaze_batch_destroy", "kaze_batch_autotune",
     "kaze_batch_properties", "kaze_fed_schedule", "kaze_fed_cycle", "kaze_refine_keypoints",
+    "kaze_derivatives", "kaze_describe_keypoints",
 )
 
 
@@ -57,6 +58,7 @@ class kaze_params(ctypes.Structure):
         ("det_threshold", ctypes.c_double),
         ("scheme", ctypes.c_int),
         ("extrema_window", ctypes.c_int),
+        ("substeps", ctypes.c_int),
     ]
 
 
@@ -108,6 +110,8 @@ def _load():
         "kaze_detector_response": (i32, [vp, i32, i32, P, vp, vp]),
         "kaze_find_extrema": (i32, [vp, i32, i32, P, vp, i32, vp, vp]),
         "kaze_refine_keypoints": (i32, [vp, i32, i32, P, vp, vp, i32, f64, vp, vp]),
+        "kaze_derivatives": (i32, [vp, i32, i32, P, vp, vp, vp]),
+        "kaze_describe_keypoints": (i32, [vp, vp, i32, i32, P, vp, vp, i32, vp, vp, vp]),
         "kaze_last_error": (ctypes.c_char_p, []),
         "kaze_profile_begin": (i32, [ctypes.c_char_p]),
         "kaze_profile_end": (i32, [ctypes.POINTER(i32), ctypes.POINTER(f64)]),
@@ -231,6 +235,18 @@ def kaze_refine_keypoints(det, W, H, p, kps, count, capacity, edge_ratio, out, s
                                      capacity, float(edge_ratio), _ptr(out), _stream(stream)))
 
 
+def kaze_derivatives(levels, W, H, p, lx, ly, stream=None):
+    _check(lib.kaze_derivatives(_ptr(levels), W, H, ctypes.byref(p), _ptr(lx), _ptr(ly),
+                                _stream(stream)))
+
+
+def kaze_describe_keypoints(lx, ly, W, H, p, kps, count, capacity, angles, descriptors,
+                            stream=None):
+    _check(lib.kaze_describe_keypoints(_ptr(lx), _ptr(ly), W, H, ctypes.byref(p), _ptr(kps),
+                                       _ptr(count), capacity, _ptr(angles), _ptr(descriptors),
+                                       _stream(stream)))
+
+
 def kaze_copy_f32(src, dst, n, stream=None):
     _check(lib.kaze_copy_f32(_ptr(src), _ptr(dst), n, _stream(stream)))
 
@@ -349,6 +365,24 @@ class Kaze:
                                        device=self.kps.device)
         kaze_refine_keypoints(self.det, self.W, self.H, self.p, self.kps, self.count,
                               self.capacity, edge_ratio, self.refined, stream)
+
+    def describe(self, stream=None):
+        """Derivatives of the last run's levels and the orientation and
+        descriptor of every refined keypoint (kaze_derivatives,
+        kaze_describe_keypoints; call refine() first): fills ``self.lx``,
+        ``self.ly``, ``self.angles`` (capacity,) and ``self.descriptors``
+        (capacity, 64), in the order of ``self.kps``."""
+        import torch
+        if getattr(self, "lx", None) is None:
+            self.lx = torch.empty_like(self.levels)
+            self.ly = torch.empty_like(self.levels)
+            cap = max(self.capacity, 1)
+            self.angles = torch.empty(cap, dtype=torch.float32, device=self.levels.device)
+            self.descriptors = torch.empty((cap, 64), dtype=torch.float32,
+                                           device=self.levels.device)
+        kaze_derivatives(self.levels, self.W, self.H, self.p, self.lx, self.ly, stream)
+        kaze_describe_keypoints(self.lx, self.ly, self.W, self.H, self.p, self.refined, self.count,
+                                self.capacity, self.angles, self.descriptors, stream)
 
     def refined_keypoints(self):
         """Host (n, 6) float64 array (level, y, x, response, edge_ratio,

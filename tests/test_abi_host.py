@@ -143,7 +143,7 @@ def test_workspace_bytes(K):
     ("sigma0", 6.0, -4), ("diffusivity", 3, -1), ("k_percentile", 0.0, -1),
     ("k_percentile", 1.5, -1), ("k_bins", 0, -1), ("k_bins", 5000, -1),
     ("sigma_cond", 1.4, -4), ("scheme", 2, -1), ("extrema_window", 2, -1),
-    ("extrema_window", -1, -1),
+    ("extrema_window", -1, -1), ("substeps", 0, -1), ("substeps", 65, -1),
 ])
 @no_gpu_only
 def test_invalid_params_rejected_before_launch(K, field, value, status):
@@ -297,3 +297,39 @@ def test_refine_arguments_rejected_before_launch(K):
     bad = K.kaze_default_params(octaves=0)
     with pytest.raises(K.KazeError):
         K.kaze_refine_keypoints(256, 64, 64, bad, 512, 768, 4, 10.0, 1024, 0)
+
+
+def test_substeps_parameter(K):
+    p = K.kaze_default_params()
+    assert p.substeps == 1
+    base = K.kaze_workspace_bytes(320, 240, p)
+    p2 = K.kaze_default_params(substeps=3)
+    assert K.kaze_workspace_bytes(320, 240, p2) == base + 320 * 240 * 4
+    for bad in (0, 65, -2):
+        assert K.kaze_workspace_bytes(320, 240, K.kaze_default_params(substeps=bad)) == 0
+    D = K.kaze_image_desc
+    im = [D(256, 100, 80, 100, 512, 1024, 2048, 4096, 10, 8192)]
+    assert K.kaze_batch_workspace_bytes(im, p2, 0) > K.kaze_batch_workspace_bytes(im, p, 0)
+
+
+def test_surrogate_rejects_substeps(K):
+    from paper_1706_06750_amd import surrogate as S
+    c = S.kaze_sg_default_config()
+    assert S.kaze_sg_scale_space_workspace_bytes(64, 64, K.kaze_default_params(), c) > 0
+    assert S.kaze_sg_scale_space_workspace_bytes(64, 64, K.kaze_default_params(substeps=2), c) == 0
+
+
+@no_gpu_only
+def test_describe_arguments_rejected_before_launch(K):
+    p = K.kaze_default_params()
+    ok = dict(lx=256, ly=512, W=64, H=64, kps=768, count=1024, capacity=4, ang=1280, desc=1536)
+    for c in (dict(capacity=-1), dict(lx=0), dict(ly=0), dict(kps=0), dict(count=0),
+              dict(ang=0), dict(desc=0), dict(desc=1538), dict(W=7), dict(H=4097)):
+        a = dict(ok, **c)
+        with pytest.raises(K.KazeError):
+            K.kaze_describe_keypoints(a["lx"], a["ly"], a["W"], a["H"], p, a["kps"], a["count"],
+                                      a["capacity"], a["ang"], a["desc"], 0)
+    for c in (dict(levels=0), dict(lx=0), dict(ly=0), dict(W=7)):
+        a = dict(dict(levels=256, lx=512, ly=768, W=64), **c)
+        with pytest.raises(K.KazeError):
+            K.kaze_derivatives(a["levels"], a["W"], 64, p, a["lx"], a["ly"], 0)
