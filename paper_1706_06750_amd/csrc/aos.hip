@@ -170,11 +170,9 @@ __device__ __forceinline__ int reflect_clamp(int i, int n) {
     return i < 0 ? 0 : i;
 }
 
-// Global-memory views of the image planes: with the address space explicit
-// and the row offsets wave-uniform, a row access is one load or store with a
-// scalar base and the lane's byte offset.
-typedef __attribute__((address_space(1))) float gfloat;
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// Image planes are read and written through gfloat with wave-uniform row
+// offsets: a row access is one load or store with a scalar base and the
+// lane's byte offset.
 
 // LDS geometry of the reduction tile: kAosTX x TY pixels.  With the
 // conductivity computed here (CG) the tile holds L on a ring of RG + 2 (the

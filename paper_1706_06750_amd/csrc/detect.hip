@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kTileThreads) void det_kernel(BatchImage d0, ImgWor
     int lt;
     resolve(d0, w, bx, d, lt);
     const int W = d.W, H = d.H;
-    float* __restrict__ det = d.det;
+    gfloat* __restrict__ det = (gfloat*)d.det;
     const float sn2 = dl.sn2[lev];
     const size_t plane = (size_t)W * H;
     const float* L = d.levels + plane * lev;
@@ -115,10 +115,10 @@ struct KeypointOut {
     float response;
 };
 
-__device__ __forceinline__ void push_keypoint(const BatchImage& d, KeypointOut* kps, int x, int y,
-                                              int lev, float v) {
-    const int idx = atomicAdd(d.count, 1);
-    if (idx < d.capacity) {
+__device__ __forceinline__ void push_keypoint(int* count, int capacity, KeypointOut* kps, int x,
+                                              int y, int lev, float v) {
+    const int idx = atomicAdd(count, 1);
+    if (idx < capacity) {
         KeypointOut k;
         k.x = x;
         k.y = y;
@@ -158,9 +158,11 @@ __global__ __launch_bounds__(256) void nms_kernel(BatchImage d0, ImgWork w, floa
     const int lev = by + 1;
     const int h = radii.h[lev];
     const size_t plane = (size_t)W * H;
-    const float* base = d.det + plane * lev;
+    const gfloat* base = (const gfloat*)d.det + plane * lev;
     KeypointOut* kps = static_cast<KeypointOut*>(d.kps);
-    const bool x_in = x >= 1 && x <= W - 2;
+    if constexpr (!WIDE)
+        if (x < 1 || x > W - 2) return;
+    const bool x_in = !WIDE || (x >= 1 && x <= W - 2);
     float v[kNmsRows];
 #pragma unroll
     for (int q = 0; q < kNmsRows; ++q) {
@@ -173,7 +175,7 @@ __global__ __launch_bounds__(256) void nms_kernel(BatchImage d0, ImgWork w, floa
         for (int q = 0; q < kNmsRows; ++q) {
             if (!(v[q] > threshold)) continue;
             const int y = y0 + q;
-            const float* c = base + (size_t)y * W + x;
+            const gfloat* c = base + (size_t)y * W + x;
             bool is_max = true;
             for (int dl = -1; dl <= 1 && is_max; ++dl)
                 for (int dy = -1; dy <= 1; ++dy)
@@ -181,7 +183,7 @@ __global__ __launch_bounds__(256) void nms_kernel(BatchImage d0, ImgWork w, floa
                         if (dl == 0 && dy == 0 && dx == 0) continue;
                         is_max = is_max && (v[q] > c[(ptrdiff_t)dl * (ptrdiff_t)plane + dy * W + dx]);
                     }
-            if (is_max) push_keypoint(d, kps, x, y, lev, v[q]);
+            if (is_max) push_keypoint(d.count, d.capacity, kps, x, y, lev, v[q]);
         }
         return;
     }
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(256) void nms_kernel(BatchImage d0, ImgWork w, floa
         const int y = y0 + q;
         bool cand = v[q] > threshold;  // false outside the image (-inf)
         if (cand) {
-            const float* c = base + (size_t)y * W + x;
+            const gfloat* c = base + (size_t)y * W + x;
             for (int dy = -1; dy <= 1; ++dy)
                 for (int dx = -1; dx <= 1; ++dx)
                     if (dy != 0 || dx != 0) cand = cand && (v[q] > c[dy * W + dx]);
@@ -217,7 +219,7 @@ __global__ __launch_bounds__(256) void nms_kernel(BatchImage d0, ImgWork w, floa
                 const int yy = wy0 + u / ww, xx = wx0 + u % ww;
                 ok = ok && (cv > base[off + (ptrdiff_t)yy * W + xx]);
             }
-            if (__ballot(!ok) == 0 && lane == l) push_keypoint(d, kps, x, y, lev, v[q]);
+            if (__ballot(!ok) == 0 && lane == l) push_keypoint(d.count, d.capacity, kps, x, y, lev, v[q]);
         }
     }
 }
@@ -272,16 +274,213 @@ __global__ __launch_bounds__(256) void refine_kernel(const float* det, int W, in
     out[i] = r;
 }
 
+// Row-rolling form for steps S <= 4 (the default schedule's are 2 and 3):
+// lane = column, so no index needs a division and every row address is
+// wave-uniform.  Phase 1 stages L on the tile + 2S ring (row by row, lanes
+// over the first 64 columns, the last 4S columns one value per thread);
+// phase 2 computes the first derivatives on the tile + S ring, each lane
+// walking a band of rows with the three values of its columns c - S, c,
+// c + S of every row in registers; phase 3 does the same over the first
+// derivatives for L_xx, L_xy, L_yy and stores det row by row.  Ring
+// positions outside the image then take the derivative at their reflected
+// position (a copy inside LDS, border tiles only).  The arithmetic is the
+// 2-D kernel's, term for term.
+constexpr int kDetRowsTY = 32;
+
+template <int S>
+struct RowDetGeom {
+    static constexpr int TY = kDetRowsTY;
+    static constexpr int NY = TY + 4 * S, NX = DTX + 4 * S, PI = NX | 1;
+    static constexpr int NYF = TY + 2 * S, NXF = DTX + 2 * S, PF = NXF | 1;
+    static constexpr int offX = NY * PI, offY = offX + NYF * PF, floats = offY + NYF * PF;
+    static constexpr int WAVES = kTileThreads / kWave;
+    static constexpr int RPW = (NY + WAVES - 1) / WAVES;     // staged rows per wave
+    static constexpr int FB = (NYF + WAVES - 1) / WAVES;     // first-derivative rows per wave
+    static constexpr int OB = TY / WAVES;                    // output rows per wave
+    static_assert(OB * WAVES == TY, "output bands tile the tile");
+};
+
+__device__ __forceinline__ float scharr3(float a0, float a1, float a2) {
+    return 0.1875f * a0 + 0.625f * a1 + 0.1875f * a2;
+}
+
+template <int S>
+__global__ __launch_bounds__(kTileThreads) void det_rows_kernel(BatchImage d0, ImgWork w,
+                                                                DetLevels dl, int lev0, int lev1) {
+    using G = RowDetGeom<S>;
+    extern __shared__ float smem[];
+    float* sI = smem;
+    float* sX = smem + G::offX;
+    float* sY = smem + G::offY;
+    int bx, by;
+    xcd_grid(bx, by);
+    const int lev = dl.list[by];  // the launch's levels with Scharr step S
+    (void)lev0;
+    (void)lev1;
+    BatchImage d;
+    int lt;
+    resolve(d0, w, bx, d, lt);
+    const int W = d.W, H = d.H;
+    const int tid = threadIdx.x, wave = uniform(tid / kWave), lane = tid % kWave;
+    const float sn2 = dl.sn2[lev];
+    const size_t plane = (size_t)W * H;
+    const gfloat* L = (const gfloat*)(d.levels + plane * lev);
+    const int ncx = (W + DTX - 1) / DTX;
+    const int tx0 = (lt % ncx) * DTX, ty0 = (lt / ncx) * G::TY;
+    constexpr float inv2s = 1.f / (float)(2 * S);
+
+    // phase 1: L on rows ty0-2S.., columns tx0-2S.. (reflected).  Offsets
+    // within a plane fit 32 bits (sides <= 4096); a tile whose ring lies in
+    // the image skips the reflection.
+    {
+        const int gy0 = ty0 - 2 * S, gx0 = tx0 - 2 * S;
+        const bool inside = gy0 >= 0 && gx0 >= 0 && gy0 + G::NY <= H && gx0 + G::NX <= W;
+        constexpr int NE = G::NY * 4 * S;  // the last 4S columns
+        constexpr int PE = (NE + kTileThreads - 1) / kTileThreads;
+        float v[G::RPW], e[PE];
+        if (inside) {
+            const gfloat* Lt = L + gy0 * W + gx0;
+#pragma unroll
+            for (int j = 0; j < G::RPW; ++j) {
+                const int r = min(wave + G::WAVES * j, G::NY - 1);
+                v[j] = Lt[r * W + lane];
+            }
+#pragma unroll
+            for (int q = 0; q < PE; ++q) {
+                const int i = tid + q * kTileThreads;
+                const int r = min(i / (4 * S), G::NY - 1), c = DTX + i % (4 * S);
+                e[q] = Lt[r * W + c];
+            }
+        } else {
+            const int gxa = reflect_index(gx0 + lane, W);
+#pragma unroll
+            for (int j = 0; j < G::RPW; ++j) {
+                const int r = min(wave + G::WAVES * j, G::NY - 1);
+                v[j] = L[uniform(reflect_index(gy0 + r, H)) * W + gxa];
+            }
+#pragma unroll
+            for (int q = 0; q < PE; ++q) {
+                const int i = tid + q * kTileThreads;
+                const int r = min(i / (4 * S), G::NY - 1), c = DTX + i % (4 * S);
+                e[q] = L[reflect_index(gy0 + r, H) * W + reflect_index(gx0 + c, W)];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < G::RPW; ++j) {
+            const int r = wave + G::WAVES * j;
+            if (r < G::NY) sI[r * G::PI + lane] = v[j];
+        }
+#pragma unroll
+        for (int q = 0; q < PE; ++q) {
+            const int i = tid + q * kTileThreads;
+            if (i < NE) sI[(i / (4 * S)) * G::PI + DTX + i % (4 * S)] = e[q];
+        }
+    }
+    __syncthreads();
+
+    // phase 2: first derivatives at f-row rf, f-column cf (image row
+    // ty0 - S + rf, column tx0 - S + cf), from staged rows rf, rf+S, rf+2S
+    // and columns cf, cf+S, cf+2S
+    {
+        const int f0 = wave * G::FB;
+        constexpr int K = G::FB + 2 * S;
+        float aL[K], aC[K], aR[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float* row = sI + min(f0 + k, G::NY - 1) * G::PI + lane;
+            aL[k] = row[0];
+            aC[k] = row[S];
+            aR[k] = row[2 * S];
+        }
+#pragma unroll
+        for (int t = 0; t < G::FB; ++t) {
+            const int rf = f0 + t;
+            if (rf < G::NYF) {
+                sX[rf * G::PF + lane] =
+                    scharr3(aR[t] - aL[t], aR[t + S] - aL[t + S], aR[t + 2 * S] - aL[t + 2 * S]) * inv2s;
+                sY[rf * G::PF + lane] =
+                    scharr3(aL[t + 2 * S] - aL[t], aC[t + 2 * S] - aC[t], aR[t + 2 * S] - aR[t]) * inv2s;
+            }
+        }
+        // the last 2S f-columns, one position per thread
+        constexpr int NE = G::NYF * 2 * S;
+        for (int i = tid; i < NE; i += kTileThreads) {
+            const int rf = i / (2 * S), cf = DTX + i % (2 * S);
+            const float* c = sI + (rf + S) * G::PI + (cf + S);
+            const float a00 = c[-S * G::PI - S], a02 = c[-S * G::PI + S];
+            const float a20 = c[S * G::PI - S], a22 = c[S * G::PI + S];
+            const float a10 = c[-S], a12 = c[S], a01 = c[-S * G::PI], a21 = c[S * G::PI];
+            sX[rf * G::PF + cf] = scharr3(a02 - a00, a12 - a10, a22 - a20) * inv2s;
+            sY[rf * G::PF + cf] = scharr3(a20 - a00, a21 - a01, a22 - a02) * inv2s;
+        }
+    }
+    __syncthreads();
+    // ring positions outside the image take the derivative at their
+    // reflected (in-image, already computed) position
+    if (ty0 - S < 0 || tx0 - S < 0 || ty0 + G::TY + S > H || tx0 + DTX + S > W) {
+        for (int i = tid; i < G::NYF * G::NXF; i += kTileThreads) {
+            const int rf = i / G::NXF, cf = i - rf * G::NXF;
+            const int gy = ty0 - S + rf, gx = tx0 - S + cf;
+            const bool out = gy < 0 || gx < 0 || gy >= H || gx >= W;
+            if (!out || gy > H - 1 + S || gx > W - 1 + S) continue;
+            const int sy = reflect_index(gy, H) - ty0 + S, sx = reflect_index(gx, W) - tx0 + S;
+            sX[rf * G::PF + cf] = sX[sy * G::PF + sx];
+            sY[rf * G::PF + cf] = sY[sy * G::PF + sx];
+        }
+        __syncthreads();
+    }
+
+    // phase 3: output row r (tile) uses f-rows r, r+S, r+2S and f-columns
+    // c, c+S, c+2S
+    {
+        const int o0 = wave * G::OB;
+        constexpr int K = G::OB + 2 * S;
+        float xL[K], xC[K], xR[K], yL[K], yC[K], yR[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float* rx = sX + (o0 + k) * G::PF + lane;
+            const float* ry = sY + (o0 + k) * G::PF + lane;
+            xL[k] = rx[0];
+            xC[k] = rx[S];
+            xR[k] = rx[2 * S];
+            yL[k] = ry[0];
+            yC[k] = ry[S];
+            yR[k] = ry[2 * S];
+        }
+        const int gx = tx0 + lane;
+        gfloat* out = (gfloat*)(d.det + plane * lev) + (ty0 + o0) * W + tx0;
+#pragma unroll
+        for (int t = 0; t < G::OB; ++t) {
+            const float Lxx =
+                scharr3(xR[t] - xL[t], xR[t + S] - xL[t + S], xR[t + 2 * S] - xL[t + 2 * S]) * inv2s;
+            const float Lxy =
+                scharr3(xL[t + 2 * S] - xL[t], xC[t + 2 * S] - xC[t], xR[t + 2 * S] - xR[t]) * inv2s;
+            const float Lyy =
+                scharr3(yL[t + 2 * S] - yL[t], yC[t + 2 * S] - yC[t], yR[t + 2 * S] - yR[t]) * inv2s;
+            if (ty0 + o0 + t < H && gx < W) out[t * W + lane] = sn2 * (Lxx * Lyy - Lxy * Lxy);
+        }
+    }
+}
+
 template <int S>
 hipError_t launch_det_s(const BatchImage& d0, const ImgWork& w, int lev0, int lev1,
                         const DetLevels& dl, hipStream_t s) {
+    DetLevels dls = dl;  // with the list of this launch's levels
     int n = 0;
-    for (int i = lev0; i < lev1; ++i) n += dl.step[i] == S;
+    for (int i = lev0; i < lev1; ++i)
+        if (dl.step[i] == S) dls.list[n++] = i;
     const int count = w.items ? w.count : det_tiles_of(d0.W, d0.H);
     if (n == 0 || count <= 0) return hipSuccess;
-    const size_t lds = (size_t)DetGeom<S>::floats * sizeof(float);
-    hipLaunchKernelGGL(det_kernel<S>, dim3(count, n), dim3(kTileThreads), lds, s, d0, w, dl, lev0,
-                       lev1);
+    if constexpr (S <= 4) {
+        static_assert(kDetRowsTY == DTY, "both forms tile alike");
+        const size_t lds = (size_t)RowDetGeom<S>::floats * sizeof(float);
+        hipLaunchKernelGGL(det_rows_kernel<S>, dim3(count, n), dim3(kTileThreads), lds, s, d0, w,
+                           dls, lev0, lev1);
+    } else {
+        const size_t lds = (size_t)DetGeom<S>::floats * sizeof(float);
+        hipLaunchKernelGGL(det_kernel<S>, dim3(count, n), dim3(kTileThreads), lds, s, d0, w, dl,
+                           lev0, lev1);
+    }
     return hipGetLastError();
 }
 

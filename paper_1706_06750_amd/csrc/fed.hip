@@ -111,10 +111,6 @@ std::vector<double> fed_schedule(double T) {
 // ---------------------------------------------------------------- device
 namespace {
 
-typedef __attribute__((address_space(1))) float gfloat;
-
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
 __device__ __forceinline__ int reflect_clamp(int i, int n) {
     i = i < 0 ? -1 - i : i;
     i = i >= n ? 2 * n - 1 - i : i;

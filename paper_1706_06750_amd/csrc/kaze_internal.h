@@ -29,6 +29,7 @@ struct Taps {
 struct DetLevels {
     int step[kMaxLevels];    // Scharr step round(sigma_n)
     float sn2[kMaxLevels];   // sigma_n^2
+    int list[kMaxLevels];    // per launch: the levels it covers, in order
 };
 
 // Per-level constants of the description stage: Scharr step, sigma_n and
@@ -46,6 +47,16 @@ struct RefinedKeypoint {
     float response, edge_ratio;
     int kept;
 };
+
+// Global-memory views.  Kernels copy their descriptors into registers
+// (resolve), which hides the address space of the pointers inside from the
+// compiler: accesses through them become flat loads and stores, which wait
+// on both memory counters.  A cast back keeps them global.
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) unsigned guint;
+
+// A wave-uniform value in a scalar register (row addresses, loop bounds).
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Half-sample symmetric reflection of index i into [0, n):
 // -1 -> 0, -2 -> 1, n -> n-1, n+1 -> n-2, periodic with period 2n.

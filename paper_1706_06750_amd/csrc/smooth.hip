@@ -32,8 +32,8 @@ __global__ __launch_bounds__(kTileThreads) void gauss_kernel(BatchImage d0, ImgW
     BatchImage d;
     int lt;
     resolve(d0, work, xcd_contiguous((int)blockIdx.x, (int)gridDim.x), d, lt);
-    const float* __restrict__ src = d.img;
-    float* __restrict__ dst = d.levels;
+    const gfloat* __restrict__ src = (const gfloat*)d.img;
+    gfloat* __restrict__ dst = (gfloat*)d.levels;
     const int W = d.W, H = d.H, ld = d.ld;
     const int ncx = (W + kTile - 1) / kTile;
     const int tx0 = (lt % ncx) * kTile, ty0 = (lt / ncx) * kTile;
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kTileThreads) void cond_kernel(BatchImage d0, ImgWo
     int lt;
     resolve(d0, w, xcd_contiguous((int)blockIdx.x, (int)gridDim.x), d, lt);
     const int W = d.W, H = d.H;
-    float* __restrict__ out = d.g;
+    gfloat* __restrict__ out = (gfloat*)d.g;
     const int ncx = (W + kTile - 1) / kTile;
     const int tx0 = (lt % ncx) * kTile, ty0 = (lt / ncx) * kTile;
     load_L_ring<G>(d.levels, W, H, tx0, ty0, sL);
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void hist_kernel(BatchImage d0, ImgWork w, int
     const int n = d.W * d.H;
     const int i0 = chunk * kHistChunk, i1 = min(n, i0 + kHistChunk);
     for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-        const float v = d.g[i];
+        const float v = ((const gfloat*)d.g)[i];
         if (v > 0.f) {
             const float m = sqrtf(v);
             int b = (int)floorf(m / hmax * fb);
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(256) void kselect_kernel(BatchImage d0, ImgWork w, 
     BatchImage d;
     int unused;
     resolve(d0, w, (int)blockIdx.x, d, unused);
-    const unsigned* __restrict__ hist = d.hist;
+    const guint* __restrict__ hist = (const guint*)d.hist;
     __shared__ unsigned long long s_scan[256];
     __shared__ int s_best;
     const int t = threadIdx.x;

@@ -54,9 +54,10 @@ __device__ __forceinline__ void stage_region(const float* __restrict__ src, int 
     constexpr int TOTAL = NY * NX;
     constexpr int PER = (TOTAL + NT - 1) / NT;
     const bool interior = gy0 >= 0 && gx0 >= 0 && gy0 + NY <= H && gx0 + NX <= W;
+    const gfloat* g = (const gfloat*)src;
     float v[PER];
     if (interior) {
-        const float* base = src + (size_t)gy0 * W + gx0;
+        const gfloat* base = g + (size_t)gy0 * W + gx0;
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int i = threadIdx.x + j * NT;
@@ -72,7 +73,7 @@ __device__ __forceinline__ void stage_region(const float* __restrict__ src, int 
             if (i < TOTAL) {
                 const int ly = i / NX, lx = i - ly * NX;
                 const int gy = reflect_index(gy0 + ly, H), gx = reflect_index(gx0 + lx, W);
-                v[j] = src[(size_t)gy * W + gx];
+                v[j] = g[(size_t)gy * W + gx];
             }
         }
     }
