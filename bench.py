@@ -42,11 +42,11 @@ def tile_label(K, shape):
     return "%dx%d" % K.AOS_SHAPES[shape]
 
 
-def traffic_from_profile(key, aos_tile, with_det):
+def traffic_from_profile(key, aos_tile, det_levels):
     """HBM bytes per step of the level segment from the committed counter
     summary profiles/level_traffic_<key>.json, if it was taken on the current
-    per-level kernel sources with the same tile shape (the detector's share
-    only where it runs in the segment)."""
+    per-level kernel sources with the same tile shape and the same number of
+    detector levels inside the segment."""
     from paper_1706_06750_amd.rocprof_summary import csrc_hash
     path = os.path.join(ROOT, "profiles", "level_traffic_%s.json" % key)
     if not os.path.exists(path):
@@ -55,7 +55,7 @@ def traffic_from_profile(key, aos_tile, with_det):
         d = json.load(fh)
     if d.get("csrc_hash") != csrc_hash(ROOT) or d.get("aos_tile") != aos_tile:
         return None
-    if bool(d.get("det_in_segment")) != bool(with_det):
+    if d.get("det_levels_in_segment") != det_levels:
         return None
     return round(d["bytes_per_level"])
 
@@ -90,15 +90,17 @@ def cpu_baseline(W, H, seed):
                       "%.1f s" % (W, H, seed, r["seconds"])}
 
 
-def level_roofline(level_us, px, traffic, levels=16, with_det=True):
+def level_roofline(level_us, px, traffic, levels=16, det_levels=0):
     """Per step of the level segment (its time / (levels - 1)); algorithmic
-    bytes of the segment spread over the steps."""
-    seg = (levels - 1) * STEP_ALGO_BYTES_PER_PX + (levels * DET_ALGO_BYTES_PER_PX if with_det else 0)
+    bytes of the segment (the steps and the detector levels that run beside
+    them) spread over the steps."""
+    seg = (levels - 1) * STEP_ALGO_BYTES_PER_PX + det_levels * DET_ALGO_BYTES_PER_PX
     algo = seg * px / (levels - 1)
     achieved = algo / (level_us * 1e-6) / 1e9
     return {
         "kernel": "one level of the level segment: conductivity + AOS step (" +
-                  "+".join(AOS_KERNELS) + ")" + (" with det_kernel overlapped" if with_det else ""),
+                  "+".join(AOS_KERNELS) + ")" +
+                  (" with the detector of %d levels overlapped" % det_levels if det_levels else ""),
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
@@ -182,20 +184,41 @@ def record(args, value, ms_per_step, config, roofline, extra):
     return rec
 
 
-def timed_graph_runs(args, K, torch, kb):
-    """Timed region: graph replays of the plan; an event pair brackets the
-    AOS-step segment of every run on the stream it runs on.  Returns
-    (seconds, microseconds per level)."""
+def timed_runs(args, K, torch, kb, eager):
+    """Timed region: runs of the plan (eager launches or graph replays); an
+    event pair brackets the AOS-step segment of every run on the stream it
+    runs on.  Returns (seconds, microseconds per level)."""
+    for _ in range(args.warmup):
+        kb.run(eager=eager)
+    torch.cuda.synchronize()
     K.kaze_profile_begin("aos_reduce")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        kb.run()
+        kb.run(eager=eager)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     runs, ms = K.kaze_profile_end()
     assert runs == args.steps
     return elapsed, 1e3 * ms / (runs * (kb.N - 1))
+
+
+def det_levels_of(kb, form):
+    """Detector levels inside the level segment of a run: a graph run's per
+    the plan; an eager run keeps the single fork of small batches out."""
+    d = kb.det_levels_in_segment
+    return d if form == "graph" or d == kb.N else 0
+
+
+def timed_plan(args, K, torch, kb, n_images):
+    """Both launch forms of the plan are timed over the same K steps; the
+    faster is the reported one.  Returns (seconds, us per level, form, the
+    per-form figures)."""
+    res = {form: timed_runs(args, K, torch, kb, form == "eager") for form in ("eager", "graph")}
+    best = min(res, key=lambda f: res[f][0])
+    forms = {f: {"images_per_s": round(n_images * args.steps / e, 3), "us_per_level": round(u, 3)}
+             for f, (e, u) in res.items()}
+    return res[best][0], res[best][1], best, forms
 
 
 def bench_single(args, K, torch, kaze_image, case):
@@ -229,23 +252,21 @@ def bench_single(args, K, torch, kaze_image, case):
     torch.cuda.synchronize()
     eager_value = eager_steps / (time.perf_counter() - t1)
 
-    # timed path: the image's plan replayed from its captured graphs
+    # timed path: the image's plan (eager launches or graph replays, the
+    # faster of the two)
     kb = K.KazeBatch([(W, H)], shape="auto")
     kb.inputs[0].copy_(img)
-    for _ in range(args.warmup):
-        kb.run()
-    torch.cuda.synchronize()
-    elapsed, level_us = timed_graph_runs(args, K, torch, kb)
+    elapsed, level_us, form, forms = timed_plan(args, K, torch, kb, 1)
     roof = level_roofline(level_us, W * H,
                           traffic_from_profile("%dx%d" % (W, H), tile_label(K, kb.shape),
-                                               kb.det_in_level_segment),
-                          with_det=kb.det_in_level_segment)
+                                               det_levels_of(kb, form)),
+                          det_levels=det_levels_of(kb, form))
     roof["timed_in"] = "the timed region (event pair around each run's AOS segment)"
     kps = int(kb.count[0].item())
     shape = tile_label(K, kb.shape)
     kb.close()
 
-    extra = {"eager_images_per_s": round(eager_value, 3),
+    extra = {"eager_images_per_s": round(eager_value, 3), "plan_launch_forms": forms,
              "kernel_breakdown": {k: {kk: round(vv, 4) for kk, vv in v.items()}
                                   for k, v in breakdown.items()}}
     if not args.no_fed:
@@ -260,7 +281,9 @@ def bench_single(args, K, torch, kaze_image, case):
     if not args.no_cpu_baseline:
         extra["cpu_baseline"] = cpu_baseline(W, H, seed)
     config = {"workload": args.workload, "image": "%dx%d" % (W, H), "seed": seed,
-              "levels": kz.N, "path": "plain AOS (no surrogate), graph replay",
+              "levels": kz.N,
+              "path": "plain AOS (no surrogate), image plan, %s" %
+                      ("eager launches" if form == "eager" else "graph replay"),
               "aos_tile": shape, "keypoints": kps}
     return record(args, args.steps / elapsed, 1e3 * elapsed / args.steps, config, roof, extra)
 
@@ -424,14 +447,11 @@ def bench_batch(args, K, torch, kaze_image, cases):
     for x, (W, H, seed) in zip(kb.inputs, cases):
         x.copy_(torch.from_numpy(kaze_image(W, H, seed)))
     px = sum(W * H for W, H in sizes)
-    for _ in range(args.warmup):
-        kb.run()
-    torch.cuda.synchronize()
-    elapsed, level_us = timed_graph_runs(args, K, torch, kb)
+    elapsed, level_us, form, forms = timed_plan(args, K, torch, kb, len(sizes))
     roof = level_roofline(level_us, px,
                           traffic_from_profile(args.workload.replace("kaze_", ""),
-                                               tile_label(K, kb.shape), kb.det_in_level_segment),
-                          with_det=kb.det_in_level_segment)
+                                               tile_label(K, kb.shape), det_levels_of(kb, form)),
+                          det_levels=det_levels_of(kb, form))
     roof["timed_in"] = "the timed region (event pair around each run's AOS segment)"
 
     n = len(sizes)
@@ -440,10 +460,13 @@ def bench_batch(args, K, torch, kaze_image, cases):
                                                        max(w for w, _ in sizes),
                                                        min(h for _, h in sizes),
                                                        max(h for _, h in sizes)),
-              "levels": kb.N, "path": "plain AOS, batched, graph replay",
+              "levels": kb.N,
+              "path": "plain AOS, batched, %s" % ("eager launches" if form == "eager"
+                                                   else "graph replay"),
               "aos_tile": tile_label(K, kb.shape),
               "autotune_ms_per_shape": kb.tune_ms}
-    extra = {"megapixels_per_s": round(px * args.steps / elapsed / 1e6, 1)}
+    extra = {"megapixels_per_s": round(px * args.steps / elapsed / 1e6, 1),
+             "plan_launch_forms": forms}
     plain_value = n * args.steps / elapsed
     kb.close()
     del kb

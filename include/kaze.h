@@ -292,20 +292,26 @@ kaze_status kaze_batch_create(const kaze_image_desc* images, int n,
                               size_t ws_bytes, kaze_batch** out);
 
 /*
- * Properties of a created batch: the AOS tile shape in use and whether the
- * level segment of a graph run (the one kaze_profile_begin("aos_reduce")
- * brackets) also holds the detector response (1: large batches, where it
- * runs on a second stream beside the steps; 0: it runs after them).
+ * Properties of a created batch: the AOS tile shape in use and the number of
+ * levels whose detector response runs inside the level segment of a graph
+ * run (the one kaze_profile_begin("aos_reduce") brackets), on a second
+ * stream beside the steps: all N for batches of 8 Mpx and more (level by
+ * level, in eager runs too), the first N - 5 for smaller ones with a
+ * detector (one launch beside the last five steps; eager runs keep it after
+ * the steps), 0 without a detector.
  */
 kaze_status kaze_batch_properties(const kaze_batch* b, int* aos_shape,
-                                  int* det_in_level_segment);
+                                  int* det_levels_in_segment);
 
 /* Enqueues one run of the plan on stream: three graph launches (base image
  * and contrast factor; the AOS steps; detector response and extrema), or
- * with eager != 0 the same kernel launches issued one by one.  Runs that
- * share a plan must be ordered on one stream.  Under kaze_profile_begin
- * with aos_reduce listed, a graph run records one event pair around its
- * AOS-step segment. */
+ * with eager != 0 the same kernel launches issued one by one (faster on
+ * this runtime for one 1920x1200 image: graph replay adds about 30 us per
+ * run).  The detector forks onto the plan's second stream as the
+ * properties below describe, ordered through events.  Runs that share a plan must be
+ * ordered on one stream.  Under kaze_profile_begin with aos_reduce listed,
+ * a run records one event pair around its AOS-step segment (and none
+ * around the single launches inside it). */
 kaze_status kaze_batch_run(kaze_batch* b, int eager, void* stream);
 
 kaze_status kaze_batch_destroy(kaze_batch* b);

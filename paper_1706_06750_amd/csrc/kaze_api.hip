@@ -47,7 +47,8 @@ const char* const kKernelNames[K_COUNT] = {
 
 struct Profiler {
     unsigned mask = 0;  // bit i: record launches of kernel i
-    bool capturing = false;
+    bool capturing = false;  // no pairs while a graph is captured
+    bool in_segment = false; // a batch run's level segment has its own pair
     std::vector<hipEvent_t> ev;  // pairs: start, stop
     int used = 0;
     static constexpr int kMaxPairs = 65536;
@@ -58,7 +59,8 @@ struct ProfScope {
     hipStream_t s;
     bool on;
     ProfScope(int id_, hipStream_t s_) : id(id_), s(s_), on(false) {
-        if (g_prof.capturing || !(g_prof.mask & (1u << id)) || g_prof.used >= Profiler::kMaxPairs)
+        if (g_prof.capturing || g_prof.in_segment || !(g_prof.mask & (1u << id)) ||
+            g_prof.used >= Profiler::kMaxPairs)
             return;
         const size_t need = 2 * (size_t)(g_prof.used + 1);
         while (g_prof.ev.size() < need) {
@@ -367,14 +369,19 @@ struct kaze_batch {
     hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
     hipStream_t side = nullptr;      // fork target while a segment is captured
     std::vector<hipEvent_t> ev;      // fork / join points (N + 1)
-    bool fork_det = false;           // detector response beside the steps
+    bool fork_det = false;           // detector response beside the steps, per level
+    int split_det = -1;              // else: levels 0..split_det forked once
 };
 
 // A captured fork spreads a graph over several hardware queues, and every
 // dependency between queues costs about 10-25 us on this runtime (measured):
-// the detector response runs beside the steps only when each step is long
-// enough to hide that, i.e. for batches of at least this many pixels.
+// the detector response of every level runs beside the steps only when each
+// step is long enough to hide that, i.e. for batches of at least this many
+// pixels.  Smaller batches fork once: the detector of the levels up to
+// kSplitDetBack before the last runs beside the remaining steps, the rest
+// after them.
 constexpr double kForkDetPixels = 8e6;
+constexpr int kSplitDetBack = 5;
 
 extern "C" kaze_status kaze_batch_destroy(kaze_batch* b);
 
@@ -455,8 +462,11 @@ kaze_status check_batch(const kaze_image_desc* im, int n, const kaze_params* p, 
 // The a1-a7 sequence of a batch, one launch per phase for all images, in
 // three segments: 0 base image and contrast factor, 1 the AOS steps and the
 // detector response, 2 extrema.  With a side stream the detector response
-// of each level forks off the step sequence (used while capturing).
-kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStream_t side) {
+// forks off the step sequence: level by level for large batches, once for
+// the first levels of small ones where `split` allows it (graph runs: in
+// eager runs that single fork measured slower than none).
+kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStream_t side,
+                            bool split_ok = true) {
     const kaze_params* p = &B.p;
     const BatchImage b0 = batch_image(0, 0);
     if (seg == 0) {
@@ -468,6 +478,7 @@ kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStre
     const ImgWork det{B.d_imgs, B.d_det, B.n_det};
     const DetLevels dl = det_levels(B.lv);
     const bool fork = B.fork_det && side != nullptr;
+    const int split = side != nullptr && split_ok && !B.fork_det ? B.split_det : -1;
     if (seg == 1) {
         // The detector response of level i needs level i only: with a side
         // stream (graph capture of a large batch) it runs there, overlapping
@@ -499,14 +510,21 @@ kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStre
                 if (st != KAZE_OK) return st;
             }
             if ((st = det_level(i)) != KAZE_OK) return st;
+            if (i == split) {  // levels 0..split beside the remaining steps
+                KZ_HIP(hipEventRecord(B.ev[i], s));
+                KZ_HIP(hipStreamWaitEvent(side, B.ev[i], 0));
+                KZ_LAUNCH(K_DET, side, launch_det(b0, det, 0, split + 1, dl, side));
+            }
         }
-        if (fork) {  // join
-            KZ_HIP(hipEventRecord(B.ev[B.N], ds));
+        if (fork || split >= 0) {  // join
+            hipStream_t js = fork ? ds : side;
+            KZ_HIP(hipEventRecord(B.ev[B.N], js));
             KZ_HIP(hipStreamWaitEvent(s, B.ev[B.N], 0));
         }
         return KAZE_OK;
     }
-    if (B.with_det && !fork) KZ_LAUNCH(K_DET, s, launch_det(b0, det, 0, B.N, dl, s));
+    if (B.with_det && !fork)
+        KZ_LAUNCH(K_DET, s, launch_det(b0, det, split >= 0 ? split + 1 : 0, B.N, dl, s));
     if (B.with_nms) {
         const ImgWork nms{B.d_imgs, B.d_nms, B.n_nms};
         KZ_LAUNCH(K_NMS, s, launch_nms(b0, nms, B.N, (float)p->det_threshold, nms_radii(p), s));
@@ -514,12 +532,21 @@ kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStre
     return KAZE_OK;
 }
 
+// Eager run of a batch plan: the same launches as its graphs, the per-level
+// detector fork of large batches onto the plan's second stream (ordered
+// through events), and under kaze_profile_begin("aos_reduce") one event pair
+// around the level segment as in a graph run.
 kaze_status enqueue_batch(const kaze_batch& B, hipStream_t s) {
-    for (int seg = 0; seg < 3; ++seg) {
-        const kaze_status st = enqueue_segment(B, seg, s, nullptr);
-        if (st != KAZE_OK) return st;
+    kaze_status st = enqueue_segment(B, 0, s, B.side, false);
+    if (st != KAZE_OK) return st;
+    {
+        ProfScope ps(K_AOS_REDUCE, s);
+        g_prof.in_segment = true;
+        st = enqueue_segment(B, 1, s, B.side, false);
+        g_prof.in_segment = false;
     }
-    return KAZE_OK;
+    if (st != KAZE_OK) return st;
+    return enqueue_segment(B, 2, s, B.side, false);
 }
 
 kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p, int shape,
@@ -543,6 +570,8 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
     double px = 0;
     for (int j = 0; j < n; ++j) px += (double)im[j].W * im[j].H;
     B->fork_det = B->with_det && px >= kForkDetPixels;
+    B->split_det = B->with_det && !B->fork_det && B->N > kSplitDetBack + 1
+                       ? B->N - 1 - kSplitDetBack : -1;
     B->d_imgs = reinterpret_cast<BatchImage*>(base + L.imgs);
     B->d_lvl = reinterpret_cast<ImageDesc*>(base + L.lvl);
     B->d_items = reinterpret_cast<int2*>(base + L.items);
@@ -1192,10 +1221,11 @@ kaze_status kaze_batch_create(const kaze_image_desc* images, int n, const kaze_p
     return batch_create(images, n, p, shape, ws, ws_bytes, out);
 }
 
-kaze_status kaze_batch_properties(const kaze_batch* b, int* aos_shape, int* det_in_level_segment) {
+kaze_status kaze_batch_properties(const kaze_batch* b, int* aos_shape, int* det_levels_in_segment) {
     if (!b) return fail(KAZE_ERR_INVALID_ARG, "batch is NULL");
     if (aos_shape) *aos_shape = b->shape;
-    if (det_in_level_segment) *det_in_level_segment = b->fork_det ? 1 : 0;
+    if (det_levels_in_segment)
+        *det_levels_in_segment = b->fork_det ? b->N : b->split_det + 1;
     return KAZE_OK;
 }
 

@@ -288,10 +288,10 @@ def kaze_batch_create(images, p, shape, ws, ws_bytes):
 
 
 def kaze_batch_properties(handle):
-    """(aos_shape, det_in_level_segment) of a created batch."""
+    """(aos_shape, det_levels_in_segment) of a created batch."""
     a, d = ctypes.c_int(), ctypes.c_int()
     _check(lib.kaze_batch_properties(handle, ctypes.byref(a), ctypes.byref(d)))
-    return a.value, bool(d.value)
+    return a.value, d.value
 
 
 def kaze_batch_run(handle, eager=False, stream=None):
@@ -466,7 +466,7 @@ class KazeBatch:
             shape = self._tuned_shape(tune_cache)
         self.shape = int(shape)
         self.handle = kaze_batch_create(descs, self.p, self.shape, self.ws, self.ws_bytes)
-        self.det_in_level_segment = kaze_batch_properties(self.handle)[1]
+        self.det_levels_in_segment = kaze_batch_properties(self.handle)[1]
 
     def _key(self):
         import hashlib

@@ -20,8 +20,8 @@ import hashlib
 import json
 import os
 
-LEVEL_KERNELS = ("aos_reduce_kernel", "aos_iface_kernel", "aos_recover_kernel", "det_kernel")
-DET_PER_STEP = 16.0 / 15.0
+AOS_KERNELS = ("aos_reduce_kernel", "aos_iface_kernel", "aos_recover_kernel")
+DET_KERNELS = ("det_kernel", "det_rows_kernel")
 
 
 def short(name: str) -> str:
@@ -86,24 +86,50 @@ def counter_means(path: str, counter: str, aos_tile: str | None = None):
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
-def traffic(fetch_csv, write_csv, W, H, copy_mib, root, aos_tile, det_per_level=False, pixels=0):
-    """det_per_level: the detector runs once per level (large batches); else
-    its dispatches cover several levels and it is reported apart."""
+def counter_totals(path: str, counter: str):
+    """Sum of the counter over every dispatch and number of dispatches, by
+    kernel (all template instances together)."""
+    tot = collections.defaultdict(float)
+    cnt = collections.defaultdict(int)
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name", r.get("counter_name")) != counter:
+            continue
+        base = short(r.get("Kernel_Name", r.get("kernel_name"))).split("<")[0]
+        tot[base] += float(r.get("Counter_Value", r.get("value")))
+        cnt[base] += 1
+    return tot, cnt
+
+
+def traffic(fetch_csv, write_csv, W, H, copy_mib, root, aos_tile, det_levels=0, pixels=0,
+            levels=16):
+    """Bytes per step of the level segment: the AOS kernels' mean dispatch
+    (the chosen tile only) plus, when det_levels detector levels run inside
+    the segment, their share: the detector's bytes per run (every run holds
+    levels - 1 reductions, whatever the shape) / levels * det_levels, spread
+    over the levels - 1 steps."""
     f = counter_means(fetch_csv, "FETCH_SIZE", aos_tile)
     w = counter_means(write_csv, "WRITE_SIZE", aos_tile)
     known_kib = copy_mib * 1024.0
     fs = known_kib / f["copy_kernel"]
     ws = known_kib / w["copy_kernel"]
     per = {}
-    for k in LEVEL_KERNELS:
-        if k == "det_kernel" and not det_per_level:
-            continue
-        mult = DET_PER_STEP if k == "det_kernel" else 1.0
+    for k in AOS_KERNELS:
         per[k] = {"fetch_kib_raw": f[k], "write_kib_raw": w[k],
-                  "bytes": mult * (f[k] * fs + w[k] * ws) * 1024.0}
+                  "bytes": (f[k] * fs + w[k] * ws) * 1024.0}
+    if det_levels:
+        ft, fc = counter_totals(fetch_csv, "FETCH_SIZE")
+        wt, wc = counter_totals(write_csv, "WRITE_SIZE")
+        runs_f = fc["aos_reduce_kernel"] / (levels - 1)
+        runs_w = wc["aos_reduce_kernel"] / (levels - 1)
+        fk = sum(ft[k] for k in DET_KERNELS) / runs_f / levels
+        wk = sum(wt[k] for k in DET_KERNELS) / runs_w / levels
+        share = det_levels / (levels - 1)
+        per["det (%d levels in the segment)" % det_levels] = {
+            "fetch_kib_raw_per_level": fk, "write_kib_raw_per_level": wk,
+            "bytes": share * (fk * fs + wk * ws) * 1024.0}
     total = sum(v["bytes"] for v in per.values())
     return {"image": "%dx%d" % (W, H) if W else None, "aos_tile": aos_tile,
-            "det_in_segment": det_per_level,
+            "det_levels_in_segment": det_levels,
             "copy_scale_fetch": fs, "copy_scale_write": ws,
             "kernels": per, "bytes_per_level": total,
             "pixels": pixels or W * H,
@@ -121,8 +147,9 @@ def main():
     b.add_argument("--image", required=True, help="WxH of the single image, or a workload name")
     b.add_argument("--copy-mib", type=int, required=True)
     b.add_argument("--aos-tile", required=True, help="AOS tile shape of the run, e.g. 60x32")
-    b.add_argument("--det-per-level", action="store_true",
-                   help="the detector runs once per level inside the level segment (large batches)")
+    b.add_argument("--det-levels", type=int, default=0,
+                   help="detector levels that run inside the level segment (the batch's "
+                        "det_levels_in_segment property)")
     b.add_argument("--pixels", type=int, default=0,
                    help="pixels per level when the run covers several images (default W*H)")
     b.add_argument("--out", required=True)
@@ -133,7 +160,7 @@ def main():
     else:
         W, H = (int(v) for v in args.image.split("x")) if "x" in args.image else (0, 0)
         d = traffic(args.fetch_csv, args.write_csv, W, H, args.copy_mib, root, args.aos_tile,
-                    args.det_per_level, args.pixels)
+                    args.det_levels, args.pixels)
         with open(args.out, "w") as fh:
             json.dump(d, fh, indent=1)
         print(json.dumps(d, indent=1))

@@ -39,6 +39,8 @@ def test_batch_matches_single_image_path(gpu_lib, shape):
     K = gpu_lib
     note(f"[batch] shape {K.AOS_SHAPES[shape]} sizes {SIZES}")
     kb, imgs = make_batch(K, SIZES, range(40, 40 + len(SIZES)), shape)
+    # a small batch forks the detector of its first N - 5 levels once
+    assert kb.det_levels_in_segment == kb.N - 5
     kb.run()
     torch.cuda.synchronize()
     for j, im in enumerate(imgs):
@@ -121,7 +123,7 @@ def test_large_batch_forks_detector_and_matches_eager(gpu_lib):
     sizes = [(1920, 1200), (1900, 1150), (1800, 1100), (1700, 1000), (1600, 1200)]  # 10 Mpx
     note("[batch] large batch %s" % sizes)
     kb, _ = make_batch(K, sizes, range(80, 85), 1)
-    assert kb.det_in_level_segment
+    assert kb.det_levels_in_segment == kb.N
     kb.run(eager=True)
     torch.cuda.synchronize()
     ref_lv = [t.clone() for t in kb.levels]
