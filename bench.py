@@ -66,28 +66,49 @@ sys.path.insert(0, %r)
 import numpy as np
 import oracle as O
 from synthetic import kaze_image
-img = kaze_image(%d, %d, %d).astype(np.float64)
+W, H, seeds = %d, %d, %r
+imgs = [kaze_image(W, H, s).astype(np.float64) for s in seeds]
 t = time.perf_counter()
-lev, k = O.build_scale_space(img)
-det = O.detector_response(lev)
-kp = O.find_extrema(det, 0.001)
-print(json.dumps({"seconds": time.perf_counter() - t, "keypoints": int(len(kp))}))
+for img in imgs:
+    lev, k = O.build_scale_space(img)
+    det = O.detector_response(lev)
+    kp = O.find_extrema(det, 0.001)
+print(json.dumps({"seconds": time.perf_counter() - t, "images": len(imgs)}))
 """
+
+CPU_BASELINE_PER_PROCESS = 2  # images per worker: about 8-10 s of work each
 
 
 def cpu_baseline(W, H, seed):
-    """The FP64 oracle on one full image of the workload, one host thread."""
+    """The FP64 oracle as it stands on the host: P single-threaded worker
+    processes (P = the cores this process may use, at most 16), each running
+    the full path on CPU_BASELINE_PER_PROCESS images of the workload's size
+    (seeds seed, seed + 1, ...), all started together; throughput = images /
+    wall time of the slowest worker (imports and input generation outside
+    the timed part)."""
+    P = max(1, min(16, len(os.sched_getaffinity(0))))
     env = dict(os.environ)
     for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         env[v] = "1"
-    out = subprocess.run([sys.executable, "-c", CPU_BASELINE_SRC % (ROOT, W, H, seed)],
-                         capture_output=True, text=True, env=env, timeout=600)
-    if out.returncode != 0:
-        raise RuntimeError("oracle baseline failed: " + out.stderr[-2000:])
-    r = json.loads(out.stdout.strip().splitlines()[-1])
-    return {"value": 1.0 / r["seconds"], "unit": "images/s", "cores": 1, "kind": "oracle",
-            "sample": "1 image %dx%d (seed %d), full path: scale space, det, extrema; "
-                      "%.1f s" % (W, H, seed, r["seconds"])}
+    procs = []
+    for w in range(P):
+        seeds = [seed + w * CPU_BASELINE_PER_PROCESS + i for i in range(CPU_BASELINE_PER_PROCESS)]
+        procs.append(subprocess.Popen([sys.executable, "-c", CPU_BASELINE_SRC % (ROOT, W, H, seeds)],
+                                      stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True,
+                                      env=env))
+    secs = []
+    for pr in procs:
+        out, err = pr.communicate(timeout=900)
+        if pr.returncode != 0:
+            raise RuntimeError("oracle baseline failed: " + err[-2000:])
+        secs.append(json.loads(out.strip().splitlines()[-1])["seconds"])
+    n = P * CPU_BASELINE_PER_PROCESS
+    return {"value": n / max(secs), "unit": "images/s", "cores": P, "kind": "oracle",
+            "sample": "%d images %dx%d (seeds %d..%d), full path: scale space, det, extrema; "
+                      "%d single-threaded processes, %.1f s each (slowest %.1f s); one image "
+                      "on one core %.2f s" % (n, W, H, seed, seed + n - 1, P,
+                                              sum(secs) / P, max(secs),
+                                              min(secs) / CPU_BASELINE_PER_PROCESS)}
 
 
 def level_roofline(level_us, px, traffic, levels=16, det_levels=0):
