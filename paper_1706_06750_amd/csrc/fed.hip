@@ -121,9 +121,12 @@ constexpr int kFedThreads = 256;
 constexpr int kFedRows = kFedRegion / (kFedThreads / kWave);  // rows per lane
 constexpr int kFedPitch = kFedRegion + 1;
 
+// The step's multiply-adds are spelled out (contraction off), so that a
+// cycle gives the same bits whatever the number of steps per launch.
 __global__ __launch_bounds__(kFedThreads) void fed_kernel(const float* src, const float* g,
                                                           float* dst, int W, int H,
                                                           FedSteps st) {
+#pragma clang fp contract(off)
     __shared__ float sA[kFedRegion * kFedPitch];
     __shared__ float sB[kFedRegion * kFedPitch];
     const int wave = uniform(threadIdx.x >> 6), c = threadIdx.x & (kWave - 1);
@@ -186,10 +189,10 @@ __global__ __launch_bounds__(kFedThreads) void fed_kernel(const float* src, cons
             const float r = c < kFedRegion - 1 ? p[k * kFedPitch + 1] : x;
             const float d = k + 1 < kFedRows ? v[k + 1] : below;
             float f = wl[k] * (l - x);
-            f += wr[k] * (r - x);
-            f += wu[k] * (up - x);
-            f += wd[k] * (d - x);
-            nv[k] = x + h * f;
+            f = __builtin_fmaf(wr[k], r - x, f);
+            f = __builtin_fmaf(wu[k], up - x, f);
+            f = __builtin_fmaf(wd[k], d - x, f);
+            nv[k] = __builtin_fmaf(h, f, x);
             up = x;
         }
 #pragma unroll
