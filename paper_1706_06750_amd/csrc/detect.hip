@@ -8,6 +8,8 @@
 // next derivative is taken.  One block per 64x32 tile and level computes the
 // first derivatives of the tile plus an s ring in LDS, then the second
 // derivatives and det; L_x, L_y, L_xx, ... never reach memory.
+#include <type_traits>
+
 #include "kaze_internal.h"
 #include "tile_cond.h"
 
@@ -304,9 +306,13 @@ __device__ __forceinline__ float scharr3(float a0, float a1, float a2) {
     return 0.1875f * a0 + 0.625f * a1 + 0.1875f * a2;
 }
 
-template <int S>
+// DERIV: write the scale-normalised first derivatives sigma_n L_x and
+// sigma_n L_y of the tile to lx and ly instead of det (phases 1-2 only).
+template <int S, bool DERIV = false>
 __global__ __launch_bounds__(kTileThreads) void det_rows_kernel(BatchImage d0, ImgWork w,
-                                                                DetLevels dl, int lev0, int lev1) {
+                                                                DetLevels dl, int lev0, int lev1,
+                                                                float* lx = nullptr,
+                                                                float* ly = nullptr) {
     using G = RowDetGeom<S>;
     extern __shared__ float smem[];
     float* sI = smem;
@@ -415,6 +421,22 @@ __global__ __launch_bounds__(kTileThreads) void det_rows_kernel(BatchImage d0, I
         }
     }
     __syncthreads();
+    if constexpr (DERIV) {
+        // tile pixel (r, c) sits at f-row r + S, f-column c + S
+        const float sn = dl.sn[lev];
+        const int gx = tx0 + lane;
+        gfloat* ox = (gfloat*)lx + plane * lev + (ty0 + wave * G::OB) * W + tx0;
+        gfloat* oy = (gfloat*)ly + plane * lev + (ty0 + wave * G::OB) * W + tx0;
+#pragma unroll
+        for (int t = 0; t < G::OB; ++t) {
+            const int rf = wave * G::OB + t + S;
+            if (ty0 + wave * G::OB + t < H && gx < W) {
+                ox[t * W + lane] = sn * sX[rf * G::PF + lane + S];
+                oy[t * W + lane] = sn * sY[rf * G::PF + lane + S];
+            }
+        }
+        return;
+    }
     // ring positions outside the image take the derivative at their
     // reflected (in-image, already computed) position
     if (ty0 - S < 0 || tx0 - S < 0 || ty0 + G::TY + S > H || tx0 + DTX + S > W) {
@@ -497,6 +519,32 @@ hipError_t launch_det(const BatchImage& d0, const ImgWork& w, int lev0, int lev1
     if (e == hipSuccess) e = launch_det_s<S>(d0, w, lev0, lev1, dl, s);
     KZ_D(1) KZ_D(2) KZ_D(3) KZ_D(4) KZ_D(5) KZ_D(6) KZ_D(7) KZ_D(8)
 #undef KZ_D
+    return e;
+}
+
+hipError_t launch_det_derivs(const BatchImage& b, int N, const DetLevels& dl, float* lx,
+                             float* ly, hipStream_t s) {
+    for (int i = 0; i < N; ++i)
+        if (dl.step[i] > 4) return hipErrorNotSupported;  // the caller's per-pixel form
+    const int count = det_tiles_of(b.W, b.H);
+    const ImgWork none{nullptr, nullptr, 0};
+    hipError_t e = hipSuccess;
+    auto one = [&](auto tag) {
+        constexpr int S = decltype(tag)::value;
+        DetLevels dls = dl;
+        int n = 0;
+        for (int i = 0; i < N; ++i)
+            if (dl.step[i] == S) dls.list[n++] = i;
+        if (n == 0 || e != hipSuccess) return;
+        const size_t lds = (size_t)RowDetGeom<S>::floats * sizeof(float);
+        hipLaunchKernelGGL((det_rows_kernel<S, true>), dim3(count, n), dim3(kTileThreads), lds, s,
+                           b, none, dls, 0, N, lx, ly);
+        e = hipGetLastError();
+    };
+    one(std::integral_constant<int, 1>{});
+    one(std::integral_constant<int, 2>{});
+    one(std::integral_constant<int, 3>{});
+    one(std::integral_constant<int, 4>{});
     return e;
 }
 

@@ -214,6 +214,7 @@ DetLevels det_levels(const std::vector<Level>& lv) {
     for (size_t i = 0; i < lv.size(); ++i) {
         dl.step[i] = lv[i].step;
         dl.sn2[i] = (float)(lv[i].sigma_n * lv[i].sigma_n);
+        dl.sn[i] = (float)lv[i].sigma_n;
     }
     return dl;
 }
@@ -1103,7 +1104,19 @@ kaze_status kaze_derivatives(const float* levels, int W, int H, const kaze_param
     if (!aligned(levels, 4) || !aligned(lx, 4) || !aligned(ly, 4))
         return fail(KAZE_ERR_INVALID_ARG, "float buffers must be 4-byte aligned");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    KZ_LAUNCH(K_DERIV, s, launch_deriv(levels, W, H, kaze_num_levels(p), desc_levels(p), lx, ly, s));
+    std::vector<Level> lv;
+    schedule(p, lv);
+    const DetLevels dl = det_levels(lv);
+    const int N = (int)lv.size();
+    bool rows = true;
+    for (int i = 0; i < N; ++i) rows = rows && lv[i].step <= 4;
+    if (rows) {
+        BatchImage b = batch_image(W, H);
+        b.levels = const_cast<float*>(levels);  // read only
+        KZ_LAUNCH(K_DERIV, s, launch_det_derivs(b, N, dl, lx, ly, s));
+    } else {
+        KZ_LAUNCH(K_DERIV, s, launch_deriv(levels, W, H, N, desc_levels(p), lx, ly, s));
+    }
     return KAZE_OK;
 }
 

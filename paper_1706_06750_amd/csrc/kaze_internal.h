@@ -29,6 +29,7 @@ struct Taps {
 struct DetLevels {
     int step[kMaxLevels];    // Scharr step round(sigma_n)
     float sn2[kMaxLevels];   // sigma_n^2
+    float sn[kMaxLevels];    // sigma_n
     int list[kMaxLevels];    // per launch: the levels it covers, in order
 };
 
@@ -374,6 +375,10 @@ hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t s);
 // orientation + M-SURF descriptor of min(*count, capacity) refined keypoints.
 hipError_t launch_deriv(const float* levels, int W, int H, int N, const DescLevels& dl, float* lx,
                         float* ly, hipStream_t s);
+// The same derivatives by the detector's row-rolling kernel (levels with a
+// Scharr step of at most 4; hipErrorNotSupported otherwise).
+hipError_t launch_det_derivs(const BatchImage& b, int N, const DetLevels& dl, float* lx,
+                             float* ly, hipStream_t s);
 hipError_t launch_describe(const float* lx, const float* ly, int W, int H, int N,
                            const DescLevels& dl, const void* kps, const int* count, int capacity,
                            float* angles, float* desc, hipStream_t s);
