@@ -445,6 +445,7 @@ __device__ __forceinline__ void seg_pcr_pairs(Eq e0, Eq e1, int lane, int pos, i
 // own rows, kept in registers.  All loads of a lane are issued at once.
 constexpr int kIfaceThreads = 256;
 
+template <int kIfaceM>
 __global__ __launch_bounds__(kIfaceThreads) void aos_iface_kernel(ImageDesc d0, AosWork w,
                                                                    int count) {
     constexpr int NR = 2 * kIfaceM;  // rows per lane
@@ -455,11 +456,11 @@ __global__ __launch_bounds__(kIfaceThreads) void aos_iface_kernel(ImageDesc d0, 
     int grp;
     resolve(d0, w, t, d, grp);
     if (d.gate && *d.gate <= d.bound) return;  // whole wavefront
-    const int rgroups = iface_groups(d.H, d.nchr);
+    const int rgroups = iface_groups(d.H, d.nchr, kIfaceM);
     const bool row = grp < rgroups;
     const int nch = row ? d.nchr : d.nchc;
     const int nl = row ? d.H : d.W;
-    const int P = iface_lanes(nch);
+    const int P = iface_lanes(nch, kIfaceM);
     const int pos = lane & (P - 1);
     const int line = (row ? grp : grp - rgroups) * (kWave / P) + lane / P;
     const bool live = line < nl;
@@ -687,15 +688,15 @@ __global__ __launch_bounds__(kBlock) void probe_err_kernel(const float* L, const
     if (threadIdx.x == 0) atomicMax(err, __float_as_uint(red[0]));
 }
 
-int work_count(const ImageDesc& d0, const AosWork& w, int ty, bool lines) {
+int work_count(const ImageDesc& d0, const AosWork& w, int ty, int lines_m) {
     if (w.items) return w.count;
-    return lines ? aos_line_groups(d0.W, d0.H) : aos_tiles_of(d0.W, d0.H, ty);
+    return lines_m ? aos_line_groups(d0.W, d0.H, lines_m) : aos_tiles_of(d0.W, d0.H, ty);
 }
 
 template <int RG, int TY, bool CG, int GM>
 hipError_t launch_reduce_t(const ImageDesc& d0, const AosWork& w, const Taps& tc, float tau,
                            float k_host, hipStream_t s) {
-    const int count = work_count(d0, w, TY, false);
+    const int count = work_count(d0, w, TY, 0);
     if (count <= 0) return hipSuccess;
     const size_t lds = (size_t)RedGeom<RG, TY, CG>::floats * sizeof(float);
     hipLaunchKernelGGL((aos_reduce_kernel<RG, TY, CG, GM>), dim3(count), dim3(kRedThreads), lds, s,
@@ -726,7 +727,7 @@ hipError_t launch_reduce_s(const ImageDesc& d0, const AosWork& w, const Taps& tc
 
 template <int TY>
 hipError_t launch_recover_t(const ImageDesc& d0, const AosWork& w, float tau, hipStream_t s) {
-    const int count = work_count(d0, w, TY, false);
+    const int count = work_count(d0, w, TY, 0);
     if (count <= 0) return hipSuccess;
     const size_t lds = (size_t)2 * TY * (kAosTX + 1) * sizeof(float);
     hipLaunchKernelGGL((aos_recover_kernel<TY>), dim3(count), dim3(TY * 4), lds, s, d0, w, tau);
@@ -744,12 +745,18 @@ hipError_t launch_aos_reduce(const ImageDesc& d0, const AosWork& w, int shape, c
     }
 }
 
-hipError_t launch_aos_iface(const ImageDesc& d0, const AosWork& w, hipStream_t s) {
-    const int count = work_count(d0, w, 0, true);
+hipError_t launch_aos_iface(const ImageDesc& d0, const AosWork& w, int M, hipStream_t s) {
+    const int count = work_count(d0, w, 0, M);
     if (count <= 0) return hipSuccess;
     const int waves = kIfaceThreads / kWave;
-    hipLaunchKernelGGL(aos_iface_kernel, dim3((count + waves - 1) / waves), dim3(kIfaceThreads), 0,
-                       s, d0, w, count);
+    if (M == kIfaceMSmall)
+        hipLaunchKernelGGL(aos_iface_kernel<kIfaceMSmall>, dim3((count + waves - 1) / waves),
+                           dim3(kIfaceThreads), 0, s, d0, w, count);
+    else if (M == kIfaceMLarge)
+        hipLaunchKernelGGL(aos_iface_kernel<kIfaceMLarge>, dim3((count + waves - 1) / waves),
+                           dim3(kIfaceThreads), 0, s, d0, w, count);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -295,12 +295,15 @@ BatchImage batch_image(int W, int H) {
 }
 
 // a3-a5: (conductivity +) chunk reduction, interface solves, recovery.
+// iface_m: chunks per lane of the interface solve the line work list was
+// built for; 0 (no work list, one image) chooses it from the image size.
 kaze_status aos_step(const ImageDesc& d, const AosWork& tiles, const AosWork& lines, int shape,
                      const Taps& tc, float tau, bool compute_g, int gmode, float k_host,
-                     hipStream_t s) {
+                     hipStream_t s, int iface_m = 0) {
+    const int M = iface_m ? iface_m : iface_m_for(aos_line_groups(d.W, d.H, kIfaceMLarge));
     KZ_LAUNCH(K_AOS_REDUCE, s,
               launch_aos_reduce(d, tiles, shape, tc, tau, compute_g, gmode, k_host, s));
-    KZ_LAUNCH(K_AOS_IFACE, s, launch_aos_iface(d, lines, s));
+    KZ_LAUNCH(K_AOS_IFACE, s, launch_aos_iface(d, lines, M, s));
     KZ_LAUNCH(K_AOS_RECOVER, s, launch_aos_recover(d, tiles, shape, tau, s));
     return KAZE_OK;
 }
@@ -372,6 +375,7 @@ struct kaze_batch {
     std::vector<hipEvent_t> ev;      // fork / join points (N + 1)
     bool fork_det = false;           // detector response beside the steps, per level
     int split_det = -1;              // else: levels 0..split_det forked once
+    int iface_m = kIfaceMLarge;      // chunks per lane of the interface solves
 };
 
 // A captured fork spreads a graph over several hardware queues, and every
@@ -393,16 +397,20 @@ struct BatchLayout {
     std::vector<size_t> scratch;  // per image
     size_t total;
     int n_tiles, n_aos, n_lines, n_hist, n_det, n_nms;
+    int iface_m;  // chunks per lane of the interface solves
 };
 
 BatchLayout batch_layout(const kaze_image_desc* im, int n, const kaze_params* p, int shape) {
     BatchLayout L;
     const int N = p->octaves * p->sublevels;
     L.n_tiles = L.n_aos = L.n_lines = L.n_hist = L.n_det = L.n_nms = 0;
+    long long groups_large = 0;
+    for (int j = 0; j < n; ++j) groups_large += aos_line_groups(im[j].W, im[j].H, kIfaceMLarge);
+    L.iface_m = iface_m_for(groups_large);
     for (int j = 0; j < n; ++j) {
         L.n_tiles += tiles_of(im[j].W, im[j].H);
         L.n_aos += aos_tiles_of(im[j].W, im[j].H, kAosShapeTY[shape]);
-        L.n_lines += aos_line_groups(im[j].W, im[j].H);
+        L.n_lines += aos_line_groups(im[j].W, im[j].H, L.iface_m);
         L.n_hist += (im[j].W * im[j].H + kHistChunk - 1) / kHistChunk;
         L.n_det += det_tiles_of(im[j].W, im[j].H);
         L.n_nms += nms_blocks_of(im[j].W, im[j].H);
@@ -507,7 +515,7 @@ kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStre
                 const AosWork at{lvl, B.d_aos, B.n_aos};
                 const AosWork al{lvl, B.d_lines, B.n_lines};
                 st = aos_step(a0, at, al, B.shape, tc, (float)(B.lv[i].tau / m), true, gmode, 1.f,
-                              s);
+                              s, B.iface_m);
                 if (st != KAZE_OK) return st;
             }
             if ((st = det_level(i)) != KAZE_OK) return st;
@@ -583,6 +591,7 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
     B->d_det = reinterpret_cast<int2*>(base + L.det);
     B->d_nms = reinterpret_cast<int2*>(base + L.nms);
     B->n_tiles = L.n_tiles;
+    B->iface_m = L.iface_m;
     B->n_aos = L.n_aos;
     B->n_lines = L.n_lines;
     B->n_hist = L.n_hist;
@@ -635,7 +644,7 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
         for (int t = 0; t < tiles_of(d.W, d.H); ++t) ht[it++] = make_int2(j, t);
         for (int t = 0; t < aos_tiles_of(d.W, d.H, kAosShapeTY[shape]); ++t)
             ha[ia++] = make_int2(j, t);
-        for (int t = 0; t < aos_line_groups(d.W, d.H); ++t) hl[il++] = make_int2(j, t);
+        for (int t = 0; t < aos_line_groups(d.W, d.H, L.iface_m); ++t) hl[il++] = make_int2(j, t);
         for (int t = 0; t < (d.W * d.H + kHistChunk - 1) / kHistChunk; ++t) hh[ih++] = make_int2(j, t);
         for (int t = 0; t < det_tiles_of(d.W, d.H); ++t) hd[idt++] = make_int2(j, t);
         for (int t = 0; t < nms_blocks_of(d.W, d.H); ++t) hn[inm++] = make_int2(j, t);

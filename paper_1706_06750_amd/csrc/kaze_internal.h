@@ -192,22 +192,30 @@ __host__ __device__ inline int aos_col_chunks(int H) { return (H + kColChunk - 1
 inline int aos_tiles_of(int W, int H, int ty) {
     return ((W + kAosTX - 1) / kAosTX) * ((H + ty - 1) / ty);
 }
-// Interface solve: every lane holds kIfaceM consecutive chunks of a line and
-// a line spans iface_lanes(chunks) lanes (a power of two), so a wavefront
+// Interface solve: every lane holds M consecutive chunks of a line and a
+// line spans iface_lanes(chunks, M) lanes (a power of two), so a wavefront
 // serves 64 / iface_lanes lines of one direction of one image.  Work items:
 // the row-line groups of the image, then its column-line groups.
-constexpr int kIfaceM = 8;
-__host__ __device__ inline int iface_lanes(int nch) {
+// Chunks per lane M: 8, or 4 for launches with few wavefronts, where the
+// shorter lane-local elimination and the doubled number of wavefronts win
+// (measured at 1920x1200: 9.5 -> 8.4 us per level, 1659 -> 1716 images/s;
+// on the 64-image batch 8 stays ahead, 597 against 607 us per level).
+constexpr int kIfaceMSmall = 4, kIfaceMLarge = 8;
+constexpr int kIfaceSmallGroups = 1024;  // wavefronts at M = 8 below which M = 4
+__host__ __device__ inline int iface_lanes(int nch, int M) {
     int p = 1;
-    while (p * kIfaceM < nch) p <<= 1;
+    while (p * M < nch) p <<= 1;
     return p;
 }
-__host__ __device__ inline int iface_groups(int lines, int nch) {
-    const int per = 64 / iface_lanes(nch);
+__host__ __device__ inline int iface_groups(int lines, int nch, int M) {
+    const int per = 64 / iface_lanes(nch, M);
     return (lines + per - 1) / per;
 }
-inline int aos_line_groups(int W, int H) {
-    return iface_groups(H, aos_row_chunks(W)) + iface_groups(W, aos_col_chunks(H));
+inline int aos_line_groups(int W, int H, int M) {
+    return iface_groups(H, aos_row_chunks(W), M) + iface_groups(W, aos_col_chunks(H), M);
+}
+inline int iface_m_for(long long groups_at_large) {
+    return groups_at_large < kIfaceSmallGroups ? kIfaceMSmall : kIfaceMLarge;
 }
 
 // One image of an AOS step.  Interface equations and solutions are stored
@@ -337,7 +345,7 @@ hipError_t launch_reset(const BatchImage& d0, const ImgWork& w, int nbins, float
 // L_next = L + (delta_x + delta_y)/2 (items: image, tile).
 hipError_t launch_aos_reduce(const ImageDesc& d0, const AosWork& w, int shape, const Taps& tc,
                              float tau, bool compute_g, int gmode, float k_host, hipStream_t s);
-hipError_t launch_aos_iface(const ImageDesc& d0, const AosWork& w, hipStream_t s);
+hipError_t launch_aos_iface(const ImageDesc& d0, const AosWork& w, int M, hipStream_t s);
 hipError_t launch_aos_recover(const ImageDesc& d0, const AosWork& w, int shape, float tau,
                               hipStream_t s);
 
