@@ -8,6 +8,7 @@
 // next derivative is taken.  One block per 64x32 tile and level computes the
 // first derivatives of the tile plus an s ring in LDS, then the second
 // derivatives and det; L_x, L_y, L_xx, ... never reach memory.
+#include <algorithm>
 #include <type_traits>
 
 #include "kaze_internal.h"
@@ -32,6 +33,23 @@ struct DetGeom {
     static constexpr int offY = offX + nfy * pF;
     static constexpr int floats = offY + nfy * pF;
 };
+
+// det at (ly, lx) of the tile from the first-derivative planes of det_kernel
+template <int S, int pF>
+__device__ __forceinline__ float det_at(const float* sX, const float* sY, int ly, int lx,
+                                        float inv2s, float sn2) {
+    const float* x = sX + (ly + S) * pF + (lx + S);
+    const float* y = sY + (ly + S) * pF + (lx + S);
+    const float x00 = x[-S * pF - S], x02 = x[-S * pF + S];
+    const float x20 = x[S * pF - S], x22 = x[S * pF + S];
+    const float Lxx = (0.1875f * (x02 - x00) + 0.625f * (x[S] - x[-S]) + 0.1875f * (x22 - x20)) * inv2s;
+    const float Lxy = (0.1875f * (x20 - x00) + 0.625f * (x[S * pF] - x[-S * pF]) +
+                       0.1875f * (x22 - x02)) * inv2s;
+    const float Lyy = (0.1875f * (y[S * pF - S] - y[-S * pF - S]) +
+                       0.625f * (y[S * pF] - y[-S * pF]) +
+                       0.1875f * (y[S * pF + S] - y[-S * pF + S])) * inv2s;
+    return sn2 * (Lxx * Lyy - Lxy * Lxy);
+}
 
 template <int S>
 __global__ __launch_bounds__(kDetThreads) void det_kernel(BatchImage d0, ImgWork w, DetLevels dl,
@@ -95,25 +113,25 @@ __global__ __launch_bounds__(kDetThreads) void det_kernel(BatchImage d0, ImgWork
     }
     __syncthreads();
 
+    // a wavefront holds one row of the tile (lane = column): its ballot is
+    // the row's mask word
+    gu64* mrow = d.mask ? (gu64*)d.mask + (size_t)lev * H * mask_words(W) + tx0 / DTX : nullptr;
 #pragma unroll
     for (int j = 0; j < DTX * DTY / kDetThreads; ++j) {
         const int i = threadIdx.x + j * kDetThreads;
         const int ly = i / DTX, lx = i - ly * DTX;
         const int gy = ty0 + ly, gx = tx0 + lx;
-        if (gy >= H || gx >= W) continue;
-        const float* x = sX + (ly + S) * G::pF + (lx + S);
-        const float* y = sY + (ly + S) * G::pF + (lx + S);
-        const float x00 = x[-S * G::pF - S], x02 = x[-S * G::pF + S];
-        const float x20 = x[S * G::pF - S], x22 = x[S * G::pF + S];
-        const float Lxx = (0.1875f * (x02 - x00) + 0.625f * (x[S] - x[-S]) + 0.1875f * (x22 - x20)) * inv2s;
-        const float Lxy = (0.1875f * (x20 - x00) + 0.625f * (x[S * G::pF] - x[-S * G::pF]) +
-                           0.1875f * (x22 - x02)) * inv2s;
-        const float Lyy = (0.1875f * (y[S * G::pF - S] - y[-S * G::pF - S]) +
-                           0.625f * (y[S * G::pF] - y[-S * G::pF]) +
-                           0.1875f * (y[S * G::pF + S] - y[-S * G::pF + S])) * inv2s;
-        det[plane * lev + (size_t)gy * W + gx] = sn2 * (Lxx * Lyy - Lxy * Lxy);
+        const bool in = gy < H && gx < W;
+        float v = 0.f;
+        if (in) v = det_at<S, G::pF>(sX, sY, ly, lx, inv2s, sn2);
+        if (in) det[plane * lev + (size_t)gy * W + gx] = v;
+        if (mrow) {
+            const unsigned long long bits = __ballot(in && v > dl.thr);
+            if (lx == 0 && gy < H) mrow[(size_t)gy * mask_words(W)] = bits;
+        }
     }
 }
+
 
 struct KeypointOut {
     int x, y, level;
@@ -229,6 +247,135 @@ __global__ __launch_bounds__(256) void nms_kernel(BatchImage d0, ImgWork w, floa
     }
 }
 
+// The same test with detector masks.  A block takes 256 consecutive 64-bit
+// mask words of a level (row segments of 64 pixels, row-major), and only
+// the positions whose bit is set (det above the threshold, typically well
+// under 1% of them) are read and tested; the rest of the level is never
+// loaded.  Set bits come in clusters (blobs of strong response), so they
+// are dealt out evenly: a block scan of the words' bit counts numbers the
+// block's set bits, and in each round thread t takes bit number
+// round * 256 + t.
+template <bool WIDE>
+__global__ __launch_bounds__(256) void nms_mask_kernel(BatchImage d0, ImgWork w, float threshold,
+                                                       NmsRadii radii) {
+    __shared__ unsigned long long s_bits[256];
+    __shared__ int s_inc[256];  // inclusive prefix sums of the bit counts
+    BatchImage d;
+    int bx, by, lb;
+    xcd_grid(bx, by);
+    if (w.items) {
+        const int2 it = w.items[bx];
+        d = w.descs[it.x];
+        lb = it.y;
+    } else {
+        d = d0;
+        lb = bx;
+    }
+    const int W = d.W, H = d.H, mw = mask_words(W);
+    const int lev = by + 1;
+    const int h = radii.h[lev];
+    const size_t plane = (size_t)W * H;
+    const gfloat* base = (const gfloat*)d.det + plane * lev;
+    KeypointOut* kps = static_cast<KeypointOut*>(d.kps);
+    const int t = threadIdx.x;
+    {
+        const int g = lb * 256 + t;  // word of the level's mask plane
+        const int y = g / mw, xw = g - y * mw;
+        unsigned long long bits = 0ull;
+        if (y >= 1 && y <= H - 2)  // rows past H fall out here too
+            bits = ((const gu64*)d.mask)[(size_t)lev * H * mw + g];
+        // columns 1 .. W-2 of the word: bits max(0, 1 - 64 xw) .. W - 2 - 64 xw
+        if (xw == 0) bits &= ~1ull;
+        const int hi = W - 2 - 64 * xw;
+        if (hi < 63) bits &= hi >= 0 ? (2ull << hi) - 1ull : 0ull;
+        s_bits[t] = bits;
+        s_inc[t] = __popcll(bits);
+    }
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {  // inclusive Hillis-Steele scan
+        const int v = t >= off ? s_inc[t - off] : 0;
+        __syncthreads();
+        s_inc[t] += v;
+        __syncthreads();
+    }
+    const int total = s_inc[255];
+    const int lane = t & (kWave - 1);
+    for (int r = 0; r < total; r += 256) {  // uniform over the block
+        const int q = r + t;
+        bool cand = false;
+        int x = 0, y = 0;
+        float v = 0.f;
+        if (q < total) {
+            // word o holding bit number q: the first with s_inc[o] > q
+            int lo = 0, hi = 255;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s_inc[mid] > q) hi = mid;
+                else lo = mid + 1;
+            }
+            unsigned long long bits = s_bits[lo];
+            for (int k = q - (s_inc[lo] - __popcll(bits)); k > 0; --k) bits &= bits - 1ull;
+            const int g = lb * 256 + lo;
+            y = g / mw;
+            x = 64 * (g - y * mw) + __ffsll((long long)bits) - 1;
+            const gfloat* c = base + (size_t)y * W + x;
+            v = c[0];
+            cand = v > threshold;
+            // own level first (all eight loads issued together), then, for
+            // the 3x3x3 test, levels lev-1 and lev+1
+            float nb[8];
+#pragma unroll
+            for (int j = 0, dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx)
+                    if (dy != 0 || dx != 0) nb[j++] = c[dy * W + dx];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) cand = cand && v > nb[j];
+            if (cand && (!WIDE || h == 1)) {
+                float up[9], dn[9];
+#pragma unroll
+                for (int j = 0, dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                    for (int dx = -1; dx <= 1; ++dx, ++j) {
+                        up[j] = c[(ptrdiff_t)plane + dy * W + dx];
+                        dn[j] = c[-(ptrdiff_t)plane + dy * W + dx];
+                    }
+                bool is_max = true;
+#pragma unroll
+                for (int j = 0; j < 9; ++j) is_max = is_max && v > up[j] && v > dn[j];
+                if (is_max) push_keypoint(d.count, d.capacity, kps, x, y, lev, v);
+            }
+        }
+        if constexpr (WIDE) {
+            if (h == 1) continue;  // uniform: the level's window is 3x3
+            // wider cross-level window: the wavefront checks its candidates
+            // one at a time with all 64 lanes over the window of levels
+            // lev-1 and lev+1 (clipped to the image)
+            unsigned long long m = __ballot(cand);
+            while (m) {
+                const int l = __ffsll((long long)m) - 1;
+                m &= m - 1;
+                const int cx = __builtin_amdgcn_readlane(x, l);
+                const int cy = __builtin_amdgcn_readlane(y, l);
+                const float cv = __builtin_bit_cast(
+                    float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+                const int wy0 = max(cy - h, 0), wy1 = min(cy + h, H - 1);
+                const int wx0 = max(cx - h, 0), wx1 = min(cx + h, W - 1);
+                const int ww = wx1 - wx0 + 1, n = ww * (wy1 - wy0 + 1);
+                bool ok = true;
+                for (int u2 = lane; u2 < 2 * n; u2 += kWave) {
+                    const int u = u2 < n ? u2 : u2 - n;
+                    const ptrdiff_t off = u2 < n ? -(ptrdiff_t)plane : (ptrdiff_t)plane;
+                    const int yy = wy0 + u / ww, xx = wx0 + u % ww;
+                    ok = ok && (cv > base[off + (ptrdiff_t)yy * W + xx]);
+                }
+                if (__ballot(!ok) == 0 && lane == l)
+                    push_keypoint(d.count, d.capacity, kps, x, y, lev, v);
+            }
+        }
+    }
+}
+
 // Keypoint refinement (Sec. II-B, Eqs. 9-12): one thread per extremum.  The
 // least-squares quadratic on the 3x3 window has orthogonal regressors, so
 // each coefficient is a projection of the nine samples.
@@ -311,21 +458,15 @@ __device__ __forceinline__ float scharr3(float a0, float a1, float a2) {
 
 // DERIV: write the scale-normalised first derivatives sigma_n L_x and
 // sigma_n L_y of the tile to lx and ly instead of det (phases 1-2 only).
-template <int S, bool DERIV = false>
-__global__ __launch_bounds__(kDetThreads) void det_rows_kernel(BatchImage d0, ImgWork w,
-                                                                DetLevels dl, int lev0, int lev1,
-                                                                float* lx = nullptr,
-                                                                float* ly = nullptr) {
+// One block: tile bx (of the work list) of level lev, Scharr step S.
+template <int S, bool DERIV>
+__device__ __forceinline__ void det_rows_tile(float* smem, const BatchImage& d0, const ImgWork& w,
+                                              const DetLevels& dl, int lev, int bx, float* lx,
+                                              float* ly) {
     using G = RowDetGeom<S>;
-    extern __shared__ float smem[];
     float* sI = smem;
     float* sX = smem + G::offX;
     float* sY = smem + G::offY;
-    int bx, by;
-    xcd_grid(bx, by);
-    const int lev = dl.list[by];  // the launch's levels with Scharr step S
-    (void)lev0;
-    (void)lev1;
     BatchImage d;
     int lt;
     resolve(d0, w, bx, d, lt);
@@ -474,6 +615,8 @@ __global__ __launch_bounds__(kDetThreads) void det_rows_kernel(BatchImage d0, Im
         }
         const int gx = tx0 + lane;
         gfloat* out = (gfloat*)(d.det + plane * lev) + (ty0 + o0) * W + tx0;
+        gu64* mrow =
+            d.mask ? (gu64*)d.mask + ((size_t)lev * H + ty0 + o0) * mask_words(W) + tx0 / DTX : nullptr;
 #pragma unroll
         for (int t = 0; t < G::OB; ++t) {
             const float Lxx =
@@ -482,9 +625,41 @@ __global__ __launch_bounds__(kDetThreads) void det_rows_kernel(BatchImage d0, Im
                 scharr3(xL[t + 2 * S] - xL[t], xC[t + 2 * S] - xC[t], xR[t + 2 * S] - xR[t]) * inv2s;
             const float Lyy =
                 scharr3(yL[t + 2 * S] - yL[t], yC[t + 2 * S] - yC[t], yR[t + 2 * S] - yR[t]) * inv2s;
-            if (ty0 + o0 + t < H && gx < W) out[t * W + lane] = sn2 * (Lxx * Lyy - Lxy * Lxy);
+            const float v = sn2 * (Lxx * Lyy - Lxy * Lxy);
+            const bool row_in = ty0 + o0 + t < H;
+            if (row_in && gx < W) out[t * W + lane] = v;
+            if (mrow) {  // the wavefront's ballot is the row's mask word
+                const unsigned long long bits = __ballot(row_in && gx < W && v > dl.thr);
+                if (lane == 0 && row_in) mrow[(size_t)t * mask_words(W)] = bits;
+            }
         }
     }
+}
+
+template <int S, bool DERIV = false>
+__global__ __launch_bounds__(kDetThreads) void det_rows_kernel(BatchImage d0, ImgWork w,
+                                                                DetLevels dl, float* lx = nullptr,
+                                                                float* ly = nullptr) {
+    extern __shared__ float smem[];
+    int bx, by;
+    xcd_grid(bx, by);
+    // the launch's levels (all of Scharr step S) are dl.list[0..gridDim.y)
+    det_rows_tile<S, DERIV>(smem, d0, w, dl, dl.list[by], bx, lx, ly);
+}
+
+// Levels of two Scharr steps in one launch (one ramp and one tail instead of
+// two): each block takes the step of its level.
+template <int SA, int SB>
+__global__ __launch_bounds__(kDetThreads) void det_rows_pair_kernel(BatchImage d0, ImgWork w,
+                                                                     DetLevels dl) {
+    extern __shared__ float smem[];
+    int bx, by;
+    xcd_grid(bx, by);
+    const int lev = dl.list[by];
+    if (dl.step[lev] == SA)
+        det_rows_tile<SA, false>(smem, d0, w, dl, lev, bx, nullptr, nullptr);
+    else
+        det_rows_tile<SB, false>(smem, d0, w, dl, lev, bx, nullptr, nullptr);
 }
 
 template <int S>
@@ -500,7 +675,7 @@ hipError_t launch_det_s(const BatchImage& d0, const ImgWork& w, int lev0, int le
         static_assert(kDetRowsTY == DTY, "both forms tile alike");
         const size_t lds = (size_t)RowDetGeom<S>::floats * sizeof(float);
         hipLaunchKernelGGL(det_rows_kernel<S>, dim3(count, n), dim3(kDetThreads), lds, s, d0, w,
-                           dls, lev0, lev1);
+                           dls, nullptr, nullptr);
     } else {
         const size_t lds = (size_t)DetGeom<S>::floats * sizeof(float);
         hipLaunchKernelGGL(det_kernel<S>, dim3(count, n), dim3(kDetThreads), lds, s, d0, w, dl,
@@ -509,14 +684,44 @@ hipError_t launch_det_s(const BatchImage& d0, const ImgWork& w, int lev0, int le
     return hipGetLastError();
 }
 
+// Levels of steps SA and SB (and no other) in [lev0, lev1): one launch.
+template <int SA, int SB>
+hipError_t launch_det_pair(const BatchImage& d0, const ImgWork& w, int lev0, int lev1,
+                           const DetLevels& dl, hipStream_t s) {
+    DetLevels dls = dl;
+    int n = 0;
+    for (int i = lev0; i < lev1; ++i) dls.list[n++] = i;
+    const int count = w.items ? w.count : det_tiles_of(d0.W, d0.H);
+    if (n == 0 || count <= 0) return hipSuccess;
+    const size_t lds =
+        (size_t)std::max(RowDetGeom<SA>::floats, RowDetGeom<SB>::floats) * sizeof(float);
+    hipLaunchKernelGGL((det_rows_pair_kernel<SA, SB>), dim3(count, n), dim3(kDetThreads), lds, s,
+                       d0, w, dls);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 int det_tiles_of(int W, int H) { return ((W + DTX - 1) / DTX) * ((H + DTY - 1) / DTY); }
 
-int nms_blocks_of(int W, int H) { return ((W + 63) / 64) * ((H + 4 * kNmsRows - 1) / (4 * kNmsRows)); }
+int nms_blocks_of(int W, int H, bool masked) {
+    if (masked) return (int)(((long long)H * mask_words(W) + 255) / 256);
+    return ((W + 63) / 64) * ((H + 4 * kNmsRows - 1) / (4 * kNmsRows));
+}
 
 hipError_t launch_det(const BatchImage& d0, const ImgWork& w, int lev0, int lev1,
                       const DetLevels& dl, hipStream_t s) {
+    // two adjacent steps (the default schedule: 2 and 3) share one launch
+    int smin = 1 << 30, smax = 0;
+    for (int i = lev0; i < lev1; ++i) {
+        smin = std::min(smin, dl.step[i]);
+        smax = std::max(smax, dl.step[i]);
+    }
+    if (smax == smin + 1 && smax <= 4) {
+        if (smin == 1) return launch_det_pair<1, 2>(d0, w, lev0, lev1, dl, s);
+        if (smin == 2) return launch_det_pair<2, 3>(d0, w, lev0, lev1, dl, s);
+        return launch_det_pair<3, 4>(d0, w, lev0, lev1, dl, s);
+    }
     hipError_t e = hipSuccess;
 #define KZ_D(S) \
     if (e == hipSuccess) e = launch_det_s<S>(d0, w, lev0, lev1, dl, s);
@@ -541,7 +746,7 @@ hipError_t launch_det_derivs(const BatchImage& b, int N, const DetLevels& dl, fl
         if (n == 0 || e != hipSuccess) return;
         const size_t lds = (size_t)RowDetGeom<S>::floats * sizeof(float);
         hipLaunchKernelGGL((det_rows_kernel<S, true>), dim3(count, n), dim3(kDetThreads), lds, s,
-                           b, none, dls, 0, N, lx, ly);
+                           b, none, dls, lx, ly);
         e = hipGetLastError();
     };
     one(std::integral_constant<int, 1>{});
@@ -561,12 +766,18 @@ hipError_t launch_refine(const float* det, int W, int H, int N, const void* kps,
 }
 
 hipError_t launch_nms(const BatchImage& d0, const ImgWork& w, int N, float threshold,
-                      const NmsRadii& radii, hipStream_t s) {
-    const int count = w.items ? w.count : nms_blocks_of(d0.W, d0.H);
+                      const NmsRadii& radii, hipStream_t s, bool masked) {
+    const int count = w.items ? w.count : nms_blocks_of(d0.W, d0.H, masked);
     if (N < 3 || count <= 0) return hipSuccess;
     bool wide = false;
     for (int i = 0; i < N && i < kMaxLevels; ++i) wide = wide || radii.h[i] > 1;
-    if (wide)
+    if (masked && wide)
+        hipLaunchKernelGGL(nms_mask_kernel<true>, dim3(count, N - 2), dim3(256), 0, s, d0, w,
+                           threshold, radii);
+    else if (masked)
+        hipLaunchKernelGGL(nms_mask_kernel<false>, dim3(count, N - 2), dim3(256), 0, s, d0, w,
+                           threshold, radii);
+    else if (wide)
         hipLaunchKernelGGL(nms_kernel<true>, dim3(count, N - 2), dim3(256), 0, s, d0, w, threshold,
                            radii);
     else

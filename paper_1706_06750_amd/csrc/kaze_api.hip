@@ -240,13 +240,14 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // Per-image scratch: conductivity plane, interface equations and solutions
 // of the AOS tile shape, histogram and hmax.
 struct Scratch {
-    size_t g, rrow, rcol, zrow, zcol, hist, hmax, tmp, sub, total;
+    size_t g, rrow, rcol, zrow, zcol, hist, hmax, tmp, sub, mask, total;
 };
 
 // fed: room for the second plane of the explicit steps (FED scheme only);
-// sub: the plane between the sub-steps of a level (more than one sub-step).
+// sub: the plane between the sub-steps of a level (more than one sub-step);
+// mask_levels: detector masks of that many levels (BatchImage::mask).
 Scratch scratch_layout(int W, int H, int nbins, int shape, size_t base, bool fed = false,
-                       bool sub = false) {
+                       bool sub = false, int mask_levels = 0) {
     Scratch w;
     (void)shape;
     const size_t ncx = aos_row_chunks(W), ncy = aos_col_chunks(H);
@@ -256,10 +257,13 @@ Scratch scratch_layout(int W, int H, int nbins, int shape, size_t base, bool fed
     w.rcol = off; off = align256(off + (size_t)W * ncy * 8 * sizeof(float));
     w.zrow = off; off = align256(off + (size_t)H * ncx * 2 * sizeof(float));
     w.zcol = off; off = align256(off + (size_t)W * ncy * 2 * sizeof(float));
-    w.hist = off; off = align256(off + (size_t)(nbins > 0 ? nbins : 1) * sizeof(unsigned));
-    w.hmax = off; off = align256(off + sizeof(unsigned));
+    w.hist = off;
+    off = align256(off + (size_t)(nbins > 0 ? nbins : 1) * kHistCopies * sizeof(unsigned));
+    w.hmax = off; off = align256(off + kHistCopies * sizeof(unsigned));
     w.tmp = off;  off = align256(off + (fed ? (size_t)W * H * sizeof(float) : 0));
     w.sub = off;  off = align256(off + (sub ? (size_t)W * H * sizeof(float) : 0));
+    w.mask = off;
+    off = align256(off + (size_t)mask_levels * H * mask_words(W) * sizeof(unsigned long long));
     w.total = off - base;
     return w;
 }
@@ -413,7 +417,7 @@ BatchLayout batch_layout(const kaze_image_desc* im, int n, const kaze_params* p,
         L.n_lines += aos_line_groups(im[j].W, im[j].H, L.iface_m);
         L.n_hist += (im[j].W * im[j].H + kHistChunk - 1) / kHistChunk;
         L.n_det += det_tiles_of(im[j].W, im[j].H);
-        L.n_nms += nms_blocks_of(im[j].W, im[j].H);
+        L.n_nms += nms_blocks_of(im[j].W, im[j].H, true);
     }
     size_t off = 0;
     L.imgs = off;  off = align256(off + n * sizeof(BatchImage));
@@ -430,7 +434,10 @@ BatchLayout batch_layout(const kaze_image_desc* im, int n, const kaze_params* p,
     L.scratch.resize(n);
     for (int j = 0; j < n; ++j) {
         L.scratch[j] = off;
-        off += scratch_layout(im[j].W, im[j].H, hist_bins(p), shape, 0, false, p->substeps > 1).total;
+        // detector masks when the batch finds extrema
+        off += scratch_layout(im[j].W, im[j].H, hist_bins(p), shape, 0, false, p->substeps > 1,
+                              im[0].count ? N : 0)
+                   .total;
     }
     L.total = off;
     return L;
@@ -485,7 +492,8 @@ kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStre
         return base_and_k(b0, images, tiles, hist, p, s);
     }
     const ImgWork det{B.d_imgs, B.d_det, B.n_det};
-    const DetLevels dl = det_levels(B.lv);
+    DetLevels dl = det_levels(B.lv);
+    dl.thr = (float)p->det_threshold;  // of the masks the extrema kernel reads
     const bool fork = B.fork_det && side != nullptr;
     const int split = side != nullptr && split_ok && !B.fork_det ? B.split_det : -1;
     if (seg == 1) {
@@ -536,7 +544,8 @@ kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStre
         KZ_LAUNCH(K_DET, s, launch_det(b0, det, split >= 0 ? split + 1 : 0, B.N, dl, s));
     if (B.with_nms) {
         const ImgWork nms{B.d_imgs, B.d_nms, B.n_nms};
-        KZ_LAUNCH(K_NMS, s, launch_nms(b0, nms, B.N, (float)p->det_threshold, nms_radii(p), s));
+        KZ_LAUNCH(K_NMS, s,
+                  launch_nms(b0, nms, B.N, (float)p->det_threshold, nms_radii(p), s, true));
     }
     return KAZE_OK;
 }
@@ -614,7 +623,8 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
     const int m = p->substeps;
     for (int j = 0; j < n; ++j) {
         const kaze_image_desc& d = im[j];
-        const Scratch sc = scratch_layout(d.W, d.H, nb, shape, L.scratch[j], false, m > 1);
+        const Scratch sc =
+            scratch_layout(d.W, d.H, nb, shape, L.scratch[j], false, m > 1, B->with_nms ? B->N : 0);
         BatchImage b = batch_image(d.W, d.H);
         b.img = d.img;
         b.ld = d.ld_img;
@@ -627,6 +637,7 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
         b.kps = d.kps;
         b.capacity = d.capacity;
         b.count = d.count;
+        b.mask = B->with_nms ? reinterpret_cast<unsigned long long*>(base + sc.mask) : nullptr;
         himgs[j] = b;
         hitems[j] = make_int2(j, 0);
         const size_t plane = (size_t)d.W * d.H;
@@ -647,7 +658,7 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
         for (int t = 0; t < aos_line_groups(d.W, d.H, L.iface_m); ++t) hl[il++] = make_int2(j, t);
         for (int t = 0; t < (d.W * d.H + kHistChunk - 1) / kHistChunk; ++t) hh[ih++] = make_int2(j, t);
         for (int t = 0; t < det_tiles_of(d.W, d.H); ++t) hd[idt++] = make_int2(j, t);
-        for (int t = 0; t < nms_blocks_of(d.W, d.H); ++t) hn[inm++] = make_int2(j, t);
+        for (int t = 0; t < nms_blocks_of(d.W, d.H, true); ++t) hn[inm++] = make_int2(j, t);
     }
     hipStream_t cs = nullptr;
     hipError_t e = hipMemcpy(base, host.data(), L.tables_end, hipMemcpyHostToDevice);

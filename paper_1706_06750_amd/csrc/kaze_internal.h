@@ -31,6 +31,7 @@ struct DetLevels {
     float sn2[kMaxLevels];   // sigma_n^2
     float sn[kMaxLevels];    // sigma_n
     int list[kMaxLevels];    // per launch: the levels it covers, in order
+    float thr;               // detector threshold of the masks (BatchImage::mask)
 };
 
 // Per-level constants of the description stage: Scharr step, sigma_n and
@@ -55,6 +56,7 @@ struct RefinedKeypoint {
 // on both memory counters.  A cast back keeps them global.
 typedef __attribute__((address_space(1))) float gfloat;
 typedef __attribute__((address_space(1))) unsigned guint;
+typedef __attribute__((address_space(1))) unsigned long long gu64;
 
 // A wave-uniform value in a scalar register (row addresses, loop bounds).
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -158,6 +160,7 @@ constexpr int kTile = 64;          // edge of the stencil tiles
 constexpr int kMaxSide = 4096;     // largest image width or height
 constexpr int kMaxCondRadius = 4;  // sigma_cond radius that keeps the fused tile within 64 KB of LDS
 constexpr int kHistChunk = 8192;   // pixels per block of the histogram kernel
+constexpr int kHistCopies = 16;   // global copies of the k histogram (atomic contention)
 constexpr int kNmsRows = 8;        // rows per thread of the extrema kernel
 
 // Buffers of one image of a (possibly batched) scale-space computation.
@@ -168,11 +171,16 @@ struct BatchImage {
     float* det;         // N planes of W x H
     float* g;           // conductivity plane (squared gradient while k is formed)
     unsigned* hist;     // k histogram
-    unsigned* hmax;     // running max of |grad| (float bits)
+    unsigned* hmax;     // running max of |grad| (float bits), kHistCopies words
     float* k;           // contrast factor (device scalar)
     void* kps;          // keypoints, capacity entries
     int capacity;
     int* count;
+    // N planes of H rows x ceil(W/64) words: bit b of word (i, y, c) is set
+    // iff det_i(64c + b, y) > DetLevels::thr.  Written by the detector
+    // beside det when not null; the extrema kernel then reads only the
+    // det values whose bit is set.
+    unsigned long long* mask;
     int W, H;
 };
 
@@ -370,9 +378,13 @@ int det_tiles_of(int W, int H);
 struct NmsRadii {
     int h[kMaxLevels];
 };
+// masked: the images carry detector masks written with this threshold
+// (items: image, block of 256 mask words of a level); else every det value
+// is read.
 hipError_t launch_nms(const BatchImage& d0, const ImgWork& w, int N, float threshold,
-                      const NmsRadii& radii, hipStream_t s);
-int nms_blocks_of(int W, int H);
+                      const NmsRadii& radii, hipStream_t s, bool masked = false);
+int nms_blocks_of(int W, int H, bool masked = false);
+__host__ __device__ inline int mask_words(int W) { return (W + 63) / 64; }
 // Refinement and edge test of capacity-bounded extrema (entries of 16 and 24
 // bytes: kaze_keypoint and kaze_keypoint_refined) on N levels of W x H;
 // thr = (r+1)^2/r.

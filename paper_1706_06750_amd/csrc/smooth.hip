@@ -111,6 +111,16 @@ __global__ __launch_bounds__(kTileThreads) void gauss_kernel(BatchImage d0, ImgW
     }
 }
 
+// max |grad| over the kHistCopies words the conductivity blocks raise (block
+// c raises word c % kHistCopies: device-scope atomics to one address are
+// serialised)
+__device__ __forceinline__ float hmax_of(const unsigned* hmax) {
+    unsigned m = 0u;
+#pragma unroll
+    for (int j = 0; j < kHistCopies; ++j) m = max(m, ((const guint*)hmax)[j]);
+    return __uint_as_float(m);
+}
+
 // ------------------------------------------------------------ conductivity
 // Conductivity of L on 64x64 tiles with the same LDS pipeline as the fused
 // AOS reduction (tile_cond.h):
@@ -153,7 +163,8 @@ __global__ __launch_bounds__(kTileThreads) void cond_kernel(BatchImage d0, ImgWo
     });
     if (mode == 2) {
         // wavefront max, then one atomic per block (|grad| >= 0, so the
-        // float bit pattern orders like an unsigned integer)
+        // float bit pattern orders like an unsigned integer) on one of
+        // kHistCopies words
         for (int off = kWave / 2; off > 0; off >>= 1)
             local_max = fmaxf(local_max, __shfl_xor(local_max, off, kWave));
         const int t = threadIdx.x;
@@ -162,7 +173,7 @@ __global__ __launch_bounds__(kTileThreads) void cond_kernel(BatchImage d0, ImgWo
         if (t == 0) {
             float m = s_max[0];
             for (int i = 1; i < kTileThreads / kWave; ++i) m = fmaxf(m, s_max[i]);
-            atomicMax(d.hmax, __float_as_uint(m));
+            atomicMax(d.hmax + lt % kHistCopies, __float_as_uint(m));
         }
     }
 }
@@ -170,7 +181,9 @@ __global__ __launch_bounds__(kTileThreads) void cond_kernel(BatchImage d0, ImgWo
 // --------------------------------------------------------------- contrast k
 // 300-bin (nbins) histogram of |grad| = sqrt(m2) over pixels with m2 > 0:
 // bin = min(floor(|grad|/hmax * nbins), nbins-1).  Integer atomics only, so
-// the counts are deterministic.
+// the counts are deterministic.  Device-scope atomics to one address are
+// serialised, so block c adds its counts to global copy c % kHistCopies
+// (bin b of copy j at hist[j * nbins + b]), and kselect sums the copies.
 __global__ __launch_bounds__(256) void hist_kernel(BatchImage d0, ImgWork w, int nbins) {
     extern __shared__ unsigned s_hist[];
     BatchImage d;
@@ -178,23 +191,34 @@ __global__ __launch_bounds__(256) void hist_kernel(BatchImage d0, ImgWork w, int
     resolve(d0, w, (int)blockIdx.x, d, chunk);
     for (int i = threadIdx.x; i < nbins; i += blockDim.x) s_hist[i] = 0u;
     __syncthreads();
-    const float hmax = __uint_as_float(d.hmax[0]);
+    const float hmax = hmax_of(d.hmax);
     const float fb = (float)nbins;
     const int n = d.W * d.H;
     const int i0 = chunk * kHistChunk, i1 = min(n, i0 + kHistChunk);
-    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-        const float v = ((const gfloat*)d.g)[i];
-        if (v > 0.f) {
-            const float m = sqrtf(v);
-            int b = (int)floorf(m / hmax * fb);
-            b = b < nbins - 1 ? b : nbins - 1;
-            b = b > 0 ? b : 0;
-            atomicAdd(&s_hist[b], 1u);
+    // eight loads in flight per thread before any of them is binned
+    constexpr int U = 8;
+    const gfloat* __restrict__ src = (const gfloat*)d.g;
+    for (int i = i0 + threadIdx.x; i < i1; i += U * blockDim.x) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = i + u * (int)blockDim.x;
+            v[u] = j < i1 ? src[j] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (v[u] > 0.f) {
+                const float m = sqrtf(v[u]);
+                int b = (int)floorf(m / hmax * fb);
+                b = b < nbins - 1 ? b : nbins - 1;
+                b = b > 0 ? b : 0;
+                atomicAdd(&s_hist[b], 1u);
+            }
         }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nbins; i += blockDim.x)
-        if (s_hist[i]) atomicAdd(&d.hist[i], s_hist[i]);
+        if (s_hist[i]) atomicAdd(&d.hist[(chunk % kHistCopies) * nbins + i], s_hist[i]);
 }
 
 // Smallest bin b whose cumulative count reaches percentile * npos; k is its
@@ -216,7 +240,13 @@ __global__ __launch_bounds__(256) void kselect_kernel(BatchImage d0, ImgWork w, 
     const int seg = (nbins + 255) / 256;
     const int b0 = t * seg, b1 = min(nbins, b0 + seg);
     unsigned long long part = 0;
-    for (int b = b0; b < b1; ++b) part += hist[b];
+    auto count_of = [&](int b) {  // bin b summed over the histogram's copies
+        unsigned c = 0u;
+#pragma unroll
+        for (int j = 0; j < kHistCopies; ++j) c += hist[j * nbins + b];
+        return c;
+    };
+    for (int b = b0; b < b1; ++b) part += count_of(b);
     s_scan[t] = part;
     if (t == 0) s_best = nbins - 1;
     __syncthreads();
@@ -234,7 +264,7 @@ __global__ __launch_bounds__(256) void kselect_kernel(BatchImage d0, ImgWork w, 
     const unsigned __int128 rhs = (unsigned __int128)pct_mant * npos;
     unsigned long long cum = s_scan[t] - part;  // exclusive prefix
     for (int b = b0; b < b1; ++b) {
-        cum += hist[b];
+        cum += count_of(b);
         if (((unsigned __int128)cum << pct_shift) >= rhs) {
             atomicMin(&s_best, b);
             break;
@@ -242,7 +272,7 @@ __global__ __launch_bounds__(256) void kselect_kernel(BatchImage d0, ImgWork w, 
     }
     __syncthreads();
     if (t == 0) {
-        const float hmax = __uint_as_float(d.hmax[0]);
+        const float hmax = hmax_of(d.hmax);
         d.k[0] = (hmax * (float)(s_best + 1)) / (float)nbins;
     }
 }
@@ -260,9 +290,10 @@ __global__ __launch_bounds__(256) void reset_kernel(BatchImage d0, ImgWork w, in
     int unused;
     resolve(d0, w, (int)blockIdx.x, d, unused);
     if (d.hist)
-        for (int i = threadIdx.x; i < nbins; i += blockDim.x) d.hist[i] = 0u;
+        for (int i = threadIdx.x; i < nbins * kHistCopies; i += blockDim.x) d.hist[i] = 0u;
     if (threadIdx.x == 0) {
-        if (d.hmax) d.hmax[0] = 0u;
+        if (d.hmax)
+            for (int j = 0; j < kHistCopies; ++j) d.hmax[j] = 0u;
         if (d.count) d.count[0] = 0;
         if (k_fill > 0.f && d.k) d.k[0] = k_fill;
     }

@@ -21,7 +21,7 @@ import json
 import os
 
 AOS_KERNELS = ("aos_reduce_kernel", "aos_iface_kernel", "aos_recover_kernel")
-DET_KERNELS = ("det_kernel", "det_rows_kernel")
+DET_KERNELS = ("det_kernel", "det_rows_kernel", "det_rows_pair_kernel")
 
 
 def short(name: str) -> str:

@@ -139,3 +139,33 @@ def test_large_batch_forks_detector_and_matches_eager(gpu_lib):
             assert torch.equal(kb.det[j], ref_det[j]), (r, j)
             assert int(kb.count[j].item()) == ref_cnt[j], (r, j)
     kb.close()
+
+
+@pytest.mark.parametrize("window", ["3x3", "sigma"])
+def test_batch_extrema_with_every_mask_bit_set(gpu_lib, window):
+    """The batch's extrema kernel reads det only where the detector's mask
+    bit (det above the threshold) is set; the single-image calls read every
+    det value.  A threshold below every response sets every bit, so the
+    mask kernel tests every position: its keypoints equal the scanning
+    kernel's on ragged widths (partial mask words) and on both windows."""
+    K = gpu_lib
+    sizes = [(67, 45), (130, 97), (9, 13), (64, 64), (200, 33)]
+    win = K.KAZE_WINDOW_3X3 if window == "3x3" else K.KAZE_WINDOW_SIGMA
+    p = K.kaze_default_params(det_threshold=-1e30, extrema_window=win)
+    cap = 1 << 16
+    kb = K.KazeBatch(sizes, params=p, capacity=cap, shape=0)
+    imgs = [kaze_image(W, H, 90 + j) for j, (W, H) in enumerate(sizes)]
+    for x, im in zip(kb.inputs, imgs):
+        x.copy_(torch.from_numpy(im))
+    kb.run()
+    torch.cuda.synchronize()
+    for j, (im, (W, H)) in enumerate(zip(imgs, sizes)):
+        kz = K.Kaze(W, H, p, capacity=cap)
+        kz.run(torch.from_numpy(im).cuda())
+        torch.cuda.synchronize()
+        n = int(kb.count[j].item())
+        note(f"[batch] every mask bit set, {window}, {W}x{H}: {n} extrema")
+        assert 0 < n <= cap
+        assert torch.equal(kb.det[j], kz.det)
+        assert np.array_equal(kb.keypoints(j), kz.keypoints())
+    kb.close()

@@ -165,6 +165,26 @@ def test_end_to_end_ragged_and_extreme_shapes(gpu_lib, W, H, seed):
     check_end_to_end(gpu_lib, W, H, seed)
 
 
+@pytest.mark.parametrize("nbins", [1, 37, 1000, 4096])
+def test_histogram_bin_counts(gpu_lib, nbins):
+    """The contrast factor for 1 to 4096 bins (the block and global
+    histograms, the copies kselect sums): within one bin width of the
+    oracle's k (the FP32 and FP64 gradients may put a pixel on either side of
+    a bin edge)."""
+    K = gpu_lib
+    W, H = 320, 240
+    img = kaze_image(W, H, 4)
+    kz = K.Kaze(W, H, K.kaze_default_params(k_bins=nbins))
+    kz.run(torch.from_numpy(img).cuda())
+    torch.cuda.synchronize()
+    L0 = O.gaussian_smooth(img.astype(np.float64), 1.6)
+    k_o = O.contrast_factor(L0, nbins=nbins)
+    hmax = float(O.gradient_magnitude(L0, 1.0).max())
+    k_g = float(kz.k.item())
+    note(f"[histogram] {nbins} bins: k {k_g:.6e} oracle {k_o:.6e} bin width {hmax / nbins:.2e}")
+    assert abs(k_g - k_o) <= hmax / nbins * 1.001
+
+
 def test_k_override_and_g1(gpu_lib):
     K = gpu_lib
     p = K.kaze_default_params(k_override=0.004)
