@@ -597,41 +597,57 @@ __device__ __forceinline__ void det_rows_tile(float* smem, const BatchImage& d0,
     }
 
     // phase 3: output row r (tile) uses f-rows r, r+S, r+2S and f-columns
-    // c, c+S, c+2S
+    // c, c+S, c+2S.  Per f-row k of the wavefront's band: the difference
+    // dX = L_x(c+2S) - L_x(c) and the Scharr-weighted sums wX, wY of L_x and
+    // L_y over the columns c, c+S, c+2S.  Then, each up to the factor
+    // 1/(2S) (the three of them folded into sigma_n^2):
+    //   L_xx = scharr3(dX[r], dX[r+S], dX[r+2S]),
+    //   L_xy = wX[r+2S] - wX[r],   L_yy = wY[r+2S] - wY[r].
     {
         const int o0 = wave * G::OB;
         constexpr int K = G::OB + 2 * S;
-        float xL[K], xC[K], xR[K], yL[K], yC[K], yR[K];
+        float dX[K], wX[K], wY[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const float* rx = sX + (o0 + k) * G::PF + lane;
             const float* ry = sY + (o0 + k) * G::PF + lane;
-            xL[k] = rx[0];
-            xC[k] = rx[S];
-            xR[k] = rx[2 * S];
-            yL[k] = ry[0];
-            yC[k] = ry[S];
-            yR[k] = ry[2 * S];
+            dX[k] = rx[2 * S] - rx[0];
+            wX[k] = scharr3(rx[0], rx[S], rx[2 * S]);
+            wY[k] = scharr3(ry[0], ry[S], ry[2 * S]);
         }
-        const int gx = tx0 + lane;
-        gfloat* out = (gfloat*)(d.det + plane * lev) + (ty0 + o0) * W + tx0;
-        gu64* mrow =
-            d.mask ? (gu64*)d.mask + ((size_t)lev * H + ty0 + o0) * mask_words(W) + tx0 / DTX : nullptr;
+        const float scale = sn2 * (inv2s * inv2s);
+        float v[G::OB];
 #pragma unroll
         for (int t = 0; t < G::OB; ++t) {
-            const float Lxx =
-                scharr3(xR[t] - xL[t], xR[t + S] - xL[t + S], xR[t + 2 * S] - xL[t + 2 * S]) * inv2s;
-            const float Lxy =
-                scharr3(xL[t + 2 * S] - xL[t], xC[t + 2 * S] - xC[t], xR[t + 2 * S] - xR[t]) * inv2s;
-            const float Lyy =
-                scharr3(yL[t + 2 * S] - yL[t], yC[t + 2 * S] - yC[t], yR[t + 2 * S] - yR[t]) * inv2s;
-            const float v = sn2 * (Lxx * Lyy - Lxy * Lxy);
-            const bool row_in = ty0 + o0 + t < H;
-            if (row_in && gx < W) out[t * W + lane] = v;
-            if (mrow) {  // the wavefront's ballot is the row's mask word
-                const unsigned long long bits = __ballot(row_in && gx < W && v > dl.thr);
-                if (lane == 0 && row_in) mrow[(size_t)t * mask_words(W)] = bits;
+            const float Lxx = scharr3(dX[t], dX[t + S], dX[t + 2 * S]);
+            const float Lxy = wX[t + 2 * S] - wX[t];
+            const float Lyy = wY[t + 2 * S] - wY[t];
+            v[t] = scale * (Lxx * Lyy - Lxy * Lxy);
+        }
+        const int gx = tx0 + lane;
+        const int rows = uniform(H - (ty0 + o0));  // rows of the band inside the image
+        gfloat* out = (gfloat*)(d.det + plane * lev) + (ty0 + o0) * W + tx0;
+        // row pointers are wave-uniform (scalar base, the lane as offset)
+        if (rows >= G::OB && tx0 + DTX <= W) {
+#pragma unroll
+            for (int t = 0; t < G::OB; ++t) (out + t * W)[lane] = v[t];
+        } else {
+#pragma unroll
+            for (int t = 0; t < G::OB; ++t)
+                if (t < rows && gx < W) (out + t * W)[lane] = v[t];
+        }
+        if (d.mask) {
+            // the mask word of row t is the wavefront's ballot; lane t
+            // stores it
+            unsigned long long word = 0ull;
+#pragma unroll
+            for (int t = 0; t < G::OB; ++t) {
+                const unsigned long long bits = __ballot(gx < W && v[t] > dl.thr);
+                word = lane == t ? bits : word;
             }
+            if (lane < G::OB && lane < rows)
+                ((gu64*)d.mask)[((size_t)lev * H + ty0 + o0 + lane) * mask_words(W) + tx0 / DTX] =
+                    word;
         }
     }
 }
