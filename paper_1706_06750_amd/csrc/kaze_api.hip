@@ -340,9 +340,9 @@ kaze_status base_and_k(const BatchImage& b0, const ImgWork& images, const ImgWor
     const Taps t0 = gauss_taps(p->sigma0);
     const Taps tc = gauss_taps(p->sigma_cond);
     const bool use_hist = !(p->k_override > 0.0);
-    KZ_LAUNCH(K_FILL, s,
-              launch_reset(b0, images, hist_bins(p), use_hist ? 0.f : (float)p->k_override, s));
-    KZ_LAUNCH(K_GAUSS, s, launch_gauss(b0, tiles, t0, s));
+    // the Gaussian's first tile of each image resets its counters
+    KZ_LAUNCH(K_GAUSS, s,
+              launch_gauss(b0, tiles, t0, hist_bins(p), use_hist ? 0.f : (float)p->k_override, s));
     if (use_hist) {
         unsigned long long mant;
         int shift;

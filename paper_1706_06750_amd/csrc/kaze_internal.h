@@ -330,7 +330,9 @@ using ImgWork = Work<BatchImage>;
 using AosWork = Work<ImageDesc>;
 
 // a1: levels[0] = G_sigma0 * img on 64x64 tiles (items: image, tile).
-hipError_t launch_gauss(const BatchImage& d0, const ImgWork& w, const Taps& taps, hipStream_t s);
+// also resets each image's counters as launch_reset does (nbins, k_fill)
+hipError_t launch_gauss(const BatchImage& d0, const ImgWork& w, const Taps& taps, int nbins,
+                        float k_fill, hipStream_t s);
 // Conductivity of levels[0] into g on 64x64 tiles (items: image, tile):
 // mode 0: g2, 1: g1 (k from d.k, or k_host if NULL), 2: squared gradient
 // magnitude and the running maximum of |grad| into hmax.

@@ -11,6 +11,20 @@
 namespace kaze {
 namespace {
 
+// Per image: zero the histogram copies, the gradient maximum words and the
+// keypoint count; set k when it is given rather than formed.  NT threads.
+template <int NT>
+__device__ __forceinline__ void reset_image(const BatchImage& d, int nbins, float k_fill) {
+    if (d.hist)
+        for (int i = threadIdx.x; i < nbins * kHistCopies; i += NT) ((guint*)d.hist)[i] = 0u;
+    if (threadIdx.x == 0) {
+        if (d.hmax)
+            for (int j = 0; j < kHistCopies; ++j) ((guint*)d.hmax)[j] = 0u;
+        if (d.count) *(__attribute__((address_space(1))) int*)d.count = 0;
+        if (k_fill > 0.f && d.k) *(gfloat*)d.k = k_fill;
+    }
+}
+
 // ---------------------------------------------------------------- G_sigma0
 template <int R>
 struct GaussGeom {
@@ -22,8 +36,11 @@ struct GaussGeom {
 };
 
 // L_0 = G_sigma0 * img on one 64x64 tile: horizontal then vertical pass.
+// The first tile of each image also resets the image's counters (the
+// gradient, histogram and extrema kernels that use them run later).
 template <int R>
-__global__ __launch_bounds__(kTileThreads) void gauss_kernel(BatchImage d0, ImgWork work, Taps taps) {
+__global__ __launch_bounds__(kTileThreads) void gauss_kernel(BatchImage d0, ImgWork work, Taps taps,
+                                                               int nbins, float k_fill) {
     using G = GaussGeom<R>;
     constexpr int T = 2 * R + 1;
     extern __shared__ float smem[];
@@ -32,6 +49,7 @@ __global__ __launch_bounds__(kTileThreads) void gauss_kernel(BatchImage d0, ImgW
     BatchImage d;
     int lt;
     resolve(d0, work, xcd_contiguous((int)blockIdx.x, (int)gridDim.x), d, lt);
+    if (lt == 0) reset_image<kTileThreads>(d, nbins, k_fill);
     const gfloat* __restrict__ src = (const gfloat*)d.img;
     gfloat* __restrict__ dst = (gfloat*)d.levels;
     const int W = d.W, H = d.H, ld = d.ld;
@@ -282,21 +300,13 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(unsigned* p, int n, unsig
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
-// Per image: zero the histogram, hmax and the keypoint count; set k when
-// it is given rather than formed.
+// reset_image() of each image on its own (one block per image)
 __global__ __launch_bounds__(256) void reset_kernel(BatchImage d0, ImgWork w, int nbins,
                                                       float k_fill) {
     BatchImage d;
     int unused;
     resolve(d0, w, (int)blockIdx.x, d, unused);
-    if (d.hist)
-        for (int i = threadIdx.x; i < nbins * kHistCopies; i += blockDim.x) d.hist[i] = 0u;
-    if (threadIdx.x == 0) {
-        if (d.hmax)
-            for (int j = 0; j < kHistCopies; ++j) d.hmax[j] = 0u;
-        if (d.count) d.count[0] = 0;
-        if (k_fill > 0.f && d.k) d.k[0] = k_fill;
-    }
+    reset_image<256>(d, nbins, k_fill);
 }
 
 // Streaming copy with 16-byte vector accesses (bandwidth reference).
@@ -322,12 +332,13 @@ int grid_for(size_t n, int block, int cap) {
 int item_count(const ImgWork& w, int single) { return w.items ? w.count : single; }
 
 template <int R>
-hipError_t launch_gauss_r(const BatchImage& d0, const ImgWork& w, const Taps& taps,
-                          hipStream_t s) {
+hipError_t launch_gauss_r(const BatchImage& d0, const ImgWork& w, const Taps& taps, int nbins,
+                          float k_fill, hipStream_t s) {
     const int count = item_count(w, tiles_of(d0.W, d0.H));
     if (count <= 0) return hipSuccess;
     const size_t lds = (size_t)GaussGeom<R>::floats * sizeof(float);
-    hipLaunchKernelGGL(gauss_kernel<R>, dim3(count), dim3(kTileThreads), lds, s, d0, w, taps);
+    hipLaunchKernelGGL(gauss_kernel<R>, dim3(count), dim3(kTileThreads), lds, s, d0, w, taps,
+                       nbins, k_fill);
     return hipGetLastError();
 }
 
@@ -344,10 +355,11 @@ hipError_t launch_cond_r(const BatchImage& d0, const ImgWork& w, const Taps& tap
 
 }  // namespace
 
-hipError_t launch_gauss(const BatchImage& d0, const ImgWork& w, const Taps& taps, hipStream_t s) {
+hipError_t launch_gauss(const BatchImage& d0, const ImgWork& w, const Taps& taps, int nbins,
+                        float k_fill, hipStream_t s) {
     switch (taps.r) {
 #define KZ_G(R) \
-    case R: return launch_gauss_r<R>(d0, w, taps, s);
+    case R: return launch_gauss_r<R>(d0, w, taps, nbins, k_fill, s);
         KZ_G(1) KZ_G(2) KZ_G(3) KZ_G(4) KZ_G(5) KZ_G(6) KZ_G(7) KZ_G(8)
         KZ_G(9) KZ_G(10) KZ_G(11) KZ_G(12) KZ_G(13) KZ_G(14) KZ_G(15) KZ_G(16)
 #undef KZ_G
