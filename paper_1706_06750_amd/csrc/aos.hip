@@ -394,6 +394,62 @@ __global__ __launch_bounds__(kRedThreads) void aos_reduce_kernel(ImageDesc d0, A
     }
 }
 
+// Conductivity g (GM 0: g2, 1: g1) of one image on kAosTX x kCondTY tiles
+// with the reduction's own band code, so g equals the g the fused
+// reduction computes, bit for bit: L on the tile + (RG + 2) ring, the
+// smoothed band, the Scharr gradient and g on the tile.
+constexpr int kCondTY = 32;
+
+template <int RG, int GM>
+__global__ __launch_bounds__(kRedThreads) void cond_band_kernel(BatchImage d, Taps tc, float k_host) {
+    using G = RedGeom<RG, kCondTY, true>;
+    extern __shared__ float smem[];
+    float* sL = smem;
+    float* sS = smem + G::offS;
+    const int tid = threadIdx.x, wave = uniform(tid >> 6), lane = tid & (kWave - 1);
+    const int W = d.W, H = d.H;
+    const int lt = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
+    const int ntx = (W + kAosTX - 1) / kAosTX;
+    const int tx0 = (lt % ntx) * kAosTX, ty0 = (lt / ntx) * kCondTY;
+    load_region<G::NLY, G::NLX, G::PL>(d.levels, W, H, ty0 - G::R, tx0 - G::R, 1.f, sL, wave,
+                                       lane);
+    __syncthreads();
+    constexpr int T = 2 * RG + 1;
+    float wt[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) wt[t] = tc.w[t];
+    smooth_band<RG, G::SPW, G::PL, G::PS>(sL, sS, wave * G::SPW, lane, wt);
+    __syncthreads();
+    const float k = d.k ? *(const gfloat*)d.k : k_host;
+    const float inv_k2 = 1.f / (k * k);  // as the reduction forms it
+    const int q0 = wave * G::QPW;
+    float gv[G::QPW];
+    conductivity_band<G::QPW, G::PS, GM>(sS, q0, lane < G::NGX ? lane : G::NGX - 1,
+                                         inv_k2 * (1.f / 1024.f), gv);
+    const bool col_in = lane >= 1 && lane <= kAosTX && tx0 - 1 + lane < W;
+    gfloat* grow = (gfloat*)d.g + (ptrdiff_t)uniform(ty0 - 1 + q0) * W + (tx0 - 1);
+#pragma unroll
+    for (int j = 0; j < G::QPW; ++j) {
+        const int q = q0 + j;
+        if (q >= 1 && q <= kCondTY && ty0 - 1 + q < H && col_in) grow[(ptrdiff_t)j * W + lane] = gv[j];
+    }
+}
+
+template <int RG>
+hipError_t launch_cond_band_r(const BatchImage& d, const Taps& tc, float k_host, int gmode,
+                              hipStream_t s) {
+    const int count = aos_tiles_of(d.W, d.H, kCondTY);
+    if (count <= 0) return hipSuccess;
+    const size_t lds = (size_t)RedGeom<RG, kCondTY, true>::offG * sizeof(float);  // L and S
+    if (gmode == 0)
+        hipLaunchKernelGGL((cond_band_kernel<RG, 0>), dim3(count), dim3(kRedThreads), lds, s, d,
+                           tc, k_host);
+    else
+        hipLaunchKernelGGL((cond_band_kernel<RG, 1>), dim3(count), dim3(kRedThreads), lds, s, d,
+                           tc, k_host);
+    return hipGetLastError();
+}
+
 // PCR step with reciprocal pivots (the pivots of these diagonally
 // dominant systems are >= their off-diagonal sums).
 __device__ __forceinline__ Eq pcr_reduce_rcp(const Eq& e, const Eq& lo, const Eq& up) {
@@ -735,6 +791,18 @@ hipError_t launch_recover_t(const ImageDesc& d0, const AosWork& w, float tau, hi
 }
 
 }  // namespace
+
+hipError_t launch_cond_band(const BatchImage& d, const Taps& tc, float k_host, int gmode,
+                            hipStream_t s) {
+    if (gmode != 0 && gmode != 1) return hipErrorInvalidValue;
+    switch (tc.r) {
+        case 1: return launch_cond_band_r<1>(d, tc, k_host, gmode, s);
+        case 2: return launch_cond_band_r<2>(d, tc, k_host, gmode, s);
+        case 3: return launch_cond_band_r<3>(d, tc, k_host, gmode, s);
+        case 4: return launch_cond_band_r<4>(d, tc, k_host, gmode, s);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_aos_reduce(const ImageDesc& d0, const AosWork& w, int shape, const Taps& tc,
                              float tau, bool compute_g, int gmode, float k_host, hipStream_t s) {

@@ -338,6 +338,11 @@ hipError_t launch_gauss(const BatchImage& d0, const ImgWork& w, const Taps& taps
 // magnitude and the running maximum of |grad| into hmax.
 hipError_t launch_cond(const BatchImage& d0, const ImgWork& w, const Taps& taps, float k_host,
                        int mode, hipStream_t s);
+// Conductivity g (gmode 0: g2, 1: g1) of one image (levels: L, g: out, k or
+// k_host) with the AOS reduction's band code: bitwise the g of the fused
+// reduction.
+hipError_t launch_cond_band(const BatchImage& d, const Taps& tc, float k_host, int gmode,
+                            hipStream_t s);
 // a2: histogram of sqrt(g) (items: image, chunk of kHistChunk pixels) and
 // the quantile (items: image, 0).
 hipError_t launch_hist(const BatchImage& d0, const ImgWork& w, int nbins, hipStream_t s);

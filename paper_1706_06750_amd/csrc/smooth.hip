@@ -369,6 +369,9 @@ hipError_t launch_gauss(const BatchImage& d0, const ImgWork& w, const Taps& taps
 
 hipError_t launch_cond(const BatchImage& d0, const ImgWork& w, const Taps& taps, float k_host,
                        int mode, hipStream_t s) {
+    // g of one image: the AOS reduction's band kernel (the same g as the
+    // fused reduction); the gradient for k (and work lists): the 64x64 tiles
+    if (!w.items && mode != 2) return launch_cond_band(d0, taps, k_host, mode, s);
     switch (taps.r) {
         case 1: return launch_cond_r<1>(d0, w, taps, k_host, mode, s);
         case 2: return launch_cond_r<2>(d0, w, taps, k_host, mode, s);

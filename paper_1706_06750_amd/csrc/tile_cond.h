@@ -7,8 +7,10 @@
 // A symmetric filter applied to a half-sample symmetric extension yields a
 // half-sample symmetric result, so ring values past the image border equal
 // the reflected in-image values, exactly as if each intermediate image were
-// reflected.  Used by the standalone conductivity kernel and by the fused
-// AOS reduction kernel, so both produce the same g.
+// reflected.  Used for the squared gradient behind the contrast factor and
+// for the conductivity of batched images; the AOS reduction and the
+// conductivity of one image use the band code beside the reduction instead
+// (their g are equal bit for bit; this pipeline rounds differently).
 //
 // Geometry is compile-time (template on the Gaussian radius): every loop is
 // unrolled, global loads are staged through registers so that all of a

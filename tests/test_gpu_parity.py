@@ -78,6 +78,26 @@ def test_conductivity_stage(gpu_lib, W, H, seed):
     assert err < g_tolerance(k32)
 
 
+@pytest.mark.parametrize("W,H,seed", [(320, 240, 1), (67, 45, 5), (130, 97, 6), (9, 13, 3)])
+def test_conductivity_equals_fused_reduction(gpu_lib, W, H, seed):
+    """kaze_conductivity runs the AOS reduction's own band code, so its g
+    equals, bit for bit, the g plane that the last fused reduction of a
+    scale-space build (level N-1, from level N-2 and the build's k) leaves in
+    the first region of the plain workspace."""
+    K = gpu_lib
+    img = kaze_image(W, H, seed)
+    kz = K.Kaze(W, H)
+    kz.scale_space(torch.from_numpy(img).cuda())
+    torch.cuda.synchronize()
+    g_fused = kz.ws[: W * H * 4].view(torch.float32).reshape(H, W).clone()
+    g = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    K.kaze_conductivity(kz.levels[kz.N - 2].contiguous(), W, H, kz.p, float(kz.k.item()), g)
+    torch.cuda.synchronize()
+    note(f"[conductivity] {W}x{H}: standalone vs fused g, max|d| "
+         f"{(g - g_fused).abs().max().item():.1e}")
+    assert torch.equal(g, g_fused)
+
+
 @pytest.mark.parametrize("W,H,seed", [(320, 240, 1), (67, 45, 5), (1920, 1200, 2),
                                       (130, 1100, 7), (64, 2100, 8), (4000, 20, 9),
                                       (4096, 9, 10), (8, 8, 11)])
