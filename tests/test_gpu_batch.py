@@ -169,3 +169,32 @@ def test_batch_extrema_with_every_mask_bit_set(gpu_lib, window):
         assert torch.equal(kb.det[j], kz.det)
         assert np.array_equal(kb.keypoints(j), kz.keypoints())
     kb.close()
+
+
+@pytest.mark.parametrize("window", ["3x3", "sigma"])
+def test_batch_extrema_at_extreme_shapes(gpu_lib, window):
+    """The batch's masked extrema against the single-image calls' scan at
+    the widest rows (4096 px: 64 mask words per row) and the thinnest
+    images the library accepts, at the default threshold and at one that
+    sets most bits."""
+    K = gpu_lib
+    sizes = [(4096, 9), (4000, 20), (64, 2100), (8, 8), (130, 1100)]
+    win = K.KAZE_WINDOW_3X3 if window == "3x3" else K.KAZE_WINDOW_SIGMA
+    imgs = [kaze_image(W, H, 110 + j) for j, (W, H) in enumerate(sizes)]
+    for thr in (0.001, -1e30):
+        p = K.kaze_default_params(det_threshold=thr, extrema_window=win)
+        cap = 1 << 18
+        kb = K.KazeBatch(sizes, params=p, capacity=cap, shape=0)
+        for x, im in zip(kb.inputs, imgs):
+            x.copy_(torch.from_numpy(im))
+        kb.run()
+        torch.cuda.synchronize()
+        for j, (im, (W, H)) in enumerate(zip(imgs, sizes)):
+            kz = K.Kaze(W, H, p, capacity=cap)
+            kz.run(torch.from_numpy(im).cuda())
+            torch.cuda.synchronize()
+            n = int(kb.count[j].item())
+            note(f"[batch] extreme shape {W}x{H}, {window}, threshold {thr:g}: {n} extrema")
+            assert n <= cap
+            assert np.array_equal(kb.keypoints(j), kz.keypoints())
+        kb.close()
