@@ -32,7 +32,6 @@
 // one thread walk a row); tile columns are walked by adjacent threads on
 // adjacent columns, so every global access is coalesced.
 #include "kaze_internal.h"
-#include "tile_cond.h"
 
 namespace kaze {
 namespace {
@@ -238,9 +237,11 @@ __device__ __forceinline__ void load_region(const float* src, int W, int H, int 
 }
 
 // Perona-Malik conductivity (Eq. 3) as a compile-time choice: GM 0 g2,
-// GM 1 g1; m2 is the squared gradient magnitude times 1/k^2.
+// GM 1 g1; m2 is the squared gradient magnitude times 1/k^2.  GM 2 passes
+// it through (with k = 1: the squared gradient itself).
 template <int GM>
 __device__ __forceinline__ float diffusivity_of(float m2k) {
+    if constexpr (GM == 2) return m2k;
     return GM == 0 ? __builtin_amdgcn_rcpf(1.f + m2k) : expf(-m2k);
 }
 
@@ -394,23 +395,29 @@ __global__ __launch_bounds__(kRedThreads) void aos_reduce_kernel(ImageDesc d0, A
     }
 }
 
-// Conductivity g (GM 0: g2, 1: g1) of one image on kAosTX x kCondTY tiles
-// with the reduction's own band code, so g equals the g the fused
-// reduction computes, bit for bit: L on the tile + (RG + 2) ring, the
-// smoothed band, the Scharr gradient and g on the tile.
-constexpr int kCondTY = 32;
-
-template <int RG, int GM>
-__global__ __launch_bounds__(kRedThreads) void cond_band_kernel(BatchImage d, Taps tc, float k_host) {
-    using G = RedGeom<RG, kCondTY, true>;
+// Conductivity on kAosTX x TY tiles with the reduction's own band code: L
+// on the tile + (RG + 2) ring, the smoothed band, the Scharr gradient, and
+// per position of the tile (GM 0) g2 or (GM 1) g1 -- the g the fused
+// reduction computes, bit for bit -- or (GM 2) the squared gradient
+// magnitude |grad L_s|^2, with the tile's maximum of |grad| stored in the
+// tile's word of the image's maxima (no atomics: the histogram and the
+// quantile kernels reduce the words).  Items: (image, tile)
+// as the reduction's, or tiles of d0 without a work list.
+template <int RG, int GM, int TY>
+__global__ __launch_bounds__(kRedThreads) void cond_band_kernel(BatchImage d0, ImgWork w, Taps tc,
+                                                                float k_host) {
+    using G = RedGeom<RG, TY, true>;
     extern __shared__ float smem[];
+    __shared__ float s_max[kRedThreads / kWave];
     float* sL = smem;
     float* sS = smem + G::offS;
     const int tid = threadIdx.x, wave = uniform(tid >> 6), lane = tid & (kWave - 1);
+    BatchImage d;
+    int lt;
+    resolve(d0, w, xcd_contiguous((int)blockIdx.x, (int)gridDim.x), d, lt);
     const int W = d.W, H = d.H;
-    const int lt = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
     const int ntx = (W + kAosTX - 1) / kAosTX;
-    const int tx0 = (lt % ntx) * kAosTX, ty0 = (lt / ntx) * kCondTY;
+    const int tx0 = (lt % ntx) * kAosTX, ty0 = (lt / ntx) * TY;
     load_region<G::NLY, G::NLX, G::PL>(d.levels, W, H, ty0 - G::R, tx0 - G::R, 1.f, sL, wave,
                                        lane);
     __syncthreads();
@@ -420,7 +427,7 @@ __global__ __launch_bounds__(kRedThreads) void cond_band_kernel(BatchImage d, Ta
     for (int t = 0; t < T; ++t) wt[t] = tc.w[t];
     smooth_band<RG, G::SPW, G::PL, G::PS>(sL, sS, wave * G::SPW, lane, wt);
     __syncthreads();
-    const float k = d.k ? *(const gfloat*)d.k : k_host;
+    const float k = GM == 2 ? 1.f : (d.k ? *(const gfloat*)d.k : k_host);
     const float inv_k2 = 1.f / (k * k);  // as the reduction forms it
     const int q0 = wave * G::QPW;
     float gv[G::QPW];
@@ -428,26 +435,51 @@ __global__ __launch_bounds__(kRedThreads) void cond_band_kernel(BatchImage d, Ta
                                          inv_k2 * (1.f / 1024.f), gv);
     const bool col_in = lane >= 1 && lane <= kAosTX && tx0 - 1 + lane < W;
     gfloat* grow = (gfloat*)d.g + (ptrdiff_t)uniform(ty0 - 1 + q0) * W + (tx0 - 1);
+    float m2max = 0.f;
 #pragma unroll
     for (int j = 0; j < G::QPW; ++j) {
         const int q = q0 + j;
-        if (q >= 1 && q <= kCondTY && ty0 - 1 + q < H && col_in) grow[(ptrdiff_t)j * W + lane] = gv[j];
+        if (q >= 1 && q <= TY && ty0 - 1 + q < H && col_in) {
+            grow[(ptrdiff_t)j * W + lane] = gv[j];
+            if constexpr (GM == 2) m2max = fmaxf(m2max, gv[j]);
+        }
+    }
+    if constexpr (GM == 2) {
+        // the square root is monotone, so the maximum is taken on |grad|^2
+        for (int off = kWave / 2; off > 0; off >>= 1)
+            m2max = fmaxf(m2max, __shfl_xor(m2max, off, kWave));
+        if (lane == 0) s_max[wave] = m2max;
+        __syncthreads();
+        if (tid == 0) {
+            float m = s_max[0];
+            for (int i = 1; i < kRedThreads / kWave; ++i) m = fmaxf(m, s_max[i]);
+            ((guint*)d.hmax)[lt] = __float_as_uint(sqrtf(m));
+        }
     }
 }
 
-template <int RG>
-hipError_t launch_cond_band_r(const BatchImage& d, const Taps& tc, float k_host, int gmode,
-                              hipStream_t s) {
-    const int count = aos_tiles_of(d.W, d.H, kCondTY);
+template <int RG, int TY>
+hipError_t launch_cond_band_t(const BatchImage& d0, const ImgWork& w, const Taps& tc,
+                              float k_host, int gmode, hipStream_t s) {
+    const int count = w.items ? w.count : aos_tiles_of(d0.W, d0.H, TY);
     if (count <= 0) return hipSuccess;
-    const size_t lds = (size_t)RedGeom<RG, kCondTY, true>::offG * sizeof(float);  // L and S
-    if (gmode == 0)
-        hipLaunchKernelGGL((cond_band_kernel<RG, 0>), dim3(count), dim3(kRedThreads), lds, s, d,
-                           tc, k_host);
-    else
-        hipLaunchKernelGGL((cond_band_kernel<RG, 1>), dim3(count), dim3(kRedThreads), lds, s, d,
-                           tc, k_host);
+    const size_t lds = (size_t)RedGeom<RG, TY, true>::offG * sizeof(float);  // L and S
+#define KZ_CB(GM)                                                                            \
+    hipLaunchKernelGGL((cond_band_kernel<RG, GM, TY>), dim3(count), dim3(kRedThreads), lds, s, \
+                       d0, w, tc, k_host)
+    if (gmode == 0) KZ_CB(0);
+    else if (gmode == 1) KZ_CB(1);
+    else KZ_CB(2);
+#undef KZ_CB
     return hipGetLastError();
+}
+
+template <int RG>
+hipError_t launch_cond_band_r(const BatchImage& d0, const ImgWork& w, const Taps& tc,
+                              float k_host, int gmode, int ty, hipStream_t s) {
+    if (ty == 32) return launch_cond_band_t<RG, 32>(d0, w, tc, k_host, gmode, s);
+    if (ty == 64) return launch_cond_band_t<RG, 64>(d0, w, tc, k_host, gmode, s);
+    return hipErrorInvalidValue;
 }
 
 // PCR step with reciprocal pivots (the pivots of these diagonally
@@ -792,14 +824,14 @@ hipError_t launch_recover_t(const ImageDesc& d0, const AosWork& w, float tau, hi
 
 }  // namespace
 
-hipError_t launch_cond_band(const BatchImage& d, const Taps& tc, float k_host, int gmode,
-                            hipStream_t s) {
-    if (gmode != 0 && gmode != 1) return hipErrorInvalidValue;
+hipError_t launch_cond(const BatchImage& d0, const ImgWork& w, const Taps& tc, float k_host,
+                       int mode, int ty, hipStream_t s) {
+    if (mode < 0 || mode > 2) return hipErrorInvalidValue;
     switch (tc.r) {
-        case 1: return launch_cond_band_r<1>(d, tc, k_host, gmode, s);
-        case 2: return launch_cond_band_r<2>(d, tc, k_host, gmode, s);
-        case 3: return launch_cond_band_r<3>(d, tc, k_host, gmode, s);
-        case 4: return launch_cond_band_r<4>(d, tc, k_host, gmode, s);
+        case 1: return launch_cond_band_r<1>(d0, w, tc, k_host, mode, ty, s);
+        case 2: return launch_cond_band_r<2>(d0, w, tc, k_host, mode, ty, s);
+        case 3: return launch_cond_band_r<3>(d0, w, tc, k_host, mode, ty, s);
+        case 4: return launch_cond_band_r<4>(d0, w, tc, k_host, mode, ty, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -12,7 +12,7 @@
 #include <type_traits>
 
 #include "kaze_internal.h"
-#include "tile_cond.h"
+#include "tile_stage.h"
 
 namespace kaze {
 namespace {

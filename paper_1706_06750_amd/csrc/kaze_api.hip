@@ -259,7 +259,8 @@ Scratch scratch_layout(int W, int H, int nbins, int shape, size_t base, bool fed
     w.zcol = off; off = align256(off + (size_t)W * ncy * 2 * sizeof(float));
     w.hist = off;
     off = align256(off + (size_t)(nbins > 0 ? nbins : 1) * kHistCopies * sizeof(unsigned));
-    w.hmax = off; off = align256(off + kHistCopies * sizeof(unsigned));
+    // one |grad| maximum per gradient tile (the smallest tile height, 32)
+    w.hmax = off; off = align256(off + (size_t)aos_tiles_of(W, H, 32) * sizeof(unsigned));
     w.tmp = off;  off = align256(off + (fed ? (size_t)W * H * sizeof(float) : 0));
     w.sub = off;  off = align256(off + (sub ? (size_t)W * H * sizeof(float) : 0));
     w.mask = off;
@@ -334,9 +335,11 @@ kaze_status fed_cycle(const float* L, const float* g, float* out, float* tmp, in
 }
 
 // a1-a2: base image and contrast factor (or the given k) for one image or a
-// batch (images / tiles / hist items select the work).
+// batch (images / tiles / AOS tiles of height cty / hist items select the
+// work).
 kaze_status base_and_k(const BatchImage& b0, const ImgWork& images, const ImgWork& tiles,
-                       const ImgWork& hist, const kaze_params* p, hipStream_t s) {
+                       const ImgWork& ctiles, int cty, const ImgWork& hist,
+                       const kaze_params* p, hipStream_t s) {
     const Taps t0 = gauss_taps(p->sigma0);
     const Taps tc = gauss_taps(p->sigma_cond);
     const bool use_hist = !(p->k_override > 0.0);
@@ -347,9 +350,9 @@ kaze_status base_and_k(const BatchImage& b0, const ImgWork& images, const ImgWor
         unsigned long long mant;
         int shift;
         percentile_fraction(p->k_percentile, &mant, &shift);
-        KZ_LAUNCH(K_GRAD, s, launch_cond(b0, tiles, tc, 1.f, 2, s));
-        KZ_LAUNCH(K_HIST, s, launch_hist(b0, hist, p->k_bins, s));
-        KZ_LAUNCH(K_KSELECT, s, launch_kselect(b0, images, p->k_bins, mant, shift, s));
+        KZ_LAUNCH(K_GRAD, s, launch_cond(b0, ctiles, tc, 1.f, 2, cty, s));
+        KZ_LAUNCH(K_HIST, s, launch_hist(b0, hist, p->k_bins, cty, s));
+        KZ_LAUNCH(K_KSELECT, s, launch_kselect(b0, images, p->k_bins, mant, shift, cty, s));
     }
     return KAZE_OK;
 }
@@ -488,8 +491,9 @@ kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStre
     if (seg == 0) {
         const ImgWork images{B.d_imgs, B.d_items, B.n};
         const ImgWork tiles{B.d_imgs, B.d_tiles, B.n_tiles};
+        const ImgWork ctiles{B.d_imgs, B.d_aos, B.n_aos};  // the plan's AOS tiles
         const ImgWork hist{B.d_imgs, B.d_hist, B.n_hist};
-        return base_and_k(b0, images, tiles, hist, p, s);
+        return base_and_k(b0, images, tiles, ctiles, kAosShapeTY[B.shape], hist, p, s);
     }
     const ImgWork det{B.d_imgs, B.d_det, B.n_det};
     DetLevels dl = det_levels(B.lv);
@@ -862,7 +866,7 @@ kaze_status sg_chain(const kaze_sg_scale_space& S, const sg::Geo& geo, int i, co
 kaze_status sg_segment(const kaze_sg_scale_space& S, int seg, hipStream_t s) {
     const kaze_params* p = &S.p;
     const ImgWork none{nullptr, nullptr, 0};
-    if (seg == 0) return base_and_k(S.b, none, none, none, p, s);
+    if (seg == 0) return base_and_k(S.b, none, none, none, kAosShapeTY[0], none, p, s);
     if (seg == 2) {
         if (S.with_det) KZ_LAUNCH(K_DET, s, launch_det(S.b, none, 0, S.N, det_levels(S.lv), s));
         if (S.with_nms)
@@ -882,7 +886,7 @@ kaze_status sg_segment(const kaze_sg_scale_space& S, int seg, hipStream_t s) {
         // conductivity of L_{i-1}: input of the surrogate and of the probe
         BatchImage bc = S.b;
         bc.levels = const_cast<float*>(Lp);
-        KZ_LAUNCH(K_COND, s, launch_cond(bc, none, tc, 1.f, gmode, s));
+        KZ_LAUNCH(K_COND, s, launch_cond(bc, none, tc, 1.f, gmode, kAosShapeTY[0], s));
         KZ_LAUNCH(K_SG_PACK, s, sg::launch_pack_input(Lp, S.b.g, S.tau + i, S.x0, nullptr, S.geo, s));
         ImageDesc d = S.aos;
         d.L = Lp;
@@ -998,7 +1002,7 @@ kaze_status kaze_build_scale_space(const float* img, int W, int H, int ld_img,
     b.hmax = reinterpret_cast<unsigned*>(base + w.hmax);
     b.k = k_out;
     const ImgWork none{nullptr, nullptr, 0};
-    st = base_and_k(b, none, none, none, p, s);
+    st = base_and_k(b, none, none, none, kAosShapeTY[0], none, p, s);
     if (st != KAZE_OK) return st;
 
     std::vector<Level> lv;
@@ -1023,7 +1027,7 @@ kaze_status kaze_build_scale_space(const float* img, int W, int H, int ld_img,
             if (fed) {
                 BatchImage bc = b;
                 bc.levels = const_cast<float*>(src);  // conductivity of the step's start
-                KZ_LAUNCH(K_COND, s, launch_cond(bc, none, tc, 1.f, gmode, s));
+                KZ_LAUNCH(K_COND, s, launch_cond(bc, none, tc, 1.f, gmode, kAosShapeTY[0], s));
                 st = fed_cycle(src, b.g, dst, reinterpret_cast<float*>(base + w.tmp), W, H, tau, s);
             } else {
                 st = aos_step(d, anone, anone, 0, tc, (float)tau, true, gmode, 1.f, s);
@@ -1050,7 +1054,8 @@ kaze_status kaze_conductivity(const float* L, int W, int H, const kaze_params* p
     b.g = g;
     const int gmode = p->diffusivity == KAZE_G2 ? 0 : 1;
     const ImgWork none{nullptr, nullptr, 0};
-    KZ_LAUNCH(K_COND, s, launch_cond(b, none, gauss_taps(p->sigma_cond), (float)k, gmode, s));
+    KZ_LAUNCH(K_COND, s,
+              launch_cond(b, none, gauss_taps(p->sigma_cond), (float)k, gmode, kAosShapeTY[0], s));
     return KAZE_OK;
 }
 

@@ -171,7 +171,7 @@ struct BatchImage {
     float* det;         // N planes of W x H
     float* g;           // conductivity plane (squared gradient while k is formed)
     unsigned* hist;     // k histogram
-    unsigned* hmax;     // running max of |grad| (float bits), kHistCopies words
+    unsigned* hmax;     // max |grad| (float bits) of each gradient tile, one word per tile
     float* k;           // contrast factor (device scalar)
     void* kps;          // keypoints, capacity entries
     int capacity;
@@ -197,7 +197,7 @@ constexpr int kAosShapeTY[kAosShapes] = {32, 64};
 
 __host__ __device__ inline int aos_row_chunks(int W) { return (W + kRowChunk - 1) / kRowChunk; }
 __host__ __device__ inline int aos_col_chunks(int H) { return (H + kColChunk - 1) / kColChunk; }
-inline int aos_tiles_of(int W, int H, int ty) {
+__host__ __device__ inline int aos_tiles_of(int W, int H, int ty) {
     return ((W + kAosTX - 1) / kAosTX) * ((H + ty - 1) / ty);
 }
 // Interface solve: every lane holds M consecutive chunks of a line and a
@@ -333,21 +333,21 @@ using AosWork = Work<ImageDesc>;
 // also resets each image's counters as launch_reset does (nbins, k_fill)
 hipError_t launch_gauss(const BatchImage& d0, const ImgWork& w, const Taps& taps, int nbins,
                         float k_fill, hipStream_t s);
-// Conductivity of levels[0] into g on 64x64 tiles (items: image, tile):
-// mode 0: g2, 1: g1 (k from d.k, or k_host if NULL), 2: squared gradient
-// magnitude and the running maximum of |grad| into hmax.
+// Conductivity of levels[0] into g with the AOS reduction's band code on
+// kAosTX x ty tiles (ty 32 or 64; items: image, tile of that height, or the
+// tiles of d0): mode 0 g2, 1 g1 (k from d.k, or k_host if NULL), bitwise the
+// g of the fused reduction; mode 2 the squared gradient magnitude and the
+// maximum of |grad| of each tile into its hmax word.
 hipError_t launch_cond(const BatchImage& d0, const ImgWork& w, const Taps& taps, float k_host,
-                       int mode, hipStream_t s);
-// Conductivity g (gmode 0: g2, 1: g1) of one image (levels: L, g: out, k or
-// k_host) with the AOS reduction's band code: bitwise the g of the fused
-// reduction.
-hipError_t launch_cond_band(const BatchImage& d, const Taps& tc, float k_host, int gmode,
-                            hipStream_t s);
+                       int mode, int ty, hipStream_t s);
 // a2: histogram of sqrt(g) (items: image, chunk of kHistChunk pixels) and
 // the quantile (items: image, 0).
-hipError_t launch_hist(const BatchImage& d0, const ImgWork& w, int nbins, hipStream_t s);
+// tile_h: the height of the gradient kernel's tiles, whose per-tile maxima
+// of |grad| the two kernels reduce.
+hipError_t launch_hist(const BatchImage& d0, const ImgWork& w, int nbins, int tile_h,
+                       hipStream_t s);
 hipError_t launch_kselect(const BatchImage& d0, const ImgWork& w, int nbins,
-                          unsigned long long pct_mant, int pct_shift, hipStream_t s);
+                          unsigned long long pct_mant, int pct_shift, int tile_h, hipStream_t s);
 // Per image (items: image, 0): zero hist, hmax and count; k = k_fill if > 0.
 hipError_t launch_reset(const BatchImage& d0, const ImgWork& w, int nbins, float k_fill,
                         hipStream_t s);

@@ -6,20 +6,18 @@
 // that extension is itself half-sample symmetric, so ring values of an
 // intermediate (smoothed) image equal the reflected interior values.
 #include "kaze_internal.h"
-#include "tile_cond.h"
+#include "tile_stage.h"
 
 namespace kaze {
 namespace {
 
-// Per image: zero the histogram copies, the gradient maximum words and the
-// keypoint count; set k when it is given rather than formed.  NT threads.
+// Per image: zero the histogram copies and the keypoint count; set k when it
+// is given rather than formed.  NT threads.
 template <int NT>
 __device__ __forceinline__ void reset_image(const BatchImage& d, int nbins, float k_fill) {
     if (d.hist)
         for (int i = threadIdx.x; i < nbins * kHistCopies; i += NT) ((guint*)d.hist)[i] = 0u;
     if (threadIdx.x == 0) {
-        if (d.hmax)
-            for (int j = 0; j < kHistCopies; ++j) ((guint*)d.hmax)[j] = 0u;
         if (d.count) *(__attribute__((address_space(1))) int*)d.count = 0;
         if (k_fill > 0.f && d.k) *(gfloat*)d.k = k_fill;
     }
@@ -129,71 +127,22 @@ __global__ __launch_bounds__(kTileThreads) void gauss_kernel(BatchImage d0, ImgW
     }
 }
 
-// max |grad| over the kHistCopies words the conductivity blocks raise (block
-// c raises word c % kHistCopies: device-scope atomics to one address are
-// serialised)
-__device__ __forceinline__ float hmax_of(const unsigned* hmax) {
+// max |grad| of an image: the maximum over the per-tile maxima the gradient
+// kernel stored (float bits of values >= 0 order like unsigned integers),
+// one slot per tile of the given height.  Called by all 256 threads of a
+// block.
+__device__ __forceinline__ float hmax_of(const BatchImage& d, int tile_h) {
+    __shared__ unsigned s_m[256 / kWave];
+    const int n = aos_tiles_of(d.W, d.H, tile_h);
+    const guint* part = (const guint*)d.hmax;
     unsigned m = 0u;
+    for (int i = threadIdx.x; i < n; i += 256) m = max(m, part[i]);
+    for (int off = kWave / 2; off > 0; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0) s_m[threadIdx.x / kWave] = m;
+    __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kHistCopies; ++j) m = max(m, ((const guint*)hmax)[j]);
+    for (int j = 0; j < 256 / kWave; ++j) m = max(m, s_m[j]);
     return __uint_as_float(m);
-}
-
-// ------------------------------------------------------------ conductivity
-// Conductivity of L on 64x64 tiles with the same LDS pipeline as the fused
-// AOS reduction (tile_cond.h):
-// mode 0: g2 = 1/(1 + |grad|^2/k^2)   (Eq. 3)
-// mode 1: g1 = exp(-|grad|^2/k^2)     (Eq. 3)
-// mode 2: |grad|^2, and the running maximum of |grad| (for the histogram).
-template <int RG>
-__global__ __launch_bounds__(kTileThreads) void cond_kernel(BatchImage d0, ImgWork w, Taps taps,
-                                                              float k_host, int mode) {
-    using G = CondGeom<RG>;
-    extern __shared__ float smem[];
-    __shared__ float s_max[kTileThreads / kWave];
-    float* sL = smem;
-    float* sS = smem + G::offS;
-    BatchImage d;
-    int lt;
-    resolve(d0, w, xcd_contiguous((int)blockIdx.x, (int)gridDim.x), d, lt);
-    const int W = d.W, H = d.H;
-    gfloat* __restrict__ out = (gfloat*)d.g;
-    const int ncx = (W + kTile - 1) / kTile;
-    const int tx0 = (lt % ncx) * kTile, ty0 = (lt / ncx) * kTile;
-    load_L_ring<G>(d.levels, W, H, tx0, ty0, sL);
-    __syncthreads();
-    smooth_tile<G>(sL, sS, taps);
-    __syncthreads();
-    const float k = (mode == 2) ? 1.f : (d.k ? d.k[0] : k_host);
-    const float inv_k2 = 1.f / (k * k);
-    float local_max = 0.f;
-    scharr_pass<G>(sS, [&](int gy, int gx, float m2) {
-        const int y = ty0 - 1 + gy, x = tx0 - 1 + gx;
-        if (gy < 1 || gy > kTile || gx < 1 || gx > kTile || y >= H || x >= W) return;
-        float v;
-        if (mode == 2) {
-            v = m2;
-            local_max = fmaxf(local_max, sqrtf(m2));
-        } else {
-            v = diffusivity(m2, inv_k2, mode);
-        }
-        out[(size_t)y * W + x] = v;
-    });
-    if (mode == 2) {
-        // wavefront max, then one atomic per block (|grad| >= 0, so the
-        // float bit pattern orders like an unsigned integer) on one of
-        // kHistCopies words
-        for (int off = kWave / 2; off > 0; off >>= 1)
-            local_max = fmaxf(local_max, __shfl_xor(local_max, off, kWave));
-        const int t = threadIdx.x;
-        if ((t & (kWave - 1)) == 0) s_max[t / kWave] = local_max;
-        __syncthreads();
-        if (t == 0) {
-            float m = s_max[0];
-            for (int i = 1; i < kTileThreads / kWave; ++i) m = fmaxf(m, s_max[i]);
-            atomicMax(d.hmax + lt % kHistCopies, __float_as_uint(m));
-        }
-    }
 }
 
 // --------------------------------------------------------------- contrast k
@@ -202,14 +151,15 @@ __global__ __launch_bounds__(kTileThreads) void cond_kernel(BatchImage d0, ImgWo
 // the counts are deterministic.  Device-scope atomics to one address are
 // serialised, so block c adds its counts to global copy c % kHistCopies
 // (bin b of copy j at hist[j * nbins + b]), and kselect sums the copies.
-__global__ __launch_bounds__(256) void hist_kernel(BatchImage d0, ImgWork w, int nbins) {
+__global__ __launch_bounds__(256) void hist_kernel(BatchImage d0, ImgWork w, int nbins,
+                                                     int tile_h) {
     extern __shared__ unsigned s_hist[];
     BatchImage d;
     int chunk;
     resolve(d0, w, (int)blockIdx.x, d, chunk);
     for (int i = threadIdx.x; i < nbins; i += blockDim.x) s_hist[i] = 0u;
     __syncthreads();
-    const float hmax = hmax_of(d.hmax);
+    const float hmax = hmax_of(d, tile_h);
     const float fb = (float)nbins;
     const int n = d.W * d.H;
     const int i0 = chunk * kHistChunk, i1 = min(n, i0 + kHistChunk);
@@ -247,7 +197,7 @@ __global__ __launch_bounds__(256) void hist_kernel(BatchImage d0, ImgWork w, int
 // segment.
 __global__ __launch_bounds__(256) void kselect_kernel(BatchImage d0, ImgWork w, int nbins,
                                                         unsigned long long pct_mant,
-                                                        int pct_shift) {
+                                                        int pct_shift, int tile_h) {
     BatchImage d;
     int unused;
     resolve(d0, w, (int)blockIdx.x, d, unused);
@@ -289,10 +239,8 @@ __global__ __launch_bounds__(256) void kselect_kernel(BatchImage d0, ImgWork w, 
         }
     }
     __syncthreads();
-    if (t == 0) {
-        const float hmax = hmax_of(d.hmax);
-        d.k[0] = (hmax * (float)(s_best + 1)) / (float)nbins;
-    }
+    const float hmax = hmax_of(d, tile_h);  // every thread of the block
+    if (t == 0) d.k[0] = (hmax * (float)(s_best + 1)) / (float)nbins;
 }
 
 // ------------------------------------------------------------------ utility
@@ -342,16 +290,6 @@ hipError_t launch_gauss_r(const BatchImage& d0, const ImgWork& w, const Taps& ta
     return hipGetLastError();
 }
 
-template <int RG>
-hipError_t launch_cond_r(const BatchImage& d0, const ImgWork& w, const Taps& taps, float k_host,
-                         int mode, hipStream_t s) {
-    const int count = item_count(w, tiles_of(d0.W, d0.H));
-    if (count <= 0) return hipSuccess;
-    const size_t lds = (size_t)CondGeom<RG>::floats * sizeof(float);
-    hipLaunchKernelGGL(cond_kernel<RG>, dim3(count), dim3(kTileThreads), lds, s, d0, w, taps,
-                       k_host, mode);
-    return hipGetLastError();
-}
 
 }  // namespace
 
@@ -367,34 +305,22 @@ hipError_t launch_gauss(const BatchImage& d0, const ImgWork& w, const Taps& taps
     }
 }
 
-hipError_t launch_cond(const BatchImage& d0, const ImgWork& w, const Taps& taps, float k_host,
-                       int mode, hipStream_t s) {
-    // g of one image: the AOS reduction's band kernel (the same g as the
-    // fused reduction); the gradient for k (and work lists): the 64x64 tiles
-    if (!w.items && mode != 2) return launch_cond_band(d0, taps, k_host, mode, s);
-    switch (taps.r) {
-        case 1: return launch_cond_r<1>(d0, w, taps, k_host, mode, s);
-        case 2: return launch_cond_r<2>(d0, w, taps, k_host, mode, s);
-        case 3: return launch_cond_r<3>(d0, w, taps, k_host, mode, s);
-        case 4: return launch_cond_r<4>(d0, w, taps, k_host, mode, s);
-        default: return hipErrorInvalidValue;
-    }
-}
 
-hipError_t launch_hist(const BatchImage& d0, const ImgWork& w, int nbins, hipStream_t s) {
+hipError_t launch_hist(const BatchImage& d0, const ImgWork& w, int nbins, int tile_h,
+                       hipStream_t s) {
     const int count = item_count(w, (d0.W * d0.H + kHistChunk - 1) / kHistChunk);
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(hist_kernel, dim3(count), dim3(256), nbins * sizeof(unsigned), s, d0, w,
-                       nbins);
+                       nbins, tile_h);
     return hipGetLastError();
 }
 
 hipError_t launch_kselect(const BatchImage& d0, const ImgWork& w, int nbins,
-                          unsigned long long pct_mant, int pct_shift, hipStream_t s) {
+                          unsigned long long pct_mant, int pct_shift, int tile_h, hipStream_t s) {
     const int count = item_count(w, 1);
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(kselect_kernel, dim3(count), dim3(256), 0, s, d0, w, nbins, pct_mant,
-                       pct_shift);
+                       pct_shift, tile_h);
     return hipGetLastError();
 }
 

@@ -44,7 +44,7 @@ def short(name: str) -> str:
 
 # Sources of the per-level kernels: a change to any of them invalidates a
 # traffic summary.
-LEVEL_SOURCES = ("aos.hip", "tile_cond.h", "kaze_internal.h", "detect.hip")
+LEVEL_SOURCES = ("aos.hip", "tile_stage.h", "kaze_internal.h", "detect.hip")
 
 
 def csrc_hash(root: str) -> str:
