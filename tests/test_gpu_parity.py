@@ -170,6 +170,25 @@ def check_end_to_end(K, W, H, seed, params=None, oracle_kw=None):
     return worst
 
 
+@pytest.mark.parametrize("sigma_cond", [0.3, 0.6, 1.3])
+def test_other_conductivity_radii(gpu_lib, sigma_cond):
+    """sigma_cond of Gaussian radius 1, 2 and 4 (ceil(3 sigma); the default
+    1.0 has 3): the whole path against the oracle, and the standalone
+    conductivity equal, bit for bit, to the g of the fused reduction."""
+    K = gpu_lib
+    p = K.kaze_default_params(sigma_cond=sigma_cond)
+    check_end_to_end(K, 160, 120, 4, p, dict(sigma_cond=sigma_cond))
+    W, H = 130, 97
+    kz = K.Kaze(W, H, p)
+    kz.scale_space(torch.from_numpy(kaze_image(W, H, 6)).cuda())
+    torch.cuda.synchronize()
+    g_fused = kz.ws[: W * H * 4].view(torch.float32).reshape(H, W).clone()
+    g = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    K.kaze_conductivity(kz.levels[kz.N - 2].contiguous(), W, H, p, float(kz.k.item()), g)
+    torch.cuda.synchronize()
+    assert torch.equal(g, g_fused)
+
+
 def test_end_to_end_320x240(gpu_lib):
     check_end_to_end(gpu_lib, 320, 240, 1)
 
