@@ -189,6 +189,43 @@ def test_other_conductivity_radii(gpu_lib, sigma_cond):
     assert torch.equal(g, g_fused)
 
 
+@pytest.mark.parametrize("sigma0", [1.0, 2.4, 3.0])
+def test_other_detector_steps(gpu_lib, sigma0):
+    """sigma0 whose levels take Scharr steps {1, 2} (one launch for both),
+    {2, 3, 4} (one launch per step) and {3, 4, 5} (step 5 on the
+    per-position detector): levels, det and keypoints against the oracle,
+    and the batch (whose detector also writes the threshold masks) equal to
+    the single-image calls."""
+    K = gpu_lib
+    W, H = 160, 120
+    p = K.kaze_default_params(sigma0=sigma0)
+    img = kaze_image(W, H, 5)
+    kz = run_gpu(K, img, p)
+    lev_o, k_o = O.build_scale_space(img.astype(np.float64), sigma0=sigma0)
+    det_o = O.detector_response(lev_o, sigma0=sigma0)
+    sched = K.kaze_schedule(kz.p)
+    note(f"[detector steps] sigma0 {sigma0}: steps {sorted({s['deriv_step'] for s in sched})}")
+    assert float(kz.k.item()) == pytest.approx(k_o, rel=1e-4)
+    lev_g, det_g = kz.levels.cpu().numpy(), kz.det.cpu().numpy()
+    for i in range(kz.N):
+        e = float(np.max(np.abs(lev_g[i] - lev_o[i])))
+        de = float(np.max(np.abs(det_g[i] - det_o[i])))
+        assert e <= LEVEL_TOL, (i, e)
+        assert de <= det_tolerance(e, sched[i]["sigma_norm"] ** 2, sched[i]["deriv_step"]), (i, de)
+    thr = kz.p.det_threshold
+    common, bad_g, bad_o = compare_keypoints(kz.keypoints(), O.find_extrema(det_o, thr), det_o, thr)
+    note(f"  keypoints common {common}, unexcused {len(bad_g)} + {len(bad_o)}")
+    assert not bad_g and not bad_o
+    kb = K.KazeBatch([(W, H), (67, 45)], params=p, shape=0)
+    kb.inputs[0].copy_(torch.from_numpy(img))
+    kb.inputs[1].copy_(torch.from_numpy(kaze_image(67, 45, 6)))
+    kb.run()
+    torch.cuda.synchronize()
+    assert torch.equal(kb.det[0], kz.det)
+    assert np.array_equal(kb.keypoints(0), kz.keypoints())
+    kb.close()
+
+
 def test_end_to_end_320x240(gpu_lib):
     check_end_to_end(gpu_lib, 320, 240, 1)
 
