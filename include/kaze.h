@@ -155,6 +155,8 @@ kaze_status kaze_build_scale_space(const float* img, int W, int H, int ld_img,
  *   L        (device) input, W x H float32, row pitch W.
  *   k        contrast factor, > 0.
  *   g        (device) output, W x H float32; must not alias L.
+ * g equals, bit for bit, the conductivity that the AOS steps of
+ * kaze_build_scale_space form internally from the same level and k.
  */
 kaze_status kaze_conductivity(const float* L, int W, int H, const kaze_params* p,
                               double k, float* g, void* stream);
