@@ -206,6 +206,23 @@ def test_batch_workspace_query(K):
     assert K.kaze_batch_workspace_bytes([D(256, 7, 80, 7, 512, 0, 2048, 0, 0, 0)], p) == 0
 
 
+def test_batch_workspace_holds_detector_masks(K):
+    """A batch that finds extrema (count given) needs, per image, N planes of
+    H x ceil(W/64) 64-bit threshold-mask words (a 256-byte aligned region)
+    more than one that stops at det."""
+    p = K.kaze_default_params()
+    N = K.kaze_num_levels(p)
+    D = K.kaze_image_desc
+    dims = [(100, 80), (300, 200), (64, 9)]
+    with_nms = [D(256, W, H, W, 512, 1024, 2048, 4096, 10, 8192) for W, H in dims]
+    det_only = [D(256, W, H, W, 512, 1024, 2048, 0, 0, 0) for W, H in dims]
+    masks = sum((N * H * ((W + 63) // 64) * 8 + 255) // 256 * 256 for W, H in dims)
+    for s in range(len(K.AOS_SHAPES)):
+        a = K.kaze_batch_workspace_bytes(with_nms, p, s)
+        b = K.kaze_batch_workspace_bytes(det_only, p, s)
+        assert a > 0 and b > 0 and a - b == masks
+
+
 @no_gpu_only
 def test_batch_create_rejects_before_any_device_call(K):
     p = K.kaze_default_params()
