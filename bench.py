@@ -81,12 +81,14 @@ CPU_BASELINE_PER_PROCESS = 2  # images per worker: about 8-10 s of work each
 
 def cpu_baseline(W, H, seed):
     """The FP64 oracle as it stands on the host: P single-threaded worker
-    processes (P = the cores this process may use, at most 16), each running
+    processes (P = the cores this process may use, at most 16: the host's CPU
+    share of one GPU on an eight-GPU machine), each running
     the full path on CPU_BASELINE_PER_PROCESS images of the workload's size
     (seeds seed, seed + 1, ...), all started together; throughput = images /
     wall time of the slowest worker (imports and input generation outside
     the timed part)."""
-    P = max(1, min(16, len(os.sched_getaffinity(0))))
+    affinity = len(os.sched_getaffinity(0))
+    P = max(1, min(16, affinity))
     env = dict(os.environ)
     for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         env[v] = "1"
@@ -104,6 +106,7 @@ def cpu_baseline(W, H, seed):
         secs.append(json.loads(out.strip().splitlines()[-1])["seconds"])
     n = P * CPU_BASELINE_PER_PROCESS
     return {"value": n / max(secs), "unit": "images/s", "cores": P, "kind": "oracle",
+            "host_cores": os.cpu_count(), "affinity_cores": affinity,
             "sample": "%d images %dx%d (seeds %d..%d), full path: scale space, det, extrema; "
                       "%d single-threaded processes, %.1f s each (slowest %.1f s); one image "
                       "on one core %.2f s" % (n, W, H, seed, seed + n - 1, P,
@@ -150,6 +153,9 @@ def main():
                     help="skip the FED-scheme measurement")
     ap.add_argument("--no-breakdown", action="store_true",
                     help="skip the per-kernel timing pass (for profiler runs)")
+    ap.add_argument("--no-batches", action="store_true",
+                    help="skip the batch measurements beside the single image (the 64-image "
+                         "uneven batch, 8 x 1920x1200, the 4K + 720p surrogate batch)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run the library's copy kernel on this many MiB, a known-size "
                          "reference for hardware byte counters")
@@ -182,6 +188,11 @@ def main():
     else:
         rec = bench_batch(args, K, torch, kaze_image, cases)
     print(json.dumps(rec), flush=True)
+
+
+def progress(msg):
+    """One line per finished stage on stderr (the JSON record is stdout)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
 
 
 def record(args, value, ms_per_step, config, roofline, extra):
@@ -275,9 +286,11 @@ def bench_single(args, K, torch, kaze_image, case):
 
     # timed path: the image's plan (eager launches or graph replays, the
     # faster of the two)
+    progress("single-image calls: %.1f images/s" % eager_value)
     kb = K.KazeBatch([(W, H)], shape="auto")
     kb.inputs[0].copy_(img)
     elapsed, level_us, form, forms = timed_plan(args, K, torch, kb, 1)
+    progress("image plan: %.1f images/s (%s)" % (args.steps / elapsed, form))
     roof = level_roofline(level_us, W * H,
                           traffic_from_profile("%dx%d" % (W, H), tile_label(K, kb.shape),
                                                det_levels_of(kb, form)),
@@ -292,15 +305,24 @@ def bench_single(args, K, torch, kaze_image, case):
                                   for k, v in breakdown.items()}}
     if not args.no_fed:
         extra["fed"] = bench_fed(args, K, torch, img, W, H, args.steps / elapsed, eager_value)
+        progress("FED done")
     if not args.no_keypoints:
         extra["keypoints"] = bench_keypoints(args, K, torch, img, W, H)
+        progress("keypoint stages done")
     if not args.no_substeps:
         extra["substeps"] = bench_substeps(args, K, torch, img, W, H, eager_value)
+        progress("sub-steps done")
     if not args.no_surrogate:
         extra["surrogate"] = bench_surrogate(args, K, torch, img, W, H, seed,
                                              args.steps / elapsed)
+        progress("surrogate done")
+    if not args.no_batches:
+        del img, kz
+        torch.cuda.empty_cache()
+        extra["batches"] = bench_batches(args, K, torch, kaze_image)
     if not args.no_cpu_baseline:
         extra["cpu_baseline"] = cpu_baseline(W, H, seed)
+        progress("CPU baseline: %.3f images/s" % extra["cpu_baseline"]["value"])
     config = {"workload": args.workload, "image": "%dx%d" % (W, H), "seed": seed,
               "levels": kz.N,
               "path": "plain AOS (no surrogate), image plan, %s" %
@@ -462,81 +484,192 @@ def bench_surrogate(args, K, torch, img, W, H, seed, plain_value):
     return out
 
 
+IMAGE_WORKER_SRC = r"""
+import sys
+sys.path.insert(0, %r)
+import numpy as np
+from synthetic import kaze_image
+for (W, H, seed, path) in %r:
+    np.save(path, kaze_image(W, H, seed))
+"""
+
+
+def parallel_images(cases, workers=16):
+    """Inputs of a workload generated by child processes (the generator is
+    pure NumPy; the children never touch the GPU), loaded back in order."""
+    import tempfile
+
+    import numpy as np
+    tmp = tempfile.mkdtemp(prefix="kaze_inputs_")
+    jobs = [(W, H, seed, os.path.join(tmp, "img%03d.npy" % j)) for j, (W, H, seed) in enumerate(cases)]
+    P = max(1, min(workers, len(os.sched_getaffinity(0)), len(jobs)))
+    procs = [subprocess.Popen([sys.executable, "-c", IMAGE_WORKER_SRC % (ROOT, jobs[w::P])],
+                              stderr=subprocess.PIPE, text=True) for w in range(P)]
+    for pr in procs:
+        _, err = pr.communicate(timeout=600)
+        if pr.returncode != 0:
+            raise RuntimeError("input generation failed: " + err[-2000:])
+    out = []
+    for _, _, _, path in jobs:
+        out.append(np.load(path))
+        os.unlink(path)
+    os.rmdir(tmp)
+    return out
+
+
+def measure_plan(args, K, torch, kb, sizes, traffic_key, steps):
+    """Times both launch forms of a created plan over `steps` runs and returns
+    the faster with its level-segment roofline."""
+    saved = args.steps, args.warmup
+    args.steps, args.warmup = steps, max(2, min(args.warmup, steps // 2))
+    try:
+        elapsed, level_us, form, forms = timed_plan(args, K, torch, kb, len(sizes))
+    finally:
+        args.steps, args.warmup = saved
+    px = sum(W * H for W, H in sizes)
+    dl = det_levels_of(kb, form)
+    roof = level_roofline(level_us, px,
+                          traffic_from_profile(traffic_key, tile_label(K, kb.shape), dl)
+                          if traffic_key else None,
+                          det_levels=dl)
+    roof["timed_in"] = "the timed region (event pair around each run's AOS segment)"
+    return {"images_per_s": round(len(sizes) * steps / elapsed, 3),
+            "megapixels_per_s": round(px * steps / elapsed / 1e6, 1),
+            "ms_per_run": round(1e3 * elapsed / steps, 4), "steps": steps,
+            "path": "plain AOS, batched, %s" % ("eager launches" if form == "eager"
+                                                else "graph replay"),
+            "aos_tile": tile_label(K, kb.shape), "autotune_ms_per_shape": kb.tune_ms,
+            "plan_launch_forms": forms, "roofline": roof}
+
+
+def batch_config(workload, sizes, N):
+    px = sum(W * H for W, H in sizes)
+    return {"workload": workload, "images": len(sizes), "pixels": px,
+            "sizes": "W in [%d,%d], H in [%d,%d]" % (min(w for w, _ in sizes),
+                                                     max(w for w, _ in sizes),
+                                                     min(h for _, h in sizes),
+                                                     max(h for _, h in sizes)),
+            "levels": N}
+
+
 def bench_batch(args, K, torch, kaze_image, cases):
+    """--workload of several images: the plain batched path is the record."""
     sizes = [(W, H) for W, H, _ in cases]
     kb = K.KazeBatch(sizes, shape="auto", capacity=1 << 12)
-    for x, (W, H, seed) in zip(kb.inputs, cases):
-        x.copy_(torch.from_numpy(kaze_image(W, H, seed)))
-    px = sum(W * H for W, H in sizes)
-    elapsed, level_us, form, forms = timed_plan(args, K, torch, kb, len(sizes))
-    roof = level_roofline(level_us, px,
-                          traffic_from_profile(args.workload.replace("kaze_", ""),
-                                               tile_label(K, kb.shape), det_levels_of(kb, form)),
-                          det_levels=det_levels_of(kb, form))
-    roof["timed_in"] = "the timed region (event pair around each run's AOS segment)"
-
-    n = len(sizes)
-    config = {"workload": args.workload, "images": n, "pixels": px,
-              "sizes": "W in [%d,%d], H in [%d,%d]" % (min(w for w, _ in sizes),
-                                                       max(w for w, _ in sizes),
-                                                       min(h for _, h in sizes),
-                                                       max(h for _, h in sizes)),
-              "levels": kb.N,
-              "path": "plain AOS, batched, %s" % ("eager launches" if form == "eager"
-                                                   else "graph replay"),
-              "aos_tile": tile_label(K, kb.shape),
-              "autotune_ms_per_shape": kb.tune_ms}
-    extra = {"megapixels_per_s": round(px * args.steps / elapsed / 1e6, 1),
-             "plan_launch_forms": forms}
-    plain_value = n * args.steps / elapsed
+    imgs = parallel_images(cases) if len(cases) > 8 else [kaze_image(*c) for c in cases]
+    for x, im in zip(kb.inputs, imgs):
+        x.copy_(torch.from_numpy(im))
+    m = measure_plan(args, K, torch, kb, sizes, args.workload.replace("kaze_", ""), args.steps)
+    config = batch_config(args.workload, sizes, kb.N)
+    config.update(path=m["path"], aos_tile=m["aos_tile"],
+                  autotune_ms_per_shape=m["autotune_ms_per_shape"])
+    extra = {"megapixels_per_s": m["megapixels_per_s"], "plan_launch_forms": m["plan_launch_forms"]}
     kb.close()
     del kb
     torch.cuda.empty_cache()
     if not args.no_surrogate and args.workload == "kaze_4k32_720p32":
-        extra["surrogate"] = bench_surrogate_batch(args, K, torch, kaze_image, cases, plain_value)
-    return record(args, plain_value, 1e3 * elapsed / args.steps, config, roof, extra)
+        extra["surrogate"] = bench_surrogate_batch(args, K, torch, cases, imgs, m["images_per_s"])
+    return record(args, m["images_per_s"], m["ms_per_run"], config, m["roofline"], extra)
 
 
-def bench_surrogate_batch(args, K, torch, kaze_image, cases, plain_value):
-    """The surrogate form over a batch: one surrogate plan per image size,
-    run once per image of the batch (default check and fallback)."""
+def bench_batches(args, K, torch, kaze_image):
+    """Batches beside the single-image record: the 64-image uneven batch and
+    eight 1920x1200 images (plain path, autotuned tile, each with its own
+    level-segment roofline), and the 4K + 720p workload through the plain
+    batched path and the batched surrogate."""
+    from synthetic import WORKLOADS
+    out = {}
+    for name, steps in (("kaze_batch64_uneven", 20), ("kaze_8x1920x1200", 20)):
+        cases = WORKLOADS[name]()
+        sizes = [(W, H) for W, H, _ in cases]
+        imgs = parallel_images(cases)
+        kb = K.KazeBatch(sizes, shape="auto", capacity=1 << 12)
+        for x, im in zip(kb.inputs, imgs):
+            x.copy_(torch.from_numpy(im))
+        m = measure_plan(args, K, torch, kb, sizes, name.replace("kaze_", ""), steps)
+        m["config"] = batch_config(name, sizes, kb.N)
+        kb.close()
+        del kb, imgs
+        torch.cuda.empty_cache()
+        out[name] = m
+        progress("%s: %.1f images/s, %.1f%% of HBM peak per level" %
+                 (name, m["images_per_s"], 100 * m["roofline"]["frac"]))
+    if not args.no_surrogate:
+        cases = WORKLOADS["kaze_4k32_720p32"]()
+        sizes = [(W, H) for W, H, _ in cases]
+        imgs = parallel_images(cases)
+        kb = K.KazeBatch(sizes, shape="auto", capacity=1 << 12)
+        for x, im in zip(kb.inputs, imgs):
+            x.copy_(torch.from_numpy(im))
+        m = measure_plan(args, K, torch, kb, sizes, "4k32_720p32", 5)
+        m["config"] = batch_config("kaze_4k32_720p32", sizes, kb.N)
+        progress("kaze_4k32_720p32 plain batched: %.1f images/s" % m["images_per_s"])
+        m["surrogate"] = bench_surrogate_batch(args, K, torch, cases, imgs, m["images_per_s"],
+                                               plain=kb)
+        kb.close()
+        del kb, imgs
+        torch.cuda.empty_cache()
+        out["kaze_4k32_720p32"] = m
+    return out
+
+
+def bench_surrogate_batch(args, K, torch, cases, imgs, plain_value, plain=None):
+    """The batched surrogate form (one plan for every image; per image and
+    level the probe check, the network where accepted, AOS where rejected)
+    on the workload: default check and every level forced to the network,
+    images/s against the plain batched path, the levels accepted and every
+    image's largest difference from the plain batched levels (when `plain`,
+    a plain plan that has run on the same inputs, is given).  Errors against
+    the FP64 oracle on this workload are measured by the GPU tests."""
+    import math
+
+    import numpy as np
     from paper_1706_06750_amd import surrogate as S
     from paper_1706_06750_amd import train_surrogate as T
     if not os.path.exists(T.DEFAULT_OUT):
         return {"skipped": "no trained weights"}
     params, _ = T.load()
     w = S.Weights(params)
-    plans = {}
-    for W, H, seed in cases:
-        if (W, H) not in plans:
-            plans[(W, H)] = S.SurrogateScaleSpace(W, H, w, probe_seed=seed, capacity=1 << 12)
-    imgs = [torch.from_numpy(kaze_image(W, H, seed)).cuda() for W, H, seed in cases]
-    accepted = 0
-
-    def one_pass():
-        nonlocal accepted
-        for (W, H, _), img in zip(cases, imgs):
-            ss = plans[(W, H)]
-            ss.img.copy_(img)
-            ss.run()
-        accepted = sum(int(sum(p.accepted())) for p in plans.values())
-
-    one_pass()
-    torch.cuda.synchronize()
-    steps = max(1, args.steps // 5)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        one_pass()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    val = len(cases) * steps / el
-    out = {"plans": ["%dx%d" % k for k in plans], "images_per_s": round(val, 3),
-           "levels_accepted_in_last_images": accepted,
-           "speedup_vs_plain_batched": round(val / plain_value, 4),
-           "note": "input copy and one graph run per image; the plain batched path is one graph "
-                   "for all images"}
-    for p in plans.values():
-        p.close()
+    sizes = [(W, H) for W, H, _ in cases]
+    out = {"plan": "kaze_sg_batch_create: every phase one launch over the %d images" % len(sizes)}
+    for name, cfg in (("default", {}), ("all_surrogate", {"bound": math.inf, "probes": 0})):
+        c = S.kaze_sg_default_config(**cfg)
+        sb = S.SurrogateBatch(sizes, w, config=c, probe_seed=cases[0][2], capacity=1 << 12)
+        for x, im in zip(sb.inputs, imgs):
+            x.copy_(torch.from_numpy(im))
+        sb.run()
+        torch.cuda.synchronize()
+        steps = 3
+        K.kaze_profile_begin("aos_reduce")
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sb.run()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        runs, ms = K.kaze_profile_end()
+        acc = sb.accepted()
+        val = len(sizes) * steps / el
+        r = {"bound": c.bound, "probes": c.probes, "images_per_s": round(val, 3),
+             "ms_per_run": round(1e3 * el / steps, 3),
+             "us_per_level": round(1e3 * ms / (max(runs, 1) * (sb.N - 1)), 3),
+             "levels_accepted": int(acc.sum()), "level_decisions": int(acc[:, 1:].size),
+             "accepted_levels_per_image": acc.sum(axis=1).tolist(),
+             "speedup_vs_plain_batched": round(val / plain_value, 4)}
+        if name == "default":
+            pe = sb.err.cpu().numpy()[:, 1:]
+            r["probe_err_range"] = [float("%.3e" % pe.min()), float("%.3e" % pe.max())]
+            if plain is not None:
+                d = [float((sb.levels[j] - plain.levels[j]).abs().max().item())
+                     for j in range(len(sizes))]
+                r["max_abs_vs_plain_batched_per_image"] = [float("%.3e" % v) for v in d]
+                r["keypoints_equal_plain_batched"] = int(sum(
+                    int(np.array_equal(sb.keypoints(j), plain.keypoints(j)))
+                    for j in range(len(sizes))))
+        out[name] = r
+        sb.close()
+        del sb
+        torch.cuda.empty_cache()
+        progress("surrogate batch (%s): %.1f images/s" % (name, r["images_per_s"]))
     return out
 
 

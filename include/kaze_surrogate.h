@@ -136,8 +136,13 @@ typedef struct {
                          kaze_batch_config.aos_shape; -1 = 0)               */
 } kaze_sg_config;
 
-/* Defaults: bound 2.5e-4 (15 steps then stay within about 4e-3 of the exact
- * steps' result), 4 probes of 32 x 32, AOS tile shape 0. */
+/* Defaults: bound 6.6e-5 per level, 4 probes of 32 x 32, AOS tile shape 0.
+ * The bound is the surrogate's error budget of 1e-3 over the 15 steps of the
+ * default schedule spread evenly: with the conductivity held fixed an AOS
+ * step does not amplify a perturbation of its input in the maximum norm
+ * (its matrix has a non-negative inverse with unit row sums), so the errors
+ * of the accepted steps add up to at most 15 x 6.6e-5 = 9.9e-4 to first
+ * order. */
 kaze_status kaze_sg_default_config(kaze_sg_config* c);
 
 typedef struct kaze_sg_scale_space kaze_sg_scale_space;
@@ -174,6 +179,40 @@ kaze_status kaze_sg_scale_space_create(const kaze_image_desc* image, const kaze_
 kaze_status kaze_sg_scale_space_run(kaze_sg_scale_space* s, int eager, void* stream);
 
 kaze_status kaze_sg_scale_space_destroy(kaze_sg_scale_space* s);
+
+/*
+ * Surrogate batches: the surrogate scale space above for many images of
+ * different sizes in one plan.  Every phase of a level is one launch over
+ * all images: the conductivity, the network input, the network and the
+ * exact solves on every image's probe windows, the network on every image
+ * whose level was accepted and the AOS step of Eq. 4 on every image whose
+ * level was rejected, each decided per image and level on the device.  Base
+ * image, contrast factor, detector response and extrema are those of
+ * kaze_batch_create (kaze.h); the detector runs after the steps.
+ *
+ * The plan is a kaze_batch: kaze_batch_run, kaze_batch_properties and
+ * kaze_batch_destroy apply to it.
+ *   images    (host) n kaze_image_desc, as for kaze_batch_create.
+ *   c         probe check and AOS tile shape (c->aos_shape, -1 = 0).
+ *   packed    (device) output of kaze_sg_pack(); read by every run.
+ *   probe_xy  (host) n x N x probes x 2 ints: top-left corner (x, y) of
+ *             probe window q of image j, level i, at
+ *             [((j * N + i) * probes + q) * 2]; level 0 is unused; may be
+ *             NULL when probes = 0.
+ *   err       (device) n x N floats written by every run: err[j * N + i] is
+ *             the probe error of image j, level i (as for one image); image
+ *             j used the surrogate for level i iff err[j * N + i] <= bound.
+ *   ws        (device) kaze_sg_batch_workspace_bytes() bytes, 256-byte
+ *             aligned, owned by the plan until it is destroyed.
+ * Limits: n <= 4096; p->scheme AOS and p->substeps 1.
+ */
+size_t kaze_sg_batch_workspace_bytes(const kaze_image_desc* images, int n,
+                                     const kaze_params* p, const kaze_sg_config* c);
+
+kaze_status kaze_sg_batch_create(const kaze_image_desc* images, int n, const kaze_params* p,
+                                 const kaze_sg_config* c, const void* packed,
+                                 const int* probe_xy, float* err, void* ws, size_t ws_bytes,
+                                 kaze_batch** out);
 
 #ifdef __cplusplus
 }

@@ -711,13 +711,17 @@ struct GlobalLineAcc {
 constexpr int kProbeChunk = 64;  // unknowns per lane: lines of up to 64 x 64
 
 // One wavefront per line through a probe window: lines 0..kProbeMax-1 are
-// rows y0 + j, lines kProbeMax.. are columns x0 + j.
+// rows y0 + j, lines kProbeMax.. are columns x0 + j.  With pdesc (batches)
+// probe p belongs to the image pdesc[rect_img[p]], else to d.
 __global__ __launch_bounds__(kBlock) void aos_probe_kernel(ImageDesc d, const int4* rects,
-                                                           int nprobes, float tau, float* delta) {
+                                                           int nprobes, float tau, float* delta,
+                                                           const ImageDesc* pdesc,
+                                                           const int* rect_img) {
     const int lane = threadIdx.x % kWave;
-    const int wv = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const int wv = uniform(blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave);
     const int probe = wv / (2 * kProbeMax), j = wv % (2 * kProbeMax);
     if (probe >= nprobes) return;
+    if (pdesc) d = pdesc[rect_img[probe]];
     const int4 r = rects[probe];  // x0, y0, w, h
     const bool row = j < kProbeMax;
     const int off = row ? j : j - kProbeMax;
@@ -751,10 +755,21 @@ __global__ __launch_bounds__(kBlock) void aos_probe_kernel(ImageDesc d, const in
     }
 }
 
+// Largest |cand - exact| over probe window blockIdx.x into *err (atomic max
+// of the float bits).  With pdesc the window's image supplies L (d.L), the
+// candidate (d.Lnext), the width and the error word (d.gate).
 __global__ __launch_bounds__(kBlock) void probe_err_kernel(const float* L, const float* cand, int W,
                                                            const int4* rects, const float* delta,
-                                                           unsigned* err) {
+                                                           unsigned* err, const ImageDesc* pdesc,
+                                                           const int* rect_img) {
     __shared__ float red[kBlock];
+    if (pdesc) {
+        const ImageDesc& d = pdesc[rect_img[blockIdx.x]];
+        L = d.L;
+        cand = d.Lnext;
+        W = d.W;
+        err = reinterpret_cast<unsigned*>(const_cast<float*>(d.gate));
+    }
     const int4 r = rects[blockIdx.x];
     const float* dl = delta + (size_t)blockIdx.x * 2 * kProbeMax * kProbeMax;
     float m = 0.f;
@@ -870,19 +885,21 @@ hipError_t launch_aos_recover(const ImageDesc& d0, const AosWork& w, int shape, 
 }
 
 hipError_t launch_aos_probe(const ImageDesc& d, const int4* rects, int nprobes, float tau,
-                            float* delta, hipStream_t s) {
+                            float* delta, hipStream_t s, const ImageDesc* pdesc,
+                            const int* rect_img) {
     if (nprobes <= 0) return hipSuccess;
     const int waves = nprobes * 2 * kProbeMax, per = kBlock / kWave;
     hipLaunchKernelGGL(aos_probe_kernel, dim3((waves + per - 1) / per), dim3(kBlock), 0, s, d, rects,
-                       nprobes, tau, delta);
+                       nprobes, tau, delta, pdesc, rect_img);
     return hipGetLastError();
 }
 
 hipError_t launch_probe_err(const float* L, const float* cand, int W, const int4* rects,
-                            int nprobes, const float* delta, unsigned* err, hipStream_t s) {
+                            int nprobes, const float* delta, unsigned* err, hipStream_t s,
+                            const ImageDesc* pdesc, const int* rect_img) {
     if (nprobes <= 0) return hipSuccess;
     hipLaunchKernelGGL(probe_err_kernel, dim3(nprobes), dim3(kBlock), 0, s, L, cand, W, rects, delta,
-                       err);
+                       err, pdesc, rect_img);
     return hipGetLastError();
 }
 

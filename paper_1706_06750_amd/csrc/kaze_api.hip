@@ -362,6 +362,10 @@ kaze_status base_and_k(const BatchImage& b0, const ImgWork& images, const ImgWor
 // ============================================================================
 // Batches: device tables, graph capture and replay.
 // ============================================================================
+namespace {
+struct SgBatch;
+}
+
 struct kaze_batch {
     int n = 0;
     int N = 0;
@@ -383,6 +387,7 @@ struct kaze_batch {
     bool fork_det = false;           // detector response beside the steps, per level
     int split_det = -1;              // else: levels 0..split_det forked once
     int iface_m = kIfaceMLarge;      // chunks per lane of the interface solves
+    SgBatch* sg = nullptr;           // surrogate steps (kaze_sg_batch_create), or none
 };
 
 // A captured fork spreads a graph over several hardware queues, and every
@@ -398,6 +403,22 @@ constexpr int kSplitDetBack = 5;
 extern "C" kaze_status kaze_batch_destroy(kaze_batch* b);
 
 namespace {
+
+// Surrogate steps of a batch (kaze_sg_batch_create); defined with the
+// surrogate scale space below.
+struct SgSpec {
+    const kaze_sg_config* c;
+    const void* packed;
+    const int* probe_xy;  // (host) n x N x probes x 2
+    float* err;           // (device) n x N
+};
+size_t sg_batch_bytes(const kaze_image_desc* im, int n, const kaze_params* p,
+                      const kaze_sg_config* c);
+kaze_status sg_batch_check(const kaze_image_desc* im, int n, const kaze_params* p,
+                           const SgSpec& sp);
+kaze_status sg_batch_build(kaze_batch* B, const kaze_image_desc* im, const SgSpec& sp,
+                           char* base, size_t off, const std::vector<size_t>& scratch);
+kaze_status sg_batch_levels(const kaze_batch& B, hipStream_t s);
 
 struct BatchLayout {
     size_t imgs, lvl, items, tiles, aos, lines, hist, det, nms, tables_end;
@@ -500,6 +521,7 @@ kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStre
     dl.thr = (float)p->det_threshold;  // of the masks the extrema kernel reads
     const bool fork = B.fork_det && side != nullptr;
     const int split = side != nullptr && split_ok && !B.fork_det ? B.split_det : -1;
+    if (seg == 1 && B.sg) return sg_batch_levels(B, s);
     if (seg == 1) {
         // The detector response of level i needs level i only: with a side
         // stream (graph capture of a large batch) it runs there, overlapping
@@ -572,14 +594,17 @@ kaze_status enqueue_batch(const kaze_batch& B, hipStream_t s) {
 }
 
 kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p, int shape,
-                         void* ws, size_t ws_bytes, kaze_batch** out) {
+                         void* ws, size_t ws_bytes, kaze_batch** out,
+                         const SgSpec* sp = nullptr) {
     kaze_status st = check_batch(im, n, p, shape);
     if (st != KAZE_OK) return st;
     if (!out) return fail(KAZE_ERR_INVALID_ARG, "out pointer is NULL");
+    if (sp && (st = sg_batch_check(im, n, p, *sp)) != KAZE_OK) return st;
     const BatchLayout L = batch_layout(im, n, p, shape);
-    if (!ws || !aligned(ws, 256) || ws_bytes < L.total)
+    const size_t total = L.total + (sp ? sg_batch_bytes(im, n, p, sp->c) : 0);
+    if (!ws || !aligned(ws, 256) || ws_bytes < total)
         return fail(KAZE_ERR_WORKSPACE, "batch workspace needs %zu bytes, 256-byte aligned (got %zu)",
-                    L.total, ws_bytes);
+                    total, ws_bytes);
     char* base = static_cast<char*>(ws);
     kaze_batch* B = new kaze_batch();
     B->n = n;
@@ -591,8 +616,9 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
     B->with_nms = im[0].count != nullptr;
     double px = 0;
     for (int j = 0; j < n; ++j) px += (double)im[j].W * im[j].H;
-    B->fork_det = B->with_det && px >= kForkDetPixels;
-    B->split_det = B->with_det && !B->fork_det && B->N > kSplitDetBack + 1
+    // surrogate batches run the detector after the steps (no fork)
+    B->fork_det = !sp && B->with_det && px >= kForkDetPixels;
+    B->split_det = !sp && B->with_det && !B->fork_det && B->N > kSplitDetBack + 1
                        ? B->N - 1 - kSplitDetBack : -1;
     B->d_imgs = reinterpret_cast<BatchImage*>(base + L.imgs);
     B->d_lvl = reinterpret_cast<ImageDesc*>(base + L.lvl);
@@ -652,6 +678,10 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
                 ImageDesc a = aos_desc(d.W, d.H, shape, base, sc, d.k);
                 a.L = src;
                 a.Lnext = ((m - 1 - q) % 2 == 0) ? d.levels + plane * i : mid;
+                if (sp) {  // the exact step runs only where the surrogate was rejected
+                    a.gate = sp->err + (size_t)j * B->N + i;
+                    a.bound = (float)sp->c->bound;
+                }
                 hlvl[((size_t)(i - 1) * m + q) * n + j] = a;
                 src = a.Lnext;
             }
@@ -666,6 +696,13 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
     }
     hipStream_t cs = nullptr;
     hipError_t e = hipMemcpy(base, host.data(), L.tables_end, hipMemcpyHostToDevice);
+    if (e == hipSuccess && sp) {
+        st = sg_batch_build(B, im, *sp, base, L.total, L.scratch);
+        if (st != KAZE_OK) {
+            kaze_batch_destroy(B);
+            return st;
+        }
+    }
     // capture each segment once on a private stream (default priority); the
     // detector response forks to a second one
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -741,6 +778,8 @@ void sg_probe_items(const sg::Geo& g, const int4* rects, int n, std::vector<int>
 // Probe windows are short: their convolutions run with few rows per wave,
 // so that the latency of one wave's row sweep stays small.
 constexpr int kProbeRows = 4;
+// Images of a surrogate batch (the input-packing grid has one row per image).
+constexpr int kSgBatchMaxImages = 4096;
 
 int sg_max_items(const kaze_sg_config* c) {
     // a window of probe_size + 2 halo pixels spans at most this many strips x chunks
@@ -925,6 +964,374 @@ kaze_status sg_run(const kaze_sg_scale_space& S, bool eager, hipStream_t s) {
     return KAZE_OK;
 }
 
+// ============================================================================
+// Batched surrogate: the surrogate scale space over many images of uneven
+// sizes.  Every phase of a level is one launch over all images (the batch's
+// work lists and per-level tables); the probe check, the acceptance and the
+// exact fallback are decided per image and level on the device.
+// ============================================================================
+struct SgBatch {
+    float bound = 0.f;
+    int probes = 0, np = 0;  // windows per image and level; per level (n x probes)
+    const unsigned char* packed = nullptr;
+    float* err = nullptr;    // caller's n x N probe errors
+    sg::bf16 *x0 = nullptr, *xa = nullptr, *xb = nullptr;  // activations of all images
+    float *delta = nullptr, *tau = nullptr;
+    BatchImage* cond = nullptr;  // (N-1) x n: conductivity of L_{i-1}
+    sg::SgImage* img = nullptr;  // (N-1) x n
+    int2* full = nullptr;        // fused-pair items of every image
+    int n_full = 0;
+    int4* rects = nullptr;       // (N-1) x np probe windows
+    int* rect_img = nullptr;     // (N-1) x np: image of each window
+    int2* pitems = nullptr;      // conv items meeting the windows, per level
+    std::vector<int> pitem_off, pitem_cnt;
+};
+
+struct SgBatchLayout {
+    size_t x0, xa, xb, delta, tau, cond, img, full, rects, rect_img, pitems, total;
+    long long px;  // padded pixels of all images
+    int n_full, max_pitems;
+};
+
+SgBatchLayout sg_batch_layout(const kaze_image_desc* im, int n, const kaze_params* p,
+                              const kaze_sg_config* c) {
+    SgBatchLayout L;
+    const int N = p->octaves * p->sublevels;
+    L.px = 0;
+    L.n_full = 0;
+    for (int j = 0; j < n; ++j) {
+        const sg::Geo g = sg::image_geo(im[j].W, im[j].H, sg::kConvRows);
+        L.px += g.sx;
+        L.n_full += ((im[j].W + sg::kPairOut - 1) / sg::kPairOut) * g.chunks;
+    }
+    const size_t np = (size_t)n * std::max(1, c->probes);
+    const size_t lv = (size_t)std::max(1, N - 1);
+    L.max_pitems = n * sg_max_items(c);
+    size_t off = 0;
+    L.x0 = off;       off = align256(off + (size_t)L.px * 8 * sizeof(sg::bf16));
+    L.xa = off;       off = align256(off + (size_t)L.px * 32 * sizeof(sg::bf16));
+    L.xb = off;       off = align256(off + (size_t)L.px * 32 * sizeof(sg::bf16));
+    L.delta = off;    off = align256(off + np * 2 * kProbeMax * kProbeMax * sizeof(float));
+    L.tau = off;      off = align256(off + (size_t)N * sizeof(float));
+    L.cond = off;     off = align256(off + lv * n * sizeof(BatchImage));
+    L.img = off;      off = align256(off + lv * n * sizeof(sg::SgImage));
+    L.full = off;     off = align256(off + (size_t)L.n_full * sizeof(int2));
+    L.rects = off;    off = align256(off + lv * np * sizeof(int4));
+    L.rect_img = off; off = align256(off + lv * np * sizeof(int));
+    L.pitems = off;   off = align256(off + lv * L.max_pitems * sizeof(int2));
+    L.total = off;
+    return L;
+}
+
+size_t sg_batch_bytes(const kaze_image_desc* im, int n, const kaze_params* p,
+                      const kaze_sg_config* c) {
+    return sg_batch_layout(im, n, p, c).total;
+}
+
+kaze_status sg_batch_check(const kaze_image_desc* im, int n, const kaze_params* p,
+                           const SgSpec& sp) {
+    kaze_status st = check_sg_config(sp.c);
+    if (st != KAZE_OK) return st;
+    if (p->substeps != 1)
+        return fail(KAZE_ERR_UNSUPPORTED, "the surrogate replaces whole level steps (substeps 1)");
+    if (n > kSgBatchMaxImages)
+        return fail(KAZE_ERR_UNSUPPORTED, "a surrogate batch holds at most %d images (got %d)",
+                    kSgBatchMaxImages, n);
+    if (!sp.packed || !aligned(sp.packed, 256))
+        return fail(KAZE_ERR_INVALID_ARG, "packed weights must be non-NULL and 256-byte aligned");
+    if (!sp.err || !aligned(sp.err, 4)) return fail(KAZE_ERR_INVALID_ARG, "err must be non-NULL");
+    const int N = p->octaves * p->sublevels, P = sp.c->probes;
+    if (P > 0) {
+        if (!sp.probe_xy) return fail(KAZE_ERR_INVALID_ARG, "probe_xy is NULL with probes > 0");
+        for (int j = 0; j < n; ++j)
+            for (int i = 1; i < N; ++i)
+                for (int q = 0; q < P; ++q) {
+                    const int* xy = sp.probe_xy + (((size_t)j * N + i) * P + q) * 2;
+                    if (xy[0] < 0 || xy[0] >= im[j].W || xy[1] < 0 || xy[1] >= im[j].H)
+                        return fail(KAZE_ERR_INVALID_ARG,
+                                    "probe (%d, %d) of image %d, level %d outside the image", xy[0],
+                                    xy[1], j, i);
+                }
+    }
+    return KAZE_OK;
+}
+
+kaze_status sg_batch_build(kaze_batch* B, const kaze_image_desc* im, const SgSpec& sp,
+                           char* base, size_t off, const std::vector<size_t>& scratch) {
+    const kaze_sg_config* c = sp.c;
+    const int n = B->n, N = B->N, P = c->probes;
+    const SgBatchLayout L = sg_batch_layout(im, n, &B->p, c);
+    if (off % 256) return fail(KAZE_ERR_WORKSPACE, "surrogate tables misaligned");
+    SgBatch* G = new SgBatch();
+    B->sg = G;  // released with the plan
+    char* sb = base + off;
+    G->bound = (float)c->bound;
+    G->probes = P;
+    G->np = n * P;
+    G->packed = static_cast<const unsigned char*>(sp.packed);
+    G->err = sp.err;
+    G->x0 = reinterpret_cast<sg::bf16*>(sb + L.x0);
+    G->xa = reinterpret_cast<sg::bf16*>(sb + L.xa);
+    G->xb = reinterpret_cast<sg::bf16*>(sb + L.xb);
+    G->delta = reinterpret_cast<float*>(sb + L.delta);
+    G->tau = reinterpret_cast<float*>(sb + L.tau);
+    G->cond = reinterpret_cast<BatchImage*>(sb + L.cond);
+    G->img = reinterpret_cast<sg::SgImage*>(sb + L.img);
+    G->full = reinterpret_cast<int2*>(sb + L.full);
+    G->n_full = L.n_full;
+    G->rects = reinterpret_cast<int4*>(sb + L.rects);
+    G->rect_img = reinterpret_cast<int*>(sb + L.rect_img);
+    G->pitems = reinterpret_cast<int2*>(sb + L.pitems);
+    G->pitem_off.assign(N, 0);
+    G->pitem_cnt.assign(N, 0);
+
+    // host image of the tables [tau, total)
+    const size_t tb = L.tau;
+    std::vector<char> host(L.total - tb, 0);
+    auto at = [&](size_t o) { return host.data() + (o - tb); };
+    float* htau = reinterpret_cast<float*>(at(L.tau));
+    BatchImage* hcond = reinterpret_cast<BatchImage*>(at(L.cond));
+    sg::SgImage* himg = reinterpret_cast<sg::SgImage*>(at(L.img));
+    int2* hfull = reinterpret_cast<int2*>(at(L.full));
+    int4* hrect = reinterpret_cast<int4*>(at(L.rects));
+    int* hrimg = reinterpret_cast<int*>(at(L.rect_img));
+    int2* hpit = reinterpret_cast<int2*>(at(L.pitems));
+    std::vector<long long> xoff(n);
+    std::vector<float*> gplane(n);
+    long long xo = 0;
+    int f = 0;
+    const int nb = hist_bins(&B->p);
+    for (int j = 0; j < n; ++j) {
+        xoff[j] = xo;
+        const sg::Geo g = sg::image_geo(im[j].W, im[j].H, sg::kConvRows);
+        xo += g.sx;
+        const int strips = (im[j].W + sg::kPairOut - 1) / sg::kPairOut;
+        for (int t = 0; t < strips * g.chunks; ++t) hfull[f++] = make_int2(j, t);
+        // the conductivity plane of the image's scratch, as batch_create lays it out
+        const Scratch sc = scratch_layout(im[j].W, im[j].H, nb, B->shape, scratch[j], false,
+                                          false, B->with_nms ? N : 0);
+        gplane[j] = reinterpret_cast<float*>(base + sc.g);
+    }
+    std::vector<int> tmp;
+    std::vector<int4> rj(std::max(1, P));
+    for (int i = 1; i < N; ++i) {
+        htau[i] = (float)B->lv[i].tau;
+        const size_t r0 = (size_t)(i - 1) * n;
+        int cnt = 0;
+        for (int j = 0; j < n; ++j) {
+            const int W = im[j].W, H = im[j].H;
+            const size_t plane = (size_t)W * H;
+            BatchImage b = batch_image(W, H);
+            b.levels = im[j].levels + plane * (i - 1);
+            b.g = gplane[j];
+            b.k = im[j].k;
+            hcond[r0 + j] = b;
+            sg::SgImage si;
+            si.xoff = xoff[j];
+            si.L = im[j].levels + plane * (i - 1);
+            si.Lnext = im[j].levels + plane * i;
+            si.g = gplane[j];
+            si.gate = sp.err + (size_t)j * N + i;
+            si.W = W;
+            si.H = H;
+            himg[r0 + j] = si;
+            for (int q = 0; q < P; ++q) {
+                const int* xy = sp.probe_xy + (((size_t)j * N + i) * P + q) * 2;
+                rj[q] = make_int4(xy[0], xy[1], std::min(c->probe_size, W - xy[0]),
+                                  std::min(c->probe_size, H - xy[1]));
+                hrect[(size_t)(i - 1) * G->np + (size_t)j * P + q] = rj[q];
+                hrimg[(size_t)(i - 1) * G->np + (size_t)j * P + q] = j;
+            }
+            if (P > 0) {
+                sg_probe_items(sg::image_geo(W, H, kProbeRows), rj.data(), P, tmp);
+                if (cnt + (int)tmp.size() > L.max_pitems)
+                    return fail(KAZE_ERR_UNSUPPORTED, "probe windows need more than %d items",
+                                L.max_pitems);
+                for (int v : tmp) hpit[(size_t)(i - 1) * L.max_pitems + cnt++] = make_int2(j, v);
+            }
+        }
+        G->pitem_off[i] = (i - 1) * L.max_pitems;
+        G->pitem_cnt[i] = cnt;
+    }
+    hipError_t e = hipMemset(sb + L.x0, 0, L.delta - L.x0);  // zero rings of the activations
+    if (e == hipSuccess)
+        e = hipMemcpy(sb + tb, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess)
+        return fail(KAZE_ERR_HIP, "surrogate batch tables: %s", hipGetErrorString(e));
+    return KAZE_OK;
+}
+
+// The six convolutions of level i over a batched work list: layer by layer
+// (probe items, rows of kProbeRows) or as three fused pairs (every image);
+// with gate non-NULL each image runs only where its probe error is <= bound.
+kaze_status sg_batch_chain(const SgBatch& G, int i, const sg::SgWork& w, bool fused,
+                           const float* gate, hipStream_t s) {
+    const sg::PackLayout P = sg::pack_layout();
+    sg::Geo geo;
+    memset(&geo, 0, sizeof(geo));
+    if (fused) {
+        geo.R = sg::kConvRows;
+        sg::bf16* buf[3] = {G.x0, G.xa, G.xb};
+        for (int pr = 0; pr < 3; ++pr) {
+            sg::Conv2Args c;
+            memset(&c, 0, sizeof(c));
+            const int la = 2 * pr, lb = la + 1;
+            c.in = buf[pr];
+            c.wa = reinterpret_cast<const sg::bf16x8*>(G.packed + P.fwd[la]);
+            c.ba = reinterpret_cast<const float*>(G.packed + P.bias[la]);
+            c.wb = reinterpret_cast<const sg::bf16x8*>(G.packed + P.fwd[lb]);
+            c.bb = reinterpret_cast<const float*>(G.packed + P.bias[lb]);
+            c.gate = gate;
+            c.bound = G.bound;
+            c.bw = w;
+            if (pr == 0) {
+                c.tauw = reinterpret_cast<const float*>(G.packed + P.tauw);
+                c.tau = G.tau + i;
+            }
+            if (pr < 2) c.out = buf[pr + 1];  // fout and base come from the image table
+            KZ_LAUNCH(pr == 0 ? K_SG_CONV1 : (pr == 1 ? K_SG_CONV : K_SG_CONV6), s,
+                      sg::launch_conv2(pr == 0 ? 8 : 32, pr < 2 ? 2 : 1, c, geo, s));
+        }
+        return KAZE_OK;
+    }
+    geo.R = kProbeRows;
+    sg::bf16* buf[sg::kLayers] = {G.x0, G.xa, G.xb, G.xa, G.xb, G.xa};
+    for (int l = 0; l < sg::kLayers; ++l) {
+        sg::ConvArgs a;
+        memset(&a, 0, sizeof(a));
+        a.in = buf[l];
+        a.wfrag = reinterpret_cast<const sg::bf16x8*>(G.packed + P.fwd[l]);
+        a.bias = reinterpret_cast<const float*>(G.packed + P.bias[l]);
+        a.gate = gate;
+        a.bound = G.bound;
+        a.bw = w;
+        if (l == 0) {
+            a.tauw = reinterpret_cast<const float*>(G.packed + P.tauw);
+            a.tau = G.tau + i;
+        }
+        if (l < sg::kLayers - 1) {
+            a.out = buf[l + 1];
+            KZ_LAUNCH(l == 0 ? K_SG_CONV1 : K_SG_CONV, s,
+                      sg::launch_conv(l == 0 ? 8 : 32, 2, sg::EPI_RELU, l == 0, a, geo, s));
+        } else {
+            KZ_LAUNCH(K_SG_CONV6, s, sg::launch_conv(32, 1, sg::EPI_OUT, false, a, geo, s));
+        }
+    }
+    return KAZE_OK;
+}
+
+// The N-1 level steps of a surrogate batch: per level the conductivity, the
+// network input, the network on the probe windows and the exact solves
+// there, then the network on every accepted image and AOS on every rejected
+// one (the per-level descriptors carry the image's error word as gate).
+kaze_status sg_batch_levels(const kaze_batch& B, hipStream_t s) {
+    const SgBatch& G = *B.sg;
+    const kaze_params* p = &B.p;
+    const int n = B.n, N = B.N;
+    const Taps tc = gauss_taps(p->sigma_cond);
+    const int gmode = p->diffusivity == KAZE_G2 ? 0 : 1;
+    const BatchImage b0 = batch_image(0, 0);
+    ImageDesc a0;
+    memset(&a0, 0, sizeof(a0));
+    KZ_LAUNCH(K_FILL, s, launch_fill_u32(reinterpret_cast<unsigned*>(G.err), n * N, 0u, s));
+    for (int i = 1; i < N; ++i) {
+        const size_t r0 = (size_t)(i - 1) * n;
+        const float tau = (float)B.lv[i].tau;
+        const ImgWork ct{G.cond + r0, B.d_aos, B.n_aos};
+        KZ_LAUNCH(K_COND, s, launch_cond(b0, ct, tc, 1.f, gmode, kAosShapeTY[B.shape], s));
+        const sg::SgImage* si = G.img + r0;
+        KZ_LAUNCH(K_SG_PACK, s, sg::launch_pack_input_batch(si, n, G.x0, s));
+        const ImageDesc* lvl = B.d_lvl + r0;  // one step per level
+        kaze_status st;
+        if (G.probes > 0) {
+            const sg::SgWork pw{si, G.pitems + G.pitem_off[i], G.pitem_cnt[i]};
+            if ((st = sg_batch_chain(G, i, pw, false, nullptr, s)) != KAZE_OK) return st;
+            const int4* r = G.rects + (size_t)(i - 1) * G.np;
+            const int* ri = G.rect_img + (size_t)(i - 1) * G.np;
+            KZ_LAUNCH(K_SG_PROBE, s, launch_aos_probe(a0, r, G.np, tau, G.delta, s, lvl, ri));
+            KZ_LAUNCH(K_SG_PROBE, s,
+                      launch_probe_err(nullptr, nullptr, 0, r, G.np, G.delta, nullptr, s, lvl, ri));
+        }
+        const sg::SgWork fw{si, G.full, G.n_full};
+        if ((st = sg_batch_chain(G, i, fw, true, G.err, s)) != KAZE_OK) return st;
+        const AosWork at{lvl, B.d_aos, B.n_aos};
+        const AosWork al{lvl, B.d_lines, B.n_lines};
+        // g of L_{i-1} is already in every image's plane: the step reads it
+        st = aos_step(a0, at, al, B.shape, tc, tau, false, gmode, 1.f, s, B.iface_m);
+        if (st != KAZE_OK) return st;
+    }
+    return KAZE_OK;
+}
+
+// Argument checks of the single-image scale space; *need = scratch bytes.
+kaze_status check_scale_space_args(const float* img, int W, int H, int ld_img,
+                                   const kaze_params* p, const float* levels, const float* k_out,
+                                   size_t* need) {
+    kaze_status st = check_params(p);
+    if (st != KAZE_OK) return st;
+    if ((st = check_size(W, H)) != KAZE_OK) return st;
+    if (!img || !levels || !k_out)
+        return fail(KAZE_ERR_INVALID_ARG, "img, levels and k_out must be non-NULL");
+    if (ld_img < W) return fail(KAZE_ERR_INVALID_ARG, "ld_img (%d) < W (%d)", ld_img, W);
+    if (!aligned(img, 4) || !aligned(levels, 4) || !aligned(k_out, 4))
+        return fail(KAZE_ERR_INVALID_ARG, "float buffers must be 4-byte aligned");
+    *need = scratch_layout(W, H, hist_bins(p), 0, 0, p->scheme == KAZE_FED, p->substeps > 1).total;
+    return KAZE_OK;
+}
+
+// a1-a5 for one image with its scratch at base (scratch_layout, validated).
+kaze_status scale_space_launches(const float* img, int W, int H, int ld_img,
+                                 const kaze_params* p, float* levels, float* k_out, char* base,
+                                 hipStream_t s) {
+    const bool fed = p->scheme == KAZE_FED;
+    const int m = p->substeps;
+    const Scratch w = scratch_layout(W, H, hist_bins(p), 0, 0, fed, m > 1);
+    BatchImage b = batch_image(W, H);
+    b.img = img;
+    b.ld = ld_img;
+    b.levels = levels;
+    b.g = reinterpret_cast<float*>(base + w.g);
+    b.hist = reinterpret_cast<unsigned*>(base + w.hist);
+    b.hmax = reinterpret_cast<unsigned*>(base + w.hmax);
+    b.k = k_out;
+    const ImgWork none{nullptr, nullptr, 0};
+    kaze_status st = base_and_k(b, none, none, none, kAosShapeTY[0], none, p, s);
+    if (st != KAZE_OK) return st;
+
+    std::vector<Level> lv;
+    schedule(p, lv);
+    const size_t plane = (size_t)W * H;
+    const Taps tc = gauss_taps(p->sigma_cond);
+    const int gmode = p->diffusivity == KAZE_G2 ? 0 : 1;
+    ImageDesc d = aos_desc(W, H, 0, base, w, k_out);
+    const AosWork anone{nullptr, nullptr, 0};
+    float* mid = reinterpret_cast<float*>(base + w.sub);
+    for (size_t i = 1; i < lv.size(); ++i) {
+        // m sub-steps from level i-1 to level i, alternating between the
+        // level's plane and the sub-step plane so that the last one writes
+        // the level
+        const double tau = lv[i].tau / m;
+        const float* src = levels + plane * (i - 1);
+        float* out = levels + plane * i;
+        for (int q = 0; q < m; ++q) {
+            float* dst = ((m - 1 - q) % 2 == 0) ? out : mid;
+            d.L = src;
+            d.Lnext = dst;
+            if (fed) {
+                BatchImage bc = b;
+                bc.levels = const_cast<float*>(src);  // conductivity of the step's start
+                KZ_LAUNCH(K_COND, s, launch_cond(bc, none, tc, 1.f, gmode, kAosShapeTY[0], s));
+                st = fed_cycle(src, b.g, dst, reinterpret_cast<float*>(base + w.tmp), W, H, tau, s);
+            } else {
+                st = aos_step(d, anone, anone, 0, tc, (float)tau, true, gmode, 1.f, s);
+            }
+            if (st != KAZE_OK) return st;
+            src = dst;
+        }
+    }
+    return KAZE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -976,67 +1383,14 @@ size_t kaze_workspace_bytes(int W, int H, const kaze_params* p) {
 kaze_status kaze_build_scale_space(const float* img, int W, int H, int ld_img,
                                    const kaze_params* p, float* levels, float* k_out, void* ws,
                                    size_t ws_bytes, void* stream) {
-    kaze_status st = check_params(p);
+    size_t need = 0;
+    kaze_status st = check_scale_space_args(img, W, H, ld_img, p, levels, k_out, &need);
     if (st != KAZE_OK) return st;
-    if ((st = check_size(W, H)) != KAZE_OK) return st;
-    if (!img || !levels || !k_out)
-        return fail(KAZE_ERR_INVALID_ARG, "img, levels and k_out must be non-NULL");
-    if (ld_img < W) return fail(KAZE_ERR_INVALID_ARG, "ld_img (%d) < W (%d)", ld_img, W);
-    if (!aligned(img, 4) || !aligned(levels, 4) || !aligned(k_out, 4))
-        return fail(KAZE_ERR_INVALID_ARG, "float buffers must be 4-byte aligned");
-    const bool fed = p->scheme == KAZE_FED;
-    const int m = p->substeps;
-    const Scratch w = scratch_layout(W, H, hist_bins(p), 0, 0, fed, m > 1);
-    if (!ws || !aligned(ws, 256) || ws_bytes < w.total)
+    if (!ws || !aligned(ws, 256) || ws_bytes < need)
         return fail(KAZE_ERR_WORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
-                    w.total, ws_bytes);
-
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    char* base = static_cast<char*>(ws);
-    BatchImage b = batch_image(W, H);
-    b.img = img;
-    b.ld = ld_img;
-    b.levels = levels;
-    b.g = reinterpret_cast<float*>(base + w.g);
-    b.hist = reinterpret_cast<unsigned*>(base + w.hist);
-    b.hmax = reinterpret_cast<unsigned*>(base + w.hmax);
-    b.k = k_out;
-    const ImgWork none{nullptr, nullptr, 0};
-    st = base_and_k(b, none, none, none, kAosShapeTY[0], none, p, s);
-    if (st != KAZE_OK) return st;
-
-    std::vector<Level> lv;
-    schedule(p, lv);
-    const size_t plane = (size_t)W * H;
-    const Taps tc = gauss_taps(p->sigma_cond);
-    const int gmode = p->diffusivity == KAZE_G2 ? 0 : 1;
-    ImageDesc d = aos_desc(W, H, 0, base, w, k_out);
-    const AosWork anone{nullptr, nullptr, 0};
-    float* mid = reinterpret_cast<float*>(base + w.sub);
-    for (size_t i = 1; i < lv.size(); ++i) {
-        // m sub-steps from level i-1 to level i, alternating between the
-        // level's plane and the sub-step plane so that the last one writes
-        // the level
-        const double tau = lv[i].tau / m;
-        const float* src = levels + plane * (i - 1);
-        float* out = levels + plane * i;
-        for (int q = 0; q < m; ++q) {
-            float* dst = ((m - 1 - q) % 2 == 0) ? out : mid;
-            d.L = src;
-            d.Lnext = dst;
-            if (fed) {
-                BatchImage bc = b;
-                bc.levels = const_cast<float*>(src);  // conductivity of the step's start
-                KZ_LAUNCH(K_COND, s, launch_cond(bc, none, tc, 1.f, gmode, kAosShapeTY[0], s));
-                st = fed_cycle(src, b.g, dst, reinterpret_cast<float*>(base + w.tmp), W, H, tau, s);
-            } else {
-                st = aos_step(d, anone, anone, 0, tc, (float)tau, true, gmode, 1.f, s);
-            }
-            if (st != KAZE_OK) return st;
-            src = dst;
-        }
-    }
-    return KAZE_OK;
+                    need, ws_bytes);
+    return scale_space_launches(img, W, H, ld_img, p, levels, k_out, static_cast<char*>(ws),
+                                static_cast<hipStream_t>(stream));
 }
 
 kaze_status kaze_conductivity(const float* L, int W, int H, const kaze_params* p, double k,
@@ -1280,6 +1634,7 @@ kaze_status kaze_batch_destroy(kaze_batch* b) {
         if (x) (void)hipGraphExecDestroy(x);
     for (hipEvent_t ev : b->ev) (void)hipEventDestroy(ev);
     if (b->side) (void)hipStreamDestroy(b->side);
+    delete b->sg;
     delete b;
     return KAZE_OK;
 }
@@ -1339,7 +1694,7 @@ kaze_status kaze_batch_autotune(const kaze_image_desc* images, int n, const kaze
 // ------------------------------------------------------ surrogate scale space
 kaze_status kaze_sg_default_config(kaze_sg_config* c) {
     if (!c) return fail(KAZE_ERR_INVALID_ARG, "config pointer is NULL");
-    c->bound = 2.5e-4;
+    c->bound = 6.6e-5;  // 15 steps x 6.6e-5 <= 1e-3
     c->probes = 4;
     c->probe_size = 32;
     c->aos_shape = -1;
@@ -1362,6 +1717,25 @@ kaze_status kaze_sg_scale_space_destroy(kaze_sg_scale_space* S) {
         if (x) (void)hipGraphExecDestroy(x);
     delete S;
     return KAZE_OK;
+}
+
+size_t kaze_sg_batch_workspace_bytes(const kaze_image_desc* images, int n, const kaze_params* p,
+                                     const kaze_sg_config* c) {
+    if (check_sg_config(c) != KAZE_OK) return 0;
+    const int shape = c->aos_shape >= 0 ? c->aos_shape : 0;
+    if (check_batch(images, n, p, shape) != KAZE_OK) return 0;
+    return batch_layout(images, n, p, shape).total + sg_batch_bytes(images, n, p, c);
+}
+
+kaze_status kaze_sg_batch_create(const kaze_image_desc* images, int n, const kaze_params* p,
+                                 const kaze_sg_config* c, const void* packed, const int* probe_xy,
+                                 float* err, void* ws, size_t ws_bytes, kaze_batch** out) {
+    if (out) *out = nullptr;
+    const kaze_status st = check_sg_config(c);
+    if (st != KAZE_OK) return st;
+    const SgSpec sp{c, packed, probe_xy, err};
+    return batch_create(images, n, p, c->aos_shape >= 0 ? c->aos_shape : 0, ws, ws_bytes, out,
+                        &sp);
 }
 
 kaze_status kaze_sg_scale_space_create(const kaze_image_desc* im, const kaze_params* p,

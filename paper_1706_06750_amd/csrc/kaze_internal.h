@@ -370,11 +370,16 @@ hipError_t launch_aos_recover(const ImageDesc& d0, const AosWork& w, int shape, 
 // increments [h][w] then the column increments [h][w] (pitch kProbeMax).
 // probe_err then compares L + (delta_x + delta_y)/2 with cand on every
 // window and raises *err (float bits, atomic max; NaN counts as +inf).
+// Batches pass pdesc and rect_img: window p then lies in the image
+// pdesc[rect_img[p]], whose L, g, Lnext (the candidate), W, H and gate (the
+// error word) replace the single-image arguments.
 constexpr int kProbeMax = 32;
 hipError_t launch_aos_probe(const ImageDesc& d, const int4* rects, int nprobes, float tau,
-                            float* delta, hipStream_t s);
+                            float* delta, hipStream_t s, const ImageDesc* pdesc = nullptr,
+                            const int* rect_img = nullptr);
 hipError_t launch_probe_err(const float* L, const float* cand, int W, const int4* rects,
-                            int nprobes, const float* delta, unsigned* err, hipStream_t s);
+                            int nprobes, const float* delta, unsigned* err, hipStream_t s,
+                            const ImageDesc* pdesc = nullptr, const int* rect_img = nullptr);
 
 // a6: det of the levels lev0 .. lev1-1 (items: image, det tile of 64 x 32).
 hipError_t launch_det(const BatchImage& d0, const ImgWork& w, int lev0, int lev1,

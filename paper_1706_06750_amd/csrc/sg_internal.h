@@ -36,6 +36,7 @@ constexpr int kStrip = 16;              // output pixels per MFMA column block
 constexpr int kWgStrip = 32;            // pixels per weight-gradient K block
 constexpr int kConvRows = 32;           // output rows per wave of the convolutions
 constexpr int kProbeHalo = 6;           // receptive-field radius of the six layers
+constexpr int kPairOut = 112;           // output columns per block of a fused layer pair
 
 // Offsets of layer l's weights and biases in the flat FP32 parameter vector
 // (weights [co][ci][3][3], then biases [co]).
@@ -67,6 +68,42 @@ struct Geo {
 };
 Geo make_geo(int n, int W, int H, int R);
 
+// Inference geometry of one image (the fields the forward kernels read).
+__host__ __device__ inline Geo image_geo(int W, int H, int R) {
+    Geo g;
+    g.n = 1;
+    g.W = W;
+    g.H = H;
+    g.R = R;
+    g.strips = (W + kStrip - 1) / kStrip;
+    g.chunks = (H + R - 1) / R;
+    g.pw = W + 2;
+    g.sx = (long long)(H + 2) * (W + 2);
+    g.PX = g.PZ = 0;
+    return g;
+}
+
+// One image of a batched forward launch (images of different sizes): its
+// planes for the level being produced and the offset of its padded NHWC
+// activations inside the batch's shared activation buffers.
+struct SgImage {
+    long long xoff;     // padded pixels of the images before it
+    const float* L;     // previous level, [H][W]
+    float* Lnext;       // the level produced: L + f
+    const float* g;     // conductivity of L, [H][W]
+    const float* gate;  // its probe error for this level (gated launches)
+    int W, H;
+};
+
+// Work list of a batched launch: item t is (image, local item), the local
+// item numbered as in the single-image launch of that image's geometry.
+// imgs == NULL: a single-image launch over the Geo passed with it.
+struct SgWork {
+    const SgImage* imgs;
+    const int2* items;
+    int count;
+};
+
 enum Epi { EPI_RELU = 0, EPI_MASK = 1, EPI_OUT = 2 };
 
 struct ConvArgs {
@@ -84,6 +121,11 @@ struct ConvArgs {
     int nitems;
     const float* gate;    // optional: the launch runs only if *gate <= bound
     float bound;
+    // batched inference (bw.imgs set): items, geometry and planes per image;
+    // in, out index the shared activation buffers at each image's offset,
+    // fout and base are the image's Lnext and L; with gate non-NULL every
+    // image runs only if its own SgImage::gate holds a value <= bound
+    SgWork bw;
 };
 
 hipError_t launch_conv(int cin, int mb, int epi, bool tau_term, const ConvArgs& a,
@@ -106,11 +148,15 @@ struct Conv2Args {
     const float* base;    // MBB == 1: added to f, or NULL
     const float* gate;    // optional: run only if *gate <= bound
     float bound;
+    SgWork bw;            // batched inference, as in ConvArgs
 };
 
 hipError_t launch_conv2(int cina, int mbb, const Conv2Args& a, const Geo& g, hipStream_t s);
 hipError_t launch_pack_input(const float* L, const float* gc, const float* tau, bf16* x0,
                              bf16* x0p, const Geo& g, hipStream_t s);
+// Layer-1 input of every image of a batch (L and g of its SgImage entry)
+// into the shared NHWC8 buffer x0 at the image's offset.
+hipError_t launch_pack_input_batch(const SgImage* imgs, int n, bf16* x0, hipStream_t s);
 hipError_t launch_loss(const float* f, const float* L, const float* Ln, const float* wts, bf16* dz6,
                        bf16* dz6p, float* lpart, int nblocks, const Geo& g, hipStream_t s);
 int loss_blocks(const Geo& g);

@@ -111,19 +111,33 @@ __device__ inline void conv_epilogue(const ConvArgs& a, const Geo& g, int s, int
 template <int CIN, int MB, int EPI, bool TAU>
 __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a, Geo g) {
     constexpr int KS = ConvK<CIN>::KS;
-    if (a.gate && !(*a.gate <= a.bound)) return;  // whole grid
     const int lane = threadIdx.x & 63;
-    const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int per = g.strips * g.chunks;
+    const int item = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
     int s, rem;
-    if (a.items) {
-        if (item >= a.nitems) return;  // whole wave
+    if (a.bw.imgs) {  // batched inference: this wave's image and its planes
+        if (item >= a.bw.count) return;  // whole wave
+        const int2 it = a.bw.items[item];
+        const SgImage im = a.bw.imgs[it.x];
+        if (a.gate && !(*im.gate <= a.bound)) return;  // whole wave
+        g = image_geo(im.W, im.H, g.R);
+        a.in += im.xoff * CIN;
+        if (a.out) a.out += im.xoff * kCh;
+        a.fout = im.Lnext;
+        a.base = im.L;
         s = 0;
-        rem = a.items[item];
+        rem = it.y;
     } else {
-        if (item >= g.n * per) return;  // whole wave
-        s = item / per;
-        rem = item - s * per;
+        if (a.gate && !(*a.gate <= a.bound)) return;  // whole grid
+        const int per = g.strips * g.chunks;
+        if (a.items) {
+            if (item >= a.nitems) return;  // whole wave
+            s = 0;
+            rem = a.items[item];
+        } else {
+            if (item >= g.n * per) return;  // whole wave
+            s = item / per;
+            rem = item - s * per;
+        }
     }
     const int chunk = rem / g.strips;
     const int strip = rem - chunk * g.strips;
@@ -242,7 +256,6 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a, Geo g) {
 // value is computed by the same MFMA sequence as in conv_kernel, so the
 // results are bitwise those of two conv_kernel launches.
 
-constexpr int kPairOut = 112;           // output columns per block
 constexpr int kPairMid = 128;           // layer-a columns per block (8 blocks)
 constexpr int kPairPix = 40;            // LDS pitch of one pixel in BF16 (80 B)
 constexpr int kPairThreads = 768;       // 8 A waves + 4 B waves
@@ -250,12 +263,34 @@ constexpr int kPairThreads = 768;       // 8 A waves + 4 B waves
 template <int CINA, int MBB, bool TAU>
 __global__ __launch_bounds__(kPairThreads) void conv2_kernel(Conv2Args a, Geo g) {
     constexpr int KSA = CINA == 32 ? 9 : 3;
-    if (a.gate && !(*a.gate <= a.bound)) return;  // whole grid
     __shared__ __align__(16) bf16 ring[4][kPairMid * kPairPix];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int j = lane & 15, q = lane >> 4;
-    const int s = blockIdx.y;
-    const int strip = (int)blockIdx.x % g.strips, chunk = (int)blockIdx.x / g.strips;
+    int s, strip, chunk;
+    if (a.bw.imgs) {  // batched inference: this block's image and its planes
+        const int t = blockIdx.x;
+        if (t >= a.bw.count) return;  // whole block
+        const int2 it = a.bw.items[t];
+        const SgImage im = a.bw.imgs[it.x];
+        if (a.gate && !(*im.gate <= a.bound)) return;  // whole block
+        g = image_geo(im.W, im.H, g.R);
+        g.strips = (im.W + kPairOut - 1) / kPairOut;
+        a.in += im.xoff * CINA;
+        if constexpr (MBB == 2) {
+            a.out += im.xoff * kCh;
+        } else {
+            a.fout = im.Lnext;
+            a.base = im.L;
+        }
+        s = 0;
+        strip = it.y % g.strips;
+        chunk = it.y / g.strips;
+    } else {
+        if (a.gate && !(*a.gate <= a.bound)) return;  // whole grid
+        s = blockIdx.y;
+        strip = (int)blockIdx.x % g.strips;
+        chunk = (int)blockIdx.x / g.strips;
+    }
     const int x0 = strip * kPairOut, y0 = chunk * g.R, y1 = min(g.H, y0 + g.R);
     const int steps = (y1 - y0) + 3;
 
@@ -459,6 +494,27 @@ __global__ __launch_bounds__(kPairThreads) void conv2_kernel(Conv2Args a, Geo g)
 // ------------------------------------------------------------ input packing
 // NHWC8: (L_hi, L_lo, L_hi, g_hi, g_lo, g_hi, 0, 0); planar (weight
 // gradient of layer 1): (L_hi, L_lo, g_hi, g_lo, tau_hi, tau_lo, 0, 0).
+__device__ inline bf16x8 input_split(float l, float c) {
+    const bf16 lh = (bf16)l, ch = (bf16)c;
+    const bf16 ll = (bf16)(l - (float)lh), cl = (bf16)(c - (float)ch);
+    const bf16 z = (bf16)0.f;
+    return bf16x8{lh, ll, lh, ch, cl, ch, z, z};
+}
+
+// Batched layer-1 input: blockIdx.y is the image; its pixels are walked with
+// a grid stride over blockIdx.x.
+__global__ __launch_bounds__(256) void pack_input_batch_kernel(const SgImage* __restrict__ imgs,
+                                                               bf16* __restrict__ x0) {
+    const SgImage im = imgs[blockIdx.y];
+    const size_t per = (size_t)im.W * im.H;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < per;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int y = (int)(i / im.W), x = (int)(i - (size_t)y * im.W);
+        const size_t pix = (size_t)im.xoff + (size_t)(y + 1) * (im.W + 2) + (x + 1);
+        *reinterpret_cast<bf16x8*>(x0 + pix * 8) = input_split(im.L[i], im.g[i]);
+    }
+}
+
 __global__ void pack_input_kernel(const float* __restrict__ L, const float* __restrict__ gc,
                                   const float* __restrict__ tau, bf16* __restrict__ x0,
                                   bf16* __restrict__ x0p, Geo g) {
@@ -471,10 +527,8 @@ __global__ void pack_input_kernel(const float* __restrict__ L, const float* __re
     const float l = L[i], c = gc[i];
     const bf16 lh = (bf16)l, ch = (bf16)c;
     const bf16 ll = (bf16)(l - (float)lh), cl = (bf16)(c - (float)ch);
-    const bf16 z = (bf16)0.f;
-    bf16x8 v = {lh, ll, lh, ch, cl, ch, z, z};
     const size_t pix = (size_t)s * g.sx + (size_t)(y + 1) * g.pw + (x + 1);
-    *reinterpret_cast<bf16x8*>(x0 + pix * 8) = v;
+    *reinterpret_cast<bf16x8*>(x0 + pix * 8) = input_split(l, c);
     if (x0p) {
         const float tp = tau[s] / kTauRef;
         const bf16 th = (bf16)tp, tl = (bf16)(tp - (float)th);
@@ -847,7 +901,7 @@ Geo make_geo(int n, int W, int H, int R) {
 
 hipError_t launch_conv(int cin, int mb, int epi, bool tau_term, const ConvArgs& a, const Geo& g,
                        hipStream_t s) {
-    const int items = a.items ? a.nitems : g.n * g.strips * g.chunks;
+    const int items = a.bw.imgs ? a.bw.count : (a.items ? a.nitems : g.n * g.strips * g.chunks);
     if (items <= 0) return hipSuccess;
     const dim3 grid((items + 3) / 4), block(256);
     if (cin == 8 && mb == 2 && epi == EPI_RELU && tau_term)
@@ -870,7 +924,9 @@ hipError_t launch_conv2(int cina, int mbb, const Conv2Args& a, const Geo& g, hip
     Geo gg = g;
     gg.strips = strips;
     gg.chunks = (g.H + g.R - 1) / g.R;
-    const dim3 grid(strips * gg.chunks, g.n), block(kPairThreads);
+    if (a.bw.imgs && a.bw.count <= 0) return hipSuccess;
+    const dim3 grid = a.bw.imgs ? dim3(a.bw.count) : dim3(strips * gg.chunks, g.n);
+    const dim3 block(kPairThreads);
     if (cina == 8 && mbb == 2)
         hipLaunchKernelGGL((conv2_kernel<8, 2, true>), grid, block, 0, s, a, gg);
     else if (cina == 32 && mbb == 2)
@@ -887,6 +943,12 @@ hipError_t launch_pack_input(const float* L, const float* gc, const float* tau, 
     const size_t total = (size_t)g.n * g.W * g.H;
     hipLaunchKernelGGL(pack_input_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, L, gc,
                        tau, x0, x0p, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_input_batch(const SgImage* imgs, int n, bf16* x0, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pack_input_batch_kernel, dim3(1024, n), dim3(256), 0, s, imgs, x0);
     return hipGetLastError();
 }
 

@@ -426,10 +426,11 @@ class KazeBatch:
     before ``run()``.  ``shape`` selects the row/column tile shape (0-3);
     ``shape="auto"`` runs the library's autotuner, caching the choice in the
     JSON file ``tune_cache`` when given (keyed by GPU architecture and the
-    list of sizes)."""
+    list of sizes).  With ``ld_pad`` > 0 each input is a view of W columns
+    of a [H][W + ld_pad] allocation (row pitch W + ld_pad)."""
 
     def __init__(self, sizes, params=None, capacity=1 << 14, shape="auto", tune_cache=None,
-                 device="cuda", with_detector=True):
+                 device="cuda", with_detector=True, ld_pad=0):
         import torch
         self.p = params if params is not None else kaze_default_params()
         self.N = kaze_num_levels(self.p)
@@ -438,7 +439,7 @@ class KazeBatch:
         self.inputs, self.levels, self.det, self.k, self.kps, self.count = [], [], [], [], [], []
         descs = []
         for W, H in self.sizes:
-            x = torch.zeros((H, W), dtype=torch.float32, device=dev)
+            x = torch.zeros((H, W + int(ld_pad)), dtype=torch.float32, device=dev)[:, :W]
             lv = torch.empty((self.N, H, W), dtype=torch.float32, device=dev)
             dt = torch.empty_like(lv) if with_detector else None
             k = torch.empty(1, dtype=torch.float32, device=dev)
@@ -450,7 +451,7 @@ class KazeBatch:
             self.k.append(k)
             self.kps.append(kp)
             self.count.append(ct)
-            descs.append(kaze_image_desc(x.data_ptr(), W, H, W, lv.data_ptr(),
+            descs.append(kaze_image_desc(x.data_ptr(), W, H, x.stride(0), lv.data_ptr(),
                                          dt.data_ptr() if dt is not None else None, k.data_ptr(),
                                          kp.data_ptr() if with_detector else None,
                                          capacity if with_detector else 0,

@@ -17,6 +17,7 @@ EXPORTS = (
     "kaze_sg_forward", "kaze_sg_gradients", "kaze_sg_adam",
     "kaze_sg_default_config", "kaze_sg_scale_space_workspace_bytes",
     "kaze_sg_scale_space_create", "kaze_sg_scale_space_run", "kaze_sg_scale_space_destroy",
+    "kaze_sg_batch_workspace_bytes", "kaze_sg_batch_create",
 )
 
 
@@ -45,6 +46,11 @@ for _name, (_res, _args) in {
                                           _sz, ctypes.POINTER(_vp)]),
     "kaze_sg_scale_space_run": (_i32, [_vp, _i32, _vp]),
     "kaze_sg_scale_space_destroy": (_i32, [_vp]),
+    "kaze_sg_batch_workspace_bytes": (_sz, [_vp, _i32, ctypes.POINTER(kaze_params),
+                                            ctypes.POINTER(kaze_sg_config)]),
+    "kaze_sg_batch_create": (_i32, [_vp, _i32, ctypes.POINTER(kaze_params),
+                                    ctypes.POINTER(kaze_sg_config), _vp, _vp, _vp, _vp, _sz,
+                                    ctypes.POINTER(_vp)]),
 }.items():
     _fn = getattr(lib, _name)
     _fn.restype = _res
@@ -204,6 +210,27 @@ def kaze_sg_scale_space_destroy(handle):
     _check(lib.kaze_sg_scale_space_destroy(handle))
 
 
+def kaze_sg_batch_workspace_bytes(descs, p, c) -> int:
+    arr = (kaze_image_desc * len(descs))(*descs)
+    return int(lib.kaze_sg_batch_workspace_bytes(arr, len(descs), ctypes.byref(p),
+                                                 ctypes.byref(c)))
+
+
+def kaze_sg_batch_create(descs, p, c, packed, probe_xy, err, ws, ws_bytes):
+    """probe_xy: (n, N, probes, 2) int32 corners, or None with no probes."""
+    arr = (kaze_image_desc * len(descs))(*descs)
+    h = _vp()
+    pxy = None
+    if probe_xy is not None:
+        import numpy as np
+        pa = np.ascontiguousarray(probe_xy, dtype=np.int32)
+        pxy = pa.ctypes.data_as(_vp)
+    _check(lib.kaze_sg_batch_create(arr, len(descs), ctypes.byref(p), ctypes.byref(c),
+                                    _ptr(packed), pxy, _ptr(err), _ptr(ws), ws_bytes,
+                                    ctypes.byref(h)))
+    return h.value
+
+
 def probe_windows(W, H, N, probes, size, seed):
     """Seeded uniform top-left corners of the probe windows, [N][probes][2]
     (level 0 unused)."""
@@ -282,6 +309,106 @@ class SurrogateScaleSpace:
     def close(self):
         if self.handle:
             kaze_sg_scale_space_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SurrogateBatch:
+    """Surrogate scale space of many images of different sizes in one plan
+    (kaze_sg_batch_create; run with kaze_batch_run).  ``inputs[j]`` is image
+    j's input [H][W] to fill before ``run()``; ``err`` is the (n, N) table of
+    probe errors each run writes (image j used the surrogate for level i iff
+    err[j, i] <= bound).  Probe windows of image j are drawn with seed
+    ``probe_seed + j``."""
+
+    def __init__(self, sizes, weights: Weights, config=None, params=None, probe_seed=0,
+                 with_detector=True, capacity=1 << 14):
+        import numpy as np
+        import torch
+        from .kaze import kaze_batch_properties
+        self.p = params if params is not None else kaze_default_params()
+        self.c = config if config is not None else kaze_sg_default_config()
+        self.N = kaze_num_levels(self.p)
+        self.sizes = [(int(w), int(h)) for w, h in sizes]
+        self.weights = weights
+        self.capacity = int(capacity) if with_detector else 0
+        dev = "cuda"
+        self.inputs, self.levels, self.det, self.k, self.kps, self.count = [], [], [], [], [], []
+        descs = []
+        for W, H in self.sizes:
+            x = torch.zeros((H, W), dtype=torch.float32, device=dev)
+            lv = torch.empty((self.N, H, W), dtype=torch.float32, device=dev)
+            dt = torch.empty_like(lv) if with_detector else None
+            k = torch.empty(1, dtype=torch.float32, device=dev)
+            kp = torch.empty((max(self.capacity, 1), 4), dtype=torch.int32, device=dev)
+            ct = torch.zeros(1, dtype=torch.int32, device=dev) if with_detector else None
+            self.inputs.append(x)
+            self.levels.append(lv)
+            self.det.append(dt)
+            self.k.append(k)
+            self.kps.append(kp)
+            self.count.append(ct)
+            d = kaze_image_desc()
+            d.img, d.W, d.H, d.ld_img = x.data_ptr(), W, H, W
+            d.levels, d.k = lv.data_ptr(), k.data_ptr()
+            d.det = dt.data_ptr() if with_detector else None
+            d.kps = kp.data_ptr() if with_detector else None
+            d.capacity = self.capacity
+            d.count = ct.data_ptr() if with_detector else None
+            descs.append(d)
+        self.descs = descs
+        n = len(self.sizes)
+        self.err = torch.zeros((n, self.N), dtype=torch.float32, device=dev)
+        P = self.c.probes
+        if P > 0:
+            self.probe_xy = np.stack([probe_windows(W, H, self.N, P, self.c.probe_size,
+                                                    probe_seed + j)
+                                      for j, (W, H) in enumerate(self.sizes)])
+        else:
+            self.probe_xy = None
+        nbytes = kaze_sg_batch_workspace_bytes(descs, self.p, self.c)
+        if nbytes == 0:
+            raise KazeError(-1, "surrogate batch sizes, parameters or config are invalid")
+        self.ws_bytes = nbytes
+        self.ws = _device_bytes(nbytes)
+        torch.cuda.synchronize()
+        self.handle = kaze_sg_batch_create(descs, self.p, self.c, weights.packed, self.probe_xy,
+                                           self.err, self.ws, nbytes)
+        self.shape = kaze_batch_properties(self.handle)[0]
+
+    def run(self, eager=False, stream=None):
+        from .kaze import kaze_batch_run
+        kaze_batch_run(self.handle, eager, stream)
+
+    def accepted(self):
+        """Host (n, N) bool array: image j used the surrogate for level i
+        (synchronises)."""
+        import numpy as np
+        acc = self.err.cpu().numpy() <= self.c.bound
+        acc[:, 0] = False
+        return np.asarray(acc)
+
+    def keypoints(self, j):
+        """Image j's keypoints (level, y, x, response) sorted by (level, y,
+        x); synchronises."""
+        import numpy as np
+        n = min(int(self.count[j].item()), self.capacity)
+        if n == 0:
+            return np.zeros((0, 4))
+        k = self.kps[j][:n].cpu().numpy()
+        resp = k[:, 3].copy().view(np.float32).astype(np.float64)
+        out = np.stack([k[:, 2], k[:, 1], k[:, 0], resp], axis=1).astype(np.float64)
+        return out[np.lexsort((out[:, 2], out[:, 1], out[:, 0]))]
+
+    def close(self):
+        from .kaze import kaze_batch_destroy
+        if getattr(self, "handle", None):
+            kaze_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

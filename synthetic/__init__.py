@@ -125,6 +125,9 @@ WORKLOADS = {
     "kaze_batch64_uneven": _uneven_batch,
     "kaze_4k32_720p32": lambda: ([(3840, 2160, 5000 + j) for j in range(32)]
                                  + [(1280, 720, 5100 + j) for j in range(32)]),
+    # eight images of the single-image size: a working set (levels and
+    # responses, 2.4 GB) well above the 256 MB last-level cache
+    "kaze_8x1920x1200": lambda: [(1920, 1200, 8000 + j) for j in range(8)],
 }
 
 

@@ -53,3 +53,15 @@ def compare_keypoints(kp_gpu, kp_orc, det_orc, threshold, radii=None):
     bad_g = [p for p in g - o if not excused(det_orc, p, threshold, radii)]
     bad_o = [p for p in o - g if not excused(det_orc, p, threshold, radii)]
     return len(g & o), bad_g, bad_o
+
+
+def recall(kp_s, kp_orc, det_orc, threshold):
+    """Keypoint recall |KP_s & KP_orc| / |KP_orc| on exact (level, y, x),
+    with oracle points that the excuse rule covers and KP_s misses left out
+    of the denominator.  Returns (recall, n_common, denominator)."""
+    s = {tuple(int(v) for v in r[:3]) for r in kp_s}
+    o = {tuple(int(v) for v in r[:3]) for r in kp_orc}
+    common = len(s & o)
+    excused_missing = sum(1 for p in o - s if excused(det_orc, p, threshold))
+    den = len(o) - excused_missing
+    return (common / den if den else 1.0), common, den

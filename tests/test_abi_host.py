@@ -350,3 +350,4 @@ def test_describe_arguments_rejected_before_launch(K):
         a = dict(dict(levels=256, lx=512, ly=768, W=64), **c)
         with pytest.raises(K.KazeError):
             K.kaze_derivatives(a["levels"], a["W"], 64, p, a["lx"], a["ly"], 0)
+

@@ -115,6 +115,46 @@ def test_uneven_batch_images_vs_oracle(gpu_lib):
     kb.close()
 
 
+def test_full_uneven_batch_equals_single_image_calls(gpu_lib):
+    """The whole 64-image uneven workload (W in [640, 1920], H in [480,
+    1200]) in one plan against the single-image calls, image by image.
+
+    The plan solves the line interfaces with 8 chunks per lane (the launch
+    has enough wavefronts), a single image of these sizes with 4, so the
+    interface elimination rounds differently.  Everything before the first
+    step is the same arithmetic and must be bitwise equal (k, level 0); the
+    later levels agree to FP32 rounding of the two eliminations (bound 1e-5,
+    a tenth of the oracle tolerance), and the keypoint sets agree up to
+    points the excuse rule covers on the single-image response."""
+    K = gpu_lib
+    sizes = batch_sizes(64, 3, 640, 1920, 480, 1200)
+    seeds = [3000 + j for j in range(64)]
+    note(f"[batch] full uneven workload, {len(sizes)} images, "
+         f"{sum(w * h for w, h in sizes) / 1e6:.1f} Mpx")
+    kb, imgs = make_batch(K, sizes, seeds, 0)
+    kb.run()
+    torch.cuda.synchronize()
+    worst_l, worst_d, n_kp, n_bitwise = 0.0, 0.0, 0, 0
+    for j, im in enumerate(imgs):
+        ref = single(K, im)
+        assert float(kb.k[j].item()) == float(ref.k.item()), j
+        assert torch.equal(kb.levels[j][0], ref.levels[0]), j
+        dl = (kb.levels[j] - ref.levels).abs().max().item()
+        dd = (kb.det[j] - ref.det).abs().max().item()
+        worst_l, worst_d = max(worst_l, dl), max(worst_d, dd)
+        n_bitwise += int(dl == 0.0)
+        assert dl <= 1e-5, (j, sizes[j], dl)
+        det_ref = ref.det.cpu().numpy().astype(np.float64)
+        kp_b, kp_r = kb.keypoints(j), ref.keypoints()
+        common, bad_b, bad_r = compare_keypoints(kp_b, kp_r, det_ref, 0.001)
+        assert not bad_b and not bad_r, (j, bad_b, bad_r)
+        n_kp += common
+        del ref
+    note(f"  64 images: worst max|dL| {worst_l:.2e}, worst max|ddet| {worst_d:.2e}, "
+         f"{n_bitwise} bitwise, {n_kp} keypoints in common")
+    kb.close()
+
+
 def test_large_batch_forks_detector_and_matches_eager(gpu_lib):
     """Above the size where the detector response runs beside the steps (a
     second stream inside the captured graph), replays still equal the eager

@@ -14,7 +14,7 @@ import pytest
 
 import oracle as O
 from synthetic import kaze_image, surrogate_params
-from kaze_parity import LEVEL_TOL, compare_keypoints, note
+from kaze_parity import LEVEL_TOL, compare_keypoints, note, recall
 
 pytestmark = pytest.mark.gpu
 
@@ -94,15 +94,19 @@ def test_surrogate_scale_space_1920x1200(trained, gpu_lib):
     kp_o = O.find_extrema(det_o, 0.001)
     errs = [float(np.abs(lev_g[i] - lev_o[i]).max()) for i in range(len(lev_o))]
     common, bad_g, bad_o = compare_keypoints(kp_g, kp_o, det_o, 0.001)
-    recall = common / max(1, len(kp_o))
+    rc, _, den = recall(kp_g, kp_o, det_o, 0.001)
     note("[sg eval] 1920x1200 seed %d bound %.1e probes %d" % (seed, ss.c.bound, ss.c.probes))
     note("  accepted  %s" % " ".join(str(int(a)) for a in acc))
     note("  probe err %s" % " ".join("%.1e" % e for e in err_probe))
     note("  max|L - L_oracle| %s" % " ".join("%.1e" % e for e in errs))
-    note("  keypoints %d / oracle %d, recall %.4f" % (len(kp_g), len(kp_o), recall))
+    note("  keypoints %d / oracle %d, recall %.4f (%d of %d)" % (len(kp_g), len(kp_o), rc,
+                                                                  common, den))
     first = next((i for i, a in enumerate(acc) if a), len(acc))
     for i in range(first):
         assert errs[i] <= LEVEL_TOL, i
     if first == len(acc):   # every level fell back: the plain path exactly
         assert not bad_g and not bad_o
+    else:                   # the surrogate bar: 1e-3 on every level, 98% recall
+        assert max(errs) <= 1e-3, errs
+        assert rc >= 0.98, rc
     ss.close()

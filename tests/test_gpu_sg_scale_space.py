@@ -53,11 +53,13 @@ def test_forced_fallback_equals_plain_path(S, gpu_lib, W, H, shape):
 
 
 def test_forced_acceptance_equals_oracle_chain(S, gpu_lib):
-    """Every level from the surrogate: the chain of 15 steps against the
-    quantized FP64 chain.  Differences are the BF16 rounding flips of each
-    step (see the forward tests); an untrained network is not contractive,
-    so later steps amplify them (about 1.3x per step here).  Each level's
-    inputs are checked bitwise by test_mixed_decisions_are_consistent."""
+    """Every level from the surrogate.  Each GPU level is compared with the
+    oracle's quantized surrogate step taken from the GPU's own previous level
+    (conductivity from that level and the GPU's k), so every level is held
+    to the single-step bar: within 2% of the step's size, the BF16 rounding
+    flips of one forward pass (see the forward tests).  The whole FP64 chain
+    is reported beside it: an untrained network is not contractive, so the
+    chain amplifies those flips (about 1.3x per step here)."""
     K = gpu_lib
     W, H = 72, 56
     th = surrogate_params(2, last_scale=0.1)
@@ -68,16 +70,25 @@ def test_forced_acceptance_equals_oracle_chain(S, gpu_lib):
     assert all(ss.accepted()[1:])
     img = kaze_image(W, H, 12).astype(np.float64)
     lev_o, k_o = C.surrogate_scale_space(img, th.astype(np.float64), [True] * 16, quantized=True)
-    lev_g = ss.levels.cpu().numpy()
-    assert float(ss.k.item()) == pytest.approx(k_o, rel=1e-4)
-    errs = [float(np.abs(lev_g[i] - lev_o[i]).max()) for i in range(16)]
-    steps = [float(np.abs(lev_o[i] - lev_o[i - 1]).max()) for i in range(1, 16)]
-    note("  max|dL| per level %s" % " ".join("%.1e" % e for e in errs))
-    note("  max step size     %s" % " ".join("%.1e" % e for e in steps))
-    assert errs[0] <= 1e-6
-    assert errs[1] <= 2e-2 * steps[0]
+    lev_g = ss.levels.cpu().numpy().astype(np.float64)
+    k_g = float(ss.k.item())
+    assert k_g == pytest.approx(k_o, rel=1e-4)
+    assert float(np.abs(lev_g[0] - lev_o[0]).max()) <= 1e-6
+    sched = O.level_schedule()
+    th64 = th.astype(np.float64)
+    step_err, step_size = [], []
     for i in range(1, 16):
-        assert errs[i] <= 0.05 * i * max(steps) + 1e-5, i
+        prev = lev_g[i - 1]
+        g = O.conductivity_g2(prev, k_g)
+        ref = C.surrogate_step(th64, prev, g, sched[i]["t"] - sched[i - 1]["t"], quantized=True)
+        step_err.append(float(np.abs(lev_g[i] - ref).max()))
+        step_size.append(float(np.abs(ref - prev).max()))
+    chain = [float(np.abs(lev_g[i] - lev_o[i]).max()) for i in range(16)]
+    note("  per-step max|dL| %s" % " ".join("%.1e" % e for e in step_err))
+    note("  max step size    %s" % " ".join("%.1e" % e for e in step_size))
+    note("  chain max|dL|    %s" % " ".join("%.1e" % e for e in chain))
+    for i in range(15):
+        assert step_err[i] <= 2e-2 * step_size[i] + 1e-6, (i + 1, step_err[i], step_size[i])
 
 
 def test_probe_error_matches_oracle(S, gpu_lib):
