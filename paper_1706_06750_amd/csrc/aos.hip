@@ -27,8 +27,8 @@
 //     sweep in registers, and L_i = L + (delta_x + delta_y)/2 is stored.
 //
 // HBM traffic per pixel and step: L read twice, g written once and read
-// once, L_i written once, plus 2 x 32 bytes of interface equations per
-// chunk.  Tile rows are staged through LDS (the transpose that lets
+// once, L_i written once, plus 24 bytes of interface equations per chunk
+// (two equations scaled to a unit diagonal) and 8 bytes of solved ends.  Tile rows are staged through LDS (the transpose that lets
 // one thread walk a row); tile columns are walked by adjacent threads on
 // adjacent columns, so every global access is coalesced.
 #include "kaze_internal.h"
@@ -154,10 +154,15 @@ typedef float vf2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) vf4 gvf4;
 typedef __attribute__((address_space(1))) vf2 gvf2;
 
+// The chunk's two equations scaled to a unit diagonal (the pivots are >= 1:
+// diagonally dominant rows), as (a0, c0, d0, a1, c1, d1) in three 8-byte
+// stores.
 __device__ __forceinline__ void store_eqs(float* dst, const Eq& e0, const Eq& e1) {
-    gvf4* o = (gvf4*)dst;
-    o[0] = vf4{e0.a, e0.b, e0.c, e0.d};
-    o[1] = vf4{e1.a, e1.b, e1.c, e1.d};
+    const float r0 = rcp(e0.b), r1 = rcp(e1.b);
+    gvf2* o = (gvf2*)dst;
+    o[0] = vf2{e0.a * r0, e0.c * r0};
+    o[1] = vf2{e0.d * r0, e1.a * r1};
+    o[2] = vf2{e1.c * r1, e1.d * r1};
 }
 
 // Index i of a line of n pixels reflected half-sample symmetrically into
@@ -378,7 +383,7 @@ __global__ __launch_bounds__(kRedThreads) void aos_reduce_kernel(ImageDesc d0, A
                 chunk_reduce<kRowChunk, false, true>(A, pos0, W, 1.f, e0, e1);
             else
                 chunk_reduce<kRowChunk, true, true>(A, pos0, W, 1.f, e0, e1);
-            store_eqs(d.rrow + ((size_t)(2 * cx + h) * H + y) * 8, e0, e1);
+            store_eqs(d.rrow + ((size_t)(2 * cx + h) * H + y) * kEqFloats, e0, e1);
         }
     } else if (wave < 2 * SW) {
         const int v = wave - SW, c = lane;
@@ -390,7 +395,7 @@ __global__ __launch_bounds__(kRedThreads) void aos_reduce_kernel(ImageDesc d0, A
                 chunk_reduce<kColChunk, false, true>(A, pos0, H, 1.f, e0, e1);
             else
                 chunk_reduce<kColChunk, true, true>(A, pos0, H, 1.f, e0, e1);
-            store_eqs(d.rcol + ((size_t)(pos0 / kColChunk) * W + x) * 8, e0, e1);
+            store_eqs(d.rcol + ((size_t)(pos0 / kColChunk) * W + x) * kEqFloats, e0, e1);
         }
     }
 }
@@ -553,26 +558,27 @@ __global__ __launch_bounds__(kIfaceThreads) void aos_iface_kernel(ImageDesc d0, 
     const int line = (row ? grp : grp - rgroups) * (kWave / P) + lane / P;
     const bool live = line < nl;
     const int lc = live ? line : nl - 1;  // clamped: every lane loads in bounds
-    gfloat* R = (gfloat*)(row ? d.rrow : d.rcol) + (size_t)lc * 8;
+    gfloat* R = (gfloat*)(row ? d.rrow : d.rcol) + (size_t)lc * kEqFloats;
     gfloat* Z = (gfloat*)(row ? d.zrow : d.zcol) + (size_t)lc * 2;
-    const size_t rs = (size_t)nl * 8, zs = (size_t)nl * 2;  // chunk strides
+    const size_t rs = (size_t)nl * kEqFloats, zs = (size_t)nl * 2;  // chunk strides
     const int c0 = pos * kIfaceM;
 
     Eq e[NR];
     {
-        vf4 va[kIfaceM], vb[kIfaceM];
+        vf2 va[kIfaceM], vb[kIfaceM], vc[kIfaceM];
 #pragma unroll
         for (int j = 0; j < kIfaceM; ++j) {
             const int c = c0 + j < nch ? c0 + j : nch - 1;
-            const gvf4* q = (const gvf4*)(R + c * rs);
+            const gvf2* q = (const gvf2*)(R + c * rs);
             va[j] = q[0];
             vb[j] = q[1];
+            vc[j] = q[2];
         }
 #pragma unroll
         for (int j = 0; j < kIfaceM; ++j) {
             const bool ok = c0 + j < nch;
-            e[2 * j] = ok ? Eq{va[j].x, va[j].y, va[j].z, va[j].w} : eq_identity();
-            e[2 * j + 1] = ok ? Eq{vb[j].x, vb[j].y, vb[j].z, vb[j].w} : eq_identity();
+            e[2 * j] = ok ? Eq{va[j].x, 1.f, va[j].y, vb[j].x} : eq_identity();
+            e[2 * j + 1] = ok ? Eq{vb[j].y, 1.f, vc[j].x, vc[j].y} : eq_identity();
         }
     }
     // x_k = dp_k + ep_k x_0 - cp_k x_{k+1} for the interior rows k, and

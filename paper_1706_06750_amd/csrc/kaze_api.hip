@@ -253,8 +253,8 @@ Scratch scratch_layout(int W, int H, int nbins, int shape, size_t base, bool fed
     const size_t ncx = aos_row_chunks(W), ncy = aos_col_chunks(H);
     size_t off = base;
     w.g = off;    off = align256(off + (size_t)W * H * sizeof(float));
-    w.rrow = off; off = align256(off + (size_t)H * ncx * 8 * sizeof(float));
-    w.rcol = off; off = align256(off + (size_t)W * ncy * 8 * sizeof(float));
+    w.rrow = off; off = align256(off + (size_t)H * ncx * kEqFloats * sizeof(float));
+    w.rcol = off; off = align256(off + (size_t)W * ncy * kEqFloats * sizeof(float));
     w.zrow = off; off = align256(off + (size_t)H * ncx * 2 * sizeof(float));
     w.zcol = off; off = align256(off + (size_t)W * ncy * 2 * sizeof(float));
     w.hist = off;

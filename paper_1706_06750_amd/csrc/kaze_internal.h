@@ -226,6 +226,10 @@ inline int iface_m_for(long long groups_at_large) {
     return groups_at_large < kIfaceSmallGroups ? kIfaceMSmall : kIfaceMLarge;
 }
 
+// The two reduced equations of a chunk (first and last unknown), each scaled
+// to a unit diagonal and stored as (a, c, d): 6 floats per chunk.
+constexpr int kEqFloats = 6;
+
 // One image of an AOS step.  Interface equations and solutions are stored
 // chunk-major, so that the lanes of one wavefront (consecutive lines) touch
 // consecutive addresses.
@@ -233,8 +237,8 @@ struct ImageDesc {
     const float* L;   // level i-1, W x H, pitch W
     float* Lnext;     // level i
     float* g;         // conductivity of L (written or read, see the kernel)
-    float* rrow;      // reduced equations of the row chunks, [nchr][H][8]
-    float* rcol;      // ... of the column chunks, [nchc][W][8]
+    float* rrow;      // reduced equations of the row chunks, [nchr][H][kEqFloats]
+    float* rcol;      // ... of the column chunks, [nchc][W][kEqFloats]
     float* zrow;      // first/last unknown of every row chunk, [nchr][H][2]
     float* zcol;      // ... of every column chunk, [nchc][W][2]
     const float* k;   // contrast factor (device scalar); NULL: use the host value
