@@ -147,6 +147,33 @@ kaze_status kaze_build_scale_space(const float* img, int W, int H, int ld_img,
                                    float* k_out, void* ws, size_t ws_bytes,
                                    void* stream);
 
+/* Bytes of the device-resident scratch of kaze_build_scale_space_noalloc
+ * (64 MiB per GPU): enough for the default parameters up to 3840 x 2160,
+ * or up to about 2560 x 1600 with FED or sub-steps. */
+#define KAZE_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/*
+ * kaze_build_scale_space without a workspace argument, for callers that
+ * cannot allocate device memory (code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Arguments, outputs and results
+ * are those of kaze_build_scale_space (the same kernels on the same scratch
+ * layout, bit for bit); the scratch is a static device array of
+ * KAZE_NOALLOC_SCRATCH_BYTES that the library's code object holds on every
+ * GPU it runs on until the process ends.  Its address is looked up on the
+ * current device the first time the call runs there; the call itself
+ * allocates and frees nothing.
+ *   Limits: returns KAZE_ERR_UNSUPPORTED, before enqueuing anything, when
+ *   kaze_workspace_bytes(W, H, p) exceeds KAZE_NOALLOC_SCRATCH_BYTES.
+ *   Concurrency: every call on one GPU uses that GPU's one scratch array,
+ *   which keeps the last call's contents (nothing in it needs to start at
+ *   zero).  Calls that can overlap on one GPU -- on different streams, or
+ *   from different threads without ordering -- race on it; order them on
+ *   one stream.
+ */
+kaze_status kaze_build_scale_space_noalloc(const float* img, int W, int H, int ld_img,
+                                           const kaze_params* p, float* levels,
+                                           float* k_out, void* stream);
+
 /*
  * Conductivity of Eqs. 2-3 for one image and a given contrast factor:
  *   g = 1/(1 + |grad L_s|^2/k^2)  (KAZE_G2)  or  exp(-|grad L_s|^2/k^2) (KAZE_G1),

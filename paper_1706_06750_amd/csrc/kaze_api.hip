@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "kaze.h"
@@ -1332,6 +1333,45 @@ kaze_status scale_space_launches(const float* img, int W, int H, int ld_img,
     return KAZE_OK;
 }
 
+// ------------------------------------------------- device-resident scratch
+// Scratch of kaze_build_scale_space_noalloc: one copy per GPU, allocated
+// with the library's code object and held until the process ends.  Host
+// code never passes `scratch` itself (on the host it names a stand-in, not
+// device memory); it uses the address hipGetSymbolAddress returns for the
+// current device.
+constexpr size_t kNoAllocScratchBytes = (size_t)KAZE_NOALLOC_SCRATCH_BYTES;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[KAZE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's scratch, resolved once per device.
+kaze_status noalloc_scratch(char** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(KAZE_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(KAZE_ERR_UNSUPPORTED, "device %d beyond the %d the library tracks", dev,
+                    kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(KAZE_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                        hipGetErrorString(e));
+        if (!aligned(ptr, 256))
+            return fail(KAZE_ERR_HIP, "device scratch at %p is not 256-byte aligned", ptr);
+        g_scratch_ptr[dev] = static_cast<char*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return KAZE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1390,6 +1430,23 @@ kaze_status kaze_build_scale_space(const float* img, int W, int H, int ld_img,
         return fail(KAZE_ERR_WORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
                     need, ws_bytes);
     return scale_space_launches(img, W, H, ld_img, p, levels, k_out, static_cast<char*>(ws),
+                                static_cast<hipStream_t>(stream));
+}
+
+kaze_status kaze_build_scale_space_noalloc(const float* img, int W, int H, int ld_img,
+                                           const kaze_params* p, float* levels, float* k_out,
+                                           void* stream) {
+    size_t need = 0;
+    kaze_status st = check_scale_space_args(img, W, H, ld_img, p, levels, k_out, &need);
+    if (st != KAZE_OK) return st;
+    if (need > kNoAllocScratchBytes)
+        return fail(KAZE_ERR_UNSUPPORTED,
+                    "a %dx%d scale space with these parameters needs %zu scratch bytes; the "
+                    "device-resident scratch holds %zu",
+                    W, H, need, kNoAllocScratchBytes);
+    char* base = nullptr;
+    if ((st = noalloc_scratch(&base)) != KAZE_OK) return st;
+    return scale_space_launches(img, W, H, ld_img, p, levels, k_out, base,
                                 static_cast<hipStream_t>(stream));
 }
 

@@ -29,7 +29,8 @@ KAZE_WINDOW_SIGMA = 1
 # Every symbol include/kaze.h declares.
 EXPORTS = (
     "kaze_default_params", "kaze_num_levels", "kaze_schedule",
-    "kaze_workspace_bytes", "kaze_build_scale_space", "kaze_conductivity",
+    "kaze_workspace_bytes", "kaze_build_scale_space", "kaze_build_scale_space_noalloc",
+    "kaze_conductivity",
     "kaze_aos_step", "kaze_detector_response", "kaze_find_extrema",
     "kaze_last_error", "kaze_profile_begin", "kaze_profile_end",
     "kaze_kernel_names", "kaze_copy_f32", "kaze_batch_workspace_bytes",
@@ -103,6 +104,7 @@ def _load():
         "kaze_schedule": (i32, [P, vp, vp, vp, vp, vp]),
         "kaze_workspace_bytes": (sz, [i32, i32, P]),
         "kaze_build_scale_space": (i32, [vp, i32, i32, i32, P, vp, vp, vp, sz, vp]),
+        "kaze_build_scale_space_noalloc": (i32, [vp, i32, i32, i32, P, vp, vp, vp]),
         "kaze_conductivity": (i32, [vp, i32, i32, P, f64, vp, vp]),
         "kaze_aos_step": (i32, [vp, vp, i32, i32, f64, vp, vp, sz, vp]),
         "kaze_fed_schedule": (i32, [f64, vp, i32]),
@@ -192,6 +194,15 @@ def kaze_workspace_bytes(W: int, H: int, p: kaze_params) -> int:
 def kaze_build_scale_space(img, W, H, ld_img, p, levels, k_out, ws, ws_bytes, stream=None):
     _check(lib.kaze_build_scale_space(_ptr(img), W, H, ld_img, ctypes.byref(p), _ptr(levels),
                                       _ptr(k_out), _ptr(ws), ws_bytes, _stream(stream)))
+
+
+# Bytes of the device-resident scratch of kaze_build_scale_space_noalloc.
+KAZE_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def kaze_build_scale_space_noalloc(img, W, H, ld_img, p, levels, k_out, stream=None):
+    _check(lib.kaze_build_scale_space_noalloc(_ptr(img), W, H, ld_img, ctypes.byref(p),
+                                              _ptr(levels), _ptr(k_out), _stream(stream)))
 
 
 def kaze_conductivity(L, W, H, p, k, g, stream=None):

@@ -351,3 +351,35 @@ def test_describe_arguments_rejected_before_launch(K):
         with pytest.raises(K.KazeError):
             K.kaze_derivatives(a["levels"], a["W"], 64, p, a["lx"], a["ly"], 0)
 
+
+def test_noalloc_scratch_limit(K):
+    p = K.kaze_default_params()
+    assert K.kaze_workspace_bytes(3840, 2160, p) <= K.KAZE_NOALLOC_SCRATCH_BYTES
+    assert K.kaze_workspace_bytes(4096, 4096, p) > K.KAZE_NOALLOC_SCRATCH_BYTES
+    fed = K.kaze_default_params(scheme=K.KAZE_FED)
+    assert K.kaze_workspace_bytes(2560, 1600, fed) <= K.KAZE_NOALLOC_SCRATCH_BYTES
+    hdr = open(HEADER).read()
+    m = re.search(r"#define KAZE_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", hdr)
+    assert m and int(m.group(1)) << int(m.group(2)) == K.KAZE_NOALLOC_SCRATCH_BYTES
+
+
+@no_gpu_only
+def test_noalloc_rejects_before_any_device_call(K):
+    p = K.kaze_default_params()
+    cases = [
+        (dict(W=4096, H=4096), -4),           # scratch would exceed the static array
+        (dict(img=0), -1), (dict(levels=0), -1), (dict(k_out=0), -1), (dict(W=7), -1),
+        (dict(ld=63), -1), (dict(img=18), -1), (dict(H=5000), -4),
+    ]
+    for c, status in cases:
+        a = dict(img=256, W=64, H=64, ld=None, levels=512, k_out=1024)
+        a.update(c)
+        ld = a["ld"] if a["ld"] is not None else a["W"]
+        with pytest.raises(K.KazeError) as e:
+            K.kaze_build_scale_space_noalloc(a["img"], a["W"], a["H"], ld, p, a["levels"],
+                                             a["k_out"], 0)
+        assert e.value.status == status, c
+    bad = K.kaze_default_params(octaves=0)
+    with pytest.raises(K.KazeError) as e:
+        K.kaze_build_scale_space_noalloc(256, 64, 64, 64, bad, 512, 1024, 0)
+    assert e.value.status == -1
