@@ -38,8 +38,9 @@ AOS_KERNELS = ("aos_reduce", "aos_iface", "aos_recover")
 
 
 def tile_label(K, shape):
-    """Width x height of the AOS tile of a shape, e.g. '60x32'."""
-    return "%dx%d" % K.AOS_SHAPES[shape]
+    """Tile, chunk lengths and interface lanes of an AOS launch shape, e.g.
+    '60x32 c30/32 m4'."""
+    return K.shape_label(shape)
 
 
 def traffic_from_profile(key, aos_tile, det_levels):
@@ -316,6 +317,7 @@ def bench_single(args, K, torch, kaze_image, case):
         extra["surrogate"] = bench_surrogate(args, K, torch, img, W, H, seed,
                                              args.steps / elapsed)
         progress("surrogate done")
+    N = kz.N
     if not args.no_batches:
         del img, kz
         torch.cuda.empty_cache()
@@ -324,7 +326,7 @@ def bench_single(args, K, torch, kaze_image, case):
         extra["cpu_baseline"] = cpu_baseline(W, H, seed)
         progress("CPU baseline: %.3f images/s" % extra["cpu_baseline"]["value"])
     config = {"workload": args.workload, "image": "%dx%d" % (W, H), "seed": seed,
-              "levels": kz.N,
+              "levels": N,
               "path": "plain AOS (no surrogate), image plan, %s" %
                       ("eager launches" if form == "eager" else "graph replay"),
               "aos_tile": shape, "keypoints": kps}

@@ -286,17 +286,39 @@ typedef struct {
     int* count;            /* 1 int output: extrema found, or NULL           */
 } kaze_image_desc;
 
-/* Number of AOS tile shapes. */
-#define KAZE_AOS_SHAPES 2
+/* Number of AOS launch shapes. */
+#define KAZE_AOS_SHAPES 6
 
-/* Tile shape of the row/column solves (width x height of the blocks of the
- * reduction and recovery launches): 0 = 60x32, 1 = 60x64; -1 = default (0).  Row lines are always cut into chunks of 30 pixels and
- * column lines into chunks of 32, and every shape evaluates the same
- * arithmetic, so all give the same result; they differ in speed only.
- * Every shape fits every image size. */
+/*
+ * Launch shape of the row/column solves of the AOS steps (Eq. 4): the blocks
+ * of the reduction and recovery launches cover tiles of 60 x ty pixels, row
+ * lines are cut into chunks of rc pixels and column lines into chunks of cc,
+ * and the interface system of every line is solved with m chunks per lane.
+ *
+ *   shape   tile    rc   cc   m
+ *     0     60x32   30   32   4
+ *     1     60x32   30   32   8
+ *     2     60x64   30   32   4
+ *     3     60x64   30   32   8
+ *     4     60x64   60   64   4
+ *     5     60x64   60   64   8
+ *
+ * rc, cc and m fix the elimination order, the tile height only the launch:
+ * shapes that differ in the tile alone give bitwise equal results, the
+ * others agree to FP32 rounding.  Every shape fits every image size.
+ * aos_shape -1 selects the default: shape 1 when the interface launch has
+ * at least 1024 wavefronts at m = 8 over all images of the call, else shape
+ * 0 (single-image calls use the same rule).
+ */
 typedef struct {
     int aos_shape;
 } kaze_batch_config;
+
+/* Tile width and height, chunk lengths and interface chunks per lane of a
+ * shape (host outputs, any may be NULL); KAZE_ERR_INVALID_ARG for a shape
+ * outside [0, KAZE_AOS_SHAPES). */
+kaze_status kaze_aos_shape_info(int shape, int* tile_w, int* tile_h, int* row_chunk,
+                                int* col_chunk, int* iface_m);
 
 typedef struct kaze_batch kaze_batch;  /* opaque plan */
 
@@ -346,11 +368,12 @@ kaze_status kaze_batch_run(kaze_batch* b, int eager, void* stream);
 kaze_status kaze_batch_destroy(kaze_batch* b);
 
 /*
- * Autotuner: for every tile shape that fits all images, builds the plan in
- * ws (sized for the maximum), times `reps` graph launches on stream, and
- * returns the fastest shape in *best and, if ms_per_shape is not NULL, the
- * mean milliseconds per run of each of the KAZE_AOS_SHAPES shapes (-1 where
- * it does not fit).  Synchronises the stream.
+ * Autotuner: for every launch shape (tile height, chunk lengths, interface
+ * chunks per lane) that fits all images, builds the plan in ws (sized for
+ * the maximum), times `reps` graph launches on stream, and returns the
+ * fastest shape in *best and, if ms_per_shape is not NULL, the mean
+ * milliseconds per run of each of the KAZE_AOS_SHAPES shapes (-1 where it
+ * does not fit).  Synchronises the stream.
  */
 kaze_status kaze_batch_autotune(const kaze_image_desc* images, int n,
                                 const kaze_params* p, void* ws, size_t ws_bytes,

@@ -336,16 +336,28 @@ __device__ __forceinline__ void tile_conductivity(const float* sL, float* sS, fl
     }
 }
 
-// Reduction: one block of 256 threads per tile of kAosTX x TY pixels.
-// Every tile row holds two row chunks (kRowChunk each), every tile column
-// TY / kColChunk column chunks; the row chunks are walked by the lanes of
-// TY / 32 wavefronts (lane = 32 * half + row), the column chunks by as many
-// wavefronts (lane = column), so every sweep runs on full wavefronts.  The
-// LDS copy of g is pre-multiplied by tau.
-template <int RG, int TY, bool CG, int GM>
+// Chunks of one tile: kAosTX / RC row chunks per tile row, walked by the
+// lanes of TY / RPW wavefronts (lane = RPW * chunk + row), and TY / CC
+// column chunks per tile column, one wavefront each (lane = column), so
+// every sweep runs on full wavefronts.
+template <int TY, int RC, int CC>
+struct TileChunks {
+    static constexpr int HALVES = kAosTX / RC;  // row chunks per tile row
+    static constexpr int RPW = kWave / HALVES;  // tile rows per row wavefront
+    static constexpr int SWR = TY / RPW;        // row wavefronts
+    static constexpr int SWC = TY / CC;         // column wavefronts
+    static_assert(HALVES * RC == kAosTX && SWR * RPW == TY && SWC * CC == TY, "tiles hold whole chunks");
+    static_assert(SWR + SWC <= 4 && RC <= CC && CC <= kMaxColChunk, "four wavefronts per tile");
+};
+
+// Reduction: one block of 256 threads per tile of kAosTX x TY pixels; each
+// tile row and tile column chunk (TileChunks) is reduced by one forward
+// sweep to two equations.  The LDS copy of g is pre-multiplied by tau.
+template <int RG, int TY, int RC, int CC, bool CG, int GM>
 __global__ __launch_bounds__(kRedThreads) void aos_reduce_kernel(ImageDesc d0, AosWork w, Taps tc,
                                                                  float tau, float k_host) {
     using G = RedGeom<RG, TY, CG>;
+    using T = TileChunks<TY, RC, CC>;
     extern __shared__ float smem[];
     float* sL = smem;
     float* sS = smem + G::offS;
@@ -371,31 +383,30 @@ __global__ __launch_bounds__(kRedThreads) void aos_reduce_kernel(ImageDesc d0, A
         __syncthreads();
     }
 
-    constexpr int SW = TY / 32;  // sweep wavefronts per direction
     Eq e0, e1;
-    if (wave < SW) {
-        const int r = wave * 32 + (lane & 31), h = lane >> 5;
-        const int y = ty0 + r, pos0 = tx0 + h * kRowChunk;
+    if (wave < T::SWR) {
+        const int r = wave * T::RPW + (lane % T::RPW), h = lane / T::RPW;
+        const int y = ty0 + r, pos0 = tx0 + h * RC;
         if (y < H && pos0 < W) {
-            const LdsLine<1, 1> A{sG + (r + 1) * G::PG + 1 + h * kRowChunk,
-                                  sL + (r + G::R) * G::PL + G::R + h * kRowChunk};
-            if (tx0 + kAosTX < W)  // both chunks and their right neighbours inside
-                chunk_reduce<kRowChunk, false, true>(A, pos0, W, 1.f, e0, e1);
+            const LdsLine<1, 1> A{sG + (r + 1) * G::PG + 1 + h * RC,
+                                  sL + (r + G::R) * G::PL + G::R + h * RC};
+            if (tx0 + kAosTX < W)  // the tile row's chunks and their right neighbours inside
+                chunk_reduce<RC, false, true>(A, pos0, W, 1.f, e0, e1);
             else
-                chunk_reduce<kRowChunk, true, true>(A, pos0, W, 1.f, e0, e1);
-            store_eqs(d.rrow + ((size_t)(2 * cx + h) * H + y) * kEqFloats, e0, e1);
+                chunk_reduce<RC, true, true>(A, pos0, W, 1.f, e0, e1);
+            store_eqs(d.rrow + ((size_t)(T::HALVES * cx + h) * H + y) * kEqFloats, e0, e1);
         }
-    } else if (wave < 2 * SW) {
-        const int v = wave - SW, c = lane;
-        const int x = tx0 + c, pos0 = ty0 + v * kColChunk;
+    } else if (wave < T::SWR + T::SWC) {
+        const int v = wave - T::SWR, c = lane;
+        const int x = tx0 + c, pos0 = ty0 + v * CC;
         if (c < kAosTX && x < W && pos0 < H) {
-            const LdsLine<G::PG, G::PL> A{sG + (v * kColChunk + 1) * G::PG + 1 + c,
-                                          sL + (v * kColChunk + G::R) * G::PL + G::R + c};
-            if (pos0 + kColChunk < H)
-                chunk_reduce<kColChunk, false, true>(A, pos0, H, 1.f, e0, e1);
+            const LdsLine<G::PG, G::PL> A{sG + (v * CC + 1) * G::PG + 1 + c,
+                                          sL + (v * CC + G::R) * G::PL + G::R + c};
+            if (pos0 + CC < H)
+                chunk_reduce<CC, false, true>(A, pos0, H, 1.f, e0, e1);
             else
-                chunk_reduce<kColChunk, true, true>(A, pos0, H, 1.f, e0, e1);
-            store_eqs(d.rcol + ((size_t)(pos0 / kColChunk) * W + x) * kEqFloats, e0, e1);
+                chunk_reduce<CC, true, true>(A, pos0, H, 1.f, e0, e1);
+            store_eqs(d.rcol + ((size_t)(pos0 / CC) * W + x) * kEqFloats, e0, e1);
         }
     }
 }
@@ -612,14 +623,15 @@ __global__ __launch_bounds__(kIfaceThreads) void aos_iface_kernel(ImageDesc d0, 
         if (live && c0 + j < nch) *(gvf2*)(Z + (c0 + j) * zs) = vf2{x[2 * j], x[2 * j + 1]};
 }
 
-// Recovery: TY / 32 row and TY / 32 column wavefronts per tile; L and
-// tau * g of the tile staged in LDS.  Both sweeps keep their increments in
-// registers; after a barrier the row lanes fold theirs into the LDS copy of
-// L (L + delta_x / 2), and after a second one the column lanes store
+// Recovery: the row and column wavefronts of TileChunks; L and tau * g of
+// the tile staged in LDS.  Both sweeps keep their increments in registers;
+// after a barrier the row lanes fold theirs into the LDS copy of L
+// (L + delta_x / 2), and after a second one the column lanes store
 // L_i = L + (delta_x + delta_y)/2 one row at a time (coalesced).
-template <int TY>
+template <int TY, int RC, int CC>
 __global__ __launch_bounds__(TY * 4) void aos_recover_kernel(ImageDesc d0, AosWork w, float tau) {
-    constexpr int NT = TY * 4, WAVES = NT / kWave, SW = TY / 32;
+    constexpr int NT = TY * 4, WAVES = NT / kWave;
+    using T = TileChunks<TY, RC, CC>;
     // LDS layout: (row, column) of the tile at sL[row * PL + column], tau * g
     // at sG[row * PG + column]
     constexpr int PL = kAosTX + 1, PG = kAosTX + 1;
@@ -657,42 +669,44 @@ __global__ __launch_bounds__(TY * 4) void aos_recover_kernel(ImageDesc d0, AosWo
         }
     }
     __syncthreads();
-    float xs[kColChunk];  // row lanes: delta_x of the chunk; column lanes: delta_y
-    const int v = wave - SW, c = lane;
-    const int xcol = tx0 + c, pos0c = ty0 + v * kColChunk;
-    const bool col_lane = wave >= SW && c < kAosTX && xcol < W && pos0c < H;
-    const int r = wave * 32 + (lane & 31), h = lane >> 5;
-    const bool row_lane = wave < SW && ty0 + r < H && tx0 + h * kRowChunk < W;
+    float xs[CC];  // row lanes: delta_x of the chunk; column lanes: delta_y
+    const int v = wave - T::SWR, c = lane;
+    const int xcol = tx0 + c, pos0c = ty0 + v * CC;
+    const bool col_lane =
+        wave >= T::SWR && wave < T::SWR + T::SWC && c < kAosTX && xcol < W && pos0c < H;
+    const int r = wave * T::RPW + (lane % T::RPW), h = lane / T::RPW;
+    const bool row_lane = wave < T::SWR && ty0 + r < H && tx0 + h * RC < W;
     if (row_lane) {
-        const int y = ty0 + r, pos0 = tx0 + h * kRowChunk;
-        const vf2 z = *(const gvf2*)((const gfloat*)d.zrow + ((size_t)(2 * cx + h) * H + y) * 2);
-        const LdsLine<1, 1> A{sG + r * PG + h * kRowChunk, sL + r * PL + h * kRowChunk};
-        float (&xr)[kRowChunk] = *reinterpret_cast<float (*)[kRowChunk]>(xs);
+        const int y = ty0 + r, pos0 = tx0 + h * RC;
+        const vf2 z =
+            *(const gvf2*)((const gfloat*)d.zrow + ((size_t)(T::HALVES * cx + h) * H + y) * 2);
+        const LdsLine<1, 1> A{sG + r * PG + h * RC, sL + r * PL + h * RC};
+        float (&xr)[RC] = *reinterpret_cast<float (*)[RC]>(xs);
         if (tx0 + kAosTX < W)
-            chunk_recover<kRowChunk, false, true>(A, pos0, W, 1.f, z.x, z.y, xr);
+            chunk_recover<RC, false, true>(A, pos0, W, 1.f, z.x, z.y, xr);
         else
-            chunk_recover<kRowChunk, true, true>(A, pos0, W, 1.f, z.x, z.y, xr);
+            chunk_recover<RC, true, true>(A, pos0, W, 1.f, z.x, z.y, xr);
     } else if (col_lane) {
-        const vf2 z = *(const gvf2*)((const gfloat*)d.zcol + ((size_t)(pos0c / kColChunk) * W + xcol) * 2);
-        const LdsLine<PG, PL> A{sG + v * kColChunk * PG + c, sL + v * kColChunk * PL + c};
-        if (pos0c + kColChunk < H)
-            chunk_recover<kColChunk, false, true>(A, pos0c, H, 1.f, z.x, z.y, xs);
+        const vf2 z = *(const gvf2*)((const gfloat*)d.zcol + ((size_t)(pos0c / CC) * W + xcol) * 2);
+        const LdsLine<PG, PL> A{sG + v * CC * PG + c, sL + v * CC * PL + c};
+        if (pos0c + CC < H)
+            chunk_recover<CC, false, true>(A, pos0c, H, 1.f, z.x, z.y, xs);
         else
-            chunk_recover<kColChunk, true, true>(A, pos0c, H, 1.f, z.x, z.y, xs);
+            chunk_recover<CC, true, true>(A, pos0c, H, 1.f, z.x, z.y, xs);
     }
     __syncthreads();
     if (row_lane) {
-        float* lp = sL + r * PL + h * kRowChunk;
+        float* lp = sL + r * PL + h * RC;
 #pragma unroll
-        for (int k = 0; k < kRowChunk; ++k) lp[k] = __builtin_fmaf(0.5f, xs[k], lp[k]);
+        for (int k = 0; k < RC; ++k) lp[k] = __builtin_fmaf(0.5f, xs[k], lp[k]);
     }
     __syncthreads();
     if (col_lane) {
         gfloat* ob = (gfloat*)d.Lnext + (ptrdiff_t)uniform(pos0c) * W + tx0;
         const int rows = uniform(H - pos0c);
 #pragma unroll
-        for (int k = 0; k < kColChunk; ++k) {
-            const int rr = v * kColChunk + k;
+        for (int k = 0; k < CC; ++k) {
+            const int rr = v * CC + k;
             if (k < rows)
                 ob[(ptrdiff_t)k * W + c] = __builtin_fmaf(0.5f, xs[k], sL[rr * PL + c]);
         }
@@ -799,48 +813,61 @@ __global__ __launch_bounds__(kBlock) void probe_err_kernel(const float* L, const
 
 int work_count(const ImageDesc& d0, const AosWork& w, int ty, int lines_m) {
     if (w.items) return w.count;
-    return lines_m ? aos_line_groups(d0.W, d0.H, lines_m) : aos_tiles_of(d0.W, d0.H, ty);
+    return lines_m ? iface_groups(d0.H, d0.nchr, lines_m) + iface_groups(d0.W, d0.nchc, lines_m)
+                   : aos_tiles_of(d0.W, d0.H, ty);
 }
 
-template <int RG, int TY, bool CG, int GM>
+template <int RG, int TY, int RC, int CC, bool CG, int GM>
 hipError_t launch_reduce_t(const ImageDesc& d0, const AosWork& w, const Taps& tc, float tau,
                            float k_host, hipStream_t s) {
     const int count = work_count(d0, w, TY, 0);
     if (count <= 0) return hipSuccess;
     const size_t lds = (size_t)RedGeom<RG, TY, CG>::floats * sizeof(float);
-    hipLaunchKernelGGL((aos_reduce_kernel<RG, TY, CG, GM>), dim3(count), dim3(kRedThreads), lds, s,
-                       d0, w, tc, tau, k_host);
+    hipLaunchKernelGGL((aos_reduce_kernel<RG, TY, RC, CC, CG, GM>), dim3(count),
+                       dim3(kRedThreads), lds, s, d0, w, tc, tau, k_host);
     return hipGetLastError();
 }
 
-template <int RG, int TY>
+template <int RG, int TY, int RC, int CC>
 hipError_t launch_reduce_g(const ImageDesc& d0, const AosWork& w, const Taps& tc, float tau,
                            int gmode, float k_host, hipStream_t s) {
-    if (gmode == 0) return launch_reduce_t<RG, TY, true, 0>(d0, w, tc, tau, k_host, s);
-    if (gmode == 1) return launch_reduce_t<RG, TY, true, 1>(d0, w, tc, tau, k_host, s);
+    if (gmode == 0) return launch_reduce_t<RG, TY, RC, CC, true, 0>(d0, w, tc, tau, k_host, s);
+    if (gmode == 1) return launch_reduce_t<RG, TY, RC, CC, true, 1>(d0, w, tc, tau, k_host, s);
     return hipErrorInvalidValue;
 }
 
-template <int TY>
+template <int TY, int RC, int CC>
 hipError_t launch_reduce_s(const ImageDesc& d0, const AosWork& w, const Taps& tc, float tau,
                            bool compute_g, int gmode, float k_host, hipStream_t s) {
-    if (!compute_g) return launch_reduce_t<1, TY, false, 0>(d0, w, tc, tau, k_host, s);
+    if (!compute_g) return launch_reduce_t<1, TY, RC, CC, false, 0>(d0, w, tc, tau, k_host, s);
     switch (tc.r) {
-        case 1: return launch_reduce_g<1, TY>(d0, w, tc, tau, gmode, k_host, s);
-        case 2: return launch_reduce_g<2, TY>(d0, w, tc, tau, gmode, k_host, s);
-        case 3: return launch_reduce_g<3, TY>(d0, w, tc, tau, gmode, k_host, s);
-        case 4: return launch_reduce_g<4, TY>(d0, w, tc, tau, gmode, k_host, s);
+        case 1: return launch_reduce_g<1, TY, RC, CC>(d0, w, tc, tau, gmode, k_host, s);
+        case 2: return launch_reduce_g<2, TY, RC, CC>(d0, w, tc, tau, gmode, k_host, s);
+        case 3: return launch_reduce_g<3, TY, RC, CC>(d0, w, tc, tau, gmode, k_host, s);
+        case 4: return launch_reduce_g<4, TY, RC, CC>(d0, w, tc, tau, gmode, k_host, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <int TY>
+template <int TY, int RC, int CC>
 hipError_t launch_recover_t(const ImageDesc& d0, const AosWork& w, float tau, hipStream_t s) {
     const int count = work_count(d0, w, TY, 0);
     if (count <= 0) return hipSuccess;
     const size_t lds = (size_t)2 * TY * (kAosTX + 1) * sizeof(float);
-    hipLaunchKernelGGL((aos_recover_kernel<TY>), dim3(count), dim3(TY * 4), lds, s, d0, w, tau);
+    hipLaunchKernelGGL((aos_recover_kernel<TY, RC, CC>), dim3(count), dim3(TY * 4), lds, s, d0, w,
+                       tau);
     return hipGetLastError();
+}
+
+// Tile height and chunk lengths of a shape, as compiled kernel variants.
+enum AosVariant { AV_32_SHORT = 0, AV_64_SHORT = 1, AV_64_LONG = 2, AV_NONE = -1 };
+AosVariant aos_variant(int shape) {
+    if (shape < 0 || shape >= kAosShapes) return AV_NONE;
+    const AosShape& a = kAosShape[shape];
+    if (a.ty == 32 && a.rc == 30 && a.cc == 32) return AV_32_SHORT;
+    if (a.ty == 64 && a.rc == 30 && a.cc == 32) return AV_64_SHORT;
+    if (a.ty == 64 && a.rc == 60 && a.cc == 64) return AV_64_LONG;
+    return AV_NONE;
 }
 
 }  // namespace
@@ -859,22 +886,28 @@ hipError_t launch_cond(const BatchImage& d0, const ImgWork& w, const Taps& tc, f
 
 hipError_t launch_aos_reduce(const ImageDesc& d0, const AosWork& w, int shape, const Taps& tc,
                              float tau, bool compute_g, int gmode, float k_host, hipStream_t s) {
-    switch (shape) {
-        case 0: return launch_reduce_s<32>(d0, w, tc, tau, compute_g, gmode, k_host, s);
-        case 1: return launch_reduce_s<64>(d0, w, tc, tau, compute_g, gmode, k_host, s);
+    switch (aos_variant(shape)) {
+        case AV_32_SHORT:
+            return launch_reduce_s<32, 30, 32>(d0, w, tc, tau, compute_g, gmode, k_host, s);
+        case AV_64_SHORT:
+            return launch_reduce_s<64, 30, 32>(d0, w, tc, tau, compute_g, gmode, k_host, s);
+        case AV_64_LONG:
+            return launch_reduce_s<64, 60, 64>(d0, w, tc, tau, compute_g, gmode, k_host, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_aos_iface(const ImageDesc& d0, const AosWork& w, int M, hipStream_t s) {
+hipError_t launch_aos_iface(const ImageDesc& d0, const AosWork& w, int shape, hipStream_t s) {
+    if (shape < 0 || shape >= kAosShapes) return hipErrorInvalidValue;
+    const int M = kAosShape[shape].m;
     const int count = work_count(d0, w, 0, M);
     if (count <= 0) return hipSuccess;
     const int waves = kIfaceThreads / kWave;
-    if (M == kIfaceMSmall)
-        hipLaunchKernelGGL(aos_iface_kernel<kIfaceMSmall>, dim3((count + waves - 1) / waves),
+    if (M == 4)
+        hipLaunchKernelGGL(aos_iface_kernel<4>, dim3((count + waves - 1) / waves),
                            dim3(kIfaceThreads), 0, s, d0, w, count);
-    else if (M == kIfaceMLarge)
-        hipLaunchKernelGGL(aos_iface_kernel<kIfaceMLarge>, dim3((count + waves - 1) / waves),
+    else if (M == 8)
+        hipLaunchKernelGGL(aos_iface_kernel<8>, dim3((count + waves - 1) / waves),
                            dim3(kIfaceThreads), 0, s, d0, w, count);
     else
         return hipErrorInvalidValue;
@@ -883,9 +916,10 @@ hipError_t launch_aos_iface(const ImageDesc& d0, const AosWork& w, int M, hipStr
 
 hipError_t launch_aos_recover(const ImageDesc& d0, const AosWork& w, int shape, float tau,
                               hipStream_t s) {
-    switch (shape) {
-        case 0: return launch_recover_t<32>(d0, w, tau, s);
-        case 1: return launch_recover_t<64>(d0, w, tau, s);
+    switch (aos_variant(shape)) {
+        case AV_32_SHORT: return launch_recover_t<32, 30, 32>(d0, w, tau, s);
+        case AV_64_SHORT: return launch_recover_t<64, 30, 32>(d0, w, tau, s);
+        case AV_64_LONG: return launch_recover_t<64, 60, 64>(d0, w, tau, s);
         default: return hipErrorInvalidValue;
     }
 }

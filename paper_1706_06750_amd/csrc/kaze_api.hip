@@ -250,8 +250,8 @@ struct Scratch {
 Scratch scratch_layout(int W, int H, int nbins, int shape, size_t base, bool fed = false,
                        bool sub = false, int mask_levels = 0) {
     Scratch w;
-    (void)shape;
-    const size_t ncx = aos_row_chunks(W), ncy = aos_col_chunks(H);
+    const size_t ncx = aos_row_chunks(W, kAosShape[shape].rc);
+    const size_t ncy = aos_col_chunks(H, kAosShape[shape].cc);
     size_t off = base;
     w.g = off;    off = align256(off + (size_t)W * H * sizeof(float));
     w.rrow = off; off = align256(off + (size_t)H * ncx * kEqFloats * sizeof(float));
@@ -286,9 +286,8 @@ ImageDesc aos_desc(int W, int H, int shape, char* base, const Scratch& w, const 
     d.H = H;
     d.gate = nullptr;
     d.bound = 0.f;
-    (void)shape;
-    d.nchr = aos_row_chunks(W);
-    d.nchc = aos_col_chunks(H);
+    d.nchr = aos_row_chunks(W, kAosShape[shape].rc);
+    d.nchc = aos_col_chunks(H, kAosShape[shape].cc);
     return d;
 }
 
@@ -300,18 +299,29 @@ BatchImage batch_image(int W, int H) {
     return b;
 }
 
-// a3-a5: (conductivity +) chunk reduction, interface solves, recovery.
-// iface_m: chunks per lane of the interface solve the line work list was
-// built for; 0 (no work list, one image) chooses it from the image size.
+// a3-a5: (conductivity +) chunk reduction, interface solves, recovery, on
+// the tiles, chunks and interface lanes of `shape`.
 kaze_status aos_step(const ImageDesc& d, const AosWork& tiles, const AosWork& lines, int shape,
                      const Taps& tc, float tau, bool compute_g, int gmode, float k_host,
-                     hipStream_t s, int iface_m = 0) {
-    const int M = iface_m ? iface_m : iface_m_for(aos_line_groups(d.W, d.H, kIfaceMLarge));
+                     hipStream_t s) {
     KZ_LAUNCH(K_AOS_REDUCE, s,
               launch_aos_reduce(d, tiles, shape, tc, tau, compute_g, gmode, k_host, s));
-    KZ_LAUNCH(K_AOS_IFACE, s, launch_aos_iface(d, lines, M, s));
+    KZ_LAUNCH(K_AOS_IFACE, s, launch_aos_iface(d, lines, shape, s));
     KZ_LAUNCH(K_AOS_RECOVER, s, launch_aos_recover(d, tiles, shape, tau, s));
     return KAZE_OK;
+}
+
+// The shape of single-image calls: the default rule of the interface lanes.
+int default_shape(int W, int H) { return default_shape_for(aos_line_groups(W, H, kAosShape[1])); }
+
+// The default shape of a batch (aos_shape -1): the same rule over the
+// interface wavefronts of all its images.
+int default_batch_shape(const kaze_image_desc* im, int n) {
+    if (!im || n < 1) return 0;
+    long long groups = 0;
+    for (int j = 0; j < n; ++j)
+        if (im[j].W >= 1 && im[j].H >= 1) groups += aos_line_groups(im[j].W, im[j].H, kAosShape[1]);
+    return default_shape_for(groups);
 }
 
 // One FED cycle of total time T (Eq. 5) from L into out with g fixed: the
@@ -387,7 +397,6 @@ struct kaze_batch {
     std::vector<hipEvent_t> ev;      // fork / join points (N + 1)
     bool fork_det = false;           // detector response beside the steps, per level
     int split_det = -1;              // else: levels 0..split_det forked once
-    int iface_m = kIfaceMLarge;      // chunks per lane of the interface solves
     SgBatch* sg = nullptr;           // surrogate steps (kaze_sg_batch_create), or none
 };
 
@@ -426,20 +435,16 @@ struct BatchLayout {
     std::vector<size_t> scratch;  // per image
     size_t total;
     int n_tiles, n_aos, n_lines, n_hist, n_det, n_nms;
-    int iface_m;  // chunks per lane of the interface solves
 };
 
 BatchLayout batch_layout(const kaze_image_desc* im, int n, const kaze_params* p, int shape) {
     BatchLayout L;
     const int N = p->octaves * p->sublevels;
     L.n_tiles = L.n_aos = L.n_lines = L.n_hist = L.n_det = L.n_nms = 0;
-    long long groups_large = 0;
-    for (int j = 0; j < n; ++j) groups_large += aos_line_groups(im[j].W, im[j].H, kIfaceMLarge);
-    L.iface_m = iface_m_for(groups_large);
     for (int j = 0; j < n; ++j) {
         L.n_tiles += tiles_of(im[j].W, im[j].H);
-        L.n_aos += aos_tiles_of(im[j].W, im[j].H, kAosShapeTY[shape]);
-        L.n_lines += aos_line_groups(im[j].W, im[j].H, L.iface_m);
+        L.n_aos += aos_tiles_of(im[j].W, im[j].H, kAosShape[shape].ty);
+        L.n_lines += aos_line_groups(im[j].W, im[j].H, kAosShape[shape]);
         L.n_hist += (im[j].W * im[j].H + kHistChunk - 1) / kHistChunk;
         L.n_det += det_tiles_of(im[j].W, im[j].H);
         L.n_nms += nms_blocks_of(im[j].W, im[j].H, true);
@@ -482,7 +487,7 @@ kaze_status check_batch(const kaze_image_desc* im, int n, const kaze_params* p, 
         if ((st = check_size(d.W, d.H)) != KAZE_OK) return st;
         if (!shape_fits(d.W, d.H, shape))
             return fail(KAZE_ERR_UNSUPPORTED, "image %d (%dx%d) does not fit tile shape %dx%d", j,
-                        d.W, d.H, kAosTX, kAosShapeTY[shape]);
+                        d.W, d.H, kAosTX, kAosShape[shape].ty);
         if (!d.img || !d.levels || !d.k)
             return fail(KAZE_ERR_INVALID_ARG, "image %d: img, levels and k must be non-NULL", j);
         if (d.ld_img < d.W) return fail(KAZE_ERR_INVALID_ARG, "image %d: ld_img < W", j);
@@ -515,7 +520,7 @@ kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStre
         const ImgWork tiles{B.d_imgs, B.d_tiles, B.n_tiles};
         const ImgWork ctiles{B.d_imgs, B.d_aos, B.n_aos};  // the plan's AOS tiles
         const ImgWork hist{B.d_imgs, B.d_hist, B.n_hist};
-        return base_and_k(b0, images, tiles, ctiles, kAosShapeTY[B.shape], hist, p, s);
+        return base_and_k(b0, images, tiles, ctiles, kAosShape[B.shape].ty, hist, p, s);
     }
     const ImgWork det{B.d_imgs, B.d_det, B.n_det};
     DetLevels dl = det_levels(B.lv);
@@ -550,7 +555,7 @@ kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStre
                 const AosWork at{lvl, B.d_aos, B.n_aos};
                 const AosWork al{lvl, B.d_lines, B.n_lines};
                 st = aos_step(a0, at, al, B.shape, tc, (float)(B.lv[i].tau / m), true, gmode, 1.f,
-                              s, B.iface_m);
+                              s);
                 if (st != KAZE_OK) return st;
             }
             if ((st = det_level(i)) != KAZE_OK) return st;
@@ -631,7 +636,6 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
     B->d_det = reinterpret_cast<int2*>(base + L.det);
     B->d_nms = reinterpret_cast<int2*>(base + L.nms);
     B->n_tiles = L.n_tiles;
-    B->iface_m = L.iface_m;
     B->n_aos = L.n_aos;
     B->n_lines = L.n_lines;
     B->n_hist = L.n_hist;
@@ -688,9 +692,10 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
             }
         }
         for (int t = 0; t < tiles_of(d.W, d.H); ++t) ht[it++] = make_int2(j, t);
-        for (int t = 0; t < aos_tiles_of(d.W, d.H, kAosShapeTY[shape]); ++t)
+        for (int t = 0; t < aos_tiles_of(d.W, d.H, kAosShape[shape].ty); ++t)
             ha[ia++] = make_int2(j, t);
-        for (int t = 0; t < aos_line_groups(d.W, d.H, L.iface_m); ++t) hl[il++] = make_int2(j, t);
+        for (int t = 0; t < aos_line_groups(d.W, d.H, kAosShape[shape]); ++t)
+            hl[il++] = make_int2(j, t);
         for (int t = 0; t < (d.W * d.H + kHistChunk - 1) / kHistChunk; ++t) hh[ih++] = make_int2(j, t);
         for (int t = 0; t < det_tiles_of(d.W, d.H); ++t) hd[idt++] = make_int2(j, t);
         for (int t = 0; t < nms_blocks_of(d.W, d.H, true); ++t) hn[inm++] = make_int2(j, t);
@@ -906,7 +911,7 @@ kaze_status sg_chain(const kaze_sg_scale_space& S, const sg::Geo& geo, int i, co
 kaze_status sg_segment(const kaze_sg_scale_space& S, int seg, hipStream_t s) {
     const kaze_params* p = &S.p;
     const ImgWork none{nullptr, nullptr, 0};
-    if (seg == 0) return base_and_k(S.b, none, none, none, kAosShapeTY[0], none, p, s);
+    if (seg == 0) return base_and_k(S.b, none, none, none, kAosShape[0].ty, none, p, s);
     if (seg == 2) {
         if (S.with_det) KZ_LAUNCH(K_DET, s, launch_det(S.b, none, 0, S.N, det_levels(S.lv), s));
         if (S.with_nms)
@@ -926,7 +931,7 @@ kaze_status sg_segment(const kaze_sg_scale_space& S, int seg, hipStream_t s) {
         // conductivity of L_{i-1}: input of the surrogate and of the probe
         BatchImage bc = S.b;
         bc.levels = const_cast<float*>(Lp);
-        KZ_LAUNCH(K_COND, s, launch_cond(bc, none, tc, 1.f, gmode, kAosShapeTY[0], s));
+        KZ_LAUNCH(K_COND, s, launch_cond(bc, none, tc, 1.f, gmode, kAosShape[0].ty, s));
         KZ_LAUNCH(K_SG_PACK, s, sg::launch_pack_input(Lp, S.b.g, S.tau + i, S.x0, nullptr, S.geo, s));
         ImageDesc d = S.aos;
         d.L = Lp;
@@ -1239,7 +1244,7 @@ kaze_status sg_batch_levels(const kaze_batch& B, hipStream_t s) {
         const size_t r0 = (size_t)(i - 1) * n;
         const float tau = (float)B.lv[i].tau;
         const ImgWork ct{G.cond + r0, B.d_aos, B.n_aos};
-        KZ_LAUNCH(K_COND, s, launch_cond(b0, ct, tc, 1.f, gmode, kAosShapeTY[B.shape], s));
+        KZ_LAUNCH(K_COND, s, launch_cond(b0, ct, tc, 1.f, gmode, kAosShape[B.shape].ty, s));
         const sg::SgImage* si = G.img + r0;
         KZ_LAUNCH(K_SG_PACK, s, sg::launch_pack_input_batch(si, n, G.x0, s));
         const ImageDesc* lvl = B.d_lvl + r0;  // one step per level
@@ -1258,7 +1263,7 @@ kaze_status sg_batch_levels(const kaze_batch& B, hipStream_t s) {
         const AosWork at{lvl, B.d_aos, B.n_aos};
         const AosWork al{lvl, B.d_lines, B.n_lines};
         // g of L_{i-1} is already in every image's plane: the step reads it
-        st = aos_step(a0, at, al, B.shape, tc, tau, false, gmode, 1.f, s, B.iface_m);
+        st = aos_step(a0, at, al, B.shape, tc, tau, false, gmode, 1.f, s);
         if (st != KAZE_OK) return st;
     }
     return KAZE_OK;
@@ -1276,7 +1281,8 @@ kaze_status check_scale_space_args(const float* img, int W, int H, int ld_img,
     if (ld_img < W) return fail(KAZE_ERR_INVALID_ARG, "ld_img (%d) < W (%d)", ld_img, W);
     if (!aligned(img, 4) || !aligned(levels, 4) || !aligned(k_out, 4))
         return fail(KAZE_ERR_INVALID_ARG, "float buffers must be 4-byte aligned");
-    *need = scratch_layout(W, H, hist_bins(p), 0, 0, p->scheme == KAZE_FED, p->substeps > 1).total;
+    *need = scratch_layout(W, H, hist_bins(p), default_shape(W, H), 0, p->scheme == KAZE_FED,
+                           p->substeps > 1).total;
     return KAZE_OK;
 }
 
@@ -1286,7 +1292,8 @@ kaze_status scale_space_launches(const float* img, int W, int H, int ld_img,
                                  hipStream_t s) {
     const bool fed = p->scheme == KAZE_FED;
     const int m = p->substeps;
-    const Scratch w = scratch_layout(W, H, hist_bins(p), 0, 0, fed, m > 1);
+    const int shape = default_shape(W, H);
+    const Scratch w = scratch_layout(W, H, hist_bins(p), shape, 0, fed, m > 1);
     BatchImage b = batch_image(W, H);
     b.img = img;
     b.ld = ld_img;
@@ -1296,7 +1303,7 @@ kaze_status scale_space_launches(const float* img, int W, int H, int ld_img,
     b.hmax = reinterpret_cast<unsigned*>(base + w.hmax);
     b.k = k_out;
     const ImgWork none{nullptr, nullptr, 0};
-    kaze_status st = base_and_k(b, none, none, none, kAosShapeTY[0], none, p, s);
+    kaze_status st = base_and_k(b, none, none, none, kAosShape[shape].ty, none, p, s);
     if (st != KAZE_OK) return st;
 
     std::vector<Level> lv;
@@ -1304,7 +1311,7 @@ kaze_status scale_space_launches(const float* img, int W, int H, int ld_img,
     const size_t plane = (size_t)W * H;
     const Taps tc = gauss_taps(p->sigma_cond);
     const int gmode = p->diffusivity == KAZE_G2 ? 0 : 1;
-    ImageDesc d = aos_desc(W, H, 0, base, w, k_out);
+    ImageDesc d = aos_desc(W, H, shape, base, w, k_out);
     const AosWork anone{nullptr, nullptr, 0};
     float* mid = reinterpret_cast<float*>(base + w.sub);
     for (size_t i = 1; i < lv.size(); ++i) {
@@ -1321,10 +1328,10 @@ kaze_status scale_space_launches(const float* img, int W, int H, int ld_img,
             if (fed) {
                 BatchImage bc = b;
                 bc.levels = const_cast<float*>(src);  // conductivity of the step's start
-                KZ_LAUNCH(K_COND, s, launch_cond(bc, none, tc, 1.f, gmode, kAosShapeTY[0], s));
+                KZ_LAUNCH(K_COND, s, launch_cond(bc, none, tc, 1.f, gmode, kAosShape[shape].ty, s));
                 st = fed_cycle(src, b.g, dst, reinterpret_cast<float*>(base + w.tmp), W, H, tau, s);
             } else {
-                st = aos_step(d, anone, anone, 0, tc, (float)tau, true, gmode, 1.f, s);
+                st = aos_step(d, anone, anone, shape, tc, (float)tau, true, gmode, 1.f, s);
             }
             if (st != KAZE_OK) return st;
             src = dst;
@@ -1417,7 +1424,9 @@ kaze_status kaze_schedule(const kaze_params* p, double* sigma, double* t, double
 
 size_t kaze_workspace_bytes(int W, int H, const kaze_params* p) {
     if (check_params(p) != KAZE_OK || check_size(W, H) != KAZE_OK) return 0;
-    return scratch_layout(W, H, hist_bins(p), 0, 0, p->scheme == KAZE_FED, p->substeps > 1).total;
+    return scratch_layout(W, H, hist_bins(p), default_shape(W, H), 0, p->scheme == KAZE_FED,
+                          p->substeps > 1)
+        .total;
 }
 
 kaze_status kaze_build_scale_space(const float* img, int W, int H, int ld_img,
@@ -1466,7 +1475,7 @@ kaze_status kaze_conductivity(const float* L, int W, int H, const kaze_params* p
     const int gmode = p->diffusivity == KAZE_G2 ? 0 : 1;
     const ImgWork none{nullptr, nullptr, 0};
     KZ_LAUNCH(K_COND, s,
-              launch_cond(b, none, gauss_taps(p->sigma_cond), (float)k, gmode, kAosShapeTY[0], s));
+              launch_cond(b, none, gauss_taps(p->sigma_cond), (float)k, gmode, kAosShape[0].ty, s));
     return KAZE_OK;
 }
 
@@ -1480,16 +1489,17 @@ kaze_status kaze_aos_step(const float* L, const float* g, int W, int H, double t
     if (!(tau > 0.0) || !isfinite(tau)) return fail(KAZE_ERR_INVALID_ARG, "tau must be > 0");
     kaze_params p;
     kaze_default_params(&p);
-    const Scratch w = scratch_layout(W, H, hist_bins(&p), 0, 0);
+    const int shape = default_shape(W, H);
+    const Scratch w = scratch_layout(W, H, hist_bins(&p), shape, 0);
     if (!ws || !aligned(ws, 256) || ws_bytes < w.total)
         return fail(KAZE_ERR_WORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
                     w.total, ws_bytes);
-    ImageDesc d = aos_desc(W, H, 0, static_cast<char*>(ws), w, nullptr);
+    ImageDesc d = aos_desc(W, H, shape, static_cast<char*>(ws), w, nullptr);
     d.L = L;
     d.Lnext = L_next;
     d.g = const_cast<float*>(g);  // read only when the conductivity is given
     const AosWork anone{nullptr, nullptr, 0};
-    return aos_step(d, anone, anone, 0, gauss_taps(p.sigma_cond), (float)tau, false, 0, 1.f,
+    return aos_step(d, anone, anone, shape, gauss_taps(p.sigma_cond), (float)tau, false, 0, 1.f,
                     static_cast<hipStream_t>(stream));
 }
 
@@ -1648,6 +1658,19 @@ kaze_status kaze_find_extrema(const float* det, int W, int H, const kaze_params*
 }
 
 // ---------------------------------------------------------------- batches
+kaze_status kaze_aos_shape_info(int shape, int* tile_w, int* tile_h, int* row_chunk,
+                                int* col_chunk, int* iface_m) {
+    if (shape < 0 || shape >= kAosShapes)
+        return fail(KAZE_ERR_INVALID_ARG, "AOS shape %d outside [0, %d)", shape, kAosShapes);
+    const AosShape& a = kAosShape[shape];
+    if (tile_w) *tile_w = kAosTX;
+    if (tile_h) *tile_h = a.ty;
+    if (row_chunk) *row_chunk = a.rc;
+    if (col_chunk) *col_chunk = a.cc;
+    if (iface_m) *iface_m = a.m;
+    return KAZE_OK;
+}
+
 size_t kaze_batch_workspace_bytes(const kaze_image_desc* images, int n, const kaze_params* p,
                                   const kaze_batch_config* cfg) {
     if (check_params(p) != KAZE_OK || p->scheme != KAZE_AOS || !images || n < 1) return 0;
@@ -1666,7 +1689,7 @@ size_t kaze_batch_workspace_bytes(const kaze_image_desc* images, int n, const ka
 kaze_status kaze_batch_create(const kaze_image_desc* images, int n, const kaze_params* p,
                               const kaze_batch_config* cfg, void* ws, size_t ws_bytes,
                               kaze_batch** out) {
-    const int shape = cfg && cfg->aos_shape >= 0 ? cfg->aos_shape : 0;
+    const int shape = cfg && cfg->aos_shape >= 0 ? cfg->aos_shape : default_batch_shape(images, n);
     return batch_create(images, n, p, shape, ws, ws_bytes, out);
 }
 
@@ -1763,7 +1786,7 @@ size_t kaze_sg_scale_space_workspace_bytes(int W, int H, const kaze_params* p,
     if (check_params(p) != KAZE_OK || p->scheme != KAZE_AOS || p->substeps != 1 ||
         check_sg_config(c) != KAZE_OK || check_size(W, H) != KAZE_OK)
         return 0;
-    const int shape = c->aos_shape >= 0 ? c->aos_shape : 0;
+    const int shape = c->aos_shape >= 0 ? c->aos_shape : default_shape(W, H);
     if (!shape_fits(W, H, shape)) return 0;
     return sg_layout(W, H, p, c, shape).total;
 }
@@ -1779,7 +1802,7 @@ kaze_status kaze_sg_scale_space_destroy(kaze_sg_scale_space* S) {
 size_t kaze_sg_batch_workspace_bytes(const kaze_image_desc* images, int n, const kaze_params* p,
                                      const kaze_sg_config* c) {
     if (check_sg_config(c) != KAZE_OK) return 0;
-    const int shape = c->aos_shape >= 0 ? c->aos_shape : 0;
+    const int shape = c->aos_shape >= 0 ? c->aos_shape : default_batch_shape(images, n);
     if (check_batch(images, n, p, shape) != KAZE_OK) return 0;
     return batch_layout(images, n, p, shape).total + sg_batch_bytes(images, n, p, c);
 }
@@ -1791,8 +1814,8 @@ kaze_status kaze_sg_batch_create(const kaze_image_desc* images, int n, const kaz
     const kaze_status st = check_sg_config(c);
     if (st != KAZE_OK) return st;
     const SgSpec sp{c, packed, probe_xy, err};
-    return batch_create(images, n, p, c->aos_shape >= 0 ? c->aos_shape : 0, ws, ws_bytes, out,
-                        &sp);
+    const int shape = c->aos_shape >= 0 ? c->aos_shape : default_batch_shape(images, n);
+    return batch_create(images, n, p, shape, ws, ws_bytes, out, &sp);
 }
 
 kaze_status kaze_sg_scale_space_create(const kaze_image_desc* im, const kaze_params* p,
@@ -1812,7 +1835,7 @@ kaze_status kaze_sg_scale_space_create(const kaze_image_desc* im, const kaze_par
     if (!im) return fail(KAZE_ERR_INVALID_ARG, "image descriptor is NULL");
     const int W = im->W, H = im->H;
     if ((st = check_size(W, H)) != KAZE_OK) return st;
-    const int shape = c->aos_shape >= 0 ? c->aos_shape : 0;
+    const int shape = c->aos_shape >= 0 ? c->aos_shape : default_shape(W, H);
     if (!shape_fits(W, H, shape))
         return fail(KAZE_ERR_UNSUPPORTED, "image does not fit AOS tile shape %d", shape);
     if (!im->img || !im->levels || !im->k)

@@ -184,19 +184,27 @@ struct BatchImage {
     int W, H;
 };
 
-// AOS line partition: every row line is cut into chunks of kRowChunk pixels,
-// every column line into chunks of kColChunk pixels.  The reduction and
-// recovery tiles are kAosTX pixels wide (two row chunks) and
-// kAosShapeTY[shape] high (one or two column chunks); the partition of the
-// lines, and so the arithmetic, is the same for every shape.
+// AOS line partition and launch shapes.  Every row line is cut into chunks
+// of rc pixels and every column line into chunks of cc pixels; the
+// reduction and recovery tiles are kAosTX pixels wide (kAosTX / rc row
+// chunks per tile row) and ty high (ty / cc column chunks per tile column);
+// the interface solve gives every lane m consecutive chunks of a line.  The
+// chunk lengths and m fix the arithmetic (the elimination order), the tile
+// height only the launch: shapes that differ in ty alone give bitwise equal
+// results, the others agree to FP32 rounding.
+struct AosShape {
+    int ty, rc, cc, m;
+};
 constexpr int kAosTX = 60;
-constexpr int kRowChunk = 30;
-constexpr int kColChunk = 32;
-constexpr int kAosShapes = 2;
-constexpr int kAosShapeTY[kAosShapes] = {32, 64};
+constexpr int kAosShapes = 6;
+constexpr AosShape kAosShape[kAosShapes] = {
+    {32, 30, 32, 4}, {32, 30, 32, 8}, {64, 30, 32, 4},
+    {64, 30, 32, 8}, {64, 60, 64, 4}, {64, 60, 64, 8},
+};
+constexpr int kMaxColChunk = 64;
 
-__host__ __device__ inline int aos_row_chunks(int W) { return (W + kRowChunk - 1) / kRowChunk; }
-__host__ __device__ inline int aos_col_chunks(int H) { return (H + kColChunk - 1) / kColChunk; }
+__host__ __device__ inline int aos_row_chunks(int W, int rc) { return (W + rc - 1) / rc; }
+__host__ __device__ inline int aos_col_chunks(int H, int cc) { return (H + cc - 1) / cc; }
 __host__ __device__ inline int aos_tiles_of(int W, int H, int ty) {
     return ((W + kAosTX - 1) / kAosTX) * ((H + ty - 1) / ty);
 }
@@ -204,11 +212,11 @@ __host__ __device__ inline int aos_tiles_of(int W, int H, int ty) {
 // line spans iface_lanes(chunks, M) lanes (a power of two), so a wavefront
 // serves 64 / iface_lanes lines of one direction of one image.  Work items:
 // the row-line groups of the image, then its column-line groups.
-// Chunks per lane M: 8, or 4 for launches with few wavefronts, where the
-// shorter lane-local elimination and the doubled number of wavefronts win
-// (measured at 1920x1200: 9.5 -> 8.4 us per level, 1659 -> 1716 images/s;
-// on the 64-image batch 8 stays ahead, 597 against 607 us per level).
-constexpr int kIfaceMSmall = 4, kIfaceMLarge = 8;
+// Default shape (aos_shape -1): 60 x 32 tiles, chunks of 30 / 32, and M = 8,
+// or M = 4 for launches with few wavefronts, where the shorter lane-local
+// elimination and the doubled number of wavefronts win (measured at
+// 1920x1200: 9.5 -> 8.4 us per level; on the 64-image batch 8 stays ahead,
+// 597 against 607 us per level).
 constexpr int kIfaceSmallGroups = 1024;  // wavefronts at M = 8 below which M = 4
 __host__ __device__ inline int iface_lanes(int nch, int M) {
     int p = 1;
@@ -219,11 +227,15 @@ __host__ __device__ inline int iface_groups(int lines, int nch, int M) {
     const int per = 64 / iface_lanes(nch, M);
     return (lines + per - 1) / per;
 }
-inline int aos_line_groups(int W, int H, int M) {
-    return iface_groups(H, aos_row_chunks(W), M) + iface_groups(W, aos_col_chunks(H), M);
+inline int aos_line_groups(int W, int H, const AosShape& a) {
+    return iface_groups(H, aos_row_chunks(W, a.rc), a.m) +
+           iface_groups(W, aos_col_chunks(H, a.cc), a.m);
 }
-inline int iface_m_for(long long groups_at_large) {
-    return groups_at_large < kIfaceSmallGroups ? kIfaceMSmall : kIfaceMLarge;
+// The default shape for images whose interface launch would have this many
+// wavefronts with M = 8: shape 1 (M = 8), or shape 0 (M = 4) below
+// kIfaceSmallGroups.
+inline int default_shape_for(long long groups_at_m8) {
+    return groups_at_m8 < kIfaceSmallGroups ? 0 : 1;
 }
 
 // The two reduced equations of a chunk (first and last unknown), each scaled
@@ -356,7 +368,7 @@ hipError_t launch_kselect(const BatchImage& d0, const ImgWork& w, int nbins,
 hipError_t launch_reset(const BatchImage& d0, const ImgWork& w, int nbins, float k_fill,
                         hipStream_t s);
 
-// a3-a5: AOS step in three launches on tiles of kAosTX x kAosShapeTY[shape].
+// a3-a5: AOS step in three launches on tiles of kAosTX x kAosShape[shape].ty.
 // reduce: (conductivity if compute_g, else g is read) + chunk reduction of
 // every row and column chunk (items: image, tile); iface: the interface
 // system of every line (items: image, group of lines, row groups first, see
@@ -364,7 +376,7 @@ hipError_t launch_reset(const BatchImage& d0, const ImgWork& w, int nbins, float
 // L_next = L + (delta_x + delta_y)/2 (items: image, tile).
 hipError_t launch_aos_reduce(const ImageDesc& d0, const AosWork& w, int shape, const Taps& tc,
                              float tau, bool compute_g, int gmode, float k_host, hipStream_t s);
-hipError_t launch_aos_iface(const ImageDesc& d0, const AosWork& w, int M, hipStream_t s);
+hipError_t launch_aos_iface(const ImageDesc& d0, const AosWork& w, int shape, hipStream_t s);
 hipError_t launch_aos_recover(const ImageDesc& d0, const AosWork& w, int shape, float tau,
                               hipStream_t s);
 

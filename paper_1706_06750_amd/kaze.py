@@ -36,7 +36,7 @@ EXPORTS = (
     "kaze_kernel_names", "kaze_copy_f32", "kaze_batch_workspace_bytes",
     "kaze_batch_create", "kaze_batch_run", "kaze_batch_destroy", "kaze_batch_autotune",
     "kaze_batch_properties", "kaze_fed_schedule", "kaze_fed_cycle", "kaze_refine_keypoints",
-    "kaze_derivatives", "kaze_describe_keypoints",
+    "kaze_derivatives", "kaze_describe_keypoints", "kaze_aos_shape_info",
 )
 
 
@@ -85,9 +85,6 @@ class kaze_batch_config(ctypes.Structure):
     _fields_ = [("aos_shape", ctypes.c_int)]
 
 
-# Block tile (width x height) of each kaze_batch_config.aos_shape; rows are
-# cut into chunks of 30 pixels and columns into chunks of 32 for every shape.
-AOS_SHAPES = ((60, 32), (60, 64))
 
 
 def _load():
@@ -125,6 +122,7 @@ def _load():
         "kaze_batch_properties": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "kaze_batch_destroy": (i32, [vp]),
         "kaze_batch_autotune": (i32, [vp, i32, P, vp, sz, i32, vp, vp, vp]),
+        "kaze_aos_shape_info": (i32, [i32] + [ctypes.POINTER(i32)] * 5),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -134,6 +132,29 @@ def _load():
 
 
 lib = _load()
+
+
+def _shape_table():
+    out = []
+    for sh in range(64):
+        v = [ctypes.c_int() for _ in range(5)]
+        if lib.kaze_aos_shape_info(sh, *[ctypes.byref(x) for x in v]) != KAZE_OK:
+            break
+        out.append(dict(zip(("tile_w", "tile_h", "row_chunk", "col_chunk", "iface_m"),
+                            (x.value for x in v))))
+    return tuple(out)
+
+
+# Launch shapes of the AOS steps (kaze_batch_config.aos_shape): tile width
+# and height, chunk lengths of rows and columns, interface chunks per lane.
+AOS_SHAPES = _shape_table()
+
+
+def shape_label(shape: int) -> str:
+    """e.g. '60x32 c30/32 m4'."""
+    a = AOS_SHAPES[shape]
+    return "%dx%d c%d/%d m%d" % (a["tile_w"], a["tile_h"], a["row_chunk"], a["col_chunk"],
+                                 a["iface_m"])
 
 
 def _check(st):
@@ -434,7 +455,8 @@ class KazeBatch:
 
     ``sizes`` is a list of (W, H).  Per-image device buffers are allocated
     here (torch); ``inputs[j]`` is image j's input tensor [H][W] to fill
-    before ``run()``.  ``shape`` selects the row/column tile shape (0-3);
+    before ``run()``.  ``shape`` selects the launch shape of the line
+    solves (an index of AOS_SHAPES);
     ``shape="auto"`` runs the library's autotuner, caching the choice in the
     JSON file ``tune_cache`` when given (keyed by GPU architecture and the
     list of sizes).  With ``ld_pad`` > 0 each input is a view of W columns
@@ -485,7 +507,7 @@ class KazeBatch:
         import torch
         arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName
         sig = hashlib.sha1(repr(sorted(self.sizes)).encode()).hexdigest()[:16]
-        return "%s|n=%d|%s" % (arch, len(self.sizes), sig)
+        return "%s|n=%d|%s|shapes=%d" % (arch, len(self.sizes), sig, len(AOS_SHAPES))
 
     def _tuned_shape(self, cache_path):
         import json
@@ -500,7 +522,8 @@ class KazeBatch:
         best, ms = kaze_batch_autotune(self.descs, self.p, self.ws, self.ws_bytes)
         self.tune_ms = ms
         if cache_path:
-            cache[key] = {"shape": best, "ms": ms, "tile": AOS_SHAPES[best]}
+            cache[key] = {"shape": best, "ms": ms, "label": shape_label(best),
+                          "labels": [shape_label(i) for i in range(len(AOS_SHAPES))]}
             tmp = cache_path + ".tmp"
             with open(tmp, "w") as fh:
                 json.dump(cache, fh, indent=1)

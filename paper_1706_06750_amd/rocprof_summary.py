@@ -66,21 +66,36 @@ def stats(path: str) -> str:
     return "\n".join(out)
 
 
-def counter_means(path: str, counter: str, aos_tile: str | None = None):
-    """Mean counter value per dispatch, by kernel.  With aos_tile ("60x32")
-    only the AOS kernels instantiated for that tile height count (the
-    autotuner runs every shape first)."""
+def parse_shape(label: str):
+    """'60x32 c30/32 m4' -> (tile height, row chunk, column chunk, interface
+    chunks per lane) as strings."""
+    tile, chunks, m = label.split()
+    rc, cc = chunks[1:].split("/")
+    return tile.split("x")[1], rc, cc, m[1:]
+
+
+def template_args(name: str):
+    return [a.strip() for a in name.split("<", 1)[1].rsplit(">", 1)[0].split(",")]
+
+
+def counter_means(path: str, counter: str, aos_shape: str | None = None):
+    """Mean counter value per dispatch, by kernel.  With aos_shape (a shape
+    label, '60x32 c30/32 m4') only the AOS kernels instantiated for that
+    shape count (the autotuner runs every shape first):
+    aos_reduce_kernel<RG, TY, RC, CC, CG, GM>, aos_iface_kernel<M>,
+    aos_recover_kernel<TY, RC, CC>."""
     acc = collections.defaultdict(list)
-    ty = aos_tile.split("x")[1] if aos_tile else None
+    want = parse_shape(aos_shape) if aos_shape else None
     for r in csv.DictReader(open(path)):
         if r.get("Counter_Name", r.get("counter_name")) != counter:
             continue
         name = short(r.get("Kernel_Name", r.get("kernel_name")))
         base = name.split("<")[0]
-        # aos_reduce_kernel<RG, TY, CG, GM>, aos_recover_kernel<TY>
-        if ty and base == "aos_reduce_kernel" and name.split("<")[1].split(",")[1].strip() != ty:
+        if want and base == "aos_reduce_kernel" and tuple(template_args(name)[1:4]) != want[:3]:
             continue
-        if ty and base == "aos_recover_kernel" and name.split("<")[1].rstrip(">").strip() != ty:
+        if want and base == "aos_recover_kernel" and tuple(template_args(name)) != want[:3]:
+            continue
+        if want and base == "aos_iface_kernel" and template_args(name)[0] != want[3]:
             continue
         acc[base].append(float(r.get("Counter_Value", r.get("value"))))
     return {k: sum(v) / len(v) for k, v in acc.items()}
@@ -103,7 +118,7 @@ def counter_totals(path: str, counter: str):
 def traffic(fetch_csv, write_csv, W, H, copy_mib, root, aos_tile, det_levels=0, pixels=0,
             levels=16):
     """Bytes per step of the level segment: the AOS kernels' mean dispatch
-    (the chosen tile only) plus, when det_levels detector levels run inside
+    (the chosen launch shape only) plus, when det_levels detector levels run inside
     the segment, their share: the detector's bytes per run (every run holds
     levels - 1 reductions, whatever the shape) / levels * det_levels, spread
     over the levels - 1 steps."""
@@ -146,7 +161,8 @@ def main():
     b.add_argument("write_csv")
     b.add_argument("--image", required=True, help="WxH of the single image, or a workload name")
     b.add_argument("--copy-mib", type=int, required=True)
-    b.add_argument("--aos-tile", required=True, help="AOS tile shape of the run, e.g. 60x32")
+    b.add_argument("--aos-tile", required=True,
+                   help="AOS launch shape of the run, e.g. '60x32 c30/32 m4'")
     b.add_argument("--det-levels", type=int, default=0,
                    help="detector levels that run inside the level segment (the batch's "
                         "det_levels_in_segment property)")
