@@ -218,21 +218,29 @@ def record(args, value, ms_per_step, config, roofline, extra):
 
 
 def timed_runs(args, K, torch, kb, eager):
-    """Timed region: runs of the plan (eager launches or graph replays); an
-    event pair brackets the AOS-step segment of every run on the stream it
-    runs on.  Returns (seconds, microseconds per level)."""
-    for _ in range(args.warmup):
+    """Timed region: runs of the plan (eager launches or graph replays), each
+    followed by the readback of every image's keypoint count into pinned
+    host memory (an asynchronous copy on the run's stream); an event pair
+    brackets the AOS-step segment of every run on the stream it runs on.
+    Returns (seconds, microseconds per level)."""
+    counts = torch.empty((max(args.steps, args.warmup), kb.counts.numel()), dtype=torch.int32,
+                         pin_memory=True)
+    for i in range(args.warmup):
         kb.run(eager=eager)
+        counts[i].copy_(kb.counts, non_blocking=True)
     torch.cuda.synchronize()
     K.kaze_profile_begin("aos_reduce")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         kb.run(eager=eager)
+        counts[i].copy_(kb.counts, non_blocking=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     runs, ms = K.kaze_profile_end()
     assert runs == args.steps
+    if not torch.equal(counts[args.steps - 1], kb.counts.cpu()):
+        raise RuntimeError("keypoint counts read back in the timed region disagree")
     return elapsed, 1e3 * ms / (runs * (kb.N - 1))
 
 

@@ -470,14 +470,16 @@ class KazeBatch:
         self.sizes = [(int(w), int(h)) for w, h in sizes]
         dev = torch.device(device)
         self.inputs, self.levels, self.det, self.k, self.kps, self.count = [], [], [], [], [], []
+        # every image's keypoint count in one tensor (one readback per run)
+        self.counts = torch.zeros(len(self.sizes), dtype=torch.int32, device=dev)
         descs = []
-        for W, H in self.sizes:
+        for j, (W, H) in enumerate(self.sizes):
             x = torch.zeros((H, W + int(ld_pad)), dtype=torch.float32, device=dev)[:, :W]
             lv = torch.empty((self.N, H, W), dtype=torch.float32, device=dev)
             dt = torch.empty_like(lv) if with_detector else None
             k = torch.empty(1, dtype=torch.float32, device=dev)
             kp = torch.empty((max(capacity, 1), 4), dtype=torch.int32, device=dev)
-            ct = torch.zeros(1, dtype=torch.int32, device=dev)
+            ct = self.counts[j:j + 1]
             self.inputs.append(x)
             self.levels.append(lv)
             self.det.append(dt)

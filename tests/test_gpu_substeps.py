@@ -54,9 +54,15 @@ def test_one_substep_is_the_default_path(gpu_lib):
     assert torch.equal(a.levels[0], c.levels[0]) and not torch.equal(a.levels[1:], c.levels[1:])
 
 
-@pytest.mark.parametrize("shape", [0, 1])
+@pytest.mark.parametrize("shape", [0, 2])
 def test_substeps_batch_equals_single(gpu_lib, shape):
+    """Sub-steps in a batch plan, bitwise against the single-image calls:
+    shapes 0 and 2 (tiles 60x32 and 60x64) share the chunk lengths and the
+    interface lanes of the single-image default at these sizes, so both
+    evaluate the same arithmetic."""
     K = gpu_lib
+    ref_shape = K.AOS_SHAPES[0]
+    assert all(K.AOS_SHAPES[shape][k] == ref_shape[k] for k in ("row_chunk", "col_chunk", "iface_m"))
     p = K.kaze_default_params(substeps=3)
     sizes = [(160, 120), (67, 45), (31, 33)]
     kb = K.KazeBatch(sizes, params=p, shape=shape)
