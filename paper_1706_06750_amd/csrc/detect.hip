@@ -5,133 +5,332 @@
 //   D_x f(x,y) = sum_{dy in -s,0,s} w_dy (f(x+s, y+dy) - f(x-s, y+dy)) / (2s),
 //   w = (3, 10, 3)/16,
 // and every derivative image is extended by half-sample reflection before the
-// next derivative is taken.  One block per 64x32 tile and level computes the
-// first derivatives of the tile plus an s ring in LDS, then the second
-// derivatives and det; L_x, L_y, L_xx, ... never reach memory.
+// next derivative is taken.  L_x, L_y, L_xx, ... never reach memory.
 #include <algorithm>
 #include <type_traits>
 
 #include "kaze_internal.h"
-#include "tile_stage.h"
 
 namespace kaze {
 namespace {
 
-constexpr int DTX = 64;
-constexpr int DTY = 32;
-// Threads of a detector block (512 measured 3% slower than 256 here, where
-// the smoothing and conductivity tiles gain from 512).
+// Threads of a detector block: four independent wavefronts.
 constexpr int kDetThreads = 256;
+constexpr int kDetWaves = kDetThreads / kWave;
 
+__device__ __forceinline__ float scharr3(float a0, float a1, float a2) {
+    return 0.1875f * a0 + 0.625f * a1 + 0.1875f * a2;
+}
+
+// Raw buffer access to one plane: the resource in scalar registers, the
+// row's byte offset in a scalar register, the lane's byte offset in a vector
+// register (no 64-bit address arithmetic per lane).  A lane offset at or
+// past the plane's bytes reads 0 and writes nothing.
+constexpr int kBufWord3 = 0x00020000;  // raw 32-bit buffer (gfx9)
+constexpr unsigned kBufOff = 0x80000000u;  // a lane offset past every plane
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_buffer(const float* p, int W, int H) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), 0, W * H * 4, kBufWord3);
+}
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff,
+                                          unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, unsigned voff,
+                                          unsigned soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+
+// Index i reflected once (half-sample symmetric) into [0, n): |i| <= n and
+// i < 2n.
+__device__ __forceinline__ int reflect1(int i, int n) {
+    return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i);
+}
+
+// A wave-uniform 64-bit word into lane t of (lo, hi): two v_writelane_b32
+// with the lane in M0 (no other code of this file uses M0).
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void place_word(unsigned long long word, int t, unsigned& lo,
+                                           unsigned& hi) {
+    const unsigned wl = (unsigned)word, wh = (unsigned)(word >> 32);
+    asm volatile(
+        "s_mov_b32 m0, %4\n\ts_nop 0\n\t"
+        "v_writelane_b32 %0, %2, m0\n\tv_writelane_b32 %1, %3, m0"
+        : "+v"(lo), "+v"(hi)
+        : "s"(wl), "s"(wh), "s"(t)
+        : "m0");
+}
+#pragma clang diagnostic pop
+
+// Exchange between the lanes of one wavefront through LDS: the LDS executes
+// a wavefront's instructions in order, and this fence keeps the compiler from
+// moving its LDS accesses across the exchange.
+__device__ __forceinline__ void wave_lds_sync() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+
+// ---------------------------------------------------------------------------
+// Strip form.  One wavefront computes det for an output strip of
+// SW = 64 - 2S columns and a band of B rows of one level.  Lane l holds the
+// first derivatives of column fx = x0 - S + l (the strip plus an S ring on
+// each side) and the wavefront walks down the rows of the band:
+//
+//  * per row of L (staged in an LDS row private to the wavefront, the 2S
+//    columns past the last lane included):
+//      dL = L(fx+S) - L(fx-S),   sL = scharr3(L(fx-S), L(fx), L(fx+S));
+//  * per row of first derivatives (rows of L at -S, 0, +S), each 2S times
+//    the derivative:
+//      Lx' = scharr3(dL[-S], dL[0], dL[+S]),   Ly' = sL[+S] - sL[-S],
+//    staged in LDS so that lane l reads lanes l - S and l + S:
+//      dX = Lx'(+S) - Lx'(-S),   wX = scharr3(Lx'(-S), Lx', Lx'(+S)),
+//      wY = scharr3(Ly'(-S), Ly', Ly'(+S));
+//  * per output row (first-derivative rows at -S, 0, +S):
+//      Lxx' = scharr3(dX[-S], dX[0], dX[+S]),  Lxy' = wX[+S] - wX[-S],
+//      Lyy' = wY[+S] - wY[-S],
+//      det = sigma_n^2 / (2S)^4 (Lxx' Lyy' - Lxy'^2).
+//
+// dL, sL, dX, wX, wY live in register rings over rows.  Reflection: L is
+// read at reflected rows and columns; a first derivative outside the image
+// is the derivative at the reflected position (the derivative image is
+// extended before the second derivative), taken horizontally through the
+// lane each output lane reads (reflected lane numbers fixed per wavefront)
+// and vertically by reading the reflected row of the rings.  The last strip
+// ends at column W and the last band at row H, so the reflected ring rows
+// are known at compile time; an output pixel (and its mask bit) is stored by
+// the one strip and band that own it.
+constexpr int kDetBand = 64;       // rows per band
+constexpr int kDetBandSmall = 8;   // rows per band of images lower than that allows
+
+// Rows per band for images of height H at step S: bands of B rows need
+// H == B or H >= B + S (only the first band meets the top border, only the
+// last the bottom one) and H >= 2S (rows of L one reflection away); lower
+// images take the per-pixel form (0).
+__host__ __device__ inline int det_band_rows(int H, int S) {
+    if (H == kDetBand || H >= kDetBand + S) return kDetBand;
+    if ((H == kDetBandSmall || H >= kDetBandSmall + S) && H >= 2 * S) return kDetBandSmall;
+    return 0;
+}
+
+__host__ __device__ inline int det_units(int W, int H, int S) {
+    const int b = det_band_rows(H, S);
+    return det_strips(W, S) * (b ? (H + b - 1) / b : 1);
+}
+
+// Output columns owned by strip j of ns ([c_lo, c_hi)) and its first column
+// x0: regular strips at j * SW, the last one aligned to end at W.
+__device__ __forceinline__ void strip_span(int W, int SW, int ns, int j, int& x0, int& c_lo,
+                                           int& c_hi) {
+    if (j == ns - 1) {
+        x0 = W > SW ? W - SW : 0;
+        c_lo = x0;
+        c_hi = W;
+    } else {
+        x0 = j * SW;
+        c_lo = x0;
+        c_hi = min(x0 + SW, W - SW);
+    }
+}
+
+// Lane holding first-derivative column c (reflected into the image) in a
+// strip whose lane 0 holds column x0 - S.
+__device__ __forceinline__ int deriv_lane(int c, int W, int x0, int S) {
+    const int l = reflect_index(c, W) - x0 + S;
+    return l < 0 ? 0 : (l > kWave - 1 ? kWave - 1 : l);
+}
+
+template <int S, int B>
+__device__ __forceinline__ void det_strip_band(const BatchImage& d, int lev, int unit,
+                                               const DetLevels& dl, float* wl, int lane) {
+    constexpr int SW = kWave - 2 * S;
+    constexpr int NL = B + 4 * S;  // rows of L
+    constexpr int NF = B + 2 * S;  // rows of first derivatives
+    static_assert(SW > 0 && B >= S, "strip and band hold the step");
+    const int W = d.W, H = d.H;
+    const int ns = det_strips(W, S), nb = (H + B - 1) / B;
+    const int j = unit % ns, b = unit / ns;
+    int x0, c_lo, c_hi;
+    strip_span(W, SW, ns, j, x0, c_lo, c_hi);
+    const bool last_b = b == nb - 1;
+    const int y0 = last_b ? H - B : b * B;
+    const int row_hi = last_b ? H : min(y0 + B, H - B);  // owned rows [y0, row_hi)
+    const bool top = y0 == 0, bot = last_b;
+    const int fx = x0 - S + lane;
+    const bool own_lane = lane >= S && lane < kWave - S && fx >= c_lo && fx < c_hi;
+    const unsigned ca = 4u * reflect_index(x0 - 2 * S + lane, W);  // byte offsets
+    const unsigned cb = 4u * reflect_index(x0 + kWave - 2 * S + min(lane, 2 * S - 1), W);
+    const unsigned co = own_lane ? 4u * fx : kBufOff;  // other lanes store nothing
+    const unsigned long long own_bits = __builtin_amdgcn_ballot_w64(own_lane);
+    const int am = deriv_lane(fx - S, W, x0, S), ap = deriv_lane(fx + S, W, x0, S);
+    const size_t plane = (size_t)W * H;
+    const __amdgpu_buffer_rsrc_t rL = plane_buffer(d.levels + plane * lev, W, H);
+    const __amdgpu_buffer_rsrc_t rD = plane_buffer(d.det + plane * lev, W, H);
+    const float scale = dl.sn2[lev] * (1.f / (16.f * S * S * S * S));
+    const float thr = dl.thr;
+    float* lrow = wl;               // L(x0 - 2S + i), i < 64 + 2S
+    float* frx = wl + 2 * kWave;    // Lx' of the lanes
+    float* fry = wl + 3 * kWave;    // Ly' of the lanes
+
+    constexpr int D = 6;  // rows of L in flight
+    float qa[D], qb[D];
+    auto issue = [&](int k) {
+        const int y = y0 - 2 * S + k;
+        const unsigned ro = 4u * (unsigned)uniform(reflect1(y, H) * W);
+        qa[k % D] = buf_load(rL, ca, ro);
+        qb[k % D] = buf_load(rL, cb, ro);
+    };
+#pragma unroll
+    for (int k = 0; k < D; ++k) issue(k);
+
+    float dL[NL], sL[NL], dX[NF], wX[NF], wY[NF];
+    unsigned mlo = 0u, mhi = 0u;  // mask word of output row t in lane t
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const float A = qa[k % D], E = qb[k % D];
+        if (k + D < NL) issue(k + D);
+        lrow[lane] = A;
+        lrow[kWave + lane] = E;  // lanes >= 2S store copies nobody reads
+        wave_lds_sync();
+        const float Lc = lrow[lane + S], Lp = lrow[lane + 2 * S];
+        wave_lds_sync();
+        dL[k] = Lp - A;
+        sL[k] = scharr3(A, Lc, Lp);
+        if (k < 2 * S) continue;
+        const int q = k - 2 * S;  // first-derivative row y0 - S + q
+        const float Lx = scharr3(dL[k - 2 * S], dL[k - S], dL[k]);
+        const float Ly = sL[k] - sL[k - 2 * S];
+        frx[lane] = Lx;
+        fry[lane] = Ly;
+        wave_lds_sync();
+        const float xm = frx[am], xp = frx[ap], ym = fry[am], yp = fry[ap];
+        wave_lds_sync();
+        dX[q] = xp - xm;
+        wX[q] = scharr3(xm, Lx, xp);
+        wY[q] = scharr3(ym, Ly, yp);
+        if (q < 2 * S) continue;
+        const int t = q - 2 * S;  // output row y0 + t: derivative rows t, t + S, t + 2S
+        float dxa = dX[t], wxa = wX[t], wya = wY[t];
+        float dxc = dX[t + 2 * S], wxc = wX[t + 2 * S], wyc = wY[t + 2 * S];
+        if (t < S && top) {  // row y0 + t - S < 0: row S - 1 - t
+            dxa = dX[2 * S - 1 - t];
+            wxa = wX[2 * S - 1 - t];
+            wya = wY[2 * S - 1 - t];
+        }
+        if (t >= B - S && bot) {  // row y0 + t + S >= H: row 2H - 1 - (y0 + t + S)
+            dxc = dX[2 * B - 1 - t];
+            wxc = wX[2 * B - 1 - t];
+            wyc = wY[2 * B - 1 - t];
+        }
+        const float Lxx = scharr3(dxa, dX[t + S], dxc);
+        const float Lxy = wxc - wxa;
+        const float Lyy = wyc - wya;
+        const float v = scale * (Lxx * Lyy - Lxy * Lxy);
+        const int yo = y0 + t;
+        if (yo < row_hi) {  // uniform
+            buf_store(v, rD, co, 4u * (unsigned)(yo * W));
+            if (d.mask)
+                place_word((__builtin_amdgcn_ballot_w64(v > thr) & own_bits) >> S, t, mlo, mhi);
+        }
+    }
+    if (d.mask && lane < B && y0 + lane < row_hi) {
+        const int mw = mask_words(W);
+        ((gu64*)d.mask)[((size_t)lev * H + y0 + lane) * mw + j] =
+            ((unsigned long long)mhi << 32) | mlo;
+    }
+}
+
+// Per-pixel form for images too low for a band (det_band_rows 0): one
+// wavefront per strip and all rows, every first derivative formed at its
+// reflected position from nine loads of L.  The same formulas as the strip
+// form.
 template <int S>
-struct DetGeom {
-    static constexpr int niy = DTY + 4 * S, nix = DTX + 4 * S;  // staged L
-    static constexpr int pI = nix | 1;
-    static constexpr int nfy = DTY + 2 * S, nfx = DTX + 2 * S;  // first derivatives
-    static constexpr int pF = nfx | 1;
-    static constexpr int offX = niy * pI;
-    static constexpr int offY = offX + nfy * pF;
-    static constexpr int floats = offY + nfy * pF;
-};
-
-// det at (ly, lx) of the tile from the first-derivative planes of det_kernel
-template <int S, int pF>
-__device__ __forceinline__ float det_at(const float* sX, const float* sY, int ly, int lx,
-                                        float inv2s, float sn2) {
-    const float* x = sX + (ly + S) * pF + (lx + S);
-    const float* y = sY + (ly + S) * pF + (lx + S);
-    const float x00 = x[-S * pF - S], x02 = x[-S * pF + S];
-    const float x20 = x[S * pF - S], x22 = x[S * pF + S];
-    const float Lxx = (0.1875f * (x02 - x00) + 0.625f * (x[S] - x[-S]) + 0.1875f * (x22 - x20)) * inv2s;
-    const float Lxy = (0.1875f * (x20 - x00) + 0.625f * (x[S * pF] - x[-S * pF]) +
-                       0.1875f * (x22 - x02)) * inv2s;
-    const float Lyy = (0.1875f * (y[S * pF - S] - y[-S * pF - S]) +
-                       0.625f * (y[S * pF] - y[-S * pF]) +
-                       0.1875f * (y[S * pF + S] - y[-S * pF + S])) * inv2s;
-    return sn2 * (Lxx * Lyy - Lxy * Lxy);
+__device__ __forceinline__ void det_strip_pixels(const BatchImage& d, int lev, int j,
+                                                 const DetLevels& dl, int lane) {
+    constexpr int SW = kWave - 2 * S;
+    const int W = d.W, H = d.H;
+    const int ns = det_strips(W, S);
+    int x0, c_lo, c_hi;
+    strip_span(W, SW, ns, j, x0, c_lo, c_hi);
+    const int fx = x0 - S + lane;
+    const bool own_lane = lane >= S && lane < kWave - S && fx >= c_lo && fx < c_hi;
+    const int ox = own_lane ? fx : c_lo;  // in-image column for every lane
+    const size_t plane = (size_t)W * H;
+    const gfloat* L = (const gfloat*)d.levels + plane * lev;
+    gfloat* det = (gfloat*)d.det + plane * lev;
+    const float scale = dl.sn2[lev] * (1.f / (16.f * S * S * S * S));
+    // (Lx', Ly') at (xf, yf), extended by reflection
+    auto deriv = [&](int xf, int yf, float& lx, float& ly) {
+        const int xr = reflect_index(xf, W), yr = reflect_index(yf, H);
+        const int xa = reflect_index(xr - S, W), xb = reflect_index(xr + S, W);
+        float dd[3], ss[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const gfloat* r = L + (ptrdiff_t)reflect_index(yr + (i - 1) * S, H) * W;
+            const float a = r[xa], c = r[xr], e = r[xb];
+            dd[i] = e - a;
+            ss[i] = scharr3(a, c, e);
+        }
+        lx = scharr3(dd[0], dd[1], dd[2]);
+        ly = ss[2] - ss[0];
+    };
+    for (int yo = 0; yo < H; ++yo) {
+        float dXr[3], wXr[3], wYr[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int yf = yo + (i - 1) * S;
+            float xm, ym, xc, yc, xp, yp;
+            deriv(ox - S, yf, xm, ym);
+            deriv(ox, yf, xc, yc);
+            deriv(ox + S, yf, xp, yp);
+            dXr[i] = xp - xm;
+            wXr[i] = scharr3(xm, xc, xp);
+            wYr[i] = scharr3(ym, yc, yp);
+        }
+        const float Lxx = scharr3(dXr[0], dXr[1], dXr[2]);
+        const float Lxy = wXr[2] - wXr[0];
+        const float Lyy = wYr[2] - wYr[0];
+        const float v = scale * (Lxx * Lyy - Lxy * Lxy);
+        if (own_lane) (det + (ptrdiff_t)yo * W)[fx] = v;
+        if (d.mask) {
+            const unsigned long long bits = __ballot(own_lane && v > dl.thr) >> S;
+            if (lane == 0)
+                ((gu64*)d.mask)[((size_t)lev * H + yo) * mask_words(W) + j] = bits;
+        }
+    }
 }
 
 template <int S>
-__global__ __launch_bounds__(kDetThreads) void det_kernel(BatchImage d0, ImgWork w, DetLevels dl,
-                                                             int lev0, int lev1) {
-    using G = DetGeom<S>;
-    extern __shared__ float smem[];
-    float* sI = smem;
-    float* sX = smem + G::offX;
-    float* sY = smem + G::offY;
-    // (tile, level) of this block: the linear block index dealt out so that
-    // each XCD works through a contiguous run of tiles of one level, whose
-    // rings then share its L2
+__device__ __forceinline__ void det_strip_unit(const BatchImage& d, int lev, int unit,
+                                               const DetLevels& dl, float* wl, int lane) {
+    if (unit >= det_units(d.W, d.H, S)) return;  // uniform per wavefront
+    const int B = det_band_rows(d.H, S);
+    if (B == kDetBand)
+        det_strip_band<S, kDetBand>(d, lev, unit, dl, wl, lane);
+    else if (B == kDetBandSmall)
+        det_strip_band<S, kDetBandSmall>(d, lev, unit, dl, wl, lane);
+    else
+        det_strip_pixels<S>(d, lev, unit, dl, lane);
+}
+
+// Levels of Scharr step S (dl.list[0 .. gridDim.y)), or (SB > 0) of steps SA
+// and SB in one launch, each block taking the step of its level.  Block bx
+// of a level holds units 4 bx .. 4 bx + 3 of its image (one per wavefront,
+// strips fastest); blocks run XCD by XCD so that neighbouring strips and
+// bands share an L2.
+template <int SA, int SB>
+__global__ __launch_bounds__(kDetThreads) void det_strip_kernel(BatchImage d0, ImgWork w,
+                                                                 DetLevels dl) {
+    __shared__ float s_rows[kDetWaves][4 * kWave];
     int bx, by;
     xcd_grid(bx, by);
-    // levels of this launch: the ones in [lev0, lev1) with Scharr step S
-    int lev = -1;
-    for (int i = lev0, seen = 0; i < lev1; ++i)
-        if (dl.step[i] == S && seen++ == by) lev = i;
-    if (lev < 0) return;  // uniform per block
+    const int lev = dl.list[by];
     BatchImage d;
-    int lt;
-    resolve(d0, w, bx, d, lt);
-    const int W = d.W, H = d.H;
-    gfloat* __restrict__ det = (gfloat*)d.det;
-    const float sn2 = dl.sn2[lev];
-    const size_t plane = (size_t)W * H;
-    const float* L = d.levels + plane * lev;
-    const int ncx = (W + DTX - 1) / DTX;
-    const int tx0 = (lt % ncx) * DTX, ty0 = (lt / ncx) * DTY;
-    stage_region<G::niy, G::nix, G::pI, kDetThreads>(L, W, H, ty0 - 2 * S, tx0 - 2 * S, sI);
-    __syncthreads();
-
-    // First derivatives on the tile plus an s ring.  A ring position outside
-    // the image takes the derivative at its reflected in-image position, so
-    // the ring holds the reflected derivative image.  Ring positions more
-    // than s past the last row/column feed no output pixel and are skipped
-    // (their reflected position may lie outside the staged region).
-    constexpr float inv2s = 1.f / (float)(2 * S);
-    constexpr int nf = G::nfy * G::nfx;
-    const bool interior = ty0 - S >= 0 && tx0 - S >= 0 && ty0 + DTY + S <= H && tx0 + DTX + S <= W;
-#pragma unroll
-    for (int j = 0; j < (nf + kDetThreads - 1) / kDetThreads; ++j) {
-        const int i = threadIdx.x + j * kDetThreads;
-        if (i >= nf) continue;
-        const int py = i / G::nfx, px = i - py * G::nfx;
-        const int gy = ty0 - S + py, gx = tx0 - S + px;
-        int ry = py + S, rx = px + S;  // position inside sI
-        if (!interior) {
-            if (gy > H - 1 + S || gx > W - 1 + S) continue;
-            ry = reflect_index(gy, H) - ty0 + 2 * S;
-            rx = reflect_index(gx, W) - tx0 + 2 * S;
-        }
-        const float* c = sI + ry * G::pI + rx;
-        const float a00 = c[-S * G::pI - S], a02 = c[-S * G::pI + S];
-        const float a20 = c[S * G::pI - S], a22 = c[S * G::pI + S];
-        const float a10 = c[-S], a12 = c[S], a01 = c[-S * G::pI], a21 = c[S * G::pI];
-        sX[py * G::pF + px] =
-            (0.1875f * (a02 - a00) + 0.625f * (a12 - a10) + 0.1875f * (a22 - a20)) * inv2s;
-        sY[py * G::pF + px] =
-            (0.1875f * (a20 - a00) + 0.625f * (a21 - a01) + 0.1875f * (a22 - a02)) * inv2s;
-    }
-    __syncthreads();
-
-    // a wavefront holds one row of the tile (lane = column): its ballot is
-    // the row's mask word
-    gu64* mrow = d.mask ? (gu64*)d.mask + (size_t)lev * H * mask_words(W) + tx0 / DTX : nullptr;
-#pragma unroll
-    for (int j = 0; j < DTX * DTY / kDetThreads; ++j) {
-        const int i = threadIdx.x + j * kDetThreads;
-        const int ly = i / DTX, lx = i - ly * DTX;
-        const int gy = ty0 + ly, gx = tx0 + lx;
-        const bool in = gy < H && gx < W;
-        float v = 0.f;
-        if (in) v = det_at<S, G::pF>(sX, sY, ly, lx, inv2s, sn2);
-        if (in) det[plane * lev + (size_t)gy * W + gx] = v;
-        if (mrow) {
-            const unsigned long long bits = __ballot(in && v > dl.thr);
-            if (lx == 0 && gy < H) mrow[(size_t)gy * mask_words(W)] = bits;
-        }
-    }
+    int lb;
+    resolve(d0, w, bx, d, lb);
+    const int wave = uniform((int)threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
+    const int unit = lb * kDetWaves + wave;
+    if (SB == 0 || dl.step[lev] == SA)
+        det_strip_unit<SA>(d, lev, unit, dl, s_rows[wave], lane);
+    else
+        det_strip_unit<SB == 0 ? SA : SB>(d, lev, unit, dl, s_rows[wave], lane);
 }
-
 
 struct KeypointOut {
     int x, y, level;
@@ -248,7 +447,8 @@ __global__ __launch_bounds__(256) void nms_kernel(BatchImage d0, ImgWork w, floa
 }
 
 // The same test with detector masks.  A block takes 256 consecutive 64-bit
-// mask words of a level (row segments of 64 pixels, row-major), and only
+// mask words of a level (the row segments of the detector's strips,
+// row-major), and only
 // the positions whose bit is set (det above the threshold, typically well
 // under 1% of them) are read and tested; the rest of the level is never
 // loaded.  Set bits come in clusters (blobs of strong response), so they
@@ -274,6 +474,8 @@ __global__ __launch_bounds__(256) void nms_mask_kernel(BatchImage d0, ImgWork w,
     const int W = d.W, H = d.H, mw = mask_words(W);
     const int lev = by + 1;
     const int h = radii.h[lev];
+    // the level's detector strips: word (y, j) holds bit b for column x0_j + b
+    const int sw = kWave - 2 * radii.step[lev], ns = det_strips(W, radii.step[lev]);
     const size_t plane = (size_t)W * H;
     const gfloat* base = (const gfloat*)d.det + plane * lev;
     KeypointOut* kps = static_cast<KeypointOut*>(d.kps);
@@ -282,11 +484,12 @@ __global__ __launch_bounds__(256) void nms_mask_kernel(BatchImage d0, ImgWork w,
         const int g = lb * 256 + t;  // word of the level's mask plane
         const int y = g / mw, xw = g - y * mw;
         unsigned long long bits = 0ull;
-        if (y >= 1 && y <= H - 2)  // rows past H fall out here too
+        if (y >= 1 && y <= H - 2 && xw < ns)  // rows past H fall out here too
             bits = ((const gu64*)d.mask)[(size_t)lev * H * mw + g];
-        // columns 1 .. W-2 of the word: bits max(0, 1 - 64 xw) .. W - 2 - 64 xw
-        if (xw == 0) bits &= ~1ull;
-        const int hi = W - 2 - 64 * xw;
+        // columns 1 .. W-2 of the word: bits 1 - x0 .. W - 2 - x0
+        const int x0 = xw == ns - 1 ? max(W - sw, 0) : xw * sw;
+        if (x0 == 0) bits &= ~1ull;
+        const int hi = W - 2 - x0;
         if (hi < 63) bits &= hi >= 0 ? (2ull << hi) - 1ull : 0ull;
         s_bits[t] = bits;
         s_inc[t] = __popcll(bits);
@@ -317,7 +520,8 @@ __global__ __launch_bounds__(256) void nms_mask_kernel(BatchImage d0, ImgWork w,
             for (int k = q - (s_inc[lo] - __popcll(bits)); k > 0; --k) bits &= bits - 1ull;
             const int g = lb * 256 + lo;
             y = g / mw;
-            x = 64 * (g - y * mw) + __ffsll((long long)bits) - 1;
+            const int xw = g - y * mw;
+            x = (xw == ns - 1 ? max(W - sw, 0) : xw * sw) + __ffsll((long long)bits) - 1;
             const gfloat* c = base + (size_t)y * W + x;
             v = c[0];
             cand = v > threshold;
@@ -426,17 +630,15 @@ __global__ __launch_bounds__(256) void refine_kernel(const float* det, int W, in
     out[i] = r;
 }
 
-// Row-rolling form for steps S <= 4 (the default schedule's are 2 and 3):
-// lane = column, so no index needs a division and every row address is
-// wave-uniform.  Phase 1 stages L on the tile + 2S ring (row by row, lanes
-// over the first 64 columns, the last 4S columns one value per thread);
-// phase 2 computes the first derivatives on the tile + S ring, each lane
-// walking a band of rows with the three values of its columns c - S, c,
-// c + S of every row in registers; phase 3 does the same over the first
-// derivatives for L_xx, L_xy, L_yy and stores det row by row.  Ring
-// positions outside the image then take the derivative at their reflected
-// position (a copy inside LDS, border tiles only).  The arithmetic is the
-// 2-D kernel's, term for term.
+
+// First derivatives for the description stage (steps S <= 4): the
+// scale-normalised sigma_n L_x and sigma_n L_y of every pixel, on 64 x 32
+// tiles, lane = column.  Phase 1 stages L on the tile + 2S ring (row by row,
+// lanes over the first 64 columns, the last 4S columns one value per
+// thread); phase 2 computes the first derivatives on the tile + S ring, each
+// lane walking a band of rows with the three values of its columns c - S,
+// c, c + S of every row in registers.
+constexpr int DTX = 64;
 constexpr int kDetRowsTY = 32;
 
 template <int S>
@@ -452,15 +654,10 @@ struct RowDetGeom {
     static_assert(OB * WAVES == TY, "output bands tile the tile");
 };
 
-__device__ __forceinline__ float scharr3(float a0, float a1, float a2) {
-    return 0.1875f * a0 + 0.625f * a1 + 0.1875f * a2;
-}
-
-// DERIV: write the scale-normalised first derivatives sigma_n L_x and
-// sigma_n L_y of the tile to lx and ly instead of det (phases 1-2 only).
-// One block: tile bx (of the work list) of level lev, Scharr step S.
-template <int S, bool DERIV>
-__device__ __forceinline__ void det_rows_tile(float* smem, const BatchImage& d0, const ImgWork& w,
+// One block: tile bx of level lev, Scharr step S; sigma_n L_x and
+// sigma_n L_y of the tile to lx and ly.
+template <int S>
+__device__ __forceinline__ void deriv_rows_tile(float* smem, const BatchImage& d0, const ImgWork& w,
                                               const DetLevels& dl, int lev, int bx, float* lx,
                                               float* ly) {
     using G = RowDetGeom<S>;
@@ -472,7 +669,6 @@ __device__ __forceinline__ void det_rows_tile(float* smem, const BatchImage& d0,
     resolve(d0, w, bx, d, lt);
     const int W = d.W, H = d.H;
     const int tid = threadIdx.x, wave = uniform(tid / kWave), lane = tid % kWave;
-    const float sn2 = dl.sn2[lev];
     const size_t plane = (size_t)W * H;
     const gfloat* L = (const gfloat*)(d.levels + plane * lev);
     const int ncx = (W + DTX - 1) / DTX;
@@ -565,160 +761,56 @@ __device__ __forceinline__ void det_rows_tile(float* smem, const BatchImage& d0,
         }
     }
     __syncthreads();
-    if constexpr (DERIV) {
-        // tile pixel (r, c) sits at f-row r + S, f-column c + S
-        const float sn = dl.sn[lev];
-        const int gx = tx0 + lane;
-        gfloat* ox = (gfloat*)lx + plane * lev + (ty0 + wave * G::OB) * W + tx0;
-        gfloat* oy = (gfloat*)ly + plane * lev + (ty0 + wave * G::OB) * W + tx0;
+    // tile pixel (r, c) sits at f-row r + S, f-column c + S
+    const float sn = dl.sn[lev];
+    const int gx = tx0 + lane;
+    gfloat* ox = (gfloat*)lx + plane * lev + (ty0 + wave * G::OB) * W + tx0;
+    gfloat* oy = (gfloat*)ly + plane * lev + (ty0 + wave * G::OB) * W + tx0;
 #pragma unroll
-        for (int t = 0; t < G::OB; ++t) {
-            const int rf = wave * G::OB + t + S;
-            if (ty0 + wave * G::OB + t < H && gx < W) {
-                ox[t * W + lane] = sn * sX[rf * G::PF + lane + S];
-                oy[t * W + lane] = sn * sY[rf * G::PF + lane + S];
-            }
-        }
-        return;
-    }
-    // ring positions outside the image take the derivative at their
-    // reflected (in-image, already computed) position
-    if (ty0 - S < 0 || tx0 - S < 0 || ty0 + G::TY + S > H || tx0 + DTX + S > W) {
-        for (int i = tid; i < G::NYF * G::NXF; i += kDetThreads) {
-            const int rf = i / G::NXF, cf = i - rf * G::NXF;
-            const int gy = ty0 - S + rf, gx = tx0 - S + cf;
-            const bool out = gy < 0 || gx < 0 || gy >= H || gx >= W;
-            if (!out || gy > H - 1 + S || gx > W - 1 + S) continue;
-            const int sy = reflect_index(gy, H) - ty0 + S, sx = reflect_index(gx, W) - tx0 + S;
-            sX[rf * G::PF + cf] = sX[sy * G::PF + sx];
-            sY[rf * G::PF + cf] = sY[sy * G::PF + sx];
-        }
-        __syncthreads();
-    }
-
-    // phase 3: output row r (tile) uses f-rows r, r+S, r+2S and f-columns
-    // c, c+S, c+2S.  Per f-row k of the wavefront's band: the difference
-    // dX = L_x(c+2S) - L_x(c) and the Scharr-weighted sums wX, wY of L_x and
-    // L_y over the columns c, c+S, c+2S.  Then, each up to the factor
-    // 1/(2S) (the three of them folded into sigma_n^2):
-    //   L_xx = scharr3(dX[r], dX[r+S], dX[r+2S]),
-    //   L_xy = wX[r+2S] - wX[r],   L_yy = wY[r+2S] - wY[r].
-    {
-        const int o0 = wave * G::OB;
-        constexpr int K = G::OB + 2 * S;
-        float dX[K], wX[K], wY[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const float* rx = sX + (o0 + k) * G::PF + lane;
-            const float* ry = sY + (o0 + k) * G::PF + lane;
-            dX[k] = rx[2 * S] - rx[0];
-            wX[k] = scharr3(rx[0], rx[S], rx[2 * S]);
-            wY[k] = scharr3(ry[0], ry[S], ry[2 * S]);
-        }
-        const float scale = sn2 * (inv2s * inv2s);
-        float v[G::OB];
-#pragma unroll
-        for (int t = 0; t < G::OB; ++t) {
-            const float Lxx = scharr3(dX[t], dX[t + S], dX[t + 2 * S]);
-            const float Lxy = wX[t + 2 * S] - wX[t];
-            const float Lyy = wY[t + 2 * S] - wY[t];
-            v[t] = scale * (Lxx * Lyy - Lxy * Lxy);
-        }
-        const int gx = tx0 + lane;
-        const int rows = uniform(H - (ty0 + o0));  // rows of the band inside the image
-        gfloat* out = (gfloat*)(d.det + plane * lev) + (ty0 + o0) * W + tx0;
-        // row pointers are wave-uniform (scalar base, the lane as offset)
-        if (rows >= G::OB && tx0 + DTX <= W) {
-#pragma unroll
-            for (int t = 0; t < G::OB; ++t) (out + t * W)[lane] = v[t];
-        } else {
-#pragma unroll
-            for (int t = 0; t < G::OB; ++t)
-                if (t < rows && gx < W) (out + t * W)[lane] = v[t];
-        }
-        if (d.mask) {
-            // the mask word of row t is the wavefront's ballot; lane t
-            // stores it
-            unsigned long long word = 0ull;
-#pragma unroll
-            for (int t = 0; t < G::OB; ++t) {
-                const unsigned long long bits = __ballot(gx < W && v[t] > dl.thr);
-                word = lane == t ? bits : word;
-            }
-            if (lane < G::OB && lane < rows)
-                ((gu64*)d.mask)[((size_t)lev * H + ty0 + o0 + lane) * mask_words(W) + tx0 / DTX] =
-                    word;
+    for (int t = 0; t < G::OB; ++t) {
+        const int rf = wave * G::OB + t + S;
+        if (ty0 + wave * G::OB + t < H && gx < W) {
+            ox[t * W + lane] = sn * sX[rf * G::PF + lane + S];
+            oy[t * W + lane] = sn * sY[rf * G::PF + lane + S];
         }
     }
 }
 
-template <int S, bool DERIV = false>
-__global__ __launch_bounds__(kDetThreads) void det_rows_kernel(BatchImage d0, ImgWork w,
-                                                                DetLevels dl, float* lx = nullptr,
-                                                                float* ly = nullptr) {
+template <int S>
+__global__ __launch_bounds__(kDetThreads) void deriv_rows_kernel(BatchImage d0, ImgWork w,
+                                                                  DetLevels dl, float* lx,
+                                                                  float* ly) {
     extern __shared__ float smem[];
     int bx, by;
     xcd_grid(bx, by);
     // the launch's levels (all of Scharr step S) are dl.list[0..gridDim.y)
-    det_rows_tile<S, DERIV>(smem, d0, w, dl, dl.list[by], bx, lx, ly);
+    deriv_rows_tile<S>(smem, d0, w, dl, dl.list[by], bx, lx, ly);
 }
 
-// Levels of two Scharr steps in one launch (one ramp and one tail instead of
-// two): each block takes the step of its level.
+// Strip launch of the levels in [lev0, lev1) with Scharr step S (SB = 0) or
+// steps SA and SB.
 template <int SA, int SB>
-__global__ __launch_bounds__(kDetThreads) void det_rows_pair_kernel(BatchImage d0, ImgWork w,
-                                                                     DetLevels dl) {
-    extern __shared__ float smem[];
-    int bx, by;
-    xcd_grid(bx, by);
-    const int lev = dl.list[by];
-    if (dl.step[lev] == SA)
-        det_rows_tile<SA, false>(smem, d0, w, dl, lev, bx, nullptr, nullptr);
-    else
-        det_rows_tile<SB, false>(smem, d0, w, dl, lev, bx, nullptr, nullptr);
-}
-
-template <int S>
-hipError_t launch_det_s(const BatchImage& d0, const ImgWork& w, int lev0, int lev1,
-                        const DetLevels& dl, hipStream_t s) {
+hipError_t launch_det_strips(const BatchImage& d0, const ImgWork& w, int lev0, int lev1,
+                             const DetLevels& dl, hipStream_t s) {
     DetLevels dls = dl;  // with the list of this launch's levels
     int n = 0;
     for (int i = lev0; i < lev1; ++i)
-        if (dl.step[i] == S) dls.list[n++] = i;
-    const int count = w.items ? w.count : det_tiles_of(d0.W, d0.H);
+        if (dl.step[i] == SA || (SB > 0 && dl.step[i] == SB)) dls.list[n++] = i;
+    const int count = w.items ? w.count : det_tiles_of(d0.W, d0.H, SA, SB > 0 ? SB : SA);
     if (n == 0 || count <= 0) return hipSuccess;
-    if constexpr (S <= 4) {
-        static_assert(kDetRowsTY == DTY, "both forms tile alike");
-        const size_t lds = (size_t)RowDetGeom<S>::floats * sizeof(float);
-        hipLaunchKernelGGL(det_rows_kernel<S>, dim3(count, n), dim3(kDetThreads), lds, s, d0, w,
-                           dls, nullptr, nullptr);
-    } else {
-        const size_t lds = (size_t)DetGeom<S>::floats * sizeof(float);
-        hipLaunchKernelGGL(det_kernel<S>, dim3(count, n), dim3(kDetThreads), lds, s, d0, w, dl,
-                           lev0, lev1);
-    }
-    return hipGetLastError();
-}
-
-// Levels of steps SA and SB (and no other) in [lev0, lev1): one launch.
-template <int SA, int SB>
-hipError_t launch_det_pair(const BatchImage& d0, const ImgWork& w, int lev0, int lev1,
-                           const DetLevels& dl, hipStream_t s) {
-    DetLevels dls = dl;
-    int n = 0;
-    for (int i = lev0; i < lev1; ++i) dls.list[n++] = i;
-    const int count = w.items ? w.count : det_tiles_of(d0.W, d0.H);
-    if (n == 0 || count <= 0) return hipSuccess;
-    const size_t lds =
-        (size_t)std::max(RowDetGeom<SA>::floats, RowDetGeom<SB>::floats) * sizeof(float);
-    hipLaunchKernelGGL((det_rows_pair_kernel<SA, SB>), dim3(count, n), dim3(kDetThreads), lds, s,
-                       d0, w, dls);
+    hipLaunchKernelGGL((det_strip_kernel<SA, SB>), dim3(count, n), dim3(kDetThreads), 0, s, d0,
+                       w, dls);
     return hipGetLastError();
 }
 
 }  // namespace
 
-int det_tiles_of(int W, int H) { return ((W + DTX - 1) / DTX) * ((H + DTY - 1) / DTY); }
+int det_tiles_of(int W, int H, int smin, int smax) {
+    int n = 0;
+    for (int S = smin; S <= smax; ++S)
+        n = std::max(n, (det_units(W, H, S) + kDetWaves - 1) / kDetWaves);
+    return n;
+}
 
 int nms_blocks_of(int W, int H, bool masked) {
     if (masked) return (int)(((long long)H * mask_words(W) + 255) / 256);
@@ -733,14 +825,22 @@ hipError_t launch_det(const BatchImage& d0, const ImgWork& w, int lev0, int lev1
         smin = std::min(smin, dl.step[i]);
         smax = std::max(smax, dl.step[i]);
     }
-    if (smax == smin + 1 && smax <= 4) {
-        if (smin == 1) return launch_det_pair<1, 2>(d0, w, lev0, lev1, dl, s);
-        if (smin == 2) return launch_det_pair<2, 3>(d0, w, lev0, lev1, dl, s);
-        return launch_det_pair<3, 4>(d0, w, lev0, lev1, dl, s);
+    if (smax == 0) return hipSuccess;
+    if (smax < 1 || smax > kMaxStep || smin < 1) return hipErrorInvalidValue;
+    if (smax == smin + 1) {
+        switch (smin) {
+            case 1: return launch_det_strips<1, 2>(d0, w, lev0, lev1, dl, s);
+            case 2: return launch_det_strips<2, 3>(d0, w, lev0, lev1, dl, s);
+            case 3: return launch_det_strips<3, 4>(d0, w, lev0, lev1, dl, s);
+            case 4: return launch_det_strips<4, 5>(d0, w, lev0, lev1, dl, s);
+            case 5: return launch_det_strips<5, 6>(d0, w, lev0, lev1, dl, s);
+            case 6: return launch_det_strips<6, 7>(d0, w, lev0, lev1, dl, s);
+            default: return launch_det_strips<7, 8>(d0, w, lev0, lev1, dl, s);
+        }
     }
     hipError_t e = hipSuccess;
 #define KZ_D(S) \
-    if (e == hipSuccess) e = launch_det_s<S>(d0, w, lev0, lev1, dl, s);
+    if (e == hipSuccess) e = launch_det_strips<S, 0>(d0, w, lev0, lev1, dl, s);
     KZ_D(1) KZ_D(2) KZ_D(3) KZ_D(4) KZ_D(5) KZ_D(6) KZ_D(7) KZ_D(8)
 #undef KZ_D
     return e;
@@ -750,7 +850,7 @@ hipError_t launch_det_derivs(const BatchImage& b, int N, const DetLevels& dl, fl
                              float* ly, hipStream_t s) {
     for (int i = 0; i < N; ++i)
         if (dl.step[i] > 4) return hipErrorNotSupported;  // the caller's per-pixel form
-    const int count = det_tiles_of(b.W, b.H);
+    const int count = ((b.W + DTX - 1) / DTX) * ((b.H + kDetRowsTY - 1) / kDetRowsTY);
     const ImgWork none{nullptr, nullptr, 0};
     hipError_t e = hipSuccess;
     auto one = [&](auto tag) {
@@ -761,8 +861,8 @@ hipError_t launch_det_derivs(const BatchImage& b, int N, const DetLevels& dl, fl
             if (dl.step[i] == S) dls.list[n++] = i;
         if (n == 0 || e != hipSuccess) return;
         const size_t lds = (size_t)RowDetGeom<S>::floats * sizeof(float);
-        hipLaunchKernelGGL((det_rows_kernel<S, true>), dim3(count, n), dim3(kDetThreads), lds, s,
-                           b, none, dls, lx, ly);
+        hipLaunchKernelGGL((deriv_rows_kernel<S>), dim3(count, n), dim3(kDetThreads), lds, s, b,
+                           none, dls, lx, ly);
         e = hipGetLastError();
     };
     one(std::integral_constant<int, 1>{});

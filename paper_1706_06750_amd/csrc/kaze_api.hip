@@ -150,13 +150,21 @@ kaze_status check_params(const kaze_params* p) {
     return KAZE_OK;
 }
 
+void schedule(const kaze_params* p, std::vector<Level>& lv);
+
 // Cross-level window half-sides: 1, or for the exact test the h whose side
 // 2h + 1 is the odd number nearest sigma_i (half up), at least 1; capped at
 // the largest image side (the window is clipped to the image anyway).
 NmsRadii nms_radii(const kaze_params* p) {
     NmsRadii r;
     const int N = p->octaves * p->sublevels;
-    for (int i = 0; i < kMaxLevels; ++i) r.h[i] = 1;
+    for (int i = 0; i < kMaxLevels; ++i) {
+        r.h[i] = 1;
+        r.step[i] = 1;
+    }
+    std::vector<Level> lv;
+    schedule(p, lv);
+    for (int i = 0; i < N && i < kMaxLevels; ++i) r.step[i] = std::min(lv[i].step, kMaxStep);
     if (p->extrema_window == KAZE_WINDOW_SIGMA) {
         for (int i = 0; i < N; ++i) {
             const int o = i / p->sublevels, s = i % p->sublevels;
@@ -437,16 +445,30 @@ struct BatchLayout {
     int n_tiles, n_aos, n_lines, n_hist, n_det, n_nms;
 };
 
+// Smallest and largest Scharr step of the detector levels.
+void step_range(const kaze_params* p, int& smin, int& smax) {
+    std::vector<Level> lv;
+    schedule(p, lv);
+    smin = 1 << 30;
+    smax = 0;
+    for (const Level& l : lv) {
+        smin = std::min(smin, l.step);
+        smax = std::max(smax, l.step);
+    }
+}
+
 BatchLayout batch_layout(const kaze_image_desc* im, int n, const kaze_params* p, int shape) {
     BatchLayout L;
     const int N = p->octaves * p->sublevels;
+    int smin, smax;
+    step_range(p, smin, smax);
     L.n_tiles = L.n_aos = L.n_lines = L.n_hist = L.n_det = L.n_nms = 0;
     for (int j = 0; j < n; ++j) {
         L.n_tiles += tiles_of(im[j].W, im[j].H);
         L.n_aos += aos_tiles_of(im[j].W, im[j].H, kAosShape[shape].ty);
         L.n_lines += aos_line_groups(im[j].W, im[j].H, kAosShape[shape]);
         L.n_hist += (im[j].W * im[j].H + kHistChunk - 1) / kHistChunk;
-        L.n_det += det_tiles_of(im[j].W, im[j].H);
+        L.n_det += det_tiles_of(im[j].W, im[j].H, smin, smax);
         L.n_nms += nms_blocks_of(im[j].W, im[j].H, true);
     }
     size_t off = 0;
@@ -607,6 +629,8 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
     if (!out) return fail(KAZE_ERR_INVALID_ARG, "out pointer is NULL");
     if (sp && (st = sg_batch_check(im, n, p, *sp)) != KAZE_OK) return st;
     const BatchLayout L = batch_layout(im, n, p, shape);
+    int smin, smax;
+    step_range(p, smin, smax);
     const size_t total = L.total + (sp ? sg_batch_bytes(im, n, p, sp->c) : 0);
     if (!ws || !aligned(ws, 256) || ws_bytes < total)
         return fail(KAZE_ERR_WORKSPACE, "batch workspace needs %zu bytes, 256-byte aligned (got %zu)",
@@ -697,7 +721,7 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
         for (int t = 0; t < aos_line_groups(d.W, d.H, kAosShape[shape]); ++t)
             hl[il++] = make_int2(j, t);
         for (int t = 0; t < (d.W * d.H + kHistChunk - 1) / kHistChunk; ++t) hh[ih++] = make_int2(j, t);
-        for (int t = 0; t < det_tiles_of(d.W, d.H); ++t) hd[idt++] = make_int2(j, t);
+        for (int t = 0; t < det_tiles_of(d.W, d.H, smin, smax); ++t) hd[idt++] = make_int2(j, t);
         for (int t = 0; t < nms_blocks_of(d.W, d.H, true); ++t) hn[inm++] = make_int2(j, t);
     }
     hipStream_t cs = nullptr;

@@ -176,10 +176,11 @@ struct BatchImage {
     void* kps;          // keypoints, capacity entries
     int capacity;
     int* count;
-    // N planes of H rows x ceil(W/64) words: bit b of word (i, y, c) is set
-    // iff det_i(64c + b, y) > DetLevels::thr.  Written by the detector
-    // beside det when not null; the extrema kernel then reads only the
-    // det values whose bit is set.
+    // N planes of H rows x mask_words(W) words: bit b of word (i, y, j) is
+    // set iff det_i(x0 + b, y) > DetLevels::thr, x0 the first column of the
+    // detector's strip j of level i (words past the level's strips unused).
+    // Written by the detector beside det when not null; the extrema kernel
+    // then reads only the det values whose bit is set.
     unsigned long long* mask;
     int W, H;
 };
@@ -397,14 +398,19 @@ hipError_t launch_probe_err(const float* L, const float* cand, int W, const int4
                             int nprobes, const float* delta, unsigned* err, hipStream_t s,
                             const ImageDesc* pdesc = nullptr, const int* rect_img = nullptr);
 
-// a6: det of the levels lev0 .. lev1-1 (items: image, det tile of 64 x 32).
+// a6: det of the levels lev0 .. lev1-1 in strips of 64 - 2S output columns
+// (S the level's Scharr step) and bands of rows, four strip-bands per block
+// (items: image, block of a level).
 hipError_t launch_det(const BatchImage& d0, const ImgWork& w, int lev0, int lev1,
                       const DetLevels& dl, hipStream_t s);
-int det_tiles_of(int W, int H);
+// Blocks per level of an image for the levels of steps smin..smax.
+int det_tiles_of(int W, int H, int smin, int smax);
 // a7: extrema of levels 1..N-2 (items: image, block of 64 x 4*kNmsRows pixels).
-// Half-side of the cross-level window of each level (1: the 3x3x3 test).
+// Half-side of the cross-level window of each level (1: the 3x3x3 test) and
+// the Scharr step of each level (the layout of its detector mask).
 struct NmsRadii {
     int h[kMaxLevels];
+    int step[kMaxLevels];
 };
 // masked: the images carry detector masks written with this threshold
 // (items: image, block of 256 mask words of a level); else every det value
@@ -412,7 +418,14 @@ struct NmsRadii {
 hipError_t launch_nms(const BatchImage& d0, const ImgWork& w, int N, float threshold,
                       const NmsRadii& radii, hipStream_t s, bool masked = false);
 int nms_blocks_of(int W, int H, bool masked = false);
-__host__ __device__ inline int mask_words(int W) { return (W + 63) / 64; }
+// Detector strips of a level with Scharr step S: 64 - 2S output columns
+// each, the last one aligned to end at column W.
+__host__ __device__ inline int det_strips(int W, int S) {
+    const int sw = 64 - 2 * S;
+    return W <= sw ? 1 : (W + sw - 1) / sw;
+}
+// Mask words per row: one per strip at the largest step.
+__host__ __device__ inline int mask_words(int W) { return det_strips(W, kMaxStep); }
 // Refinement and edge test of capacity-bounded extrema (entries of 16 and 24
 // bytes: kaze_keypoint and kaze_keypoint_refined) on N levels of W x H;
 // thr = (r+1)^2/r.

@@ -21,12 +21,12 @@ import json
 import os
 
 AOS_KERNELS = ("aos_reduce_kernel", "aos_iface_kernel", "aos_recover_kernel")
-DET_KERNELS = ("det_kernel", "det_rows_kernel", "det_rows_pair_kernel")
+DET_KERNELS = ("det_strip_kernel",)
 
 
 def short(name: str) -> str:
-    """'void kaze::(anonymous namespace)::det_kernel<2>(float const*, ...)'
-    -> 'det_kernel<2>'."""
+    """'void kaze::(anonymous namespace)::det_strip_kernel<2, 3>(kaze::BatchImage, ...)'
+    -> 'det_strip_kernel<2, 3>'."""
     n = name.replace("(anonymous namespace)::", "")
     if n.startswith("void "):
         n = n[5:]

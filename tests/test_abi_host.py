@@ -226,15 +226,17 @@ def test_aos_shape_table(K):
 
 def test_batch_workspace_holds_detector_masks(K):
     """A batch that finds extrema (count given) needs, per image, N planes of
-    H x ceil(W/64) 64-bit threshold-mask words (a 256-byte aligned region)
-    more than one that stops at det."""
+    H rows of 64-bit threshold-mask words (a 256-byte aligned region) more
+    than one that stops at det: one word per detector strip at the largest
+    Scharr step (8: strips of 64 - 16 = 48 columns)."""
     p = K.kaze_default_params()
     N = K.kaze_num_levels(p)
     D = K.kaze_image_desc
     dims = [(100, 80), (300, 200), (64, 9)]
     with_nms = [D(256, W, H, W, 512, 1024, 2048, 4096, 10, 8192) for W, H in dims]
     det_only = [D(256, W, H, W, 512, 1024, 2048, 0, 0, 0) for W, H in dims]
-    masks = sum((N * H * ((W + 63) // 64) * 8 + 255) // 256 * 256 for W, H in dims)
+    words = lambda W: 1 if W <= 48 else (W + 47) // 48
+    masks = sum((N * H * words(W) * 8 + 255) // 256 * 256 for W, H in dims)
     for s in range(len(K.AOS_SHAPES)):
         a = K.kaze_batch_workspace_bytes(with_nms, p, s)
         b = K.kaze_batch_workspace_bytes(det_only, p, s)
