@@ -46,19 +46,18 @@ def tile_label(K, shape):
 def traffic_from_profile(key, aos_tile, det_levels):
     """HBM bytes per step of the level segment from the committed counter
     summary profiles/level_traffic_<key>.json, if it was taken on the current
-    per-level kernel sources with the same tile shape and the same number of
-    detector levels inside the segment."""
-    from paper_1706_06750_amd.rocprof_summary import csrc_hash
+    per-level kernel sources: the chosen launch shape's AOS kernels plus the
+    detector levels that run inside the segment."""
+    from paper_1706_06750_amd.rocprof_summary import csrc_hash, segment_bytes
     path = os.path.join(ROOT, "profiles", "level_traffic_%s.json" % key)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("csrc_hash") != csrc_hash(ROOT) or d.get("aos_tile") != aos_tile:
+    if d.get("csrc_hash") != csrc_hash(ROOT) or "aos_by_shape" not in d:
         return None
-    if d.get("det_levels_in_segment") != det_levels:
-        return None
-    return round(d["bytes_per_level"])
+    b = segment_bytes(d, aos_tile, det_levels)
+    return None if b is None else round(b)
 
 
 CPU_BASELINE_SRC = r"""

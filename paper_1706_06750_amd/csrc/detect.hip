@@ -18,8 +18,10 @@ namespace {
 constexpr int kDetThreads = 256;
 constexpr int kDetWaves = kDetThreads / kWave;
 
+// (3 a0 + 10 a1 + 3 a2) / 16 as one multiply and two fused multiply-adds in
+// a fixed order, so that every kernel and instantiation rounds alike.
 __device__ __forceinline__ float scharr3(float a0, float a1, float a2) {
-    return 0.1875f * a0 + 0.625f * a1 + 0.1875f * a2;
+    return __builtin_fmaf(0.1875f, a2, __builtin_fmaf(0.625f, a1, 0.1875f * a0));
 }
 
 // Raw buffer access to one plane: the resource in scalar registers, the
@@ -139,6 +141,7 @@ __device__ __forceinline__ int deriv_lane(int c, int W, int x0, int S) {
 template <int S, int B>
 __device__ __forceinline__ void det_strip_band(const BatchImage& d, int lev, int unit,
                                                const DetLevels& dl, float* wl, int lane) {
+#pragma clang fp contract(off)
     constexpr int SW = kWave - 2 * S;
     constexpr int NL = B + 4 * S;  // rows of L
     constexpr int NF = B + 2 * S;  // rows of first derivatives
@@ -221,7 +224,7 @@ __device__ __forceinline__ void det_strip_band(const BatchImage& d, int lev, int
         const float Lxx = scharr3(dxa, dX[t + S], dxc);
         const float Lxy = wxc - wxa;
         const float Lyy = wyc - wya;
-        const float v = scale * (Lxx * Lyy - Lxy * Lxy);
+        const float v = scale * __builtin_fmaf(Lxx, Lyy, -(Lxy * Lxy));
         const int yo = y0 + t;
         if (yo < row_hi) {  // uniform
             buf_store(v, rD, co, 4u * (unsigned)(yo * W));
@@ -243,6 +246,7 @@ __device__ __forceinline__ void det_strip_band(const BatchImage& d, int lev, int
 template <int S>
 __device__ __forceinline__ void det_strip_pixels(const BatchImage& d, int lev, int j,
                                                  const DetLevels& dl, int lane) {
+#pragma clang fp contract(off)
     constexpr int SW = kWave - 2 * S;
     const int W = d.W, H = d.H;
     const int ns = det_strips(W, S);
@@ -286,7 +290,7 @@ __device__ __forceinline__ void det_strip_pixels(const BatchImage& d, int lev, i
         const float Lxx = scharr3(dXr[0], dXr[1], dXr[2]);
         const float Lxy = wXr[2] - wXr[0];
         const float Lyy = wYr[2] - wYr[0];
-        const float v = scale * (Lxx * Lyy - Lxy * Lxy);
+        const float v = scale * __builtin_fmaf(Lxx, Lyy, -(Lxy * Lxy));
         if (own_lane) (det + (ptrdiff_t)yo * W)[fx] = v;
         if (d.mask) {
             const unsigned long long bits = __ballot(own_lane && v > dl.thr) >> S;
