@@ -9,7 +9,7 @@ decide the whole fit.  The forward pass, the backward pass and Adam run in
 libkaze's MFMA kernels; this module only schedules them and moves tensors.
 
     python -m paper_1706_06750_amd.train_surrogate [--images 2000] [--size 512]
-        [--epochs 3] [--batch 16] [--lr 1e-3] [--out weights/surrogate_512.npz]
+        [--epochs 3] [--batch 16] [--lr 1e-3] [--levels 1-3] [--out weights/surrogate_512.npz]
 """
 from __future__ import annotations
 
@@ -48,16 +48,18 @@ def make_images(n, size, seed0, workers):
 
 
 class PairSource:
-    """Level pairs of a chunk of images from the plain GPU path."""
+    """Level pairs of a chunk of images from the plain GPU path (the steps
+    into the levels in `levels`, default every level 1..N-1)."""
 
-    def __init__(self, K, size, chunk):
+    def __init__(self, K, size, chunk, levels=None):
         import torch
         self.K, self.size, self.chunk = K, size, chunk
         self.kb = K.KazeBatch([(size, size)] * chunk, shape=0, with_detector=False)
         self.N = self.kb.N
+        self.levels = list(levels) if levels else list(range(1, self.N))
         sched = K.kaze_schedule(self.kb.p)
         self.tau = torch.tensor([s["tau"] for s in sched], dtype=torch.float32, device="cuda")
-        n = chunk * (self.N - 1)
+        n = chunk * len(self.levels)
         self.L = torch.empty((n, size, size), device="cuda")
         self.g = torch.empty_like(self.L)
         self.Ln = torch.empty_like(self.L)
@@ -73,7 +75,7 @@ class PairSource:
         for j in range(self.chunk):
             lev = self.kb.levels[j]
             k = float(self.kb.k[j].item())
-            for i in range(1, self.N):
+            for i in self.levels:
                 self.L[r].copy_(lev[i - 1])
                 self.Ln[r].copy_(lev[i])
                 K.kaze_conductivity(lev[i - 1], s, s, self.kb.p, k, self.g[r])
@@ -113,7 +115,8 @@ def evaluate(K, S, w, size=512, images=16, image_seed=410000, workers=None, chun
 
 
 def train(images=2000, size=512, epochs=3, batch=16, lr=1e-3, lr_min=1e-5, chunk=16, seed=0,
-          image_seed=400000, workers=None, log_every=100, out=DEFAULT_OUT, verbose=True):
+          image_seed=400000, workers=None, log_every=100, out=DEFAULT_OUT, verbose=True,
+          levels=None):
     import torch
     from . import kaze as K
     from . import surrogate as S
@@ -124,11 +127,11 @@ def train(images=2000, size=512, epochs=3, batch=16, lr=1e-3, lr_min=1e-5, chunk
     imgs = torch.from_numpy(host).cuda()
     del host
     t_gen = time.time() - t0
-    src = PairSource(K, size, chunk)
+    src = PairSource(K, size, chunk, levels)
     w = S.Weights(surrogate_params(seed))
     plan = S.Plan(batch, size, size, training=True)
     rng = np.random.default_rng(seed + 1)
-    pairs_per_chunk = chunk * (src.N - 1)
+    pairs_per_chunk = chunk * len(src.levels)
     steps_per_chunk = pairs_per_chunk // batch
     n_chunks = images // chunk
     total = epochs * n_chunks * steps_per_chunk
@@ -167,7 +170,7 @@ def train(images=2000, size=512, epochs=3, batch=16, lr=1e-3, lr_min=1e-5, chunk
         print("no step: per-level max  %s" % " ".join("%.1e" % v for v in held["max_no_step"][1:]))
     meta = {"images": images, "size": size, "epochs": epochs, "batch": batch, "lr": lr,
             "lr_min": lr_min, "chunk": chunk, "init_seed": seed, "image_seed": image_seed,
-            "steps": step, "pairs_per_epoch": n_chunks * pairs_per_chunk,
+            "steps": step, "pairs_per_epoch": n_chunks * pairs_per_chunk, "levels": src.levels,
             "image_generation_s": round(t_gen, 2), "train_s": round(t_train, 2),
             "held_out": held, "loss_history": history}
     if out:
@@ -193,9 +196,15 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workers", type=int, default=None)
     ap.add_argument("--out", default=DEFAULT_OUT)
+    ap.add_argument("--levels", default=None,
+                    help="train on the steps into levels lo-hi only (e.g. 1-3); default all")
     a = ap.parse_args()
+    levels = None
+    if a.levels:
+        lo, hi = (int(v) for v in a.levels.split("-"))
+        levels = range(lo, hi + 1)
     _, meta = train(a.images, a.size, a.epochs, a.batch, a.lr, chunk=a.chunk, seed=a.seed,
-                    workers=a.workers, out=a.out)
+                    workers=a.workers, out=a.out, levels=levels)
     print(json.dumps({k: v for k, v in meta.items() if k != "loss_history"}))
 
 
