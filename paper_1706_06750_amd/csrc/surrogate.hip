@@ -46,6 +46,15 @@ __device__ inline bf16x8 zero8() {
 
 __device__ inline bf16x8 ld8(const bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
 
+// Workgroup barrier for exchanges through LDS only: waits for the wave's LDS
+// accesses, not for its global loads, so rows prefetched into registers stay
+// in flight across it (a full __syncthreads also waits for every outstanding
+// global load).  The memory clobber keeps the compiler from moving LDS
+// accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // ------------------------------------------------------------- convolution
 template <int CIN>
 struct ConvK {
@@ -366,13 +375,14 @@ __global__ __launch_bounds__(kPairThreads) void conv2_kernel(Conv2Args a, Geo g)
             R[2] = ld8(p_ + 2 * CINA);                                    \
         }                                                                 \
     }
-            // layer-a row ya reads padded rows ya, ya+1, ya+2; the ring holds
-            // them with row ya+3 loaded one step ahead
-#define KZ_ASTEP(tt, RA, RB, RC, RD)                                                          \
+            // layer-a row ya reads padded rows ya, ya+1, ya+2; the ring of
+            // five holds them with rows ya+3 and ya+4 loaded one and two
+            // steps ahead
+#define KZ_ASTEP(tt, RA, RB, RC, RE)                                                          \
     {                                                                                         \
         const int ya_ = y0 - 1 + (tt);                                                        \
         if ((tt) < steps) {                                                                   \
-            if ((tt) <= steps - 3) KZ_LOADROW(RD, ya_ + 3)                                    \
+            if ((tt) <= steps - 4) KZ_LOADROW(RE, ya_ + 4)                                    \
             f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};           \
             if (ya_ >= 0 && ya_ < g.H && (tt) <= steps - 2) {                                 \
                 _Pragma("unroll") for (int dx = 0; dx < 3; ++dx)                              \
@@ -386,18 +396,20 @@ __global__ __launch_bounds__(kPairThreads) void conv2_kernel(Conv2Args a, Geo g)
                         acc[mb] = mfma(wf[mb][6 + dx], RC[dx], acc[mb]);                      \
             }                                                                                 \
             if ((tt) <= steps - 2) store_row((tt) & 3, ya_, acc);                             \
-            __syncthreads();                                                                  \
+            lds_barrier();                                                                      \
         }                                                                                     \
     }
-            bf16x8 ra[3], rb[3], rc[3], rd[3];
+            bf16x8 ra[3], rb[3], rc[3], rd[3], re[3];
             KZ_LOADROW(ra, y0 - 1)
             KZ_LOADROW(rb, y0)
             KZ_LOADROW(rc, y0 + 1)
-            for (int t = 0; t < steps; t += 4) {
-                KZ_ASTEP(t, ra, rb, rc, rd)
+            KZ_LOADROW(rd, y0 + 2)
+            for (int t = 0; t < steps; t += 5) {
+                KZ_ASTEP(t, ra, rb, rc, re)
                 KZ_ASTEP(t + 1, rb, rc, rd, ra)
-                KZ_ASTEP(t + 2, rc, rd, ra, rb)
-                KZ_ASTEP(t + 3, rd, ra, rb, rc)
+                KZ_ASTEP(t + 2, rc, rd, re, rb)
+                KZ_ASTEP(t + 3, rd, re, ra, rc)
+                KZ_ASTEP(t + 4, re, ra, rb, rd)
             }
 #undef KZ_ASTEP
 #undef KZ_LOADROW
@@ -421,7 +433,7 @@ __global__ __launch_bounds__(kPairThreads) void conv2_kernel(Conv2Args a, Geo g)
                     }
                     store_row(t & 3, ya, acc);
                 }
-                __syncthreads();
+                lds_barrier();    
             }
         }
     } else {
@@ -486,7 +498,7 @@ __global__ __launch_bounds__(kPairThreads) void conv2_kernel(Conv2Args a, Geo g)
                     }
                 }
             }
-            __syncthreads();
+            lds_barrier();    
         }
     }
 }
