@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(PKG_DIR, "libkaze.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed-FP32 instructions are kept out of the generated code on purpose.
-HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function"]
 
@@ -53,7 +53,7 @@ def build(verbose: bool = False) -> str:
                 raise RuntimeError("hipcc failed (%d) on %s:\n%s" % (rc, cmd[-3], err))
             if verbose and err.strip():
                 print(err, file=sys.stderr)
-        rc, err = _run([HIPCC] + HIP_FLAGS + objs + ["-o", tmp], verbose)
+        rc, err = _run([HIPCC] + HIP_FLAGS + ["-shared"] + objs + ["-o", tmp], verbose)
         if rc != 0:
             raise RuntimeError("link failed (%d):\n%s" % (rc, err))
         os.replace(tmp, LIB_PATH)

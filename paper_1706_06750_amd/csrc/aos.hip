@@ -54,18 +54,23 @@ __device__ __forceinline__ float coupling(bool inside, float tau, float ga, floa
 // Chunk of M unknowns at line positions pos0 .. pos0+M-1 of a line of n
 // pixels.  Acc::g(k), Acc::L(k) give conductivity and level at chunk index
 // k in [-1, M] (the ring supplies -1 and M).  Positions past the line end
-// are identity rows (decoupled, solution 0).
+// are identity rows (decoupled, solution 0).  The right-hand side of row k
+// is the flux difference f_k - f_{k-1}, f_k = w_{k,k+1} (L_{k+1} - L_k):
+// each flux is formed once and used by both rows it joins.
 template <int M, bool CHECK = true, bool PRE = false, class Acc>
 __device__ __forceinline__ void chunk_reduce(const Acc& A, int pos0, int n, float tau, Eq& E0,
                                              Eq& E1) {
 #pragma clang fp contract(off)
-    float gm = A.g(-1), Lm = A.L(-1), g0 = A.g(0), L0 = A.L(0);
+    const float gm = A.g(-1), Lm = A.L(-1);
+    float g0 = A.g(0), L0 = A.L(0);
     float gp = A.g(1), Lp = A.L(1);
     float wl = coupling<true, PRE>(pos0 > 0 && pos0 < n, tau, gm, g0);
+    float fl = wl * (L0 - Lm);  // flux into the chunk across its left end
     float wr = coupling<CHECK, PRE>(pos0 < n - 1, tau, g0, gp);
-    const Eq first = aos_row(wl, wr, Lm - L0, Lp - L0);
+    float fr = wr * (Lp - L0);
+    const Eq first{-wl, (1.f + wl) + wr, -wr, fr - fl};
     wl = wr;
-    Lm = L0;
+    fl = fr;
     g0 = gp;
     L0 = Lp;
     // x_k + cp x_{k+1} = dp + ep x_0 over the interior, and
@@ -76,7 +81,8 @@ __device__ __forceinline__ void chunk_reduce(const Acc& A, int pos0, int n, floa
         gp = A.g(k + 1);
         Lp = A.L(k + 1);
         wr = coupling<CHECK, PRE>(pos0 + k < n - 1, tau, g0, gp);
-        const float d = __builtin_fmaf(wl, Lm - L0, wr * (Lp - L0));
+        fr = wr * (Lp - L0);
+        const float d = fr - fl;
         const float r = rcp(__builtin_fmaf(wl, cp, (1.f + wl) + wr));
         dp = __builtin_fmaf(wl, dp, d) * r;
         ep = (wl * ep) * r;
@@ -85,14 +91,15 @@ __device__ __forceinline__ void chunk_reduce(const Acc& A, int pos0, int n, floa
         be = __builtin_fmaf(P, ep, be);
         P = -P * cp;
         wl = wr;
-        Lm = L0;
+        fl = fr;
         g0 = gp;
         L0 = Lp;
     }
     gp = A.g(M);
     Lp = A.L(M);
     wr = coupling<CHECK, PRE>(pos0 + M - 1 < n - 1, tau, g0, gp);
-    const Eq last = aos_row(wl, wr, Lm - L0, Lp - L0);
+    fr = wr * (Lp - L0);
+    const Eq last{-wl, (1.f + wl) + wr, -wr, fr - fl};
     E1 = Eq{last.a * ep, last.b - last.a * cp, last.c, last.d - last.a * dp};
     E0 = Eq{first.a, first.b + first.c * be, first.c * P, first.d - first.c * al};
 }
@@ -104,14 +111,17 @@ __device__ __forceinline__ void chunk_recover(const Acc& A, int pos0, int n, flo
                                               float z1, float (&x)[M]) {
 #pragma clang fp contract(off)
     float cpa[M];
-    float gm = A.g(0), Lm = A.L(0), g0 = A.g(1), L0 = A.L(1);
+    const float gm = A.g(0), Lm = A.L(0);
+    float g0 = A.g(1), L0 = A.L(1);
     float wl = coupling<CHECK, PRE>(pos0 + 1 < n, tau, gm, g0);
+    float fl = wl * (L0 - Lm);
     float cp = 0.f, dp = 0.f;
 #pragma unroll
     for (int k = 1; k <= M - 2; ++k) {
         const float gp = A.g(k + 1), Lp = A.L(k + 1);
         const float wr = coupling<CHECK, PRE>(pos0 + k < n - 1, tau, g0, gp);
-        float d = __builtin_fmaf(wl, Lm - L0, wr * (Lp - L0));
+        const float fr = wr * (Lp - L0);
+        float d = fr - fl;
         const float b = (1.f + wl) + wr;
         float a = -wl, c = -wr;
         if (k == 1) {
@@ -128,7 +138,7 @@ __device__ __forceinline__ void chunk_recover(const Acc& A, int pos0, int n, flo
         cpa[k] = cp;
         x[k] = dp;
         wl = wr;
-        Lm = L0;
+        fl = fr;
         g0 = gp;
         L0 = Lp;
     }
@@ -184,7 +194,9 @@ __device__ __forceinline__ int reflect_clamp(int i, int n) {
 // S on the tile + 2 ring (exactly one wavefront wide: kAosTX + 4 = 64) and g
 // on the tile + 1 ring; otherwise L and g on the tile + 1 ring.  The S area
 // has rows beyond the tile + 2 ring so that every wavefront's band of g rows
-// reads whole rows; they are never written and feed no stored value.
+// reads whole rows; they are never written and feed no stored value.  S is
+// dead once g is formed, so g takes S's place (a barrier between the last
+// read of S and the first write of g): less LDS per tile, more tiles per CU.
 template <int RG, int TY, bool CG>
 struct RedGeom {
     static constexpr int WAVES = 4;
@@ -196,8 +208,9 @@ struct RedGeom {
     static constexpr int QPW = (NGY + WAVES - 1) / WAVES;  // g rows per wavefront
     static constexpr int NSA = WAVES * QPW + 2;             // S rows allocated
     static constexpr int offS = NLY * PL;
-    static constexpr int offG = offS + (CG ? NSA * PS : 0);
-    static constexpr int floats = offG + NGY * PG;
+    static constexpr int offG = offS;  // g over S (CG) or right after L
+    static constexpr int floats = offS + (CG && NSA * PS > NGY * PG ? NSA * PS : NGY * PG);
+    static constexpr int floatsLS = offS + NSA * PS;  // L and S (the conductivity kernel)
     static_assert(kAosTX + 4 == kWave, "the smoothed band is one wavefront wide");
     static_assert(NLX <= 2 * kWave, "two loads per L row");
     static_assert(SPW * WAVES == NSY, "S bands tile the region");
@@ -279,9 +292,12 @@ __device__ __forceinline__ void smooth_band(const float* sL, float* sS, int s0, 
 }
 
 // Conductivity on rows [q0, q0 + QPW) of a grid whose element (q, i) is
-// centred on S(q + 1, i + 1): the 3x3 Scharr gradient of S (unscaled:
-// Lx' = 32 Lx, Ly' = 32 Ly, so |grad|^2 = m2' / 1024, folded into c2 =
-// 1/(1024 k^2)) and g of Eq. 3 for column ic, into gv.
+// centred on S(q + 1, i + 1): the 3x3 Scharr gradient of S with weights
+// (1, 10/3, 1) instead of (3, 10, 3) and unscaled (Lx' = 32 Lx / 3,
+// Ly' = 32 Ly / 3, so |grad|^2 = 9 m2' / 1024, folded into c2 =
+// 9/(1024 k^2)) and g of Eq. 3 for column ic, into gv.
+constexpr float kTenThirds = 10.f / 3.f;
+
 template <int QPW, int PS, int GM>
 __device__ __forceinline__ void conductivity_band(const float* sS, int q0, int ic, float c2,
                                                   float (&gv)[QPW]) {
@@ -292,11 +308,11 @@ __device__ __forceinline__ void conductivity_band(const float* sS, int q0, int i
     for (int k = 0; k < QPW + 2; ++k) {
         const float a = sp[k * PS], b = sp[k * PS + 1], c = sp[k * PS + 2];
         D[k] = c - a;
-        Tt[k] = __builtin_fmaf(10.f, b, 3.f * (a + c));
+        Tt[k] = __builtin_fmaf(kTenThirds, b, a + c);
     }
 #pragma unroll
     for (int k = 0; k < QPW; ++k) {
-        const float lx = __builtin_fmaf(10.f, D[k + 1], 3.f * (D[k] + D[k + 2]));
+        const float lx = __builtin_fmaf(kTenThirds, D[k + 1], D[k] + D[k + 2]);
         const float ly = Tt[k + 2] - Tt[k];
         gv[k] = diffusivity_of<GM>(__builtin_fmaf(lx, lx, ly * ly) * c2);
     }
@@ -320,7 +336,8 @@ __device__ __forceinline__ void tile_conductivity(const float* sL, float* sS, fl
     const int q0 = wave * G::QPW;
     float gv[G::QPW];
     conductivity_band<G::QPW, G::PS, GM>(sS, q0, lane < G::NGX ? lane : G::NGX - 1,
-                                         inv_k2 * (1.f / 1024.f), gv);
+                                         inv_k2 * (9.f / 1024.f), gv);
+    __syncthreads();  // every wavefront has read S: g overwrites it
     const bool lane_g = lane < G::NGX;
     const bool col_in = lane >= 1 && lane <= kAosTX && tx0 - 1 + lane < W;
     float* gl = sG + q0 * G::PG + lane;
@@ -448,7 +465,7 @@ __global__ __launch_bounds__(kRedThreads) void cond_band_kernel(BatchImage d0, I
     const int q0 = wave * G::QPW;
     float gv[G::QPW];
     conductivity_band<G::QPW, G::PS, GM>(sS, q0, lane < G::NGX ? lane : G::NGX - 1,
-                                         inv_k2 * (1.f / 1024.f), gv);
+                                         inv_k2 * (9.f / 1024.f), gv);
     const bool col_in = lane >= 1 && lane <= kAosTX && tx0 - 1 + lane < W;
     gfloat* grow = (gfloat*)d.g + (ptrdiff_t)uniform(ty0 - 1 + q0) * W + (tx0 - 1);
     float m2max = 0.f;
@@ -479,7 +496,7 @@ hipError_t launch_cond_band_t(const BatchImage& d0, const ImgWork& w, const Taps
                               float k_host, int gmode, hipStream_t s) {
     const int count = w.items ? w.count : aos_tiles_of(d0.W, d0.H, TY);
     if (count <= 0) return hipSuccess;
-    const size_t lds = (size_t)RedGeom<RG, TY, true>::offG * sizeof(float);  // L and S
+    const size_t lds = (size_t)RedGeom<RG, TY, true>::floatsLS * sizeof(float);
 #define KZ_CB(GM)                                                                            \
     hipLaunchKernelGGL((cond_band_kernel<RG, GM, TY>), dim3(count), dim3(kRedThreads), lds, s, \
                        d0, w, tc, k_host)

@@ -139,6 +139,43 @@ def test_detector_stage(gpu_lib):
         assert err < 1e-8, (i, err)
 
 
+@pytest.mark.parametrize("W,H,sigma0", [(200, 150, 4.0), (200, 150, 4.5), (70, 66, 4.0),
+                                         (40, 20, 4.5), (33, 12, 4.5), (61, 9, 1.6)])
+def test_detector_stage_all_steps(gpu_lib, W, H, sigma0):
+    """The detector on every Scharr step it accepts (sigma0 4.0 gives steps
+    4, 5, 6, 7 in each octave, 4.5 gives 5, 5, 6, 8) and on every form of
+    its strips: bands of 64 rows, bands of 8 rows (70x66, 40x20), the
+    per-pixel form of images too low for a band (33x12 at steps above 4,
+    61x9), widths of one strip and of several with the last one aligned to
+    the image end.  Inputs are smooth random levels.  Bound per level: the
+    FP32 error of det = sigma_n^2 (Lxx Lyy - Lxy^2) is a few units of the
+    second derivatives' rounding times their size (the products cancel, so
+    |det| itself is no scale): 1e-6 sigma_n^2 max(|Lxx| + |Lyy| + 2 |Lxy|),
+    from the oracle's own derivatives."""
+    from scipy.ndimage import gaussian_filter
+    K = gpu_lib
+    note(f"[detector] {W}x{H} sigma0 {sigma0}")
+    p = K.kaze_default_params(sigma0=sigma0)
+    N = K.kaze_num_levels(p)
+    rng = np.random.default_rng(W * 1000 + H)
+    lev = np.stack([gaussian_filter(rng.random((H, W)), 1.5, mode="reflect") for _ in range(N)])
+    lev32 = f32(lev)
+    det = torch.empty(lev.shape, dtype=torch.float32, device="cuda")
+    K.kaze_detector_response(dev(lev32), W, H, p, det)
+    torch.cuda.synchronize()
+    ref = O.detector_response(lev32, sigma0=sigma0)
+    d = det.cpu().numpy()
+    for lv in O.level_schedule(sigma0, 4, 4):
+        i = lv["i"]
+        sn = lv["sigma"] / 2.0 ** lv["o"]
+        st = O.derivative_step(sn)
+        Lx, Ly = O.scharr_dx(lev32[i], st), O.scharr_dy(lev32[i], st)
+        scale = np.max(np.abs(O.scharr_dx(Lx, st)) + np.abs(O.scharr_dy(Ly, st))
+                       + 2 * np.abs(O.scharr_dy(Lx, st)))
+        err = np.max(np.abs(d[i] - ref[i]))
+        assert err <= 1e-6 * sn * sn * scale, (i, st, err, sn * sn * scale)
+
+
 # ---------------------------------------------------------------- end to end
 def check_end_to_end(K, W, H, seed, params=None, oracle_kw=None):
     note(f"[end-to-end] {W}x{H} seed {seed} params {params and dict((f, getattr(params, f)) for f, _ in params._fields_)}")
