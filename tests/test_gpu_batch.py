@@ -96,6 +96,39 @@ def test_batch_graph_replays_match_eager(gpu_lib):
     kb.close()
 
 
+@pytest.mark.parametrize("sigma0", [0.6, 3.2])
+def test_batch_detector_fork_at_other_schedules(gpu_lib, sigma0):
+    """Schedules with other Scharr steps (sigma0 0.6: every step 1; sigma0
+    3.2: steps 3 to 5, two detector launches): the single fork of a small
+    batch's first N - 5 levels in graph runs, eager runs and the
+    single-image calls agree bitwise, keypoints included."""
+    K = gpu_lib
+    p = K.kaze_default_params(sigma0=sigma0)
+    sizes = SIZES[:4]
+    note(f"[batch] sigma0 {sigma0}: sizes {sizes}")
+    kb, imgs = make_batch(K, sizes, range(120, 124), 0, params=p)
+    assert kb.det_levels_in_segment == kb.N - 5
+    kb.run(eager=True)
+    torch.cuda.synchronize()
+    ref_det = [t.clone() for t in kb.det]
+    ref_cnt = [int(c.item()) for c in kb.count]
+    for t in kb.det:
+        t.fill_(-1.0)
+    kb.run()
+    torch.cuda.synchronize()
+    for j, im in enumerate(imgs):
+        assert torch.equal(kb.det[j], ref_det[j]), j
+        assert int(kb.count[j].item()) == ref_cnt[j], j
+        H, W = im.shape
+        kz = K.Kaze(W, H, params=p)
+        kz.run(torch.from_numpy(im).cuda())
+        torch.cuda.synchronize()
+        assert torch.equal(kb.levels[j], kz.levels), j
+        assert torch.equal(kb.det[j], kz.det), j
+        assert np.array_equal(kb.keypoints(j), kz.keypoints()), j
+    kb.close()
+
+
 def test_autotuner_and_cache(gpu_lib, tmp_path):
     K = gpu_lib
     cache = str(tmp_path / "tune.json")
