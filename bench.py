@@ -243,6 +243,64 @@ def timed_runs(args, K, torch, kb, eager):
     return elapsed, 1e3 * ms / (runs * (kb.N - 1))
 
 
+def run_distribution_and_transfers(args, K, torch, kb, img_cpu, form, reps=50):
+    """Outside the timed region: the per-run time distribution of the plan
+    (an event pair around every run and its keypoint-count readback, on the
+    stream the plan runs on), the upload of the FP32 image from pinned host
+    memory and the download of the keypoint list into pinned host memory,
+    each timed with event pairs.  The PCIe-inclusive rate adds one upload
+    and one download to the median run (no overlap between them)."""
+    eager = form == "eager"
+    s = torch.cuda.current_stream()
+    counts = torch.empty(kb.counts.numel(), dtype=torch.int32, pin_memory=True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for _ in range(3):
+        kb.run(eager=eager)
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record(s)
+        kb.run(eager=eager)
+        counts.copy_(kb.counts, non_blocking=True)
+        b.record(s)
+    torch.cuda.synchronize()
+    run_us = sorted(1e3 * a.elapsed_time(b) for a, b in ev)
+
+    def pct(v, q):
+        return v[min(len(v) - 1, int(round(q * (len(v) - 1))))]
+
+    host = torch.from_numpy(img_cpu).pin_memory()
+    up = []
+    for _ in range(20):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        kb.inputs[0].copy_(host, non_blocking=True)
+        b.record(s)
+        torch.cuda.synchronize()
+        up.append(1e3 * a.elapsed_time(b))
+    kb.run(eager=eager)
+    torch.cuda.synchronize()
+    n = min(int(kb.count[0].item()), kb.capacity)
+    kp_host = torch.empty((max(n, 1), 4), dtype=torch.int32, pin_memory=True)
+    down = []
+    for _ in range(20):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        kp_host[:n].copy_(kb.kps[0][:n], non_blocking=True)
+        b.record(s)
+        torch.cuda.synchronize()
+        down.append(1e3 * a.elapsed_time(b))
+    up_us, down_us = sorted(up)[len(up) // 2], sorted(down)[len(down) // 2]
+    med = pct(run_us, 0.5)
+    nbytes = img_cpu.nbytes
+    return {"per_run_us": {"median": round(med, 2), "p10": round(pct(run_us, 0.1), 2),
+                           "p90": round(pct(run_us, 0.9), 2), "runs": reps, "form": form},
+            "upload": {"bytes": nbytes, "us": round(up_us, 2),
+                       "GB_per_s": round(nbytes / (up_us * 1e-6) / 1e9, 2)},
+            "keypoint_download": {"keypoints": n, "bytes": 16 * n, "us": round(down_us, 2)},
+            "pcie_inclusive_images_per_s": round(1e6 / (up_us + med + down_us), 2)}
+
+
 def det_levels_of(kb, form):
     """Detector levels inside the level segment of a run: a graph run's per
     the plan; an eager run keeps the single fork of small batches out."""
@@ -306,9 +364,11 @@ def bench_single(args, K, torch, kaze_image, case):
     roof["timed_in"] = "the timed region (event pair around each run's AOS segment)"
     kps = int(kb.count[0].item())
     shape = tile_label(K, kb.shape)
+    transfers = run_distribution_and_transfers(args, K, torch, kb, kaze_image(W, H, seed), form)
     kb.close()
 
     extra = {"eager_images_per_s": round(eager_value, 3), "plan_launch_forms": forms,
+             "run_distribution_and_transfers": transfers,
              "kernel_breakdown": {k: {kk: round(vv, 4) for kk, vv in v.items()}
                                   for k, v in breakdown.items()}}
     if not args.no_fed:
