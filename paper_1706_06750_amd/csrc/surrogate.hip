@@ -931,11 +931,55 @@ hipError_t launch_conv(int cin, int mb, int epi, bool tau_term, const ConvArgs& 
     return hipGetLastError();
 }
 
+// Blocks of the fused pair resident on the current device at once (compute
+// units x blocks per unit), looked up once per device.
+int pair_slots() {
+    constexpr int kMaxDevices = 64;
+    static int slots[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 0;
+    if (slots[dev] == 0) {
+        int cus = 0, per = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, conv2_kernel<32, 2, false>,
+                                                         kPairThreads, 0) != hipSuccess)
+            return 0;
+        slots[dev] = std::max(1, cus * per);
+    }
+    return slots[dev];
+}
+
+// Rows per block of a fused pair over n images of height H in `strips`
+// column strips.  A block walks its rows one step each (plus three steps of
+// fill), so a launch takes about rounds x (R + 3) steps, rounds being the
+// number of times the grid fills the device: the chunk count minimising that
+// product.  Every output row is computed by the same instructions whatever
+// the block, so the choice does not change a bit of the result.
+int pair_rows(int n, int H, int strips) {
+    const int slots = pair_slots();
+    if (slots <= 0) return kConvRows;
+    const long long per = (long long)n * strips;
+    long long best = -1;
+    int rows = kConvRows;
+    for (int chunks = 1; chunks <= H; ++chunks) {
+        const int R = (H + chunks - 1) / chunks;
+        if ((H + R - 1) / R != chunks) continue;  // same R as fewer chunks
+        const long long rounds = (per * chunks + slots - 1) / slots;
+        const long long cost = rounds * (R + 3);
+        if (best < 0 || cost < best) {
+            best = cost;
+            rows = R;
+        }
+    }
+    return rows;
+}
+
 hipError_t launch_conv2(int cina, int mbb, const Conv2Args& a, const Geo& g, hipStream_t s) {
     const int strips = (g.W + kPairOut - 1) / kPairOut;
     Geo gg = g;
     gg.strips = strips;
-    gg.chunks = (g.H + g.R - 1) / g.R;
+    if (!a.bw.imgs) gg.R = pair_rows(g.n, g.H, strips);  // batches: rows fixed by their items
+    gg.chunks = (g.H + gg.R - 1) / gg.R;
     if (a.bw.imgs && a.bw.count <= 0) return hipSuccess;
     const dim3 grid = a.bw.imgs ? dim3(a.bw.count) : dim3(strips * gg.chunks, g.n);
     const dim3 block(kPairThreads);
