@@ -66,6 +66,9 @@ typedef enum { KAZE_AOS = 0, KAZE_FED = 1 } kaze_scheme;
  *                      clipped at the image border. */
 typedef enum { KAZE_WINDOW_3X3 = 0, KAZE_WINDOW_SIGMA = 1 } kaze_extrema_window;
 
+/* Largest histogram of the contrast factor k (kaze_params.k_bins). */
+#define KAZE_MAX_K_BINS 4096
+
 /*
  * Parameters of the method (host struct, read during the call only).
  * kaze_default_params() fills the values used throughout: sigma0 = 1.6,
@@ -78,7 +81,7 @@ typedef struct {
     double sigma0;         /* base scale of Eq. 6; pre-smoothing width          */
     double sigma_cond;     /* Gaussian width before the conductivity gradient   */
     int    diffusivity;    /* KAZE_G2 (default) or KAZE_G1, Eq. 3               */
-    int    k_bins;         /* histogram bins, 1..4096                           */
+    int    k_bins;         /* histogram bins, 1..KAZE_MAX_K_BINS                */
     double k_percentile;   /* quantile of the gradient histogram, [1e-6, 1]     */
     double k_override;     /* > 0: use this contrast factor, skip the histogram */
     double det_threshold;  /* detector threshold of Sec. II-B (compared in FP32) */

@@ -136,8 +136,8 @@ kaze_status check_params(const kaze_params* p) {
     if (!(p->k_override > 0.0)) {
         if (!(p->k_percentile >= 1e-6 && p->k_percentile <= 1.0))
             return fail(KAZE_ERR_INVALID_ARG, "k_percentile must be in [1e-6, 1]");
-        if (p->k_bins < 1 || p->k_bins > 4096)
-            return fail(KAZE_ERR_INVALID_ARG, "k_bins must be in [1, 4096]");
+        if (p->k_bins < 1 || p->k_bins > KAZE_MAX_K_BINS)
+            return fail(KAZE_ERR_INVALID_ARG, "k_bins must be in [1, %d]", KAZE_MAX_K_BINS);
     }
     if (!isfinite(p->det_threshold))
         return fail(KAZE_ERR_INVALID_ARG, "det_threshold must be finite");

@@ -5,6 +5,7 @@
 // symmetric reflection at the image border; a symmetric filter applied to
 // that extension is itself half-sample symmetric, so ring values of an
 // intermediate (smoothed) image equal the reflected interior values.
+#include "kaze.h"
 #include "kaze_internal.h"
 #include "tile_stage.h"
 
@@ -203,18 +204,19 @@ __global__ __launch_bounds__(256) void kselect_kernel(BatchImage d0, ImgWork w, 
     resolve(d0, w, (int)blockIdx.x, d, unused);
     const guint* __restrict__ hist = (const guint*)d.hist;
     __shared__ unsigned long long s_scan[256];
+    __shared__ unsigned s_count[KAZE_MAX_K_BINS];  // bin counts summed over the copies
     __shared__ int s_best;
     const int t = threadIdx.x;
     const int seg = (nbins + 255) / 256;
     const int b0 = t * seg, b1 = min(nbins, b0 + seg);
     unsigned long long part = 0;
-    auto count_of = [&](int b) {  // bin b summed over the histogram's copies
+    for (int b = b0; b < b1; ++b) {
         unsigned c = 0u;
 #pragma unroll
         for (int j = 0; j < kHistCopies; ++j) c += hist[j * nbins + b];
-        return c;
-    };
-    for (int b = b0; b < b1; ++b) part += count_of(b);
+        s_count[b] = c;
+        part += c;
+    }
     s_scan[t] = part;
     if (t == 0) s_best = nbins - 1;
     __syncthreads();
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(256) void kselect_kernel(BatchImage d0, ImgWork w, 
     const unsigned __int128 rhs = (unsigned __int128)pct_mant * npos;
     unsigned long long cum = s_scan[t] - part;  // exclusive prefix
     for (int b = b0; b < b1; ++b) {
-        cum += count_of(b);
+        cum += s_count[b];  // written by this thread
         if (((unsigned __int128)cum << pct_shift) >= rhs) {
             atomicMin(&s_best, b);
             break;
