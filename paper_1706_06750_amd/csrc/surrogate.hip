@@ -26,6 +26,9 @@
 // input and of dZ; the tap's column shift is applied in registers with
 // byte alignment.  Per-wave partial sums are reduced in a fixed order, so
 // every result is deterministic.
+#include <algorithm>
+#include <atomic>
+
 #include "kaze_internal.h"
 #include "sg_internal.h"
 
@@ -935,18 +938,20 @@ hipError_t launch_conv(int cin, int mb, int epi, bool tau_term, const ConvArgs& 
 // units x blocks per unit), looked up once per device.
 int pair_slots() {
     constexpr int kMaxDevices = 64;
-    static int slots[kMaxDevices] = {};
+    static std::atomic<int> slots[kMaxDevices];  // 0: not looked up yet
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 0;
-    if (slots[dev] == 0) {
+    int v = slots[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
         int cus = 0, per = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, conv2_kernel<32, 2, false>,
                                                          kPairThreads, 0) != hipSuccess)
             return 0;
-        slots[dev] = std::max(1, cus * per);
+        v = std::max(1, cus * per);
+        slots[dev].store(v, std::memory_order_relaxed);  // every thread stores the same value
     }
-    return slots[dev];
+    return v;
 }
 
 // Rows per block of a fused pair over n images of height H in `strips`
