@@ -148,6 +148,106 @@ __device__ __forceinline__ void chunk_recover(const Acc& A, int pos0, int n, flo
     for (int k = M - 2; k >= 1; --k) x[k] = __builtin_fmaf(-cpa[k], x[k + 1], x[k]);
 }
 
+// The interior of a chunk (both ends known, as in chunk_recover) in two
+// halves on two lanes: the lower lane eliminates rows 1 .. MH forward from
+// x_0, the upper lane rows M-2 .. MH+1 backward from x_{M-1}; then
+//   x_MH = dp - cp x_{MH+1},  x_{MH+1} = dq - aq x_MH
+// gives the two middle values (split_middle), and each lane substitutes
+// back through its own half.  Every coefficient of the lower half is formed
+// as in chunk_recover, and the upper half mirrors it.
+template <int M>
+struct SplitChunk {
+    static constexpr int MH = (M - 2) / 2;  // last interior row of the lower half
+    static constexpr int NU = M - 1 - MH;   // elements MH+1 .. M-1 of the upper half
+    static_assert(MH >= 1 && NU >= 2, "both halves hold interior rows");
+};
+
+// Lower lane: x[k] for k = 0 .. MH holds dp_k (x_0 = z0), cpa[k] cp_k.
+template <int M, bool CHECK, class Acc>
+__device__ __forceinline__ void split_lower(const Acc& A, int pos0, int n, float z0,
+                                            float (&x)[SplitChunk<M>::MH + 1],
+                                            float (&cpa)[SplitChunk<M>::MH + 1]) {
+#pragma clang fp contract(off)
+    constexpr int MH = SplitChunk<M>::MH;
+    const float gm = A.g(0), Lm = A.L(0);
+    float g0 = A.g(1), L0 = A.L(1);
+    float wl = coupling<CHECK, true>(pos0 + 1 < n, 1.f, gm, g0);
+    float fl = wl * (L0 - Lm);
+    float cp = 0.f, dp = 0.f;
+#pragma unroll
+    for (int k = 1; k <= MH; ++k) {
+        const float gp = A.g(k + 1), Lp = A.L(k + 1);
+        const float wr = coupling<CHECK, true>(pos0 + k < n - 1, 1.f, g0, gp);
+        const float fr = wr * (Lp - L0);
+        float d = fr - fl;
+        const float b = (1.f + wl) + wr;
+        float a = -wl;
+        const float c = -wr;
+        if (k == 1) {
+            d = __builtin_fmaf(-a, z0, d);
+            a = 0.f;
+        }
+        const float r = rcp(__builtin_fmaf(-a, cp, b));
+        cp = c * r;
+        dp = __builtin_fmaf(-a, dp, d) * r;
+        cpa[k] = cp;
+        x[k] = dp;
+        wl = wr;
+        fl = fr;
+        g0 = gp;
+        L0 = Lp;
+    }
+    x[0] = z0;
+}
+
+// Upper lane: x[i] for element MH+1+i (i = 0 .. NU-1) holds dq (the last,
+// element M-1, holds z1), aqa[i] aq.
+template <int M, bool CHECK, class Acc>
+__device__ __forceinline__ void split_upper(const Acc& A, int pos0, int n, float z1,
+                                            float (&x)[SplitChunk<M>::NU],
+                                            float (&aqa)[SplitChunk<M>::NU]) {
+#pragma clang fp contract(off)
+    constexpr int MH = SplitChunk<M>::MH;
+    const float gq = A.g(M - 1), Lq = A.L(M - 1);
+    float g0 = A.g(M - 2), L0 = A.L(M - 2);
+    float wr = coupling<CHECK, true>(pos0 + M - 2 < n - 1, 1.f, g0, gq);
+    float fr = wr * (Lq - L0);
+    float aq = 0.f, dq = 0.f;
+#pragma unroll
+    for (int k = M - 2; k >= MH + 1; --k) {
+        const float gm = A.g(k - 1), Lm = A.L(k - 1);
+        const float wl = coupling<CHECK, true>(pos0 + k - 1 < n - 1, 1.f, gm, g0);
+        const float fl = wl * (L0 - Lm);
+        float d = fr - fl;
+        const float b = (1.f + wl) + wr;
+        const float a = -wl;
+        float c = -wr;
+        if (k == M - 2) {
+            d = __builtin_fmaf(-c, z1, d);
+            c = 0.f;
+        }
+        const float r = rcp(__builtin_fmaf(-c, aq, b));
+        aq = a * r;
+        dq = __builtin_fmaf(-c, dq, d) * r;
+        aqa[k - MH - 1] = aq;
+        x[k - MH - 1] = dq;
+        wr = wl;
+        fr = fl;
+        g0 = gm;
+        L0 = Lm;
+    }
+    x[SplitChunk<M>::NU - 1] = z1;
+}
+
+// The two middle values from the lower lane's (cp, dp) at MH and the upper
+// lane's (aq, dq) at MH+1; both lanes evaluate it alike.
+__device__ __forceinline__ void split_middle(float cp, float dp, float aq, float dq, float& xm,
+                                             float& xm1) {
+#pragma clang fp contract(off)
+    xm = __builtin_fmaf(-cp, dq, dp) * rcp(__builtin_fmaf(-cp, aq, 1.f));
+    xm1 = __builtin_fmaf(-aq, xm, dq);
+}
+
 // LDS accessor of one chunk with compile-time strides: element k (which may
 // be -1) at gp[k * GS] and Lp[k * LS], so every access is an immediate
 // offset from the thread's base address.
@@ -730,6 +830,172 @@ __global__ __launch_bounds__(TY * 4) void aos_recover_kernel(ImageDesc d0, AosWo
     }
 }
 
+// Recovery of tiles whose row chunk spans the tile width and whose column
+// chunk spans its height (60 x 64 tiles, chunks of 60 and 64): each chunk is
+// solved by two lanes (split_lower / split_upper) in two wavefronts, rows
+// in wavefronts 0 (lower halves) and 1 (upper halves), columns in 2 and 3,
+// so the serial walk is half a chunk long and all four wavefronts sweep.
+// The middle values pass through LDS; otherwise as aos_recover_kernel.
+template <int TY, int RC, int CC>
+__global__ __launch_bounds__(256) void aos_recover_split_kernel(ImageDesc d0, AosWork w,
+                                                                float tau) {
+    static_assert(RC == kAosTX && CC == TY && TY == kWave, "one chunk per tile row and column");
+    using SR = SplitChunk<RC>;
+    using SC = SplitChunk<CC>;
+    constexpr int WAVES = 4;
+    constexpr int PL = kAosTX + 1, PG = kAosTX + 1;
+    extern __shared__ float smem[];
+    float* sL = smem;
+    float* sG = smem + TY * PL;
+    float* sX = sG + TY * PG;  // [direction][half][lane][2]
+    const int tid = threadIdx.x, wave = uniform(tid >> 6), lane = tid & (kWave - 1);
+    ImageDesc d;
+    int lt;
+    resolve(d0, w, xcd_contiguous((int)blockIdx.x, (int)gridDim.x), d, lt);
+    if (d.gate && *d.gate <= d.bound) return;  // whole block
+    const int W = d.W, H = d.H;
+    const int ntx = (W + kAosTX - 1) / kAosTX;
+    const int cx = lt % ntx, cy = lt / ntx;
+    const int tx0 = cx * kAosTX, ty0 = cy * TY;
+    {
+        constexpr int PER = TY / WAVES;
+        const bool in_x = lane < kAosTX && tx0 + lane < W;
+        const gfloat* Lb = (const gfloat*)d.L + (ptrdiff_t)uniform(ty0 + wave) * W + tx0;
+        const gfloat* gb = (const gfloat*)d.g + (ptrdiff_t)uniform(ty0 + wave) * W + tx0;
+        float vl[PER], vg[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const bool in = in_x && ty0 + wave + WAVES * i < H;
+            vl[i] = in ? Lb[(ptrdiff_t)(WAVES * i) * W + lane] : 0.f;
+            vg[i] = in ? gb[(ptrdiff_t)(WAVES * i) * W + lane] : 0.f;
+        }
+        if (lane < kAosTX) {
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int r = wave + WAVES * i;
+                sL[r * PL + lane] = vl[i];
+                sG[r * PG + lane] = tau * vg[i];
+            }
+        }
+    }
+    __syncthreads();
+    const bool rows = wave < 2, upper = (wave & 1) != 0;  // wave-uniform
+    // row lanes: tile row `lane`; column lanes: tile column `lane`
+    const int y = ty0 + lane, xcol = tx0 + lane;
+    const bool live = rows ? y < H : (lane < kAosTX && xcol < W);
+    // one half of a chunk per lane: the lower half's dp (x_0 = z0) and cp,
+    // or the upper half's dq (its last element z1) and aq
+    constexpr int NX = SC::NU > SR::MH + 1 ? SC::NU : SR::MH + 1;
+    static_assert(SC::MH + 1 <= NX && SR::NU <= NX, "halves fit");
+    float x[NX], c[NX];
+    float* ex = sX + ((rows ? 0 : 2) + (upper ? 1 : 0)) * 2 * kWave + 2 * lane;
+    const float* partner = sX + ((rows ? 0 : 2) + (upper ? 0 : 1)) * 2 * kWave + 2 * lane;
+    if (live) {
+        if (rows) {
+            const vf2 z = *(const gvf2*)((const gfloat*)d.zrow + ((size_t)cx * H + y) * 2);
+            const LdsLine<1, 1> A{sG + lane * PG, sL + lane * PL};
+            const bool chk = !(tx0 + kAosTX < W);
+            if (!upper) {
+                auto& xl = *reinterpret_cast<float (*)[SR::MH + 1]>(x);
+                auto& cl = *reinterpret_cast<float (*)[SR::MH + 1]>(c);
+                if (chk)
+                    split_lower<RC, true>(A, tx0, W, z.x, xl, cl);
+                else
+                    split_lower<RC, false>(A, tx0, W, z.x, xl, cl);
+                ex[0] = c[SR::MH];
+                ex[1] = x[SR::MH];
+            } else {
+                auto& xu = *reinterpret_cast<float (*)[SR::NU]>(x);
+                auto& cu = *reinterpret_cast<float (*)[SR::NU]>(c);
+                if (chk)
+                    split_upper<RC, true>(A, tx0, W, z.y, xu, cu);
+                else
+                    split_upper<RC, false>(A, tx0, W, z.y, xu, cu);
+                ex[0] = c[0];
+                ex[1] = x[0];
+            }
+        } else {
+            const vf2 z = *(const gvf2*)((const gfloat*)d.zcol + ((size_t)(ty0 / CC) * W + xcol) * 2);
+            const LdsLine<PG, PL> A{sG + lane, sL + lane};
+            const bool chk = !(ty0 + CC < H);
+            if (!upper) {
+                auto& xl = *reinterpret_cast<float (*)[SC::MH + 1]>(x);
+                auto& cl = *reinterpret_cast<float (*)[SC::MH + 1]>(c);
+                if (chk)
+                    split_lower<CC, true>(A, ty0, H, z.x, xl, cl);
+                else
+                    split_lower<CC, false>(A, ty0, H, z.x, xl, cl);
+                ex[0] = c[SC::MH];
+                ex[1] = x[SC::MH];
+            } else {
+                auto& xu = *reinterpret_cast<float (*)[SC::NU]>(x);
+                auto& cu = *reinterpret_cast<float (*)[SC::NU]>(c);
+                if (chk)
+                    split_upper<CC, true>(A, ty0, H, z.y, xu, cu);
+                else
+                    split_upper<CC, false>(A, ty0, H, z.y, xu, cu);
+                ex[0] = c[0];
+                ex[1] = x[0];
+            }
+        }
+    }
+    __syncthreads();  // the middle coefficients of every chunk are in LDS
+    if (live) {
+        float xm, xm1;
+        if (!upper) {
+            split_middle(ex[0], ex[1], partner[0], partner[1], xm, xm1);
+            if (rows) {
+                x[SR::MH] = xm;
+#pragma unroll
+                for (int k = SR::MH - 1; k >= 1; --k) x[k] = __builtin_fmaf(-c[k], x[k + 1], x[k]);
+            } else {
+                x[SC::MH] = xm;
+#pragma unroll
+                for (int k = SC::MH - 1; k >= 1; --k) x[k] = __builtin_fmaf(-c[k], x[k + 1], x[k]);
+            }
+        } else {
+            split_middle(partner[0], partner[1], ex[0], ex[1], xm, xm1);
+            x[0] = xm1;
+            if (rows) {
+#pragma unroll
+                for (int i = 1; i <= SR::NU - 2; ++i) x[i] = __builtin_fmaf(-c[i], x[i - 1], x[i]);
+            } else {
+#pragma unroll
+                for (int i = 1; i <= SC::NU - 2; ++i) x[i] = __builtin_fmaf(-c[i], x[i - 1], x[i]);
+            }
+        }
+    }
+    if (rows && live) {  // L + delta_x / 2 into the LDS copy of L (rows own their elements)
+        float* lp = sL + lane * PL;
+        if (!upper) {
+#pragma unroll
+            for (int k = 0; k <= SR::MH; ++k) lp[k] = __builtin_fmaf(0.5f, x[k], lp[k]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < SR::NU; ++i)
+                lp[SR::MH + 1 + i] = __builtin_fmaf(0.5f, x[i], lp[SR::MH + 1 + i]);
+        }
+    }
+    __syncthreads();
+    if (!rows && live) {  // L_i = L + (delta_x + delta_y)/2, one row at a time
+        gfloat* ob = (gfloat*)d.Lnext + (ptrdiff_t)uniform(ty0) * W + tx0;
+        const int nrows = uniform(H - ty0);
+        if (!upper) {
+#pragma unroll
+            for (int k = 0; k <= SC::MH; ++k)
+                if (k < nrows)
+                    ob[(ptrdiff_t)k * W + lane] = __builtin_fmaf(0.5f, x[k], sL[k * PL + lane]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < SC::NU; ++i) {
+                const int k = SC::MH + 1 + i;
+                if (k < nrows)
+                    ob[(ptrdiff_t)k * W + lane] = __builtin_fmaf(0.5f, x[i], sL[k * PL + lane]);
+            }
+        }
+    }
+}
+
 // Global-memory accessor of one whole line for the probe solves: element
 // k of the chunk at pos0, index clamped into the line (positions outside it
 // get zero coupling weights in the chunk routines).
@@ -876,6 +1142,19 @@ hipError_t launch_recover_t(const ImageDesc& d0, const AosWork& w, float tau, hi
     return hipGetLastError();
 }
 
+// Long chunks (a row chunk across the tile, a column chunk down it): two
+// lanes per chunk (aos_recover_split_kernel).
+template <int TY, int RC, int CC>
+hipError_t launch_recover_split_t(const ImageDesc& d0, const AosWork& w, float tau,
+                                  hipStream_t s) {
+    const int count = work_count(d0, w, TY, 0);
+    if (count <= 0) return hipSuccess;
+    const size_t lds = ((size_t)2 * TY * (kAosTX + 1) + 4 * 2 * kWave) * sizeof(float);
+    hipLaunchKernelGGL((aos_recover_split_kernel<TY, RC, CC>), dim3(count), dim3(256), lds, s, d0,
+                       w, tau);
+    return hipGetLastError();
+}
+
 // Tile height and chunk lengths of a shape, as compiled kernel variants.
 enum AosVariant { AV_32_SHORT = 0, AV_64_SHORT = 1, AV_64_LONG = 2, AV_NONE = -1 };
 AosVariant aos_variant(int shape) {
@@ -936,7 +1215,7 @@ hipError_t launch_aos_recover(const ImageDesc& d0, const AosWork& w, int shape, 
     switch (aos_variant(shape)) {
         case AV_32_SHORT: return launch_recover_t<32, 30, 32>(d0, w, tau, s);
         case AV_64_SHORT: return launch_recover_t<64, 30, 32>(d0, w, tau, s);
-        case AV_64_LONG: return launch_recover_t<64, 60, 64>(d0, w, tau, s);
+        case AV_64_LONG: return launch_recover_split_t<64, 60, 64>(d0, w, tau, s);
         default: return hipErrorInvalidValue;
     }
 }
