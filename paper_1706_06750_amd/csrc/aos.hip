@@ -248,6 +248,37 @@ __device__ __forceinline__ void split_middle(float cp, float dp, float aq, float
     xm1 = __builtin_fmaf(-aq, xm, dq);
 }
 
+// Value of the neighbouring lane of the pair (lanes 2i, 2i+1).
+__device__ __forceinline__ float pair_swap(float v) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+}
+
+// A chunk reduced in two halves on a lane pair (even lane: lower half, odd:
+// upper half, each by chunk_reduce): the lower half's last row and the upper
+// half's first row couple the two middle unknowns x_h, x_{h+1}; solving that
+// 2x2 in terms of x_0 and x_{M-1} and substituting into the lower half's
+// first row and the upper half's last row gives the chunk's own two
+// equations, which the even lane returns in (e0, e1).
+__device__ __forceinline__ void merge_halves(Eq& e0, Eq& e1) {
+#pragma clang fp contract(off)
+    const Eq u0{pair_swap(e0.a), pair_swap(e0.b), pair_swap(e0.c), pair_swap(e0.d)};
+    const Eq u1{pair_swap(e1.a), pair_swap(e1.b), pair_swap(e1.c), pair_swap(e1.d)};
+    // e1: e1.a x_0 + e1.b x_h + e1.c x_{h+1} = e1.d
+    // u0: u0.a x_h + u0.b x_{h+1} + u0.c x_{M-1} = u0.d
+    const float inv = rcp(e1.b * u0.b - e1.c * u0.a);
+    const float a0 = (e1.d * u0.b - e1.c * u0.d) * inv;  // x_h = a0 + a1 x_0 + a2 x_{M-1}
+    const float a1 = -(e1.a * u0.b) * inv;
+    const float a2 = (e1.c * u0.c) * inv;
+    const float b0 = (e1.b * u0.d - u0.a * e1.d) * inv;  // x_{h+1} = b0 + b1 x_0 + b2 x_{M-1}
+    const float b1 = (e1.a * u0.a) * inv;
+    const float b2 = -(e1.b * u0.c) * inv;
+    const Eq m0{e0.a, e0.b + e0.c * a1, e0.c * a2, e0.d - e0.c * a0};
+    const Eq m1{u1.a * b1, u1.b + u1.a * b2, u1.c, u1.d - u1.a * b0};
+    e0 = m0;
+    e1 = m1;
+}
+
 // LDS accessor of one chunk with compile-time strides: element k (which may
 // be -1) at gp[k * GS] and Lp[k * LS], so every access is an immediate
 // offset from the thread's base address.
@@ -501,7 +532,37 @@ __global__ __launch_bounds__(kRedThreads) void aos_reduce_kernel(ImageDesc d0, A
     }
 
     Eq e0, e1;
-    if (wave < T::SWR) {
+    if constexpr (RC == kAosTX && CC == TY && TY == kWave) {
+        // long chunks (one per tile row and column): two lanes per chunk,
+        // rows in wavefronts 0-1, columns in 2-3 (merge_halves)
+        constexpr int MR = RC / 2, MC = CC / 2;
+        const int half = lane & 1, line = 32 * (wave & 1) + (lane >> 1);
+        if (wave < 2) {
+            const int y = ty0 + line;
+            if (y < H) {
+                const LdsLine<1, 1> A{sG + (line + 1) * G::PG + 1 + half * MR,
+                                      sL + (line + G::R) * G::PL + G::R + half * MR};
+                if (tx0 + kAosTX < W)
+                    chunk_reduce<MR, false, true>(A, tx0 + half * MR, W, 1.f, e0, e1);
+                else
+                    chunk_reduce<MR, true, true>(A, tx0 + half * MR, W, 1.f, e0, e1);
+                merge_halves(e0, e1);
+                if (!half) store_eqs(d.rrow + ((size_t)cx * H + y) * kEqFloats, e0, e1);
+            }
+        } else {
+            const int x = tx0 + line;
+            if (line < kAosTX && x < W) {
+                const LdsLine<G::PG, G::PL> A{sG + (half * MC + 1) * G::PG + 1 + line,
+                                              sL + (half * MC + G::R) * G::PL + G::R + line};
+                if (ty0 + CC < H)
+                    chunk_reduce<MC, false, true>(A, ty0 + half * MC, H, 1.f, e0, e1);
+                else
+                    chunk_reduce<MC, true, true>(A, ty0 + half * MC, H, 1.f, e0, e1);
+                merge_halves(e0, e1);
+                if (!half) store_eqs(d.rcol + ((size_t)(ty0 / CC) * W + x) * kEqFloats, e0, e1);
+            }
+        }
+    } else if (wave < T::SWR) {
         const int r = wave * T::RPW + (lane % T::RPW), h = lane / T::RPW;
         const int y = ty0 + r, pos0 = tx0 + h * RC;
         if (y < H && pos0 < W) {
