@@ -297,18 +297,21 @@ typedef struct {
  * of the reduction and recovery launches cover tiles of 60 x ty pixels, row
  * lines are cut into chunks of rc pixels and column lines into chunks of cc,
  * and the interface system of every line is solved with m chunks per lane.
+ * With l = 2 lanes per chunk each chunk is reduced and recovered in two
+ * halves on a lane pair (the halves meet in a 2x2 system of their middle
+ * unknowns); with l = 1 one lane walks the whole chunk.
  *
- *   shape   tile    rc   cc   m
- *     0     60x32   30   32   4
- *     1     60x32   30   32   8
- *     2     60x64   30   32   4
- *     3     60x64   30   32   8
- *     4     60x64   60   64   4
- *     5     60x64   60   64   8
+ *   shape   tile    rc   cc   m   l
+ *     0     60x32   30   32   4   2
+ *     1     60x32   30   32   8   2
+ *     2     60x64   30   32   4   1
+ *     3     60x64   30   32   8   1
+ *     4     60x64   60   64   4   2
+ *     5     60x64   60   64   8   2
  *
- * rc, cc and m fix the elimination order, the tile height only the launch:
- * shapes that differ in the tile alone give bitwise equal results, the
- * others agree to FP32 rounding.  Every shape fits every image size.
+ * rc, cc, m and l fix the elimination order, so the shapes agree with each
+ * other to FP32 rounding; a shape's results do not depend on the images
+ * batched with it.  Every shape fits every image size.
  * aos_shape -1 selects the default: shape 1 when the interface launch has
  * at least 1024 wavefronts at m = 8 over all images of the call, else shape
  * 0 (single-image calls use the same rule).
@@ -317,11 +320,11 @@ typedef struct {
     int aos_shape;
 } kaze_batch_config;
 
-/* Tile width and height, chunk lengths and interface chunks per lane of a
- * shape (host outputs, any may be NULL); KAZE_ERR_INVALID_ARG for a shape
- * outside [0, KAZE_AOS_SHAPES). */
+/* Tile width and height, chunk lengths, interface chunks per lane and sweep
+ * lanes per chunk of a shape (host outputs, any may be NULL);
+ * KAZE_ERR_INVALID_ARG for a shape outside [0, KAZE_AOS_SHAPES). */
 kaze_status kaze_aos_shape_info(int shape, int* tile_w, int* tile_h, int* row_chunk,
-                                int* col_chunk, int* iface_m);
+                                int* col_chunk, int* iface_m, int* chunk_lanes);
 
 typedef struct kaze_batch kaze_batch;  /* opaque plan */
 

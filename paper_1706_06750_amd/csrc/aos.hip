@@ -532,22 +532,26 @@ __global__ __launch_bounds__(kRedThreads) void aos_reduce_kernel(ImageDesc d0, A
     }
 
     Eq e0, e1;
-    if constexpr (RC == kAosTX && CC == TY && TY == kWave) {
-        // long chunks (one per tile row and column): two lanes per chunk,
-        // rows in wavefronts 0-1, columns in 2-3 (merge_halves)
+    if constexpr (chunk_lanes(TY, RC, CC) == 2) {
+        // one wavefront of row chunks and one column chunk per tile column:
+        // two lanes per chunk, rows in wavefronts 0-1, columns in 2-3
+        // (merge_halves)
         constexpr int MR = RC / 2, MC = CC / 2;
+        static_assert(2 * MR == RC && 2 * MC == CC, "chunks of even length");
         const int half = lane & 1, line = 32 * (wave & 1) + (lane >> 1);
         if (wave < 2) {
-            const int y = ty0 + line;
-            if (y < H) {
-                const LdsLine<1, 1> A{sG + (line + 1) * G::PG + 1 + half * MR,
-                                      sL + (line + G::R) * G::PL + G::R + half * MR};
+            const int r = line % TY, h = line / TY;  // row chunk h of tile row r
+            const int y = ty0 + r, pos0 = tx0 + h * RC;
+            if (y < H && pos0 < W) {
+                const LdsLine<1, 1> A{sG + (r + 1) * G::PG + 1 + h * RC + half * MR,
+                                      sL + (r + G::R) * G::PL + G::R + h * RC + half * MR};
                 if (tx0 + kAosTX < W)
-                    chunk_reduce<MR, false, true>(A, tx0 + half * MR, W, 1.f, e0, e1);
+                    chunk_reduce<MR, false, true>(A, pos0 + half * MR, W, 1.f, e0, e1);
                 else
-                    chunk_reduce<MR, true, true>(A, tx0 + half * MR, W, 1.f, e0, e1);
+                    chunk_reduce<MR, true, true>(A, pos0 + half * MR, W, 1.f, e0, e1);
                 merge_halves(e0, e1);
-                if (!half) store_eqs(d.rrow + ((size_t)cx * H + y) * kEqFloats, e0, e1);
+                if (!half)
+                    store_eqs(d.rrow + ((size_t)(T::HALVES * cx + h) * H + y) * kEqFloats, e0, e1);
             }
         } else {
             const int x = tx0 + line;
@@ -891,16 +895,19 @@ __global__ __launch_bounds__(TY * 4) void aos_recover_kernel(ImageDesc d0, AosWo
     }
 }
 
-// Recovery of tiles whose row chunk spans the tile width and whose column
-// chunk spans its height (60 x 64 tiles, chunks of 60 and 64): each chunk is
-// solved by two lanes (split_lower / split_upper) in two wavefronts, rows
-// in wavefronts 0 (lower halves) and 1 (upper halves), columns in 2 and 3,
-// so the serial walk is half a chunk long and all four wavefronts sweep.
-// The middle values pass through LDS; otherwise as aos_recover_kernel.
+// Recovery of tiles with one wavefront of row chunks and one column chunk
+// per tile column (60 x 64 tiles with chunks of 60 and 64, 60 x 32 tiles
+// with chunks of 30 and 32): each chunk is solved by two lanes (split_lower
+// / split_upper) in two wavefronts, rows in wavefronts 0 (lower halves) and
+// 1 (upper halves), columns in 2 and 3, so the serial walk is half a chunk
+// long and four wavefronts sweep.  The middle values pass through LDS;
+// otherwise as aos_recover_kernel.
 template <int TY, int RC, int CC>
 __global__ __launch_bounds__(256) void aos_recover_split_kernel(ImageDesc d0, AosWork w,
                                                                 float tau) {
-    static_assert(RC == kAosTX && CC == TY && TY == kWave, "one chunk per tile row and column");
+    using T = TileChunks<TY, RC, CC>;
+    static_assert(chunk_lanes(TY, RC, CC) == 2 && T::HALVES * TY == kWave,
+                  "one wavefront of row chunks and one column chunk per tile column");
     using SR = SplitChunk<RC>;
     using SC = SplitChunk<CC>;
     constexpr int WAVES = 4;
@@ -941,9 +948,10 @@ __global__ __launch_bounds__(256) void aos_recover_split_kernel(ImageDesc d0, Ao
     }
     __syncthreads();
     const bool rows = wave < 2, upper = (wave & 1) != 0;  // wave-uniform
-    // row lanes: tile row `lane`; column lanes: tile column `lane`
-    const int y = ty0 + lane, xcol = tx0 + lane;
-    const bool live = rows ? y < H : (lane < kAosTX && xcol < W);
+    // row lanes: chunk h of tile row r (lane = h TY + r); column lanes: tile column `lane`
+    const int r = lane % TY, h = lane / TY;
+    const int y = ty0 + r, xcol = tx0 + lane, px0 = tx0 + h * RC;
+    const bool live = rows ? (y < H && px0 < W) : (lane < kAosTX && xcol < W);
     // one half of a chunk per lane: the lower half's dp (x_0 = z0) and cp,
     // or the upper half's dq (its last element z1) and aq
     constexpr int NX = SC::NU > SR::MH + 1 ? SC::NU : SR::MH + 1;
@@ -953,25 +961,26 @@ __global__ __launch_bounds__(256) void aos_recover_split_kernel(ImageDesc d0, Ao
     const float* partner = sX + ((rows ? 0 : 2) + (upper ? 0 : 1)) * 2 * kWave + 2 * lane;
     if (live) {
         if (rows) {
-            const vf2 z = *(const gvf2*)((const gfloat*)d.zrow + ((size_t)cx * H + y) * 2);
-            const LdsLine<1, 1> A{sG + lane * PG, sL + lane * PL};
+            const vf2 z =
+                *(const gvf2*)((const gfloat*)d.zrow + ((size_t)(T::HALVES * cx + h) * H + y) * 2);
+            const LdsLine<1, 1> A{sG + r * PG + h * RC, sL + r * PL + h * RC};
             const bool chk = !(tx0 + kAosTX < W);
             if (!upper) {
                 auto& xl = *reinterpret_cast<float (*)[SR::MH + 1]>(x);
                 auto& cl = *reinterpret_cast<float (*)[SR::MH + 1]>(c);
                 if (chk)
-                    split_lower<RC, true>(A, tx0, W, z.x, xl, cl);
+                    split_lower<RC, true>(A, px0, W, z.x, xl, cl);
                 else
-                    split_lower<RC, false>(A, tx0, W, z.x, xl, cl);
+                    split_lower<RC, false>(A, px0, W, z.x, xl, cl);
                 ex[0] = c[SR::MH];
                 ex[1] = x[SR::MH];
             } else {
                 auto& xu = *reinterpret_cast<float (*)[SR::NU]>(x);
                 auto& cu = *reinterpret_cast<float (*)[SR::NU]>(c);
                 if (chk)
-                    split_upper<RC, true>(A, tx0, W, z.y, xu, cu);
+                    split_upper<RC, true>(A, px0, W, z.y, xu, cu);
                 else
-                    split_upper<RC, false>(A, tx0, W, z.y, xu, cu);
+                    split_upper<RC, false>(A, px0, W, z.y, xu, cu);
                 ex[0] = c[0];
                 ex[1] = x[0];
             }
@@ -1027,7 +1036,7 @@ __global__ __launch_bounds__(256) void aos_recover_split_kernel(ImageDesc d0, Ao
         }
     }
     if (rows && live) {  // L + delta_x / 2 into the LDS copy of L (rows own their elements)
-        float* lp = sL + lane * PL;
+        float* lp = sL + r * PL + h * RC;
         if (!upper) {
 #pragma unroll
             for (int k = 0; k <= SR::MH; ++k) lp[k] = __builtin_fmaf(0.5f, x[k], lp[k]);
@@ -1271,10 +1280,14 @@ hipError_t launch_aos_iface(const ImageDesc& d0, const AosWork& w, int shape, hi
     return hipGetLastError();
 }
 
+static_assert(chunk_lanes(32, 30, 32) == 2 && chunk_lanes(64, 30, 32) == 1 &&
+                  chunk_lanes(64, 60, 64) == 2,
+              "the recovery variants below match the lanes per chunk of each shape");
+
 hipError_t launch_aos_recover(const ImageDesc& d0, const AosWork& w, int shape, float tau,
                               hipStream_t s) {
     switch (aos_variant(shape)) {
-        case AV_32_SHORT: return launch_recover_t<32, 30, 32>(d0, w, tau, s);
+        case AV_32_SHORT: return launch_recover_split_t<32, 30, 32>(d0, w, tau, s);
         case AV_64_SHORT: return launch_recover_t<64, 30, 32>(d0, w, tau, s);
         case AV_64_LONG: return launch_recover_split_t<64, 60, 64>(d0, w, tau, s);
         default: return hipErrorInvalidValue;

@@ -1683,7 +1683,7 @@ kaze_status kaze_find_extrema(const float* det, int W, int H, const kaze_params*
 
 // ---------------------------------------------------------------- batches
 kaze_status kaze_aos_shape_info(int shape, int* tile_w, int* tile_h, int* row_chunk,
-                                int* col_chunk, int* iface_m) {
+                                int* col_chunk, int* iface_m, int* chunk_lanes_out) {
     if (shape < 0 || shape >= kAosShapes)
         return fail(KAZE_ERR_INVALID_ARG, "AOS shape %d outside [0, %d)", shape, kAosShapes);
     const AosShape& a = kAosShape[shape];
@@ -1692,6 +1692,7 @@ kaze_status kaze_aos_shape_info(int shape, int* tile_w, int* tile_h, int* row_ch
     if (row_chunk) *row_chunk = a.rc;
     if (col_chunk) *col_chunk = a.cc;
     if (iface_m) *iface_m = a.m;
+    if (chunk_lanes_out) *chunk_lanes_out = chunk_lanes(a.ty, a.rc, a.cc);
     return KAZE_OK;
 }
 

@@ -203,6 +203,13 @@ constexpr AosShape kAosShape[kAosShapes] = {
     {64, 30, 32, 8}, {64, 60, 64, 4}, {64, 60, 64, 8},
 };
 constexpr int kMaxColChunk = 64;
+// Lanes per chunk in the sweeps of a shape: 2 when the tile's row chunks
+// fill one wavefront and one column chunk spans the tile height (every
+// chunk then goes to a lane pair and all four wavefronts of the tile sweep),
+// else 1.
+constexpr int chunk_lanes(int ty, int rc, int cc) {
+    return (kAosTX / rc) * ty == 64 && cc == ty ? 2 : 1;
+}
 
 __host__ __device__ inline int aos_row_chunks(int W, int rc) { return (W + rc - 1) / rc; }
 __host__ __device__ inline int aos_col_chunks(int H, int cc) { return (H + cc - 1) / cc; }

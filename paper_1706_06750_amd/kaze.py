@@ -122,7 +122,7 @@ def _load():
         "kaze_batch_properties": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "kaze_batch_destroy": (i32, [vp]),
         "kaze_batch_autotune": (i32, [vp, i32, P, vp, sz, i32, vp, vp, vp]),
-        "kaze_aos_shape_info": (i32, [i32] + [ctypes.POINTER(i32)] * 5),
+        "kaze_aos_shape_info": (i32, [i32] + [ctypes.POINTER(i32)] * 6),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -137,16 +137,17 @@ lib = _load()
 def _shape_table():
     out = []
     for sh in range(64):
-        v = [ctypes.c_int() for _ in range(5)]
+        v = [ctypes.c_int() for _ in range(6)]
         if lib.kaze_aos_shape_info(sh, *[ctypes.byref(x) for x in v]) != KAZE_OK:
             break
-        out.append(dict(zip(("tile_w", "tile_h", "row_chunk", "col_chunk", "iface_m"),
-                            (x.value for x in v))))
+        out.append(dict(zip(("tile_w", "tile_h", "row_chunk", "col_chunk", "iface_m",
+                             "chunk_lanes"), (x.value for x in v))))
     return tuple(out)
 
 
 # Launch shapes of the AOS steps (kaze_batch_config.aos_shape): tile width
-# and height, chunk lengths of rows and columns, interface chunks per lane.
+# and height, chunk lengths of rows and columns, interface chunks per lane,
+# sweep lanes per chunk.
 AOS_SHAPES = _shape_table()
 
 

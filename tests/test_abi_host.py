@@ -209,18 +209,18 @@ def test_batch_workspace_query(K):
 def test_aos_shape_table(K):
     """The library's shape table is the one include/kaze.h documents."""
     hdr = open(HEADER).read()
-    rows = re.findall(r"^ \*\s+(\d)\s+(\d+)x(\d+)\s+(\d+)\s+(\d+)\s+(\d+)\s*$", hdr,
+    rows = re.findall(r"^ \*\s+(\d)\s+(\d+)x(\d+)\s+(\d+)\s+(\d+)\s+(\d+)\s+(\d)\s*$", hdr,
                       flags=re.M)
     m = re.search(r"#define KAZE_AOS_SHAPES (\d+)", hdr)
     assert m and int(m.group(1)) == len(K.AOS_SHAPES) == len(rows)
     for r in rows:
         a = K.AOS_SHAPES[int(r[0])]
-        assert (a["tile_w"], a["tile_h"], a["row_chunk"], a["col_chunk"], a["iface_m"]) == \
-            tuple(int(v) for v in r[1:]), r
+        assert (a["tile_w"], a["tile_h"], a["row_chunk"], a["col_chunk"], a["iface_m"],
+                a["chunk_lanes"]) == tuple(int(v) for v in r[1:]), r
         # whole chunks per tile: the kernels' lane mapping assumes it
         assert a["tile_w"] % a["row_chunk"] == 0 and a["tile_h"] % a["col_chunk"] == 0
     for bad in (-1, len(K.AOS_SHAPES)):
-        assert K.lib.kaze_aos_shape_info(bad, None, None, None, None, None) == \
+        assert K.lib.kaze_aos_shape_info(bad, None, None, None, None, None, None) == \
             K.KAZE_ERR_INVALID_ARG
 
 

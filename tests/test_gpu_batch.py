@@ -35,10 +35,10 @@ def make_batch(K, sizes, seeds, shape, **kw):
 
 
 def _same_arithmetic(K, a, b):
-    """Shapes that differ in the tile height alone evaluate the same
-    arithmetic (chunk lengths and interface lanes fix it)."""
+    """Shapes with the same chunk lengths, interface chunks per lane and
+    sweep lanes per chunk evaluate the same arithmetic."""
     x, y = K.AOS_SHAPES[a], K.AOS_SHAPES[b]
-    return all(x[k] == y[k] for k in ("row_chunk", "col_chunk", "iface_m"))
+    return all(x[k] == y[k] for k in ("row_chunk", "col_chunk", "iface_m", "chunk_lanes"))
 
 
 @pytest.mark.parametrize("shape", range(6))

@@ -56,13 +56,13 @@ def test_one_substep_is_the_default_path(gpu_lib):
 
 @pytest.mark.parametrize("shape", [0, 2])
 def test_substeps_batch_equals_single(gpu_lib, shape):
-    """Sub-steps in a batch plan, bitwise against the single-image calls:
-    shapes 0 and 2 (tiles 60x32 and 60x64) share the chunk lengths and the
-    interface lanes of the single-image default at these sizes, so both
-    evaluate the same arithmetic."""
+    """Sub-steps in a batch plan against the single-image calls (shape 0 at
+    these sizes): bitwise for shape 0; shape 2 (60x64 tiles, one lane per
+    chunk) rounds differently, so within 1e-5 with the keypoint sets equal up
+    to the excuse rule."""
     K = gpu_lib
-    ref_shape = K.AOS_SHAPES[0]
-    assert all(K.AOS_SHAPES[shape][k] == ref_shape[k] for k in ("row_chunk", "col_chunk", "iface_m"))
+    keys = ("row_chunk", "col_chunk", "iface_m", "chunk_lanes")
+    exact = all(K.AOS_SHAPES[shape][k] == K.AOS_SHAPES[0][k] for k in keys)
     p = K.kaze_default_params(substeps=3)
     sizes = [(160, 120), (67, 45), (31, 33)]
     kb = K.KazeBatch(sizes, params=p, shape=shape)
@@ -73,7 +73,13 @@ def test_substeps_batch_equals_single(gpu_lib, shape):
     torch.cuda.synchronize()
     for j, im in enumerate(imgs):
         ref = run(K, im, substeps=3)
-        assert torch.equal(kb.levels[j], ref.levels)
-        assert np.array_equal(kb.keypoints(j), ref.keypoints())
+        if exact:
+            assert torch.equal(kb.levels[j], ref.levels)
+            assert np.array_equal(kb.keypoints(j), ref.keypoints())
+        else:
+            assert (kb.levels[j] - ref.levels).abs().max().item() <= 1e-5
+            det_ref = ref.det.cpu().numpy().astype(np.float64)
+            _, bad_b, bad_r = compare_keypoints(kb.keypoints(j), ref.keypoints(), det_ref, 0.001)
+            assert not bad_b and not bad_r, (j, bad_b, bad_r)
     kb.close()
 
