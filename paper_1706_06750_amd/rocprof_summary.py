@@ -23,6 +23,15 @@ import json
 import os
 
 AOS_KERNELS = ("aos_reduce_kernel", "aos_iface_kernel", "aos_recover_kernel")
+# recovery kernels by name (two lanes per chunk, or one), counted as one role
+RECOVER_NAMES = ("aos_recover_kernel", "aos_recover_split_kernel")
+
+
+def base_name(name: str) -> str:
+    """Kernel name without template arguments, the recovery variants under
+    aos_recover_kernel."""
+    base = name.split("<")[0]
+    return "aos_recover_kernel" if base in RECOVER_NAMES else base
 DET_KERNELS = ("det_strip_kernel",)
 
 
@@ -92,14 +101,14 @@ def counter_means(path: str, counter: str, aos_shape: str | None = None):
     """Mean counter value per dispatch, by kernel.  With aos_shape (a shape
     label, '60x32 c30/32 m4') only the AOS kernels of that shape count (the
     autotuner runs every shape first): aos_reduce_kernel<RG, TY, RC, CC, CG,
-    GM>, aos_recover_kernel<TY, RC, CC>, and aos_iface_kernel<M> dispatches
+    GM>, aos_recover(_split)_kernel<TY, RC, CC>, and aos_iface_kernel<M> dispatches
     whose preceding reduction (in dispatch order) had that shape's tile."""
     acc = collections.defaultdict(list)
     want = parse_shape(aos_shape) if aos_shape else None
     last_tile = None
     for r in _rows(path, counter):
         name = short(r.get("Kernel_Name", r.get("kernel_name")))
-        base = name.split("<")[0]
+        base = base_name(name)
         if base == "aos_reduce_kernel":
             last_tile = tuple(template_args(name)[1:4])
         if want and base == "aos_reduce_kernel" and last_tile != want[:3]:
@@ -121,7 +130,7 @@ def counter_totals(path: str, counter: str):
     for r in csv.DictReader(open(path)):
         if r.get("Counter_Name", r.get("counter_name")) != counter:
             continue
-        base = short(r.get("Kernel_Name", r.get("kernel_name"))).split("<")[0]
+        base = base_name(short(r.get("Kernel_Name", r.get("kernel_name"))))
         tot[base] += float(r.get("Counter_Value", r.get("value")))
         cnt[base] += 1
     return tot, cnt
@@ -136,7 +145,7 @@ def shapes_present(path: str, counter: str):
         if r.get("Counter_Name", r.get("counter_name")) != counter:
             continue
         name = short(r.get("Kernel_Name", r.get("kernel_name")))
-        base = name.split("<")[0]
+        base = base_name(name)
         if base == "aos_recover_kernel":
             tiles.add(tuple(template_args(name)))
         elif base == "aos_iface_kernel":
