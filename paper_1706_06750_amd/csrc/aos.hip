@@ -688,12 +688,68 @@ __device__ __forceinline__ Eq pcr_reduce_rcp(const Eq& e, const Eq& lo, const Eq
     return Eq{-k1 * lo.a, e.b - k1 * lo.c - k2 * up.a, -k2 * up.c, e.d - k1 * lo.d - k2 * up.d};
 }
 
+// Equations of lane l - S (below) and l + S (above) within the lane's row of
+// 16 (DPP row shifts, S < 16); a source outside the row reads zeros, which
+// the callers replace by identity rows (segments of at most 16 lanes never
+// reach across a row).
+template <int S>
+__device__ __forceinline__ float dpp_below(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                 0x110 + S, 0xF, 0xF, true));
+}
+template <int S>
+__device__ __forceinline__ float dpp_above(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                 0x100 + S, 0xF, 0xF, true));
+}
+template <int S>
+__device__ __forceinline__ Eq eq_below(const Eq& e) {
+    return Eq{dpp_below<S>(e.a), dpp_below<S>(e.b), dpp_below<S>(e.c), dpp_below<S>(e.d)};
+}
+template <int S>
+__device__ __forceinline__ Eq eq_above(const Eq& e) {
+    return Eq{dpp_above<S>(e.a), dpp_above<S>(e.b), dpp_above<S>(e.c), dpp_above<S>(e.d)};
+}
+
+// One PCR round at stride S with DPP exchanges (segments of P <= 16 lanes).
+template <int S>
+__device__ __forceinline__ void pcr_round_dpp(Eq& e0, Eq& e1, int pos, int P) {
+    const bool has_lo = pos >= S, has_up = pos + S < P;
+    Eq lo0 = eq_below<S>(e0), up0 = eq_above<S>(e0);
+    Eq lo1 = eq_below<S>(e1), up1 = eq_above<S>(e1);
+    if (!has_lo) { lo0 = eq_identity(); lo1 = eq_identity(); }
+    if (!has_up) { up0 = eq_identity(); up1 = eq_identity(); }
+    const Eq n0 = pcr_reduce_rcp(e0, lo0, up0);
+    const Eq n1 = pcr_reduce_rcp(e1, lo1, up1);
+    e0 = n0;
+    e1 = n1;
+}
+
 // PCR over segments of P lanes (P a power of two, segments aligned): lane
 // `pos` of a segment holds the two reduced equations of its part of the
 // line (e0 for its first unknown, e1 for its last); neighbours outside the
 // segment are identity rows.  Every lane of the wavefront must take part.
 __device__ __forceinline__ void seg_pcr_pairs(Eq e0, Eq e1, int lane, int pos, int P, float& z0,
                                               float& z1) {
+    if (P <= 16) {  // wave-uniform: every exchange inside a DPP row, same values
+        {
+            Eq prev1 = eq_below<1>(e1);
+            Eq next0 = eq_above<1>(e0);
+            if (pos == 0) prev1 = eq_identity();
+            if (pos == P - 1) next0 = eq_identity();
+            const Eq n0 = pcr_reduce_rcp(e0, prev1, e1);
+            const Eq n1 = pcr_reduce_rcp(e1, e0, next0);
+            e0 = n0;
+            e1 = n1;
+        }
+        if (P > 1) pcr_round_dpp<1>(e0, e1, pos, P);
+        if (P > 2) pcr_round_dpp<2>(e0, e1, pos, P);
+        if (P > 4) pcr_round_dpp<4>(e0, e1, pos, P);
+        if (P > 8) pcr_round_dpp<8>(e0, e1, pos, P);
+        z0 = e0.d * rcp(e0.b);
+        z1 = e1.d * rcp(e1.b);
+        return;
+    }
     {
         Eq prev1 = lane_read(e1, lane > 0 ? lane - 1 : 0);
         Eq next0 = lane_read(e0, lane < kWave - 1 ? lane + 1 : kWave - 1);
