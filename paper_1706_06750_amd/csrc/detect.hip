@@ -98,7 +98,7 @@ __device__ __forceinline__ void wave_lds_sync() { __builtin_amdgcn_fence(__ATOMI
 // ends at column W and the last band at row H, so the reflected ring rows
 // are known at compile time; an output pixel (and its mask bit) is stored by
 // the one strip and band that own it.
-constexpr int kDetBand = 64;       // rows per band
+constexpr int kDetBand = 32;       // rows per band
 constexpr int kDetBandSmall = 8;   // rows per band of images lower than that allows
 
 // Rows per band for images of height H at step S: bands of B rows need
