@@ -98,21 +98,21 @@ __device__ __forceinline__ void wave_lds_sync() { __builtin_amdgcn_fence(__ATOMI
 // ends at column W and the last band at row H, so the reflected ring rows
 // are known at compile time; an output pixel (and its mask bit) is stored by
 // the one strip and band that own it.
-constexpr int kDetBand = 32;       // rows per band
-constexpr int kDetBandSmall = 8;   // rows per band of images lower than that allows
+constexpr int kDetBandSmall = 8;   // rows per band of images lower than `band` allows
 
-// Rows per band for images of height H at step S: bands of B rows need
+// Rows per band for images of height H at step S, bands of `band` rows
+// (kDetBandShort or kDetBandTall) where they fit: bands of B rows need
 // H == B or H >= B + S (only the first band meets the top border, only the
 // last the bottom one) and H >= 2S (rows of L one reflection away); lower
 // images take the per-pixel form (0).
-__host__ __device__ inline int det_band_rows(int H, int S) {
-    if (H == kDetBand || H >= kDetBand + S) return kDetBand;
+__host__ __device__ inline int det_band_rows(int H, int S, int band) {
+    if (H == band || H >= band + S) return band;
     if ((H == kDetBandSmall || H >= kDetBandSmall + S) && H >= 2 * S) return kDetBandSmall;
     return 0;
 }
 
-__host__ __device__ inline int det_units(int W, int H, int S) {
-    const int b = det_band_rows(H, S);
+__host__ __device__ inline int det_units(int W, int H, int S, int band) {
+    const int b = det_band_rows(H, S, band);
     return det_strips(W, S) * (b ? (H + b - 1) / b : 1);
 }
 
@@ -303,10 +303,12 @@ __device__ __forceinline__ void det_strip_pixels(const BatchImage& d, int lev, i
 template <int S>
 __device__ __forceinline__ void det_strip_unit(const BatchImage& d, int lev, int unit,
                                                const DetLevels& dl, float* wl, int lane) {
-    if (unit >= det_units(d.W, d.H, S)) return;  // uniform per wavefront
-    const int B = det_band_rows(d.H, S);
-    if (B == kDetBand)
-        det_strip_band<S, kDetBand>(d, lev, unit, dl, wl, lane);
+    if (unit >= det_units(d.W, d.H, S, dl.band)) return;  // uniform per wavefront
+    const int B = det_band_rows(d.H, S, dl.band);
+    if (B == kDetBandTall)
+        det_strip_band<S, kDetBandTall>(d, lev, unit, dl, wl, lane);
+    else if (B == kDetBandShort)
+        det_strip_band<S, kDetBandShort>(d, lev, unit, dl, wl, lane);
     else if (B == kDetBandSmall)
         det_strip_band<S, kDetBandSmall>(d, lev, unit, dl, wl, lane);
     else
@@ -800,7 +802,7 @@ hipError_t launch_det_strips(const BatchImage& d0, const ImgWork& w, int lev0, i
     int n = 0;
     for (int i = lev0; i < lev1; ++i)
         if (dl.step[i] == SA || (SB > 0 && dl.step[i] == SB)) dls.list[n++] = i;
-    const int count = w.items ? w.count : det_tiles_of(d0.W, d0.H, SA, SB > 0 ? SB : SA);
+    const int count = w.items ? w.count : det_tiles_of(d0.W, d0.H, SA, SB > 0 ? SB : SA, dl.band);
     if (n == 0 || count <= 0) return hipSuccess;
     hipLaunchKernelGGL((det_strip_kernel<SA, SB>), dim3(count, n), dim3(kDetThreads), 0, s, d0,
                        w, dls);
@@ -809,10 +811,10 @@ hipError_t launch_det_strips(const BatchImage& d0, const ImgWork& w, int lev0, i
 
 }  // namespace
 
-int det_tiles_of(int W, int H, int smin, int smax) {
+int det_tiles_of(int W, int H, int smin, int smax, int band) {
     int n = 0;
     for (int S = smin; S <= smax; ++S)
-        n = std::max(n, (det_units(W, H, S) + kDetWaves - 1) / kDetWaves);
+        n = std::max(n, (det_units(W, H, S, band) + kDetWaves - 1) / kDetWaves);
     return n;
 }
 
@@ -823,6 +825,7 @@ int nms_blocks_of(int W, int H, bool masked) {
 
 hipError_t launch_det(const BatchImage& d0, const ImgWork& w, int lev0, int lev1,
                       const DetLevels& dl, hipStream_t s) {
+    if (dl.band != kDetBandShort && dl.band != kDetBandTall) return hipErrorInvalidValue;
     // two adjacent steps (the default schedule: 2 and 3) share one launch
     int smin = 1 << 30, smax = 0;
     for (int i = lev0; i < lev1; ++i) {

@@ -217,9 +217,12 @@ kaze_status check_steps(const kaze_params* p) {
     return KAZE_OK;
 }
 
-DetLevels det_levels(const std::vector<Level>& lv) {
+// Per-level detector constants; band: rows per detector band (det_band_for
+// of the pixels of one run).
+DetLevels det_levels(const std::vector<Level>& lv, int band) {
     DetLevels dl;
     memset(&dl, 0, sizeof(dl));
+    dl.band = band;
     for (size_t i = 0; i < lv.size(); ++i) {
         dl.step[i] = lv[i].step;
         dl.sn2[i] = (float)(lv[i].sigma_n * lv[i].sigma_n);
@@ -404,6 +407,7 @@ struct kaze_batch {
     hipStream_t side = nullptr;      // fork target while a segment is captured
     std::vector<hipEvent_t> ev;      // fork / join points (N + 1)
     bool fork_det = false;           // detector response beside the steps, per level
+    int det_band = kDetBandShort;    // rows per detector band (det_band_for of the plan's pixels)
     int split_det = -1;              // else: levels 0..split_det forked once
     SgBatch* sg = nullptr;           // surrogate steps (kaze_sg_batch_create), or none
 };
@@ -457,18 +461,26 @@ void step_range(const kaze_params* p, int& smin, int& smax) {
     }
 }
 
+// Pixels of one run of a batch.
+double batch_pixels(const kaze_image_desc* im, int n) {
+    double px = 0;
+    for (int j = 0; j < n; ++j) px += (double)im[j].W * im[j].H;
+    return px;
+}
+
 BatchLayout batch_layout(const kaze_image_desc* im, int n, const kaze_params* p, int shape) {
     BatchLayout L;
     const int N = p->octaves * p->sublevels;
     int smin, smax;
     step_range(p, smin, smax);
+    const int band = det_band_for(batch_pixels(im, n));
     L.n_tiles = L.n_aos = L.n_lines = L.n_hist = L.n_det = L.n_nms = 0;
     for (int j = 0; j < n; ++j) {
         L.n_tiles += tiles_of(im[j].W, im[j].H);
         L.n_aos += aos_tiles_of(im[j].W, im[j].H, kAosShape[shape].ty);
         L.n_lines += aos_line_groups(im[j].W, im[j].H, kAosShape[shape]);
         L.n_hist += (im[j].W * im[j].H + kHistChunk - 1) / kHistChunk;
-        L.n_det += det_tiles_of(im[j].W, im[j].H, smin, smax);
+        L.n_det += det_tiles_of(im[j].W, im[j].H, smin, smax, band);
         L.n_nms += nms_blocks_of(im[j].W, im[j].H, true);
     }
     size_t off = 0;
@@ -545,7 +557,7 @@ kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStre
         return base_and_k(b0, images, tiles, ctiles, kAosShape[B.shape].ty, hist, p, s);
     }
     const ImgWork det{B.d_imgs, B.d_det, B.n_det};
-    DetLevels dl = det_levels(B.lv);
+    DetLevels dl = det_levels(B.lv, B.det_band);
     dl.thr = (float)p->det_threshold;  // of the masks the extrema kernel reads
     const bool fork = B.fork_det && side != nullptr;
     const int split = side != nullptr && split_ok && !B.fork_det ? B.split_det : -1;
@@ -644,8 +656,8 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
     B->shape = shape;
     B->with_det = im[0].det != nullptr;
     B->with_nms = im[0].count != nullptr;
-    double px = 0;
-    for (int j = 0; j < n; ++j) px += (double)im[j].W * im[j].H;
+    const double px = batch_pixels(im, n);
+    B->det_band = det_band_for(px);
     // surrogate batches run the detector after the steps (no fork)
     B->fork_det = !sp && B->with_det && px >= kForkDetPixels;
     B->split_det = !sp && B->with_det && !B->fork_det && B->N > kSplitDetBack + 1
@@ -721,7 +733,8 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
         for (int t = 0; t < aos_line_groups(d.W, d.H, kAosShape[shape]); ++t)
             hl[il++] = make_int2(j, t);
         for (int t = 0; t < (d.W * d.H + kHistChunk - 1) / kHistChunk; ++t) hh[ih++] = make_int2(j, t);
-        for (int t = 0; t < det_tiles_of(d.W, d.H, smin, smax); ++t) hd[idt++] = make_int2(j, t);
+        for (int t = 0; t < det_tiles_of(d.W, d.H, smin, smax, B->det_band); ++t)
+            hd[idt++] = make_int2(j, t);
         for (int t = 0; t < nms_blocks_of(d.W, d.H, true); ++t) hn[inm++] = make_int2(j, t);
     }
     hipStream_t cs = nullptr;
@@ -937,7 +950,10 @@ kaze_status sg_segment(const kaze_sg_scale_space& S, int seg, hipStream_t s) {
     const ImgWork none{nullptr, nullptr, 0};
     if (seg == 0) return base_and_k(S.b, none, none, none, kAosShape[0].ty, none, p, s);
     if (seg == 2) {
-        if (S.with_det) KZ_LAUNCH(K_DET, s, launch_det(S.b, none, 0, S.N, det_levels(S.lv), s));
+        if (S.with_det)
+            KZ_LAUNCH(K_DET, s,
+                      launch_det(S.b, none, 0, S.N,
+                                 det_levels(S.lv, det_band_for((double)S.b.W * S.b.H)), s));
         if (S.with_nms)
             KZ_LAUNCH(K_NMS, s,
                       launch_nms(S.b, none, S.N, (float)p->det_threshold, nms_radii(p), s));
@@ -1576,7 +1592,7 @@ kaze_status kaze_derivatives(const float* levels, int W, int H, const kaze_param
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<Level> lv;
     schedule(p, lv);
-    const DetLevels dl = det_levels(lv);
+    const DetLevels dl = det_levels(lv, det_band_for((double)W * H));
     const int N = (int)lv.size();
     bool rows = true;
     for (int i = 0; i < N; ++i) rows = rows && lv[i].step <= 4;
@@ -1654,7 +1670,9 @@ kaze_status kaze_detector_response(const float* levels, int W, int H, const kaze
     b.det = det;
     const ImgWork none{nullptr, nullptr, 0};
     hipStream_t s = static_cast<hipStream_t>(stream);
-    KZ_LAUNCH(K_DET, s, launch_det(b, none, 0, (int)lv.size(), det_levels(lv), s));
+    KZ_LAUNCH(K_DET, s,
+              launch_det(b, none, 0, (int)lv.size(), det_levels(lv, det_band_for((double)W * H)),
+                         s));
     return KAZE_OK;
 }
 

@@ -32,7 +32,18 @@ struct DetLevels {
     float sn[kMaxLevels];    // sigma_n
     int list[kMaxLevels];    // per launch: the levels it covers, in order
     float thr;               // detector threshold of the masks (BatchImage::mask)
+    int band;                // rows per detector band (det_band_for)
 };
+
+// Rows per band of the detector's strips: short bands give more wavefronts
+// for the same work (faster while the levels sit in the 256 MB cache),
+// tall ones re-read fewer halo rows (less HBM traffic on large batches).
+constexpr int kDetBandShort = 32;
+constexpr int kDetBandTall = 64;
+constexpr double kTallBandPixels = 32e6;  // pixels per run from which bands are tall
+inline int det_band_for(double pixels) {
+    return pixels >= kTallBandPixels ? kDetBandTall : kDetBandShort;
+}
 
 // Per-level constants of the description stage: Scharr step, sigma_n and
 // the level's scale sigma_i (Eq. 6).
@@ -411,7 +422,7 @@ hipError_t launch_probe_err(const float* L, const float* cand, int W, const int4
 hipError_t launch_det(const BatchImage& d0, const ImgWork& w, int lev0, int lev1,
                       const DetLevels& dl, hipStream_t s);
 // Blocks per level of an image for the levels of steps smin..smax.
-int det_tiles_of(int W, int H, int smin, int smax);
+int det_tiles_of(int W, int H, int smin, int smax, int band);
 // a7: extrema of levels 1..N-2 (items: image, block of 64 x 4*kNmsRows pixels).
 // Half-side of the cross-level window of each level (1: the 3x3x3 test) and
 // the Scharr step of each level (the layout of its detector mask).
