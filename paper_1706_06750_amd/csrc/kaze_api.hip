@@ -66,7 +66,8 @@ struct ProfScope {
         const size_t need = 2 * (size_t)(g_prof.used + 1);
         while (g_prof.ev.size() < need) {
             hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return;
+            // timing only: no system-scope cache write-back at each record
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return;
             g_prof.ev.push_back(e);
         }
         on = hipEventRecord(g_prof.ev[2 * g_prof.used], s) == hipSuccess;
