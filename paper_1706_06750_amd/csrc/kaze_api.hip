@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "kaze.h"
@@ -2058,14 +2059,15 @@ kaze_status kaze_profile_end(int* launches, double* total_ms) {
 }
 
 const char* kaze_kernel_names(void) {
-    static char buf[512] = "";
-    if (!buf[0]) {
+    static const std::string names = [] {  // built once, thread-safe initialisation
+        std::string s;
         for (int i = 0; i < K_COUNT; ++i) {
-            if (i) strcat(buf, ",");
-            strcat(buf, kKernelNames[i]);
+            if (i) s += ",";
+            s += kKernelNames[i];
         }
-    }
-    return buf;
+        return s;
+    }();
+    return names.c_str();
 }
 
 kaze_status kaze_copy_f32(const float* src, float* dst, size_t n, void* stream) {
