@@ -520,12 +520,12 @@ __global__ __launch_bounds__(kRedThreads) void aos_reduce_kernel(ImageDesc d0, A
     const int cx = lt % ntx, cy = lt / ntx;
     const int tx0 = cx * kAosTX, ty0 = cy * TY;
 
+    const float k = CG && d.k ? d.k[0] : k_host;  // issued with the staging loads
     load_region<G::NLY, G::NLX, G::PL>(d.L, W, H, ty0 - G::R, tx0 - G::R, 1.f, sL, wave, lane);
     if constexpr (!CG)
         load_region<G::NGY, G::NGX, G::PG>(d.g, W, H, ty0 - 1, tx0 - 1, tau, sG, wave, lane);
     __syncthreads();
     if constexpr (CG) {
-        const float k = d.k ? d.k[0] : k_host;
         tile_conductivity<RG, TY, GM>(sL, sS, sG, tc, 1.f / (k * k), tau, d.g, W, H, tx0, ty0,
                                       wave, lane);
         __syncthreads();
@@ -981,6 +981,15 @@ __global__ __launch_bounds__(256) void aos_recover_split_kernel(ImageDesc d0, Ao
     const int ntx = (W + kAosTX - 1) / kAosTX;
     const int cx = lt % ntx, cy = lt / ntx;
     const int tx0 = cx * kAosTX, ty0 = cy * TY;
+    const bool rows = wave < 2, upper = (wave & 1) != 0;  // wave-uniform
+    // row lanes: chunk h of tile row r (lane = h TY + r); column lanes: tile column `lane`
+    const int r = lane % TY, h = lane / TY;
+    const int y = ty0 + r, xcol = tx0 + lane, px0 = tx0 + h * RC;
+    const bool live = rows ? (y < H && px0 < W) : (lane < kAosTX && xcol < W);
+    vf2 z = {0.f, 0.f};  // the chunk's end values, loaded with the tile
+    if (live)
+        z = rows ? *(const gvf2*)((const gfloat*)d.zrow + ((size_t)(T::HALVES * cx + h) * H + y) * 2)
+                 : *(const gvf2*)((const gfloat*)d.zcol + ((size_t)(ty0 / CC) * W + xcol) * 2);
     {
         constexpr int PER = TY / WAVES;
         const bool in_x = lane < kAosTX && tx0 + lane < W;
@@ -996,18 +1005,13 @@ __global__ __launch_bounds__(256) void aos_recover_split_kernel(ImageDesc d0, Ao
         if (lane < kAosTX) {
 #pragma unroll
             for (int i = 0; i < PER; ++i) {
-                const int r = wave + WAVES * i;
-                sL[r * PL + lane] = vl[i];
-                sG[r * PG + lane] = tau * vg[i];
+                const int rr = wave + WAVES * i;
+                sL[rr * PL + lane] = vl[i];
+                sG[rr * PG + lane] = tau * vg[i];
             }
         }
     }
     __syncthreads();
-    const bool rows = wave < 2, upper = (wave & 1) != 0;  // wave-uniform
-    // row lanes: chunk h of tile row r (lane = h TY + r); column lanes: tile column `lane`
-    const int r = lane % TY, h = lane / TY;
-    const int y = ty0 + r, xcol = tx0 + lane, px0 = tx0 + h * RC;
-    const bool live = rows ? (y < H && px0 < W) : (lane < kAosTX && xcol < W);
     // one half of a chunk per lane: the lower half's dp (x_0 = z0) and cp,
     // or the upper half's dq (its last element z1) and aq
     constexpr int NX = SC::NU > SR::MH + 1 ? SC::NU : SR::MH + 1;
@@ -1017,8 +1021,6 @@ __global__ __launch_bounds__(256) void aos_recover_split_kernel(ImageDesc d0, Ao
     const float* partner = sX + ((rows ? 0 : 2) + (upper ? 0 : 1)) * 2 * kWave + 2 * lane;
     if (live) {
         if (rows) {
-            const vf2 z =
-                *(const gvf2*)((const gfloat*)d.zrow + ((size_t)(T::HALVES * cx + h) * H + y) * 2);
             const LdsLine<1, 1> A{sG + r * PG + h * RC, sL + r * PL + h * RC};
             const bool chk = !(tx0 + kAosTX < W);
             if (!upper) {
@@ -1041,7 +1043,6 @@ __global__ __launch_bounds__(256) void aos_recover_split_kernel(ImageDesc d0, Ao
                 ex[1] = x[0];
             }
         } else {
-            const vf2 z = *(const gvf2*)((const gfloat*)d.zcol + ((size_t)(ty0 / CC) * W + xcol) * 2);
             const LdsLine<PG, PL> A{sG + lane, sL + lane};
             const bool chk = !(ty0 + CC < H);
             if (!upper) {
