@@ -161,7 +161,7 @@ def main():
                          "reference for hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(images shard across GPUs with no communication; see the design notes)",
               file=sys.stderr)
         sys.exit(2)
