@@ -153,6 +153,9 @@ def main():
                     help="skip the FED-scheme measurement")
     ap.add_argument("--no-breakdown", action="store_true",
                     help="skip the per-kernel timing pass (for profiler runs)")
+    ap.add_argument("--forms", choices=("both", "eager", "graph"), default="both",
+                    help="launch forms of the image and batch plans to time (both: the "
+                         "faster is reported)")
     ap.add_argument("--no-batches", action="store_true",
                     help="skip the batch measurements beside the single image (the 64-image "
                          "uneven batch, 8 x 1920x1200, the 4K + 720p surrogate batch)")
@@ -309,10 +312,11 @@ def det_levels_of(kb, form):
 
 
 def timed_plan(args, K, torch, kb, n_images):
-    """Both launch forms of the plan are timed over the same K steps; the
-    faster is the reported one.  Returns (seconds, us per level, form, the
-    per-form figures)."""
-    res = {form: timed_runs(args, K, torch, kb, form == "eager") for form in ("eager", "graph")}
+    """Both launch forms of the plan (or the one --forms names) are timed over
+    the same K steps; the faster is the reported one.  Returns (seconds, us
+    per level, form, the per-form figures)."""
+    names = ("eager", "graph") if args.forms == "both" else (args.forms,)
+    res = {form: timed_runs(args, K, torch, kb, form == "eager") for form in names}
     best = min(res, key=lambda f: res[f][0])
     forms = {f: {"images_per_s": round(n_images * args.steps / e, 3), "us_per_level": round(u, 3)}
              for f, (e, u) in res.items()}
