@@ -24,6 +24,11 @@ __device__ __forceinline__ float scharr3(float a0, float a1, float a2) {
     return __builtin_fmaf(0.1875f, a2, __builtin_fmaf(0.625f, a1, 0.1875f * a0));
 }
 
+// The same weights across rows, rounded alike when the outer rows swap.
+__device__ __forceinline__ float scharr3v(float a0, float a1, float a2) {
+    return __builtin_fmaf(0.625f, a1, 0.1875f * (a0 + a2));
+}
+
 // Raw buffer access to one plane: the resource in scalar registers, the
 // row's byte offset in a scalar register, the lane's byte offset in a vector
 // register (no 64-bit address arithmetic per lane).  A lane offset at or
@@ -97,7 +102,10 @@ __device__ __forceinline__ void wave_lds_sync() { __builtin_amdgcn_fence(__ATOMI
 // and vertically by reading the reflected row of the rings.  The last strip
 // ends at column W and the last band at row H, so the reflected ring rows
 // are known at compile time; an output pixel (and its mask bit) is stored by
-// the one strip and band that own it.
+// the one strip and band that own it.  Vertical differences change sign
+// exactly under a vertical mirror and the vertical Scharr sums (scharr3v)
+// are symmetric in their outer rows, so det of mirrored levels is the
+// mirrored det, bit for bit.
 constexpr int kDetBandSmall = 8;   // rows per band of images lower than `band` allows
 
 // Rows per band for images of height H at step S, bands of `band` rows
@@ -197,7 +205,7 @@ __device__ __forceinline__ void det_strip_band(const BatchImage& d, int lev, int
         sL[k] = scharr3(A, Lc, Lp);
         if (k < 2 * S) continue;
         const int q = k - 2 * S;  // first-derivative row y0 - S + q
-        const float Lx = scharr3(dL[k - 2 * S], dL[k - S], dL[k]);
+        const float Lx = scharr3v(dL[k - 2 * S], dL[k - S], dL[k]);
         const float Ly = sL[k] - sL[k - 2 * S];
         frx[lane] = Lx;
         fry[lane] = Ly;
@@ -221,7 +229,7 @@ __device__ __forceinline__ void det_strip_band(const BatchImage& d, int lev, int
             wxc = wX[2 * B - 1 - t];
             wyc = wY[2 * B - 1 - t];
         }
-        const float Lxx = scharr3(dxa, dX[t + S], dxc);
+        const float Lxx = scharr3v(dxa, dX[t + S], dxc);
         const float Lxy = wxc - wxa;
         const float Lyy = wyc - wya;
         const float v = scale * __builtin_fmaf(Lxx, Lyy, -(Lxy * Lxy));
@@ -271,7 +279,7 @@ __device__ __forceinline__ void det_strip_pixels(const BatchImage& d, int lev, i
             dd[i] = e - a;
             ss[i] = scharr3(a, c, e);
         }
-        lx = scharr3(dd[0], dd[1], dd[2]);
+        lx = scharr3v(dd[0], dd[1], dd[2]);
         ly = ss[2] - ss[0];
     };
     for (int yo = 0; yo < H; ++yo) {
@@ -287,7 +295,7 @@ __device__ __forceinline__ void det_strip_pixels(const BatchImage& d, int lev, i
             wXr[i] = scharr3(xm, xc, xp);
             wYr[i] = scharr3(ym, yc, yp);
         }
-        const float Lxx = scharr3(dXr[0], dXr[1], dXr[2]);
+        const float Lxx = scharr3v(dXr[0], dXr[1], dXr[2]);
         const float Lxy = wXr[2] - wXr[0];
         const float Lyy = wYr[2] - wYr[0];
         const float v = scale * __builtin_fmaf(Lxx, Lyy, -(Lxy * Lxy));

@@ -176,6 +176,33 @@ def test_detector_stage_all_steps(gpu_lib, W, H, sigma0):
         assert err <= 1e-6 * sn * sn * scale, (i, st, err, sn * sn * scale)
 
 
+@pytest.mark.parametrize("W,H,sigma0", [(320, 240, 1.6), (130, 70, 1.6), (200, 150, 4.0),
+                                         (40, 20, 4.5), (33, 12, 4.5)])
+def test_detector_mirror_equivariant(gpu_lib, W, H, sigma0):
+    """det = sigma_n^2 (Lxx Lyy - Lxy^2) is unchanged by a vertical mirror of
+    the levels (Lxy changes sign and is squared).  In the kernels' FP32
+    arithmetic it holds bit for bit: vertical differences change sign
+    exactly and the vertical Scharr sums are symmetric in their outer rows,
+    so a mistake in the reflection at the bottom border that the top does
+    not share, or an asymmetric vertical stencil, fails it.  Cases: bands
+    of 32 rows with an aligned last band (320x240, 130x70), steps 4-7
+    (200x150), bands of 8 rows (40x20) and the per-pixel form (33x12)."""
+    from scipy.ndimage import gaussian_filter
+    K = gpu_lib
+    note(f"[detector mirror] {W}x{H} sigma0 {sigma0}")
+    p = K.kaze_default_params(sigma0=sigma0)
+    N = K.kaze_num_levels(p)
+    rng = np.random.default_rng(W * 7 + H)
+    lev = f32(np.stack([gaussian_filter(rng.random((H, W)), 1.5, mode="reflect")
+                        for _ in range(N)]))
+    det = torch.empty(lev.shape, dtype=torch.float32, device="cuda")
+    det_m = torch.empty(lev.shape, dtype=torch.float32, device="cuda")
+    K.kaze_detector_response(dev(lev), W, H, p, det)
+    K.kaze_detector_response(dev(np.ascontiguousarray(lev[:, ::-1, :])), W, H, p, det_m)
+    torch.cuda.synchronize()
+    assert torch.equal(det_m.flip(1), det)
+
+
 # ---------------------------------------------------------------- end to end
 def check_end_to_end(K, W, H, seed, params=None, oracle_kw=None):
     note(f"[end-to-end] {W}x{H} seed {seed} params {params and dict((f, getattr(params, f)) for f, _ in params._fields_)}")
