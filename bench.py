@@ -305,10 +305,9 @@ def run_distribution_and_transfers(args, K, torch, kb, img_cpu, form, reps=50):
 
 
 def det_levels_of(kb, form):
-    """Detector levels inside the level segment of a run: a graph run's per
-    the plan; an eager run keeps the single fork of small batches out."""
-    d = kb.det_levels_in_segment
-    return d if form == "graph" or d == kb.N else 0
+    """Detector levels inside the level segment of a run (either launch form):
+    all levels for batches that fork the detector beside the steps, else 0."""
+    return kb.det_levels_in_segment
 
 
 def timed_plan(args, K, torch, kb, n_images):

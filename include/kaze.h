@@ -350,12 +350,11 @@ kaze_status kaze_batch_create(const kaze_image_desc* images, int n,
 
 /*
  * Properties of a created batch: the AOS tile shape in use and the number of
- * levels whose detector response runs inside the level segment of a graph
- * run (the one kaze_profile_begin("aos_reduce") brackets), on a second
- * stream beside the steps: all N for batches of 8 Mpx and more (level by
- * level, in eager runs too), the first N - 5 for smaller ones with a
- * detector (one launch beside the last five steps; eager runs keep it after
- * the steps), 0 without a detector.
+ * levels whose detector response runs inside the level segment of a run
+ * (the one kaze_profile_begin("aos_reduce") brackets), on a second stream
+ * beside the steps: all N for batches of 8 Mpx and more with a detector
+ * (level by level, in graph and eager runs), else 0 (the detector runs
+ * after the steps).
  */
 kaze_status kaze_batch_properties(const kaze_batch* b, int* aos_shape,
                                   int* det_levels_in_segment);
@@ -363,7 +362,7 @@ kaze_status kaze_batch_properties(const kaze_batch* b, int* aos_shape,
 /* Enqueues one run of the plan on stream: three graph launches (base image
  * and contrast factor; the AOS steps; detector response and extrema), or
  * with eager != 0 the same kernel launches issued one by one (faster on
- * this runtime for one 1920x1200 image: graph replay adds about 30 us per
+ * this runtime for one 1920x1200 image: graph replay adds about 20 us per
  * run).  The detector forks onto the plan's second stream as the
  * properties below describe, ordered through events.  Runs that share a plan must be
  * ordered on one stream.  Under kaze_profile_begin with aos_reduce listed,

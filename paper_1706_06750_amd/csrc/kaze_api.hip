@@ -410,7 +410,6 @@ struct kaze_batch {
     std::vector<hipEvent_t> ev;      // fork / join points (N + 1)
     bool fork_det = false;           // detector response beside the steps, per level
     int det_band = kDetBandShort;    // rows per detector band (det_band_for of the plan's pixels)
-    int split_det = -1;              // else: levels 0..split_det forked once
     SgBatch* sg = nullptr;           // surrogate steps (kaze_sg_batch_create), or none
 };
 
@@ -418,11 +417,11 @@ struct kaze_batch {
 // dependency between queues costs about 10-25 us on this runtime (measured):
 // the detector response of every level runs beside the steps only when each
 // step is long enough to hide that, i.e. for batches of at least this many
-// pixels.  Smaller batches fork once: the detector of the levels up to
-// kSplitDetBack before the last runs beside the remaining steps, the rest
-// after them.
+// pixels.  Smaller batches run it after the steps: their step kernels need
+// every compute unit, and detector blocks beside them slowed the steps
+// (24.2 -> 27.7 us per level of one 1920x1200 image) by more than the
+// detector took after them.
 constexpr double kForkDetPixels = 8e6;
-constexpr int kSplitDetBack = 5;
 
 extern "C" kaze_status kaze_batch_destroy(kaze_batch* b);
 
@@ -543,12 +542,9 @@ kaze_status check_batch(const kaze_image_desc* im, int n, const kaze_params* p, 
 
 // The a1-a7 sequence of a batch, one launch per phase for all images, in
 // three segments: 0 base image and contrast factor, 1 the AOS steps and the
-// detector response, 2 extrema.  With a side stream the detector response
-// forks off the step sequence: level by level for large batches, once for
-// the first levels of small ones where `split` allows it (graph runs: in
-// eager runs that single fork measured slower than none).
-kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStream_t side,
-                            bool split_ok = true) {
+// detector response, 2 extrema.  With a side stream the detector response of
+// large batches forks off the step sequence level by level.
+kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStream_t side) {
     const kaze_params* p = &B.p;
     const BatchImage b0 = batch_image(0, 0);
     if (seg == 0) {
@@ -562,7 +558,6 @@ kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStre
     DetLevels dl = det_levels(B.lv, B.det_band);
     dl.thr = (float)p->det_threshold;  // of the masks the extrema kernel reads
     const bool fork = B.fork_det && side != nullptr;
-    const int split = side != nullptr && split_ok && !B.fork_det ? B.split_det : -1;
     if (seg == 1 && B.sg) return sg_batch_levels(B, s);
     if (seg == 1) {
         // The detector response of level i needs level i only: with a side
@@ -595,21 +590,14 @@ kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStre
                 if (st != KAZE_OK) return st;
             }
             if ((st = det_level(i)) != KAZE_OK) return st;
-            if (i == split) {  // levels 0..split beside the remaining steps
-                KZ_HIP(hipEventRecord(B.ev[i], s));
-                KZ_HIP(hipStreamWaitEvent(side, B.ev[i], 0));
-                KZ_LAUNCH(K_DET, side, launch_det(b0, det, 0, split + 1, dl, side));
-            }
         }
-        if (fork || split >= 0) {  // join
-            hipStream_t js = fork ? ds : side;
-            KZ_HIP(hipEventRecord(B.ev[B.N], js));
+        if (fork) {  // join
+            KZ_HIP(hipEventRecord(B.ev[B.N], ds));
             KZ_HIP(hipStreamWaitEvent(s, B.ev[B.N], 0));
         }
         return KAZE_OK;
     }
-    if (B.with_det && !fork)
-        KZ_LAUNCH(K_DET, s, launch_det(b0, det, split >= 0 ? split + 1 : 0, B.N, dl, s));
+    if (B.with_det && !fork) KZ_LAUNCH(K_DET, s, launch_det(b0, det, 0, B.N, dl, s));
     if (B.with_nms) {
         const ImgWork nms{B.d_imgs, B.d_nms, B.n_nms};
         KZ_LAUNCH(K_NMS, s,
@@ -623,16 +611,16 @@ kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStre
 // through events), and under kaze_profile_begin("aos_reduce") one event pair
 // around the level segment as in a graph run.
 kaze_status enqueue_batch(const kaze_batch& B, hipStream_t s) {
-    kaze_status st = enqueue_segment(B, 0, s, B.side, false);
+    kaze_status st = enqueue_segment(B, 0, s, B.side);
     if (st != KAZE_OK) return st;
     {
         ProfScope ps(K_AOS_REDUCE, s);
         g_prof.in_segment = true;
-        st = enqueue_segment(B, 1, s, B.side, false);
+        st = enqueue_segment(B, 1, s, B.side);
         g_prof.in_segment = false;
     }
     if (st != KAZE_OK) return st;
-    return enqueue_segment(B, 2, s, B.side, false);
+    return enqueue_segment(B, 2, s, B.side);
 }
 
 kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p, int shape,
@@ -662,8 +650,6 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
     B->det_band = det_band_for(px);
     // surrogate batches run the detector after the steps (no fork)
     B->fork_det = !sp && B->with_det && px >= kForkDetPixels;
-    B->split_det = !sp && B->with_det && !B->fork_det && B->N > kSplitDetBack + 1
-                       ? B->N - 1 - kSplitDetBack : -1;
     B->d_imgs = reinterpret_cast<BatchImage*>(base + L.imgs);
     B->d_lvl = reinterpret_cast<ImageDesc*>(base + L.lvl);
     B->d_items = reinterpret_cast<int2*>(base + L.items);
@@ -1742,7 +1728,7 @@ kaze_status kaze_batch_properties(const kaze_batch* b, int* aos_shape, int* det_
     if (!b) return fail(KAZE_ERR_INVALID_ARG, "batch is NULL");
     if (aos_shape) *aos_shape = b->shape;
     if (det_levels_in_segment)
-        *det_levels_in_segment = b->fork_det ? b->N : b->split_det + 1;
+        *det_levels_in_segment = b->fork_det ? b->N : 0;
     return KAZE_OK;
 }
 

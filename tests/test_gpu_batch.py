@@ -52,8 +52,8 @@ def test_batch_matches_single_image_path(gpu_lib, shape):
     assert len(K.AOS_SHAPES) == 6
     note(f"[batch] shape {K.shape_label(shape)} sizes {SIZES}")
     kb, imgs = make_batch(K, SIZES, range(40, 40 + len(SIZES)), shape)
-    # a small batch forks the detector of its first N - 5 levels once
-    assert kb.det_levels_in_segment == kb.N - 5
+    # a small batch runs the detector after the steps
+    assert kb.det_levels_in_segment == 0
     kb.run()
     torch.cuda.synchronize()
     exact = _same_arithmetic(K, shape, 0)
@@ -97,17 +97,17 @@ def test_batch_graph_replays_match_eager(gpu_lib):
 
 
 @pytest.mark.parametrize("sigma0", [0.6, 3.2])
-def test_batch_detector_fork_at_other_schedules(gpu_lib, sigma0):
+def test_batch_detector_at_other_schedules(gpu_lib, sigma0):
     """Schedules with other Scharr steps (sigma0 0.6: every step 1; sigma0
-    3.2: steps 3 to 5, two detector launches): the single fork of a small
-    batch's first N - 5 levels in graph runs, eager runs and the
-    single-image calls agree bitwise, keypoints included."""
+    3.2: steps 3 to 5, two detector launches): a small batch's graph runs,
+    eager runs and the single-image calls agree bitwise, keypoints
+    included."""
     K = gpu_lib
     p = K.kaze_default_params(sigma0=sigma0)
     sizes = SIZES[:4]
     note(f"[batch] sigma0 {sigma0}: sizes {sizes}")
     kb, imgs = make_batch(K, sizes, range(120, 124), 0, params=p)
-    assert kb.det_levels_in_segment == kb.N - 5
+    assert kb.det_levels_in_segment == 0
     kb.run(eager=True)
     torch.cuda.synchronize()
     ref_det = [t.clone() for t in kb.det]
