@@ -352,7 +352,7 @@ kaze_status kaze_batch_create(const kaze_image_desc* images, int n,
  * Properties of a created batch: the AOS tile shape in use and the number of
  * levels whose detector response runs inside the level segment of a run
  * (the one kaze_profile_begin("aos_reduce") brackets), on a second stream
- * beside the steps: all N for batches of 8 Mpx and more with a detector
+ * beside the steps: all N for batches of 32 Mpx and more with a detector
  * (level by level, in graph and eager runs), else 0 (the detector runs
  * after the steps).
  */

@@ -413,15 +413,13 @@ struct kaze_batch {
     SgBatch* sg = nullptr;           // surrogate steps (kaze_sg_batch_create), or none
 };
 
-// A captured fork spreads a graph over several hardware queues, and every
-// dependency between queues costs about 10-25 us on this runtime (measured):
-// the detector response of every level runs beside the steps only when each
-// step is long enough to hide that, i.e. for batches of at least this many
-// pixels.  Smaller batches run it after the steps: their step kernels need
-// every compute unit, and detector blocks beside them slowed the steps
-// (24.2 -> 27.7 us per level of one 1920x1200 image) by more than the
-// detector took after them.
-constexpr double kForkDetPixels = 8e6;
+// The detector response of every level runs beside the steps, on a second
+// stream, only for batches of at least this many pixels.  Smaller batches
+// run it after the steps: detector blocks beside the step kernels slowed the
+// steps by more than the detector took after them (one 1920x1200 image:
+// 24.2 -> 27.7 us per level; 8 x 1920x1200: 3260 against 3505 images/s),
+// while batches of 67 and 295 Mpx gain 2.5% from the overlap.
+constexpr double kForkDetPixels = 32e6;
 
 extern "C" kaze_status kaze_batch_destroy(kaze_batch* b);
 

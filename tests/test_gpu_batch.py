@@ -200,9 +200,9 @@ def test_large_batch_forks_detector_and_matches_eager(gpu_lib):
     second stream inside the captured graph), replays still equal the eager
     sequence bitwise."""
     K = gpu_lib
-    sizes = [(1920, 1200), (1900, 1150), (1800, 1100), (1700, 1000), (1600, 1200)]  # 10 Mpx
-    note("[batch] large batch %s" % sizes)
-    kb, _ = make_batch(K, sizes, range(80, 85), 1)
+    sizes = [(1920, 1200)] * 11 + [(1900, 1150), (1800, 1100), (1700, 1000), (1600, 1200)]
+    note("[batch] large batch of %d images, %.1f Mpx" % (len(sizes), sum(w * h for w, h in sizes) / 1e6))
+    kb, _ = make_batch(K, sizes, range(80, 80 + len(sizes)), 1)
     assert kb.det_levels_in_segment == kb.N
     kb.run(eager=True)
     torch.cuda.synchronize()
