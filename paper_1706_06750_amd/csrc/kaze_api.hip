@@ -558,9 +558,9 @@ kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStre
     const bool fork = B.fork_det && side != nullptr;
     if (seg == 1 && B.sg) return sg_batch_levels(B, s);
     if (seg == 1) {
-        // The detector response of level i needs level i only: with a side
-        // stream (graph capture of a large batch) it runs there, overlapping
-        // the later steps.
+        // The detector response of level i needs level i only: in a large
+        // batch (graph and eager runs) it runs on the side stream,
+        // overlapping the later steps.
         const Taps tc = gauss_taps(p->sigma_cond);
         const int gmode = p->diffusivity == KAZE_G2 ? 0 : 1;
         hipStream_t ds = fork ? side : s;
