@@ -202,6 +202,17 @@ bool shape_fits(int W, int H, int shape) {
     return shape >= 0 && shape < kAosShapes;
 }
 
+// Every AOS shape serves the longest line in one wavefront: the interface
+// solve spans at most 64 lanes of M chunks each (iface_lanes), which
+// check_size guarantees for every accepted image.
+constexpr bool shapes_fit_one_wavefront() {
+    for (const AosShape& a : kAosShape)
+        if ((kMaxSide + a.rc - 1) / a.rc > 64 * a.m || (kMaxSide + a.cc - 1) / a.cc > 64 * a.m)
+            return false;
+    return true;
+}
+static_assert(shapes_fit_one_wavefront(), "an AOS shape needs more than 64 interface lanes");
+
 kaze_status check_size(int W, int H) {
     if (W < 8 || H < 8) return fail(KAZE_ERR_INVALID_ARG, "image must be at least 8x8");
     if (W > kMaxSide || H > kMaxSide)
