@@ -370,10 +370,10 @@ kaze_status fed_cycle(const float* L, const float* g, float* out, float* tmp, in
 }
 
 // a1-a2: base image and contrast factor (or the given k) for one image or a
-// batch (images / tiles / AOS tiles of height cty / hist items select the
-// work).
+// batch (images / tiles / AOS tiles of height cty / hist items of hist_chunk
+// pixels select the work).
 kaze_status base_and_k(const BatchImage& b0, const ImgWork& images, const ImgWork& tiles,
-                       const ImgWork& ctiles, int cty, const ImgWork& hist,
+                       const ImgWork& ctiles, int cty, const ImgWork& hist, int hist_chunk,
                        const kaze_params* p, hipStream_t s) {
     const Taps t0 = gauss_taps(p->sigma0);
     const Taps tc = gauss_taps(p->sigma_cond);
@@ -386,7 +386,7 @@ kaze_status base_and_k(const BatchImage& b0, const ImgWork& images, const ImgWor
         int shift;
         percentile_fraction(p->k_percentile, &mant, &shift);
         KZ_LAUNCH(K_GRAD, s, launch_cond(b0, ctiles, tc, 1.f, 2, cty, s));
-        KZ_LAUNCH(K_HIST, s, launch_hist(b0, hist, p->k_bins, cty, s));
+        KZ_LAUNCH(K_HIST, s, launch_hist(b0, hist, p->k_bins, cty, hist_chunk, s));
         KZ_LAUNCH(K_KSELECT, s, launch_kselect(b0, images, p->k_bins, mant, shift, cty, s));
     }
     return KAZE_OK;
@@ -421,6 +421,7 @@ struct kaze_batch {
     std::vector<hipEvent_t> ev;      // fork / join points (N + 1)
     bool fork_det = false;           // detector response beside the steps, per level
     int det_band = kDetBandShort;    // rows per detector band (det_band_for of the plan's pixels)
+    int hist_chunk = kHistChunk;     // pixels per histogram block (hist_chunk_for of the same)
     SgBatch* sg = nullptr;           // surrogate steps (kaze_sg_batch_create), or none
 };
 
@@ -484,12 +485,13 @@ BatchLayout batch_layout(const kaze_image_desc* im, int n, const kaze_params* p,
     int smin, smax;
     step_range(p, smin, smax);
     const int band = det_band_for(batch_pixels(im, n));
+    const int hist_chunk = hist_chunk_for(batch_pixels(im, n));
     L.n_tiles = L.n_aos = L.n_lines = L.n_hist = L.n_det = L.n_nms = 0;
     for (int j = 0; j < n; ++j) {
         L.n_tiles += tiles_of(im[j].W, im[j].H);
         L.n_aos += aos_tiles_of(im[j].W, im[j].H, kAosShape[shape].ty);
         L.n_lines += aos_line_groups(im[j].W, im[j].H, kAosShape[shape]);
-        L.n_hist += (im[j].W * im[j].H + kHistChunk - 1) / kHistChunk;
+        L.n_hist += (im[j].W * im[j].H + hist_chunk - 1) / hist_chunk;
         L.n_det += det_tiles_of(im[j].W, im[j].H, smin, smax, band);
         L.n_nms += nms_blocks_of(im[j].W, im[j].H, true);
     }
@@ -561,7 +563,8 @@ kaze_status enqueue_segment(const kaze_batch& B, int seg, hipStream_t s, hipStre
         const ImgWork tiles{B.d_imgs, B.d_tiles, B.n_tiles};
         const ImgWork ctiles{B.d_imgs, B.d_aos, B.n_aos};  // the plan's AOS tiles
         const ImgWork hist{B.d_imgs, B.d_hist, B.n_hist};
-        return base_and_k(b0, images, tiles, ctiles, kAosShape[B.shape].ty, hist, p, s);
+        return base_and_k(b0, images, tiles, ctiles, kAosShape[B.shape].ty, hist, B.hist_chunk, p,
+                          s);
     }
     const ImgWork det{B.d_imgs, B.d_det, B.n_det};
     DetLevels dl = det_levels(B.lv, B.det_band);
@@ -657,6 +660,7 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
     B->with_nms = im[0].count != nullptr;
     const double px = batch_pixels(im, n);
     B->det_band = det_band_for(px);
+    B->hist_chunk = hist_chunk_for(px);
     // surrogate batches run the detector after the steps (no fork)
     B->fork_det = !sp && B->with_det && px >= kForkDetPixels;
     B->d_imgs = reinterpret_cast<BatchImage*>(base + L.imgs);
@@ -729,7 +733,8 @@ kaze_status batch_create(const kaze_image_desc* im, int n, const kaze_params* p,
             ha[ia++] = make_int2(j, t);
         for (int t = 0; t < aos_line_groups(d.W, d.H, kAosShape[shape]); ++t)
             hl[il++] = make_int2(j, t);
-        for (int t = 0; t < (d.W * d.H + kHistChunk - 1) / kHistChunk; ++t) hh[ih++] = make_int2(j, t);
+        for (int t = 0; t < (d.W * d.H + B->hist_chunk - 1) / B->hist_chunk; ++t)
+            hh[ih++] = make_int2(j, t);
         for (int t = 0; t < det_tiles_of(d.W, d.H, smin, smax, B->det_band); ++t)
             hd[idt++] = make_int2(j, t);
         for (int t = 0; t < nms_blocks_of(d.W, d.H, true); ++t) hn[inm++] = make_int2(j, t);
@@ -945,7 +950,9 @@ kaze_status sg_chain(const kaze_sg_scale_space& S, const sg::Geo& geo, int i, co
 kaze_status sg_segment(const kaze_sg_scale_space& S, int seg, hipStream_t s) {
     const kaze_params* p = &S.p;
     const ImgWork none{nullptr, nullptr, 0};
-    if (seg == 0) return base_and_k(S.b, none, none, none, kAosShape[0].ty, none, p, s);
+    if (seg == 0)
+        return base_and_k(S.b, none, none, none, kAosShape[0].ty, none,
+                          hist_chunk_for((double)S.b.W * S.b.H), p, s);
     if (seg == 2) {
         if (S.with_det)
             KZ_LAUNCH(K_DET, s,
@@ -1340,7 +1347,8 @@ kaze_status scale_space_launches(const float* img, int W, int H, int ld_img,
     b.hmax = reinterpret_cast<unsigned*>(base + w.hmax);
     b.k = k_out;
     const ImgWork none{nullptr, nullptr, 0};
-    kaze_status st = base_and_k(b, none, none, none, kAosShape[shape].ty, none, p, s);
+    kaze_status st = base_and_k(b, none, none, none, kAosShape[shape].ty, none,
+                                hist_chunk_for((double)W * H), p, s);
     if (st != KAZE_OK) return st;
 
     std::vector<Level> lv;

@@ -152,8 +152,9 @@ __device__ __forceinline__ float hmax_of(const BatchImage& d, int tile_h) {
 // the counts are deterministic.  Device-scope atomics to one address are
 // serialised, so block c adds its counts to global copy c % kHistCopies
 // (bin b of copy j at hist[j * nbins + b]), and kselect sums the copies.
+// Block c bins pixels [c * chunk_px, (c + 1) * chunk_px).
 __global__ __launch_bounds__(256) void hist_kernel(BatchImage d0, ImgWork w, int nbins,
-                                                     int tile_h) {
+                                                     int tile_h, int chunk_px) {
     extern __shared__ unsigned s_hist[];
     BatchImage d;
     int chunk;
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(256) void hist_kernel(BatchImage d0, ImgWork w, int
     const float hmax = hmax_of(d, tile_h);
     const float fb = (float)nbins;
     const int n = d.W * d.H;
-    const int i0 = chunk * kHistChunk, i1 = min(n, i0 + kHistChunk);
+    const int i0 = chunk * chunk_px, i1 = min(n, i0 + chunk_px);
     // eight loads in flight per thread before any of them is binned
     constexpr int U = 8;
     const gfloat* __restrict__ src = (const gfloat*)d.g;
@@ -308,12 +309,13 @@ hipError_t launch_gauss(const BatchImage& d0, const ImgWork& w, const Taps& taps
 }
 
 
-hipError_t launch_hist(const BatchImage& d0, const ImgWork& w, int nbins, int tile_h,
+hipError_t launch_hist(const BatchImage& d0, const ImgWork& w, int nbins, int tile_h, int chunk,
                        hipStream_t s) {
-    const int count = item_count(w, (d0.W * d0.H + kHistChunk - 1) / kHistChunk);
+    if (chunk < 256) return hipErrorInvalidValue;
+    const int count = item_count(w, (d0.W * d0.H + chunk - 1) / chunk);
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(hist_kernel, dim3(count), dim3(256), nbins * sizeof(unsigned), s, d0, w,
-                       nbins, tile_h);
+                       nbins, tile_h, chunk);
     return hipGetLastError();
 }
 
