@@ -195,6 +195,22 @@ def test_full_uneven_batch_equals_single_image_calls(gpu_lib):
     kb.close()
 
 
+def test_detector_fork_threshold(gpu_lib):
+    """The detector runs beside the steps from 32 Mpx per batch and after
+    them below (8 x 1920x1200, 18.4 Mpx, measured faster that way); a batch
+    without a detector has no detector levels in its segment."""
+    K = gpu_lib
+    below = K.KazeBatch([(1920, 1200)] * 8, shape=0)
+    assert below.det_levels_in_segment == 0
+    below.close()
+    above = K.KazeBatch([(1920, 1200)] * 14, shape=0)  # 32.3 Mpx
+    assert above.det_levels_in_segment == above.N
+    above.close()
+    nodet = K.KazeBatch([(1920, 1200)] * 14, shape=0, with_detector=False)
+    assert nodet.det_levels_in_segment == 0
+    nodet.close()
+
+
 def test_large_batch_forks_detector_and_matches_eager(gpu_lib):
     """Above the size where the detector response runs beside the steps (a
     second stream inside the captured graph), replays still equal the eager
